@@ -1,0 +1,482 @@
+/*
+ * su2_oracle.c -- plain FP64 CPU reference for the pure-gauge SU(2) heat bath.
+ *
+ * TEST INFRASTRUCTURE ONLY: compiled and called by the tests, the smoke check
+ * and the benchmark's CPU-baseline leg, never by the product path.  It shares
+ * no code with the GPU library.  Written for clarity, not speed: every step is
+ * the definition from the paper, in FP64, in the paper's order.
+ *
+ * Paper: Cardoso & Bicudo, "Lattice SU(2) on GPU's" (LAT2010).
+ *   Sec. 2, SU(2) parametrisation   U = a0 + i a.sigma, a0^2 + |a|^2 = 1
+ *   Sec. 2, heat-bath weight        dP(U) ~ exp[(beta/2) Tr(U V)], V = six staples
+ *   Sec. 2, normalisation           U~ = V / sqrt(det V) = V / k
+ *   Sec. 2, a0 distribution         P(a0) ~ sqrt(1 - a0^2) exp(beta k a0)
+ *   Sec. 2, new link                U' = X U~^{-1}  (X the sampled element)
+ *   Sec. 4 / Fig. 3 caption         per direction: even sites, then odd sites
+ *   Sec. 4, kernel list             cold/hot start, plaquette, Polyakov loop, sums
+ *
+ * Readings where the paper is silent (the same readings the GPU library takes):
+ *   - a0 sampler: Kennedy-Pendleton for alpha = beta k >= 1; below that the
+ *     exact rejection from the Haar (semicircle) marginal with acceptance
+ *     exp(alpha (a0 - 1)); both capped at SAMPLER_TRIAL_CAP trials (the cap is
+ *     unreachable in practice: acceptance is >= 0.41 for every alpha).
+ *   - direction of a: uniform on the sphere, |a| = sqrt(delta (2 - delta)).
+ *   - randoms: Philox4x32-10 keyed by the seed, counter (site, sweep,
+ *     mu | tag<<2 | replica<<6, draw), words mapped to (2*(w>>9)+1) 2^-24.
+ */
+#include "su2_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define SAMPLER_TRIAL_CAP 1000
+#define KP_MIN_ALPHA 1.0
+
+/* ------------------------------------------------------------------ Philox */
+/* Salmon et al., "Parallel random numbers: as easy as 1, 2, 3" (SC'11):
+ * Philox4x32 with multipliers 0xD2511F53, 0xCD9E8D57 and Weyl key increments
+ * 0x9E3779B9, 0xBB67AE85; ten rounds, key bumped between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void orc_philox_batch(int64_t n, const uint32_t *ctr, uint64_t seed, uint32_t *out)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+double orc_uniform(uint32_t w)
+{
+    return (2.0 * (double)(w >> 9) + 1.0) * ldexp(1.0, -24);
+}
+
+static void block(uint64_t seed, uint32_t site, uint32_t sweep, uint32_t word2,
+                  uint32_t draw, double u[4], uint32_t w_out[4])
+{
+    uint32_t ctr[4] = {site, sweep, word2, draw};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    for (int i = 0; i < 4; ++i) {
+        if (u) u[i] = orc_uniform(w[i]);
+        if (w_out) w_out[i] = w[i];
+    }
+}
+
+static uint32_t word2_of(uint32_t mu, uint32_t tag, uint32_t replica)
+{
+    return mu | (tag << 2) | (replica << 6);
+}
+
+/* -------------------------------------------------------------- quaternions */
+/* (a0 + i a.s)(b0 + i b.s) = (a0 b0 - a.b) + i (a0 b + b0 a - a x b).s */
+void orc_qmul(const double a[4], const double b[4], double c[4])
+{
+    double r0 = a[0] * b[0] - (a[1] * b[1] + a[2] * b[2] + a[3] * b[3]);
+    double r1 = a[0] * b[1] + b[0] * a[1] - (a[2] * b[3] - a[3] * b[2]);
+    double r2 = a[0] * b[2] + b[0] * a[2] - (a[3] * b[1] - a[1] * b[3]);
+    double r3 = a[0] * b[3] + b[0] * a[3] - (a[1] * b[2] - a[2] * b[1]);
+    c[0] = r0; c[1] = r1; c[2] = r2; c[3] = r3;
+}
+
+void orc_qdag(const double a[4], double c[4])
+{
+    c[0] = a[0]; c[1] = -a[1]; c[2] = -a[2]; c[3] = -a[3];
+}
+
+void orc_qmul_batch(int64_t n, const double *a, const double *b, double *c)
+{
+    for (int64_t i = 0; i < n; ++i) orc_qmul(a + 4 * i, b + 4 * i, c + 4 * i);
+}
+
+static double qnorm(const double a[4])
+{
+    return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
+}
+
+/* ----------------------------------------------------------------- lattice */
+int orc_check_dims(const int32_t dims[4])
+{
+    for (int i = 0; i < 4; ++i)
+        if (dims[i] < 2 || (dims[i] & 1)) return -1;
+    return 0;
+}
+
+int64_t orc_volume(const int32_t dims[4])
+{
+    return (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+}
+
+static void coords(const int32_t dims[4], int64_t s, int c[4])
+{
+    for (int i = 0; i < 4; ++i) {
+        c[i] = (int)(s % dims[i]);
+        s /= dims[i];
+    }
+}
+
+static int64_t site_of(const int32_t dims[4], const int c[4])
+{
+    return c[0] + (int64_t)dims[0] * (c[1] + (int64_t)dims[1] * (c[2] + (int64_t)dims[2] * c[3]));
+}
+
+int orc_parity(const int32_t dims[4], int64_t s)
+{
+    int c[4];
+    coords(dims, s, c);
+    return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+int64_t orc_shift(const int32_t dims[4], int64_t s, int mu, int step)
+{
+    int c[4];
+    coords(dims, s, c);
+    c[mu] = ((c[mu] + step) % dims[mu] + dims[mu]) % dims[mu];
+    return site_of(dims, c);
+}
+
+static const double *link(const double *U, int64_t s, int mu)
+{
+    return U + (s * 4 + mu) * 4;
+}
+
+/* Six staples around U_mu(s) (Sec. 2), oriented so that (1/2) Tr(U_mu(s) V)
+ * is the sum of the six plaquettes containing U_mu(s):
+ *   forward  U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
+ *   backward U_nu(s+mu-nu)^+ U_mu(s-nu)^+ U_nu(s-nu)                        */
+void orc_staple(const int32_t dims[4], const double *U, int64_t s, int mu, double V[4])
+{
+    V[0] = V[1] = V[2] = V[3] = 0.0;
+    int64_t s_pmu = orc_shift(dims, s, mu, +1);
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        int64_t s_pnu = orc_shift(dims, s, nu, +1);
+        int64_t s_mnu = orc_shift(dims, s, nu, -1);
+        int64_t s_pmu_mnu = orc_shift(dims, s_pmu, nu, -1);
+        double a[4], b[4], t[4], f[4];
+
+        orc_qdag(link(U, s_pnu, mu), b);
+        orc_qmul(link(U, s_pmu, nu), b, t);
+        orc_qdag(link(U, s, nu), a);
+        orc_qmul(t, a, f);
+        for (int c = 0; c < 4; ++c) V[c] += f[c];
+
+        orc_qdag(link(U, s_pmu_mnu, nu), a);
+        orc_qdag(link(U, s_mnu, mu), b);
+        orc_qmul(a, b, t);
+        orc_qmul(t, link(U, s_mnu, nu), f);
+        for (int c = 0; c < 4; ++c) V[c] += f[c];
+    }
+}
+
+/* ----------------------------------------------------------------- sampler */
+/* Draw a0 with density ~ sqrt(1 - a0^2) exp(alpha a0) on [-1, 1] (Sec. 2) and
+ * return delta = 1 - a0.
+ *   alpha >= 1: Kennedy-Pendleton.  With uniforms r1..r4 of trial t,
+ *     delta = -(ln r1 + cos^2(2 pi r2) ln r3) / alpha is Gamma(3/2, alpha)
+ *     distributed; accepting when r4^2 <= 1 - delta/2 supplies the missing
+ *     factor sqrt(1 - delta/2) of sqrt(delta (2 - delta)).
+ *   alpha < 1: a0 = sqrt(r1) cos(2 pi r2) is the first coordinate of a
+ *     uniform point in the unit disc, i.e. the Haar marginal
+ *     (2/pi) sqrt(1 - a0^2); accept when r3 <= exp(alpha (a0 - 1)).      */
+double orc_sample_delta(double alpha, uint64_t seed, uint32_t site, uint32_t sweep,
+                        uint32_t mu, uint32_t replica, int32_t *ntrials, double *margin)
+{
+    const uint32_t w2 = word2_of(mu, ORC_TAG_TRIAL, replica);
+    double min_margin = fabs(alpha - KP_MIN_ALPHA);
+    double delta = 0.0;
+    int accepted = 0;
+    int t;
+    for (t = 0; t < SAMPLER_TRIAL_CAP; ++t) {
+        double r[4];
+        block(seed, site, sweep, w2, (uint32_t)t, r, NULL);
+        double m;
+        if (alpha >= KP_MIN_ALPHA) {
+            double c = cos(2.0 * M_PI * r[1]);
+            delta = -(log(r[0]) + c * c * log(r[2])) / alpha;
+            m = (1.0 - 0.5 * delta) - r[3] * r[3];
+        } else {
+            double a0 = sqrt(r[0]) * cos(2.0 * M_PI * r[1]);
+            delta = 1.0 - a0;
+            m = exp(alpha * (a0 - 1.0)) - r[2];
+        }
+        if (fabs(m) < min_margin) min_margin = fabs(m);
+        if (m >= 0.0) {
+            accepted = 1;
+            break;
+        }
+    }
+    if (!accepted) delta = 0.0; /* unreachable in practice; fixed, documented value */
+    if (ntrials) *ntrials = accepted ? t + 1 : SAMPLER_TRIAL_CAP;
+    if (margin) *margin = min_margin;
+    return delta;
+}
+
+void orc_sample_delta_batch(int64_t n, const double *alpha, uint64_t seed,
+                            const uint32_t *site, uint32_t sweep, uint32_t mu,
+                            uint32_t replica, double *delta, int32_t *ntrials,
+                            double *margin)
+{
+    for (int64_t i = 0; i < n; ++i)
+        delta[i] = orc_sample_delta(alpha[i], seed, site[i], sweep, mu, replica,
+                                    ntrials ? ntrials + i : NULL, margin ? margin + i : NULL);
+}
+
+/* X = (1 - delta, |a| n) with n uniform on the 2-sphere from (r5, r6):
+ * cos(theta) = 1 - 2 r5, sin(theta) = 2 sqrt(r5 (1 - r5)), phi = 2 pi r6,
+ * |a| = sqrt(delta (2 - delta)) = sqrt(1 - a0^2). */
+static void element_from_delta(double delta, const double rdir[2], double X[4])
+{
+    double amag = sqrt(delta * (2.0 - delta));
+    double cth = 1.0 - 2.0 * rdir[0];
+    double sth = 2.0 * sqrt(rdir[0] * (1.0 - rdir[0]));
+    double phi = 2.0 * M_PI * rdir[1];
+    X[0] = 1.0 - delta;
+    X[1] = amag * sth * cos(phi);
+    X[2] = amag * sth * sin(phi);
+    X[3] = amag * cth;
+}
+
+void orc_heatbath_link(const double V[4], double beta, uint64_t seed, uint32_t site,
+                       uint32_t sweep, uint32_t mu, uint32_t replica, double out[4],
+                       double *margin)
+{
+    /* k = sqrt(det V); for a quaternion sum det V = |V|^2 (Sec. 2). */
+    double k = qnorm(V);
+    double Ut[4] = {1.0, 0.0, 0.0, 0.0};
+    if (k > 0.0)
+        for (int c = 0; c < 4; ++c) Ut[c] = V[c] / k;
+    double alpha = beta * k;
+    double delta = orc_sample_delta(alpha, seed, site, sweep, mu, replica, NULL, margin);
+    double rd[4];
+    block(seed, site, sweep, word2_of(mu, ORC_TAG_DIR, replica), 0u, rd, NULL);
+    double X[4], Utd[4];
+    element_from_delta(delta, rd, X);
+    /* U' = X U~^{-1} = X U~^+ */
+    orc_qdag(Ut, Utd);
+    orc_qmul(X, Utd, out);
+}
+
+/* ------------------------------------------------------------------ passes */
+static void update_site(const int32_t dims[4], double *U, int64_t s, int mu, uint32_t sweep,
+                        double beta, uint64_t seed, uint32_t replica, double *margin)
+{
+    double V[4], out[4], m;
+    orc_staple(dims, U, s, mu, V);
+    orc_heatbath_link(V, beta, seed, (uint32_t)s, sweep, (uint32_t)mu, replica, out, &m);
+    memcpy(U + (s * 4 + mu) * 4, out, sizeof(out));
+    if (margin) margin[s] = m;
+}
+
+static uint64_t splitmix(uint64_t *x)
+{
+    uint64_t z = (*x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void orc_pass(const int32_t dims[4], double *U, int mu, int parity, uint32_t sweep,
+              double beta, uint64_t seed, uint32_t replica, int order, uint64_t order_seed,
+              double *margin)
+{
+    int64_t V = orc_volume(dims);
+    if (order == 3) {
+#pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < V; ++s)
+            if (orc_parity(dims, s) == parity)
+                update_site(dims, U, s, mu, sweep, beta, seed, replica, margin);
+        return;
+    }
+    int64_t *sites = (int64_t *)malloc(sizeof(int64_t) * (size_t)V);
+    int64_t n = 0;
+    for (int64_t s = 0; s < V; ++s)
+        if (orc_parity(dims, s) == parity) sites[n++] = s;
+    if (order == 1) {
+        for (int64_t i = 0; i < n / 2; ++i) {
+            int64_t tmp = sites[i];
+            sites[i] = sites[n - 1 - i];
+            sites[n - 1 - i] = tmp;
+        }
+    } else if (order == 2) {
+        uint64_t st = order_seed;
+        for (int64_t i = n - 1; i > 0; --i) {
+            int64_t j = (int64_t)(splitmix(&st) % (uint64_t)(i + 1));
+            int64_t tmp = sites[i];
+            sites[i] = sites[j];
+            sites[j] = tmp;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        update_site(dims, U, sites[i], mu, sweep, beta, seed, replica, margin);
+    free(sites);
+}
+
+void orc_sweeps(const int32_t dims[4], double *U, int32_t nsweeps, uint32_t sweep0,
+                double beta, uint64_t seed, uint32_t replica, int32_t reunit_every,
+                int nthreads, double *plaq_hist, double *poly_hist)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int order = nthreads > 1 ? 3 : 0;
+    for (int32_t i = 0; i < nsweeps; ++i) {
+        uint32_t sw = sweep0 + (uint32_t)i;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int p = 0; p < 2; ++p)
+                orc_pass(dims, U, mu, p, sw, beta, seed, replica, order, 0, NULL);
+        if (reunit_every > 0 && ((sw + 1u) % (uint32_t)reunit_every) == 0u)
+            orc_reunitarize(dims, U);
+        if (plaq_hist) plaq_hist[i] = orc_plaquette(dims, U);
+        if (poly_hist) {
+            double ls, la;
+            orc_polyakov(dims, U, &ls, &la);
+            poly_hist[i] = ls;
+        }
+    }
+}
+
+/* ------------------------------------------------------------ init / misc */
+void orc_haar_from_block(const uint32_t w[4], double out[4])
+{
+    double u[4];
+    for (int i = 0; i < 4; ++i) u[i] = orc_uniform(w[i]);
+    double r01 = sqrt(-2.0 * log(u[0]));
+    double r23 = sqrt(-2.0 * log(u[2]));
+    double g[4] = {r01 * cos(2.0 * M_PI * u[1]), r01 * sin(2.0 * M_PI * u[1]),
+                   r23 * cos(2.0 * M_PI * u[3]), r23 * sin(2.0 * M_PI * u[3])};
+    double n = qnorm(g);
+    for (int i = 0; i < 4; ++i) out[i] = g[i] / n;
+}
+
+void orc_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint32_t replica)
+{
+    int64_t V = orc_volume(dims);
+    for (int64_t s = 0; s < V; ++s)
+        for (int mu = 0; mu < 4; ++mu) {
+            double *l = U + (s * 4 + mu) * 4;
+            if (start == 0) {
+                l[0] = 1.0; l[1] = l[2] = l[3] = 0.0;
+            } else {
+                uint32_t w[4];
+                block(seed, (uint32_t)s, 0u, word2_of((uint32_t)mu, ORC_TAG_HOT, replica), 0u,
+                      NULL, w);
+                orc_haar_from_block(w, l);
+            }
+        }
+}
+
+void orc_reunitarize(const int32_t dims[4], double *U)
+{
+    int64_t n = orc_volume(dims) * 4;
+    for (int64_t i = 0; i < n; ++i) {
+        double *l = U + 4 * i;
+        double nn = qnorm(l);
+        for (int c = 0; c < 4; ++c) l[c] /= nn;
+    }
+}
+
+/* Mean plaquette: (1/6V) sum_s sum_{mu<nu} (1/2) Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+ */
+double orc_plaquette(const int32_t dims[4], const double *U)
+{
+    int64_t V = orc_volume(dims);
+    double sum = 0.0;
+    for (int64_t s = 0; s < V; ++s)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                double a[4], b[4], t1[4], t2[4], t3[4];
+                orc_qmul(link(U, s, mu), link(U, orc_shift(dims, s, mu, 1), nu), t1);
+                orc_qdag(link(U, orc_shift(dims, s, nu, 1), mu), a);
+                orc_qmul(t1, a, t2);
+                orc_qdag(link(U, s, nu), b);
+                orc_qmul(t2, b, t3);
+                sum += t3[0];
+            }
+    return sum / (6.0 * (double)V);
+}
+
+double orc_staple_action(const int32_t dims[4], const double *U)
+{
+    int64_t V = orc_volume(dims);
+    double sum = 0.0;
+    for (int64_t s = 0; s < V; ++s)
+        for (int mu = 0; mu < 4; ++mu) {
+            double St[4], t[4];
+            orc_staple(dims, U, s, mu, St);
+            orc_qmul(link(U, s, mu), St, t);
+            sum += t[0];
+        }
+    return sum;
+}
+
+/* L(x) = (1/2) Tr prod_{t=0}^{Nt-1} U_3(x, t), t = 0 leftmost; mean over x. */
+void orc_polyakov(const int32_t dims[4], const double *U, double *mean_signed, double *abs_mean)
+{
+    int64_t Ns3 = (int64_t)dims[0] * dims[1] * dims[2];
+    double sum = 0.0;
+    for (int64_t xs = 0; xs < Ns3; ++xs) {
+        double P[4] = {1.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < dims[3]; ++t) {
+            double tmp[4];
+            orc_qmul(P, link(U, xs + Ns3 * t, 3), tmp);
+            memcpy(P, tmp, sizeof(P));
+        }
+        sum += P[0];
+    }
+    double m = sum / (double)Ns3;
+    if (mean_signed) *mean_signed = m;
+    if (abs_mean) *abs_mean = fabs(m);
+}
+
+/* U_mu(s) -> G(s) U_mu(s) G(s+mu)^+ with G Haar from Philox tag 3. */
+void orc_gauge_transform(const int32_t dims[4], double *U, uint64_t seed, uint32_t replica)
+{
+    int64_t V = orc_volume(dims);
+    double *G = (double *)malloc(sizeof(double) * 4 * (size_t)V);
+    for (int64_t s = 0; s < V; ++s) {
+        uint32_t w[4];
+        block(seed, (uint32_t)s, 0u, word2_of(0u, ORC_TAG_GAUGE, replica), 0u, NULL, w);
+        orc_haar_from_block(w, G + 4 * s);
+    }
+    for (int64_t s = 0; s < V; ++s)
+        for (int mu = 0; mu < 4; ++mu) {
+            double *l = U + (s * 4 + mu) * 4;
+            double gd[4], t[4];
+            orc_qdag(G + 4 * orc_shift(dims, s, mu, 1), gd);
+            orc_qmul(G + 4 * s, l, t);
+            orc_qmul(t, gd, l);
+        }
+    free(G);
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

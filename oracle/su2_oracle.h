@@ -1,0 +1,108 @@
+/*
+ * su2_oracle.h -- plain FP64 CPU reference for the pure-gauge SU(2) heat bath.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This oracle exists to check the GPU library; it is
+ * compiled and called only by the test suite, the smoke check and the CPU
+ * baseline of the benchmark.  The product path never links or calls it, and it
+ * shares no source with the GPU library (its own Philox, its own quaternion
+ * algebra, its own lattice indexing).
+ *
+ * Paper: N. Cardoso and P. Bicudo, "Lattice SU(2) on GPU's", LAT2010
+ * (arXiv:1010.1486).  The update equations follow Sec. 2 of the paper; the
+ * schedule (per direction, even sites then odd sites) follows Sec. 4 and the
+ * caption of its Fig. 3.
+ *
+ * Conventions (identical to the GPU library, restated here independently):
+ *   site    s = x + Nx*(y + Ny*(z + Nz*t)), directions mu = 0:x 1:y 2:z 3:t
+ *   parity  (x+y+z+t) & 1; every extent must be even and >= 2
+ *   links   U[(s*4 + mu)*4 + c], c = a0..a3 with U = a0*1 + i a.sigma
+ *   randoms Philox4x32-10, key = seed, counter = (site, sweep,
+ *           mu | tag<<2 | replica<<6, draw); tags: 0 a0 trials, 1 direction,
+ *           2 hot start, 3 gauge transform, 4 learned proposal, 5 training data,
+ *           6 replica beta
+ */
+#ifndef SU2_ORACLE_H
+#define SU2_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_TAG_TRIAL 0u
+#define ORC_TAG_DIR 1u
+#define ORC_TAG_HOT 2u
+#define ORC_TAG_GAUGE 3u
+#define ORC_TAG_LEARN 4u
+#define ORC_TAG_TRAIN 5u
+#define ORC_TAG_BETA 6u
+
+/* Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Batch form for tests: n counters (4 words each) -> n outputs. */
+void orc_philox_batch(int64_t n, const uint32_t *ctr, uint64_t seed, uint32_t *out);
+/* 32-bit word -> uniform in (0,1): (2*(w>>9)+1) * 2^-24. */
+double orc_uniform(uint32_t w);
+
+/* Quaternion algebra for U = a0 + i a.sigma. */
+void orc_qmul(const double a[4], const double b[4], double c[4]);
+void orc_qdag(const double a[4], double c[4]);
+void orc_qmul_batch(int64_t n, const double *a, const double *b, double *c);
+
+/* Lattice indexing. */
+int orc_check_dims(const int32_t dims[4]);               /* 0 ok, -1 bad */
+int64_t orc_volume(const int32_t dims[4]);
+int orc_parity(const int32_t dims[4], int64_t s);
+int64_t orc_shift(const int32_t dims[4], int64_t s, int mu, int step);
+
+/* Sum of the six staples around U_mu(s) (Sec. 2). */
+void orc_staple(const int32_t dims[4], const double *U, int64_t s, int mu, double V[4]);
+
+/* Exact a0 sampler for density ~ sqrt(1-a0^2) exp(alpha a0).  Returns
+ * delta = 1 - a0; *ntrials = trials used; *margin = smallest |decision margin|
+ * of every floating-point decision taken (branch choice and accept tests). */
+double orc_sample_delta(double alpha, uint64_t seed, uint32_t site, uint32_t sweep,
+                        uint32_t mu, uint32_t replica, int32_t *ntrials, double *margin);
+void orc_sample_delta_batch(int64_t n, const double *alpha, uint64_t seed,
+                            const uint32_t *site, uint32_t sweep, uint32_t mu,
+                            uint32_t replica, double *delta, int32_t *ntrials,
+                            double *margin);
+
+/* Heat-bath update of one link given its staple sum V (writes the new link). */
+void orc_heatbath_link(const double V[4], double beta, uint64_t seed, uint32_t site,
+                       uint32_t sweep, uint32_t mu, uint32_t replica, double out[4],
+                       double *margin);
+
+/* One checkerboard pass over every site of the given parity, direction mu.
+ * order: 0 lexicographic, 1 reversed, 2 shuffled (order_seed), 3 OpenMP.
+ * margin (length V, may be NULL) receives each updated site's smallest margin. */
+void orc_pass(const int32_t dims[4], double *U, int mu, int parity, uint32_t sweep,
+              double beta, uint64_t seed, uint32_t replica, int order, uint64_t order_seed,
+              double *margin);
+/* nsweeps full sweeps (mu 0..3, even then odd) starting at sweep index sweep0.
+ * reunit_every > 0 reunitarises after every sweep whose 1-based count is a
+ * multiple of it.  plaq_hist (may be NULL) receives the plaquette after every
+ * sweep.  nthreads > 1 uses OpenMP inside each pass. */
+void orc_sweeps(const int32_t dims[4], double *U, int32_t nsweeps, uint32_t sweep0,
+                double beta, uint64_t seed, uint32_t replica, int32_t reunit_every,
+                int nthreads, double *plaq_hist, double *poly_hist);
+
+void orc_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint32_t replica);
+void orc_reunitarize(const int32_t dims[4], double *U);
+double orc_plaquette(const int32_t dims[4], const double *U);
+/* sum over all sites and mu of (1/2) Tr(U_mu(s) V(s,mu)). */
+double orc_staple_action(const int32_t dims[4], const double *U);
+void orc_polyakov(const int32_t dims[4], const double *U, double *mean_signed,
+                  double *abs_mean);
+void orc_gauge_transform(const int32_t dims[4], double *U, uint64_t seed, uint32_t replica);
+/* Haar-random SU(2) element from one Philox block (Box-Muller + normalise). */
+void orc_haar_from_block(const uint32_t w[4], double out[4]);
+
+int orc_max_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif
