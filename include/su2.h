@@ -1,0 +1,157 @@
+/*
+ * su2.h -- C ABI of libsu2, the MI355X (gfx950) SU(2) pure-gauge heat bath.
+ *
+ * Method: N. Cardoso and P. Bicudo, "Lattice SU(2) on GPU's", LAT2010
+ * (arXiv:1010.1486).  Sec. 2 defines the update: for each link, the staple
+ * sum V of the six neighbouring products, k = sqrt(det V), U~ = V/k, a0 drawn
+ * from sqrt(1 - a0^2) exp(beta k a0), a uniform direction for the rest of the
+ * element X, and U' = X U~^{-1}.  Sec. 4 (and the caption of its Fig. 3) fixes
+ * the schedule: per direction mu, first the even sites, then the odd sites,
+ * eight passes per sweep; and the measurements: mean plaquette and Polyakov
+ * loop summed over the lattice.
+ *
+ * Conventions
+ *   Lattice     periodic Nx x Ny x Nz x Nt, every extent even and >= 2; site
+ *               s = x + Nx*(y + Ny*(z + Nz*t)); mu = 0:x 1:y 2:z 3:t; parity
+ *               (x+y+z+t) & 1.
+ *   Links       U = a0 + i a.sigma stored as 4 FP32 reals.  Device layout: 32
+ *               planes of V/2 floats, plane ((mu*2 + parity)*4 + c) holding
+ *               component c of U_mu at the half-site h = s >> 1 of every site
+ *               of that parity (64*V bytes).  Host exchange layout (get/set):
+ *               float[V][4 mu][4 c] in canonical site order.
+ *   Randoms     Philox4x32-10, key = seed, counter = (site, sweep index,
+ *               mu | tag<<2 | replica<<6, draw).  Results are bit-identical
+ *               for identical (links, seed, sweep index, replica, beta).
+ *   Sampler     alpha = beta k >= 1: Kennedy-Pendleton; alpha < 1: rejection
+ *               from the Haar (semicircle) marginal; both exact.
+ *
+ * Errors: every function returns SU2_OK (0) or a negative code and never
+ * aborts; su2_last_error() gives a thread-local message for the last failure.
+ * Asynchrony: functions documented as "enqueue" return after launching work on
+ * the context's stream; functions returning host values synchronise it.
+ * Threading: contexts are independent; one context must not be used from two
+ * host threads at once.
+ */
+#ifndef SU2_H
+#define SU2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct su2_ctx su2_ctx;
+
+enum {
+    SU2_OK = 0,
+    SU2_EINVAL = -1, /* null pointer, negative count, non-finite beta, bad enum */
+    SU2_EODD = -2,   /* an extent is odd or < 2 (the checkerboard needs even extents) */
+    SU2_ENOMEM = -3, /* device allocation failed, or caller buffer too small */
+    SU2_EHIP = -4,   /* a HIP runtime call failed (message has the HIP error string) */
+    SU2_ESTATE = -5, /* call not valid in the context's state (e.g. no proposal loaded) */
+    SU2_ERANGE = -6  /* a size exceeds the library's index range (V/2 >= 2^31) */
+};
+
+enum { SU2_COLD = 0, SU2_HOT = 1 };
+enum { SU2_KP = 0, SU2_LEARNED = 1 };
+enum { SU2_MEAS_PLAQ = 1, SU2_MEAS_POLY = 2 };
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char *su2_last_error(void);
+
+/* Device bytes the caller must provide to su2_init_ext for these extents:
+ * links 64*V; scratch = counters, FP64 result slots and FP64 block partials.
+ * Return 0 when the extents are invalid. */
+size_t su2_links_bytes(const int32_t dims[4]);
+size_t su2_scratch_bytes(const int32_t dims[4]);
+
+/* Create a context with library-owned device memory and stream, and write the
+ * cold (all links 1) or hot (Haar-random, Philox tag 2) start (Sec. 4: the
+ * initialisation kernels).  dims: host array of 4 extents.  The sweep index
+ * starts at 0.  Free with su2_destroy. */
+int su2_init(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start);
+
+/* As su2_init, but on caller-owned device memory and stream: links_dev
+ * (>= su2_links_bytes) and scratch_dev (>= su2_scratch_bytes), both device
+ * pointers that the caller keeps alive until su2_destroy; hip_stream is a
+ * hipStream_t (NULL = the null stream).  The library allocates no device
+ * memory for the context. */
+int su2_init_ext(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
+                 void *links_dev, size_t links_bytes, void *scratch_dev, size_t scratch_bytes,
+                 void *hip_stream);
+
+/* Synchronise the stream and release the context (and library-owned memory). */
+int su2_destroy(su2_ctx *ctx);
+
+/* Enqueue nsweeps (>= 0) heat-bath sweeps (Sec. 2 update, Sec. 4 schedule: for
+ * mu = 0..3, even sites then odd sites).  mode SU2_KP uses the exact sampler;
+ * SU2_LEARNED the learned proposal with an exact Metropolis step (needs
+ * su2_set_proposal).  The sweep index advances by nsweeps. */
+int su2_heatbath_sweep(su2_ctx *ctx, int32_t nsweeps, int mode);
+
+/* Enqueue nsweeps sweeps and measure after each one.  reunit_every > 0
+ * reunitarises after every sweep whose index j satisfies (j+1) % reunit_every
+ * == 0, before measuring.  meas: SU2_MEAS_PLAQ | SU2_MEAS_POLY.  dev_history:
+ * device FP64 buffer of 3*nsweeps entries, receiving (plaquette, signed mean
+ * Polyakov loop, its absolute value) per sweep (0 where not measured).  The
+ * plaquette is fused into the odd passes of mu = 1, 2, 3 (no extra read of the
+ * field) except on reunitarisation sweeps, where it is measured afterwards. */
+int su2_sweep_measure(su2_ctx *ctx, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
+                      double *dev_history);
+
+/* Enqueue U <- U/|U| for every link, |U|^2 in FP64. */
+int su2_reunitarize(su2_ctx *ctx);
+
+/* Mean plaquette (1/6V) sum_s sum_{mu<nu} (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+
+ * U_nu(s)^+ (Sec. 4), per-site FP32 products, FP64 global sum.  Synchronous:
+ * *out is a host pointer. */
+int su2_plaquette(su2_ctx *ctx, double *out);
+
+/* Mean Polyakov loop (1/Ns^3) sum_x (1/2)Tr prod_{t=0}^{Nt-1} U_3(x,t) (Sec. 4),
+ * ordered product with t = 0 leftmost, FP64 sum; and its absolute value.
+ * Synchronous; host pointers (either may be NULL). */
+int su2_polyakov(su2_ctx *ctx, double *out_signed, double *out_abs);
+
+/* Copy links to / from the host exchange layout float[V][4][4] (host pointer,
+ * 64*V bytes).  Synchronous. */
+int su2_get_links(su2_ctx *ctx, float *host);
+int su2_set_links(su2_ctx *ctx, const float *host);
+
+/* Sweep index (Philox counter word 1) of the next sweep; beta; replica id
+ * (Philox counter word 2 bits 6..31).  Setters apply to work enqueued later. */
+int su2_get_sweep(su2_ctx *ctx, uint32_t *out);
+int su2_set_sweep(su2_ctx *ctx, uint32_t sweep);
+int su2_set_beta(su2_ctx *ctx, double beta);
+int su2_set_replica(su2_ctx *ctx, uint32_t replica);
+
+/* Device pointer of the link planes and the context's hipStream_t. */
+int su2_links_device(su2_ctx *ctx, void **links_dev, void **hip_stream);
+
+/* Wait for all work enqueued on the context's stream. */
+int su2_synchronize(su2_ctx *ctx);
+
+/* Launch configuration of the pass kernel: block size (64..1024, multiple of
+ * 64) and the XCD-contiguous workgroup remap (0/1). */
+int su2_set_launch(su2_ctx *ctx, int block, int xcd_remap);
+
+/* ----------------------------------------------------------- test hooks */
+/* Philox4x32-10 on the GPU: n counters (host, 4 words each) -> host out. */
+int su2_test_philox(const uint32_t *ctr_host, int64_t n, uint64_t seed, uint32_t *out_host);
+/* Heat-bath update of n independent links from given staple sums V (host,
+ * float[n][4]); link i uses site index i.  out_host float[n][4]; ntrials_host
+ * (may be NULL) receives the sampler's trial count per link. */
+int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_t seed,
+                            uint32_t sweep, uint32_t mu, uint32_t replica, float *out_host,
+                            int32_t *ntrials_host);
+/* Enqueue one (mu, parity) pass at the current sweep index (index unchanged). */
+int su2_test_pass(su2_ctx *ctx, int mu, int parity);
+/* Enqueue U_mu(x) -> G(x) U_mu(x) G(x+mu)^+ with G Haar from Philox tag 3. */
+int su2_test_gauge_transform(su2_ctx *ctx, uint64_t seed);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SU2_H */

@@ -20,7 +20,9 @@
  *     exact rejection from the Haar (semicircle) marginal with acceptance
  *     exp(alpha (a0 - 1)); both capped at SAMPLER_TRIAL_CAP trials (the cap is
  *     unreachable in practice: acceptance is >= 0.41 for every alpha).
- *   - direction of a: uniform on the sphere, |a| = sqrt(delta (2 - delta)).
+ *   - direction of a: uniform on the sphere, |a| = sqrt(delta (2 - delta)),
+ *     its two uniforms taken from the unused low 9 bits of the words of the
+ *     first trial's block (18-bit uniforms).
  *   - randoms: Philox4x32-10 keyed by the seed, counter (site, sweep,
  *     mu | tag<<2 | replica<<6, draw), words mapped to (2*(w>>9)+1) 2^-24.
  */
@@ -71,6 +73,11 @@ void orc_philox_batch(int64_t n, const uint32_t *ctr, uint64_t seed, uint32_t *o
 double orc_uniform(uint32_t w)
 {
     return (2.0 * (double)(w >> 9) + 1.0) * ldexp(1.0, -24);
+}
+
+double orc_uniform18(uint32_t m)
+{
+    return (2.0 * (double)(m & 0x3FFFFu) + 1.0) * ldexp(1.0, -19);
 }
 
 static void block(uint64_t seed, uint32_t site, uint32_t sweep, uint32_t word2,
@@ -271,8 +278,14 @@ void orc_heatbath_link(const double V[4], double beta, uint64_t seed, uint32_t s
         for (int c = 0; c < 4; ++c) Ut[c] = V[c] / k;
     double alpha = beta * k;
     double delta = orc_sample_delta(alpha, seed, site, sweep, mu, replica, NULL, margin);
-    double rd[4];
-    block(seed, site, sweep, word2_of(mu, ORC_TAG_DIR, replica), 0u, rd, NULL);
+    /* Direction uniforms: the 9 low bits of each word of the first trial's
+     * block are not used by the a0 uniforms (which take bits 9..31); they give
+     * two independent 18-bit uniforms (2m+1) 2^-19. */
+    uint32_t w[4];
+    block(seed, site, sweep, word2_of(mu, ORC_TAG_TRIAL, replica), 0u, NULL, w);
+    double rd[2];
+    rd[0] = orc_uniform18((w[0] & 511u) | ((w[1] & 511u) << 9));
+    rd[1] = orc_uniform18((w[2] & 511u) | ((w[3] & 511u) << 9));
     double X[4], Utd[4];
     element_from_delta(delta, rd, X);
     /* U' = X U~^{-1} = X U~^+ */

@@ -17,7 +17,8 @@
  *   parity  (x+y+z+t) & 1; every extent must be even and >= 2
  *   links   U[(s*4 + mu)*4 + c], c = a0..a3 with U = a0*1 + i a.sigma
  *   randoms Philox4x32-10, key = seed, counter = (site, sweep,
- *           mu | tag<<2 | replica<<6, draw); tags: 0 a0 trials, 1 direction,
+ *           mu | tag<<2 | replica<<6, draw); tags: 0 a0 trials (the low 9 bits
+ *           of the words of draw 0 give the direction), 1 reserved,
  *           2 hot start, 3 gauge transform, 4 learned proposal, 5 training data,
  *           6 replica beta
  */
@@ -44,6 +45,8 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 void orc_philox_batch(int64_t n, const uint32_t *ctr, uint64_t seed, uint32_t *out);
 /* 32-bit word -> uniform in (0,1): (2*(w>>9)+1) * 2^-24. */
 double orc_uniform(uint32_t w);
+/* 18-bit value m -> (2m+1) * 2^-19 (direction uniforms). */
+double orc_uniform18(uint32_t m);
 
 /* Quaternion algebra for U = a0 + i a.sigma. */
 void orc_qmul(const double a[4], const double b[4], double c[4]);

@@ -37,6 +37,7 @@ def _load():
         "orc_philox4x32_10": (None, [_u32p, _u32p, _u32p]),
         "orc_philox_batch": (None, [c_i64, _u32p, c_u64, _u32p]),
         "orc_uniform": (c_d, [c_u32]),
+        "orc_uniform18": (c_d, [c_u32]),
         "orc_qmul_batch": (None, [c_i64, _f64p, _f64p, _f64p]),
         "orc_check_dims": (c_int, [_i32p]),
         "orc_volume": (c_i64, [_i32p]),
@@ -77,7 +78,7 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-TAG_TRIAL, TAG_DIR, TAG_HOT, TAG_GAUGE, TAG_LEARN, TAG_TRAIN, TAG_BETA = range(7)
+TAG_TRIAL, TAG_RESERVED, TAG_HOT, TAG_GAUGE, TAG_LEARN, TAG_TRAIN, TAG_BETA = range(7)
 
 
 def word2(mu, tag, replica=0):

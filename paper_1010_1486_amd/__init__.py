@@ -1,0 +1,5 @@
+"""MI355X-native SU(2) pure-gauge heat bath (Cardoso & Bicudo, "Lattice SU(2)
+on GPU's").  The compute path is libsu2.so (HIP kernels for gfx950 behind the
+C ABI of include/su2.h); this package is its Python binding."""
+from .su2 import *  # noqa: F401,F403
+from .su2 import Lattice, SU2Error, lib, header_functions  # noqa: F401

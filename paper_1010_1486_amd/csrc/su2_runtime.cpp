@@ -1,0 +1,532 @@
+// su2_runtime.cpp -- C ABI of libsu2: contexts, argument checks, memory,
+// the sweep schedule (Sec. 4: per direction, even then odd sites) and the
+// measurement plumbing around the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/su2.h"
+#include "su2_internal.h"
+
+using su2dev::Geom;
+
+namespace su2rt {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+}  // namespace su2rt
+
+using namespace su2rt;
+
+struct su2_ctx {
+    int32_t dims[4];
+    Geom g;
+    int64_t volume;
+    double beta;
+    uint64_t seed;
+    uint32_t replica;
+    uint32_t sweep;  // host mirror of the device sweep counter
+    float *links;
+    size_t links_bytes;
+    unsigned char *scratch;
+    size_t scratch_bytes;
+    bool own_mem;
+    bool own_stream;
+    hipStream_t stream;
+    LaunchCfg cfg;
+
+    Counters *counters() { return reinterpret_cast<Counters *>(scratch + kCountersOff); }
+    double *results() { return reinterpret_cast<double *>(scratch + kResultsOff); }
+    double *partials() { return reinterpret_cast<double *>(scratch + kPartialsOff); }
+    size_t partial_stride() const { return max_partial_blocks(volume); }
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));              \
+            return SU2_EHIP;                                                            \
+        }                                                                               \
+    } while (0)
+
+int fail(int code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int check_dims(const int32_t *dims)
+{
+    if (!dims) return fail(SU2_EINVAL, "dims is NULL");
+    for (int i = 0; i < 4; ++i)
+        if (dims[i] < 2 || (dims[i] & 1))
+            return fail(SU2_EODD, "every extent must be even and >= 2 (got " +
+                                      std::to_string(dims[i]) + " in direction " +
+                                      std::to_string(i) + ")");
+    int64_t v = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+    if (v / 2 >= (int64_t)1 << 31) return fail(SU2_ERANGE, "V/2 must be < 2^31");
+    return SU2_OK;
+}
+
+Geom make_geom(const int32_t *d)
+{
+    Geom g;
+    g.nx = d[0];
+    g.ny = d[1];
+    g.nz = d[2];
+    g.nt = d[3];
+    g.vh = (uint32_t)(((int64_t)d[0] * d[1] * d[2] * d[3]) / 2);
+    g.hx = (uint32_t)(d[0] / 2);
+    g.sy = g.hx;
+    g.sz = g.hx * (uint32_t)d[1];
+    g.st = g.sz * (uint32_t)d[2];
+    return g;
+}
+
+size_t scratch_bytes_for(int64_t volume)
+{
+    return kPartialsOff + sizeof(double) * kPartialArrays * max_partial_blocks(volume);
+}
+
+int check_ctx(su2_ctx *c)
+{
+    if (!c) return fail(SU2_EINVAL, "context is NULL");
+    return SU2_OK;
+}
+
+// The sweep index the device uses is read from the device counter; keep the
+// host mirror in step.
+int enqueue_sweeps(su2_ctx *c, int32_t n, int mode, int32_t reunit_every, int meas,
+                   double *hist)
+{
+    if (mode != SU2_KP && mode != SU2_LEARNED) return fail(SU2_EINVAL, "unknown mode");
+    if (mode == SU2_LEARNED) return fail(SU2_ESTATE, "no learned proposal loaded");
+    const float beta = (float)c->beta;
+    const size_t stride = c->partial_stride();
+    double *part = c->partials();
+    const int nb_pass = pass_grid(c->g, c->cfg);
+    const double inv6v = 1.0 / (6.0 * (double)c->volume);
+    // history slots restart at 0 for this call
+    if (hist) HIP_TRY(launch_set_counter(c->counters(), 0, 0, 2, c->stream));
+    for (int32_t i = 0; i < n; ++i) {
+        const uint32_t j = c->sweep + (uint32_t)i;
+        const bool reunit = reunit_every > 0 && ((j + 1u) % (uint32_t)reunit_every) == 0u;
+        const bool fused = hist && (meas & SU2_MEAS_PLAQ) && !reunit;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int par = 0; par < 2; ++par) {
+                double *pp = (fused && par == 1 && mu >= 1) ? part + (size_t)(mu - 1) * stride
+                                                            : nullptr;
+                HIP_TRY(launch_pass(c->links, c->g, mu, par, &c->counters()->sweep, beta,
+                                    c->seed, c->replica, pp, c->cfg, c->stream));
+            }
+        int mflags = 0;
+        if (reunit) HIP_TRY(launch_reunitarize(c->links, c->g, c->stream));
+        if (hist && (meas & SU2_MEAS_PLAQ)) {
+            if (fused) {
+                mflags |= 1;
+            } else {
+                int nb = 0;
+                HIP_TRY(launch_plaquette(c->links, c->g, part + 3 * stride, &nb, c->stream));
+                HIP_TRY(launch_finalize(part + 3 * stride, nb, 1, stride, inv6v,
+                                        c->results() + R_PLAQ, 0, c->stream));
+                mflags |= 2;
+            }
+        }
+        if (hist && (meas & SU2_MEAS_POLY)) {
+            int nb = 0;
+            const double inv_ns3 = 1.0 / ((double)c->dims[0] * c->dims[1] * c->dims[2]);
+            HIP_TRY(launch_polyakov(c->links, c->g, part + 3 * stride, &nb, c->stream));
+            HIP_TRY(launch_finalize(part + 3 * stride, nb, 1, stride, inv_ns3,
+                                    c->results() + R_POLY_SIGNED, 1, c->stream));
+            mflags |= 4;
+        }
+        if (hist && !mflags) mflags = 8;  // history row of zeros
+        HIP_TRY(launch_sweep_end(c->counters(), part, nb_pass, stride, inv6v, mflags, hist,
+                                 c->results(), c->stream));
+    }
+    c->sweep += (uint32_t)n;
+    return SU2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *su2_last_error(void) { return g_last_error.c_str(); }
+
+size_t su2_links_bytes(const int32_t dims[4])
+{
+    if (!dims) return 0;
+    for (int i = 0; i < 4; ++i)
+        if (dims[i] < 2 || (dims[i] & 1)) return 0;
+    return (size_t)64 * (size_t)dims[0] * dims[1] * dims[2] * dims[3];
+}
+
+size_t su2_scratch_bytes(const int32_t dims[4])
+{
+    if (!su2_links_bytes(dims)) return 0;
+    return scratch_bytes_for((int64_t)dims[0] * dims[1] * dims[2] * dims[3]);
+}
+
+static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed,
+                       int start, void *links_dev, size_t links_bytes, void *scratch_dev,
+                       size_t scratch_bytes, void *stream, bool ext)
+{
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
+    if (start != SU2_COLD && start != SU2_HOT) return fail(SU2_EINVAL, "start must be COLD or HOT");
+    const size_t need_l = su2_links_bytes(dims), need_s = su2_scratch_bytes(dims);
+    if (ext) {
+        if (!links_dev || !scratch_dev) return fail(SU2_EINVAL, "device buffer is NULL");
+        if (links_bytes < need_l || scratch_bytes < need_s)
+            return fail(SU2_ENOMEM, "caller buffers too small: need links " +
+                                        std::to_string(need_l) + " B, scratch " +
+                                        std::to_string(need_s) + " B");
+    }
+    su2_ctx *c = new (std::nothrow) su2_ctx();
+    if (!c) return fail(SU2_ENOMEM, "host allocation failed");
+    std::memcpy(c->dims, dims, sizeof(c->dims));
+    c->g = make_geom(dims);
+    c->volume = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+    c->beta = beta;
+    c->seed = seed;
+    c->replica = 0;
+    c->sweep = 0;
+    c->links_bytes = need_l;
+    c->scratch_bytes = need_s;
+    c->own_mem = !ext;
+    c->own_stream = false;
+    if (ext) {
+        c->links = static_cast<float *>(links_dev);
+        c->scratch = static_cast<unsigned char *>(scratch_dev);
+        c->stream = static_cast<hipStream_t>(stream);
+    } else {
+        void *l = nullptr, *s = nullptr;
+        hipError_t e = hipMalloc(&l, need_l);
+        if (e == hipSuccess) e = hipMalloc(&s, need_s);
+        if (e != hipSuccess) {
+            if (l) (void)hipFree(l);
+            delete c;
+            return fail(e == hipErrorOutOfMemory ? SU2_ENOMEM : SU2_EHIP,
+                        std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        c->links = static_cast<float *>(l);
+        c->scratch = static_cast<unsigned char *>(s);
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            (void)hipFree(l);
+            (void)hipFree(s);
+            delete c;
+            return fail(SU2_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        c->stream = st;
+        c->own_stream = true;
+    }
+    hipError_t e = launch_set_counter(c->counters(), 0, 0, 3, c->stream);
+    if (e == hipSuccess) e = launch_init(c->links, c->g, start, seed, 0, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        set_error(std::string("init: ") + hipGetErrorString(e));
+        su2_destroy(c);
+        return SU2_EHIP;
+    }
+    *out = c;
+    return SU2_OK;
+}
+
+int su2_init(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start)
+{
+    return init_common(out, dims, beta, seed, start, nullptr, 0, nullptr, 0, nullptr, false);
+}
+
+int su2_init_ext(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
+                 void *links_dev, size_t links_bytes, void *scratch_dev, size_t scratch_bytes,
+                 void *hip_stream)
+{
+    return init_common(out, dims, beta, seed, start, links_dev, links_bytes, scratch_dev,
+                       scratch_bytes, hip_stream, true);
+}
+
+int su2_destroy(su2_ctx *c)
+{
+    if (!c) return fail(SU2_EINVAL, "context is NULL");
+    int rc = SU2_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(SU2_EHIP, "sync on destroy");
+    if (c->own_mem) {
+        (void)hipFree(c->links);
+        (void)hipFree(c->scratch);
+    }
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return rc;
+}
+
+int su2_heatbath_sweep(su2_ctx *c, int32_t nsweeps, int mode)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (nsweeps < 0) return fail(SU2_EINVAL, "nsweeps must be >= 0");
+    return enqueue_sweeps(c, nsweeps, mode, 0, 0, nullptr);
+}
+
+int su2_sweep_measure(su2_ctx *c, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
+                      double *dev_history)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (nsweeps < 0 || reunit_every < 0) return fail(SU2_EINVAL, "negative count");
+    if (!dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
+    if (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)) return fail(SU2_EINVAL, "bad meas flags");
+    return enqueue_sweeps(c, nsweeps, mode, reunit_every, meas, dev_history);
+}
+
+int su2_reunitarize(su2_ctx *c)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    HIP_TRY(launch_reunitarize(c->links, c->g, c->stream));
+    return SU2_OK;
+}
+
+int su2_plaquette(su2_ctx *c, double *out)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    const size_t stride = c->partial_stride();
+    double *part = c->partials() + 3 * stride;
+    int nb = 0;
+    HIP_TRY(launch_plaquette(c->links, c->g, part, &nb, c->stream));
+    HIP_TRY(launch_finalize(part, nb, 1, stride, 1.0 / (6.0 * (double)c->volume),
+                            c->results() + R_PLAQ, 0, c->stream));
+    double v = 0.0;
+    HIP_TRY(hipMemcpyAsync(&v, c->results() + R_PLAQ, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *out = v;
+    return SU2_OK;
+}
+
+int su2_polyakov(su2_ctx *c, double *out_signed, double *out_abs)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    const size_t stride = c->partial_stride();
+    double *part = c->partials() + 3 * stride;
+    int nb = 0;
+    HIP_TRY(launch_polyakov(c->links, c->g, part, &nb, c->stream));
+    HIP_TRY(launch_finalize(part, nb, 1, stride,
+                            1.0 / ((double)c->dims[0] * c->dims[1] * c->dims[2]),
+                            c->results() + R_POLY_SIGNED, 1, c->stream));
+    double v[2] = {0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(v, c->results() + R_POLY_SIGNED, 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (out_signed) *out_signed = v[0];
+    if (out_abs) *out_abs = v[1];
+    return SU2_OK;
+}
+
+int su2_get_links(su2_ctx *c, float *host)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!host) return fail(SU2_EINVAL, "host is NULL");
+    std::vector<float> planes(c->links_bytes / sizeof(float));
+    HIP_TRY(hipMemcpyAsync(planes.data(), c->links, c->links_bytes, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int64_t vh = c->g.vh;
+    const int32_t *d = c->dims;
+    for (int64_t s = 0; s < c->volume; ++s) {
+        int64_t r = s;
+        const int x = (int)(r % d[0]);
+        r /= d[0];
+        const int y = (int)(r % d[1]);
+        r /= d[1];
+        const int z = (int)(r % d[2]);
+        const int t = (int)(r / d[2]);
+        const int par = (x + y + z + t) & 1;
+        const int64_t h = s >> 1;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int k = 0; k < 4; ++k)
+                host[(s * 4 + mu) * 4 + k] = planes[((mu * 2 + par) * 4 + k) * vh + h];
+    }
+    return SU2_OK;
+}
+
+int su2_set_links(su2_ctx *c, const float *host)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!host) return fail(SU2_EINVAL, "host is NULL");
+    std::vector<float> planes(c->links_bytes / sizeof(float));
+    const int64_t vh = c->g.vh;
+    const int32_t *d = c->dims;
+    for (int64_t s = 0; s < c->volume; ++s) {
+        int64_t r = s;
+        const int x = (int)(r % d[0]);
+        r /= d[0];
+        const int y = (int)(r % d[1]);
+        r /= d[1];
+        const int z = (int)(r % d[2]);
+        const int t = (int)(r / d[2]);
+        const int par = (x + y + z + t) & 1;
+        const int64_t h = s >> 1;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int k = 0; k < 4; ++k)
+                planes[((mu * 2 + par) * 4 + k) * vh + h] = host[(s * 4 + mu) * 4 + k];
+    }
+    HIP_TRY(hipMemcpyAsync(c->links, planes.data(), c->links_bytes, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SU2_OK;
+}
+
+int su2_get_sweep(su2_ctx *c, uint32_t *out)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    *out = c->sweep;
+    return SU2_OK;
+}
+
+int su2_set_sweep(su2_ctx *c, uint32_t sweep)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    HIP_TRY(launch_set_counter(c->counters(), sweep, 0, 1, c->stream));
+    c->sweep = sweep;
+    return SU2_OK;
+}
+
+int su2_set_beta(su2_ctx *c, double beta)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
+    c->beta = beta;
+    return SU2_OK;
+}
+
+int su2_set_replica(su2_ctx *c, uint32_t replica)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (replica >= (1u << 26)) return fail(SU2_EINVAL, "replica id must be < 2^26");
+    c->replica = replica;
+    return SU2_OK;
+}
+
+int su2_links_device(su2_ctx *c, void **links_dev, void **hip_stream)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (links_dev) *links_dev = c->links;
+    if (hip_stream) *hip_stream = c->stream;
+    return SU2_OK;
+}
+
+int su2_synchronize(su2_ctx *c)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SU2_OK;
+}
+
+int su2_set_launch(su2_ctx *c, int block, int xcd_remap)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (block < 64 || block > 256 || (block % 64) != 0)
+        return fail(SU2_EINVAL, "block must be 64, 128, 192 or 256");
+    c->cfg.pass_block = block;
+    c->cfg.xcd_remap = xcd_remap != 0;
+    return SU2_OK;
+}
+
+int su2_test_philox(const uint32_t *ctr_host, int64_t n, uint64_t seed, uint32_t *out_host)
+{
+    if (n < 0 || (n > 0 && (!ctr_host || !out_host))) return fail(SU2_EINVAL, "bad arguments");
+    if (n == 0) return SU2_OK;
+    void *d_in = nullptr, *d_out = nullptr;
+    const size_t bytes = (size_t)n * 16;
+    HIP_TRY(hipMalloc(&d_in, bytes));
+    hipError_t e = hipMalloc(&d_out, bytes);
+    if (e == hipSuccess) e = hipMemcpy(d_in, ctr_host, bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_test_philox((const uint32_t *)d_in, n, seed, (uint32_t *)d_out, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out_host, d_out, bytes, hipMemcpyDeviceToHost);
+    (void)hipFree(d_in);
+    if (d_out) (void)hipFree(d_out);
+    if (e != hipSuccess) return fail(SU2_EHIP, std::string("test_philox: ") + hipGetErrorString(e));
+    return SU2_OK;
+}
+
+int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_t seed,
+                            uint32_t sweep, uint32_t mu, uint32_t replica, float *out_host,
+                            int32_t *ntrials_host)
+{
+    if (n < 0 || (n > 0 && (!V_host || !out_host))) return fail(SU2_EINVAL, "bad arguments");
+    if (!std::isfinite(beta) || mu > 3) return fail(SU2_EINVAL, "bad beta or mu");
+    if (n >= ((int64_t)1 << 32)) return fail(SU2_ERANGE, "n must be < 2^32");
+    if (n == 0) return SU2_OK;
+    void *d_v = nullptr, *d_o = nullptr, *d_t = nullptr;
+    const size_t bytes = (size_t)n * 16;
+    HIP_TRY(hipMalloc(&d_v, bytes));
+    hipError_t e = hipMalloc(&d_o, bytes);
+    if (e == hipSuccess && ntrials_host) e = hipMalloc(&d_t, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMemcpy(d_v, V_host, bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_test_links((const float *)d_v, n, (float)beta, seed, sweep, mu, replica,
+                              (float *)d_o, (int32_t *)d_t, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out_host, d_o, bytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ntrials_host)
+        e = hipMemcpy(ntrials_host, d_t, (size_t)n * 4, hipMemcpyDeviceToHost);
+    (void)hipFree(d_v);
+    if (d_o) (void)hipFree(d_o);
+    if (d_t) (void)hipFree(d_t);
+    if (e != hipSuccess)
+        return fail(SU2_EHIP, std::string("test_heatbath_links: ") + hipGetErrorString(e));
+    return SU2_OK;
+}
+
+int su2_test_pass(su2_ctx *c, int mu, int parity)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (mu < 0 || mu > 3 || parity < 0 || parity > 1) return fail(SU2_EINVAL, "bad mu/parity");
+    HIP_TRY(launch_pass(c->links, c->g, mu, parity, &c->counters()->sweep, (float)c->beta,
+                        c->seed, c->replica, nullptr, c->cfg, c->stream));
+    return SU2_OK;
+}
+
+int su2_test_gauge_transform(su2_ctx *c, uint64_t seed)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    void *G = nullptr;
+    HIP_TRY(hipMalloc(&G, (size_t)c->volume * 16));
+    hipError_t e = launch_gauge(c->links, c->g, (float *)G, seed, c->replica, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(G);
+    if (e != hipSuccess) return fail(SU2_EHIP, std::string("gauge: ") + hipGetErrorString(e));
+    return SU2_OK;
+}
+
+}  // extern "C"

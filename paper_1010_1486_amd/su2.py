@@ -1,0 +1,316 @@
+"""Python binding of libsu2 (the C ABI in include/su2.h).
+
+Argument marshalling only: every step of the heat bath and of the
+measurements runs in the library's HIP kernels.  torch provides device memory
+(caller-owned buffers passed to su2_init_ext) and the stream (torch's current
+stream on the chosen device).  If libsu2.so has not been built this module
+raises on first use; there is no fallback.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsu2.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "su2.h")
+
+SU2_OK, SU2_EINVAL, SU2_EODD, SU2_ENOMEM, SU2_EHIP, SU2_ESTATE, SU2_ERANGE = 0, -1, -2, -3, -4, -5, -6
+SU2_COLD, SU2_HOT = 0, 1
+SU2_KP, SU2_LEARNED = 0, 1
+SU2_MEAS_PLAQ, SU2_MEAS_POLY = 1, 2
+
+_ERR_NAMES = {SU2_EINVAL: "SU2_EINVAL", SU2_EODD: "SU2_EODD", SU2_ENOMEM: "SU2_ENOMEM",
+              SU2_EHIP: "SU2_EHIP", SU2_ESTATE: "SU2_ESTATE", SU2_ERANGE: "SU2_ERANGE"}
+
+
+class SU2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_i32, _u32, _i64, _u64, _sz, _d, _int = (ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64,
+                                         ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double,
+                                         ctypes.c_int)
+_SIGS = {
+    "su2_last_error": (ctypes.c_char_p, []),
+    "su2_links_bytes": (_sz, [_vp]),
+    "su2_scratch_bytes": (_sz, [_vp]),
+    "su2_init": (_int, [_vp, _vp, _d, _u64, _int]),
+    "su2_init_ext": (_int, [_vp, _vp, _d, _u64, _int, _vp, _sz, _vp, _sz, _vp]),
+    "su2_destroy": (_int, [_vp]),
+    "su2_heatbath_sweep": (_int, [_vp, _i32, _int]),
+    "su2_sweep_measure": (_int, [_vp, _i32, _int, _i32, _int, _vp]),
+    "su2_reunitarize": (_int, [_vp]),
+    "su2_plaquette": (_int, [_vp, _vp]),
+    "su2_polyakov": (_int, [_vp, _vp, _vp]),
+    "su2_get_links": (_int, [_vp, _vp]),
+    "su2_set_links": (_int, [_vp, _vp]),
+    "su2_get_sweep": (_int, [_vp, _vp]),
+    "su2_set_sweep": (_int, [_vp, _u32]),
+    "su2_set_beta": (_int, [_vp, _d]),
+    "su2_set_replica": (_int, [_vp, _u32]),
+    "su2_links_device": (_int, [_vp, _vp, _vp]),
+    "su2_synchronize": (_int, [_vp]),
+    "su2_set_launch": (_int, [_vp, _int, _int]),
+    "su2_test_philox": (_int, [_vp, _i64, _u64, _vp]),
+    "su2_test_heatbath_links": (_int, [_vp, _i64, _d, _u64, _u32, _u32, _u32, _vp, _vp]),
+    "su2_test_pass": (_int, [_vp, _int, _int]),
+    "su2_test_gauge_transform": (_int, [_vp, _u64]),
+}
+
+
+def lib():
+    """Load libsu2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no CPU fallback)")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(l, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = l
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/su2.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(su2_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(rc):
+    if rc != SU2_OK:
+        raise SU2Error(rc, lib().su2_last_error().decode())
+    return rc
+
+
+def _p(a):
+    return a.ctypes.data_as(_vp)
+
+
+def _dims(dims):
+    d = np.ascontiguousarray(dims, dtype=np.int32)
+    if d.shape != (4,):
+        raise ValueError("dims must have 4 entries")
+    return d
+
+
+# ---------------------------------------------------------------- raw names
+def su2_links_bytes(dims):
+    return lib().su2_links_bytes(_p(_dims(dims)))
+
+
+def su2_scratch_bytes(dims):
+    return lib().su2_scratch_bytes(_p(_dims(dims)))
+
+
+def su2_init(dims, beta, seed, start):
+    """Context with library-owned memory and stream; returns an opaque handle."""
+    h = _vp()
+    _check(lib().su2_init(ctypes.byref(h), _p(_dims(dims)), float(beta), int(seed), int(start)))
+    return h
+
+
+def su2_init_ext(dims, beta, seed, start, links_ptr, links_bytes, scratch_ptr, scratch_bytes,
+                 stream):
+    h = _vp()
+    _check(lib().su2_init_ext(ctypes.byref(h), _p(_dims(dims)), float(beta), int(seed),
+                              int(start), _vp(links_ptr), links_bytes, _vp(scratch_ptr),
+                              scratch_bytes, _vp(stream)))
+    return h
+
+
+def su2_destroy(h):
+    _check(lib().su2_destroy(h))
+
+
+def su2_heatbath_sweep(h, nsweeps, mode=SU2_KP):
+    _check(lib().su2_heatbath_sweep(h, int(nsweeps), int(mode)))
+
+
+def su2_sweep_measure(h, nsweeps, mode, reunit_every, meas, dev_history_ptr):
+    _check(lib().su2_sweep_measure(h, int(nsweeps), int(mode), int(reunit_every), int(meas),
+                                   _vp(dev_history_ptr)))
+
+
+def su2_reunitarize(h):
+    _check(lib().su2_reunitarize(h))
+
+
+def su2_plaquette(h):
+    v = ctypes.c_double()
+    _check(lib().su2_plaquette(h, ctypes.byref(v)))
+    return v.value
+
+
+def su2_polyakov(h):
+    s, a = ctypes.c_double(), ctypes.c_double()
+    _check(lib().su2_polyakov(h, ctypes.byref(s), ctypes.byref(a)))
+    return s.value, a.value
+
+
+def su2_get_links(h, volume):
+    out = np.empty((volume, 4, 4), dtype=np.float32)
+    _check(lib().su2_get_links(h, _p(out)))
+    return out
+
+
+def su2_set_links(h, links):
+    a = np.ascontiguousarray(links, dtype=np.float32)
+    _check(lib().su2_set_links(h, _p(a)))
+
+
+def su2_get_sweep(h):
+    v = ctypes.c_uint32()
+    _check(lib().su2_get_sweep(h, ctypes.byref(v)))
+    return v.value
+
+
+def su2_set_sweep(h, sweep):
+    _check(lib().su2_set_sweep(h, int(sweep)))
+
+
+def su2_set_beta(h, beta):
+    _check(lib().su2_set_beta(h, float(beta)))
+
+
+def su2_set_replica(h, replica):
+    _check(lib().su2_set_replica(h, int(replica)))
+
+
+def su2_synchronize(h):
+    _check(lib().su2_synchronize(h))
+
+
+def su2_set_launch(h, block, xcd_remap):
+    _check(lib().su2_set_launch(h, int(block), int(xcd_remap)))
+
+
+def su2_links_device(h):
+    p, s = _vp(), _vp()
+    _check(lib().su2_links_device(h, ctypes.byref(p), ctypes.byref(s)))
+    return p.value, s.value
+
+
+def su2_test_philox(ctr, seed):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(c)
+    _check(lib().su2_test_philox(_p(c), c.shape[0], int(seed), _p(out)))
+    return out
+
+
+def su2_test_heatbath_links(V, beta, seed, sweep, mu, replica=0, want_trials=False):
+    v = np.ascontiguousarray(V, dtype=np.float32).reshape(-1, 4)
+    out = np.empty_like(v)
+    nt = np.empty(v.shape[0], dtype=np.int32) if want_trials else None
+    _check(lib().su2_test_heatbath_links(_p(v), v.shape[0], float(beta), int(seed), int(sweep),
+                                         int(mu), int(replica), _p(out),
+                                         _p(nt) if nt is not None else None))
+    return (out, nt) if want_trials else out
+
+
+def su2_test_pass(h, mu, parity):
+    _check(lib().su2_test_pass(h, int(mu), int(parity)))
+
+
+def su2_test_gauge_transform(h, seed):
+    _check(lib().su2_test_gauge_transform(h, int(seed)))
+
+
+# ------------------------------------------------------------ convenience
+class Lattice:
+    """A lattice whose links and scratch are torch tensors on a GPU, run on
+    torch's current stream of that device (su2_init_ext)."""
+
+    def __init__(self, dims, beta, seed, start=SU2_COLD, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.dims = [int(d) for d in dims]
+        self.volume = int(np.prod(self.dims))
+        self.device = torch.device(device)
+        lb, sb = su2_links_bytes(self.dims), su2_scratch_bytes(self.dims)
+        if lb == 0:
+            raise SU2Error(SU2_EODD, f"invalid extents {self.dims}")
+        self.links_t = torch.empty(lb, dtype=torch.uint8, device=self.device)
+        self.scratch_t = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = su2_init_ext(self.dims, beta, seed, start, self.links_t.data_ptr(), lb,
+                              self.scratch_t.data_ptr(), sb, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            su2_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def heatbath_sweep(self, n, mode=SU2_KP):
+        su2_heatbath_sweep(self.h, n, mode)
+
+    def sweep_measure(self, n, mode=SU2_KP, reunit_every=0, meas=SU2_MEAS_PLAQ, hist=None):
+        torch = self.torch
+        if hist is None:
+            hist = torch.zeros((max(n, 1), 3), dtype=torch.float64, device=self.device)
+        su2_sweep_measure(self.h, n, mode, reunit_every, meas, hist.data_ptr())
+        return hist
+
+    def reunitarize(self):
+        su2_reunitarize(self.h)
+
+    def plaquette(self):
+        return su2_plaquette(self.h)
+
+    def polyakov(self):
+        return su2_polyakov(self.h)
+
+    def get_links(self):
+        return su2_get_links(self.h, self.volume)
+
+    def set_links(self, links):
+        su2_set_links(self.h, links)
+
+    @property
+    def sweep(self):
+        return su2_get_sweep(self.h)
+
+    def set_sweep(self, s):
+        su2_set_sweep(self.h, s)
+
+    def set_beta(self, b):
+        su2_set_beta(self.h, b)
+
+    def set_replica(self, r):
+        su2_set_replica(self.h, r)
+
+    def set_launch(self, block, xcd_remap=True):
+        su2_set_launch(self.h, block, xcd_remap)
+
+    def synchronize(self):
+        su2_synchronize(self.h)
+
+    def test_pass(self, mu, parity):
+        su2_test_pass(self.h, mu, parity)
+
+    def test_gauge_transform(self, seed):
+        su2_test_gauge_transform(self.h, seed)

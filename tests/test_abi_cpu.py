@@ -1,0 +1,60 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/su2.h declares, and rejects bad arguments before any
+device work."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_1010_1486_amd as su2
+
+
+def test_library_exports_every_declared_function():
+    lib = su2.lib()
+    names = su2.header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_sizes():
+    assert su2.su2_links_bytes([4, 4, 4, 4]) == 64 * 256
+    assert su2.su2_links_bytes([48, 48, 48, 48]) == 64 * 48 ** 4
+    assert su2.su2_links_bytes([3, 4, 4, 4]) == 0
+    assert su2.su2_scratch_bytes([4, 4, 4, 4]) > 256
+
+
+@pytest.mark.parametrize("dims", [[3, 4, 4, 4], [4, 4, 4, 5], [0, 4, 4, 4], [4, 1, 4, 4]])
+def test_odd_or_small_extents_rejected(dims):
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_init(dims, 2.3, 1, su2.SU2_COLD)
+    assert e.value.code == su2.SU2_EODD
+
+
+def test_bad_arguments_rejected():
+    for beta in (float("nan"), float("inf")):
+        with pytest.raises(su2.SU2Error) as e:
+            su2.su2_init([4, 4, 4, 4], beta, 1, su2.SU2_COLD)
+        assert e.value.code == su2.SU2_EINVAL
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_init([4, 4, 4, 4], 2.0, 1, 7)
+    assert e.value.code == su2.SU2_EINVAL
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_init([2048, 2048, 2048, 2], 2.0, 1, su2.SU2_COLD)
+    assert e.value.code == su2.SU2_ERANGE
+    lib = su2.lib()
+    assert lib.su2_init(None, None, 1.0, 1, 0) == su2.SU2_EINVAL
+    assert lib.su2_heatbath_sweep(None, 1, 0) == su2.SU2_EINVAL
+    assert lib.su2_plaquette(None, None) == su2.SU2_EINVAL
+    assert lib.su2_destroy(None) == su2.SU2_EINVAL
+    assert b"NULL" in lib.su2_last_error()
+    h = ctypes.c_void_p()
+    d = np.array([4, 4, 4, 4], np.int32)
+    rc = lib.su2_init_ext(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), 2.0, 1, 0,
+                          None, 0, None, 0, None)
+    assert rc == su2.SU2_EINVAL
+    rc = lib.su2_init_ext(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), 2.0, 1, 0,
+                          ctypes.c_void_p(4096), 16, ctypes.c_void_p(8192), 16, None)
+    assert rc == su2.SU2_ENOMEM
+    assert lib.su2_test_philox(None, -1, 0, None) == su2.SU2_EINVAL
+    assert lib.su2_test_philox(None, 0, 0, None) == su2.SU2_OK

@@ -1,0 +1,114 @@
+"""GPU heat bath vs the FP64 CPU oracle from identical inputs (through the C ABI).
+
+Link-level parity holds because both sides draw the same Philox streams and
+follow the same sampler; FP32-vs-FP64 can flip only decisions whose margin is
+below the flag threshold, which are excluded and counted (expected ~1e-6 per
+decision).  Tolerance: 1e-5 absolute per link component.
+"""
+import numpy as np
+import pytest
+
+from tests import inputs
+from tests.gpu_util import MARGIN_FLAG, announce, compare_pass, max_flags, parities
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [[2, 2, 2, 2], [4, 4, 4, 4], [4, 6, 2, 8], [8, 6, 8, 10], [12, 10, 8, 6]]
+
+
+def test_philox_bitwise(su2, orc):
+    announce("philox bitwise")
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, (5000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:3] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [5308415, 1999, 0x1C3, 7]]
+    for seed in (0, 1, 2 ** 64 - 1, 0xDEADBEEF12345678):
+        np.testing.assert_array_equal(su2.su2_test_philox(ctr, seed), orc.philox(ctr, seed))
+
+
+def test_single_link_updates(su2, orc):
+    announce("single-link heat bath vs oracle")
+    V = inputs.random_staples(20000, 3, kmin=0.01, kmax=6.0)
+    V[:3] = 0.0  # k = 0: Haar
+    beta = 2.3
+    got, ntr = su2.su2_test_heatbath_links(V, beta, 17, 9, 2, replica=5, want_trials=True)
+    nflag = 0
+    for i in range(V.shape[0]):
+        want, m = orc.heatbath_link(V[i].astype(np.float64), beta, 17, i, 9, 2, 5)
+        if m < MARGIN_FLAG:
+            nflag += 1
+            continue
+        assert np.abs(got[i] - want).max() < 1e-5, (i, got[i], want, m)
+    _, otr, om = orc.sample_delta(beta * np.linalg.norm(V.astype(np.float64), axis=1), 17,
+                                  np.arange(V.shape[0], dtype=np.uint32), 9, 2, 5)
+    keep = om >= MARGIN_FLAG
+    np.testing.assert_array_equal(ntr[keep], otr[keep])
+    assert nflag <= max_flags(V.shape[0])
+
+
+@pytest.mark.parametrize("dims", DIMS, ids=lambda d: "x".join(map(str, d)))
+def test_every_pass_matches_oracle(su2, orc, dims):
+    announce(f"per-pass parity dims={dims}")
+    links = inputs.random_links(dims, 10 + sum(dims), spread=0.6)
+    beta, seed = 2.4, 12345
+    par_of = parities(orc, dims)
+    with su2.Lattice(dims, beta, seed) as lat:
+        lat.set_sweep(3)
+        lat.set_links(links)
+        total_flag = 0
+        for mu in range(4):
+            for p in range(2):
+                before = lat.get_links()
+                U = before.astype(np.float64)
+                margin = orc.do_pass(dims, U, mu, p, 3, beta, seed, want_margin=True)
+                lat.test_pass(mu, p)
+                got = lat.get_links()
+                err, nflag = compare_pass(got, U, margin, p, mu, par_of)
+                total_flag += nflag
+                assert err < 1e-5, (mu, p, err)
+                # everything else untouched, bit for bit
+                mask = np.ones(got.shape[:2], bool)
+                mask[par_of == p, mu] = False
+                np.testing.assert_array_equal(got[mask], before[mask])
+        assert total_flag <= max_flags(4 * int(np.prod(dims)))
+
+
+@pytest.mark.parametrize("dims", [[4, 4, 4, 4], [4, 6, 2, 8]], ids=lambda d: "x".join(map(str, d)))
+def test_hot_start_and_sweeps_match_oracle(su2, orc, dims):
+    """Config-1 style: hot start (Philox seed 1), beta 2.3, sweeps compared one
+    at a time from the GPU's own links (resynchronised each sweep)."""
+    announce(f"hot start + sweeps dims={dims}")
+    beta, seed = 2.3, 1
+    with su2.Lattice(dims, beta, seed, su2.SU2_HOT) as lat:
+        start = lat.get_links()
+        np.testing.assert_allclose(start, orc.init(dims, 1, seed), atol=2e-6, rtol=0)
+        skipped = 0
+        for sw in range(12):
+            U = lat.get_links().astype(np.float64)
+            margins = [orc.do_pass(dims, U, mu, p, sw, beta, seed, want_margin=True)
+                       for mu in range(4) for p in range(2)]
+            lat.heatbath_sweep(1)
+            got = lat.get_links()
+            if min(np.min(m) for m in margins) < MARGIN_FLAG:
+                skipped += 1
+                continue
+            assert np.abs(got - U).max() < 1e-5, sw
+        assert skipped <= 3
+        assert lat.sweep == 12
+
+
+def test_plaquette_history_config1(su2, orc):
+    """4^4, hot start seed 1, beta 2.3: per-sweep plaquette history (fused into
+    the sweep) against the oracle's, sweep by sweep from identical links."""
+    announce("config-1 plaquette history")
+    dims, beta, seed = [4, 4, 4, 4], 2.3, 1
+    with su2.Lattice(dims, beta, seed, su2.SU2_HOT) as lat:
+        for sw in range(20):
+            U = lat.get_links().astype(np.float64)
+            ph, _ = orc.sweeps(dims, U, 1, sw, beta, seed, measure=True)
+            hist = lat.sweep_measure(1, meas=su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY).cpu().numpy()
+            got = lat.get_links().astype(np.float64)
+            # observables of the GPU's own configuration, FP64 oracle sums
+            assert abs(hist[0, 0] - orc.plaquette(dims, got)) < 1e-6
+            assert abs(hist[0, 1] - orc.polyakov(dims, got)[0]) < 1e-6
+            if np.abs(got - U).max() < 1e-5:
+                assert abs(hist[0, 0] - ph[0]) < 1e-6

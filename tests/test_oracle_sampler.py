@@ -80,6 +80,26 @@ def test_heatbath_link_distribution(orc, vseed):
     assert abs(tr.mean() - k * m1) < 5 * tr.std() / np.sqrt(4000)
 
 
+def test_heatbath_direction_is_isotropic(orc):
+    """The vector part of X is uniform on the sphere: cos(theta) = X3/|X| and
+    phi = atan2(X2, X1) are uniform; their 18-bit uniforms come from the low
+    bits of the first trial's Philox words."""
+    V = np.array([2.0, 0.3, -0.4, 0.1])
+    Ut, k = _frame(V)
+    n = 30_000
+    X = np.array([orc.qmul(orc.heatbath_link(V, 1.3, 5, i, 2, 1)[0], Ut)[0] for i in range(n)])
+    v = X[:, 1:] / np.linalg.norm(X[:, 1:], axis=1, keepdims=True)
+    from scipy import stats as st
+    assert st.kstest(v[:, 2], "uniform", args=(-1, 2)).pvalue > 1e-4
+    phi = np.arctan2(v[:, 1], v[:, 0])
+    assert st.kstest(phi, "uniform", args=(-np.pi, 2 * np.pi)).pvalue > 1e-4
+    # the direction is independent of a0
+    assert abs(np.corrcoef(X[:, 0], v[:, 2])[0, 1]) < 5 / np.sqrt(n)
+    w = np.array([0, 511, 0x1FF00], dtype=np.uint32)
+    u = [orc._load().orc_uniform18(int(m)) for m in w]
+    assert u[0] == 2.0 ** -19 and 0 < min(u) and max(u) < 1
+
+
 def test_heatbath_zero_staple_is_haar(orc):
     n = 40_000
     a0 = np.array([orc.heatbath_link(np.zeros(4), 2.0, 5, i, 0, 0)[0][0] for i in range(n)])
