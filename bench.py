@@ -79,6 +79,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--pass-launches", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="short program for rocprofv3 --pmc runs: 16 pass launches in sweep "
+                         "order, then 4 plain device copies of the field size (339.7 MB) "
+                         "that calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -94,6 +98,19 @@ def main():
     stream = lat.stream
     meas = su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY
     hist = torch.zeros((max(args.steps, args.warmup, 1), 3), dtype=torch.float64, device=dev)
+
+    if args.counters:
+        lat.heatbath_sweep(2)
+        for i in range(16):
+            lat.test_pass((i // 2) % 4, i % 2)
+        x = torch.ones(su2.su2_links_bytes(DIMS) // 4, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(4):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": True, "pass_launches": 16, "copy_bytes": 4 * x.numel()}))
+        lat.close()
+        return
 
     print(f"[bench] warmup {args.warmup} sweeps on {DIMS}", file=sys.stderr, flush=True)
     lat.sweep_measure(args.warmup, reunit_every=10, meas=meas, hist=hist)
@@ -113,7 +130,7 @@ def main():
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for i in range(args.pass_launches):
-            lat.test_pass(i % 4, (i // 4) % 2)
+            lat.test_pass((i // 2) % 4, i % 2)  # sweep order: mu outer, parity inner
         e1.record(stream)
     e1.synchronize()
     pass_ms = e0.elapsed_time(e1) / args.pass_launches
@@ -132,6 +149,9 @@ def main():
                    "dims": DIMS, "beta": BETA, "links": 4 * V, "mode": "plain KP"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x copy "
+                                     "calibration + WRITE_SIZE)",
+                     "traffic_gbs": None if traffic is None else traffic / (pass_ms * 1e-3) / 1e9,
                      "kernel": "pass_kernel", "avg_launch_us": pass_ms * 1e3,
                      "bytes_per_update": BYTES_PER_UPDATE, "updates_per_launch": V // 2},
         "plaquette_mean_last_half": float(h[args.steps // 2:, 0].mean()),

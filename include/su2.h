@@ -51,7 +51,7 @@ enum {
     SU2_ENOMEM = -3, /* device allocation failed, or caller buffer too small */
     SU2_EHIP = -4,   /* a HIP runtime call failed (message has the HIP error string) */
     SU2_ESTATE = -5, /* call not valid in the context's state (e.g. no proposal loaded) */
-    SU2_ERANGE = -6  /* a size exceeds the library's index range (V/2 >= 2^31) */
+    SU2_ERANGE = -6  /* a size exceeds the library's index range (V/2 >= 2^30) */
 };
 
 enum { SU2_COLD = 0, SU2_HOT = 1 };
@@ -62,8 +62,9 @@ enum { SU2_MEAS_PLAQ = 1, SU2_MEAS_POLY = 2 };
 const char *su2_last_error(void);
 
 /* Device bytes the caller must provide to su2_init_ext for these extents:
- * links 64*V; scratch = counters, FP64 result slots and FP64 block partials.
- * Return 0 when the extents are invalid. */
+ * links 64*V; scratch 256 (sweep counter, history index, the fixed-point
+ * accumulators of the global sums, FP64 result slots).  Return 0 when the
+ * extents are invalid. */
 size_t su2_links_bytes(const int32_t dims[4]);
 size_t su2_scratch_bytes(const int32_t dims[4]);
 
@@ -97,7 +98,9 @@ int su2_heatbath_sweep(su2_ctx *ctx, int32_t nsweeps, int mode);
  * device FP64 buffer of 3*nsweeps entries, receiving (plaquette, signed mean
  * Polyakov loop, its absolute value) per sweep (0 where not measured).  The
  * plaquette is fused into the odd passes of mu = 1, 2, 3 (no extra read of the
- * field) except on reunitarisation sweeps, where it is measured afterwards. */
+ * field) except on reunitarisation sweeps, where it is measured afterwards.
+ * Global sums: FP64 within each workgroup, then 64-bit fixed point (2^-28)
+ * across workgroups, so results are bit-reproducible. */
 int su2_sweep_measure(su2_ctx *ctx, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
                       double *dev_history);
 
@@ -132,9 +135,12 @@ int su2_links_device(su2_ctx *ctx, void **links_dev, void **hip_stream);
 /* Wait for all work enqueued on the context's stream. */
 int su2_synchronize(su2_ctx *ctx);
 
-/* Launch configuration of the pass kernel: block size (64..1024, multiple of
- * 64) and the XCD-contiguous workgroup remap (0/1). */
-int su2_set_launch(su2_ctx *ctx, int block, int xcd_remap);
+/* Launch configuration of the pass kernel: block size (64, 128, 192 or 256
+ * threads); flags: bit 0 = XCD-contiguous workgroup remap, bit 1 = disable
+ * the alternating (forward, backward) pass order; and the traversal tile
+ * of (z, t) planes, tile_z x tile_t (powers of two that divide Nz and Nt;
+ * 0 keeps the current value).  Results do not depend on it. */
+int su2_set_launch(su2_ctx *ctx, int block, int flags, int tile_z, int tile_t);
 
 /* ----------------------------------------------------------- test hooks */
 /* Philox4x32-10 on the GPU: n counters (host, 4 words each) -> host out. */
@@ -147,6 +153,12 @@ int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_
                             int32_t *ntrials_host);
 /* Enqueue one (mu, parity) pass at the current sweep index (index unchanged). */
 int su2_test_pass(su2_ctx *ctx, int mu, int parity);
+/* Host-side evaluation (no GPU needed) of the pass kernel's index map for
+ * extents dims and traversal tile tile_z x tile_t (0 = default): for each of
+ * the V/2 thread indices g of a pass over `parity`, out[9g] = canonical site of
+ * the thread, out[9g + 1 + 2d] / out[9g + 2 + 2d] = half-site index (s >> 1)
+ * of its +1 / -1 neighbour in direction d.  out: host uint32[9 * V/2]. */
+int su2_test_index_map(const int32_t dims[4], int tile_z, int tile_t, int parity, uint32_t *out);
 /* Enqueue U_mu(x) -> G(x) U_mu(x) G(x+mu)^+ with G Haar from Philox tag 3. */
 int su2_test_gauge_transform(su2_ctx *ctx, uint64_t seed);
 

@@ -17,12 +17,74 @@ namespace su2dev {
 // h = s >> 1 of the canonical site s = x + Nx*(y + Ny*(z + Nz*t)).
 struct Geom {
     int32_t nx, ny, nz, nt;
-    uint32_t vh;   // V/2
-    uint32_t hx;   // Nx/2 (half-sites per x row)
-    uint32_t sy;   // half-site stride of y (= Nx/2)
-    uint32_t sz;   // half-site stride of z (= Nx*Ny/2)
-    uint32_t st;   // half-site stride of t (= Nx*Ny*Nz/2)
+    uint32_t vh;  // V/2
+    uint32_t hx;  // Nx/2: half-sites per x row
+    uint32_t P;   // Nx*Ny/2: half-sites per (x, y) plane = half-site stride of z
+    uint32_t PZ;  // Nx*Ny*Nz/2: half-site stride of t
+    // wrap-around jumps in half-sites: (Ny-1)*hx, (Nz-1)*P, (Nt-1)*PZ
+    uint32_t wy, wz, wt;
+    // Traversal of the pass kernel: (x, y) planes are visited in tiles of
+    // 2^lg_tz x 2^lg_tt (z, t) planes, ntz tiles along z.
+    uint32_t lg_tz, lg_tt, ntz;
+    // Exact division of 31-bit numerators by P, hx and ntz: q = (n * m) >> s.
+    uint32_t m_P, s_P, m_hx, s_hx, m_ntz, s_ntz;
 };
+
+// n / d for n < 2^31 with m = ceil(2^(31+l)/d), s = 31 + l, l = ceil(log2 d)
+// (Granlund & Montgomery 1994, Thm. 4.2 with N = 31).
+__host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t m, uint32_t s)
+{
+    return (uint32_t)(((uint64_t)n * m) >> s);
+}
+
+// ---------------------------------------------------- pass traversal
+// Coordinates of the thread's site in the pass traversal: (x, y) planes are
+// contiguous in memory; the order of the (z, t) planes is tiled so that the
+// t-neighbours a workgroup needs were fetched by recent workgroups of the same
+// XCD (the logical block id already groups each XCD's workgroups).
+struct PassSite {
+    uint32_t h;  // half-site index
+    int x, y, z, t;
+};
+
+__host__ __device__ __forceinline__ PassSite pass_site(const Geom &g, uint32_t gid, int par)
+{
+    PassSite ps;
+    const uint32_t q = fdiv(gid, g.m_P, g.s_P);  // plane in traversal order
+    const uint32_t r = gid - q * g.P;             // half-site within the (x, y) plane
+    const uint32_t lg = g.lg_tz + g.lg_tt;
+    const uint32_t tile = q >> lg, w = q & ((1u << lg) - 1u);
+    const uint32_t tt = fdiv(tile, g.m_ntz, g.s_ntz), tzi = tile - tt * g.ntz;
+    ps.z = (int)((tzi << g.lg_tz) + (w & ((1u << g.lg_tz) - 1u)));
+    ps.t = (int)((tt << g.lg_tt) + (w >> g.lg_tz));
+    const uint32_t y = fdiv(r, g.m_hx, g.s_hx);
+    const uint32_t xh = r - y * g.hx;
+    ps.y = (int)y;
+    ps.x = (int)(2u * xh) + ((par + ps.y + ps.z + ps.t) & 1);
+    ps.h = r + g.P * (uint32_t)ps.z + g.PZ * (uint32_t)ps.t;
+    return ps;
+}
+
+// Half-site offsets (mod 2^32) of the +/-1 neighbours in each direction; they
+// add up for diagonal neighbours because each depends on its own coordinate.
+struct Deltas {
+    uint32_t p[4], m[4];
+};
+
+__host__ __device__ __forceinline__ Deltas neighbour_deltas(const Geom &g, const PassSite &s)
+{
+    Deltas d;
+    const bool xodd = s.x & 1;
+    d.p[0] = xodd ? (s.x == g.nx - 1 ? 1u - g.hx : 1u) : 0u;
+    d.m[0] = xodd ? 0u : (s.x == 0 ? g.hx - 1u : 0xFFFFFFFFu);
+    d.p[1] = s.y == g.ny - 1 ? 0u - g.wy : g.hx;
+    d.m[1] = s.y == 0 ? g.wy : 0u - g.hx;
+    d.p[2] = s.z == g.nz - 1 ? 0u - g.wz : g.P;
+    d.m[2] = s.z == 0 ? g.wz : 0u - g.P;
+    d.p[3] = s.t == g.nt - 1 ? 0u - g.wt : g.PZ;
+    d.m[3] = s.t == 0 ? g.wt : 0u - g.PZ;
+    return d;
+}
 
 __device__ __forceinline__ const float *plane(const float *base, uint32_t vh, int mu, int par,
                                               int c)
@@ -109,15 +171,23 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     return U4{c0, c1, c2, c3};
 }
 
-// 32-bit word -> (2*(w>>9)+1) * 2^-24: exact in FP32, never 0 or 1.
+// 32-bit word -> (2*(w>>9)+1) * 2^-24: exact in FP32, never 0 or 1.  The 23
+// high bits become the mantissa of a float in [1, 2); subtracting 1 - 2^-24
+// is exact (Sterbenz) and yields (2m+1) 2^-24.
 __device__ __forceinline__ float u01(uint32_t w)
 {
-    return (float)(((w >> 9) << 1) | 1u) * 5.9604644775390625e-08f;
+    return __uint_as_float((w >> 9) | 0x3f800000u) - 0.99999994039535522f;
+}
+
+// 18-bit value m -> (2m+1) * 2^-19.
+__device__ __forceinline__ float u18(uint32_t m)
+{
+    return (float)(2u * m + 1u) * 1.9073486328125e-06f;
 }
 
 enum : uint32_t {
-    TAG_TRIAL = 0,
-    TAG_DIR = 1,
+    TAG_TRIAL = 0,  // a0 trials; the low 9 bits of draw 0's words give the direction
+    TAG_RESERVED = 1,
     TAG_HOT = 2,
     TAG_GAUGE = 3,
     TAG_LEARN = 4,
@@ -130,73 +200,101 @@ __device__ __forceinline__ uint32_t word2(uint32_t mu, uint32_t tag, uint32_t re
     return mu | (tag << 2) | (replica << 6);
 }
 
+// Hardware transcendentals (single instructions on gfx950).
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// cos(2 pi x), sin(2 pi x): the hardware sine/cosine take revolutions.
+__device__ __forceinline__ float hw_cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+__device__ __forceinline__ float hw_sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kLog2e = 1.4426950408889634f;
+
 // ----------------------------------------------------------------- sampler
 // Exact draw of a0 from sqrt(1 - a0^2) exp(alpha a0) on [-1, 1] (Sec. 2),
 // returned as delta = 1 - a0.  alpha >= 1: Kennedy-Pendleton (delta is
 // Gamma(3/2, alpha) from two logs and a cos^2, accepted with probability
 // sqrt(1 - delta/2)).  alpha < 1: a0 = sqrt(r1) cos(2 pi r2) is Haar
-// (semicircle) distributed, accepted with probability exp(alpha (a0 - 1)).
+// (semicircle) distributed, accepted with probability exp(alpha (a0 - 1)),
+// tested as log2 r3 <= alpha (a0 - 1) log2 e.  Trial t uses the Philox block
+// (site, sweep, w2trial, t); the caller passes trial 0's block in `w0`.
 // The trial cap is unreachable in practice (acceptance >= 0.41 everywhere);
 // on reaching it delta = 0.
 constexpr int kTrialCap = 1000;
 constexpr float kKPMinAlpha = 1.0f;
 
-__device__ __forceinline__ float sample_delta(float alpha, uint32_t site, uint32_t sweep,
+__device__ __forceinline__ float sample_delta(float alpha, U4 w, uint32_t site, uint32_t sweep,
                                               uint32_t w2trial, uint32_t k0, uint32_t k1,
                                               int *ntrials = nullptr)
 {
+    const bool kp = alpha >= kKPMinAlpha;
+    const float neg_ln2_over_alpha = -kLn2 * hw_rcp(alpha);
     float delta = 0.0f;
     int t = 0;
-    if (alpha >= kKPMinAlpha) {
-        const float inv_alpha = 1.0f / alpha;
-        for (; t < kTrialCap; ++t) {
-            U4 w = philox(site, sweep, w2trial, (uint32_t)t, k0, k1);
-            const float r1 = u01(w.a), r2 = u01(w.b), r3 = u01(w.c), r4 = u01(w.d);
-            const float c = cospif(2.0f * r2);
-            const float d = -(logf(r1) + c * c * logf(r3)) * inv_alpha;
-            if (r4 * r4 <= 1.0f - 0.5f * d) {
-                delta = d;
-                break;
-            }
+    for (;;) {
+        const float r1 = u01(w.a), r2 = u01(w.b), r3 = u01(w.c), r4 = u01(w.d);
+        float d;
+        bool acc;
+        if (kp) {
+            const float c = hw_cos_rev(r2);
+            d = neg_ln2_over_alpha * (hw_log2(r1) + c * c * hw_log2(r3));
+            acc = r4 * r4 <= 1.0f - 0.5f * d;
+        } else {
+            const float a0 = hw_sqrt(r1) * hw_cos_rev(r2);
+            d = 1.0f - a0;
+            acc = hw_log2(r3) <= alpha * (a0 - 1.0f) * kLog2e;
         }
-    } else {
-        for (; t < kTrialCap; ++t) {
-            U4 w = philox(site, sweep, w2trial, (uint32_t)t, k0, k1);
-            const float r1 = u01(w.a), r2 = u01(w.b), r3 = u01(w.c);
-            const float a0 = sqrtf(r1) * cospif(2.0f * r2);
-            if (r3 <= expf(alpha * (a0 - 1.0f))) {
-                delta = 1.0f - a0;
-                break;
-            }
+        if (acc) {
+            delta = d;
+            break;
         }
+        if (++t >= kTrialCap) break;
+        w = philox(site, sweep, w2trial, (uint32_t)t, k0, k1);
     }
     if (ntrials) *ntrials = t + 1;
     return delta;
 }
 
-// X = (1 - delta, |a| n), n uniform on the sphere from (r5, r6) of the
-// direction block; |a| = sqrt(delta (2 - delta)) avoids cancellation near a0 = 1.
-__device__ __forceinline__ Q element_from_delta(float delta, float r5, float r6)
+// Direction uniforms from the low 9 bits of trial 0's words.
+__device__ __forceinline__ void dir_uniforms(const U4 &w, float &r5, float &r6)
 {
-    const float amag = sqrtf(delta * (2.0f - delta));
-    const float cth = 1.0f - 2.0f * r5;
-    const float sth = 2.0f * sqrtf(r5 * (1.0f - r5));
-    const float cph = cospif(2.0f * r6), sph = sinpif(2.0f * r6);
-    return Q{1.0f - delta, amag * sth * cph, amag * sth * sph, amag * cth};
+    r5 = u18((w.a & 511u) | ((w.b & 511u) << 9));
+    r6 = u18((w.c & 511u) | ((w.d & 511u) << 9));
 }
 
-// Heat-bath update of one link from its staple sum V: U' = X U~^+, U~ = V/k.
+// X = (1 - delta, |a| n), n uniform on the sphere from (r5, r6):
+// cos(theta) = 1 - 2 r5, sin(theta) = 2 sqrt(r5 (1 - r5)), phi = 2 pi r6;
+// |a| = sqrt(delta (2 - delta)) avoids cancellation near a0 = 1.
+__device__ __forceinline__ Q element_from_delta(float delta, float r5, float r6)
+{
+    const float amag = hw_sqrt(delta * (2.0f - delta));
+    const float cth = 1.0f - 2.0f * r5;
+    const float sth = 2.0f * hw_sqrt(r5 * (1.0f - r5));
+    const float as = amag * sth;
+    return Q{1.0f - delta, as * hw_cos_rev(r6), as * hw_sin_rev(r6), amag * cth};
+}
+
+// Heat-bath update of one link from its staple sum V: U' = X U~^+ with
+// U~ = V/k, k = |V| (det V = |V|^2 for a sum of quaternions).  k = 0 (only in
+// constructed inputs) gives U~ = 1 and a Haar X.
 __device__ __forceinline__ Q heatbath_link(const Q &V, float beta, uint32_t site, uint32_t sweep,
-                                           uint32_t mu, uint32_t replica, uint32_t k0,
-                                           uint32_t k1)
+                                           uint32_t w2trial, uint32_t k0, uint32_t k1,
+                                           int *ntrials = nullptr)
 {
     const float k2 = qdot(V, V);
-    const float k = sqrtf(k2);
-    const float alpha = beta * k;
-    const float delta = sample_delta(alpha, site, sweep, word2(mu, TAG_TRIAL, replica), k0, k1);
-    const U4 wd = philox(site, sweep, word2(mu, TAG_DIR, replica), 0u, k0, k1);
-    const Q X = element_from_delta(delta, u01(wd.a), u01(wd.b));
-    Q Ut = (k2 > 0.0f) ? Q{V.w / k, V.x / k, V.y / k, V.z / k} : Q{1.0f, 0.0f, 0.0f, 0.0f};
+    const bool zero = !(k2 > 0.0f);
+    const float inv_k = zero ? 0.0f : hw_rsq(k2);
+    const float alpha = beta * k2 * inv_k;
+    const U4 w0 = philox(site, sweep, w2trial, 0u, k0, k1);
+    float r5, r6;
+    dir_uniforms(w0, r5, r6);
+    const float delta = sample_delta(alpha, w0, site, sweep, w2trial, k0, k1, ntrials);
+    const Q X = element_from_delta(delta, r5, r6);
+    const Q Ut = zero ? Q{1.0f, 0.0f, 0.0f, 0.0f}
+                      : Q{V.w * inv_k, V.x * inv_k, V.y * inv_k, V.z * inv_k};
     return qmul(X, qdag(Ut));
 }
 

@@ -13,49 +13,66 @@ namespace su2rt {
 
 void set_error(const std::string &msg);
 
-// Scratch layout (bytes): [0,64) device counters, [64,256) FP64 result slots,
-// [256, ...) FP64 block partials (kPartialArrays arrays of max_blocks each).
+// Scratch layout (bytes): [0,64) device counters, [64,256) FP64 result
+// slots, [256, 256 + kAccBytes) fixed-point accumulators.
 constexpr size_t kCountersOff = 0;
 constexpr size_t kResultsOff = 64;
-constexpr size_t kPartialsOff = 256;
-constexpr int kPartialArrays = 4;
-constexpr int kMinBlock = 64;
+constexpr size_t kAccOff = 256;
+
+// Global sums: every workgroup reduces its values in FP64 (wave shuffles,
+// then LDS) and adds the block sum, rounded to a multiple of 2^-kFixedShift,
+// to a 64-bit integer accumulator.  Integer addition is associative, so the
+// total does not depend on the order in which workgroups finish, and the adds
+// can be spread over kBuckets counters (workgroup b uses bucket b mod
+// kBuckets, each on its own 128-byte line) so that they do not serialise on
+// one address.
+constexpr int kFixedShift = 28;
+constexpr int kBuckets = 256;
+constexpr int kBucketStride = 16;  // 16 x 8 B = one 128-byte line per bucket
+constexpr int kNumAcc = 2;
+constexpr size_t kAccBytes = (size_t)kNumAcc * kBuckets * kBucketStride * 8;
+constexpr size_t kScratchBytes = kAccOff + kAccBytes;
 
 struct Counters {
     uint32_t sweep;     // sweep index used by the next pass (Philox counter word 1)
-    uint32_t meas_idx;  // next history slot written by a measured sweep
+    uint32_t meas_idx;  // next history row written by a measured sweep
 };
 
 enum Result { R_PLAQ = 0, R_POLY_SIGNED = 1, R_POLY_ABS = 2 };
+enum Acc { ACC_PLAQ = 0, ACC_POLY = 1 };
 
-size_t max_partial_blocks(int64_t volume);
+// Accumulator `which`, bucket b: acc + (which * kBuckets + b) * kBucketStride.
+struct Sums {
+    Counters *cnt;
+    unsigned long long *acc;
+};
 
 struct LaunchCfg {
     int pass_block = 256;
-    int pass_sites_per_thread = 1;
     bool xcd_remap = true;
+    bool snake = true;  // odd-parity passes traverse backwards
 };
 
 // Kernel launchers (all asynchronous on `stream`; return hipError_t).
 hipError_t launch_init(float *links, const su2dev::Geom &g, int start, uint64_t seed,
                        uint32_t replica, hipStream_t stream);
-hipError_t launch_pass(float *links, const su2dev::Geom &g, int mu, int par,
-                       const uint32_t *sweep_ptr, float beta, uint64_t seed, uint32_t replica,
-                       double *partial, const LaunchCfg &cfg, hipStream_t stream);
+// measure: accumulate (1/2)Tr(U' V_nu), nu < mu, into acc[ACC_PLAQ].
+hipError_t launch_pass(float *links, const su2dev::Geom &g, int mu, int par, Sums c,
+                       float beta, uint64_t seed, uint32_t replica, bool measure,
+                       const LaunchCfg &cfg, hipStream_t stream);
 int pass_grid(const su2dev::Geom &g, const LaunchCfg &cfg);
-hipError_t launch_plaquette(const float *links, const su2dev::Geom &g, double *partial,
-                            int *nblocks, hipStream_t stream);
-hipError_t launch_polyakov(const float *links, const su2dev::Geom &g, double *partial,
-                           int *nblocks, hipStream_t stream);
-// Sum `narrays` partial arrays of `nblocks` entries (stride `stride`) in a fixed
-// order, scale, and store into out[0] (and |.| into out[1] when abs_too).
-hipError_t launch_finalize(const double *partial, int nblocks, int narrays, size_t stride,
-                           double scale, double *out, int abs_too, hipStream_t stream);
-// Plaquette of a fused sweep: sums the three measured passes' partials,
-// appends to hist[3 * meas_idx] and advances the counters.
-hipError_t launch_sweep_end(Counters *counters, const double *partial, int nblocks,
-                            size_t stride, double scale, int measure, double *hist,
-                            const double *extra_poly, hipStream_t stream);
+// Sum of all plaquettes into acc[ACC_PLAQ]; sum of L(x) into acc[ACC_POLY].
+hipError_t launch_plaquette(const float *links, const su2dev::Geom &g, Sums c,
+                            hipStream_t stream);
+hipError_t launch_polyakov(const float *links, const su2dev::Geom &g, Sums c,
+                           hipStream_t stream);
+// out[0] = acc[which] * scale, out[1] = |out[0]|; resets acc[which].
+hipError_t launch_take(Sums c, int which, double scale, double *out, hipStream_t stream);
+// End of a sweep.  flags: 1 plaquette in acc[ACC_PLAQ], 2 Polyakov in
+// acc[ACC_POLY], 4 append a history row (P, L, |L|) at hist[3*meas_idx].
+// Resets the accumulators and advances the sweep counter.
+hipError_t launch_sweep_end(Sums c, int flags, double plaq_scale, double poly_scale,
+                            double *hist, hipStream_t stream);
 hipError_t launch_reunitarize(float *links, const su2dev::Geom &g, hipStream_t stream);
 hipError_t launch_gauge(float *links, const su2dev::Geom &g, float *G, uint64_t seed,
                         uint32_t replica, hipStream_t stream);
@@ -64,7 +81,8 @@ hipError_t launch_test_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uin
 hipError_t launch_test_links(const float *V, int64_t n, float beta, uint64_t seed,
                              uint32_t sweep, uint32_t mu, uint32_t replica, float *out,
                              int32_t *ntrials, hipStream_t stream);
-hipError_t launch_set_counter(Counters *c, uint32_t sweep, uint32_t meas, int which,
+// which: 1 set sweep, 2 set meas_idx, 4 zero the accumulators.
+hipError_t launch_set_counter(Sums c, uint32_t sweep, uint32_t meas, int which,
                               hipStream_t stream);
 
 }  // namespace su2rt

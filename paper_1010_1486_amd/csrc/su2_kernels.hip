@@ -6,8 +6,9 @@
 //   Sec. 4   kernels: cold/hot start, heat bath per (direction, parity),
 //            plaquette, Polyakov loop, sum over the lattice
 // The pass kernel streams the structure-of-arrays planes of one (mu, parity)
-// class; plaquette and Polyakov sums are FP64 wave/LDS trees with block
-// partials summed by a one-block kernel in a fixed order (deterministic).
+// class.  Plaquette and Polyakov sums are FP64 within a workgroup (wave
+// shuffles, then LDS) and 64-bit fixed point across workgroups, so every sum
+// is independent of scheduling order.
 #include "su2_internal.h"
 
 using namespace su2dev;
@@ -34,25 +35,6 @@ __device__ __forceinline__ uint32_t hidx(const Geom &g, int x, int y, int z, int
                                         (uint32_t)g.nz * (uint32_t)t));
 }
 
-__device__ __forceinline__ int wrap_up(int c, int n) { return c + 1 == n ? 0 : c + 1; }
-__device__ __forceinline__ int wrap_dn(int c, int n) { return c == 0 ? n - 1 : c - 1; }
-
-struct Site {
-    int c[4];
-};
-
-__device__ __forceinline__ uint32_t hidx(const Geom &g, const Site &s)
-{
-    return hidx(g, s.c[0], s.c[1], s.c[2], s.c[3]);
-}
-
-__device__ __forceinline__ Site shifted(const Geom &g, Site s, int mu, int step)
-{
-    const int n = mu == 0 ? g.nx : mu == 1 ? g.ny : mu == 2 ? g.nz : g.nt;
-    s.c[mu] = step > 0 ? wrap_up(s.c[mu], n) : wrap_dn(s.c[mu], n);
-    return s;
-}
-
 // FP64 sum over the block; the result is valid in thread 0.  Fixed order.
 __device__ __forceinline__ double block_sum(double v)
 {
@@ -70,16 +52,83 @@ __device__ __forceinline__ double block_sum(double v)
     return r;
 }
 
+__device__ __forceinline__ unsigned long long to_fixed(double v)
+{
+    return (unsigned long long)__double2ll_rn(v * (double)(1ll << kFixedShift));
+}
+
+__device__ __forceinline__ double from_fixed(unsigned long long u)
+{
+    return (double)(long long)u * (1.0 / (double)(1ll << kFixedShift));
+}
+
+__device__ __forceinline__ unsigned long long *bucket(unsigned long long *acc, int which, uint32_t b)
+{
+    return acc + ((size_t)which * kBuckets + (b % kBuckets)) * kBucketStride;
+}
+
+// Thread 0 adds the block's FP64 sum to bucket (block id mod kBuckets) of
+// fixed-point accumulator `which`.
+__device__ __forceinline__ void block_accumulate(double v, unsigned long long *acc, int which)
+{
+    const double b = block_sum(v);
+    if (threadIdx.x == 0) atomicAdd(bucket(acc, which, blockIdx.x), to_fixed(b));
+}
+
+// Exact integer total of accumulator `which` over its buckets, computed by a
+// block of kBuckets threads (valid in thread 0); the buckets are reset.
+__device__ __forceinline__ unsigned long long take_total(unsigned long long *acc, int which)
+{
+    __shared__ unsigned long long part[kBuckets / 64];
+    unsigned long long *p = bucket(acc, which, threadIdx.x);
+    unsigned long long v = *p;
+    *p = 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long t = 0ull;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBuckets / 64; ++i) t += part[i];
+    __syncthreads();
+    return t;
+}
+
 // Map the hardware workgroup id to a logical tile so that the workgroups one
 // XCD runs (dispatched round-robin over the 8 XCDs) cover one contiguous
-// stretch of the lattice and share that XCD's L2.
-__device__ __forceinline__ uint32_t logical_block(uint32_t b, uint32_t nb, bool remap)
+// stretch of the lattice and share that XCD's L2.  With `reverse`, each XCD
+// walks its stretch backwards: alternating passes then start where the
+// previous pass ended, on data still held by the memory-side cache.
+__device__ __forceinline__ uint32_t logical_block(uint32_t b, uint32_t nb, int remap, int reverse)
 {
-    if (!remap) return b;
-    const uint32_t per = nb >> 3;          // full rounds
+    if (!remap) return reverse ? nb - 1u - b : b;
+    const uint32_t per = nb >> 3;  // full rounds
     const uint32_t full = per << 3;
-    if (b >= full) return b;               // ragged tail keeps its id
-    return (b & 7u) * per + (b >> 3);
+    if (b >= full) return b;  // ragged tail keeps its id
+    const uint32_t local = reverse ? per - 1u - (b >> 3) : (b >> 3);
+    return (b & 7u) * per + local;
+}
+
+// One (mu, parity) plane group of the link field: four component planes at
+// uniform byte addresses, indexed by a 32-bit byte offset.
+struct Arr {
+    const char *c0, *c1, *c2, *c3;
+};
+
+__device__ __forceinline__ Arr arr(const float *links, uint32_t vh, int mu, int par)
+{
+    const size_t pb = (size_t)vh * 4u;
+    const char *b = reinterpret_cast<const char *>(links) + (size_t)((mu * 2 + par) * 4) * pb;
+    return Arr{b, b + pb, b + 2 * pb, b + 3 * pb};
+}
+
+__device__ __forceinline__ Q ld(const Arr &a, uint32_t h)
+{
+    const uint32_t off = h * 4u;
+    return Q{*reinterpret_cast<const float *>(a.c0 + off),
+             *reinterpret_cast<const float *>(a.c1 + off),
+             *reinterpret_cast<const float *>(a.c2 + off),
+             *reinterpret_cast<const float *>(a.c3 + off)};
 }
 
 // ------------------------------------------------------------------- init
@@ -101,171 +150,171 @@ __global__ void init_kernel(float *__restrict__ links, Geom g, int start, uint32
 }
 
 // ------------------------------------------------------------------- pass
-// One heat-bath pass over the sites of parity `par`, direction `mu`.  With
+// One heat-bath pass over the sites of parity `par` in direction MU.  With
 // MEASURE, (1/2)Tr(U'_mu(s) V_nu(s)) summed over nu < mu is accumulated: over
 // the odd passes of mu = 1, 2, 3 this is every plaquette of the end-of-sweep
 // configuration exactly once.
-template <bool MEASURE>
-__global__ __launch_bounds__(256) void pass_kernel(float *__restrict__ links, Geom g, int mu,
-                                                   int par, const uint32_t *__restrict__ sweep_ptr,
-                                                   float beta, uint32_t k0, uint32_t k1,
-                                                   uint32_t replica, double *__restrict__ partial,
-                                                   int remap)
+template <int MU, bool MEASURE>
+__global__ __launch_bounds__(256) void pass_kernel(float *__restrict__ links, Geom g, int par,
+                                                   Sums sums, float beta, uint32_t k0,
+                                                   uint32_t k1, uint32_t replica, int remap,
+                                                   int reverse)
 {
-    const uint32_t blk = logical_block(blockIdx.x, gridDim.x, remap);
-    const uint32_t h = blk * blockDim.x + threadIdx.x;
+    const uint32_t blk = logical_block(blockIdx.x, gridDim.x, remap, reverse);
+    const uint32_t gid = blk * blockDim.x + threadIdx.x;
     float meas = 0.0f;
-    if (h < g.vh) {
-        const uint32_t sweep = *sweep_ptr;
+    if (gid < g.vh) {
+        const uint32_t sweep = sums.cnt->sweep;
         const int opp = par ^ 1;
-        Site s;
-        decode(g, h, par, s.c[0], s.c[1], s.c[2], s.c[3]);
-        const Site s_pmu = shifted(g, s, mu, +1);
+        const PassSite s = pass_site(g, gid, par);
+        const Deltas d = neighbour_deltas(g, s);
+        const uint32_t h = s.h;
+        const Arr Umu_o = arr(links, g.vh, MU, opp);
         Q V{0.0f, 0.0f, 0.0f, 0.0f};
         Q Vlow{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int nu = 0; nu < 4; ++nu) {
-            if (nu == mu) continue;
-            const Site s_pnu = shifted(g, s, nu, +1);
-            const Site s_mnu = shifted(g, s, nu, -1);
-            const Site s_pmu_mnu = shifted(g, s_pmu, nu, -1);
+            if (nu == MU) continue;
+            const Arr Unu_p = arr(links, g.vh, nu, par);
+            const Arr Unu_o = arr(links, g.vh, nu, opp);
             // forward: U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
-            const Q A = load_q(links, g.vh, nu, opp, hidx(g, s_pmu));
-            const Q B = load_q(links, g.vh, mu, opp, hidx(g, s_pnu));
-            const Q C = load_q(links, g.vh, nu, par, h);
-            const Q fwd = qmul(qmul(A, qdag(B)), qdag(C));
-            // backward: U_nu(s+mu-nu)^+ U_mu(s-nu)^+ U_nu(s-nu)
-            const Q D = load_q(links, g.vh, nu, par, hidx(g, s_pmu_mnu));
-            const Q E = load_q(links, g.vh, mu, opp, hidx(g, s_mnu));
-            const Q F = load_q(links, g.vh, nu, opp, hidx(g, s_mnu));
-            const Q bwd = qmul(qmul(qdag(D), qdag(E)), F);
-            const Q st = qadd(fwd, bwd);
+            const Q A = ld(Unu_o, h + d.p[MU]);
+            const Q B = ld(Umu_o, h + d.p[nu]);
+            const Q C = ld(Unu_p, h);
+            // backward: U_nu(s+mu-nu)^+ U_mu(s-nu)^+ U_nu(s-nu) = (E D)^+ F
+            const Q D = ld(Unu_p, h + d.p[MU] + d.m[nu]);
+            const Q E = ld(Umu_o, h + d.m[nu]);
+            const Q F = ld(Unu_o, h + d.m[nu]);
+            const Q st = qadd(qmul(qmul(A, qdag(B)), qdag(C)), qmul(qdag(qmul(E, D)), F));
             V = qadd(V, st);
-            if (MEASURE && nu < mu) Vlow = qadd(Vlow, st);
+            if (MEASURE && nu < MU) Vlow = qadd(Vlow, st);
         }
-        const uint32_t site = 2u * h + (uint32_t)(s.c[0] & 1);
-        const Q Un = heatbath_link(V, beta, site, sweep, (uint32_t)mu, replica, k0, k1);
-        store_q(links, g.vh, mu, par, h, Un);
+        const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
+        const Q Un = heatbath_link(V, beta, site, sweep, word2((uint32_t)MU, TAG_TRIAL, replica),
+                                   k0, k1);
+        store_q(links, g.vh, MU, par, h, Un);
         if (MEASURE) meas = retr(Un, Vlow);
     }
-    if (MEASURE) {
-        const double b = block_sum((double)meas);
-        if (threadIdx.x == 0) partial[blk] = b;
-    }
+    if (MEASURE) block_accumulate((double)meas, sums.acc, ACC_PLAQ);
 }
 
 // -------------------------------------------------------------- plaquette
-// One thread per site (both parities): the six plaquettes
-// (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+ = (1/2)Tr(P Q^+) with
-// P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
+// One thread per site, both parities, in the pass traversal order: the six
+// plaquettes (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+ = (1/2)Tr(P Q^+)
+// with P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
 __global__ __launch_bounds__(256) void plaquette_kernel(const float *__restrict__ links, Geom g,
-                                                        double *__restrict__ partial)
+                                                        Sums sums, int remap)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t blk = logical_block(blockIdx.x, gridDim.x, remap, 0);
+    const uint32_t i = blk * blockDim.x + threadIdx.x;
     double acc = 0.0;
     if (i < 2u * g.vh) {
         const int par = i >= g.vh ? 1 : 0;
-        const uint32_t h = par ? i - g.vh : i;
         const int opp = par ^ 1;
-        Site s;
-        decode(g, h, par, s.c[0], s.c[1], s.c[2], s.c[3]);
+        const PassSite s = pass_site(g, par ? i - g.vh : i, par);
+        const Deltas d = neighbour_deltas(g, s);
         Q U[4];
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) U[mu] = load_q(links, g.vh, mu, par, h);
+        for (int mu = 0; mu < 4; ++mu) U[mu] = ld(arr(links, g.vh, mu, par), s.h);
         float sum = 0.0f;
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            const uint32_t hm = hidx(g, shifted(g, s, mu, +1));
+        for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
             for (int nu = mu + 1; nu < 4; ++nu) {
-                const uint32_t hn = hidx(g, shifted(g, s, nu, +1));
-                const Q P = qmul(U[mu], load_q(links, g.vh, nu, opp, hm));
-                const Q Qq = qmul(U[nu], load_q(links, g.vh, mu, opp, hn));
+                const Q P = qmul(U[mu], ld(arr(links, g.vh, nu, opp), s.h + d.p[mu]));
+                const Q Qq = qmul(U[nu], ld(arr(links, g.vh, mu, opp), s.h + d.p[nu]));
                 sum += retr_adj(P, Qq);
             }
-        }
         acc = (double)sum;
     }
-    const double b = block_sum(acc);
-    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+    block_accumulate(acc, sums.acc, ACC_PLAQ);
 }
 
 // --------------------------------------------------------------- Polyakov
-// One thread per spatial site: L(x) = (1/2)Tr prod_{t=0}^{Nt-1} U_3(x, t).
-__global__ __launch_bounds__(256) void polyakov_kernel(const float *__restrict__ links, Geom g,
-                                                       double *__restrict__ partial)
+// L(x) = (1/2)Tr prod_{t=0}^{Nt-1} U_3(x, t), t = 0 leftmost.  A workgroup
+// holds 64 spatial sites and S waves; wave w multiplies the w-th of S
+// contiguous t-segments for its 64 sites (consecutive lanes read consecutive
+// sites), and wave 0 multiplies the S segment products in t order from LDS.
+template <int S>
+__global__ __launch_bounds__(512) void polyakov_kernel(const float *__restrict__ links, Geom g,
+                                                       Sums sums)
 {
+    __shared__ Q seg_prod[S][64];
     const uint32_t ns3 = (uint32_t)g.nx * g.ny * g.nz;
-    const uint32_t xs = blockIdx.x * blockDim.x + threadIdx.x;
-    double acc = 0.0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t xs = blockIdx.x * 64u + (uint32_t)lane;
+    Q P{1.0f, 0.0f, 0.0f, 0.0f};
     if (xs < ns3) {
         const int x = (int)(xs % (uint32_t)g.nx);
         const uint32_t r = xs / (uint32_t)g.nx;
         const int y = (int)(r % (uint32_t)g.ny), z = (int)(r / (uint32_t)g.ny);
-        Q P{1.0f, 0.0f, 0.0f, 0.0f};
-        for (int t = 0; t < g.nt; ++t) {
-            const int par = (x + y + z + t) & 1;
-            P = qmul(P, load_q(links, g.vh, 3, par, hidx(g, x, y, z, t)));
+        const int len = g.nt / S;
+        const int t0 = w * len;
+        const int pbase = (x + y + z) & 1;
+        const uint32_t h0 = xs >> 1;
+        for (int t = t0; t < t0 + len; ++t) {
+            // site xs + ns3 t has half-site (xs >> 1) + t ns3/2 because ns3 is even
+            const Q U = load_q(links, g.vh, 3, (pbase + t) & 1, h0 + (uint32_t)t * (ns3 >> 1));
+            P = qmul(P, U);
         }
-        acc = (double)P.w;
     }
-    const double b = block_sum(acc);
-    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+    seg_prod[w][lane] = P;
+    __syncthreads();
+    double acc = 0.0;
+    if (w == 0 && xs < ns3) {
+        Q T = seg_prod[0][lane];
+#pragma unroll
+        for (int k = 1; k < S; ++k) T = qmul(T, seg_prod[k][lane]);
+        acc = (double)T.w;
+    }
+    block_accumulate(acc, sums.acc, ACC_POLY);
 }
 
-__global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict__ partial,
-                                                       int nblocks, int narrays, size_t stride,
-                                                       double scale, double *__restrict__ out,
-                                                       int abs_too)
+// ---------------------------------------------------------- bookkeeping
+// Launched with kBuckets threads.
+__global__ __launch_bounds__(kBuckets) void take_kernel(Sums sums, int which, double scale,
+                                                        double *__restrict__ out)
 {
-    double acc = 0.0;
-    for (int a = 0; a < narrays; ++a)
-        for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partial[a * stride + i];
-    const double tot = block_sum(acc);
+    const unsigned long long t = take_total(sums.acc, which);
     if (threadIdx.x == 0) {
-        out[0] = tot * scale;
-        if (abs_too) out[1] = fabs(tot * scale);
+        const double v = from_fixed(t) * scale;
+        out[0] = v;
+        out[1] = fabs(v);
     }
 }
 
-// End of a sweep: optional fused-plaquette sum, history append, counters.
-// measure: bit 0 plaquette from the fused partials, bit 1 plaquette from
-// extra[R_PLAQ], bit 2 Polyakov from extra[R_POLY_*].
-__global__ __launch_bounds__(256) void sweep_end_kernel(Counters *__restrict__ c,
-                                                        const double *__restrict__ partial,
-                                                        int nblocks, size_t stride, double scale,
-                                                        int measure, double *__restrict__ hist,
-                                                        const double *__restrict__ extra)
+// End of a sweep (kBuckets threads): flags 1 plaquette, 2 Polyakov, 4 append
+// a history row; accumulators reset, sweep counter advanced.
+__global__ __launch_bounds__(kBuckets) void sweep_end_kernel(Sums sums, int flags,
+                                                             double plaq_scale, double poly_scale,
+                                                             double *__restrict__ hist)
 {
-    double acc = 0.0;
-    if (measure & 1)
-        for (int a = 0; a < 3; ++a)
-            for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partial[a * stride + i];
-    const double tot = block_sum(acc);
+    const unsigned long long tp = take_total(sums.acc, ACC_PLAQ);
+    const unsigned long long tl = take_total(sums.acc, ACC_POLY);
     if (threadIdx.x == 0) {
-        if (measure && hist) {
+        Counters *c = sums.cnt;
+        if ((flags & 4) && hist) {
             const uint32_t m = c->meas_idx;
-            double p = 0.0, ls = 0.0, la = 0.0;
-            if (measure & 1) p = tot * scale;
-            if (measure & 2) p = extra[R_PLAQ];
-            if (measure & 4) {
-                ls = extra[R_POLY_SIGNED];
-                la = extra[R_POLY_ABS];
-            }
+            const double p = (flags & 1) ? from_fixed(tp) * plaq_scale : 0.0;
+            const double l = (flags & 2) ? from_fixed(tl) * poly_scale : 0.0;
             hist[3 * (size_t)m + 0] = p;
-            hist[3 * (size_t)m + 1] = ls;
-            hist[3 * (size_t)m + 2] = la;
+            hist[3 * (size_t)m + 1] = l;
+            hist[3 * (size_t)m + 2] = fabs(l);
             c->meas_idx = m + 1;
         }
         c->sweep = c->sweep + 1;
     }
 }
 
-__global__ void set_counter_kernel(Counters *c, uint32_t sweep, uint32_t meas, int which)
+// which: 1 set sweep, 2 set meas_idx, 4 zero the accumulators (kBuckets threads).
+__global__ __launch_bounds__(kBuckets) void set_counter_kernel(Sums sums, uint32_t sweep,
+                                                               uint32_t meas, int which)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (which & 1) c->sweep = sweep;
-        if (which & 2) c->meas_idx = meas;
+    if (which & 4)
+        for (int a = 0; a < kNumAcc; ++a) *bucket(sums.acc, a, threadIdx.x) = 0ull;
+    if (threadIdx.x == 0) {
+        if (which & 1) sums.cnt->sweep = sweep;
+        if (which & 2) sums.cnt->meas_idx = meas;
     }
 }
 
@@ -302,11 +351,12 @@ __global__ void gauge_apply_kernel(float *__restrict__ links, Geom g,
     const int mp = blockIdx.y;
     if (h >= g.vh) return;
     const int mu = mp >> 1, par = mp & 1;
-    Site s;
-    decode(g, h, par, s.c[0], s.c[1], s.c[2], s.c[3]);
-    const uint32_t site = 2u * h + (uint32_t)(s.c[0] & 1);
-    const Site f = shifted(g, s, mu, +1);
-    const uint32_t fsite = 2u * hidx(g, f) + (uint32_t)(f.c[0] & 1);
+    int c[4];
+    decode(g, h, par, c[0], c[1], c[2], c[3]);
+    const uint32_t site = 2u * h + (uint32_t)(c[0] & 1);
+    const int n[4] = {g.nx, g.ny, g.nz, g.nt};
+    c[mu] = c[mu] + 1 == n[mu] ? 0 : c[mu] + 1;
+    const uint32_t fsite = 2u * hidx(g, c[0], c[1], c[2], c[3]) + (uint32_t)(c[0] & 1);
     const float4 a = G[site], b = G[fsite];
     const Q U = load_q(links, g.vh, mu, par, h);
     const Q r = qmul(qmul(Q{a.x, a.y, a.z, a.w}, U), qdag(Q{b.x, b.y, b.z, b.w}));
@@ -334,27 +384,34 @@ __global__ void test_links_kernel(const float4 *__restrict__ V, int64_t n, float
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float4 v = V[i];
-    const Q Vq{v.x, v.y, v.z, v.w};
-    const Q U = heatbath_link(Vq, beta, (uint32_t)i, sweep, mu, replica, k0, k1);
+    int nt = 0;
+    const Q U = heatbath_link(Q{v.x, v.y, v.z, v.w}, beta, (uint32_t)i, sweep,
+                              word2(mu, TAG_TRIAL, replica), k0, k1, &nt);
     out[i] = make_float4(U.w, U.x, U.y, U.z);
-    if (ntrials) {
-        int nt = 0;
-        sample_delta(beta * sqrtf(qdot(Vq, Vq)), (uint32_t)i, sweep, word2(mu, TAG_TRIAL, replica),
-                     k0, k1, &nt);
-        ntrials[i] = nt;
-    }
+    if (ntrials) ntrials[i] = nt;
 }
 
 inline uint32_t lo32(uint64_t v) { return (uint32_t)v; }
 inline uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
 inline unsigned nblk(uint64_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
-}  // namespace
-
-size_t max_partial_blocks(int64_t volume)
+template <int MU>
+void launch_pass_mu(float *links, const Geom &g, int par, Sums c, float beta, uint64_t seed,
+                    uint32_t replica, bool measure, const LaunchCfg &cfg, hipStream_t stream)
 {
-    return (size_t)((volume + kMinBlock - 1) / kMinBlock) + 8;
+    const unsigned nb = nblk(g.vh, (unsigned)cfg.pass_block);
+    const int rev = cfg.snake ? par : 0;
+    if (measure)
+        hipLaunchKernelGGL((pass_kernel<MU, true>), dim3(nb), dim3(cfg.pass_block), 0, stream,
+                           links, g, par, c, beta, lo32(seed), hi32(seed), replica,
+                           (int)cfg.xcd_remap, rev);
+    else
+        hipLaunchKernelGGL((pass_kernel<MU, false>), dim3(nb), dim3(cfg.pass_block), 0, stream,
+                           links, g, par, c, beta, lo32(seed), hi32(seed), replica,
+                           (int)cfg.xcd_remap, rev);
 }
+
+}  // namespace
 
 hipError_t launch_init(float *links, const Geom &g, int start, uint64_t seed, uint32_t replica,
                        hipStream_t stream)
@@ -367,61 +424,60 @@ hipError_t launch_init(float *links, const Geom &g, int start, uint64_t seed, ui
 
 int pass_grid(const Geom &g, const LaunchCfg &cfg) { return (int)nblk(g.vh, cfg.pass_block); }
 
-hipError_t launch_pass(float *links, const Geom &g, int mu, int par, const uint32_t *sweep_ptr,
-                       float beta, uint64_t seed, uint32_t replica, double *partial,
-                       const LaunchCfg &cfg, hipStream_t stream)
+hipError_t launch_pass(float *links, const Geom &g, int mu, int par, Sums c, float beta,
+                       uint64_t seed, uint32_t replica, bool measure, const LaunchCfg &cfg,
+                       hipStream_t stream)
 {
-    const unsigned nb = (unsigned)pass_grid(g, cfg);
-    if (partial)
-        hipLaunchKernelGGL(pass_kernel<true>, dim3(nb), dim3(cfg.pass_block), 0, stream, links, g,
-                           mu, par, sweep_ptr, beta, lo32(seed), hi32(seed), replica, partial,
-                           (int)cfg.xcd_remap);
-    else
-        hipLaunchKernelGGL(pass_kernel<false>, dim3(nb), dim3(cfg.pass_block), 0, stream, links,
-                           g, mu, par, sweep_ptr, beta, lo32(seed), hi32(seed), replica, partial,
-                           (int)cfg.xcd_remap);
+    switch (mu) {
+    case 0: launch_pass_mu<0>(links, g, par, c, beta, seed, replica, measure, cfg, stream); break;
+    case 1: launch_pass_mu<1>(links, g, par, c, beta, seed, replica, measure, cfg, stream); break;
+    case 2: launch_pass_mu<2>(links, g, par, c, beta, seed, replica, measure, cfg, stream); break;
+    default: launch_pass_mu<3>(links, g, par, c, beta, seed, replica, measure, cfg, stream); break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_plaquette(const float *links, const Geom &g, double *partial, int *nblocks,
-                            hipStream_t stream)
+hipError_t launch_plaquette(const float *links, const Geom &g, Sums c, hipStream_t stream)
 {
-    const unsigned nb = nblk(2ull * g.vh, 256);
-    *nblocks = (int)nb;
-    hipLaunchKernelGGL(plaquette_kernel, dim3(nb), dim3(256), 0, stream, links, g, partial);
+    hipLaunchKernelGGL(plaquette_kernel, dim3(nblk(2ull * g.vh, 256)), dim3(256), 0, stream,
+                       links, g, c, 1);
     return hipGetLastError();
 }
 
-hipError_t launch_polyakov(const float *links, const Geom &g, double *partial, int *nblocks,
-                           hipStream_t stream)
+hipError_t launch_polyakov(const float *links, const Geom &g, Sums c, hipStream_t stream)
 {
-    const unsigned nb = nblk((uint64_t)g.nx * g.ny * g.nz, 256);
-    *nblocks = (int)nb;
-    hipLaunchKernelGGL(polyakov_kernel, dim3(nb), dim3(256), 0, stream, links, g, partial);
+    const uint64_t ns3 = (uint64_t)g.nx * g.ny * g.nz;
+    int S = 1;
+    while (S < 8 && g.nt % (2 * S) == 0) S *= 2;
+    const dim3 grid(nblk(ns3, 64)), block(64 * S);
+    switch (S) {
+    case 8: hipLaunchKernelGGL(polyakov_kernel<8>, grid, block, 0, stream, links, g, c); break;
+    case 4: hipLaunchKernelGGL(polyakov_kernel<4>, grid, block, 0, stream, links, g, c); break;
+    case 2: hipLaunchKernelGGL(polyakov_kernel<2>, grid, block, 0, stream, links, g, c); break;
+    default: hipLaunchKernelGGL(polyakov_kernel<1>, grid, block, 0, stream, links, g, c); break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partial, int nblocks, int narrays, size_t stride,
-                           double scale, double *out, int abs_too, hipStream_t stream)
+hipError_t launch_take(Sums c, int which, double scale, double *out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, stream, partial, nblocks, narrays,
-                       stride, scale, out, abs_too);
+    hipLaunchKernelGGL(take_kernel, dim3(1), dim3(kBuckets), 0, stream, c, which, scale, out);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_end(Counters *counters, const double *partial, int nblocks,
-                            size_t stride, double scale, int measure, double *hist,
-                            const double *extra, hipStream_t stream)
+hipError_t launch_sweep_end(Sums c, int flags, double plaq_scale, double poly_scale,
+                            double *hist, hipStream_t stream)
 {
-    hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(256), 0, stream, counters, partial,
-                       nblocks, stride, scale, measure, hist, extra);
+    hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(kBuckets), 0, stream, c, flags, plaq_scale,
+                       poly_scale, hist);
     return hipGetLastError();
 }
 
-hipError_t launch_set_counter(Counters *c, uint32_t sweep, uint32_t meas, int which,
+hipError_t launch_set_counter(Sums c, uint32_t sweep, uint32_t meas, int which,
                               hipStream_t stream)
 {
-    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, stream, c, sweep, meas, which);
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(kBuckets), 0, stream, c, sweep, meas,
+                       which);
     return hipGetLastError();
 }
 

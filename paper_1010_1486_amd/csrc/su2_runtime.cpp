@@ -3,6 +3,7 @@
 // measurement plumbing around the gfx950 kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -42,9 +43,11 @@ struct su2_ctx {
     LaunchCfg cfg;
 
     Counters *counters() { return reinterpret_cast<Counters *>(scratch + kCountersOff); }
+    Sums sums()
+    {
+        return Sums{counters(), reinterpret_cast<unsigned long long *>(scratch + kAccOff)};
+    }
     double *results() { return reinterpret_cast<double *>(scratch + kResultsOff); }
-    double *partials() { return reinterpret_cast<double *>(scratch + kPartialsOff); }
-    size_t partial_stride() const { return max_partial_blocks(volume); }
 };
 
 namespace {
@@ -73,11 +76,33 @@ int check_dims(const int32_t *dims)
                                       std::to_string(dims[i]) + " in direction " +
                                       std::to_string(i) + ")");
     int64_t v = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
-    if (v / 2 >= (int64_t)1 << 31) return fail(SU2_ERANGE, "V/2 must be < 2^31");
+    if (v / 2 >= (int64_t)1 << 30) return fail(SU2_ERANGE, "V/2 must be < 2^30");
     return SU2_OK;
 }
 
-Geom make_geom(const int32_t *d)
+// Multiplier and shift for exact division of 31-bit numerators by d
+// (Granlund & Montgomery 1994, Thm. 4.2 with N = 31).
+void magic(uint32_t d, uint32_t &m, uint32_t &s)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    m = (uint32_t)(((1ull << (31 + l)) + d - 1) / d);
+    s = 31 + l;
+}
+
+uint32_t host_fdiv(uint32_t n, uint32_t m, uint32_t s)
+{
+    return (uint32_t)(((uint64_t)n * m) >> s);
+}
+
+uint32_t pow2_divisor_log(int32_t n, uint32_t cap)
+{
+    uint32_t l = 0;
+    while (l < cap && (n % (2 << l)) == 0) ++l;
+    return l;
+}
+
+Geom make_geom(const int32_t *d, uint32_t lg_tz, uint32_t lg_tt)
 {
     Geom g;
     g.nx = d[0];
@@ -86,16 +111,33 @@ Geom make_geom(const int32_t *d)
     g.nt = d[3];
     g.vh = (uint32_t)(((int64_t)d[0] * d[1] * d[2] * d[3]) / 2);
     g.hx = (uint32_t)(d[0] / 2);
-    g.sy = g.hx;
-    g.sz = g.hx * (uint32_t)d[1];
-    g.st = g.sz * (uint32_t)d[2];
+    g.P = g.hx * (uint32_t)d[1];
+    g.PZ = g.P * (uint32_t)d[2];
+    g.wy = (uint32_t)(d[1] - 1) * g.hx;
+    g.wz = (uint32_t)(d[2] - 1) * g.P;
+    g.wt = (uint32_t)(d[3] - 1) * g.PZ;
+    g.lg_tz = std::min(lg_tz, pow2_divisor_log(d[2], 8));
+    g.lg_tt = std::min(lg_tt, pow2_divisor_log(d[3], 8));
+    g.ntz = (uint32_t)d[2] >> g.lg_tz;
+    magic(g.P, g.m_P, g.s_P);
+    magic(g.hx, g.m_hx, g.s_hx);
+    magic(g.ntz, g.m_ntz, g.s_ntz);
     return g;
 }
 
-size_t scratch_bytes_for(int64_t volume)
+// The divisions are exact by construction; check the extreme numerators.
+bool geom_selfcheck(const Geom &g)
 {
-    return kPartialsOff + sizeof(double) * kPartialArrays * max_partial_blocks(volume);
+    const uint32_t ns[] = {0u, 1u, g.P - 1u, g.P, g.vh - 1u, g.vh / 2u + 7u};
+    for (uint32_t n : ns) {
+        if (host_fdiv(n, g.m_P, g.s_P) != n / g.P) return false;
+        if (host_fdiv(n, g.m_hx, g.s_hx) != n / g.hx) return false;
+        if (host_fdiv(n, g.m_ntz, g.s_ntz) != n / g.ntz) return false;
+    }
+    return true;
 }
+
+size_t scratch_bytes_for(int64_t) { return kScratchBytes; }
 
 int check_ctx(su2_ctx *c)
 {
@@ -111,47 +153,25 @@ int enqueue_sweeps(su2_ctx *c, int32_t n, int mode, int32_t reunit_every, int me
     if (mode != SU2_KP && mode != SU2_LEARNED) return fail(SU2_EINVAL, "unknown mode");
     if (mode == SU2_LEARNED) return fail(SU2_ESTATE, "no learned proposal loaded");
     const float beta = (float)c->beta;
-    const size_t stride = c->partial_stride();
-    double *part = c->partials();
-    const int nb_pass = pass_grid(c->g, c->cfg);
     const double inv6v = 1.0 / (6.0 * (double)c->volume);
-    // history slots restart at 0 for this call
-    if (hist) HIP_TRY(launch_set_counter(c->counters(), 0, 0, 2, c->stream));
+    const double inv_ns3 = 1.0 / ((double)c->dims[0] * c->dims[1] * c->dims[2]);
+    // history rows restart at 0 for this call
+    if (hist) HIP_TRY(launch_set_counter(c->sums(), 0, 0, 2, c->stream));
     for (int32_t i = 0; i < n; ++i) {
         const uint32_t j = c->sweep + (uint32_t)i;
         const bool reunit = reunit_every > 0 && ((j + 1u) % (uint32_t)reunit_every) == 0u;
-        const bool fused = hist && (meas & SU2_MEAS_PLAQ) && !reunit;
+        const bool want_p = hist && (meas & SU2_MEAS_PLAQ);
+        const bool fused = want_p && !reunit;
         for (int mu = 0; mu < 4; ++mu)
-            for (int par = 0; par < 2; ++par) {
-                double *pp = (fused && par == 1 && mu >= 1) ? part + (size_t)(mu - 1) * stride
-                                                            : nullptr;
-                HIP_TRY(launch_pass(c->links, c->g, mu, par, &c->counters()->sweep, beta,
-                                    c->seed, c->replica, pp, c->cfg, c->stream));
-            }
-        int mflags = 0;
+            for (int par = 0; par < 2; ++par)
+                HIP_TRY(launch_pass(c->links, c->g, mu, par, c->sums(), beta, c->seed,
+                                    c->replica, fused && par == 1 && mu >= 1, c->cfg, c->stream));
         if (reunit) HIP_TRY(launch_reunitarize(c->links, c->g, c->stream));
-        if (hist && (meas & SU2_MEAS_PLAQ)) {
-            if (fused) {
-                mflags |= 1;
-            } else {
-                int nb = 0;
-                HIP_TRY(launch_plaquette(c->links, c->g, part + 3 * stride, &nb, c->stream));
-                HIP_TRY(launch_finalize(part + 3 * stride, nb, 1, stride, inv6v,
-                                        c->results() + R_PLAQ, 0, c->stream));
-                mflags |= 2;
-            }
-        }
-        if (hist && (meas & SU2_MEAS_POLY)) {
-            int nb = 0;
-            const double inv_ns3 = 1.0 / ((double)c->dims[0] * c->dims[1] * c->dims[2]);
-            HIP_TRY(launch_polyakov(c->links, c->g, part + 3 * stride, &nb, c->stream));
-            HIP_TRY(launch_finalize(part + 3 * stride, nb, 1, stride, inv_ns3,
-                                    c->results() + R_POLY_SIGNED, 1, c->stream));
-            mflags |= 4;
-        }
-        if (hist && !mflags) mflags = 8;  // history row of zeros
-        HIP_TRY(launch_sweep_end(c->counters(), part, nb_pass, stride, inv6v, mflags, hist,
-                                 c->results(), c->stream));
+        if (want_p && !fused) HIP_TRY(launch_plaquette(c->links, c->g, c->sums(), c->stream));
+        const bool want_l = hist && (meas & SU2_MEAS_POLY);
+        if (want_l) HIP_TRY(launch_polyakov(c->links, c->g, c->sums(), c->stream));
+        const int flags = (want_p ? 1 : 0) | (want_l ? 2 : 0) | (hist ? 4 : 0);
+        HIP_TRY(launch_sweep_end(c->sums(), flags, inv6v, inv_ns3, hist, c->stream));
     }
     c->sweep += (uint32_t)n;
     return SU2_OK;
@@ -198,7 +218,11 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
     su2_ctx *c = new (std::nothrow) su2_ctx();
     if (!c) return fail(SU2_ENOMEM, "host allocation failed");
     std::memcpy(c->dims, dims, sizeof(c->dims));
-    c->g = make_geom(dims);
+    c->g = make_geom(dims, 3, 3);
+    if (!geom_selfcheck(c->g)) {
+        delete c;
+        return fail(SU2_ERANGE, "index arithmetic self-check failed for these extents");
+    }
     c->volume = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
     c->beta = beta;
     c->seed = seed;
@@ -235,7 +259,7 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
         c->stream = st;
         c->own_stream = true;
     }
-    hipError_t e = launch_set_counter(c->counters(), 0, 0, 3, c->stream);
+    hipError_t e = launch_set_counter(c->sums(), 0, 0, 7, c->stream);
     if (e == hipSuccess) e = launch_init(c->links, c->g, start, seed, 0, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -306,17 +330,14 @@ int su2_plaquette(su2_ctx *c, double *out)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
-    const size_t stride = c->partial_stride();
-    double *part = c->partials() + 3 * stride;
-    int nb = 0;
-    HIP_TRY(launch_plaquette(c->links, c->g, part, &nb, c->stream));
-    HIP_TRY(launch_finalize(part, nb, 1, stride, 1.0 / (6.0 * (double)c->volume),
-                            c->results() + R_PLAQ, 0, c->stream));
-    double v = 0.0;
-    HIP_TRY(hipMemcpyAsync(&v, c->results() + R_PLAQ, sizeof(double), hipMemcpyDeviceToHost,
+    HIP_TRY(launch_plaquette(c->links, c->g, c->sums(), c->stream));
+    HIP_TRY(launch_take(c->sums(), ACC_PLAQ, 1.0 / (6.0 * (double)c->volume),
+                        c->results() + R_PLAQ, c->stream));
+    double v[2] = {0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(v, c->results() + R_PLAQ, 2 * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    *out = v;
+    *out = v[0];
     return SU2_OK;
 }
 
@@ -324,13 +345,10 @@ int su2_polyakov(su2_ctx *c, double *out_signed, double *out_abs)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    const size_t stride = c->partial_stride();
-    double *part = c->partials() + 3 * stride;
-    int nb = 0;
-    HIP_TRY(launch_polyakov(c->links, c->g, part, &nb, c->stream));
-    HIP_TRY(launch_finalize(part, nb, 1, stride,
-                            1.0 / ((double)c->dims[0] * c->dims[1] * c->dims[2]),
-                            c->results() + R_POLY_SIGNED, 1, c->stream));
+    HIP_TRY(launch_polyakov(c->links, c->g, c->sums(), c->stream));
+    HIP_TRY(launch_take(c->sums(), ACC_POLY,
+                        1.0 / ((double)c->dims[0] * c->dims[1] * c->dims[2]),
+                        c->results() + R_POLY_SIGNED, c->stream));
     double v[2] = {0.0, 0.0};
     HIP_TRY(hipMemcpyAsync(v, c->results() + R_POLY_SIGNED, 2 * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
@@ -409,7 +427,7 @@ int su2_set_sweep(su2_ctx *c, uint32_t sweep)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIP_TRY(launch_set_counter(c->counters(), sweep, 0, 1, c->stream));
+    HIP_TRY(launch_set_counter(c->sums(), sweep, 0, 1, c->stream));
     c->sweep = sweep;
     return SU2_OK;
 }
@@ -449,14 +467,35 @@ int su2_synchronize(su2_ctx *c)
     return SU2_OK;
 }
 
-int su2_set_launch(su2_ctx *c, int block, int xcd_remap)
+static int lg_of_tile(int tile, int32_t extent, uint32_t cur, uint32_t *out)
+{
+    if (tile == 0) {
+        *out = cur;
+        return SU2_OK;
+    }
+    if (tile < 0 || (tile & (tile - 1)) || extent % tile)
+        return fail(SU2_EINVAL, "tile sizes must be powers of two dividing the extent");
+    uint32_t l = 0;
+    while ((1 << l) < tile) ++l;
+    *out = l;
+    return SU2_OK;
+}
+
+int su2_set_launch(su2_ctx *c, int block, int xcd_remap, int tile_z, int tile_t)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (block < 64 || block > 256 || (block % 64) != 0)
         return fail(SU2_EINVAL, "block must be 64, 128, 192 or 256");
+    uint32_t lz, lt;
+    if ((rc = lg_of_tile(tile_z, c->dims[2], c->g.lg_tz, &lz))) return rc;
+    if ((rc = lg_of_tile(tile_t, c->dims[3], c->g.lg_tt, &lt))) return rc;
+    Geom g = make_geom(c->dims, lz, lt);
+    if (!geom_selfcheck(g)) return fail(SU2_ERANGE, "index arithmetic self-check failed");
+    c->g = g;
     c->cfg.pass_block = block;
-    c->cfg.xcd_remap = xcd_remap != 0;
+    c->cfg.xcd_remap = (xcd_remap & 1) != 0;
+    c->cfg.snake = (xcd_remap & 2) == 0;
     return SU2_OK;
 }
 
@@ -511,8 +550,32 @@ int su2_test_pass(su2_ctx *c, int mu, int parity)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1) return fail(SU2_EINVAL, "bad mu/parity");
-    HIP_TRY(launch_pass(c->links, c->g, mu, parity, &c->counters()->sweep, (float)c->beta,
-                        c->seed, c->replica, nullptr, c->cfg, c->stream));
+    HIP_TRY(launch_pass(c->links, c->g, mu, parity, c->sums(), (float)c->beta, c->seed,
+                        c->replica, false, c->cfg, c->stream));
+    return SU2_OK;
+}
+
+int su2_test_index_map(const int32_t dims[4], int tile_z, int tile_t, int parity, uint32_t *out)
+{
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!out || (parity != 0 && parity != 1)) return fail(SU2_EINVAL, "bad arguments");
+    Geom g0 = make_geom(dims, 3, 3);
+    uint32_t lz, lt;
+    if ((rc = lg_of_tile(tile_z, dims[2], g0.lg_tz, &lz))) return rc;
+    if ((rc = lg_of_tile(tile_t, dims[3], g0.lg_tt, &lt))) return rc;
+    const Geom g = make_geom(dims, lz, lt);
+    if (!geom_selfcheck(g)) return fail(SU2_ERANGE, "index arithmetic self-check failed");
+    for (uint32_t gid = 0; gid < g.vh; ++gid) {
+        const su2dev::PassSite ps = su2dev::pass_site(g, gid, parity);
+        const su2dev::Deltas d = su2dev::neighbour_deltas(g, ps);
+        uint32_t *o = out + 9 * (size_t)gid;
+        o[0] = 2u * ps.h + (uint32_t)(ps.x & 1);
+        for (int k = 0; k < 4; ++k) {
+            o[1 + 2 * k] = ps.h + d.p[k];
+            o[2 + 2 * k] = ps.h + d.m[k];
+        }
+    }
     return SU2_OK;
 }
 

@@ -57,11 +57,12 @@ _SIGS = {
     "su2_set_replica": (_int, [_vp, _u32]),
     "su2_links_device": (_int, [_vp, _vp, _vp]),
     "su2_synchronize": (_int, [_vp]),
-    "su2_set_launch": (_int, [_vp, _int, _int]),
+    "su2_set_launch": (_int, [_vp, _int, _int, _int, _int]),
     "su2_test_philox": (_int, [_vp, _i64, _u64, _vp]),
     "su2_test_heatbath_links": (_int, [_vp, _i64, _d, _u64, _u32, _u32, _u32, _vp, _vp]),
     "su2_test_pass": (_int, [_vp, _int, _int]),
     "su2_test_gauge_transform": (_int, [_vp, _u64]),
+    "su2_test_index_map": (_int, [_vp, _int, _int, _int, _vp]),
 }
 
 
@@ -193,8 +194,8 @@ def su2_synchronize(h):
     _check(lib().su2_synchronize(h))
 
 
-def su2_set_launch(h, block, xcd_remap):
-    _check(lib().su2_set_launch(h, int(block), int(xcd_remap)))
+def su2_set_launch(h, block, xcd_remap, tile_z=0, tile_t=0):
+    _check(lib().su2_set_launch(h, int(block), int(xcd_remap), int(tile_z), int(tile_t)))
 
 
 def su2_links_device(h):
@@ -222,6 +223,14 @@ def su2_test_heatbath_links(V, beta, seed, sweep, mu, replica=0, want_trials=Fal
 
 def su2_test_pass(h, mu, parity):
     _check(lib().su2_test_pass(h, int(mu), int(parity)))
+
+
+def su2_test_index_map(dims, parity, tile_z=0, tile_t=0):
+    d = _dims(dims)
+    vh = int(np.prod(d.astype(np.int64))) // 2
+    out = np.empty((vh, 9), dtype=np.uint32)
+    _check(lib().su2_test_index_map(_p(d), int(tile_z), int(tile_t), int(parity), _p(out)))
+    return out
 
 
 def su2_test_gauge_transform(h, seed):
@@ -303,8 +312,8 @@ class Lattice:
     def set_replica(self, r):
         su2_set_replica(self.h, r)
 
-    def set_launch(self, block, xcd_remap=True):
-        su2_set_launch(self.h, block, xcd_remap)
+    def set_launch(self, block, xcd_remap=True, tile_z=0, tile_t=0):
+        su2_set_launch(self.h, block, xcd_remap, tile_z, tile_t)
 
     def synchronize(self):
         su2_synchronize(self.h)

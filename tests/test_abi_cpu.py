@@ -21,7 +21,7 @@ def test_sizes():
     assert su2.su2_links_bytes([4, 4, 4, 4]) == 64 * 256
     assert su2.su2_links_bytes([48, 48, 48, 48]) == 64 * 48 ** 4
     assert su2.su2_links_bytes([3, 4, 4, 4]) == 0
-    assert su2.su2_scratch_bytes([4, 4, 4, 4]) > 256
+    assert su2.su2_scratch_bytes([4, 4, 4, 4]) >= 256
 
 
 @pytest.mark.parametrize("dims", [[3, 4, 4, 4], [4, 4, 4, 5], [0, 4, 4, 4], [4, 1, 4, 4]])
@@ -58,3 +58,33 @@ def test_bad_arguments_rejected():
     assert rc == su2.SU2_ENOMEM
     assert lib.su2_test_philox(None, -1, 0, None) == su2.SU2_EINVAL
     assert lib.su2_test_philox(None, 0, 0, None) == su2.SU2_OK
+
+
+@pytest.mark.parametrize("dims,tiles", [
+    ([2, 2, 2, 2], (0, 0)), ([4, 4, 4, 4], (0, 0)), ([4, 6, 2, 8], (2, 4)),
+    ([8, 6, 8, 10], (8, 2)), ([12, 10, 8, 6], (4, 2)), ([6, 4, 12, 16], (4, 16)),
+    ([48, 4, 48, 8], (16, 8))], ids=str)
+def test_pass_index_map_matches_oracle_neighbours(orc, dims, tiles):
+    """The pass kernel's traversal (tiled (z,t)-plane order, magic-number
+    division, additive neighbour offsets) evaluated on the host: every site of
+    the parity is visited exactly once and every neighbour index equals the
+    oracle's periodic shift."""
+    V = int(np.prod(dims))
+    for par in (0, 1):
+        m = su2.su2_test_index_map(dims, par, *tiles).astype(np.int64)
+        sites = m[:, 0]
+        assert np.array_equal(np.sort(sites), np.sort(
+            [s for s in range(V) if orc.parity(dims, s) == par]))
+        for row in m[:: max(1, len(m) // 400)]:
+            s = int(row[0])
+            for d in range(4):
+                assert row[1 + 2 * d] == orc.shift(dims, s, d, +1) >> 1
+                assert row[2 + 2 * d] == orc.shift(dims, s, d, -1) >> 1
+        assert m[:, 1:].max() < V // 2
+
+
+def test_index_map_rejects_bad_tiles():
+    with pytest.raises(su2.SU2Error):
+        su2.su2_test_index_map([4, 4, 6, 4], 0, tile_z=4)
+    with pytest.raises(su2.SU2Error):
+        su2.su2_test_index_map([4, 4, 4, 4], 0, tile_t=3)

@@ -124,6 +124,12 @@ def test_resume_and_determinism(su2):
     with su2.Lattice(dims, 2.2, 5, su2.SU2_HOT) as d:
         d.heatbath_sweep(6)
         np.testing.assert_array_equal(d.get_links(), full)
+    # measured histories (fixed-point global sums) are bit-reproducible
+    hs = []
+    for _ in range(2):
+        with su2.Lattice(dims, 2.2, 5, su2.SU2_HOT) as e:
+            hs.append(e.sweep_measure(5, reunit_every=2, meas=3).cpu().numpy())
+    np.testing.assert_array_equal(hs[0], hs[1])
 
 
 def test_replica_changes_stream(su2):
