@@ -485,6 +485,224 @@ void orc_gauge_transform(const int32_t dims[4], double *U, uint64_t seed, uint32
     free(G);
 }
 
+/* ======================================================= learned proposal */
+/* The proposal for a0 is a monotone rational-quadratic spline flow (Durkan,
+ * Bekasov, Murray, Papamakarios 2019) whose 47 parameters come from a small
+ * MLP of alpha; the Metropolis step with weight w(x) = exp(alpha x)
+ * sqrt(1 - x^2) / q(x) keeps the heat-bath distribution of Sec. 2 exact. */
+#define NN_MIN_BIN 1e-3
+#define NN_MIN_DERIV 1e-3
+
+double orc_nn_feature(double alpha)
+{
+    return 2.0 * (log(alpha) - log(ORC_NN_ALPHA_LO)) / (log(ORC_NN_ALPHA_HI) - log(ORC_NN_ALPHA_LO)) -
+           1.0;
+}
+
+void orc_nn_forward(const float *prm, double f, double out[ORC_NN_OUT])
+{
+    const float *W1 = prm, *b1 = prm + 32, *W2 = prm + 64, *b2 = prm + 64 + 1024;
+    const float *W3 = prm + 64 + 1024 + 32, *b3 = W3 + 47 * 32;
+    double h1[ORC_NN_H], h2[ORC_NN_H];
+    for (int i = 0; i < ORC_NN_H; ++i) h1[i] = tanh((double)W1[i] * f + (double)b1[i]);
+    for (int i = 0; i < ORC_NN_H; ++i) {
+        double a = b2[i];
+        for (int j = 0; j < ORC_NN_H; ++j) a += (double)W2[i * ORC_NN_H + j] * h1[j];
+        h2[i] = tanh(a);
+    }
+    for (int i = 0; i < ORC_NN_OUT; ++i) {
+        double a = b3[i];
+        for (int j = 0; j < ORC_NN_H; ++j) a += (double)W3[i * ORC_NN_H + j] * h2[j];
+        out[i] = a;
+    }
+}
+
+static void knots_from_logits(const double *logit, double *k)
+{
+    double mx = logit[0], sum = 0.0, p[ORC_NN_BINS];
+    for (int i = 1; i < ORC_NN_BINS; ++i) mx = logit[i] > mx ? logit[i] : mx;
+    for (int i = 0; i < ORC_NN_BINS; ++i) sum += (p[i] = exp(logit[i] - mx));
+    k[0] = -1.0;
+    for (int i = 0; i < ORC_NN_BINS; ++i)
+        k[i + 1] = k[i] + 2.0 * (NN_MIN_BIN + (1.0 - ORC_NN_BINS * NN_MIN_BIN) * p[i] / sum);
+    k[ORC_NN_BINS] = 1.0;
+}
+
+static double softplus(double t) { return t > 30.0 ? t : log1p(exp(t)); }
+
+void orc_spline_from_raw(const double raw[ORC_NN_OUT], double x[17], double y[17], double d[17])
+{
+    knots_from_logits(raw, x);
+    knots_from_logits(raw + ORC_NN_BINS, y);
+    d[0] = d[ORC_NN_BINS] = 1.0;
+    for (int k = 1; k < ORC_NN_BINS; ++k) d[k] = NN_MIN_DERIV + softplus(raw[2 * ORC_NN_BINS + k - 1]);
+}
+
+static int find_bin(const double *knots, double v)
+{
+    int k = 0;
+    for (int i = 1; i < ORC_NN_BINS; ++i)
+        if (v >= knots[i]) k = i;
+    return k;
+}
+
+/* In bin k, with xi = (x - x_k)/W, s = H/W:
+ *   g  = y_k + H [s xi^2 + d_k xi (1-xi)] / [s + (d_{k+1} + d_k - 2s) xi (1-xi)]
+ *   g' = s^2 [d_{k+1} xi^2 + 2 s xi (1-xi) + d_k (1-xi)^2] / [ ... ]^2        */
+static double rq_eval(const double x[17], const double y[17], const double d[17], int k,
+                      double xi, double *logderiv)
+{
+    const double W = x[k + 1] - x[k], H = y[k + 1] - y[k], s = H / W;
+    const double om = xi * (1.0 - xi);
+    const double den = s + (d[k + 1] + d[k] - 2.0 * s) * om;
+    const double g = y[k] + H * (s * xi * xi + d[k] * om) / den;
+    const double num = d[k + 1] * xi * xi + 2.0 * s * om + d[k] * (1.0 - xi) * (1.0 - xi);
+    if (logderiv) *logderiv = 2.0 * log(s) + log(num) - 2.0 * log(den);
+    return g;
+}
+
+double orc_spline_fwd(const double x[17], const double y[17], const double d[17], double xv,
+                      double *logderiv)
+{
+    const int k = find_bin(x, xv);
+    const double xi = (xv - x[k]) / (x[k + 1] - x[k]);
+    return rq_eval(x, y, d, k, xi, logderiv);
+}
+
+/* Inverse in bin k: xi is the root in [0, 1] of a xi^2 + b xi + c = 0 with
+ *   a = H (s - d_k) + (u - y_k)(d_{k+1} + d_k - 2s)
+ *   b = H d_k - (u - y_k)(d_{k+1} + d_k - 2s)
+ *   c = -s (u - y_k)
+ * taken in the cancellation-free form xi = 2c / (-b - sqrt(b^2 - 4ac)).     */
+double orc_spline_inv(const double x[17], const double y[17], const double d[17], double u,
+                      double *logderiv)
+{
+    const int k = find_bin(y, u);
+    const double W = x[k + 1] - x[k], H = y[k + 1] - y[k], s = H / W;
+    const double dy = u - y[k], t = d[k + 1] + d[k] - 2.0 * s;
+    const double a = H * (s - d[k]) + dy * t;
+    const double b = H * d[k] - dy * t;
+    const double c = -s * dy;
+    double disc = b * b - 4.0 * a * c;
+    if (disc < 0.0) disc = 0.0;
+    const double xi = 2.0 * c / (-b - sqrt(disc));
+    rq_eval(x, y, d, k, xi, logderiv);
+    return x[k] + xi * W;
+}
+
+void orc_nn_table(const float *params, double *table)
+{
+    for (int j = 0; j < ORC_NN_TABLE_ROWS; ++j) {
+        const double f = -1.0 + 2.0 * j / (ORC_NN_TABLE_ROWS - 1);
+        double raw[ORC_NN_OUT], x[17], y[17], d[17];
+        orc_nn_forward(params, f, raw);
+        orc_spline_from_raw(raw, x, y, d);
+        double *row = table + (size_t)j * ORC_NN_ROW;
+        for (int k = 1; k <= ORC_NN_BINS; ++k) {
+            row[k - 1] = x[k];
+            row[16 + k - 1] = y[k];
+            row[32 + k - 1] = d[k];
+        }
+    }
+}
+
+int orc_table_row(double alpha, double *margin)
+{
+    const double p = (orc_nn_feature(alpha) + 1.0) * 0.5 * (ORC_NN_TABLE_ROWS - 1);
+    int j = (int)floor(p + 0.5);
+    if (j < 0) j = 0;
+    if (j > ORC_NN_TABLE_ROWS - 1) j = ORC_NN_TABLE_ROWS - 1;
+    if (margin) *margin = fabs((p - floor(p)) - 0.5) * 2.0 / (ORC_NN_TABLE_ROWS - 1);
+    return j;
+}
+
+void orc_table_knots(const double *table, int row, double x[17], double y[17], double d[17])
+{
+    const double *r = table + (size_t)row * ORC_NN_ROW;
+    x[0] = y[0] = -1.0;
+    d[0] = 1.0;
+    for (int k = 1; k <= ORC_NN_BINS; ++k) {
+        x[k] = r[k - 1];
+        y[k] = r[16 + k - 1];
+        d[k] = r[32 + k - 1];
+    }
+}
+
+/* log w(x) = alpha x + (1/2) ln(1 - x^2) - ln g'(x)  (the constant ln 1/2 of
+ * q cancels in the Metropolis ratio). */
+static double log_weight(double alpha, double xv, double logderiv)
+{
+    const double one_m_x2 = (1.0 - xv) * (1.0 + xv);
+    if (!(one_m_x2 > 0.0)) return -INFINITY;
+    return alpha * xv + 0.5 * log(one_m_x2) - logderiv;
+}
+
+void orc_learned_link(const double V[4], const double Uold[4], const double *table, double beta,
+                      uint64_t seed, uint32_t site, uint32_t sweep, uint32_t mu, uint32_t replica,
+                      double out[4], double *margin, int *accepted)
+{
+    const double k = qnorm(V);
+    const double alpha = beta * k;
+    double m = fmin(fabs(alpha - ORC_NN_ALPHA_LO), fabs(alpha - ORC_NN_ALPHA_HI));
+    if (!(alpha >= ORC_NN_ALPHA_LO && alpha <= ORC_NN_ALPHA_HI)) {
+        double mh;
+        orc_heatbath_link(V, beta, seed, site, sweep, mu, replica, out, &mh);
+        if (margin) *margin = fmin(m, mh);
+        if (accepted) *accepted = -1;
+        return;
+    }
+    double Ut[4], Utd[4];
+    for (int c = 0; c < 4; ++c) Ut[c] = V[c] / k;
+    double mrow;
+    const int row = orc_table_row(alpha, &mrow);
+    m = fmin(m, mrow);
+    double x[17], y[17], d[17];
+    orc_table_knots(table, row, x, y, d);
+    double r[4];
+    block(seed, site, sweep, word2_of(mu, ORC_TAG_LEARN, replica), 0u, r, NULL);
+    double ld_new, ld_old, t[4];
+    const double a0n = orc_spline_inv(x, y, d, 2.0 * r[0] - 1.0, &ld_new);
+    orc_qmul(Uold, Ut, t);
+    double xo = t[0];
+    if (xo > 1.0) xo = 1.0;
+    if (xo < -1.0) xo = -1.0;
+    orc_spline_fwd(x, y, d, xo, &ld_old);
+    const double lw = log_weight(alpha, a0n, ld_new) - log_weight(alpha, xo, ld_old);
+    const double dm = lw - log(r[1]);
+    m = fmin(m, fabs(dm));
+    if (dm > 0.0) {
+        const double amag = sqrt((1.0 - a0n) * (1.0 + a0n));
+        const double cth = 1.0 - 2.0 * r[2], sth = 2.0 * sqrt(r[2] * (1.0 - r[2]));
+        const double phi = 2.0 * M_PI * r[3];
+        const double X[4] = {a0n, amag * sth * cos(phi), amag * sth * sin(phi), amag * cth};
+        orc_qdag(Ut, Utd);
+        orc_qmul(X, Utd, out);
+        if (accepted) *accepted = 1;
+    } else {
+        memcpy(out, Uold, 4 * sizeof(double));
+        if (accepted) *accepted = 0;
+    }
+    if (margin) *margin = m;
+}
+
+void orc_learned_pass(const int32_t dims[4], double *U, const double *table, int mu, int parity,
+                      uint32_t sweep, double beta, uint64_t seed, uint32_t replica,
+                      double *margin, int32_t *accepted)
+{
+    const int64_t Vol = orc_volume(dims);
+    for (int64_t s = 0; s < Vol; ++s) {
+        if (orc_parity(dims, s) != parity) continue;
+        double St[4], out[4], m;
+        int acc;
+        orc_staple(dims, U, s, mu, St);
+        orc_learned_link(St, U + (s * 4 + mu) * 4, table, beta, seed, (uint32_t)s, sweep,
+                         (uint32_t)mu, replica, out, &m, &acc);
+        memcpy(U + (s * 4 + mu) * 4, out, sizeof(out));
+        if (margin) margin[s] = m;
+        if (accepted) accepted[s] = acc;
+    }
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP

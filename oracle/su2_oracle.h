@@ -102,6 +102,49 @@ void orc_gauge_transform(const int32_t dims[4], double *U, uint64_t seed, uint32
 /* Haar-random SU(2) element from one Philox block (Box-Muller + normalise). */
 void orc_haar_from_block(const uint32_t w[4], double out[4]);
 
+/* ===================================================== learned proposal ===
+ * Conditioner: MLP 1 -> 32 -> 32 -> 47 (tanh, tanh, linear) on the feature
+ * f(alpha) = 2 (ln alpha - ln 0.5) / (ln 30 - ln 0.5) - 1.  Parameters (FP32,
+ * 2671): W1[32], b1[32], W2[32][32] (row = output unit), b2[32], W3[47][32],
+ * b3[47].  Outputs: 16 width logits, 16 height logits, 15 derivative logits.
+ * Spline: monotone rational-quadratic on [-1, 1] (Durkan et al. 2019), 16
+ * bins, widths/heights 2 (m + (1 - 16 m) softmax), m = 1e-3, interior
+ * derivatives 1e-3 + softplus, boundary derivatives 1.  The flow maps a0 to
+ * u = g(a0), uniform on [-1, 1]; the proposal density is q(a0) = g'(a0) / 2.
+ * Table: rows j = 0..255 at f_j = -1 + 2 j / 255 holding 48 floats
+ * [x1..x15, 1, y1..y15, 1, d1..d15, 1]; an update uses the nearest row. */
+#define ORC_NN_H 32
+#define ORC_NN_OUT 47
+#define ORC_NN_BINS 16
+#define ORC_NN_NPARAM 2671
+#define ORC_NN_TABLE_ROWS 256
+#define ORC_NN_ROW 48
+#define ORC_NN_ALPHA_LO 0.5
+#define ORC_NN_ALPHA_HI 30.0
+
+double orc_nn_feature(double alpha);
+void orc_nn_forward(const float *params, double f, double out[ORC_NN_OUT]);
+/* knots x[0..16], y[0..16], derivatives d[0..16] from the 47 raw outputs */
+void orc_spline_from_raw(const double raw[ORC_NN_OUT], double x[17], double y[17], double d[17]);
+/* g(x) and ln g'(x) */
+double orc_spline_fwd(const double x[17], const double y[17], const double d[17], double xv,
+                      double *logderiv);
+/* g^{-1}(u) and ln g'(x) at that point */
+double orc_spline_inv(const double x[17], const double y[17], const double d[17], double u,
+                      double *logderiv);
+void orc_nn_table(const float *params, double *table /* 256 x 48 */);
+/* Row index used for alpha (nearest), with the margin of that choice. */
+int orc_table_row(double alpha, double *margin);
+void orc_table_knots(const double *table, int row, double x[17], double y[17], double d[17]);
+/* Learned-proposal Metropolis update of one link (fallback: exact heat bath).
+ * accepted: 1 accepted, 0 rejected, -1 exact fallback. */
+void orc_learned_link(const double V[4], const double Uold[4], const double *table, double beta,
+                      uint64_t seed, uint32_t site, uint32_t sweep, uint32_t mu, uint32_t replica,
+                      double out[4], double *margin, int *accepted);
+void orc_learned_pass(const int32_t dims[4], double *U, const double *table, int mu, int parity,
+                      uint32_t sweep, double beta, uint64_t seed, uint32_t replica,
+                      double *margin, int32_t *accepted);
+
 int orc_max_threads(void);
 
 #ifdef __cplusplus
@@ -109,3 +152,4 @@ int orc_max_threads(void);
 #endif
 
 #endif
+

@@ -20,6 +20,7 @@ _lib = None
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 
 
 def _load():
@@ -59,6 +60,18 @@ def _load():
         "orc_gauge_transform": (None, [_i32p, _f64p, c_u64, c_u32]),
         "orc_haar_from_block": (None, [_u32p, _f64p]),
         "orc_max_threads": (c_int, []),
+        "orc_nn_feature": (c_d, [c_d]),
+        "orc_nn_forward": (None, [_f32p, c_d, _f64p]),
+        "orc_spline_from_raw": (None, [_f64p, _f64p, _f64p, _f64p]),
+        "orc_spline_fwd": (c_d, [_f64p, _f64p, _f64p, c_d, ctypes.POINTER(c_d)]),
+        "orc_spline_inv": (c_d, [_f64p, _f64p, _f64p, c_d, ctypes.POINTER(c_d)]),
+        "orc_nn_table": (None, [_f32p, _f64p]),
+        "orc_table_row": (c_int, [c_d, ctypes.POINTER(c_d)]),
+        "orc_table_knots": (None, [_f64p, c_int, _f64p, _f64p, _f64p]),
+        "orc_learned_link": (None, [_f64p, _f64p, _f64p, c_d, c_u64, c_u32, c_u32, c_u32, c_u32,
+                                    _f64p, ctypes.POINTER(c_d), ctypes.POINTER(c_int)]),
+        "orc_learned_pass": (None, [_i32p, _f64p, _f64p, c_int, c_int, c_u32, c_d, c_u64, c_u32,
+                                    vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -213,3 +226,74 @@ def haar_from_words(w):
 
 def max_threads():
     return _load().orc_max_threads()
+
+
+# ------------------------------------------------------- learned proposal
+NN_NPARAM, NN_OUT, NN_BINS, NN_ROWS, NN_ROW = 2671, 47, 16, 256, 48
+ALPHA_LO, ALPHA_HI = 0.5, 30.0
+
+
+def nn_feature(alpha):
+    return _load().orc_nn_feature(float(alpha))
+
+
+def nn_forward(params, f):
+    out = np.zeros(NN_OUT)
+    _load().orc_nn_forward(np.ascontiguousarray(params, np.float32), float(f), out)
+    return out
+
+
+def spline_from_raw(raw):
+    x, y, d = np.zeros(17), np.zeros(17), np.zeros(17)
+    _load().orc_spline_from_raw(np.ascontiguousarray(raw, np.float64), x, y, d)
+    return x, y, d
+
+
+def spline_fwd(knots, xv):
+    ld = ctypes.c_double()
+    g = _load().orc_spline_fwd(*knots, float(xv), ctypes.byref(ld))
+    return g, ld.value
+
+
+def spline_inv(knots, u):
+    ld = ctypes.c_double()
+    x = _load().orc_spline_inv(*knots, float(u), ctypes.byref(ld))
+    return x, ld.value
+
+
+def nn_table(params):
+    t = np.zeros((NN_ROWS, NN_ROW))
+    _load().orc_nn_table(np.ascontiguousarray(params, np.float32), t)
+    return t
+
+
+def table_row(alpha):
+    m = ctypes.c_double()
+    j = _load().orc_table_row(float(alpha), ctypes.byref(m))
+    return j, m.value
+
+
+def table_knots(table, row):
+    x, y, d = np.zeros(17), np.zeros(17), np.zeros(17)
+    _load().orc_table_knots(np.ascontiguousarray(table, np.float64), int(row), x, y, d)
+    return x, y, d
+
+
+def learned_link(V, Uold, table, beta, seed, site, sweep, mu, replica=0):
+    out = np.zeros(4)
+    m, acc = ctypes.c_double(), ctypes.c_int()
+    _load().orc_learned_link(np.ascontiguousarray(V, np.float64),
+                             np.ascontiguousarray(Uold, np.float64),
+                             np.ascontiguousarray(table, np.float64), float(beta),
+                             np.uint64(seed), int(site), int(sweep), int(mu), int(replica), out,
+                             ctypes.byref(m), ctypes.byref(acc))
+    return out, m.value, acc.value
+
+
+def learned_pass(dims, U, table, mu, par, sweep, beta, seed, replica=0):
+    margin = np.full(volume(dims), np.inf)
+    acc = np.full(volume(dims), -2, dtype=np.int32)
+    _load().orc_learned_pass(_dims(dims), _c(U), np.ascontiguousarray(table, np.float64),
+                             int(mu), int(par), int(sweep), float(beta), np.uint64(seed),
+                             int(replica), _ptr(margin), _ptr(acc))
+    return margin, acc

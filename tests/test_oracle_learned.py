@@ -1,0 +1,162 @@
+"""Pins of the oracle's learned proposal: the rational-quadratic spline
+(Durkan et al. 2019) against its defining properties, the FP64 NLL gradient
+against central finite differences, the table against direct evaluation, and
+the independence-Metropolis step against the heat-bath distribution of Sec. 2
+(chi-square) and against its acceptance rate computed by quadrature."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import nn_oracle as nn
+from tests import inputs, stats
+
+
+def random_params(seed, scale=0.4):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(nn.NPARAM) * scale).astype(np.float32)
+
+
+def identity_params(seed=0):
+    p = random_params(seed)
+    p[1120:1120 + 1504] = 0.0
+    p[2624:] = nn.identity_raw_bias()
+    return p
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_spline_properties(orc, seed):
+    rng = np.random.default_rng(seed)
+    raw = rng.standard_normal(47) * 2.0
+    kn = orc.spline_from_raw(raw)
+    x, y, d = kn
+    assert x[0] == -1 and x[16] == 1 and y[0] == -1 and y[16] == 1
+    assert np.all(np.diff(x) >= 2e-3 - 1e-15) and np.all(np.diff(y) >= 2e-3 - 1e-15)
+    assert d[0] == 1 and d[16] == 1 and np.all(d[1:16] > 1e-3)
+    assert orc.spline_fwd(kn, -1.0)[0] == pytest.approx(-1, abs=1e-15)
+    assert orc.spline_fwd(kn, 1.0)[0] == pytest.approx(1, abs=1e-15)
+    xs = np.linspace(-1, 1, 2001)
+    g = np.array([orc.spline_fwd(kn, v)[0] for v in xs])
+    assert np.all(np.diff(g) > 0)
+    # knots are interpolated: g(x_k) = y_k
+    for k in range(17):
+        assert orc.spline_fwd(kn, x[k])[0] == pytest.approx(y[k], abs=1e-13)
+    # inverse, derivative vs finite differences, normalisation of q = g'/2
+    for v in rng.uniform(-0.999, 0.999, 200):
+        gv, ld = orc.spline_fwd(kn, v)
+        xi, ld2 = orc.spline_inv(kn, gv)
+        assert xi == pytest.approx(v, abs=1e-12) and ld2 == pytest.approx(ld, abs=1e-9)
+        h = 1e-6
+        if np.min(np.abs(x - v)) < 10 * h:
+            continue  # g'' jumps at a knot; the stencil needs a smooth interval
+        G = lambda t: orc.spline_fwd(kn, v + t * h)[0]
+        fd = (-G(2) + 8 * G(1) - 8 * G(-1) + G(-2)) / (12 * h)  # fourth-order stencil
+        assert math.log(fd) == pytest.approx(ld, abs=1e-6)
+    q = lambda v: 0.5 * math.exp(orc.spline_fwd(kn, v)[1])
+    tot = sum(integrate.quad(q, x[k], x[k + 1], epsabs=1e-13)[0] for k in range(16))
+    assert tot == pytest.approx(1.0, abs=1e-10)
+
+
+def test_identity_spline(orc):
+    p = identity_params()
+    for a in (0.5, 3.0, 30.0):
+        kn = orc.spline_from_raw(orc.nn_forward(p, orc.nn_feature(a)))
+        for v in np.linspace(-1, 1, 17):
+            g, ld = orc.spline_fwd(kn, v)
+            # FP32 parameters: the boundary-derivative bias is exact to ~1e-8
+            assert g == pytest.approx(v, abs=1e-7) and ld == pytest.approx(0, abs=1e-7)
+
+
+def test_torch_nll_matches_c_forward(orc):
+    p = random_params(4)
+    al = inputs.log_uniform(300, 0.5, 30, 5)
+    a0 = np.random.default_rng(6).uniform(-0.999, 0.999, 300)
+    loss, _ = nn.loss_and_grad(p, al, a0)
+    ld = [orc.spline_fwd(orc.spline_from_raw(orc.nn_forward(p, orc.nn_feature(a))), x)[1]
+          for a, x in zip(al, a0)]
+    assert loss == pytest.approx(-(math.log(0.5) + np.mean(ld)), abs=1e-12)
+    assert nn.feature(np.array([0.5, 30.0])).numpy() == pytest.approx([-1, 1], abs=1e-15)
+
+
+def test_gradient_matches_finite_differences():
+    p = random_params(7).astype(np.float64)
+    al = inputs.log_uniform(64, 0.5, 30, 8)
+    a0 = np.random.default_rng(9).uniform(-0.995, 0.995, 64)
+    _, g = nn.loss_and_grad(p, al, a0)
+    idx = [0, 5, 31, 32, 40, 64, 500, 1087, 1088, 1119, 1120, 1200, 1700, 2600, 2623, 2624,
+           2640, 2656, 2670]
+    import torch
+    def L(i, t):
+        q = p.copy()
+        q[i] += t
+        return float(nn.nll(torch.tensor(q), al, a0))
+
+    for i in idx:
+        h = 1e-4  # fourth-order stencil: truncation ~h^4, rounding ~1e-16/h
+        fd = (-L(i, 2 * h) + 8 * L(i, h) - 8 * L(i, -h) + L(i, -2 * h)) / (12 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-9), i
+
+
+def test_table_rows(orc):
+    p = random_params(10)
+    t = orc.nn_table(p)
+    for j in (0, 17, 128, 255):
+        f = -1 + 2 * j / 255
+        x, y, d = orc.spline_from_raw(orc.nn_forward(p, f))
+        np.testing.assert_allclose(t[j, :16], x[1:], atol=0)
+        np.testing.assert_allclose(t[j, 16:32], y[1:], atol=0)
+        np.testing.assert_allclose(t[j, 32:48], d[1:], atol=0)
+    assert orc.table_row(0.5)[0] == 0 and orc.table_row(30.0)[0] == 255
+    a_mid = 0.5 * 60 ** (0.5 / 255)  # halfway between rows 0 and 1
+    assert orc.table_row(a_mid * 1.001)[0] == 1 and orc.table_row(a_mid / 1.001)[0] == 0
+
+
+def _chain(orc, table, V, beta, n, seed):
+    k = np.linalg.norm(V)
+    Ut = V / k
+    U = np.array([1.0, 0, 0, 0])
+    xs, acc = np.empty(n), 0
+    for t in range(n):
+        U, _, a = orc.learned_link(V, U, table, beta, seed, 0, t, 0)
+        acc += a == 1
+        xs[t] = orc.qmul(U, Ut)[0][0]
+    return xs, acc / n
+
+
+def test_mh_chain_is_stationary_and_acceptance_matches_quadrature(orc):
+    """Identity spline = uniform proposal q = 1/2: the independence sampler's
+    acceptance is (1/2) int int min(p(x), p(y)) dx dy by quadrature."""
+    table = orc.nn_table(identity_params())
+    V = np.array([0.9, 0.3, -0.2, 0.1])
+    beta = 1.0
+    alpha = beta * np.linalg.norm(V)
+    xs, acc = _chain(orc, table, V, beta, 60_000, 3)
+    chi2, dof, p = stats.chi2_equiprobable(xs[1000:][::3], alpha, nbins=40)
+    assert p > 1e-4, (chi2, dof)
+    grid = np.linspace(-1, 1, 4001)
+    pd = stats.a0_pdf(grid, alpha)
+    A = 0.5 * np.trapezoid([np.trapezoid(np.minimum(pi, pd), grid) for pi in pd], grid)
+    assert acc == pytest.approx(A, abs=0.01)
+
+
+def test_mh_chain_random_net_stationary(orc):
+    """An arbitrary (untrained, non-uniform) proposal still leaves the exact
+    distribution stationary; only the acceptance rate depends on the net."""
+    table = orc.nn_table(random_params(11, scale=0.15))
+    V = np.array([2.5, -1.0, 0.4, 0.8])
+    beta = 2.0
+    xs, acc = _chain(orc, table, V, beta, 80_000, 4)
+    assert 0.1 < acc < 1.0
+    chi2, dof, p = stats.chi2_equiprobable(xs[2000:][::8], beta * np.linalg.norm(V), nbins=30)
+    assert p > 1e-4, (chi2, dof)
+
+
+def test_mh_fallback_outside_range_is_heat_bath(orc):
+    table = orc.nn_table(random_params(12))
+    V = np.array([20.0, 3.0, 0.0, 0.0])  # alpha = 2 * |V| > 30
+    Uold = np.array([1.0, 0, 0, 0])
+    out, m, a = orc.learned_link(V, Uold, table, 2.0, 5, 7, 3, 1)
+    want, _ = orc.heatbath_link(V, 2.0, 5, 7, 3, 1)
+    assert a == -1
+    np.testing.assert_array_equal(out, want)
