@@ -142,6 +142,53 @@ int su2_synchronize(su2_ctx *ctx);
  * 0 keeps the current value).  Results do not depend on it. */
 int su2_set_launch(su2_ctx *ctx, int block, int flags, int tile_z, int tile_t);
 
+/* ======================================================= learned proposal
+ * An independence-Metropolis update of a0 with a learned proposal replaces the
+ * exact sampler inside the pass (SU2_LEARNED); the heat-bath distribution of
+ * Sec. 2 stays exact because the Metropolis ratio uses the proposal density.
+ * Proposal: a 16-bin monotone rational-quadratic spline flow g on [-1, 1]
+ * (Durkan et al. 2019) with q(a0) = g'(a0)/2, its 47 parameters given by an
+ * MLP 1 -> 32 -> 32 -> 47 (tanh) of f(alpha) = 2 ln(alpha/0.5)/ln 60 - 1,
+ * alpha = beta k.  For alpha outside [0.5, 30] the exact sampler is used.
+ * Parameters: 2671 FP32, order W1[32] b1[32] W2[32][32] b2[32] W3[47][32]
+ * b3[47] (rows = output units).  Training minimises the NLL of exact-sampler
+ * draws with Adam (b1 0.9, b2 0.999, eps 1e-8), all on the GPU.  The pass
+ * uses a 256-row table of the spline at f = -1 + 2j/255 (nearest row), rows
+ * of 48 floats [x1..x15, 1, y1..y15, 1, d1..d15, 1]. */
+typedef struct su2_nn su2_nn;
+
+int su2_nn_num_params(void);
+/* params_host: 2671 floats, or NULL for the default initialisation from
+ * `seed` (hidden layers uniform in +-1/sqrt(fan_in), output weights 0, output
+ * biases giving the identity spline, i.e. a uniform proposal).  hip_stream:
+ * stream for the object's work (NULL = null stream).  Library-owned memory. */
+int su2_nn_create(su2_nn **out, const float *params_host, uint64_t seed, void *hip_stream);
+int su2_nn_destroy(su2_nn *nn);
+int su2_nn_get_params(su2_nn *nn, float *params_host);
+int su2_nn_set_params(su2_nn *nn, const float *params_host);
+/* Generate n training pairs on the GPU: alpha log-uniform in [alpha_lo,
+ * alpha_hi] (Philox tag 5, draw (i, 0, 0|5<<2, 0)), a0 from the exact sampler
+ * (trial blocks (i, 0, 1|5<<2, t)).  Replaces any data held. */
+int su2_nn_sample_data(su2_nn *nn, int64_t n, double alpha_lo, double alpha_hi, uint64_t seed);
+/* Caller-provided training data (host arrays of n floats). */
+int su2_nn_set_data(su2_nn *nn, int64_t n, const float *alpha_host, const float *a0_host);
+/* Data held: *n, and (if non-NULL) copies into host arrays of *n floats. */
+int su2_nn_get_data(su2_nn *nn, int64_t *n, float *alpha_host, float *a0_host);
+/* Mean NLL and its gradient (host float[2671]) over samples [offset,
+ * offset + batch) (indices mod n).  Synchronous. */
+int su2_nn_loss_grad(su2_nn *nn, int64_t offset, int32_t batch, double *loss, float *grad_host);
+/* `steps` Adam steps on consecutive minibatches of the data (wrapping);
+ * loss_history_host (may be NULL) receives each step's mean NLL.  Synchronous. */
+int su2_nn_train(su2_nn *nn, int32_t steps, int32_t batch, double lr, double *loss_history_host);
+/* Evaluate the 256-row spline table from the current parameters / copy it. */
+int su2_nn_build_table(su2_nn *nn);
+int su2_nn_get_table(su2_nn *nn, float *table_host);
+/* Use nn's table for SU2_LEARNED sweeps of ctx (NULL unsets).  The su2_nn must
+ * outlive every sweep enqueued with it and its table must be built. */
+int su2_set_proposal(su2_ctx *ctx, su2_nn *nn);
+/* Learned proposals made and accepted since the last reset (synchronous). */
+int su2_get_accept_stats(su2_ctx *ctx, uint64_t *proposed, uint64_t *accepted, int reset);
+
 /* ----------------------------------------------------------- test hooks */
 /* Philox4x32-10 on the GPU: n counters (host, 4 words each) -> host out. */
 int su2_test_philox(const uint32_t *ctr_host, int64_t n, uint64_t seed, uint32_t *out_host);
@@ -151,14 +198,21 @@ int su2_test_philox(const uint32_t *ctr_host, int64_t n, uint64_t seed, uint32_t
 int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_t seed,
                             uint32_t sweep, uint32_t mu, uint32_t replica, float *out_host,
                             int32_t *ntrials_host);
-/* Enqueue one (mu, parity) pass at the current sweep index (index unchanged). */
-int su2_test_pass(su2_ctx *ctx, int mu, int parity);
+/* Enqueue one (mu, parity) pass at the current sweep index (index unchanged);
+ * mode SU2_KP or SU2_LEARNED. */
+int su2_test_pass(su2_ctx *ctx, int mu, int parity, int mode);
 /* Host-side evaluation (no GPU needed) of the pass kernel's index map for
  * extents dims and traversal tile tile_z x tile_t (0 = default): for each of
  * the V/2 thread indices g of a pass over `parity`, out[9g] = canonical site of
  * the thread, out[9g + 1 + 2d] / out[9g + 2 + 2d] = half-site index (s >> 1)
  * of its +1 / -1 neighbour in direction d.  out: host uint32[9 * V/2]. */
 int su2_test_index_map(const int32_t dims[4], int tile_z, int tile_t, int parity, uint32_t *out);
+/* Learned-proposal update of n independent links (host float[n][4] staples V
+ * and old links Uold); link i uses site index i.  accepted_host (may be NULL):
+ * 1 accepted, 0 rejected, -1 exact fallback. */
+int su2_test_learned_links(su2_nn *nn, const float *V_host, const float *Uold_host, int64_t n,
+                           double beta, uint64_t seed, uint32_t sweep, uint32_t mu,
+                           uint32_t replica, float *out_host, int32_t *accepted_host);
 /* Enqueue U_mu(x) -> G(x) U_mu(x) G(x+mu)^+ with G Haar from Philox tag 3. */
 int su2_test_gauge_transform(su2_ctx *ctx, uint64_t seed);
 

@@ -212,7 +212,13 @@ void orc_staple(const int32_t dims[4], const double *U, int64_t s, int mu, doubl
 double orc_sample_delta(double alpha, uint64_t seed, uint32_t site, uint32_t sweep,
                         uint32_t mu, uint32_t replica, int32_t *ntrials, double *margin)
 {
-    const uint32_t w2 = word2_of(mu, ORC_TAG_TRIAL, replica);
+    return orc_sample_delta_w2(alpha, seed, site, sweep, word2_of(mu, ORC_TAG_TRIAL, replica),
+                               ntrials, margin);
+}
+
+double orc_sample_delta_w2(double alpha, uint64_t seed, uint32_t site, uint32_t sweep,
+                           uint32_t w2, int32_t *ntrials, double *margin)
+{
     double min_margin = fabs(alpha - KP_MIN_ALPHA);
     double delta = 0.0;
     int accepted = 0;
@@ -639,15 +645,18 @@ static double log_weight(double alpha, double xv, double logderiv)
 
 void orc_learned_link(const double V[4], const double Uold[4], const double *table, double beta,
                       uint64_t seed, uint32_t site, uint32_t sweep, uint32_t mu, uint32_t replica,
-                      double out[4], double *margin, int *accepted)
+                      double out[4], double margin[3], int *accepted)
 {
     const double k = qnorm(V);
     const double alpha = beta * k;
-    double m = fmin(fabs(alpha - ORC_NN_ALPHA_LO), fabs(alpha - ORC_NN_ALPHA_HI));
+    /* margins: [0] Metropolis log-ratio (or the exact sampler's decisions),
+     * [1] distance of the table position to the nearest rounding boundary in
+     * rows, [2] distance of alpha to the ends of the table range */
+    double m3[3] = {INFINITY, INFINITY,
+                    fmin(fabs(alpha - ORC_NN_ALPHA_LO), fabs(alpha - ORC_NN_ALPHA_HI))};
     if (!(alpha >= ORC_NN_ALPHA_LO && alpha <= ORC_NN_ALPHA_HI)) {
-        double mh;
-        orc_heatbath_link(V, beta, seed, site, sweep, mu, replica, out, &mh);
-        if (margin) *margin = fmin(m, mh);
+        orc_heatbath_link(V, beta, seed, site, sweep, mu, replica, out, &m3[0]);
+        if (margin) memcpy(margin, m3, sizeof(m3));
         if (accepted) *accepted = -1;
         return;
     }
@@ -655,7 +664,7 @@ void orc_learned_link(const double V[4], const double Uold[4], const double *tab
     for (int c = 0; c < 4; ++c) Ut[c] = V[c] / k;
     double mrow;
     const int row = orc_table_row(alpha, &mrow);
-    m = fmin(m, mrow);
+    m3[1] = mrow * 0.5 * (ORC_NN_TABLE_ROWS - 1);
     double x[17], y[17], d[17];
     orc_table_knots(table, row, x, y, d);
     double r[4];
@@ -669,7 +678,7 @@ void orc_learned_link(const double V[4], const double Uold[4], const double *tab
     orc_spline_fwd(x, y, d, xo, &ld_old);
     const double lw = log_weight(alpha, a0n, ld_new) - log_weight(alpha, xo, ld_old);
     const double dm = lw - log(r[1]);
-    m = fmin(m, fabs(dm));
+    m3[0] = fabs(dm);
     if (dm > 0.0) {
         const double amag = sqrt((1.0 - a0n) * (1.0 + a0n));
         const double cth = 1.0 - 2.0 * r[2], sth = 2.0 * sqrt(r[2] * (1.0 - r[2]));
@@ -682,7 +691,7 @@ void orc_learned_link(const double V[4], const double Uold[4], const double *tab
         memcpy(out, Uold, 4 * sizeof(double));
         if (accepted) *accepted = 0;
     }
-    if (margin) *margin = m;
+    if (margin) memcpy(margin, m3, sizeof(m3));
 }
 
 void orc_learned_pass(const int32_t dims[4], double *U, const double *table, int mu, int parity,
@@ -692,14 +701,28 @@ void orc_learned_pass(const int32_t dims[4], double *U, const double *table, int
     const int64_t Vol = orc_volume(dims);
     for (int64_t s = 0; s < Vol; ++s) {
         if (orc_parity(dims, s) != parity) continue;
-        double St[4], out[4], m;
+        double St[4], out[4], m[3];
         int acc;
         orc_staple(dims, U, s, mu, St);
         orc_learned_link(St, U + (s * 4 + mu) * 4, table, beta, seed, (uint32_t)s, sweep,
-                         (uint32_t)mu, replica, out, &m, &acc);
+                         (uint32_t)mu, replica, out, m, &acc);
         memcpy(U + (s * 4 + mu) * 4, out, sizeof(out));
-        if (margin) margin[s] = m;
+        if (margin) memcpy(margin + 3 * s, m, sizeof(m));
         if (accepted) accepted[s] = acc;
+    }
+}
+
+/* Training data: sample i has alpha = lo (hi/lo)^u with u the first uniform of
+ * block (i, 0, 0 | 5<<2, 0) (log-uniform on [lo, hi]), and a0 = 1 - delta from
+ * the exact sampler with trial blocks (i, 0, 1 | 5<<2, t). */
+void orc_nn_data(int64_t n, double lo, double hi, uint64_t seed, double *alpha, double *a0)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double u[4];
+        block(seed, (uint32_t)i, 0u, word2_of(0u, ORC_TAG_TRAIN, 0u), 0u, u, NULL);
+        alpha[i] = lo * pow(hi / lo, u[0]);
+        a0[i] = 1.0 - orc_sample_delta_w2(alpha[i], seed, (uint32_t)i, 0u,
+                                          word2_of(1u, ORC_TAG_TRAIN, 0u), NULL, NULL);
     }
 }
 

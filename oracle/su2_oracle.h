@@ -67,6 +67,8 @@ void orc_staple(const int32_t dims[4], const double *U, int64_t s, int mu, doubl
  * of every floating-point decision taken (branch choice and accept tests). */
 double orc_sample_delta(double alpha, uint64_t seed, uint32_t site, uint32_t sweep,
                         uint32_t mu, uint32_t replica, int32_t *ntrials, double *margin);
+double orc_sample_delta_w2(double alpha, uint64_t seed, uint32_t site, uint32_t sweep,
+                           uint32_t w2, int32_t *ntrials, double *margin);
 void orc_sample_delta_batch(int64_t n, const double *alpha, uint64_t seed,
                             const uint32_t *site, uint32_t sweep, uint32_t mu,
                             uint32_t replica, double *delta, int32_t *ntrials,
@@ -137,13 +139,18 @@ void orc_nn_table(const float *params, double *table /* 256 x 48 */);
 int orc_table_row(double alpha, double *margin);
 void orc_table_knots(const double *table, int row, double x[17], double y[17], double d[17]);
 /* Learned-proposal Metropolis update of one link (fallback: exact heat bath).
- * accepted: 1 accepted, 0 rejected, -1 exact fallback. */
+ * accepted: 1 accepted, 0 rejected, -1 exact fallback.  margin[3]: the
+ * Metropolis log-ratio margin (or the exact sampler's), the table-row
+ * rounding margin in rows, the distance of alpha to the table range ends. */
 void orc_learned_link(const double V[4], const double Uold[4], const double *table, double beta,
                       uint64_t seed, uint32_t site, uint32_t sweep, uint32_t mu, uint32_t replica,
-                      double out[4], double *margin, int *accepted);
+                      double out[4], double margin[3], int *accepted);
+/* margin: 3 per site (as above), may be NULL. */
 void orc_learned_pass(const int32_t dims[4], double *U, const double *table, int mu, int parity,
                       uint32_t sweep, double beta, uint64_t seed, uint32_t replica,
                       double *margin, int32_t *accepted);
+
+void orc_nn_data(int64_t n, double lo, double hi, uint64_t seed, double *alpha, double *a0);
 
 int orc_max_threads(void);
 

@@ -61,6 +61,7 @@ def _load():
         "orc_haar_from_block": (None, [_u32p, _f64p]),
         "orc_max_threads": (c_int, []),
         "orc_nn_feature": (c_d, [c_d]),
+        "orc_nn_data": (None, [c_i64, c_d, c_d, c_u64, _f64p, _f64p]),
         "orc_nn_forward": (None, [_f32p, c_d, _f64p]),
         "orc_spline_from_raw": (None, [_f64p, _f64p, _f64p, _f64p]),
         "orc_spline_fwd": (c_d, [_f64p, _f64p, _f64p, c_d, ctypes.POINTER(c_d)]),
@@ -69,7 +70,7 @@ def _load():
         "orc_table_row": (c_int, [c_d, ctypes.POINTER(c_d)]),
         "orc_table_knots": (None, [_f64p, c_int, _f64p, _f64p, _f64p]),
         "orc_learned_link": (None, [_f64p, _f64p, _f64p, c_d, c_u64, c_u32, c_u32, c_u32, c_u32,
-                                    _f64p, ctypes.POINTER(c_d), ctypes.POINTER(c_int)]),
+                                    _f64p, _f64p, ctypes.POINTER(c_int)]),
         "orc_learned_pass": (None, [_i32p, _f64p, _f64p, c_int, c_int, c_u32, c_d, c_u64, c_u32,
                                     vp, vp]),
     }
@@ -280,20 +281,29 @@ def table_knots(table, row):
 
 
 def learned_link(V, Uold, table, beta, seed, site, sweep, mu, replica=0):
+    """Returns (new link, margins (mh, row, range), accepted 1 / 0 / -1 fallback)."""
     out = np.zeros(4)
-    m, acc = ctypes.c_double(), ctypes.c_int()
+    m = np.zeros(3)
+    acc = ctypes.c_int()
     _load().orc_learned_link(np.ascontiguousarray(V, np.float64),
                              np.ascontiguousarray(Uold, np.float64),
                              np.ascontiguousarray(table, np.float64), float(beta),
                              np.uint64(seed), int(site), int(sweep), int(mu), int(replica), out,
-                             ctypes.byref(m), ctypes.byref(acc))
-    return out, m.value, acc.value
+                             m, ctypes.byref(acc))
+    return out, m, acc.value
 
 
 def learned_pass(dims, U, table, mu, par, sweep, beta, seed, replica=0):
-    margin = np.full(volume(dims), np.inf)
+    """Returns (margins (V, 3), accepted (V,)) for the updated sites."""
+    margin = np.full((volume(dims), 3), np.inf)
     acc = np.full(volume(dims), -2, dtype=np.int32)
     _load().orc_learned_pass(_dims(dims), _c(U), np.ascontiguousarray(table, np.float64),
                              int(mu), int(par), int(sweep), float(beta), np.uint64(seed),
                              int(replica), _ptr(margin), _ptr(acc))
     return margin, acc
+
+
+def nn_data(n, lo, hi, seed):
+    a, x = np.zeros(n), np.zeros(n)
+    _load().orc_nn_data(int(n), float(lo), float(hi), np.uint64(seed), a, x)
+    return a, x

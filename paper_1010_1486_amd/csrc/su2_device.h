@@ -298,6 +298,113 @@ __device__ __forceinline__ Q heatbath_link(const Q &V, float beta, uint32_t site
     return qmul(X, qdag(Ut));
 }
 
+
+// ---------------------------------------------------------- learned proposal
+// A monotone rational-quadratic spline flow g on [-1, 1] (Durkan et al. 2019)
+// maps a0 to u = g(a0), uniform on [-1, 1]; its density q(a0) = g'(a0)/2 is
+// the proposal of an independence Metropolis step whose weight
+// w(x) = exp(alpha x) sqrt(1 - x^2) / q(x) keeps the heat-bath distribution of
+// Sec. 2 exact.  The spline of each alpha comes from the nearest row of a
+// 256-row table (rows at f = -1 + 2 j / 255, f = log-scaled alpha in
+// [0.5, 30]) holding [x1..x15, 1, y1..y15, 1, d1..d15, 1]; x0 = y0 = -1 and
+// d0 = 1 are implicit.  Outside [0.5, 30] the exact sampler is used.
+constexpr int kNNRows = 256;
+constexpr int kNNRow = 48;
+constexpr float kNNAlphaLo = 0.5f;
+constexpr float kNNAlphaHi = 30.0f;
+constexpr float kNNLog2Range = 5.9068905956085187f;  // log2(30 / 0.5)
+
+__device__ __forceinline__ int nn_table_row(float alpha)
+{
+    // p = (f + 1) (rows - 1) / 2 = log2(alpha / 0.5) (rows - 1) / log2(60)
+    const float p = hw_log2(alpha * 2.0f) * ((float)(kNNRows - 1) / kNNLog2Range);
+    const int j = (int)(p + 0.5f);
+    return j < 0 ? 0 : (j > kNNRows - 1 ? kNNRows - 1 : j);
+}
+
+struct RQBin {
+    float xl, W, yl, H, dl, dh;
+};
+
+// Bin of v among the knots starting at row[off] (off = 0: x, 16: y).
+__device__ __forceinline__ RQBin rq_bin(const float *__restrict__ row, int off, float v)
+{
+    const float4 *r4 = reinterpret_cast<const float4 *>(row + off);
+    int k = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 t = r4[q];
+        k += (v >= t.x) + (v >= t.y) + (v >= t.z) + (q < 3 ? (v >= t.w) : 0);
+    }
+    RQBin b;
+    b.xl = k ? row[k - 1] : -1.0f;
+    b.W = row[k] - b.xl;
+    b.yl = k ? row[16 + k - 1] : -1.0f;
+    b.H = row[16 + k] - b.yl;
+    b.dl = k ? row[32 + k - 1] : 1.0f;
+    b.dh = row[32 + k];
+    return b;
+}
+
+// g'(x) at relative position xi in the bin, s = H / W.
+__device__ __forceinline__ float rq_deriv(const RQBin &b, float s, float xi)
+{
+    const float om = xi * (1.0f - xi);
+    const float den = s + (b.dh + b.dl - 2.0f * s) * om;
+    const float num = b.dh * xi * xi + 2.0f * s * om + b.dl * (1.0f - xi) * (1.0f - xi);
+    return s * s * num / (den * den);
+}
+
+// Learned-proposal Metropolis update of one link.  acc: 1 accepted, 0
+// rejected (U' = Uold), -1 exact fallback (alpha outside the table range).
+__device__ __forceinline__ Q learned_link(const Q &V, const Q &Uold, const float *__restrict__ table,
+                                          float beta, uint32_t site, uint32_t sweep, uint32_t mu,
+                                          uint32_t replica, uint32_t k0, uint32_t k1, int &acc)
+{
+    const float k2 = qdot(V, V);
+    const float inv_k = k2 > 0.0f ? hw_rsq(k2) : 0.0f;
+    const float alpha = beta * k2 * inv_k;
+    if (!(alpha >= kNNAlphaLo && alpha <= kNNAlphaHi)) {
+        acc = -1;
+        return heatbath_link(V, beta, site, sweep, word2(mu, TAG_TRIAL, replica), k0, k1);
+    }
+    const Q Ut{V.w * inv_k, V.x * inv_k, V.y * inv_k, V.z * inv_k};
+    const float *row = table + (size_t)nn_table_row(alpha) * kNNRow;
+    const U4 w = philox(site, sweep, word2(mu, TAG_LEARN, replica), 0u, k0, k1);
+    const float u = 2.0f * u01(w.a) - 1.0f;
+    // proposal a0' = g^{-1}(u): root xi of a xi^2 + b xi + c = 0 in the bin
+    const RQBin bn = rq_bin(row, 16, u);
+    const float sn = bn.H * hw_rcp(bn.W);
+    const float dy = u - bn.yl, tt = bn.dh + bn.dl - 2.0f * sn;
+    const float qa = bn.H * (sn - bn.dl) + dy * tt;
+    const float qb = bn.H * bn.dl - dy * tt;
+    const float qc = -sn * dy;
+    const float disc = fmaxf(qb * qb - 4.0f * qa * qc, 0.0f);
+    const float xin = 2.0f * qc / (-qb - hw_sqrt(disc));
+    const float a0n = bn.xl + xin * bn.W;
+    const float gn = rq_deriv(bn, sn, xin);
+    // current link in the frame of the staple: x_old = (U_old U~)_0
+    const float xo = fminf(fmaxf(retr(Uold, Ut), -1.0f), 1.0f);
+    const RQBin bo = rq_bin(row, 0, xo);
+    const float so = bo.H * hw_rcp(bo.W);
+    const float go = rq_deriv(bo, so, (xo - bo.xl) * hw_rcp(bo.W));
+    // ln w(a0') - ln w(x_old) = alpha (a0' - x_old)
+    //   + (1/2) ln[(1 - a0'^2) g'(x_old)^2 / ((1 - x_old^2) g'(a0')^2)]
+    const float ratio = ((1.0f - a0n) * (1.0f + a0n) * go * go) /
+                        ((1.0f - xo) * (1.0f + xo) * gn * gn);
+    const float dlog2 = alpha * (a0n - xo) * kLog2e + 0.5f * hw_log2(ratio);
+    if (hw_log2(u01(w.b)) < dlog2) {
+        acc = 1;
+        const float r5 = u01(w.c), r6 = u01(w.d);
+        const float amag = hw_sqrt((1.0f - a0n) * (1.0f + a0n));
+        const float as = amag * 2.0f * hw_sqrt(r5 * (1.0f - r5));
+        const Q X{a0n, as * hw_cos_rev(r6), as * hw_sin_rev(r6), amag * (1.0f - 2.0f * r5)};
+        return qmul(X, qdag(Ut));
+    }
+    acc = 0;
+    return Uold;
+}
+
 // Haar-random element from one Philox block: two Box-Muller pairs, normalised.
 __device__ __forceinline__ Q haar_from_block(const U4 &w)
 {

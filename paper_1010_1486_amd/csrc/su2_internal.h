@@ -29,7 +29,7 @@ constexpr size_t kAccOff = 256;
 constexpr int kFixedShift = 28;
 constexpr int kBuckets = 256;
 constexpr int kBucketStride = 16;  // 16 x 8 B = one 128-byte line per bucket
-constexpr int kNumAcc = 2;
+constexpr int kNumAcc = 4;  // plaquette, Polyakov (fixed point); proposals, accepts (counts)
 constexpr size_t kAccBytes = (size_t)kNumAcc * kBuckets * kBucketStride * 8;
 constexpr size_t kScratchBytes = kAccOff + kAccBytes;
 
@@ -39,7 +39,7 @@ struct Counters {
 };
 
 enum Result { R_PLAQ = 0, R_POLY_SIGNED = 1, R_POLY_ABS = 2 };
-enum Acc { ACC_PLAQ = 0, ACC_POLY = 1 };
+enum Acc { ACC_PLAQ = 0, ACC_POLY = 1, ACC_PROPOSED = 2, ACC_ACCEPTED = 3 };
 
 // Accumulator `which`, bucket b: acc + (which * kBuckets + b) * kBucketStride.
 struct Sums {
@@ -57,9 +57,37 @@ struct LaunchCfg {
 hipError_t launch_init(float *links, const su2dev::Geom &g, int start, uint64_t seed,
                        uint32_t replica, hipStream_t stream);
 // measure: accumulate (1/2)Tr(U' V_nu), nu < mu, into acc[ACC_PLAQ].
+// table != nullptr: learned-proposal Metropolis update (counts into
+// acc[ACC_PROPOSED] / acc[ACC_ACCEPTED]); else the exact heat bath.
 hipError_t launch_pass(float *links, const su2dev::Geom &g, int mu, int par, Sums c,
                        float beta, uint64_t seed, uint32_t replica, bool measure,
-                       const LaunchCfg &cfg, hipStream_t stream);
+                       const float *table, const LaunchCfg &cfg, hipStream_t stream);
+// out[0] = proposals, out[1] = accepts summed over the buckets; reset if asked.
+hipError_t launch_counts(Sums c, unsigned long long *out, int reset, hipStream_t stream);
+
+// ------------------------------------------------------- learned proposal
+constexpr int kNNParams = 2671;
+constexpr int kNNActRows = 176;  // per-sample record rows of the backward pass
+
+struct NNBuffers {
+    float *params, *grad, *m, *v;  // kNNParams each
+    float *alpha, *a0;             // training data
+    float *act, *loss;             // kNNActRows x batch, batch
+    float *table;                  // kNNRows x kNNRow
+};
+
+hipError_t launch_nn_data(float *alpha, float *a0, int64_t n, float lo, float hi, uint64_t seed,
+                          hipStream_t stream);
+// Forward/backward of samples [offset, offset + batch) (mod n) and the
+// gradient of the mean NLL into nb.grad; mean loss into *loss_out if given.
+hipError_t launch_nn_step(const NNBuffers &nb, int64_t offset, int batch, int64_t n,
+                          double *loss_out, hipStream_t stream);
+hipError_t launch_nn_adam(const NNBuffers &nb, float lr, int step, hipStream_t stream);
+hipError_t launch_nn_table(const float *params, float *table, hipStream_t stream);
+hipError_t launch_test_learned(const float *table, const float *V, const float *Uold, int64_t n,
+                               float beta, uint64_t seed, uint32_t sweep, uint32_t mu,
+                               uint32_t replica, float *out, int32_t *accepted,
+                               hipStream_t stream);
 int pass_grid(const su2dev::Geom &g, const LaunchCfg &cfg);
 // Sum of all plaquettes into acc[ACC_PLAQ]; sum of L(x) into acc[ACC_POLY].
 hipError_t launch_plaquette(const float *links, const su2dev::Geom &g, Sums c,

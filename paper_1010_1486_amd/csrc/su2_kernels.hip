@@ -49,6 +49,7 @@ __device__ __forceinline__ double block_sum(double v)
         const int nw = (blockDim.x + 63) >> 6;
         for (int i = 0; i < nw; ++i) r += wsum[i];
     }
+    __syncthreads();  // wsum may be reused by the next call
     return r;
 }
 
@@ -154,15 +155,16 @@ __global__ void init_kernel(float *__restrict__ links, Geom g, int start, uint32
 // MEASURE, (1/2)Tr(U'_mu(s) V_nu(s)) summed over nu < mu is accumulated: over
 // the odd passes of mu = 1, 2, 3 this is every plaquette of the end-of-sweep
 // configuration exactly once.
-template <int MU, bool MEASURE>
+template <int MU, bool MEASURE, bool LEARNED>
 __global__ __launch_bounds__(256) void pass_kernel(float *__restrict__ links, Geom g, int par,
                                                    Sums sums, float beta, uint32_t k0,
                                                    uint32_t k1, uint32_t replica, int remap,
-                                                   int reverse)
+                                                   int reverse, const float *__restrict__ table)
 {
     const uint32_t blk = logical_block(blockIdx.x, gridDim.x, remap, reverse);
     const uint32_t gid = blk * blockDim.x + threadIdx.x;
     float meas = 0.0f;
+    int acc = -1;
     if (gid < g.vh) {
         const uint32_t sweep = sums.cnt->sweep;
         const int opp = par ^ 1;
@@ -190,12 +192,27 @@ __global__ __launch_bounds__(256) void pass_kernel(float *__restrict__ links, Ge
             if (MEASURE && nu < MU) Vlow = qadd(Vlow, st);
         }
         const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
-        const Q Un = heatbath_link(V, beta, site, sweep, word2((uint32_t)MU, TAG_TRIAL, replica),
-                                   k0, k1);
+        Q Un;
+        if (LEARNED) {
+            const Q Uold = ld(arr(links, g.vh, MU, par), h);
+            Un = learned_link(V, Uold, table, beta, site, sweep, (uint32_t)MU, replica, k0, k1,
+                              acc);
+        } else {
+            Un = heatbath_link(V, beta, site, sweep, word2((uint32_t)MU, TAG_TRIAL, replica), k0,
+                               k1);
+        }
         store_q(links, g.vh, MU, par, h, Un);
         if (MEASURE) meas = retr(Un, Vlow);
     }
     if (MEASURE) block_accumulate((double)meas, sums.acc, ACC_PLAQ);
+    if (LEARNED) {
+        const double np = block_sum(acc >= 0 ? 1.0 : 0.0);
+        const double na = block_sum(acc == 1 ? 1.0 : 0.0);
+        if (threadIdx.x == 0) {
+            atomicAdd(bucket(sums.acc, ACC_PROPOSED, blockIdx.x), (unsigned long long)np);
+            atomicAdd(bucket(sums.acc, ACC_ACCEPTED, blockIdx.x), (unsigned long long)na);
+        }
+    }
 }
 
 // -------------------------------------------------------------- plaquette
@@ -306,12 +323,36 @@ __global__ __launch_bounds__(kBuckets) void sweep_end_kernel(Sums sums, int flag
     }
 }
 
+// Proposal / accept counts of learned passes (kBuckets threads).
+__global__ __launch_bounds__(kBuckets) void counts_kernel(Sums sums, unsigned long long *out,
+                                                          int reset)
+{
+    __shared__ unsigned long long part[2][kBuckets / 64];
+    for (int a = 0; a < 2; ++a) {
+        unsigned long long *p = bucket(sums.acc, ACC_PROPOSED + a, threadIdx.x);
+        unsigned long long v = *p;
+        if (reset) *p = 0ull;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if ((threadIdx.x & 63) == 0) part[a][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 2; ++a) {
+            unsigned long long t = 0ull;
+            for (int i = 0; i < kBuckets / 64; ++i) t += part[a][i];
+            out[a] = t;
+        }
+}
+
 // which: 1 set sweep, 2 set meas_idx, 4 zero the accumulators (kBuckets threads).
 __global__ __launch_bounds__(kBuckets) void set_counter_kernel(Sums sums, uint32_t sweep,
                                                                uint32_t meas, int which)
 {
     if (which & 4)
         for (int a = 0; a < kNumAcc; ++a) *bucket(sums.acc, a, threadIdx.x) = 0ull;
+    else if (which & 8)
+        for (int a = 0; a < 2; ++a) *bucket(sums.acc, a, threadIdx.x) = 0ull;
     if (threadIdx.x == 0) {
         if (which & 1) sums.cnt->sweep = sweep;
         if (which & 2) sums.cnt->meas_idx = meas;
@@ -395,20 +436,34 @@ inline uint32_t lo32(uint64_t v) { return (uint32_t)v; }
 inline uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
 inline unsigned nblk(uint64_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
-template <int MU>
+template <int MU, bool LEARNED>
 void launch_pass_mu(float *links, const Geom &g, int par, Sums c, float beta, uint64_t seed,
-                    uint32_t replica, bool measure, const LaunchCfg &cfg, hipStream_t stream)
+                    uint32_t replica, bool measure, const float *table, const LaunchCfg &cfg,
+                    hipStream_t stream)
 {
     const unsigned nb = nblk(g.vh, (unsigned)cfg.pass_block);
     const int rev = cfg.snake ? par : 0;
     if (measure)
-        hipLaunchKernelGGL((pass_kernel<MU, true>), dim3(nb), dim3(cfg.pass_block), 0, stream,
-                           links, g, par, c, beta, lo32(seed), hi32(seed), replica,
-                           (int)cfg.xcd_remap, rev);
+        hipLaunchKernelGGL((pass_kernel<MU, true, LEARNED>), dim3(nb), dim3(cfg.pass_block), 0,
+                           stream, links, g, par, c, beta, lo32(seed), hi32(seed), replica,
+                           (int)cfg.xcd_remap, rev, table);
     else
-        hipLaunchKernelGGL((pass_kernel<MU, false>), dim3(nb), dim3(cfg.pass_block), 0, stream,
-                           links, g, par, c, beta, lo32(seed), hi32(seed), replica,
-                           (int)cfg.xcd_remap, rev);
+        hipLaunchKernelGGL((pass_kernel<MU, false, LEARNED>), dim3(nb), dim3(cfg.pass_block), 0,
+                           stream, links, g, par, c, beta, lo32(seed), hi32(seed), replica,
+                           (int)cfg.xcd_remap, rev, table);
+}
+
+template <bool LEARNED>
+void launch_pass_l(float *links, const Geom &g, int mu, int par, Sums c, float beta,
+                   uint64_t seed, uint32_t replica, bool measure, const float *table,
+                   const LaunchCfg &cfg, hipStream_t stream)
+{
+    switch (mu) {
+    case 0: launch_pass_mu<0, LEARNED>(links, g, par, c, beta, seed, replica, measure, table, cfg, stream); break;
+    case 1: launch_pass_mu<1, LEARNED>(links, g, par, c, beta, seed, replica, measure, table, cfg, stream); break;
+    case 2: launch_pass_mu<2, LEARNED>(links, g, par, c, beta, seed, replica, measure, table, cfg, stream); break;
+    default: launch_pass_mu<3, LEARNED>(links, g, par, c, beta, seed, replica, measure, table, cfg, stream); break;
+    }
 }
 
 }  // namespace
@@ -425,15 +480,20 @@ hipError_t launch_init(float *links, const Geom &g, int start, uint64_t seed, ui
 int pass_grid(const Geom &g, const LaunchCfg &cfg) { return (int)nblk(g.vh, cfg.pass_block); }
 
 hipError_t launch_pass(float *links, const Geom &g, int mu, int par, Sums c, float beta,
-                       uint64_t seed, uint32_t replica, bool measure, const LaunchCfg &cfg,
-                       hipStream_t stream)
+                       uint64_t seed, uint32_t replica, bool measure, const float *table,
+                       const LaunchCfg &cfg, hipStream_t stream)
 {
-    switch (mu) {
-    case 0: launch_pass_mu<0>(links, g, par, c, beta, seed, replica, measure, cfg, stream); break;
-    case 1: launch_pass_mu<1>(links, g, par, c, beta, seed, replica, measure, cfg, stream); break;
-    case 2: launch_pass_mu<2>(links, g, par, c, beta, seed, replica, measure, cfg, stream); break;
-    default: launch_pass_mu<3>(links, g, par, c, beta, seed, replica, measure, cfg, stream); break;
-    }
+    if (table)
+        launch_pass_l<true>(links, g, mu, par, c, beta, seed, replica, measure, table, cfg, stream);
+    else
+        launch_pass_l<false>(links, g, mu, par, c, beta, seed, replica, measure, nullptr, cfg,
+                             stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_counts(Sums c, unsigned long long *out, int reset, hipStream_t stream)
+{
+    hipLaunchKernelGGL(counts_kernel, dim3(1), dim3(kBuckets), 0, stream, c, out, reset);
     return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@
 #include "su2_internal.h"
 
 using su2dev::Geom;
+using su2dev::kNNRow;
+using su2dev::kNNRows;
 
 namespace su2rt {
 
@@ -41,6 +43,7 @@ struct su2_ctx {
     bool own_stream;
     hipStream_t stream;
     LaunchCfg cfg;
+    const float *table = nullptr;  // learned-proposal table (device), owned by an su2_nn
 
     Counters *counters() { return reinterpret_cast<Counters *>(scratch + kCountersOff); }
     Sums sums()
@@ -151,7 +154,9 @@ int enqueue_sweeps(su2_ctx *c, int32_t n, int mode, int32_t reunit_every, int me
                    double *hist)
 {
     if (mode != SU2_KP && mode != SU2_LEARNED) return fail(SU2_EINVAL, "unknown mode");
-    if (mode == SU2_LEARNED) return fail(SU2_ESTATE, "no learned proposal loaded");
+    if (mode == SU2_LEARNED && !c->table)
+        return fail(SU2_ESTATE, "no learned proposal loaded (su2_set_proposal)");
+    const float *table = mode == SU2_LEARNED ? c->table : nullptr;
     const float beta = (float)c->beta;
     const double inv6v = 1.0 / (6.0 * (double)c->volume);
     const double inv_ns3 = 1.0 / ((double)c->dims[0] * c->dims[1] * c->dims[2]);
@@ -165,7 +170,8 @@ int enqueue_sweeps(su2_ctx *c, int32_t n, int mode, int32_t reunit_every, int me
         for (int mu = 0; mu < 4; ++mu)
             for (int par = 0; par < 2; ++par)
                 HIP_TRY(launch_pass(c->links, c->g, mu, par, c->sums(), beta, c->seed,
-                                    c->replica, fused && par == 1 && mu >= 1, c->cfg, c->stream));
+                                    c->replica, fused && par == 1 && mu >= 1, table, c->cfg,
+                                    c->stream));
         if (reunit) HIP_TRY(launch_reunitarize(c->links, c->g, c->stream));
         if (want_p && !fused) HIP_TRY(launch_plaquette(c->links, c->g, c->sums(), c->stream));
         const bool want_l = hist && (meas & SU2_MEAS_POLY);
@@ -545,13 +551,16 @@ int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_
     return SU2_OK;
 }
 
-int su2_test_pass(su2_ctx *c, int mu, int parity)
+int su2_test_pass(su2_ctx *c, int mu, int parity, int mode)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1) return fail(SU2_EINVAL, "bad mu/parity");
+    if (mode != SU2_KP && mode != SU2_LEARNED) return fail(SU2_EINVAL, "unknown mode");
+    if (mode == SU2_LEARNED && !c->table) return fail(SU2_ESTATE, "no learned proposal loaded");
     HIP_TRY(launch_pass(c->links, c->g, mu, parity, c->sums(), (float)c->beta, c->seed,
-                        c->replica, false, c->cfg, c->stream));
+                        c->replica, false, mode == SU2_LEARNED ? c->table : nullptr, c->cfg,
+                        c->stream));
     return SU2_OK;
 }
 
@@ -592,4 +601,289 @@ int su2_test_gauge_transform(su2_ctx *c, uint64_t seed)
     return SU2_OK;
 }
 
+/* ===================================================== learned proposal */
+struct su2_nn {
+    NNBuffers b;
+    int64_t ndata = 0;     // training samples held
+    int64_t act_cap = 0;   // batch capacity of the per-sample record
+    int step = 0;          // Adam step counter
+    bool table_ready = false;
+    hipStream_t stream = nullptr;
+    double *dev_loss = nullptr;  // per-step losses of the last train call
+    int loss_cap = 0;
+};
+
+static void nn_free(su2_nn *n)
+{
+    // b.a0 lives inside the b.alpha allocation and b.loss inside b.act
+    float *bufs[] = {n->b.params, n->b.grad, n->b.m, n->b.v, n->b.alpha, n->b.act, n->b.table};
+    for (float *p : bufs)
+        if (p) (void)hipFree(p);
+    if (n->dev_loss) (void)hipFree(n->dev_loss);
+}
+
+// Default parameters: hidden layers uniform in +-1/sqrt(fan_in) from a
+// splitmix64 stream of the seed, biases 0; output weights 0 and output biases
+// that make the spline the identity (the untrained proposal is uniform).
+static void nn_default_params(uint64_t seed, std::vector<float> &p)
+{
+    p.assign(kNNParams, 0.0f);
+    uint64_t st = seed ^ 0x5DEECE66Dull;
+    auto next = [&]() {
+        uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * 0x1.0p-53;
+    };
+    for (int i = 0; i < 32; ++i) p[i] = (float)(2.0 * next() - 1.0);  // fan_in 1
+    for (int i = 0; i < 1024; ++i) p[64 + i] = (float)((2.0 * next() - 1.0) / std::sqrt(32.0));
+    const float id = (float)std::log(std::expm1(1.0 - 1e-3));
+    for (int i = 32; i < 47; ++i) p[2624 + i] = id;
+}
+
+int su2_nn_num_params(void) { return kNNParams; }
+
+int su2_nn_create(su2_nn **out, const float *params_host, uint64_t seed, void *hip_stream)
+{
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    *out = nullptr;
+    su2_nn *n = new (std::nothrow) su2_nn();
+    if (!n) return fail(SU2_ENOMEM, "host allocation failed");
+    n->stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipSuccess;
+    float **bufs[] = {&n->b.params, &n->b.grad, &n->b.m, &n->b.v};
+    for (float **pp : bufs)
+        if (e == hipSuccess) e = hipMalloc(pp, kNNParams * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&n->b.table, (size_t)kNNRows * kNNRow * sizeof(float));
+    std::vector<float> init;
+    if (!params_host) nn_default_params(seed, init);
+    const float *src = params_host ? params_host : init.data();
+    if (e == hipSuccess)
+        e = hipMemcpy(n->b.params, src, kNNParams * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(n->b.m, 0, kNNParams * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(n->b.v, 0, kNNParams * sizeof(float));
+    if (e != hipSuccess) {
+        nn_free(n);
+        delete n;
+        return fail(SU2_EHIP, std::string("nn_create: ") + hipGetErrorString(e));
+    }
+    *out = n;
+    return SU2_OK;
+}
+
+int su2_nn_destroy(su2_nn *n)
+{
+    if (!n) return fail(SU2_EINVAL, "nn is NULL");
+    (void)hipStreamSynchronize(n->stream);
+    nn_free(n);
+    delete n;
+    return SU2_OK;
+}
+
+int su2_nn_get_params(su2_nn *n, float *host)
+{
+    if (!n || !host) return fail(SU2_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    HIP_TRY(hipMemcpy(host, n->b.params, kNNParams * sizeof(float), hipMemcpyDeviceToHost));
+    return SU2_OK;
+}
+
+int su2_nn_set_params(su2_nn *n, const float *host)
+{
+    if (!n || !host) return fail(SU2_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    HIP_TRY(hipMemcpy(n->b.params, host, kNNParams * sizeof(float), hipMemcpyHostToDevice));
+    n->table_ready = false;
+    return SU2_OK;
+}
+
+static int nn_reserve_data(su2_nn *n, int64_t count)
+{
+    if (n->b.alpha) (void)hipFree(n->b.alpha);
+    n->b.alpha = n->b.a0 = nullptr;
+    n->ndata = 0;
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, (size_t)count * 2 * sizeof(float)));
+    n->b.alpha = static_cast<float *>(p);
+    n->b.a0 = n->b.alpha + count;
+    n->ndata = count;
+    return SU2_OK;
+}
+
+int su2_nn_sample_data(su2_nn *n, int64_t count, double alpha_lo, double alpha_hi, uint64_t seed)
+{
+    if (!n) return fail(SU2_EINVAL, "nn is NULL");
+    if (count <= 0 || count >= ((int64_t)1 << 32)) return fail(SU2_EINVAL, "count out of range");
+    if (!(alpha_lo > 0.0) || !(alpha_hi > alpha_lo) || !std::isfinite(alpha_hi))
+        return fail(SU2_EINVAL, "need 0 < alpha_lo < alpha_hi");
+    int rc = nn_reserve_data(n, count);
+    if (rc) return rc;
+    HIP_TRY(launch_nn_data(n->b.alpha, n->b.a0, count, (float)alpha_lo, (float)alpha_hi, seed,
+                           n->stream));
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    return SU2_OK;
+}
+
+int su2_nn_set_data(su2_nn *n, int64_t count, const float *alpha_host, const float *a0_host)
+{
+    if (!n || !alpha_host || !a0_host || count <= 0) return fail(SU2_EINVAL, "bad arguments");
+    int rc = nn_reserve_data(n, count);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(n->b.alpha, alpha_host, count * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(n->b.a0, a0_host, count * sizeof(float), hipMemcpyHostToDevice));
+    return SU2_OK;
+}
+
+int su2_nn_get_data(su2_nn *n, int64_t *count, float *alpha_host, float *a0_host)
+{
+    if (!n || !count) return fail(SU2_EINVAL, "bad arguments");
+    *count = n->ndata;
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    if (alpha_host && n->ndata)
+        HIP_TRY(hipMemcpy(alpha_host, n->b.alpha, n->ndata * sizeof(float), hipMemcpyDeviceToHost));
+    if (a0_host && n->ndata)
+        HIP_TRY(hipMemcpy(a0_host, n->b.a0, n->ndata * sizeof(float), hipMemcpyDeviceToHost));
+    return SU2_OK;
+}
+
+static int nn_reserve_act(su2_nn *n, int batch)
+{
+    if (batch <= n->act_cap) return SU2_OK;
+    if (n->b.act) (void)hipFree(n->b.act);
+    n->b.act = n->b.loss = nullptr;
+    n->act_cap = 0;
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, (size_t)batch * (kNNActRows + 1) * sizeof(float)));
+    n->b.act = static_cast<float *>(p);
+    n->b.loss = n->b.act + (size_t)batch * kNNActRows;
+    n->act_cap = batch;
+    return SU2_OK;
+}
+
+int su2_nn_loss_grad(su2_nn *n, int64_t offset, int32_t batch, double *loss, float *grad_host)
+{
+    if (!n || batch <= 0 || offset < 0) return fail(SU2_EINVAL, "bad arguments");
+    if (!n->ndata) return fail(SU2_ESTATE, "no training data");
+    int rc = nn_reserve_act(n, batch);
+    if (rc) return rc;
+    if (n->loss_cap < 1) {
+        void *p = nullptr;
+        HIP_TRY(hipMalloc(&p, sizeof(double)));
+        n->dev_loss = static_cast<double *>(p);
+        n->loss_cap = 1;
+    }
+    HIP_TRY(launch_nn_step(n->b, offset % n->ndata, batch, n->ndata, n->dev_loss, n->stream));
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    if (loss) HIP_TRY(hipMemcpy(loss, n->dev_loss, sizeof(double), hipMemcpyDeviceToHost));
+    if (grad_host)
+        HIP_TRY(hipMemcpy(grad_host, n->b.grad, kNNParams * sizeof(float), hipMemcpyDeviceToHost));
+    return SU2_OK;
+}
+
+int su2_nn_train(su2_nn *n, int32_t steps, int32_t batch, double lr, double *loss_history_host)
+{
+    if (!n || steps < 0 || batch <= 0 || !(lr > 0.0)) return fail(SU2_EINVAL, "bad arguments");
+    if (!n->ndata) return fail(SU2_ESTATE, "no training data");
+    int rc = nn_reserve_act(n, batch);
+    if (rc) return rc;
+    if (n->loss_cap < steps) {
+        if (n->dev_loss) (void)hipFree(n->dev_loss);
+        n->dev_loss = nullptr;
+        n->loss_cap = 0;
+        void *p = nullptr;
+        HIP_TRY(hipMalloc(&p, (size_t)std::max(steps, 1) * sizeof(double)));
+        n->dev_loss = static_cast<double *>(p);
+        n->loss_cap = std::max(steps, 1);
+    }
+    int64_t offset = 0;
+    for (int32_t t = 0; t < steps; ++t) {
+        HIP_TRY(launch_nn_step(n->b, offset, batch, n->ndata,
+                               loss_history_host ? n->dev_loss + t : nullptr, n->stream));
+        HIP_TRY(launch_nn_adam(n->b, (float)lr, ++n->step, n->stream));
+        offset = (offset + batch) % n->ndata;
+    }
+    n->table_ready = false;
+    if (loss_history_host && steps > 0) {
+        HIP_TRY(hipStreamSynchronize(n->stream));
+        HIP_TRY(hipMemcpy(loss_history_host, n->dev_loss, steps * sizeof(double),
+                          hipMemcpyDeviceToHost));
+    }
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    return SU2_OK;
+}
+
+int su2_nn_build_table(su2_nn *n)
+{
+    if (!n) return fail(SU2_EINVAL, "nn is NULL");
+    HIP_TRY(launch_nn_table(n->b.params, n->b.table, n->stream));
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    n->table_ready = true;
+    return SU2_OK;
+}
+
+int su2_nn_get_table(su2_nn *n, float *host)
+{
+    if (!n || !host) return fail(SU2_EINVAL, "NULL argument");
+    if (!n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
+    HIP_TRY(hipMemcpy(host, n->b.table, (size_t)kNNRows * kNNRow * sizeof(float),
+                      hipMemcpyDeviceToHost));
+    return SU2_OK;
+}
+
+int su2_set_proposal(su2_ctx *c, su2_nn *n)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (n && !n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
+    c->table = n ? n->b.table : nullptr;
+    return SU2_OK;
+}
+
+int su2_get_accept_stats(su2_ctx *c, uint64_t *proposed, uint64_t *accepted, int reset)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    unsigned long long *slot = reinterpret_cast<unsigned long long *>(c->results() + 4);
+    HIP_TRY(launch_counts(c->sums(), slot, reset, c->stream));
+    unsigned long long v[2] = {0ull, 0ull};
+    HIP_TRY(hipMemcpyAsync(v, slot, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (proposed) *proposed = v[0];
+    if (accepted) *accepted = v[1];
+    return SU2_OK;
+}
+
+int su2_test_learned_links(su2_nn *n, const float *V_host, const float *Uold_host, int64_t count,
+                           double beta, uint64_t seed, uint32_t sweep, uint32_t mu,
+                           uint32_t replica, float *out_host, int32_t *accepted_host)
+{
+    if (!n || count < 0 || (count > 0 && (!V_host || !Uold_host || !out_host)))
+        return fail(SU2_EINVAL, "bad arguments");
+    if (!n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
+    if (count >= ((int64_t)1 << 32) || mu > 3) return fail(SU2_EINVAL, "bad count or mu");
+    if (count == 0) return SU2_OK;
+    const size_t bytes = (size_t)count * 16;
+    void *dv = nullptr, *du = nullptr, *dout = nullptr, *dacc = nullptr;
+    hipError_t e = hipMalloc(&dv, bytes);
+    if (e == hipSuccess) e = hipMalloc(&du, bytes);
+    if (e == hipSuccess) e = hipMalloc(&dout, bytes);
+    if (e == hipSuccess && accepted_host) e = hipMalloc(&dacc, (size_t)count * 4);
+    if (e == hipSuccess) e = hipMemcpy(dv, V_host, bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(du, Uold_host, bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_test_learned(n->b.table, (const float *)dv, (const float *)du, count,
+                                (float)beta, seed, sweep, mu, replica, (float *)dout,
+                                (int32_t *)dacc, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out_host, dout, bytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && accepted_host)
+        e = hipMemcpy(accepted_host, dacc, (size_t)count * 4, hipMemcpyDeviceToHost);
+    void *bufs[] = {dv, du, dout, dacc};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    if (e != hipSuccess) return fail(SU2_EHIP, std::string("test_learned: ") + hipGetErrorString(e));
+    return SU2_OK;
+}
+
 }  // extern "C"
+

@@ -60,9 +60,25 @@ _SIGS = {
     "su2_set_launch": (_int, [_vp, _int, _int, _int, _int]),
     "su2_test_philox": (_int, [_vp, _i64, _u64, _vp]),
     "su2_test_heatbath_links": (_int, [_vp, _i64, _d, _u64, _u32, _u32, _u32, _vp, _vp]),
-    "su2_test_pass": (_int, [_vp, _int, _int]),
+    "su2_test_pass": (_int, [_vp, _int, _int, _int]),
     "su2_test_gauge_transform": (_int, [_vp, _u64]),
     "su2_test_index_map": (_int, [_vp, _int, _int, _int, _vp]),
+    "su2_nn_num_params": (_int, []),
+    "su2_nn_create": (_int, [_vp, _vp, _u64, _vp]),
+    "su2_nn_destroy": (_int, [_vp]),
+    "su2_nn_get_params": (_int, [_vp, _vp]),
+    "su2_nn_set_params": (_int, [_vp, _vp]),
+    "su2_nn_sample_data": (_int, [_vp, _i64, _d, _d, _u64]),
+    "su2_nn_set_data": (_int, [_vp, _i64, _vp, _vp]),
+    "su2_nn_get_data": (_int, [_vp, _vp, _vp, _vp]),
+    "su2_nn_loss_grad": (_int, [_vp, _i64, _i32, _vp, _vp]),
+    "su2_nn_train": (_int, [_vp, _i32, _i32, _d, _vp]),
+    "su2_nn_build_table": (_int, [_vp]),
+    "su2_nn_get_table": (_int, [_vp, _vp]),
+    "su2_set_proposal": (_int, [_vp, _vp]),
+    "su2_get_accept_stats": (_int, [_vp, _vp, _vp, _int]),
+    "su2_test_learned_links": (_int, [_vp, _vp, _vp, _i64, _d, _u64, _u32, _u32, _u32, _vp,
+                                      _vp]),
 }
 
 
@@ -221,8 +237,8 @@ def su2_test_heatbath_links(V, beta, seed, sweep, mu, replica=0, want_trials=Fal
     return (out, nt) if want_trials else out
 
 
-def su2_test_pass(h, mu, parity):
-    _check(lib().su2_test_pass(h, int(mu), int(parity)))
+def su2_test_pass(h, mu, parity, mode=SU2_KP):
+    _check(lib().su2_test_pass(h, int(mu), int(parity), int(mode)))
 
 
 def su2_test_index_map(dims, parity, tile_z=0, tile_t=0):
@@ -235,6 +251,147 @@ def su2_test_index_map(dims, parity, tile_z=0, tile_t=0):
 
 def su2_test_gauge_transform(h, seed):
     _check(lib().su2_test_gauge_transform(h, int(seed)))
+
+
+NN_NPARAM, NN_ROWS, NN_ROW = 2671, 256, 48
+
+
+def su2_nn_create(params=None, seed=0, stream=None):
+    h = _vp()
+    pa = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().su2_nn_create(ctypes.byref(h), None if pa is None else _p(pa), int(seed),
+                               _vp(stream)))
+    return h
+
+
+def su2_nn_destroy(h):
+    _check(lib().su2_nn_destroy(h))
+
+
+def su2_nn_get_params(h):
+    out = np.empty(NN_NPARAM, dtype=np.float32)
+    _check(lib().su2_nn_get_params(h, _p(out)))
+    return out
+
+
+def su2_nn_set_params(h, params):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().su2_nn_set_params(h, _p(a)))
+
+
+def su2_nn_sample_data(h, n, alpha_lo, alpha_hi, seed):
+    _check(lib().su2_nn_sample_data(h, int(n), float(alpha_lo), float(alpha_hi), int(seed)))
+
+
+def su2_nn_set_data(h, alpha, a0):
+    a = np.ascontiguousarray(alpha, dtype=np.float32)
+    x = np.ascontiguousarray(a0, dtype=np.float32)
+    _check(lib().su2_nn_set_data(h, a.size, _p(a), _p(x)))
+
+
+def su2_nn_get_data(h):
+    n = ctypes.c_int64()
+    _check(lib().su2_nn_get_data(h, ctypes.byref(n), None, None))
+    a = np.empty(n.value, dtype=np.float32)
+    x = np.empty(n.value, dtype=np.float32)
+    _check(lib().su2_nn_get_data(h, ctypes.byref(n), _p(a), _p(x)))
+    return a, x
+
+
+def su2_nn_loss_grad(h, offset, batch):
+    loss = ctypes.c_double()
+    g = np.empty(NN_NPARAM, dtype=np.float32)
+    _check(lib().su2_nn_loss_grad(h, int(offset), int(batch), ctypes.byref(loss), _p(g)))
+    return loss.value, g
+
+
+def su2_nn_train(h, steps, batch, lr):
+    hist = np.empty(max(int(steps), 1), dtype=np.float64)
+    _check(lib().su2_nn_train(h, int(steps), int(batch), float(lr), _p(hist)))
+    return hist[:steps]
+
+
+def su2_nn_build_table(h):
+    _check(lib().su2_nn_build_table(h))
+
+
+def su2_nn_get_table(h):
+    out = np.empty((NN_ROWS, NN_ROW), dtype=np.float32)
+    _check(lib().su2_nn_get_table(h, _p(out)))
+    return out
+
+
+def su2_set_proposal(ctx, nn):
+    _check(lib().su2_set_proposal(ctx, nn))
+
+
+def su2_get_accept_stats(ctx, reset=False):
+    p, a = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().su2_get_accept_stats(ctx, ctypes.byref(p), ctypes.byref(a), int(reset)))
+    return p.value, a.value
+
+
+def su2_test_learned_links(nn, V, Uold, beta, seed, sweep, mu, replica=0):
+    v = np.ascontiguousarray(V, dtype=np.float32).reshape(-1, 4)
+    u = np.ascontiguousarray(Uold, dtype=np.float32).reshape(-1, 4)
+    out = np.empty_like(v)
+    acc = np.empty(v.shape[0], dtype=np.int32)
+    _check(lib().su2_test_learned_links(nn, _p(v), _p(u), v.shape[0], float(beta), int(seed),
+                                        int(sweep), int(mu), int(replica), _p(out), _p(acc)))
+    return out, acc
+
+
+class NN:
+    """Learned-proposal network held by the library (su2_nn)."""
+
+    def __init__(self, params=None, seed=0, stream=None):
+        self.h = su2_nn_create(params, seed, stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            su2_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    params = property(lambda self: su2_nn_get_params(self.h))
+
+    def set_params(self, p):
+        su2_nn_set_params(self.h, p)
+
+    def sample_data(self, n, alpha_lo=0.5, alpha_hi=30.0, seed=0):
+        su2_nn_sample_data(self.h, n, alpha_lo, alpha_hi, seed)
+
+    def set_data(self, alpha, a0):
+        su2_nn_set_data(self.h, alpha, a0)
+
+    def data(self):
+        return su2_nn_get_data(self.h)
+
+    def loss_grad(self, offset, batch):
+        return su2_nn_loss_grad(self.h, offset, batch)
+
+    def train(self, steps, batch, lr=1e-3):
+        return su2_nn_train(self.h, steps, batch, lr)
+
+    def build_table(self):
+        su2_nn_build_table(self.h)
+
+    def table(self):
+        return su2_nn_get_table(self.h)
+
+    def test_links(self, V, Uold, beta, seed, sweep, mu, replica=0):
+        return su2_test_learned_links(self.h, V, Uold, beta, seed, sweep, mu, replica)
 
 
 # ------------------------------------------------------------ convenience
@@ -318,8 +475,14 @@ class Lattice:
     def synchronize(self):
         su2_synchronize(self.h)
 
-    def test_pass(self, mu, parity):
-        su2_test_pass(self.h, mu, parity)
+    def test_pass(self, mu, parity, mode=SU2_KP):
+        su2_test_pass(self.h, mu, parity, mode)
 
     def test_gauge_transform(self, seed):
         su2_test_gauge_transform(self.h, seed)
+
+    def set_proposal(self, nn):
+        su2_set_proposal(self.h, None if nn is None else nn.h)
+
+    def accept_stats(self, reset=False):
+        return su2_get_accept_stats(self.h, reset)

@@ -35,3 +35,19 @@ def compare_pass(got, want, margin, par, mu, parity_of_site, tol=1e-5):
         n = np.linalg.norm(got[flagged, mu], axis=1)
         assert np.all(np.abs(n - 1) < 1e-5)
     return err, int(flagged.sum())
+
+
+# Learned-update decisions (per type, each about 10x its FP32 error): the
+# Metropolis log-ratio (alpha <= 30 times an a0 error of ~1e-6), the table row
+# (the row position has an FP32 error of ~1e-4 rows), the table range ends.
+LEARNED_FLAGS = (3e-4, 2e-3, 3e-4)
+
+
+def learned_flagged(margins):
+    m = np.asarray(margins).reshape(-1, 3)
+    return (m[:, 0] < LEARNED_FLAGS[0]) | (m[:, 1] < LEARNED_FLAGS[1]) | (m[:, 2] < LEARNED_FLAGS[2])
+
+
+def max_learned_flags(n_updates):
+    """Row rounding dominates: 2 x 2e-3 of the updates, with a 5x margin."""
+    return int(5 * (2 * LEARNED_FLAGS[1] + 2 * LEARNED_FLAGS[0]) * n_updates) + 3

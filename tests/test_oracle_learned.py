@@ -157,6 +157,7 @@ def test_mh_fallback_outside_range_is_heat_bath(orc):
     V = np.array([20.0, 3.0, 0.0, 0.0])  # alpha = 2 * |V| > 30
     Uold = np.array([1.0, 0, 0, 0])
     out, m, a = orc.learned_link(V, Uold, table, 2.0, 5, 7, 3, 1)
+    assert m[1] == np.inf and m[2] > 0
     want, _ = orc.heatbath_link(V, 2.0, 5, 7, 3, 1)
     assert a == -1
     np.testing.assert_array_equal(out, want)
