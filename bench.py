@@ -58,6 +58,84 @@ def traffic_from_profile():
     return float(t.group(1))
 
 
+def tau_int(x, c=6.0):
+    """Integrated autocorrelation time, Madras-Sokal automatic window."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    x = x - x.mean()
+    var = x.var()
+    if var == 0 or n < 8:
+        return 0.5
+    f = np.fft.rfft(x, 2 * n)
+    acf = np.fft.irfft(f * np.conj(f))[:n] / (var * np.arange(n, 0, -1))
+    tau = 0.5
+    for w in range(1, n):
+        tau += acf[w]
+        if w >= c * tau:
+            break
+    return max(tau, 0.5)
+
+
+def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
+    """64 replicas, L = 8 + 2 (r mod 7) (8^4 .. 20^4), beta uniform in [1.8, 3.0]
+    (seeded), hot start; the learned proposal is trained on the GPU on 1e7
+    exact-sampler draws (alpha log-uniform in [0.5, 30]).  Each mode: autotuned
+    launch, then graph-captured chunks of batched sweeps with the plaquette
+    measured every sweep.  Effective rate = sweeps/s / (2 tau_int(P)), averaged
+    over the replicas."""
+    n = 64
+    L = [8 + 2 * (r % 7) for r in range(n)]
+    dims = [[l] * 4 for l in L]
+    betas = np.random.default_rng(5).uniform(1.8, 3.0, n)
+    links = 4 * sum(l ** 4 for l in L)
+    side = torch.cuda.Stream(device=dev)
+    out = {"workload": "64 replicas L=8+2(r mod 7), beta~U[1.8,3.0] (seed 5), hot start; "
+                       f"{therm} thermalisation + {sweeps} measured sweeps per mode",
+           "links_per_sweep": links}
+    with torch.cuda.stream(side):
+        net = su2.NN(seed=5)
+        t0 = time.perf_counter()
+        net.sample_data(10_000_000, 0.5, 30.0, seed=5)
+        hist = net.train(3000, 8192, 3e-3)
+        net.build_table()
+        torch.cuda.synchronize()
+        out["training"] = {"samples": 10_000_000, "steps": 3000, "batch": 8192, "lr": 3e-3,
+                           "seconds": time.perf_counter() - t0,
+                           "nll_first_100": float(hist[:100].mean()),
+                           "nll_last_100": float(hist[-100:].mean())}
+        for name, mode in (("plain", su2.SU2_KP), ("learned", su2.SU2_LEARNED)):
+            b = su2.Batch(dims, betas, [1] * n, seed=5, device=dev)
+            b.set_proposal(net)
+            tuned_us = b.autotune(None, mode)
+            b.sweep(therm, mode)
+            b.accept_stats(reset=True)
+            h = torch.zeros((sweeps, n, 3), dtype=torch.float64, device=dev)
+            b.capture(chunk, mode, meas=su2.SU2_MEAS_PLAQ, hist=h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.replay(sweeps // chunk)
+            b.synchronize()
+            dt = time.perf_counter() - t0
+            prop, acc = b.accept_stats()
+            P = h.cpu().numpy()[:, :, 0]
+            taus = np.array([tau_int(P[:, r]) for r in range(n)])
+            sps = sweeps / dt
+            out[name] = {"link_updates_per_s": links * sps, "sweeps_per_s": sps,
+                         "tuned_us_per_sweep": tuned_us,
+                         "tau_int_plaquette_mean": float(taus.mean()),
+                         "effective_sweeps_per_s": float(np.mean(sps / (2 * taus))),
+                         "acceptance": (float(acc.sum() / prop.sum()) if prop.sum() else None),
+                         "mean_plaquette": float(P.mean())}
+            b.close()
+        net.close()
+    torch.cuda.synchronize()
+    out["learned_over_plain_updates"] = (out["learned"]["link_updates_per_s"] /
+                                         out["plain"]["link_updates_per_s"])
+    out["learned_over_plain_effective"] = (out["learned"]["effective_sweeps_per_s"] /
+                                           out["plain"]["effective_sweeps_per_s"])
+    return out
+
+
 def cpu_baseline(sample_sweeps=1):
     from oracle import su2_oracle as orc
     threads = orc.max_threads()
@@ -79,6 +157,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--pass-launches", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the batched plain-vs-learned comparison")
     ap.add_argument("--counters", action="store_true",
                     help="short program for rocprofv3 --pmc runs: 16 pass launches in sweep "
                          "order, then 4 plain device copies of the field size (339.7 MB) "
@@ -112,6 +192,8 @@ def main():
         lat.close()
         return
 
+    tuned_us = lat.autotune(None, su2.SU2_KP)
+    print(f"[bench] autotuned launch: {tuned_us:.1f} us per sweep", file=sys.stderr, flush=True)
     print(f"[bench] warmup {args.warmup} sweeps on {DIMS}", file=sys.stderr, flush=True)
     lat.sweep_measure(args.warmup, reunit_every=10, meas=meas, hist=hist)
     torch.cuda.synchronize()
@@ -155,8 +237,13 @@ def main():
                      "kernel": "pass_kernel", "avg_launch_us": pass_ms * 1e3,
                      "bytes_per_update": BYTES_PER_UPDATE, "updates_per_launch": V // 2},
         "plaquette_mean_last_half": float(h[args.steps // 2:, 0].mean()),
+        "autotuned_us_per_sweep": tuned_us,
+        "launch": lat.launch(),
     }
     lat.close()
+    if not args.no_learned:
+        print("[bench] batched plain vs learned proposal", file=sys.stderr, flush=True)
+        out["learned_vs_plain"] = learned_vs_plain(su2, torch, dev)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

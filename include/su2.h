@@ -137,10 +137,68 @@ int su2_synchronize(su2_ctx *ctx);
 
 /* Launch configuration of the pass kernel: block size (64, 128, 192 or 256
  * threads); flags: bit 0 = XCD-contiguous workgroup remap, bit 1 = disable
- * the alternating (forward, backward) pass order; and the traversal tile
- * of (z, t) planes, tile_z x tile_t (powers of two that divide Nz and Nt;
- * 0 keeps the current value).  Results do not depend on it. */
-int su2_set_launch(su2_ctx *ctx, int block, int flags, int tile_z, int tile_t);
+ * the alternating (forward, backward) pass order; the traversal tile of
+ * (z, t) planes, tile_z x tile_t (powers of two <= 256, clipped to divisors
+ * of Nz and Nt; 0 keeps the current value); grid_cap > 0 runs the pass as a
+ * persistent grid of at most grid_cap workgroups looping over the work (0 =
+ * one workgroup per tile).  Results do not depend on it.  Drops captured
+ * sweeps. */
+int su2_set_launch(su2_ctx *ctx, int block, int flags, int tile_z, int tile_t, int grid_cap);
+/* Current launch configuration (tiles as applied to this lattice's extents). */
+int su2_get_launch(su2_ctx *ctx, int *block, int *flags, int *tile_z, int *tile_t, int *grid_cap);
+
+/* Autotuner: times candidate launch configurations (block size, order flags,
+ * traversal tile, persistent grid) on this lattice with sweeps of `mode`,
+ * restores links and counters afterwards, and applies the fastest.  With a
+ * cache_path (JSON lines, one entry per device and set of extents), a cached
+ * choice is applied without timing and new choices are appended.
+ * *best_us_per_sweep (may be NULL) receives its time per sweep. */
+int su2_autotune(su2_ctx *ctx, const char *cache_path, int mode, double *best_us_per_sweep);
+
+/* hipGraph capture: record nsweeps sweeps exactly as su2_sweep_measure (meas
+ * = 0: as su2_heatbath_sweep) would enqueue them, then replay the recording
+ * `count` times with su2_replay_sweeps (one graph launch per replay; the
+ * sweep index and the history row index advance on the device, so replay k
+ * appends rows k*nsweeps..).  With reunit_every > 0, nsweeps must be a
+ * multiple of it and the current sweep index a multiple of it.  Needs a
+ * non-null stream; later launch or proposal changes drop the recording. */
+int su2_capture_sweeps(su2_ctx *ctx, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
+                       double *dev_history);
+int su2_replay_sweeps(su2_ctx *ctx, int32_t count);
+
+/* ============================================================== batches
+ * n replicas with their own extents, couplings and starts advance together:
+ * every kernel launch covers all of them (the pass maps its workgroups onto
+ * the replicas' tiles), so small lattices fill the GPU.  Replica r uses
+ * Philox replica id r, i.e. it follows exactly the chain of a single context
+ * with the same extents, beta, seed and su2_set_replica(r).  Library-owned
+ * device memory; hip_stream as for su2_init_ext (capture and autotuning need
+ * a non-null stream). */
+typedef struct su2_batch su2_batch;
+
+/* dims: host int32[n][4]; betas: host double[n]; starts: host int[n]. */
+int su2_batch_init(su2_batch **out, int32_t n, const int32_t *dims, const double *betas,
+                   const int *starts, uint64_t seed, void *hip_stream);
+int su2_batch_destroy(su2_batch *b);
+int su2_batch_size(su2_batch *b, int32_t *n);
+int su2_batch_sweep(su2_batch *b, int32_t nsweeps, int mode);
+/* As su2_sweep_measure; dev_history is FP64[nsweeps][n][3]. */
+int su2_batch_sweep_measure(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_every,
+                            int meas, double *dev_history);
+int su2_batch_capture(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
+                      double *dev_history);
+int su2_batch_replay(su2_batch *b, int32_t count);
+/* Plaquette and Polyakov loop of every replica into host arrays of n (any may
+ * be NULL).  Synchronous. */
+int su2_batch_observables(su2_batch *b, double *plaq, double *poly_signed, double *poly_abs);
+int su2_batch_get_links(su2_batch *b, int32_t replica, float *host);
+int su2_batch_set_links(su2_batch *b, int32_t replica, const float *host);
+int su2_batch_set_launch(su2_batch *b, int block, int flags, int tile_z, int tile_t,
+                         int grid_cap);
+int su2_batch_autotune(su2_batch *b, const char *cache_path, int mode, double *best_us);
+int su2_batch_synchronize(su2_batch *b);
+/* Per-replica learned proposals made / accepted (host uint64[n] each). */
+int su2_batch_get_accept_stats(su2_batch *b, uint64_t *proposed, uint64_t *accepted, int reset);
 
 /* ======================================================= learned proposal
  * An independence-Metropolis update of a0 with a learned proposal replaces the
@@ -186,6 +244,7 @@ int su2_nn_get_table(su2_nn *nn, float *table_host);
 /* Use nn's table for SU2_LEARNED sweeps of ctx (NULL unsets).  The su2_nn must
  * outlive every sweep enqueued with it and its table must be built. */
 int su2_set_proposal(su2_ctx *ctx, su2_nn *nn);
+int su2_batch_set_proposal(su2_batch *b, su2_nn *nn);
 /* Learned proposals made and accepted since the last reset (synchronous). */
 int su2_get_accept_stats(su2_ctx *ctx, uint64_t *proposed, uint64_t *accepted, int reset);
 

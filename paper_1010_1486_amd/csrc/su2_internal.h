@@ -13,12 +13,6 @@ namespace su2rt {
 
 void set_error(const std::string &msg);
 
-// Scratch layout (bytes): [0,64) device counters, [64,256) FP64 result
-// slots, [256, 256 + kAccBytes) fixed-point accumulators.
-constexpr size_t kCountersOff = 0;
-constexpr size_t kResultsOff = 64;
-constexpr size_t kAccOff = 256;
-
 // Global sums: every workgroup reduces its values in FP64 (wave shuffles,
 // then LDS) and adds the block sum, rounded to a multiple of 2^-kFixedShift,
 // to a 64-bit integer accumulator.  Integer addition is associative, so the
@@ -31,39 +25,80 @@ constexpr int kBuckets = 256;
 constexpr int kBucketStride = 16;  // 16 x 8 B = one 128-byte line per bucket
 constexpr int kNumAcc = 4;  // plaquette, Polyakov (fixed point); proposals, accepts (counts)
 constexpr size_t kAccBytes = (size_t)kNumAcc * kBuckets * kBucketStride * 8;
-constexpr size_t kScratchBytes = kAccOff + kAccBytes;
+
+enum Result { R_PLAQ = 0, R_POLY_SIGNED = 1, R_POLY_ABS = 2, R_COUNTS = 4 };
+enum Acc { ACC_PLAQ = 0, ACC_POLY = 1, ACC_PROPOSED = 2, ACC_ACCEPTED = 3 };
 
 struct Counters {
     uint32_t sweep;     // sweep index used by the next pass (Philox counter word 1)
     uint32_t meas_idx;  // next history row written by a measured sweep
+    uint32_t pad[14];
 };
 
-enum Result { R_PLAQ = 0, R_POLY_SIGNED = 1, R_POLY_ABS = 2 };
-enum Acc { ACC_PLAQ = 0, ACC_POLY = 1, ACC_PROPOSED = 2, ACC_ACCEPTED = 3 };
-
-// Accumulator `which`, bucket b: acc + (which * kBuckets + b) * kBucketStride.
-struct Sums {
-    Counters *cnt;
-    unsigned long long *acc;
+// Device-resident descriptor of one lattice (replica) of an ensemble.  A
+// single lattice is an ensemble of one.
+struct Rep {
+    su2dev::Geom g;
+    float *links;              // 32 planes of g.vh floats
+    Counters *cnt;             // this replica's counters
+    unsigned long long *acc;   // this replica's kNumAcc x kBuckets accumulators
+    double *results;           // 8 FP64 result slots
+    float beta;
+    uint32_t replica;          // Philox replica id
+    uint32_t first_block;      // first pass workgroup of this replica (multiple of 8)
+    uint32_t nblocks;          // pass workgroups of this replica
 };
+
+// Per-replica scratch: counters, accumulators, result slots.
+constexpr size_t kRepScratch = sizeof(Counters) + kAccBytes + 8 * sizeof(double);
 
 struct LaunchCfg {
     int pass_block = 256;
     bool xcd_remap = true;
-    bool snake = true;  // odd-parity passes traverse backwards
+    bool snake = true;        // odd-parity passes traverse backwards
+    uint32_t grid_cap = 0;    // > 0: persistent pass grid of at most this many workgroups
+};
+
+// Everything a launch needs to address an ensemble on the device.
+struct Ens {
+    const Rep *reps;          // device array of nrep descriptors
+    const uint32_t *bmap;     // pass workgroup -> replica (nullptr when nrep == 1)
+    int nrep;
+    uint32_t total_blocks;    // pass workgroups over all replicas (padded)
+    uint32_t max_vh;          // largest V/2 over the replicas
+    uint32_t max_ns3;         // largest spatial volume
+    int poly_s;               // Polyakov segments (common divisor of every Nt)
 };
 
 // Kernel launchers (all asynchronous on `stream`; return hipError_t).
-hipError_t launch_init(float *links, const su2dev::Geom &g, int start, uint64_t seed,
-                       uint32_t replica, hipStream_t stream);
+hipError_t launch_init(const Ens &e, const int *starts_dev, uint64_t seed, hipStream_t stream);
 // measure: accumulate (1/2)Tr(U' V_nu), nu < mu, into acc[ACC_PLAQ].
 // table != nullptr: learned-proposal Metropolis update (counts into
 // acc[ACC_PROPOSED] / acc[ACC_ACCEPTED]); else the exact heat bath.
-hipError_t launch_pass(float *links, const su2dev::Geom &g, int mu, int par, Sums c,
-                       float beta, uint64_t seed, uint32_t replica, bool measure,
+hipError_t launch_pass(const Ens &e, int mu, int par, uint64_t seed, bool measure,
                        const float *table, const LaunchCfg &cfg, hipStream_t stream);
-// out[0] = proposals, out[1] = accepts summed over the buckets; reset if asked.
-hipError_t launch_counts(Sums c, unsigned long long *out, int reset, hipStream_t stream);
+// Sum of all plaquettes into acc[ACC_PLAQ]; sum of L(x) into acc[ACC_POLY].
+hipError_t launch_plaquette(const Ens &e, hipStream_t stream);
+hipError_t launch_polyakov(const Ens &e, hipStream_t stream);
+// results[R_PLAQ] = plaquette, results[R_POLY_*] = Polyakov loop from the
+// accumulators (flags 1 / 2), which are reset.
+hipError_t launch_take(const Ens &e, int flags, hipStream_t stream);
+// End of a sweep.  flags: 1 plaquette in acc[ACC_PLAQ], 2 Polyakov in
+// acc[ACC_POLY], 4 append a history row (P, L, |L|) per replica at
+// hist[3 * (meas_idx * nrep + r)].  Resets the accumulators, advances sweep.
+hipError_t launch_sweep_end(const Ens &e, int flags, double *hist, hipStream_t stream);
+hipError_t launch_reunitarize(const Ens &e, hipStream_t stream);
+// which: 1 set sweep, 2 set meas_idx, 4 zero all accumulators, 8 zero counts.
+hipError_t launch_set_counter(const Ens &e, uint32_t sweep, uint32_t meas, int which,
+                              hipStream_t stream);
+// results[R_COUNTS..] = proposals, accepts (as uint64); reset if asked.
+hipError_t launch_counts(const Ens &e, int reset, hipStream_t stream);
+hipError_t launch_gauge(const Ens &e, float *G, uint64_t seed, hipStream_t stream);
+hipError_t launch_test_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
+                              hipStream_t stream);
+hipError_t launch_test_links(const float *V, int64_t n, float beta, uint64_t seed,
+                             uint32_t sweep, uint32_t mu, uint32_t replica, float *out,
+                             int32_t *ntrials, hipStream_t stream);
 
 // ------------------------------------------------------- learned proposal
 constexpr int kNNParams = 2671;
@@ -88,29 +123,5 @@ hipError_t launch_test_learned(const float *table, const float *V, const float *
                                float beta, uint64_t seed, uint32_t sweep, uint32_t mu,
                                uint32_t replica, float *out, int32_t *accepted,
                                hipStream_t stream);
-int pass_grid(const su2dev::Geom &g, const LaunchCfg &cfg);
-// Sum of all plaquettes into acc[ACC_PLAQ]; sum of L(x) into acc[ACC_POLY].
-hipError_t launch_plaquette(const float *links, const su2dev::Geom &g, Sums c,
-                            hipStream_t stream);
-hipError_t launch_polyakov(const float *links, const su2dev::Geom &g, Sums c,
-                           hipStream_t stream);
-// out[0] = acc[which] * scale, out[1] = |out[0]|; resets acc[which].
-hipError_t launch_take(Sums c, int which, double scale, double *out, hipStream_t stream);
-// End of a sweep.  flags: 1 plaquette in acc[ACC_PLAQ], 2 Polyakov in
-// acc[ACC_POLY], 4 append a history row (P, L, |L|) at hist[3*meas_idx].
-// Resets the accumulators and advances the sweep counter.
-hipError_t launch_sweep_end(Sums c, int flags, double plaq_scale, double poly_scale,
-                            double *hist, hipStream_t stream);
-hipError_t launch_reunitarize(float *links, const su2dev::Geom &g, hipStream_t stream);
-hipError_t launch_gauge(float *links, const su2dev::Geom &g, float *G, uint64_t seed,
-                        uint32_t replica, hipStream_t stream);
-hipError_t launch_test_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
-                              hipStream_t stream);
-hipError_t launch_test_links(const float *V, int64_t n, float beta, uint64_t seed,
-                             uint32_t sweep, uint32_t mu, uint32_t replica, float *out,
-                             int32_t *ntrials, hipStream_t stream);
-// which: 1 set sweep, 2 set meas_idx, 4 zero the accumulators.
-hipError_t launch_set_counter(Sums c, uint32_t sweep, uint32_t meas, int which,
-                              hipStream_t stream);
 
 }  // namespace su2rt

@@ -68,12 +68,13 @@ __device__ __forceinline__ unsigned long long *bucket(unsigned long long *acc, i
     return acc + ((size_t)which * kBuckets + (b % kBuckets)) * kBucketStride;
 }
 
-// Thread 0 adds the block's FP64 sum to bucket (block id mod kBuckets) of
+// Thread 0 adds the block's FP64 sum to bucket (b mod kBuckets) of
 // fixed-point accumulator `which`.
-__device__ __forceinline__ void block_accumulate(double v, unsigned long long *acc, int which)
+__device__ __forceinline__ void block_accumulate(double v, unsigned long long *acc, int which,
+                                                 uint32_t b)
 {
-    const double b = block_sum(v);
-    if (threadIdx.x == 0) atomicAdd(bucket(acc, which, blockIdx.x), to_fixed(b));
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) atomicAdd(bucket(acc, which, b), to_fixed(s));
 }
 
 // Exact integer total of accumulator `which` over its buckets, computed by a
@@ -111,123 +112,160 @@ __device__ __forceinline__ uint32_t logical_block(uint32_t b, uint32_t nb, int r
 }
 
 // One (mu, parity) plane group of the link field: four component planes at
-// uniform byte addresses, indexed by a 32-bit byte offset.
+// uniform byte addresses in the global address space (so loads use a scalar
+// base and a 32-bit vector offset), indexed by a 32-bit byte offset.
+typedef __attribute__((address_space(1))) const char gchar;
+typedef __attribute__((address_space(1))) const float gfloat;
+typedef __attribute__((address_space(1))) float gfloat_w;
+
 struct Arr {
-    const char *c0, *c1, *c2, *c3;
+    gchar *c0, *c1, *c2, *c3;
 };
 
 __device__ __forceinline__ Arr arr(const float *links, uint32_t vh, int mu, int par)
 {
     const size_t pb = (size_t)vh * 4u;
-    const char *b = reinterpret_cast<const char *>(links) + (size_t)((mu * 2 + par) * 4) * pb;
+    gchar *b = (gchar *)links + (size_t)((mu * 2 + par) * 4) * pb;
     return Arr{b, b + pb, b + 2 * pb, b + 3 * pb};
 }
 
 __device__ __forceinline__ Q ld(const Arr &a, uint32_t h)
 {
     const uint32_t off = h * 4u;
-    return Q{*reinterpret_cast<const float *>(a.c0 + off),
-             *reinterpret_cast<const float *>(a.c1 + off),
-             *reinterpret_cast<const float *>(a.c2 + off),
-             *reinterpret_cast<const float *>(a.c3 + off)};
+    return Q{*(gfloat *)(a.c0 + off), *(gfloat *)(a.c1 + off), *(gfloat *)(a.c2 + off),
+             *(gfloat *)(a.c3 + off)};
+}
+
+__device__ __forceinline__ void st(float *links, uint32_t vh, int mu, int par, uint32_t h,
+                                   const Q &q)
+{
+    gfloat_w *p = (gfloat_w *)links + (size_t)((mu * 2 + par) * 4) * vh + h;
+    p[0] = q.w;
+    p[vh] = q.x;
+    p[2 * (size_t)vh] = q.y;
+    p[3 * (size_t)vh] = q.z;
+}
+
+__device__ __forceinline__ Q ldq(const float *links, uint32_t vh, int mu, int par, uint32_t h)
+{
+    gfloat *p = (gfloat *)links + (size_t)((mu * 2 + par) * 4) * vh + h;
+    return Q{p[0], p[vh], p[2 * (size_t)vh], p[3 * (size_t)vh]};
 }
 
 // ------------------------------------------------------------------- init
-__global__ void init_kernel(float *__restrict__ links, Geom g, int start, uint32_t k0,
-                            uint32_t k1, uint32_t replica)
+// grid (blocks over V/2, 8 = mu * 2 + parity, replica)
+__global__ void init_kernel(const Rep *__restrict__ reps, const int *__restrict__ starts,
+                            uint32_t k0, uint32_t k1)
 {
+    const Rep &R = reps[blockIdx.z];
     const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    const int mp = blockIdx.y;  // mu * 2 + parity
-    if (h >= g.vh) return;
-    const int mu = mp >> 1, par = mp & 1;
+    if (h >= R.g.vh) return;
+    const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
     Q q{1.0f, 0.0f, 0.0f, 0.0f};
-    if (start) {
+    if (starts[blockIdx.z]) {
         int x, y, z, t;
-        decode(g, h, par, x, y, z, t);
+        decode(R.g, h, par, x, y, z, t);
         const uint32_t s = 2u * h + (uint32_t)(x & 1);
-        q = haar_from_block(philox(s, 0u, word2((uint32_t)mu, TAG_HOT, replica), 0u, k0, k1));
+        q = haar_from_block(philox(s, 0u, word2((uint32_t)mu, TAG_HOT, R.replica), 0u, k0, k1));
     }
-    store_q(links, g.vh, mu, par, h, q);
+    st(R.links, R.g.vh, mu, par, h, q);
 }
 
 // ------------------------------------------------------------------- pass
-// One heat-bath pass over the sites of parity `par` in direction MU.  With
-// MEASURE, (1/2)Tr(U'_mu(s) V_nu(s)) summed over nu < mu is accumulated: over
-// the odd passes of mu = 1, 2, 3 this is every plaquette of the end-of-sweep
-// configuration exactly once.
+// One heat-bath pass over the sites of parity `par` in direction MU, for
+// every replica of the ensemble.  Workgroup ids b in [0, total) are mapped
+// to replicas by bmap (each replica's range starts at a multiple of 8, so
+// b mod 8 is still the XCD); with a capped grid the workgroups loop over b
+// (persistent).  With MEASURE, (1/2)Tr(U'_mu(s) V_nu(s)) summed over nu < mu
+// is accumulated: over the odd passes of mu = 1, 2, 3 this is every
+// plaquette of the end-of-sweep configuration exactly once.
 template <int MU, bool MEASURE, bool LEARNED>
-__global__ __launch_bounds__(256) void pass_kernel(float *__restrict__ links, Geom g, int par,
-                                                   Sums sums, float beta, uint32_t k0,
-                                                   uint32_t k1, uint32_t replica, int remap,
-                                                   int reverse, const float *__restrict__ table)
+__global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
+                                                   const uint32_t *__restrict__ bmap,
+                                                   uint32_t total, int par, uint32_t k0,
+                                                   uint32_t k1, int remap, int reverse,
+                                                   const float *__restrict__ table)
 {
-    const uint32_t blk = logical_block(blockIdx.x, gridDim.x, remap, reverse);
-    const uint32_t gid = blk * blockDim.x + threadIdx.x;
-    float meas = 0.0f;
-    int acc = -1;
-    if (gid < g.vh) {
-        const uint32_t sweep = sums.cnt->sweep;
-        const int opp = par ^ 1;
-        const PassSite s = pass_site(g, gid, par);
-        const Deltas d = neighbour_deltas(g, s);
-        const uint32_t h = s.h;
-        const Arr Umu_o = arr(links, g.vh, MU, opp);
-        Q V{0.0f, 0.0f, 0.0f, 0.0f};
-        Q Vlow{0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const Rep &R = reps[bmap ? bmap[b] : 0u];
+        const uint32_t local = b - R.first_block;
+        if (local >= R.nblocks) continue;  // padding workgroup (uniform)
+        const Geom &g = R.g;
+        const uint32_t blk = logical_block(local, R.nblocks, remap, reverse);
+        const uint32_t gid = blk * blockDim.x + threadIdx.x;
+        float meas = 0.0f;
+        int acc = -1;
+        if (gid < g.vh) {
+            // uniform: a scalar load through the constant address space
+            const uint32_t sweep =
+                *(const __attribute__((address_space(4))) uint32_t *)&R.cnt->sweep;
+            const int opp = par ^ 1;
+            const float *links = R.links;
+            const PassSite s = pass_site(g, gid, par);
+            const Deltas d = neighbour_deltas(g, s);
+            const uint32_t h = s.h;
+            const Arr Umu_o = arr(links, g.vh, MU, opp);
+            Q V{0.0f, 0.0f, 0.0f, 0.0f};
+            Q Vlow{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int nu = 0; nu < 4; ++nu) {
-            if (nu == MU) continue;
-            const Arr Unu_p = arr(links, g.vh, nu, par);
-            const Arr Unu_o = arr(links, g.vh, nu, opp);
-            // forward: U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
-            const Q A = ld(Unu_o, h + d.p[MU]);
-            const Q B = ld(Umu_o, h + d.p[nu]);
-            const Q C = ld(Unu_p, h);
-            // backward: U_nu(s+mu-nu)^+ U_mu(s-nu)^+ U_nu(s-nu) = (E D)^+ F
-            const Q D = ld(Unu_p, h + d.p[MU] + d.m[nu]);
-            const Q E = ld(Umu_o, h + d.m[nu]);
-            const Q F = ld(Unu_o, h + d.m[nu]);
-            const Q st = qadd(qmul(qmul(A, qdag(B)), qdag(C)), qmul(qdag(qmul(E, D)), F));
-            V = qadd(V, st);
-            if (MEASURE && nu < MU) Vlow = qadd(Vlow, st);
+            for (int nu = 0; nu < 4; ++nu) {
+                if (nu == MU) continue;
+                const Arr Unu_p = arr(links, g.vh, nu, par);
+                const Arr Unu_o = arr(links, g.vh, nu, opp);
+                // forward: U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
+                const Q A = ld(Unu_o, h + d.p[MU]);
+                const Q B = ld(Umu_o, h + d.p[nu]);
+                const Q C = ld(Unu_p, h);
+                // backward: U_nu(s+mu-nu)^+ U_mu(s-nu)^+ U_nu(s-nu) = (E D)^+ F
+                const Q D = ld(Unu_p, h + d.p[MU] + d.m[nu]);
+                const Q E = ld(Umu_o, h + d.m[nu]);
+                const Q F = ld(Unu_o, h + d.m[nu]);
+                const Q st = qadd(qmul(qmul(A, qdag(B)), qdag(C)), qmul(qdag(qmul(E, D)), F));
+                V = qadd(V, st);
+                if (MEASURE && nu < MU) Vlow = qadd(Vlow, st);
+            }
+            const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
+            Q Un;
+            if (LEARNED) {
+                const Q Uold = ld(arr(links, g.vh, MU, par), h);
+                Un = learned_link(V, Uold, table, R.beta, site, sweep, (uint32_t)MU, R.replica,
+                                  k0, k1, acc);
+            } else {
+                Un = heatbath_link(V, R.beta, site, sweep,
+                                   word2((uint32_t)MU, TAG_TRIAL, R.replica), k0, k1);
+            }
+            st(R.links, g.vh, MU, par, h, Un);
+            if (MEASURE) meas = retr(Un, Vlow);
         }
-        const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
-        Q Un;
+        if (MEASURE) block_accumulate((double)meas, R.acc, ACC_PLAQ, b);
         if (LEARNED) {
-            const Q Uold = ld(arr(links, g.vh, MU, par), h);
-            Un = learned_link(V, Uold, table, beta, site, sweep, (uint32_t)MU, replica, k0, k1,
-                              acc);
-        } else {
-            Un = heatbath_link(V, beta, site, sweep, word2((uint32_t)MU, TAG_TRIAL, replica), k0,
-                               k1);
-        }
-        store_q(links, g.vh, MU, par, h, Un);
-        if (MEASURE) meas = retr(Un, Vlow);
-    }
-    if (MEASURE) block_accumulate((double)meas, sums.acc, ACC_PLAQ);
-    if (LEARNED) {
-        const double np = block_sum(acc >= 0 ? 1.0 : 0.0);
-        const double na = block_sum(acc == 1 ? 1.0 : 0.0);
-        if (threadIdx.x == 0) {
-            atomicAdd(bucket(sums.acc, ACC_PROPOSED, blockIdx.x), (unsigned long long)np);
-            atomicAdd(bucket(sums.acc, ACC_ACCEPTED, blockIdx.x), (unsigned long long)na);
+            const double np = block_sum(acc >= 0 ? 1.0 : 0.0);
+            const double na = block_sum(acc == 1 ? 1.0 : 0.0);
+            if (threadIdx.x == 0) {
+                atomicAdd(bucket(R.acc, ACC_PROPOSED, b), (unsigned long long)np);
+                atomicAdd(bucket(R.acc, ACC_ACCEPTED, b), (unsigned long long)na);
+            }
         }
     }
 }
 
 // -------------------------------------------------------------- plaquette
-// One thread per site, both parities, in the pass traversal order: the six
-// plaquettes (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+ = (1/2)Tr(P Q^+)
-// with P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
-__global__ __launch_bounds__(256) void plaquette_kernel(const float *__restrict__ links, Geom g,
-                                                        Sums sums, int remap)
+// grid (blocks over V, 1, replica).  One thread per site, both parities, in
+// the pass traversal order: (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
+// = (1/2)Tr(P Q^+) with P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
+__global__ __launch_bounds__(256) void plaquette_kernel(const Rep *__restrict__ reps, int remap)
 {
-    const uint32_t blk = logical_block(blockIdx.x, gridDim.x, remap, 0);
+    const Rep &R = reps[blockIdx.z];
+    const Geom &g = R.g;
+    const uint32_t nb = (2u * g.vh + blockDim.x - 1) / blockDim.x;
+    if (blockIdx.x >= nb) return;  // uniform: whole workgroup
+    const uint32_t blk = logical_block(blockIdx.x, nb, remap, 0);
     const uint32_t i = blk * blockDim.x + threadIdx.x;
     double acc = 0.0;
     if (i < 2u * g.vh) {
         const int par = i >= g.vh ? 1 : 0;
         const int opp = par ^ 1;
+        const float *links = R.links;
         const PassSite s = pass_site(g, par ? i - g.vh : i, par);
         const Deltas d = neighbour_deltas(g, s);
         Q U[4];
@@ -244,20 +282,23 @@ __global__ __launch_bounds__(256) void plaquette_kernel(const float *__restrict_
             }
         acc = (double)sum;
     }
-    block_accumulate(acc, sums.acc, ACC_PLAQ);
+    block_accumulate(acc, R.acc, ACC_PLAQ, blockIdx.x);
 }
 
 // --------------------------------------------------------------- Polyakov
-// L(x) = (1/2)Tr prod_{t=0}^{Nt-1} U_3(x, t), t = 0 leftmost.  A workgroup
-// holds 64 spatial sites and S waves; wave w multiplies the w-th of S
-// contiguous t-segments for its 64 sites (consecutive lanes read consecutive
-// sites), and wave 0 multiplies the S segment products in t order from LDS.
+// grid (spatial sites / 64, 1, replica).  L(x) = (1/2)Tr prod_t U_3(x, t),
+// t = 0 leftmost.  A workgroup holds 64 spatial sites and S waves; wave w
+// multiplies the w-th of S contiguous t-segments for its 64 sites
+// (consecutive lanes read consecutive sites), and wave 0 multiplies the S
+// segment products in t order from LDS.
 template <int S>
-__global__ __launch_bounds__(512) void polyakov_kernel(const float *__restrict__ links, Geom g,
-                                                       Sums sums)
+__global__ __launch_bounds__(512) void polyakov_kernel(const Rep *__restrict__ reps)
 {
     __shared__ Q seg_prod[S][64];
+    const Rep &R = reps[blockIdx.z];
+    const Geom &g = R.g;
     const uint32_t ns3 = (uint32_t)g.nx * g.ny * g.nz;
+    if (blockIdx.x * 64u >= ns3) return;  // uniform: whole workgroup
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t xs = blockIdx.x * 64u + (uint32_t)lane;
     Q P{1.0f, 0.0f, 0.0f, 0.0f};
@@ -271,7 +312,7 @@ __global__ __launch_bounds__(512) void polyakov_kernel(const float *__restrict__
         const uint32_t h0 = xs >> 1;
         for (int t = t0; t < t0 + len; ++t) {
             // site xs + ns3 t has half-site (xs >> 1) + t ns3/2 because ns3 is even
-            const Q U = load_q(links, g.vh, 3, (pbase + t) & 1, h0 + (uint32_t)t * (ns3 >> 1));
+            const Q U = ldq(R.links, g.vh, 3, (pbase + t) & 1, h0 + (uint32_t)t * (ns3 >> 1));
             P = qmul(P, U);
         }
     }
@@ -284,52 +325,58 @@ __global__ __launch_bounds__(512) void polyakov_kernel(const float *__restrict__
         for (int k = 1; k < S; ++k) T = qmul(T, seg_prod[k][lane]);
         acc = (double)T.w;
     }
-    block_accumulate(acc, sums.acc, ACC_POLY);
+    block_accumulate(acc, R.acc, ACC_POLY, blockIdx.x);
 }
 
 // ---------------------------------------------------------- bookkeeping
-// Launched with kBuckets threads.
-__global__ __launch_bounds__(kBuckets) void take_kernel(Sums sums, int which, double scale,
-                                                        double *__restrict__ out)
+// All launched with grid (1, 1, replica) and kBuckets threads.
+__global__ __launch_bounds__(kBuckets) void take_kernel(const Rep *__restrict__ reps, int flags)
 {
-    const unsigned long long t = take_total(sums.acc, which);
+    const Rep &R = reps[blockIdx.z];
+    const unsigned long long tp = (flags & 1) ? take_total(R.acc, ACC_PLAQ) : 0ull;
+    const unsigned long long tl = (flags & 2) ? take_total(R.acc, ACC_POLY) : 0ull;
     if (threadIdx.x == 0) {
-        const double v = from_fixed(t) * scale;
-        out[0] = v;
-        out[1] = fabs(v);
+        const Geom &g = R.g;
+        if (flags & 1) R.results[R_PLAQ] = from_fixed(tp) / (12.0 * (double)g.vh);
+        if (flags & 2) {
+            const double l = from_fixed(tl) / ((double)g.nx * g.ny * g.nz);
+            R.results[R_POLY_SIGNED] = l;
+            R.results[R_POLY_ABS] = fabs(l);
+        }
     }
 }
 
-// End of a sweep (kBuckets threads): flags 1 plaquette, 2 Polyakov, 4 append
-// a history row; accumulators reset, sweep counter advanced.
-__global__ __launch_bounds__(kBuckets) void sweep_end_kernel(Sums sums, int flags,
-                                                             double plaq_scale, double poly_scale,
+__global__ __launch_bounds__(kBuckets) void sweep_end_kernel(const Rep *__restrict__ reps,
+                                                             int nrep, int flags,
                                                              double *__restrict__ hist)
 {
-    const unsigned long long tp = take_total(sums.acc, ACC_PLAQ);
-    const unsigned long long tl = take_total(sums.acc, ACC_POLY);
+    const Rep &R = reps[blockIdx.z];
+    const unsigned long long tp = take_total(R.acc, ACC_PLAQ);
+    const unsigned long long tl = take_total(R.acc, ACC_POLY);
     if (threadIdx.x == 0) {
-        Counters *c = sums.cnt;
+        Counters *c = R.cnt;
+        const Geom &g = R.g;
         if ((flags & 4) && hist) {
             const uint32_t m = c->meas_idx;
-            const double p = (flags & 1) ? from_fixed(tp) * plaq_scale : 0.0;
-            const double l = (flags & 2) ? from_fixed(tl) * poly_scale : 0.0;
-            hist[3 * (size_t)m + 0] = p;
-            hist[3 * (size_t)m + 1] = l;
-            hist[3 * (size_t)m + 2] = fabs(l);
+            const double p = (flags & 1) ? from_fixed(tp) / (12.0 * (double)g.vh) : 0.0;
+            const double l = (flags & 2) ? from_fixed(tl) / ((double)g.nx * g.ny * g.nz) : 0.0;
+            double *row = hist + 3 * ((size_t)m * nrep + blockIdx.z);
+            row[0] = p;
+            row[1] = l;
+            row[2] = fabs(l);
             c->meas_idx = m + 1;
         }
         c->sweep = c->sweep + 1;
     }
 }
 
-// Proposal / accept counts of learned passes (kBuckets threads).
-__global__ __launch_bounds__(kBuckets) void counts_kernel(Sums sums, unsigned long long *out,
+__global__ __launch_bounds__(kBuckets) void counts_kernel(const Rep *__restrict__ reps,
                                                           int reset)
 {
     __shared__ unsigned long long part[2][kBuckets / 64];
+    const Rep &R = reps[blockIdx.z];
     for (int a = 0; a < 2; ++a) {
-        unsigned long long *p = bucket(sums.acc, ACC_PROPOSED + a, threadIdx.x);
+        unsigned long long *p = bucket(R.acc, ACC_PROPOSED + a, threadIdx.x);
         unsigned long long v = *p;
         if (reset) *p = 0ull;
 #pragma unroll
@@ -337,61 +384,66 @@ __global__ __launch_bounds__(kBuckets) void counts_kernel(Sums sums, unsigned lo
         if ((threadIdx.x & 63) == 0) part[a][threadIdx.x >> 6] = v;
     }
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+        unsigned long long *out = reinterpret_cast<unsigned long long *>(R.results + R_COUNTS);
         for (int a = 0; a < 2; ++a) {
             unsigned long long t = 0ull;
             for (int i = 0; i < kBuckets / 64; ++i) t += part[a][i];
             out[a] = t;
         }
+    }
 }
 
-// which: 1 set sweep, 2 set meas_idx, 4 zero the accumulators (kBuckets threads).
-__global__ __launch_bounds__(kBuckets) void set_counter_kernel(Sums sums, uint32_t sweep,
-                                                               uint32_t meas, int which)
+__global__ __launch_bounds__(kBuckets) void set_counter_kernel(const Rep *__restrict__ reps,
+                                                               uint32_t sweep, uint32_t meas,
+                                                               int which)
 {
+    const Rep &R = reps[blockIdx.z];
     if (which & 4)
-        for (int a = 0; a < kNumAcc; ++a) *bucket(sums.acc, a, threadIdx.x) = 0ull;
+        for (int a = 0; a < kNumAcc; ++a) *bucket(R.acc, a, threadIdx.x) = 0ull;
     else if (which & 8)
-        for (int a = 0; a < 2; ++a) *bucket(sums.acc, a, threadIdx.x) = 0ull;
+        for (int a = ACC_PROPOSED; a < kNumAcc; ++a) *bucket(R.acc, a, threadIdx.x) = 0ull;
     if (threadIdx.x == 0) {
-        if (which & 1) sums.cnt->sweep = sweep;
-        if (which & 2) sums.cnt->meas_idx = meas;
+        if (which & 1) R.cnt->sweep = sweep;
+        if (which & 2) R.cnt->meas_idx = meas;
     }
 }
 
 // --------------------------------------------------------------- reunit
-// U <- U / |U| with |U|^2 accumulated in FP64.
-__global__ __launch_bounds__(256) void reunit_kernel(float *__restrict__ links, Geom g)
+// grid (blocks over V/2, 8, replica).  U <- U / |U|, |U|^2 in FP64.
+__global__ __launch_bounds__(256) void reunit_kernel(const Rep *__restrict__ reps)
 {
+    const Rep &R = reps[blockIdx.z];
     const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    const int mp = blockIdx.y;
-    if (h >= g.vh) return;
-    const int mu = mp >> 1, par = mp & 1;
-    const Q q = load_q(links, g.vh, mu, par, h);
+    if (h >= R.g.vh) return;
+    const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
+    const Q q = ldq(R.links, R.g.vh, mu, par, h);
     const double n2 = (double)q.w * q.w + (double)q.x * q.x + (double)q.y * q.y +
                       (double)q.z * q.z;
     const double inv = 1.0 / sqrt(n2);
-    store_q(links, g.vh, mu, par, h,
-            Q{(float)(q.w * inv), (float)(q.x * inv), (float)(q.y * inv), (float)(q.z * inv)});
+    st(R.links, R.g.vh, mu, par, h,
+       Q{(float)(q.w * inv), (float)(q.x * inv), (float)(q.y * inv), (float)(q.z * inv)});
 }
 
 // ---------------------------------------------------------- gauge (tests)
-__global__ void gauge_gen_kernel(float4 *__restrict__ G, Geom g, uint32_t k0, uint32_t k1,
-                                 uint32_t replica)
+// Replica 0 only (G holds one field of gauge rotations).
+__global__ void gauge_gen_kernel(const Rep *__restrict__ reps, float4 *__restrict__ G,
+                                 uint32_t k0, uint32_t k1)
 {
+    const Rep &R = reps[0];
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= 2u * g.vh) return;
-    const Q q = haar_from_block(philox(s, 0u, word2(0u, TAG_GAUGE, replica), 0u, k0, k1));
+    if (s >= 2u * R.g.vh) return;
+    const Q q = haar_from_block(philox(s, 0u, word2(0u, TAG_GAUGE, R.replica), 0u, k0, k1));
     G[s] = make_float4(q.w, q.x, q.y, q.z);
 }
 
-__global__ void gauge_apply_kernel(float *__restrict__ links, Geom g,
-                                   const float4 *__restrict__ G)
+__global__ void gauge_apply_kernel(const Rep *__restrict__ reps, const float4 *__restrict__ G)
 {
+    const Rep &R = reps[0];
+    const Geom &g = R.g;
     const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    const int mp = blockIdx.y;
     if (h >= g.vh) return;
-    const int mu = mp >> 1, par = mp & 1;
+    const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
     int c[4];
     decode(g, h, par, c[0], c[1], c[2], c[3]);
     const uint32_t site = 2u * h + (uint32_t)(c[0] & 1);
@@ -399,9 +451,9 @@ __global__ void gauge_apply_kernel(float *__restrict__ links, Geom g,
     c[mu] = c[mu] + 1 == n[mu] ? 0 : c[mu] + 1;
     const uint32_t fsite = 2u * hidx(g, c[0], c[1], c[2], c[3]) + (uint32_t)(c[0] & 1);
     const float4 a = G[site], b = G[fsite];
-    const Q U = load_q(links, g.vh, mu, par, h);
+    const Q U = ldq(R.links, g.vh, mu, par, h);
     const Q r = qmul(qmul(Q{a.x, a.y, a.z, a.w}, U), qdag(Q{b.x, b.y, b.z, b.w}));
-    store_q(links, g.vh, mu, par, h, r);
+    st(R.links, g.vh, mu, par, h, r);
 }
 
 // ---------------------------------------------------------- test hooks
@@ -435,125 +487,117 @@ __global__ void test_links_kernel(const float4 *__restrict__ V, int64_t n, float
 inline uint32_t lo32(uint64_t v) { return (uint32_t)v; }
 inline uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
 inline unsigned nblk(uint64_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+inline unsigned round8(unsigned n) { return (n + 7u) & ~7u; }
 
 template <int MU, bool LEARNED>
-void launch_pass_mu(float *links, const Geom &g, int par, Sums c, float beta, uint64_t seed,
-                    uint32_t replica, bool measure, const float *table, const LaunchCfg &cfg,
-                    hipStream_t stream)
+void launch_pass_mu(const Ens &e, int par, uint64_t seed, bool measure, const float *table,
+                    const LaunchCfg &cfg, hipStream_t stream)
 {
-    const unsigned nb = nblk(g.vh, (unsigned)cfg.pass_block);
+    unsigned grid = e.total_blocks;
+    if (cfg.grid_cap && cfg.grid_cap < grid) grid = cfg.grid_cap & ~7u;
+    if (grid == 0) grid = 8;
     const int rev = cfg.snake ? par : 0;
     if (measure)
-        hipLaunchKernelGGL((pass_kernel<MU, true, LEARNED>), dim3(nb), dim3(cfg.pass_block), 0,
-                           stream, links, g, par, c, beta, lo32(seed), hi32(seed), replica,
+        hipLaunchKernelGGL((pass_kernel<MU, true, LEARNED>), dim3(grid), dim3(cfg.pass_block), 0,
+                           stream, e.reps, e.bmap, e.total_blocks, par, lo32(seed), hi32(seed),
                            (int)cfg.xcd_remap, rev, table);
     else
-        hipLaunchKernelGGL((pass_kernel<MU, false, LEARNED>), dim3(nb), dim3(cfg.pass_block), 0,
-                           stream, links, g, par, c, beta, lo32(seed), hi32(seed), replica,
+        hipLaunchKernelGGL((pass_kernel<MU, false, LEARNED>), dim3(grid), dim3(cfg.pass_block), 0,
+                           stream, e.reps, e.bmap, e.total_blocks, par, lo32(seed), hi32(seed),
                            (int)cfg.xcd_remap, rev, table);
 }
 
 template <bool LEARNED>
-void launch_pass_l(float *links, const Geom &g, int mu, int par, Sums c, float beta,
-                   uint64_t seed, uint32_t replica, bool measure, const float *table,
-                   const LaunchCfg &cfg, hipStream_t stream)
+void launch_pass_l(const Ens &e, int mu, int par, uint64_t seed, bool measure,
+                   const float *table, const LaunchCfg &cfg, hipStream_t stream)
 {
     switch (mu) {
-    case 0: launch_pass_mu<0, LEARNED>(links, g, par, c, beta, seed, replica, measure, table, cfg, stream); break;
-    case 1: launch_pass_mu<1, LEARNED>(links, g, par, c, beta, seed, replica, measure, table, cfg, stream); break;
-    case 2: launch_pass_mu<2, LEARNED>(links, g, par, c, beta, seed, replica, measure, table, cfg, stream); break;
-    default: launch_pass_mu<3, LEARNED>(links, g, par, c, beta, seed, replica, measure, table, cfg, stream); break;
+    case 0: launch_pass_mu<0, LEARNED>(e, par, seed, measure, table, cfg, stream); break;
+    case 1: launch_pass_mu<1, LEARNED>(e, par, seed, measure, table, cfg, stream); break;
+    case 2: launch_pass_mu<2, LEARNED>(e, par, seed, measure, table, cfg, stream); break;
+    default: launch_pass_mu<3, LEARNED>(e, par, seed, measure, table, cfg, stream); break;
     }
 }
 
 }  // namespace
 
-hipError_t launch_init(float *links, const Geom &g, int start, uint64_t seed, uint32_t replica,
-                       hipStream_t stream)
+hipError_t launch_init(const Ens &e, const int *starts_dev, uint64_t seed, hipStream_t stream)
 {
-    dim3 grid(nblk(g.vh, 256), 8);
-    hipLaunchKernelGGL(init_kernel, grid, dim3(256), 0, stream, links, g, start, lo32(seed),
-                       hi32(seed), replica);
+    hipLaunchKernelGGL(init_kernel, dim3(nblk(e.max_vh, 256), 8, e.nrep), dim3(256), 0, stream,
+                       e.reps, starts_dev, lo32(seed), hi32(seed));
     return hipGetLastError();
 }
 
-int pass_grid(const Geom &g, const LaunchCfg &cfg) { return (int)nblk(g.vh, cfg.pass_block); }
-
-hipError_t launch_pass(float *links, const Geom &g, int mu, int par, Sums c, float beta,
-                       uint64_t seed, uint32_t replica, bool measure, const float *table,
-                       const LaunchCfg &cfg, hipStream_t stream)
+hipError_t launch_pass(const Ens &e, int mu, int par, uint64_t seed, bool measure,
+                       const float *table, const LaunchCfg &cfg, hipStream_t stream)
 {
     if (table)
-        launch_pass_l<true>(links, g, mu, par, c, beta, seed, replica, measure, table, cfg, stream);
+        launch_pass_l<true>(e, mu, par, seed, measure, table, cfg, stream);
     else
-        launch_pass_l<false>(links, g, mu, par, c, beta, seed, replica, measure, nullptr, cfg,
-                             stream);
+        launch_pass_l<false>(e, mu, par, seed, measure, nullptr, cfg, stream);
     return hipGetLastError();
 }
 
-hipError_t launch_counts(Sums c, unsigned long long *out, int reset, hipStream_t stream)
+hipError_t launch_plaquette(const Ens &e, hipStream_t stream)
 {
-    hipLaunchKernelGGL(counts_kernel, dim3(1), dim3(kBuckets), 0, stream, c, out, reset);
+    hipLaunchKernelGGL(plaquette_kernel, dim3(round8(nblk(2ull * e.max_vh, 256)), 1, e.nrep),
+                       dim3(256), 0, stream, e.reps, 1);
     return hipGetLastError();
 }
 
-hipError_t launch_plaquette(const float *links, const Geom &g, Sums c, hipStream_t stream)
+hipError_t launch_polyakov(const Ens &e, hipStream_t stream)
 {
-    hipLaunchKernelGGL(plaquette_kernel, dim3(nblk(2ull * g.vh, 256)), dim3(256), 0, stream,
-                       links, g, c, 1);
-    return hipGetLastError();
-}
-
-hipError_t launch_polyakov(const float *links, const Geom &g, Sums c, hipStream_t stream)
-{
-    const uint64_t ns3 = (uint64_t)g.nx * g.ny * g.nz;
-    int S = 1;
-    while (S < 8 && g.nt % (2 * S) == 0) S *= 2;
-    const dim3 grid(nblk(ns3, 64)), block(64 * S);
-    switch (S) {
-    case 8: hipLaunchKernelGGL(polyakov_kernel<8>, grid, block, 0, stream, links, g, c); break;
-    case 4: hipLaunchKernelGGL(polyakov_kernel<4>, grid, block, 0, stream, links, g, c); break;
-    case 2: hipLaunchKernelGGL(polyakov_kernel<2>, grid, block, 0, stream, links, g, c); break;
-    default: hipLaunchKernelGGL(polyakov_kernel<1>, grid, block, 0, stream, links, g, c); break;
+    const dim3 grid(nblk(e.max_ns3, 64), 1, e.nrep), block(64 * e.poly_s);
+    switch (e.poly_s) {
+    case 8: hipLaunchKernelGGL(polyakov_kernel<8>, grid, block, 0, stream, e.reps); break;
+    case 4: hipLaunchKernelGGL(polyakov_kernel<4>, grid, block, 0, stream, e.reps); break;
+    case 2: hipLaunchKernelGGL(polyakov_kernel<2>, grid, block, 0, stream, e.reps); break;
+    default: hipLaunchKernelGGL(polyakov_kernel<1>, grid, block, 0, stream, e.reps); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_take(Sums c, int which, double scale, double *out, hipStream_t stream)
+hipError_t launch_take(const Ens &e, int flags, hipStream_t stream)
 {
-    hipLaunchKernelGGL(take_kernel, dim3(1), dim3(kBuckets), 0, stream, c, which, scale, out);
+    hipLaunchKernelGGL(take_kernel, dim3(1, 1, e.nrep), dim3(kBuckets), 0, stream, e.reps, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_end(Sums c, int flags, double plaq_scale, double poly_scale,
-                            double *hist, hipStream_t stream)
+hipError_t launch_sweep_end(const Ens &e, int flags, double *hist, hipStream_t stream)
 {
-    hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(kBuckets), 0, stream, c, flags, plaq_scale,
-                       poly_scale, hist);
+    hipLaunchKernelGGL(sweep_end_kernel, dim3(1, 1, e.nrep), dim3(kBuckets), 0, stream, e.reps,
+                       e.nrep, flags, hist);
     return hipGetLastError();
 }
 
-hipError_t launch_set_counter(Sums c, uint32_t sweep, uint32_t meas, int which,
+hipError_t launch_counts(const Ens &e, int reset, hipStream_t stream)
+{
+    hipLaunchKernelGGL(counts_kernel, dim3(1, 1, e.nrep), dim3(kBuckets), 0, stream, e.reps,
+                       reset);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_counter(const Ens &e, uint32_t sweep, uint32_t meas, int which,
                               hipStream_t stream)
 {
-    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(kBuckets), 0, stream, c, sweep, meas,
-                       which);
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1, 1, e.nrep), dim3(kBuckets), 0, stream, e.reps,
+                       sweep, meas, which);
     return hipGetLastError();
 }
 
-hipError_t launch_reunitarize(float *links, const Geom &g, hipStream_t stream)
+hipError_t launch_reunitarize(const Ens &e, hipStream_t stream)
 {
-    hipLaunchKernelGGL(reunit_kernel, dim3(nblk(g.vh, 256), 8), dim3(256), 0, stream, links, g);
+    hipLaunchKernelGGL(reunit_kernel, dim3(nblk(e.max_vh, 256), 8, e.nrep), dim3(256), 0, stream,
+                       e.reps);
     return hipGetLastError();
 }
 
-hipError_t launch_gauge(float *links, const Geom &g, float *G, uint64_t seed, uint32_t replica,
-                        hipStream_t stream)
+hipError_t launch_gauge(const Ens &e, float *G, uint64_t seed, hipStream_t stream)
 {
-    hipLaunchKernelGGL(gauge_gen_kernel, dim3(nblk(2ull * g.vh, 256)), dim3(256), 0, stream,
-                       (float4 *)G, g, lo32(seed), hi32(seed), replica);
-    hipLaunchKernelGGL(gauge_apply_kernel, dim3(nblk(g.vh, 256), 8), dim3(256), 0, stream, links,
-                       g, (const float4 *)G);
+    hipLaunchKernelGGL(gauge_gen_kernel, dim3(nblk(2ull * e.max_vh, 256)), dim3(256), 0, stream,
+                       e.reps, (float4 *)G, lo32(seed), hi32(seed));
+    hipLaunchKernelGGL(gauge_apply_kernel, dim3(nblk(e.max_vh, 256), 8), dim3(256), 0, stream,
+                       e.reps, (const float4 *)G);
     return hipGetLastError();
 }
 

@@ -1,10 +1,13 @@
-// su2_runtime.cpp -- C ABI of libsu2: contexts, argument checks, memory,
-// the sweep schedule (Sec. 4: per direction, even then odd sites) and the
-// measurement plumbing around the gfx950 kernels.
+// su2_runtime.cpp -- C ABI of libsu2: ensembles of lattices (a single lattice
+// is an ensemble of one), argument checks, memory, the sweep schedule (Sec. 4:
+// per direction, even sites then odd sites), measurements, hipGraph capture of
+// sweeps and the launch autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -27,34 +30,6 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 using namespace su2rt;
 
-struct su2_ctx {
-    int32_t dims[4];
-    Geom g;
-    int64_t volume;
-    double beta;
-    uint64_t seed;
-    uint32_t replica;
-    uint32_t sweep;  // host mirror of the device sweep counter
-    float *links;
-    size_t links_bytes;
-    unsigned char *scratch;
-    size_t scratch_bytes;
-    bool own_mem;
-    bool own_stream;
-    hipStream_t stream;
-    LaunchCfg cfg;
-    const float *table = nullptr;  // learned-proposal table (device), owned by an su2_nn
-
-    Counters *counters() { return reinterpret_cast<Counters *>(scratch + kCountersOff); }
-    Sums sums()
-    {
-        return Sums{counters(), reinterpret_cast<unsigned long long *>(scratch + kAccOff)};
-    }
-    double *results() { return reinterpret_cast<double *>(scratch + kResultsOff); }
-};
-
-namespace {
-
 #define HIP_TRY(expr)                                                                   \
     do {                                                                                \
         hipError_t e_ = (expr);                                                         \
@@ -63,6 +38,8 @@ namespace {
             return SU2_EHIP;                                                            \
         }                                                                               \
     } while (0)
+
+namespace {
 
 int fail(int code, const std::string &msg)
 {
@@ -140,7 +117,519 @@ bool geom_selfcheck(const Geom &g)
     return true;
 }
 
-size_t scratch_bytes_for(int64_t) { return kScratchBytes; }
+// tile 0 keeps `cur`; else a power of two (the geometry clips it to a divisor).
+int lg_of_tile(int tile, uint32_t cur, uint32_t *out)
+{
+    if (tile == 0) {
+        *out = cur;
+        return SU2_OK;
+    }
+    if (tile < 0 || (tile & (tile - 1)) || tile > 256)
+        return fail(SU2_EINVAL, "tile sizes must be powers of two <= 256");
+    uint32_t l = 0;
+    while ((1 << l) < tile) ++l;
+    *out = l;
+    return SU2_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int64_t volume_of(const int32_t *d) { return (int64_t)d[0] * d[1] * d[2] * d[3]; }
+
+}  // namespace
+
+// ================================================================ Ensemble
+// n lattices (replicas) with their own extents and couplings, run by the same
+// launches.  Device scratch layout: [descriptors][pass workgroup -> replica map
+// (n > 1)][per replica: counters, accumulators, result slots].
+class Ensemble {
+public:
+    int n = 0;
+    std::vector<std::array<int32_t, 4>> dims;
+    std::vector<double> beta;
+    std::vector<uint32_t> replica;
+    std::vector<float *> links;
+    std::vector<Geom> geom;
+    std::vector<uint32_t> first_block, nblocks;
+    uint32_t total_blocks = 0, max_vh = 0, max_ns3 = 0;
+    int poly_s = 1;
+    float *pool = nullptr;
+    bool own_pool = false;
+    unsigned char *scratch = nullptr;
+    bool own_scratch = false;
+    size_t bmap_off = 0, rep_off = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t seed = 0;
+    uint32_t sweep = 0;  // host mirror of the (common) sweep counter
+    LaunchCfg cfg;
+    uint32_t lg_tz = 3, lg_tt = 3;
+    const float *table = nullptr;
+    // captured sweeps
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int32_t g_nsweeps = 0;
+
+    static size_t descr_bytes(int n) { return align_up((size_t)n * sizeof(Rep), 256); }
+    static size_t bmap_bytes(int n, const std::vector<std::array<int32_t, 4>> &d)
+    {
+        if (n <= 1) return 0;
+        size_t blocks = 0;  // worst case: 64-thread workgroups
+        for (auto &x : d) blocks += align_up((size_t)(volume_of(x.data()) / 2 + 63) / 64, 8);
+        return align_up(blocks * 4, 256);
+    }
+    static size_t rep_bytes() { return align_up(kRepScratch, 256); }
+    static size_t scratch_need(int n, const std::vector<std::array<int32_t, 4>> &d)
+    {
+        return descr_bytes(n) + bmap_bytes(n, d) + (size_t)n * rep_bytes();
+    }
+
+    Rep *d_reps() const { return reinterpret_cast<Rep *>(scratch); }
+    uint32_t *d_bmap() const
+    {
+        return n > 1 ? reinterpret_cast<uint32_t *>(scratch + bmap_off) : nullptr;
+    }
+    unsigned char *rep_scratch(int r) const { return scratch + rep_off + (size_t)r * rep_bytes(); }
+    Counters *cnt(int r) const { return reinterpret_cast<Counters *>(rep_scratch(r)); }
+    unsigned long long *acc(int r) const
+    {
+        return reinterpret_cast<unsigned long long *>(rep_scratch(r) + sizeof(Counters));
+    }
+    double *results(int r) const
+    {
+        return reinterpret_cast<double *>(rep_scratch(r) + sizeof(Counters) + kAccBytes);
+    }
+
+    Ens ens() const
+    {
+        return Ens{d_reps(), d_bmap(), n, total_blocks, max_vh, max_ns3, poly_s};
+    }
+
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        g_nsweeps = 0;
+    }
+
+    // Geometry, workgroup ranges and descriptors (uploaded synchronously).
+    int upload()
+    {
+        drop_graph();
+        geom.resize(n);
+        first_block.resize(n);
+        nblocks.resize(n);
+        uint32_t fb = 0;
+        max_vh = max_ns3 = 0;
+        poly_s = 8;
+        for (int r = 0; r < n; ++r) {
+            geom[r] = make_geom(dims[r].data(), lg_tz, lg_tt);
+            if (!geom_selfcheck(geom[r]))
+                return fail(SU2_ERANGE, "index arithmetic self-check failed for these extents");
+            nblocks[r] = (geom[r].vh + cfg.pass_block - 1) / cfg.pass_block;
+            first_block[r] = fb;
+            fb += (nblocks[r] + 7u) & ~7u;
+            max_vh = std::max(max_vh, geom[r].vh);
+            max_ns3 = std::max(max_ns3, (uint32_t)(dims[r][0] * dims[r][1] * dims[r][2]));
+            while (dims[r][3] % poly_s) poly_s /= 2;
+        }
+        total_blocks = n > 1 ? fb : nblocks[0];
+        std::vector<Rep> h(n);
+        for (int r = 0; r < n; ++r) {
+            h[r].g = geom[r];
+            h[r].links = links[r];
+            h[r].cnt = cnt(r);
+            h[r].acc = acc(r);
+            h[r].results = results(r);
+            h[r].beta = (float)beta[r];
+            h[r].replica = replica[r];
+            h[r].first_block = first_block[r];
+            h[r].nblocks = nblocks[r];
+        }
+        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipMemcpy(d_reps(), h.data(), n * sizeof(Rep), hipMemcpyHostToDevice));
+        if (n > 1) {
+            std::vector<uint32_t> map(total_blocks);
+            for (int r = 0; r < n; ++r) {
+                const uint32_t end = r + 1 < n ? first_block[r + 1] : total_blocks;
+                for (uint32_t b = first_block[r]; b < end; ++b) map[b] = (uint32_t)r;
+            }
+            HIP_TRY(hipMemcpy(d_bmap(), map.data(), map.size() * 4, hipMemcpyHostToDevice));
+        }
+        return SU2_OK;
+    }
+
+    int init(const std::vector<int> &starts)
+    {
+        int *d = nullptr;
+        HIP_TRY(hipMalloc(&d, n * sizeof(int)));
+        hipError_t e = hipMemcpy(d, starts.data(), n * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_set_counter(ens(), 0, 0, 7, stream);
+        if (e == hipSuccess) e = launch_init(ens(), d, seed, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        (void)hipFree(d);
+        if (e != hipSuccess) return fail(SU2_EHIP, std::string("init: ") + hipGetErrorString(e));
+        sweep = 0;
+        return SU2_OK;
+    }
+
+    const float *mode_table(int mode, int *rc)
+    {
+        *rc = SU2_OK;
+        if (mode != SU2_KP && mode != SU2_LEARNED) *rc = fail(SU2_EINVAL, "unknown mode");
+        else if (mode == SU2_LEARNED && !table)
+            *rc = fail(SU2_ESTATE, "no learned proposal loaded (su2_set_proposal)");
+        return mode == SU2_LEARNED ? table : nullptr;
+    }
+
+    // Enqueue n sweeps; the sweep index the device uses comes from the
+    // device counters, and the host mirror decides the reunitarisation
+    // schedule.  hist rows restart at 0 for this call.
+    int enqueue(int32_t ns, int mode, int32_t reunit_every, int meas, double *hist,
+                bool reset_rows = true)
+    {
+        int rc;
+        const float *tab = mode_table(mode, &rc);
+        if (rc) return rc;
+        if (hist && reset_rows) HIP_TRY(launch_set_counter(ens(), 0, 0, 2, stream));
+        for (int32_t i = 0; i < ns; ++i) {
+            const uint32_t j = sweep + (uint32_t)i;
+            const bool reunit = reunit_every > 0 && ((j + 1u) % (uint32_t)reunit_every) == 0u;
+            const bool want_p = hist && (meas & SU2_MEAS_PLAQ);
+            const bool fused = want_p && !reunit;
+            for (int mu = 0; mu < 4; ++mu)
+                for (int par = 0; par < 2; ++par)
+                    HIP_TRY(launch_pass(ens(), mu, par, seed, fused && par == 1 && mu >= 1, tab,
+                                        cfg, stream));
+            if (reunit) HIP_TRY(launch_reunitarize(ens(), stream));
+            if (want_p && !fused) HIP_TRY(launch_plaquette(ens(), stream));
+            const bool want_l = hist && (meas & SU2_MEAS_POLY);
+            if (want_l) HIP_TRY(launch_polyakov(ens(), stream));
+            const int flags = (want_p ? 1 : 0) | (want_l ? 2 : 0) | (hist ? 4 : 0);
+            HIP_TRY(launch_sweep_end(ens(), flags, hist, stream));
+        }
+        sweep += (uint32_t)ns;
+        return SU2_OK;
+    }
+
+    // Capture `ns` sweeps (as enqueue) into a graph replayed by replay().  The
+    // history rows continue across replays (the row index lives on the device).
+    int capture(int32_t ns, int mode, int32_t reunit_every, int meas, double *hist)
+    {
+        if (ns <= 0) return fail(SU2_EINVAL, "nsweeps must be > 0");
+        if (reunit_every > 0 && (ns % reunit_every || sweep % (uint32_t)reunit_every))
+            return fail(SU2_EINVAL, "with reunitarisation the captured sweeps must span whole "
+                                    "periods starting at a period boundary");
+        int rc;
+        mode_table(mode, &rc);
+        if (rc) return rc;
+        if (!stream) return fail(SU2_ESTATE, "graph capture needs a non-null stream");
+        drop_graph();
+        if (hist) HIP_TRY(launch_set_counter(ens(), 0, 0, 2, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const uint32_t s0 = sweep;
+        HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue(ns, mode, reunit_every, meas, hist, false);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(stream, &gr);
+        sweep = s0;  // capturing ran nothing
+        if (rc) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return fail(SU2_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            return fail(SU2_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        graph = gr;
+        g_nsweeps = ns;
+        return SU2_OK;
+    }
+
+    int replay(int32_t count)
+    {
+        if (!gexec) return fail(SU2_ESTATE, "no captured sweeps");
+        if (count < 0) return fail(SU2_EINVAL, "count must be >= 0");
+        for (int32_t i = 0; i < count; ++i) HIP_TRY(hipGraphLaunch(gexec, stream));
+        sweep += (uint32_t)(count * g_nsweeps);
+        return SU2_OK;
+    }
+
+    // flags 1 plaquette, 2 Polyakov; results into host arrays (n entries).
+    int observe(int flags, double *plaq, double *poly_s, double *poly_a)
+    {
+        if (flags & 1) HIP_TRY(launch_plaquette(ens(), stream));
+        if (flags & 2) HIP_TRY(launch_polyakov(ens(), stream));
+        HIP_TRY(launch_take(ens(), flags, stream));
+        std::vector<double> v(3 * (size_t)n);
+        for (int r = 0; r < n; ++r)
+            HIP_TRY(hipMemcpyAsync(&v[3 * r], results(r), 3 * sizeof(double),
+                                   hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (int r = 0; r < n; ++r) {
+            if (plaq) plaq[r] = v[3 * r + R_PLAQ];
+            if (poly_s) poly_s[r] = v[3 * r + R_POLY_SIGNED];
+            if (poly_a) poly_a[r] = v[3 * r + R_POLY_ABS];
+        }
+        return SU2_OK;
+    }
+
+    int counts(int reset, uint64_t *proposed, uint64_t *accepted)
+    {
+        HIP_TRY(launch_counts(ens(), reset, stream));
+        std::vector<unsigned long long> v(2 * (size_t)n);
+        for (int r = 0; r < n; ++r)
+            HIP_TRY(hipMemcpyAsync(&v[2 * r], results(r) + R_COUNTS, 2 * sizeof(uint64_t),
+                                   hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (int r = 0; r < n; ++r) {
+            if (proposed) proposed[r] = v[2 * r];
+            if (accepted) accepted[r] = v[2 * r + 1];
+        }
+        return SU2_OK;
+    }
+
+    int get_links(int r, float *host)
+    {
+        const int32_t *d = dims[r].data();
+        const int64_t V = volume_of(d), vh = V / 2;
+        std::vector<float> planes((size_t)V * 16);
+        HIP_TRY(hipMemcpyAsync(planes.data(), links[r], planes.size() * 4, hipMemcpyDeviceToHost,
+                               stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (int64_t s = 0; s < V; ++s) {
+            int64_t q = s;
+            const int x = (int)(q % d[0]);
+            q /= d[0];
+            const int y = (int)(q % d[1]);
+            q /= d[1];
+            const int z = (int)(q % d[2]);
+            const int t = (int)(q / d[2]);
+            const int par = (x + y + z + t) & 1;
+            for (int mu = 0; mu < 4; ++mu)
+                for (int k = 0; k < 4; ++k)
+                    host[(s * 4 + mu) * 4 + k] = planes[((mu * 2 + par) * 4 + k) * vh + (s >> 1)];
+        }
+        return SU2_OK;
+    }
+
+    int set_links(int r, const float *host)
+    {
+        const int32_t *d = dims[r].data();
+        const int64_t V = volume_of(d), vh = V / 2;
+        std::vector<float> planes((size_t)V * 16);
+        for (int64_t s = 0; s < V; ++s) {
+            int64_t q = s;
+            const int x = (int)(q % d[0]);
+            q /= d[0];
+            const int y = (int)(q % d[1]);
+            q /= d[1];
+            const int z = (int)(q % d[2]);
+            const int t = (int)(q / d[2]);
+            const int par = (x + y + z + t) & 1;
+            for (int mu = 0; mu < 4; ++mu)
+                for (int k = 0; k < 4; ++k)
+                    planes[((mu * 2 + par) * 4 + k) * vh + (s >> 1)] = host[(s * 4 + mu) * 4 + k];
+        }
+        HIP_TRY(hipMemcpyAsync(links[r], planes.data(), planes.size() * 4, hipMemcpyHostToDevice,
+                               stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return SU2_OK;
+    }
+
+    int set_sweep(uint32_t s)
+    {
+        HIP_TRY(launch_set_counter(ens(), s, 0, 1, stream));
+        sweep = s;
+        return SU2_OK;
+    }
+
+    int set_launch(int block, int flags, int tile_z, int tile_t, int grid_cap)
+    {
+        if (block < 64 || block > 256 || (block % 64) != 0)
+            return fail(SU2_EINVAL, "block must be 64, 128, 192 or 256");
+        if (grid_cap < 0) return fail(SU2_EINVAL, "grid_cap must be >= 0");
+        uint32_t lz, lt;
+        int rc;
+        if ((rc = lg_of_tile(tile_z, lg_tz, &lz))) return rc;
+        if ((rc = lg_of_tile(tile_t, lg_tt, &lt))) return rc;
+        cfg.pass_block = block;
+        cfg.xcd_remap = (flags & 1) != 0;
+        cfg.snake = (flags & 2) == 0;
+        cfg.grid_cap = (uint32_t)grid_cap;
+        lg_tz = lz;
+        lg_tt = lt;
+        return upload();
+    }
+
+    // Time candidate launch configurations on the ensemble itself (state saved
+    // and restored), keep the fastest; cache by device and extents.
+    int autotune(const char *cache_path, int mode, double *best_us);
+
+    void release()
+    {
+        drop_graph();
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (own_pool && pool) (void)hipFree(pool);
+        if (own_scratch && scratch) (void)hipFree(scratch);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        pool = nullptr;
+        scratch = nullptr;
+        stream = nullptr;
+    }
+};
+
+namespace {
+
+std::string tune_key(const Ensemble &E, int mode)
+{
+    hipDeviceProp_t prop;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::string k = "dev=";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) k += prop.gcnArchName;
+    std::vector<std::array<int32_t, 4>> d = E.dims;
+    std::sort(d.begin(), d.end());
+    k += ";mode=" + std::to_string(mode) + ";n=" + std::to_string(E.n) + ";dims=";
+    for (auto &x : d)
+        k += std::to_string(x[0]) + "x" + std::to_string(x[1]) + "x" + std::to_string(x[2]) +
+             "x" + std::to_string(x[3]) + ",";
+    return k;
+}
+
+struct TuneEntry {
+    int block, flags, tz, tt, grid;
+    double us;
+};
+
+bool cache_lookup(const char *path, const std::string &key, TuneEntry *e)
+{
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    std::vector<char> line(1 << 16);
+    std::vector<char> k(1 << 16);
+    bool found = false;
+    while (std::fgets(line.data(), (int)line.size(), f)) {
+        TuneEntry t;
+        if (std::sscanf(line.data(),
+                        "{\"key\": \"%65000[^\"]\", \"block\": %d, \"flags\": %d, \"tile_z\": %d, "
+                        "\"tile_t\": %d, \"grid_cap\": %d, \"us_per_sweep\": %lf}",
+                        k.data(), &t.block, &t.flags, &t.tz, &t.tt, &t.grid, &t.us) == 7 &&
+            key == k.data()) {
+            *e = t;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const TuneEntry &t)
+{
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"block\": %d, \"flags\": %d, \"tile_z\": %d, \"tile_t\": %d, "
+                 "\"grid_cap\": %d, \"us_per_sweep\": %.3f}\n",
+                 key.c_str(), t.block, t.flags, t.tz, t.tt, t.grid, t.us);
+    std::fclose(f);
+}
+
+}  // namespace
+
+int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
+{
+    int rc;
+    mode_table(mode, &rc);
+    if (rc) return rc;
+    const std::string key = tune_key(*this, mode);
+    TuneEntry best{};
+    if (cache_lookup(cache_path, key, &best)) {
+        if (best_us) *best_us = best.us;
+        return set_launch(best.block, best.flags, best.tz, best.tt, best.grid);
+    }
+    // snapshot of the state the trial sweeps change
+    std::vector<void *> saved(n, nullptr);
+    std::vector<Counters> cnt_saved(n);
+    for (int r = 0; r < n; ++r) {
+        const size_t b = (size_t)volume_of(dims[r].data()) * 64;
+        HIP_TRY(hipMalloc(&saved[r], b));
+        HIP_TRY(hipMemcpyAsync(saved[r], links[r], b, hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(&cnt_saved[r], cnt(r), sizeof(Counters), hipMemcpyDeviceToHost,
+                               stream));
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    const uint32_t sweep0 = sweep;
+    const int blocks[] = {256, 128};
+    const int flagset[] = {1, 3};  // remap + alternating order, remap only
+    const int tiles[][2] = {{8, 8}, {4, 8}, {2, 16}, {1, 1}, {16, 16}};
+    const int grids[] = {0, 2048, 4096};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    best.us = 1e30;
+    const int trial_sweeps = 2;
+    for (int b : blocks) {
+        for (int fl : flagset) {
+            for (auto &t : tiles) {
+                for (int gc : grids) {
+                    if ((rc = set_launch(b, fl, t[0], t[1], gc))) break;
+                    if ((rc = enqueue(1, mode, 0, 0, nullptr))) break;  // warm-up
+                    HIP_TRY(hipEventRecord(e0, stream));
+                    if ((rc = enqueue(trial_sweeps, mode, 0, 0, nullptr))) break;
+                    HIP_TRY(hipEventRecord(e1, stream));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    const double us = 1e3 * ms / trial_sweeps;
+                    if (us < best.us) best = TuneEntry{b, fl, t[0], t[1], gc, us};
+                }
+                if (rc) break;
+            }
+            if (rc) break;
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // restore the state whatever happened
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < n; ++r) {
+        const size_t b = (size_t)volume_of(dims[r].data()) * 64;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(links[r], saved[r], b, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(cnt(r), &cnt_saved[r], sizeof(Counters), hipMemcpyHostToDevice,
+                               stream);
+    }
+    if (e == hipSuccess) e = launch_set_counter(ens(), 0, 0, 4, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    for (void *p : saved) (void)hipFree(p);
+    sweep = sweep0;
+    if (e != hipSuccess) return fail(SU2_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    if (rc) return rc;
+    cache_store(cache_path, key, best);
+    if (best_us) *best_us = best.us;
+    return set_launch(best.block, best.flags, best.tz, best.tt, best.grid);
+}
+
+// ===================================================== single lattice (C ABI)
+struct su2_ctx {
+    Ensemble E;
+};
+
+struct su2_batch {
+    Ensemble E;
+};
+
+namespace {
 
 int check_ctx(su2_ctx *c)
 {
@@ -148,38 +637,9 @@ int check_ctx(su2_ctx *c)
     return SU2_OK;
 }
 
-// The sweep index the device uses is read from the device counter; keep the
-// host mirror in step.
-int enqueue_sweeps(su2_ctx *c, int32_t n, int mode, int32_t reunit_every, int meas,
-                   double *hist)
+int check_batch(su2_batch *b)
 {
-    if (mode != SU2_KP && mode != SU2_LEARNED) return fail(SU2_EINVAL, "unknown mode");
-    if (mode == SU2_LEARNED && !c->table)
-        return fail(SU2_ESTATE, "no learned proposal loaded (su2_set_proposal)");
-    const float *table = mode == SU2_LEARNED ? c->table : nullptr;
-    const float beta = (float)c->beta;
-    const double inv6v = 1.0 / (6.0 * (double)c->volume);
-    const double inv_ns3 = 1.0 / ((double)c->dims[0] * c->dims[1] * c->dims[2]);
-    // history rows restart at 0 for this call
-    if (hist) HIP_TRY(launch_set_counter(c->sums(), 0, 0, 2, c->stream));
-    for (int32_t i = 0; i < n; ++i) {
-        const uint32_t j = c->sweep + (uint32_t)i;
-        const bool reunit = reunit_every > 0 && ((j + 1u) % (uint32_t)reunit_every) == 0u;
-        const bool want_p = hist && (meas & SU2_MEAS_PLAQ);
-        const bool fused = want_p && !reunit;
-        for (int mu = 0; mu < 4; ++mu)
-            for (int par = 0; par < 2; ++par)
-                HIP_TRY(launch_pass(c->links, c->g, mu, par, c->sums(), beta, c->seed,
-                                    c->replica, fused && par == 1 && mu >= 1, table, c->cfg,
-                                    c->stream));
-        if (reunit) HIP_TRY(launch_reunitarize(c->links, c->g, c->stream));
-        if (want_p && !fused) HIP_TRY(launch_plaquette(c->links, c->g, c->sums(), c->stream));
-        const bool want_l = hist && (meas & SU2_MEAS_POLY);
-        if (want_l) HIP_TRY(launch_polyakov(c->links, c->g, c->sums(), c->stream));
-        const int flags = (want_p ? 1 : 0) | (want_l ? 2 : 0) | (hist ? 4 : 0);
-        HIP_TRY(launch_sweep_end(c->sums(), flags, inv6v, inv_ns3, hist, c->stream));
-    }
-    c->sweep += (uint32_t)n;
+    if (!b) return fail(SU2_EINVAL, "batch is NULL");
     return SU2_OK;
 }
 
@@ -194,13 +654,14 @@ size_t su2_links_bytes(const int32_t dims[4])
     if (!dims) return 0;
     for (int i = 0; i < 4; ++i)
         if (dims[i] < 2 || (dims[i] & 1)) return 0;
-    return (size_t)64 * (size_t)dims[0] * dims[1] * dims[2] * dims[3];
+    return (size_t)64 * (size_t)volume_of(dims);
 }
 
 size_t su2_scratch_bytes(const int32_t dims[4])
 {
     if (!su2_links_bytes(dims)) return 0;
-    return scratch_bytes_for((int64_t)dims[0] * dims[1] * dims[2] * dims[3]);
+    std::vector<std::array<int32_t, 4>> d{{dims[0], dims[1], dims[2], dims[3]}};
+    return Ensemble::scratch_need(1, d);
 }
 
 static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed,
@@ -223,55 +684,39 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
     }
     su2_ctx *c = new (std::nothrow) su2_ctx();
     if (!c) return fail(SU2_ENOMEM, "host allocation failed");
-    std::memcpy(c->dims, dims, sizeof(c->dims));
-    c->g = make_geom(dims, 3, 3);
-    if (!geom_selfcheck(c->g)) {
-        delete c;
-        return fail(SU2_ERANGE, "index arithmetic self-check failed for these extents");
-    }
-    c->volume = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
-    c->beta = beta;
-    c->seed = seed;
-    c->replica = 0;
-    c->sweep = 0;
-    c->links_bytes = need_l;
-    c->scratch_bytes = need_s;
-    c->own_mem = !ext;
-    c->own_stream = false;
+    Ensemble &E = c->E;
+    E.n = 1;
+    E.dims = {{dims[0], dims[1], dims[2], dims[3]}};
+    E.beta = {beta};
+    E.replica = {0u};
+    E.seed = seed;
     if (ext) {
-        c->links = static_cast<float *>(links_dev);
-        c->scratch = static_cast<unsigned char *>(scratch_dev);
-        c->stream = static_cast<hipStream_t>(stream);
+        E.pool = static_cast<float *>(links_dev);
+        E.scratch = static_cast<unsigned char *>(scratch_dev);
+        E.stream = static_cast<hipStream_t>(stream);
     } else {
         void *l = nullptr, *s = nullptr;
         hipError_t e = hipMalloc(&l, need_l);
         if (e == hipSuccess) e = hipMalloc(&s, need_s);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
             if (l) (void)hipFree(l);
+            if (s) (void)hipFree(s);
             delete c;
             return fail(e == hipErrorOutOfMemory ? SU2_ENOMEM : SU2_EHIP,
-                        std::string("hipMalloc: ") + hipGetErrorString(e));
+                        std::string("allocation: ") + hipGetErrorString(e));
         }
-        c->links = static_cast<float *>(l);
-        c->scratch = static_cast<unsigned char *>(s);
-        hipStream_t st = nullptr;
-        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-        if (e != hipSuccess) {
-            (void)hipFree(l);
-            (void)hipFree(s);
-            delete c;
-            return fail(SU2_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
-        }
-        c->stream = st;
-        c->own_stream = true;
+        E.pool = static_cast<float *>(l);
+        E.scratch = static_cast<unsigned char *>(s);
+        E.own_pool = E.own_scratch = E.own_stream = true;
     }
-    hipError_t e = launch_set_counter(c->sums(), 0, 0, 7, c->stream);
-    if (e == hipSuccess) e = launch_init(c->links, c->g, start, seed, 0, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-        set_error(std::string("init: ") + hipGetErrorString(e));
-        su2_destroy(c);
-        return SU2_EHIP;
+    E.links = {E.pool};
+    E.bmap_off = Ensemble::descr_bytes(1);
+    E.rep_off = E.bmap_off;
+    if ((rc = E.upload()) || (rc = E.init({start}))) {
+        E.release();
+        delete c;
+        return rc;
     }
     *out = c;
     return SU2_OK;
@@ -293,15 +738,9 @@ int su2_init_ext(su2_ctx **out, const int32_t dims[4], double beta, uint64_t see
 int su2_destroy(su2_ctx *c)
 {
     if (!c) return fail(SU2_EINVAL, "context is NULL");
-    int rc = SU2_OK;
-    if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(SU2_EHIP, "sync on destroy");
-    if (c->own_mem) {
-        (void)hipFree(c->links);
-        (void)hipFree(c->scratch);
-    }
-    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    c->E.release();
     delete c;
-    return rc;
+    return SU2_OK;
 }
 
 int su2_heatbath_sweep(su2_ctx *c, int32_t nsweeps, int mode)
@@ -309,7 +748,7 @@ int su2_heatbath_sweep(su2_ctx *c, int32_t nsweeps, int mode)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (nsweeps < 0) return fail(SU2_EINVAL, "nsweeps must be >= 0");
-    return enqueue_sweeps(c, nsweeps, mode, 0, 0, nullptr);
+    return c->E.enqueue(nsweeps, mode, 0, 0, nullptr);
 }
 
 int su2_sweep_measure(su2_ctx *c, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
@@ -320,14 +759,32 @@ int su2_sweep_measure(su2_ctx *c, int32_t nsweeps, int mode, int32_t reunit_ever
     if (nsweeps < 0 || reunit_every < 0) return fail(SU2_EINVAL, "negative count");
     if (!dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
     if (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)) return fail(SU2_EINVAL, "bad meas flags");
-    return enqueue_sweeps(c, nsweeps, mode, reunit_every, meas, dev_history);
+    return c->E.enqueue(nsweeps, mode, reunit_every, meas, dev_history);
+}
+
+int su2_capture_sweeps(su2_ctx *c, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
+                       double *dev_history)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (reunit_every < 0 || (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)))
+        return fail(SU2_EINVAL, "bad arguments");
+    if (meas && !dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
+    return c->E.capture(nsweeps, mode, reunit_every, meas, meas ? dev_history : nullptr);
+}
+
+int su2_replay_sweeps(su2_ctx *c, int32_t count)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    return c->E.replay(count);
 }
 
 int su2_reunitarize(su2_ctx *c)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIP_TRY(launch_reunitarize(c->links, c->g, c->stream));
+    HIP_TRY(launch_reunitarize(c->E.ens(), c->E.stream));
     return SU2_OK;
 }
 
@@ -336,32 +793,14 @@ int su2_plaquette(su2_ctx *c, double *out)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
-    HIP_TRY(launch_plaquette(c->links, c->g, c->sums(), c->stream));
-    HIP_TRY(launch_take(c->sums(), ACC_PLAQ, 1.0 / (6.0 * (double)c->volume),
-                        c->results() + R_PLAQ, c->stream));
-    double v[2] = {0.0, 0.0};
-    HIP_TRY(hipMemcpyAsync(v, c->results() + R_PLAQ, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    *out = v[0];
-    return SU2_OK;
+    return c->E.observe(1, out, nullptr, nullptr);
 }
 
 int su2_polyakov(su2_ctx *c, double *out_signed, double *out_abs)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIP_TRY(launch_polyakov(c->links, c->g, c->sums(), c->stream));
-    HIP_TRY(launch_take(c->sums(), ACC_POLY,
-                        1.0 / ((double)c->dims[0] * c->dims[1] * c->dims[2]),
-                        c->results() + R_POLY_SIGNED, c->stream));
-    double v[2] = {0.0, 0.0};
-    HIP_TRY(hipMemcpyAsync(v, c->results() + R_POLY_SIGNED, 2 * sizeof(double),
-                           hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (out_signed) *out_signed = v[0];
-    if (out_abs) *out_abs = v[1];
-    return SU2_OK;
+    return c->E.observe(2, nullptr, out_signed, out_abs);
 }
 
 int su2_get_links(su2_ctx *c, float *host)
@@ -369,27 +808,7 @@ int su2_get_links(su2_ctx *c, float *host)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
-    std::vector<float> planes(c->links_bytes / sizeof(float));
-    HIP_TRY(hipMemcpyAsync(planes.data(), c->links, c->links_bytes, hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    const int64_t vh = c->g.vh;
-    const int32_t *d = c->dims;
-    for (int64_t s = 0; s < c->volume; ++s) {
-        int64_t r = s;
-        const int x = (int)(r % d[0]);
-        r /= d[0];
-        const int y = (int)(r % d[1]);
-        r /= d[1];
-        const int z = (int)(r % d[2]);
-        const int t = (int)(r / d[2]);
-        const int par = (x + y + z + t) & 1;
-        const int64_t h = s >> 1;
-        for (int mu = 0; mu < 4; ++mu)
-            for (int k = 0; k < 4; ++k)
-                host[(s * 4 + mu) * 4 + k] = planes[((mu * 2 + par) * 4 + k) * vh + h];
-    }
-    return SU2_OK;
+    return c->E.get_links(0, host);
 }
 
 int su2_set_links(su2_ctx *c, const float *host)
@@ -397,27 +816,7 @@ int su2_set_links(su2_ctx *c, const float *host)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
-    std::vector<float> planes(c->links_bytes / sizeof(float));
-    const int64_t vh = c->g.vh;
-    const int32_t *d = c->dims;
-    for (int64_t s = 0; s < c->volume; ++s) {
-        int64_t r = s;
-        const int x = (int)(r % d[0]);
-        r /= d[0];
-        const int y = (int)(r % d[1]);
-        r /= d[1];
-        const int z = (int)(r % d[2]);
-        const int t = (int)(r / d[2]);
-        const int par = (x + y + z + t) & 1;
-        const int64_t h = s >> 1;
-        for (int mu = 0; mu < 4; ++mu)
-            for (int k = 0; k < 4; ++k)
-                planes[((mu * 2 + par) * 4 + k) * vh + h] = host[(s * 4 + mu) * 4 + k];
-    }
-    HIP_TRY(hipMemcpyAsync(c->links, planes.data(), c->links_bytes, hipMemcpyHostToDevice,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    return SU2_OK;
+    return c->E.set_links(0, host);
 }
 
 int su2_get_sweep(su2_ctx *c, uint32_t *out)
@@ -425,7 +824,7 @@ int su2_get_sweep(su2_ctx *c, uint32_t *out)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
-    *out = c->sweep;
+    *out = c->E.sweep;
     return SU2_OK;
 }
 
@@ -433,9 +832,7 @@ int su2_set_sweep(su2_ctx *c, uint32_t sweep)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIP_TRY(launch_set_counter(c->sums(), sweep, 0, 1, c->stream));
-    c->sweep = sweep;
-    return SU2_OK;
+    return c->E.set_sweep(sweep);
 }
 
 int su2_set_beta(su2_ctx *c, double beta)
@@ -443,8 +840,8 @@ int su2_set_beta(su2_ctx *c, double beta)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
-    c->beta = beta;
-    return SU2_OK;
+    c->E.beta[0] = beta;
+    return c->E.upload();
 }
 
 int su2_set_replica(su2_ctx *c, uint32_t replica)
@@ -452,16 +849,16 @@ int su2_set_replica(su2_ctx *c, uint32_t replica)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (replica >= (1u << 26)) return fail(SU2_EINVAL, "replica id must be < 2^26");
-    c->replica = replica;
-    return SU2_OK;
+    c->E.replica[0] = replica;
+    return c->E.upload();
 }
 
 int su2_links_device(su2_ctx *c, void **links_dev, void **hip_stream)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (links_dev) *links_dev = c->links;
-    if (hip_stream) *hip_stream = c->stream;
+    if (links_dev) *links_dev = c->E.links[0];
+    if (hip_stream) *hip_stream = c->E.stream;
     return SU2_OK;
 }
 
@@ -469,42 +866,203 @@ int su2_synchronize(su2_ctx *c)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipStreamSynchronize(c->E.stream));
     return SU2_OK;
 }
 
-static int lg_of_tile(int tile, int32_t extent, uint32_t cur, uint32_t *out)
-{
-    if (tile == 0) {
-        *out = cur;
-        return SU2_OK;
-    }
-    if (tile < 0 || (tile & (tile - 1)) || extent % tile)
-        return fail(SU2_EINVAL, "tile sizes must be powers of two dividing the extent");
-    uint32_t l = 0;
-    while ((1 << l) < tile) ++l;
-    *out = l;
-    return SU2_OK;
-}
-
-int su2_set_launch(su2_ctx *c, int block, int xcd_remap, int tile_z, int tile_t)
+int su2_set_launch(su2_ctx *c, int block, int flags, int tile_z, int tile_t, int grid_cap)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (block < 64 || block > 256 || (block % 64) != 0)
-        return fail(SU2_EINVAL, "block must be 64, 128, 192 or 256");
-    uint32_t lz, lt;
-    if ((rc = lg_of_tile(tile_z, c->dims[2], c->g.lg_tz, &lz))) return rc;
-    if ((rc = lg_of_tile(tile_t, c->dims[3], c->g.lg_tt, &lt))) return rc;
-    Geom g = make_geom(c->dims, lz, lt);
-    if (!geom_selfcheck(g)) return fail(SU2_ERANGE, "index arithmetic self-check failed");
-    c->g = g;
-    c->cfg.pass_block = block;
-    c->cfg.xcd_remap = (xcd_remap & 1) != 0;
-    c->cfg.snake = (xcd_remap & 2) == 0;
+    return c->E.set_launch(block, flags, tile_z, tile_t, grid_cap);
+}
+
+int su2_get_launch(su2_ctx *c, int *block, int *flags, int *tile_z, int *tile_t, int *grid_cap)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    const Ensemble &E = c->E;
+    if (block) *block = E.cfg.pass_block;
+    if (flags) *flags = (E.cfg.xcd_remap ? 1 : 0) | (E.cfg.snake ? 0 : 2);
+    if (tile_z) *tile_z = 1 << E.geom[0].lg_tz;
+    if (tile_t) *tile_t = 1 << E.geom[0].lg_tt;
+    if (grid_cap) *grid_cap = (int)E.cfg.grid_cap;
     return SU2_OK;
 }
 
+int su2_autotune(su2_ctx *c, const char *cache_path, int mode, double *best_us_per_sweep)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    return c->E.autotune(cache_path, mode, best_us_per_sweep);
+}
+
+/* ============================================================== batches */
+int su2_batch_init(su2_batch **out, int32_t n, const int32_t *dims, const double *betas,
+                   const int *starts, uint64_t seed, void *hip_stream)
+{
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n <= 0 || n > 65535 || !dims || !betas || !starts)
+        return fail(SU2_EINVAL, "need 1 <= n <= 65535 and non-NULL arrays");
+    int rc;
+    for (int r = 0; r < n; ++r) {
+        if ((rc = check_dims(dims + 4 * r))) return rc;
+        if (!std::isfinite(betas[r])) return fail(SU2_EINVAL, "betas must be finite");
+        if (starts[r] != SU2_COLD && starts[r] != SU2_HOT)
+            return fail(SU2_EINVAL, "start must be COLD or HOT");
+    }
+    su2_batch *b = new (std::nothrow) su2_batch();
+    if (!b) return fail(SU2_ENOMEM, "host allocation failed");
+    Ensemble &E = b->E;
+    E.n = n;
+    E.seed = seed;
+    E.stream = static_cast<hipStream_t>(hip_stream);
+    size_t pool_bytes = 0;
+    std::vector<size_t> off(n);
+    for (int r = 0; r < n; ++r) {
+        E.dims.push_back({dims[4 * r], dims[4 * r + 1], dims[4 * r + 2], dims[4 * r + 3]});
+        E.beta.push_back(betas[r]);
+        E.replica.push_back((uint32_t)r);
+        off[r] = pool_bytes;
+        pool_bytes = align_up(pool_bytes + (size_t)volume_of(dims + 4 * r) * 64, 256);
+    }
+    const size_t scratch = Ensemble::scratch_need(n, E.dims);
+    void *p = nullptr, *s = nullptr;
+    hipError_t e = hipMalloc(&p, pool_bytes);
+    if (e == hipSuccess) e = hipMalloc(&s, scratch);
+    if (e != hipSuccess) {
+        if (p) (void)hipFree(p);
+        delete b;
+        return fail(e == hipErrorOutOfMemory ? SU2_ENOMEM : SU2_EHIP,
+                    std::string("allocation: ") + hipGetErrorString(e));
+    }
+    E.pool = static_cast<float *>(p);
+    E.scratch = static_cast<unsigned char *>(s);
+    E.own_pool = E.own_scratch = true;
+    for (int r = 0; r < n; ++r)
+        E.links.push_back(reinterpret_cast<float *>(reinterpret_cast<char *>(p) + off[r]));
+    E.bmap_off = Ensemble::descr_bytes(n);
+    E.rep_off = E.bmap_off + Ensemble::bmap_bytes(n, E.dims);
+    if ((rc = E.upload()) || (rc = E.init(std::vector<int>(starts, starts + n)))) {
+        E.release();
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return SU2_OK;
+}
+
+int su2_batch_destroy(su2_batch *b)
+{
+    if (!b) return fail(SU2_EINVAL, "batch is NULL");
+    b->E.release();
+    delete b;
+    return SU2_OK;
+}
+
+int su2_batch_size(su2_batch *b, int32_t *n)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (!n) return fail(SU2_EINVAL, "n is NULL");
+    *n = b->E.n;
+    return SU2_OK;
+}
+
+int su2_batch_sweep(su2_batch *b, int32_t nsweeps, int mode)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (nsweeps < 0) return fail(SU2_EINVAL, "nsweeps must be >= 0");
+    return b->E.enqueue(nsweeps, mode, 0, 0, nullptr);
+}
+
+int su2_batch_sweep_measure(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_every,
+                            int meas, double *dev_history)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (nsweeps < 0 || reunit_every < 0) return fail(SU2_EINVAL, "negative count");
+    if (!dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
+    if (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)) return fail(SU2_EINVAL, "bad meas flags");
+    return b->E.enqueue(nsweeps, mode, reunit_every, meas, dev_history);
+}
+
+int su2_batch_capture(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
+                      double *dev_history)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (reunit_every < 0 || (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)))
+        return fail(SU2_EINVAL, "bad arguments");
+    if (meas && !dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
+    return b->E.capture(nsweeps, mode, reunit_every, meas, meas ? dev_history : nullptr);
+}
+
+int su2_batch_replay(su2_batch *b, int32_t count)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    return b->E.replay(count);
+}
+
+int su2_batch_observables(su2_batch *b, double *plaq, double *poly_signed, double *poly_abs)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    const int flags = (plaq ? 1 : 0) | ((poly_signed || poly_abs) ? 2 : 0);
+    if (!flags) return SU2_OK;
+    return b->E.observe(flags, plaq, poly_signed, poly_abs);
+}
+
+int su2_batch_get_links(su2_batch *b, int32_t r, float *host)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (r < 0 || r >= b->E.n || !host) return fail(SU2_EINVAL, "bad replica or NULL");
+    return b->E.get_links(r, host);
+}
+
+int su2_batch_set_links(su2_batch *b, int32_t r, const float *host)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (r < 0 || r >= b->E.n || !host) return fail(SU2_EINVAL, "bad replica or NULL");
+    return b->E.set_links(r, host);
+}
+
+int su2_batch_set_launch(su2_batch *b, int block, int flags, int tile_z, int tile_t,
+                         int grid_cap)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    return b->E.set_launch(block, flags, tile_z, tile_t, grid_cap);
+}
+
+int su2_batch_autotune(su2_batch *b, const char *cache_path, int mode, double *best_us)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    return b->E.autotune(cache_path, mode, best_us);
+}
+
+int su2_batch_synchronize(su2_batch *b)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(b->E.stream));
+    return SU2_OK;
+}
+
+int su2_batch_get_accept_stats(su2_batch *b, uint64_t *proposed, uint64_t *accepted, int reset)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    return b->E.counts(reset, proposed, accepted);
+}
+
+/* ================================================================ tests */
 int su2_test_philox(const uint32_t *ctr_host, int64_t n, uint64_t seed, uint32_t *out_host)
 {
     if (n < 0 || (n > 0 && (!ctr_host || !out_host))) return fail(SU2_EINVAL, "bad arguments");
@@ -556,11 +1114,9 @@ int su2_test_pass(su2_ctx *c, int mu, int parity, int mode)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1) return fail(SU2_EINVAL, "bad mu/parity");
-    if (mode != SU2_KP && mode != SU2_LEARNED) return fail(SU2_EINVAL, "unknown mode");
-    if (mode == SU2_LEARNED && !c->table) return fail(SU2_ESTATE, "no learned proposal loaded");
-    HIP_TRY(launch_pass(c->links, c->g, mu, parity, c->sums(), (float)c->beta, c->seed,
-                        c->replica, false, mode == SU2_LEARNED ? c->table : nullptr, c->cfg,
-                        c->stream));
+    const float *tab = c->E.mode_table(mode, &rc);
+    if (rc) return rc;
+    HIP_TRY(launch_pass(c->E.ens(), mu, parity, c->E.seed, false, tab, c->E.cfg, c->E.stream));
     return SU2_OK;
 }
 
@@ -569,10 +1125,11 @@ int su2_test_index_map(const int32_t dims[4], int tile_z, int tile_t, int parity
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!out || (parity != 0 && parity != 1)) return fail(SU2_EINVAL, "bad arguments");
-    Geom g0 = make_geom(dims, 3, 3);
     uint32_t lz, lt;
-    if ((rc = lg_of_tile(tile_z, dims[2], g0.lg_tz, &lz))) return rc;
-    if ((rc = lg_of_tile(tile_t, dims[3], g0.lg_tt, &lt))) return rc;
+    if ((rc = lg_of_tile(tile_z, 3, &lz))) return rc;
+    if ((rc = lg_of_tile(tile_t, 3, &lt))) return rc;
+    if ((tile_z && dims[2] % tile_z) || (tile_t && dims[3] % tile_t))
+        return fail(SU2_EINVAL, "tile sizes must divide the extents");
     const Geom g = make_geom(dims, lz, lt);
     if (!geom_selfcheck(g)) return fail(SU2_ERANGE, "index arithmetic self-check failed");
     for (uint32_t gid = 0; gid < g.vh; ++gid) {
@@ -593,9 +1150,9 @@ int su2_test_gauge_transform(su2_ctx *c, uint64_t seed)
     int rc = check_ctx(c);
     if (rc) return rc;
     void *G = nullptr;
-    HIP_TRY(hipMalloc(&G, (size_t)c->volume * 16));
-    hipError_t e = launch_gauge(c->links, c->g, (float *)G, seed, c->replica, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    HIP_TRY(hipMalloc(&G, (size_t)volume_of(c->E.dims[0].data()) * 16));
+    hipError_t e = launch_gauge(c->E.ens(), (float *)G, seed, c->E.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->E.stream);
     (void)hipFree(G);
     if (e != hipSuccess) return fail(SU2_EHIP, std::string("gauge: ") + hipGetErrorString(e));
     return SU2_OK;
@@ -836,7 +1393,18 @@ int su2_set_proposal(su2_ctx *c, su2_nn *n)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (n && !n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
-    c->table = n ? n->b.table : nullptr;
+    c->E.drop_graph();
+    c->E.table = n ? n->b.table : nullptr;
+    return SU2_OK;
+}
+
+int su2_batch_set_proposal(su2_batch *b, su2_nn *n)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (n && !n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
+    b->E.drop_graph();
+    b->E.table = n ? n->b.table : nullptr;
     return SU2_OK;
 }
 
@@ -844,14 +1412,7 @@ int su2_get_accept_stats(su2_ctx *c, uint64_t *proposed, uint64_t *accepted, int
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    unsigned long long *slot = reinterpret_cast<unsigned long long *>(c->results() + 4);
-    HIP_TRY(launch_counts(c->sums(), slot, reset, c->stream));
-    unsigned long long v[2] = {0ull, 0ull};
-    HIP_TRY(hipMemcpyAsync(v, slot, sizeof(v), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (proposed) *proposed = v[0];
-    if (accepted) *accepted = v[1];
-    return SU2_OK;
+    return c->E.counts(reset, proposed, accepted);
 }
 
 int su2_test_learned_links(su2_nn *n, const float *V_host, const float *Uold_host, int64_t count,

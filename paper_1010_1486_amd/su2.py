@@ -57,7 +57,26 @@ _SIGS = {
     "su2_set_replica": (_int, [_vp, _u32]),
     "su2_links_device": (_int, [_vp, _vp, _vp]),
     "su2_synchronize": (_int, [_vp]),
-    "su2_set_launch": (_int, [_vp, _int, _int, _int, _int]),
+    "su2_set_launch": (_int, [_vp, _int, _int, _int, _int, _int]),
+    "su2_autotune": (_int, [_vp, ctypes.c_char_p, _int, _vp]),
+    "su2_get_launch": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "su2_capture_sweeps": (_int, [_vp, _i32, _int, _i32, _int, _vp]),
+    "su2_replay_sweeps": (_int, [_vp, _i32]),
+    "su2_batch_init": (_int, [_vp, _i32, _vp, _vp, _vp, _u64, _vp]),
+    "su2_batch_destroy": (_int, [_vp]),
+    "su2_batch_size": (_int, [_vp, _vp]),
+    "su2_batch_sweep": (_int, [_vp, _i32, _int]),
+    "su2_batch_sweep_measure": (_int, [_vp, _i32, _int, _i32, _int, _vp]),
+    "su2_batch_capture": (_int, [_vp, _i32, _int, _i32, _int, _vp]),
+    "su2_batch_replay": (_int, [_vp, _i32]),
+    "su2_batch_observables": (_int, [_vp, _vp, _vp, _vp]),
+    "su2_batch_get_links": (_int, [_vp, _i32, _vp]),
+    "su2_batch_set_links": (_int, [_vp, _i32, _vp]),
+    "su2_batch_set_launch": (_int, [_vp, _int, _int, _int, _int, _int]),
+    "su2_batch_autotune": (_int, [_vp, ctypes.c_char_p, _int, _vp]),
+    "su2_batch_synchronize": (_int, [_vp]),
+    "su2_batch_get_accept_stats": (_int, [_vp, _vp, _vp, _int]),
+    "su2_batch_set_proposal": (_int, [_vp, _vp]),
     "su2_test_philox": (_int, [_vp, _i64, _u64, _vp]),
     "su2_test_heatbath_links": (_int, [_vp, _i64, _d, _u64, _u32, _u32, _u32, _vp, _vp]),
     "su2_test_pass": (_int, [_vp, _int, _int, _int]),
@@ -210,8 +229,31 @@ def su2_synchronize(h):
     _check(lib().su2_synchronize(h))
 
 
-def su2_set_launch(h, block, xcd_remap, tile_z=0, tile_t=0):
-    _check(lib().su2_set_launch(h, int(block), int(xcd_remap), int(tile_z), int(tile_t)))
+def su2_set_launch(h, block, flags, tile_z=0, tile_t=0, grid_cap=0):
+    _check(lib().su2_set_launch(h, int(block), int(flags), int(tile_z), int(tile_t),
+                                int(grid_cap)))
+
+
+def su2_get_launch(h):
+    v = [ctypes.c_int() for _ in range(5)]
+    _check(lib().su2_get_launch(h, *[ctypes.byref(x) for x in v]))
+    return dict(zip(("block", "flags", "tile_z", "tile_t", "grid_cap"), (x.value for x in v)))
+
+
+def su2_autotune(h, cache_path=None, mode=SU2_KP):
+    us = ctypes.c_double()
+    _check(lib().su2_autotune(h, None if cache_path is None else cache_path.encode(), int(mode),
+                              ctypes.byref(us)))
+    return us.value
+
+
+def su2_capture_sweeps(h, nsweeps, mode=SU2_KP, reunit_every=0, meas=0, dev_history_ptr=None):
+    _check(lib().su2_capture_sweeps(h, int(nsweeps), int(mode), int(reunit_every), int(meas),
+                                    _vp(dev_history_ptr)))
+
+
+def su2_replay_sweeps(h, count):
+    _check(lib().su2_replay_sweeps(h, int(count)))
 
 
 def su2_links_device(h):
@@ -469,8 +511,22 @@ class Lattice:
     def set_replica(self, r):
         su2_set_replica(self.h, r)
 
-    def set_launch(self, block, xcd_remap=True, tile_z=0, tile_t=0):
-        su2_set_launch(self.h, block, xcd_remap, tile_z, tile_t)
+    def set_launch(self, block, flags=1, tile_z=0, tile_t=0, grid_cap=0):
+        """flags: bit 0 XCD remap, bit 1 disables the alternating pass order."""
+        su2_set_launch(self.h, block, flags, tile_z, tile_t, grid_cap)
+
+    def autotune(self, cache_path=None, mode=SU2_KP):
+        return su2_autotune(self.h, cache_path, mode)
+
+    def launch(self):
+        return su2_get_launch(self.h)
+
+    def capture(self, nsweeps, mode=SU2_KP, reunit_every=0, meas=0, hist=None):
+        su2_capture_sweeps(self.h, nsweeps, mode, reunit_every, meas,
+                           None if hist is None else hist.data_ptr())
+
+    def replay(self, count):
+        su2_replay_sweeps(self.h, count)
 
     def synchronize(self):
         su2_synchronize(self.h)
@@ -486,3 +542,99 @@ class Lattice:
 
     def accept_stats(self, reset=False):
         return su2_get_accept_stats(self.h, reset)
+
+
+class Batch:
+    """n replicas (su2_batch) on torch's current stream of the device."""
+
+    def __init__(self, dims, betas, starts, seed, device="cuda:0"):
+        import torch  # noqa: F811
+        self.torch = torch
+        self.device = torch.device(device)
+        d = np.ascontiguousarray(dims, dtype=np.int32).reshape(-1, 4)
+        self.n = d.shape[0]
+        self.dims = [list(map(int, x)) for x in d]
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(betas, np.float64), (self.n,)))
+        st = np.ascontiguousarray(np.broadcast_to(np.asarray(starts, np.int32), (self.n,)))
+        self.betas = b.copy()
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _vp()
+        _check(lib().su2_batch_init(ctypes.byref(h), self.n, _p(d), _p(b), _p(st), int(seed),
+                                    _vp(self.stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            _check(lib().su2_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def sweep(self, n, mode=SU2_KP):
+        _check(lib().su2_batch_sweep(self.h, int(n), int(mode)))
+
+    def _hist(self, rows, hist):
+        if hist is None:
+            hist = self.torch.zeros((max(rows, 1), self.n, 3), dtype=self.torch.float64,
+                                    device=self.device)
+        return hist
+
+    def sweep_measure(self, n, mode=SU2_KP, reunit_every=0, meas=SU2_MEAS_PLAQ, hist=None):
+        hist = self._hist(n, hist)
+        _check(lib().su2_batch_sweep_measure(self.h, int(n), int(mode), int(reunit_every),
+                                             int(meas), _vp(hist.data_ptr())))
+        return hist
+
+    def capture(self, n, mode=SU2_KP, reunit_every=0, meas=0, hist=None):
+        _check(lib().su2_batch_capture(self.h, int(n), int(mode), int(reunit_every), int(meas),
+                                       None if hist is None else _vp(hist.data_ptr())))
+
+    def replay(self, count):
+        _check(lib().su2_batch_replay(self.h, int(count)))
+
+    def observables(self):
+        p, s, a = np.empty(self.n), np.empty(self.n), np.empty(self.n)
+        _check(lib().su2_batch_observables(self.h, _p(p), _p(s), _p(a)))
+        return p, s, a
+
+    def get_links(self, r):
+        V = int(np.prod(self.dims[r]))
+        out = np.empty((V, 4, 4), dtype=np.float32)
+        _check(lib().su2_batch_get_links(self.h, int(r), _p(out)))
+        return out
+
+    def set_links(self, r, links):
+        a = np.ascontiguousarray(links, dtype=np.float32)
+        _check(lib().su2_batch_set_links(self.h, int(r), _p(a)))
+
+    def set_launch(self, block, flags=1, tile_z=0, tile_t=0, grid_cap=0):
+        _check(lib().su2_batch_set_launch(self.h, int(block), int(flags), int(tile_z),
+                                          int(tile_t), int(grid_cap)))
+
+    def autotune(self, cache_path=None, mode=SU2_KP):
+        us = ctypes.c_double()
+        _check(lib().su2_batch_autotune(self.h, None if cache_path is None else
+                                        cache_path.encode(), int(mode), ctypes.byref(us)))
+        return us.value
+
+    def synchronize(self):
+        _check(lib().su2_batch_synchronize(self.h))
+
+    def set_proposal(self, nn):
+        _check(lib().su2_batch_set_proposal(self.h, None if nn is None else nn.h))
+
+    def accept_stats(self, reset=False):
+        p = np.zeros(self.n, dtype=np.uint64)
+        a = np.zeros(self.n, dtype=np.uint64)
+        _check(lib().su2_batch_get_accept_stats(self.h, _p(p), _p(a), int(reset)))
+        return p, a
