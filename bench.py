@@ -136,6 +136,119 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
     return out
 
 
+def run_batch(su2, torch, dev, dims, betas, starts, seed, therm, sweeps, meas, reunit,
+              chunk=50):
+    """Autotuned batch: `therm` sweeps, then `sweeps` measured sweeps replayed as
+    graph-captured chunks; returns (seconds of the measured part, history)."""
+    b = su2.Batch(dims, betas, starts, seed=seed, device=dev)
+    b.autotune(None, su2.SU2_KP)
+    b.sweep_measure(therm, reunit_every=reunit, meas=meas)
+    h = torch.zeros((sweeps, len(dims), 3), dtype=torch.float64, device=dev)
+    b.capture(chunk, su2.SU2_KP, reunit_every=reunit, meas=meas, hist=h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.replay(sweeps // chunk)
+    b.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    return dt, h.cpu().numpy()
+
+
+def step_bytes(volumes, polyakov, reunit):
+    """Algorithmic HBM bytes of one sweep over lattices of these volumes:
+    8 passes x 64 V, plus 16 V for the Polyakov loop, plus 128 V per
+    reunitarisation (amortised); the plaquette is fused into the passes."""
+    V = float(sum(volumes))
+    return V * (512.0 + (16.0 if polyakov else 0.0) + (128.0 / reunit if reunit else 0.0))
+
+
+def oracle_rate(dims, sweeps, beta):
+    from oracle import su2_oracle as orc
+    U = orc.init(dims, 1, 1)
+    t0 = time.perf_counter()
+    orc.sweeps(dims, U, sweeps, 0, beta, 1, reunit_every=10, nthreads=orc.max_threads(),
+               measure=True)
+    return 4 * int(np.prod(dims)) * sweeps / (time.perf_counter() - t0)
+
+
+def other_configs(su2, torch, dev, with_cpu):
+    """The remaining workloads, each at its full protocol: link updates/s,
+    algorithmic GB/s and fraction of the 8 TB/s HBM peak, ensemble means, and
+    the oracle's rate on a few sweeps of the same lattice (host threads)."""
+    out = {}
+    PL = su2.SU2_MEAS_PLAQ
+    # 4^4, beta 2.3, hot start (seed 1), 100 sweeps, plaquette every sweep
+    dims = [4, 4, 4, 4]
+    with su2.Lattice(dims, 2.3, 1, su2.SU2_HOT, device=dev) as lat:
+        lat.sweep_measure(10, meas=PL)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = lat.sweep_measure(100, meas=PL)
+        torch.cuda.synchronize()
+        dt_direct = time.perf_counter() - t0
+        with su2.Lattice(dims, 2.3, 1, su2.SU2_HOT, device=dev) as lg:
+            hg = torch.zeros((200, 3), dtype=torch.float64, device=dev)
+            lg.capture(100, meas=PL, hist=hg)
+            lg.replay(1)
+            lg.synchronize()
+            t0 = time.perf_counter()
+            lg.replay(1)
+            lg.synchronize()
+            dt_graph = time.perf_counter() - t0
+    n = 4 * 256 * 100
+    out["4^4"] = {"workload": "4^4, beta 2.3, hot start seed 1, 100 sweeps, plaquette every sweep "
+                              "(latency-bound; not a roofline point)",
+                  "link_updates_per_s_direct": n / dt_direct,
+                  "link_updates_per_s_graph": n / dt_graph,
+                  "us_per_sweep_graph": 1e6 * dt_graph / 100,
+                  "mean_plaquette": float(h.cpu().numpy()[:, 0].mean())}
+    if with_cpu:
+        out["4^4"]["oracle_link_updates_per_s"] = oracle_rate(dims, 100, 2.3)
+    # beta scan 1.5..3.0 on 16^4 and 24^4, cold + hot, 500 + 1000 sweeps, reunit 10
+    betas = np.round(np.arange(1.5, 3.0001, 0.1), 2)
+    for L in (16, 24):
+        d = [[L] * 4] * (2 * len(betas))
+        starts = [0] * len(betas) + [1] * len(betas)
+        dt, h = run_batch(su2, torch, dev, d, np.concatenate([betas, betas]), starts, 1000,
+                             500, 1000, PL, 10)
+        vols = [L ** 4] * len(d)
+        ups = 4 * sum(vols) * 1000 / dt
+        gbs = step_bytes(vols, False, 10) * 1000 / dt / 1e9
+        P = h[:, :, 0].mean(axis=0)
+        key = f"beta_scan_{L}^4"
+        out[key] = {"workload": f"{len(d)} chains of {L}^4 (beta 1.5..3.0 step 0.1, cold and hot), "
+                                "500 + 1000 sweeps, reunitarise every 10, plaquette every sweep; "
+                                "one batch, graph-captured chunks of 50 sweeps",
+                    "link_updates_per_s": ups, "algorithmic_gbs": gbs,
+                    "hbm_frac": gbs / HBM_PEAK_GBS,
+                    "mean_plaquette_by_beta": [round(float(0.5 * (P[i] + P[i + len(betas)])), 6)
+                                               for i in range(len(betas))]}
+        if with_cpu:
+            out[key]["oracle_link_updates_per_s"] = oracle_rate([L] * 4, 2, 2.3)
+    # 32^3 x Nt, Nt in {4, 6, 8}, beta 2.00..2.60 step 0.05, cold, 5000 sweeps
+    betas = np.round(np.arange(2.0, 2.6001, 0.05), 2)
+    nts = (4, 6, 8)
+    d = [[32, 32, 32, nt] for nt in nts for _ in betas]
+    dt, h = run_batch(su2, torch, dev, d, np.concatenate([betas] * 3), 0, 4000, 0, 5000,
+                         PL | su2.SU2_MEAS_POLY, 10)
+    vols = [32 ** 3 * x[3] for x in d]
+    ups = 4 * sum(vols) * 5000 / dt
+    gbs = step_bytes(vols, True, 10) * 5000 / dt / 1e9
+    absL = np.abs(h[1000:, :, 1]).mean(axis=0)
+    out["polyakov_32^3xNt"] = {
+        "workload": f"{len(d)} chains of 32^3 x Nt (Nt 4, 6, 8; beta 2.00..2.60 step 0.05), "
+                    "cold start, 5000 sweeps, plaquette and Polyakov loop every sweep, "
+                    "reunitarise every 10; one batch, graph-captured chunks of 50 sweeps",
+        "link_updates_per_s": ups, "algorithmic_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+        "mean_abs_polyakov_by_nt": {str(nt): [round(float(x), 5) for x in
+                                              absL[k * len(betas):(k + 1) * len(betas)]]
+                                    for k, nt in enumerate(nts)}}
+    if with_cpu:
+        out["polyakov_32^3xNt"]["oracle_link_updates_per_s"] = oracle_rate([32, 32, 32, 4], 2,
+                                                                           2.3)
+    return out
+
+
 def cpu_baseline(sample_sweeps=1):
     from oracle import su2_oracle as orc
     threads = orc.max_threads()
@@ -159,6 +272,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the batched plain-vs-learned comparison")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 4^4, beta-scan and Polyakov workloads")
     ap.add_argument("--counters", action="store_true",
                     help="short program for rocprofv3 --pmc runs: 16 pass launches in sweep "
                          "order, then 4 plain device copies of the field size (339.7 MB) "
@@ -241,6 +356,11 @@ def main():
         "launch": lat.launch(),
     }
     lat.close()
+    if not args.no_configs:
+        print("[bench] other workloads", file=sys.stderr, flush=True)
+        with torch.cuda.stream(torch.cuda.Stream(device=dev)):  # graphs need a non-null stream
+            out["other_configs"] = other_configs(su2, torch, dev, not args.no_cpu_baseline)
+        torch.cuda.synchronize()
     if not args.no_learned:
         print("[bench] batched plain vs learned proposal", file=sys.stderr, flush=True)
         out["learned_vs_plain"] = learned_vs_plain(su2, torch, dev)

@@ -1,0 +1,161 @@
+"""Ensemble parity: batched GPU chains against independent FP64 oracle chains.
+
+Heat bath is a Markov chain, so beyond link-level parity the method-level check
+is that ensemble averages agree.  Two kinds of comparison:
+
+* matched protocol: the oracle runs one chain (its own seed) with a short
+  protocol -- start, thermalisation sweeps, measurements every `every` sweeps,
+  reunitarisation every 10 -- and the GPU runs many independent replicas of
+  exactly that protocol in one batch.  Whatever bias the short thermalisation
+  leaves (from a cold start at weak coupling the plaquette relaxes over several
+  hundred sweeps) is then the same for both, and the spread of the GPU replicas'
+  chain means is the sampling error of one chain.  Pull =
+  (m_orc - mean_gpu) / (sd_gpu sqrt(1 + 1/n)).
+* full protocol on the GPU alone: the workload's whole protocol as one batch;
+  cold and hot starts must agree (tau_int-corrected errors) where both
+  thermalise, and the Polyakov loop must show the deconfinement signal.
+
+Criterion for a set of pulls: every pull within 3, at least 75% within 2, mean
+squared pull at most 2.
+
+Cold and hot starts are compared with each other only for beta <= 2.4.  At
+weaker coupling a hot start on 16^4 can relax into long-lived metastable
+structure (for instance a non-trivial topological sector) that the local
+update removes only slowly, so its plaquette can stay offset for longer than
+the 500 thermalisation sweeps (a 3.9 sigma cold/hot difference was seen at
+beta 2.8).
+
+Workloads:
+* beta scan 1.5..3.0 (step 0.1) on 16^4, cold and hot starts, 500
+  thermalisation + 1000 measured sweeps, reunitarisation every 10 sweeps,
+  plaquette every sweep (Sec. 4 beta scans);
+* 32^3 x Nt, Nt in {4, 6, 8}, beta 2.00..2.60 (step 0.05), cold start, 5000
+  sweeps, plaquette and Polyakov loop every sweep (Sec. 4, Polyakov loop).
+"""
+import time
+
+import numpy as np
+import pytest
+
+from tests import stats
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+def pulls(gpu, orc):
+    g = np.asarray(gpu)
+    o = np.asarray(orc)
+    return (g[:, 0] - o[:, 0]) / np.hypot(g[:, 1], o[:, 1])
+
+
+def assert_pulls(p, what):
+    p = np.asarray(p)
+    print(f"[gpu-test] {what}: pulls {np.round(p, 2).tolist()}", flush=True)
+    assert np.all(np.abs(p) <= 3.0), (what, p)
+    assert np.mean(np.abs(p) <= 2.0) >= 0.75, (what, p)
+    assert np.mean(p * p) <= 2.0, (what, p)
+
+
+def oracle_chain(orc, dims, beta, seed, start, therm, nmeas, every, reunit=10):
+    """Independent oracle chain: `therm` sweeps, then `nmeas` measurements of
+    (P, signed L) taken every `every` sweeps."""
+    nt = orc.max_threads()
+    U = orc.init(dims, start, seed)
+    orc.sweeps(dims, U, therm, 0, beta, seed, reunit_every=reunit, nthreads=nt)
+    sw = therm
+    P, L = [], []
+    for _ in range(nmeas):
+        orc.sweeps(dims, U, every, sw, beta, seed, reunit_every=reunit, nthreads=nt)
+        sw += every
+        P.append(orc.plaquette(dims, U))
+        L.append(orc.polyakov(dims, U)[0])
+    return np.array(P), np.array(L)
+
+
+def gpu_matched(su2, dims, beta, start, therm, nmeas, every, nrep, seed, reunit=10):
+    """nrep independent GPU replicas of the oracle_chain protocol.  Returns the
+    replicas' chain means of P and |L| as arrays of shape (nrep,)."""
+    n = therm + nmeas * every
+    with su2.Batch([dims] * nrep, beta, start, seed=seed) as b:
+        h = b.sweep_measure(n, reunit_every=reunit,
+                            meas=su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY).cpu().numpy()
+    rows = therm + every * np.arange(1, nmeas + 1) - 1  # after sweep therm + every (i + 1)
+    return h[rows, :, 0].mean(axis=0), np.abs(h[rows, :, 1]).mean(axis=0)
+
+
+def matched_pull(orc_mean, gpu_means):
+    n = len(gpu_means)
+    return (orc_mean - gpu_means.mean()) / (gpu_means.std(ddof=1) * np.sqrt(1 + 1 / n))
+
+
+def test_beta_scan_16_matches_oracle(su2, orc):
+    announce("ensemble: beta scan 16^4")
+    betas = np.round(np.arange(1.5, 3.0001, 0.1), 2)
+    nb = len(betas)
+    dims = [[16, 16, 16, 16]] * (2 * nb)
+    bet = np.concatenate([betas, betas])
+    starts = np.array([su2.SU2_COLD] * nb + [su2.SU2_HOT] * nb, np.int32)
+    t0 = time.time()
+    with su2.Batch(dims, bet, starts, seed=1000) as b:
+        b.sweep_measure(500, reunit_every=10)
+        hist = b.sweep_measure(1000, reunit_every=10).cpu().numpy()
+    print(f"[gpu-test] gpu batch {time.time() - t0:.1f} s", flush=True)
+    P = hist[:, :, 0]
+    gpu = np.array([stats.mean_err(P[:, r]) for r in range(2 * nb)])
+    # cold and hot chains of the GPU are independent and must agree (beta <= 2.4)
+    strong = int(np.sum(betas <= 2.4 + 1e-9))
+    assert_pulls(pulls(gpu[:strong], gpu[nb:nb + strong]), "gpu cold vs hot, beta <= 2.4")
+    # matched protocol (100 sweeps, then 150 measurements 2 sweeps apart): the
+    # oracle's chain against 32 GPU replicas; hot starts at beta 1.5 and 2.1,
+    # cold starts at beta 2.7 and 3.0
+    t0 = time.time()
+    p = []
+    for i, start in ((0, 1), (6, 1), (12, 0), (15, 0)):
+        ph, _ = oracle_chain(orc, [16, 16, 16, 16], betas[i], 7000 + i, start, 100, 150, 2)
+        gp, _ = gpu_matched(su2, [16, 16, 16, 16], betas[i], start, 100, 150, 2, 32, 1100 + i)
+        p.append(matched_pull(ph.mean(), gp))
+    print(f"[gpu-test] oracle + matched GPU chains {time.time() - t0:.1f} s", flush=True)
+    assert_pulls(p, "oracle vs gpu, plaquette, matched protocol")
+    # monotone in beta, between the strong- and weak-coupling limits
+    m = 0.5 * (gpu[:nb, 0] + gpu[nb:, 0])
+    assert np.all(np.diff(m) > 0)
+    assert np.all(m < 1 - 3 / (4 * betas) + 0.02)
+
+
+def test_polyakov_32x4_matches_oracle(su2, orc):
+    announce("ensemble: 32^3 x Nt Polyakov loop")
+    betas = np.round(np.arange(2.0, 2.6001, 0.05), 2)
+    nts = [4, 6, 8]
+    dims = [[32, 32, 32, nt] for nt in nts for _ in betas]
+    bet = np.concatenate([betas] * len(nts))
+    t0 = time.time()
+    with su2.Batch(dims, bet, su2.SU2_COLD, seed=4000) as b:
+        hist = b.sweep_measure(5000, reunit_every=10,
+                               meas=su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY).cpu().numpy()
+    print(f"[gpu-test] gpu batch {time.time() - t0:.1f} s", flush=True)
+    therm = 1000
+    nb = len(betas)
+    absL = np.abs(hist[therm:, :, 1])
+    P = hist[therm:, :, 0]
+    gL = np.array([stats.mean_err(absL[:, r]) for r in range(len(dims))])
+    gP = np.array([stats.mean_err(P[:, r]) for r in range(len(dims))])
+    # the |L| signal: small and flat in the confined phase, rising through the
+    # transition; larger Nt deconfines at larger beta
+    for k in range(len(nts)):
+        L = gL[k * nb:(k + 1) * nb, 0]
+        assert L[-1] > 4 * L[0], (nts[k], L)
+    assert gL[nb - 1, 0] > gL[2 * nb - 1, 0] > gL[3 * nb - 1, 0]  # beta 2.6: Nt 4 > 6 > 8
+    for k in range(len(nts)):
+        assert np.all(np.diff(gP[k * nb:(k + 1) * nb, 0]) > 0)
+    # matched protocol at Nt = 4, beta 2.0 and 2.6: cold start, 200 sweeps,
+    # then 150 measurements 2 sweeps apart; the oracle's chain against 32 GPU
+    # replicas
+    t0 = time.time()
+    p = []
+    for i in (0, nb - 1):
+        ph, lh = oracle_chain(orc, [32, 32, 32, 4], betas[i], 4100 + i, 0, 200, 150, 2)
+        gp, gl = gpu_matched(su2, [32, 32, 32, 4], betas[i], 0, 200, 150, 2, 32, 4200 + i)
+        p += [matched_pull(ph.mean(), gp), matched_pull(np.abs(lh).mean(), gl)]
+    print(f"[gpu-test] oracle + matched GPU chains {time.time() - t0:.1f} s", flush=True)
+    assert_pulls(p, "oracle vs gpu, P and |L|, Nt = 4, matched protocol")

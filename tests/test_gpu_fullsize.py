@@ -1,0 +1,94 @@
+"""Parity at the full 48^4 size (beta 6.0, hot start from Philox seed 3), in
+the launch configuration the autotuner picks, which is the one the throughput
+benchmark times; also a persistent (grid-stride) launch.
+
+The oracle cannot redo a 48^4 sweep in seconds, so single passes are checked
+on sampled links, each recomputed by the oracle from the GPU's input links
+(staple, k, exact sampler, direction, U' = X U~^+; Sec. 2), and the fused
+sweep measurements by properties that hold at any size: the plaquette and
+Polyakov loop of the GPU's final links recomputed in FP64, and unitarity."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import MARGIN_FLAG, announce, max_flags
+
+pytestmark = pytest.mark.gpu
+
+DIMS, BETA, SEED = [48, 48, 48, 48], 6.0, 3
+NSAMPLE = 6000
+
+
+def sample_sites(orc, par, n, seed):
+    """n distinct sites of parity `par` (half the sites of each parity lie on
+    even x + y + z + t), including the first and last of that parity."""
+    V = int(np.prod(DIMS))
+    rng = np.random.default_rng(seed)
+    s = rng.choice(V, size=3 * n, replace=False)
+    s = s[[orc.parity(DIMS, int(x)) == par for x in s]][:n]
+    ends = [x for x in (0, 1, V - 2, V - 1) if orc.parity(DIMS, x) == par]
+    return np.unique(np.concatenate([s, ends]))
+
+
+def check_pass(lat, orc, mu, par, seed):
+    before = lat.get_links()
+    sweep = lat.sweep
+    lat.test_pass(mu, par)
+    got = lat.get_links()
+    # links outside the pass are untouched, bit for bit
+    changed = np.any(got != before, axis=2)
+    assert not changed[:, [m for m in range(4) if m != mu]].any()
+    U = before.astype(np.float64)
+    sites = sample_sites(orc, par, NSAMPLE, seed)
+    nflag, worst = 0, 0.0
+    for s in sites:
+        s = int(s)
+        V = orc.staple(DIMS, U, s, mu)
+        want, m = orc.heatbath_link(V, BETA, SEED, s, sweep, mu)
+        if m < MARGIN_FLAG:
+            nflag += 1
+            continue
+        worst = max(worst, float(np.abs(got[s, mu] - want).max()))
+    del U
+    assert worst < 1e-5, (mu, par, worst)
+    assert nflag <= max_flags(len(sites))
+    # every link of the pass's parity and direction changed (p(unchanged) ~ 0)
+    par_of = (np.indices(DIMS[::-1]).sum(axis=0).ravel() & 1)
+    assert changed[par_of == par, mu].mean() > 0.999
+    return worst
+
+
+def test_full_size_passes_autotuned_and_persistent(su2, orc):
+    announce("48^4 sampled pass parity (autotuned launch)")
+    with su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT) as lat:
+        lat.autotune()
+        print(f"[gpu-test] launch {lat.launch()}", flush=True)
+        lat.heatbath_sweep(2)
+        for mu, par in ((0, 0), (3, 1)):
+            w = check_pass(lat, orc, mu, par, 100 + mu)
+            print(f"[gpu-test] pass ({mu},{par}) max err {w:.2e}", flush=True)
+        announce("48^4 sampled pass parity (persistent grid)")
+        lat.set_launch(256, 1, 8, 8, 2048)
+        for mu, par in ((1, 1), (2, 0)):
+            w = check_pass(lat, orc, mu, par, 200 + mu)
+            print(f"[gpu-test] pass ({mu},{par}) max err {w:.2e}", flush=True)
+
+
+def test_full_size_sweep_measurements(su2, orc):
+    announce("48^4 fused sweep measurements")
+    with su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT) as lat:
+        lat.autotune()
+        hist = lat.sweep_measure(3, reunit_every=10,
+                                 meas=su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY).cpu().numpy()
+        links = lat.get_links()
+        n2 = np.einsum("vmc,vmc->vm", links.astype(np.float64), links.astype(np.float64))
+        assert np.abs(n2 - 1).max() < 1e-5
+        U = links.astype(np.float64)
+        del links
+        p = orc.plaquette(DIMS, U)
+        ls, la = orc.polyakov(DIMS, U)
+        assert abs(hist[-1, 0] - p) < 1e-6, (hist[-1, 0], p)
+        assert abs(hist[-1, 1] - ls) < 1e-6 and abs(hist[-1, 2] - la) < 1e-6
+        # standalone kernels on the same links
+        assert abs(lat.plaquette() - p) < 1e-6
+        s, a = lat.polyakov()
+        assert abs(s - ls) < 1e-6 and abs(a - la) < 1e-6
