@@ -211,7 +211,7 @@ int su2_batch_get_accept_stats(su2_batch *b, uint64_t *proposed, uint64_t *accep
  * Parameters: 2671 FP32, order W1[32] b1[32] W2[32][32] b2[32] W3[47][32]
  * b3[47] (rows = output units).  Training minimises the NLL of exact-sampler
  * draws with Adam (b1 0.9, b2 0.999, eps 1e-8), all on the GPU.  The pass
- * uses a 256-row table of the spline at f = -1 + 2j/255 (nearest row), rows
+ * uses a 64-row table of the spline at f = -1 + 2j/63 (nearest row), rows
  * of 48 floats [x1..x15, 1, y1..y15, 1, d1..d15, 1]. */
 typedef struct su2_nn su2_nn;
 
@@ -238,7 +238,8 @@ int su2_nn_loss_grad(su2_nn *nn, int64_t offset, int32_t batch, double *loss, fl
 /* `steps` Adam steps on consecutive minibatches of the data (wrapping);
  * loss_history_host (may be NULL) receives each step's mean NLL.  Synchronous. */
 int su2_nn_train(su2_nn *nn, int32_t steps, int32_t batch, double lr, double *loss_history_host);
-/* Evaluate the 256-row spline table from the current parameters / copy it. */
+/* Evaluate the 64-row spline table from the current parameters / copy it
+ * (host float[64 * 48]). */
 int su2_nn_build_table(su2_nn *nn);
 int su2_nn_get_table(su2_nn *nn, float *table_host);
 /* Use nn's table for SU2_LEARNED sweeps of ctx (NULL unsets).  The su2_nn must

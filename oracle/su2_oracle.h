@@ -119,7 +119,7 @@ void orc_haar_from_block(const uint32_t w[4], double out[4]);
 #define ORC_NN_OUT 47
 #define ORC_NN_BINS 16
 #define ORC_NN_NPARAM 2671
-#define ORC_NN_TABLE_ROWS 256
+#define ORC_NN_TABLE_ROWS 64
 #define ORC_NN_ROW 48
 #define ORC_NN_ALPHA_LO 0.5
 #define ORC_NN_ALPHA_HI 30.0
@@ -134,7 +134,7 @@ double orc_spline_fwd(const double x[17], const double y[17], const double d[17]
 /* g^{-1}(u) and ln g'(x) at that point */
 double orc_spline_inv(const double x[17], const double y[17], const double d[17], double u,
                       double *logderiv);
-void orc_nn_table(const float *params, double *table /* 256 x 48 */);
+void orc_nn_table(const float *params, double *table /* 64 x 48 */);
 /* Row index used for alpha (nearest), with the margin of that choice. */
 int orc_table_row(double alpha, double *margin);
 void orc_table_knots(const double *table, int row, double x[17], double y[17], double d[17]);

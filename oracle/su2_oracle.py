@@ -230,7 +230,7 @@ def max_threads():
 
 
 # ------------------------------------------------------- learned proposal
-NN_NPARAM, NN_OUT, NN_BINS, NN_ROWS, NN_ROW = 2671, 47, 16, 256, 48
+NN_NPARAM, NN_OUT, NN_BINS, NN_ROWS, NN_ROW = 2671, 47, 16, 64, 48
 ALPHA_LO, ALPHA_HI = 0.5, 30.0
 
 

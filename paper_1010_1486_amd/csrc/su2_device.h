@@ -305,10 +305,11 @@ __device__ __forceinline__ Q heatbath_link(const Q &V, float beta, uint32_t site
 // the proposal of an independence Metropolis step whose weight
 // w(x) = exp(alpha x) sqrt(1 - x^2) / q(x) keeps the heat-bath distribution of
 // Sec. 2 exact.  The spline of each alpha comes from the nearest row of a
-// 256-row table (rows at f = -1 + 2 j / 255, f = log-scaled alpha in
-// [0.5, 30]) holding [x1..x15, 1, y1..y15, 1, d1..d15, 1]; x0 = y0 = -1 and
-// d0 = 1 are implicit.  Outside [0.5, 30] the exact sampler is used.
-constexpr int kNNRows = 256;
+// 64-row table (rows at f = -1 + 2 j / 63, f = log-scaled alpha in [0.5, 30];
+// neighbouring rows are 6.7% apart in alpha) holding [x1..x15, 1, y1..y15, 1,
+// d1..d15, 1]; x0 = y0 = -1 and d0 = 1 are implicit.  The table is 12 KB, so
+// the pass keeps it in LDS.  Outside [0.5, 30] the exact sampler is used.
+constexpr int kNNRows = 64;
 constexpr int kNNRow = 48;
 constexpr float kNNAlphaLo = 0.5f;
 constexpr float kNNAlphaHi = 30.0f;
@@ -322,37 +323,63 @@ __device__ __forceinline__ int nn_table_row(float alpha)
     return j < 0 ? 0 : (j > kNNRows - 1 ? kNNRows - 1 : j);
 }
 
+// The device table is preceded by kNNTablePad floats of padding (the LDS copy
+// in the pass by 4), so that the update may read the float before a row
+// unconditionally (bin 0 has no stored left knot) and then select the
+// implicit value.
+constexpr int kNNTablePad = 16;
+
+// Index k of the bin holding v among the knots t1..t15 of one row (held in
+// registers, loaded as four float4: t[i] = knots[i - 1]): k = #{i : v >= t_i}
+// for increasing knots, found by a four-step binary search with selects.
+__device__ __forceinline__ int rq_bin_index(const float4 &a, const float4 &b, const float4 &c,
+                                            const float4 &d, float v)
+{
+    // t1..t4 = a, t5..t8 = b, t9..t12 = c, t13..t15 = d.xyz
+    const bool c1 = v >= b.w;                       // t8
+    const bool c2 = v >= (c1 ? c.w : a.w);          // t12 | t4
+    const float s2lo = c1 ? c.y : a.y;              // t10 | t2
+    const float s2hi = c1 ? d.y : b.y;              // t14 | t6
+    const bool c3 = v >= (c2 ? s2hi : s2lo);
+    const float q0 = c1 ? c.x : a.x, q1 = c1 ? c.z : a.z;  // t9 | t1, t11 | t3
+    const float q2 = c1 ? d.x : b.x, q3 = c1 ? d.z : b.z;  // t13 | t5, t15 | t7
+    const float r0 = c2 ? q2 : q0, r1 = c2 ? q3 : q1;
+    const bool c4 = v >= (c3 ? r1 : r0);
+    return (c1 ? 8 : 0) | (c2 ? 4 : 0) | (c3 ? 2 : 0) | (c4 ? 1 : 0);
+}
+
 struct RQBin {
     float xl, W, yl, H, dl, dh;
 };
 
-// Bin of v among the knots starting at row[off] (off = 0: x, 16: y).
-__device__ __forceinline__ RQBin rq_bin(const float *__restrict__ row, int off, float v)
+// Bin k of a row: x_k, x_{k+1} - x_k, y_k, y_{k+1} - y_k, d_k, d_{k+1}.  One
+// vector offset serves all six loads (the k - 1 entries may read the padding
+// or the previous row; bin 0 then takes the implicit -1, -1, 1).
+__device__ __forceinline__ RQBin rq_bin_at(const float *__restrict__ row, int k)
 {
-    const float4 *r4 = reinterpret_cast<const float4 *>(row + off);
-    int k = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float4 t = r4[q];
-        k += (v >= t.x) + (v >= t.y) + (v >= t.z) + (q < 3 ? (v >= t.w) : 0);
-    }
+    const float *p = row + k;
+    const float x0 = p[-1], x1 = p[0], y0 = p[15], y1 = p[16], d0 = p[31], d1 = p[32];
+    const bool first = k == 0;
     RQBin b;
-    b.xl = k ? row[k - 1] : -1.0f;
-    b.W = row[k] - b.xl;
-    b.yl = k ? row[16 + k - 1] : -1.0f;
-    b.H = row[16 + k] - b.yl;
-    b.dl = k ? row[32 + k - 1] : 1.0f;
-    b.dh = row[32 + k];
+    b.xl = first ? -1.0f : x0;
+    b.yl = first ? -1.0f : y0;
+    b.dl = first ? 1.0f : d0;
+    b.W = x1 - b.xl;
+    b.H = y1 - b.yl;
+    b.dh = d1;
     return b;
 }
 
-// g'(x) at relative position xi in the bin, s = H / W.
-__device__ __forceinline__ float rq_deriv(const RQBin &b, float s, float xi)
+// g'(x) = s^2 num / den^2 at relative position xi in the bin (s = H / W),
+// returned as (s^2 num, den^2) so that quotients can share one reciprocal.
+__device__ __forceinline__ void rq_deriv_parts(const RQBin &b, float s, float xi, float &num,
+                                               float &den2)
 {
     const float om = xi * (1.0f - xi);
     const float den = s + (b.dh + b.dl - 2.0f * s) * om;
-    const float num = b.dh * xi * xi + 2.0f * s * om + b.dl * (1.0f - xi) * (1.0f - xi);
-    return s * s * num / (den * den);
+    const float omx = 1.0f - xi;
+    num = s * s * (b.dh * xi * xi + 2.0f * s * om + b.dl * omx * omx);
+    den2 = den * den;
 }
 
 // Learned-proposal Metropolis update of one link.  acc: 1 accepted, 0
@@ -370,29 +397,37 @@ __device__ __forceinline__ Q learned_link(const Q &V, const Q &Uold, const float
     }
     const Q Ut{V.w * inv_k, V.x * inv_k, V.y * inv_k, V.z * inv_k};
     const float *row = table + (size_t)nn_table_row(alpha) * kNNRow;
+    const float4 *r4 = reinterpret_cast<const float4 *>(row);
+    const float4 xa = r4[0], xb = r4[1], xc = r4[2], xd = r4[3];
+    const float4 ya = r4[4], yb = r4[5], yc = r4[6], yd = r4[7];
     const U4 w = philox(site, sweep, word2(mu, TAG_LEARN, replica), 0u, k0, k1);
     const float u = 2.0f * u01(w.a) - 1.0f;
-    // proposal a0' = g^{-1}(u): root xi of a xi^2 + b xi + c = 0 in the bin
-    const RQBin bn = rq_bin(row, 16, u);
+    // current link in the frame of the staple: x_old = (U_old U~)_0
+    const float xo = fminf(fmaxf(retr(Uold, Ut), -1.0f), 1.0f);
+    const RQBin bn = rq_bin_at(row, rq_bin_index(ya, yb, yc, yd, u));
+    const RQBin bo = rq_bin_at(row, rq_bin_index(xa, xb, xc, xd, xo));
+    // proposal a0' = g^{-1}(u): root xi of qa xi^2 + qb xi + qc = 0 in the bin
     const float sn = bn.H * hw_rcp(bn.W);
     const float dy = u - bn.yl, tt = bn.dh + bn.dl - 2.0f * sn;
     const float qa = bn.H * (sn - bn.dl) + dy * tt;
     const float qb = bn.H * bn.dl - dy * tt;
     const float qc = -sn * dy;
     const float disc = fmaxf(qb * qb - 4.0f * qa * qc, 0.0f);
-    const float xin = 2.0f * qc / (-qb - hw_sqrt(disc));
+    const float xin = 2.0f * qc * hw_rcp(-qb - hw_sqrt(disc));
     const float a0n = bn.xl + xin * bn.W;
-    const float gn = rq_deriv(bn, sn, xin);
-    // current link in the frame of the staple: x_old = (U_old U~)_0
-    const float xo = fminf(fmaxf(retr(Uold, Ut), -1.0f), 1.0f);
-    const RQBin bo = rq_bin(row, 0, xo);
-    const float so = bo.H * hw_rcp(bo.W);
-    const float go = rq_deriv(bo, so, (xo - bo.xl) * hw_rcp(bo.W));
+    const float rwo = hw_rcp(bo.W);
+    const float so = bo.H * rwo;
+    float nn_, dn2, no_, do2;
+    rq_deriv_parts(bn, sn, xin, nn_, dn2);
+    rq_deriv_parts(bo, so, (xo - bo.xl) * rwo, no_, do2);
     // ln w(a0') - ln w(x_old) = alpha (a0' - x_old)
-    //   + (1/2) ln[(1 - a0'^2) g'(x_old)^2 / ((1 - x_old^2) g'(a0')^2)]
-    const float ratio = ((1.0f - a0n) * (1.0f + a0n) * go * go) /
-                        ((1.0f - xo) * (1.0f + xo) * gn * gn);
-    const float dlog2 = alpha * (a0n - xo) * kLog2e + 0.5f * hw_log2(ratio);
+    //   + (1/2) ln[(1 - a0'^2) / (1 - x_old^2)] + ln[g'(x_old) / g'(a0')],
+    // g'(x_old) / g'(a0') = (no_ dn2) / (nn_ do2).  Both quotients stay well
+    // inside the FP32 range; 1 - x_old^2 = 0 gives +inf (accept), 1 - a0'^2
+    // = 0 gives -inf (reject), both NaN (reject).
+    const float qg = (no_ * dn2) * hw_rcp(nn_ * do2);
+    const float qs = (1.0f - a0n) * (1.0f + a0n) * hw_rcp((1.0f - xo) * (1.0f + xo));
+    const float dlog2 = alpha * (a0n - xo) * kLog2e + 0.5f * hw_log2(qs) + hw_log2(qg);
     if (hw_log2(u01(w.b)) < dlog2) {
         acc = 1;
         const float r5 = u01(w.c), r6 = u01(w.d);

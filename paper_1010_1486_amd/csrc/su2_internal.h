@@ -108,7 +108,8 @@ struct NNBuffers {
     float *params, *grad, *m, *v;  // kNNParams each
     float *alpha, *a0;             // training data
     float *act, *loss;             // kNNActRows x batch, batch
-    float *table;                  // kNNRows x kNNRow
+    float *table;                  // kNNRows x kNNRow, kNNTablePad floats into table_alloc
+    float *table_alloc;
 };
 
 hipError_t launch_nn_data(float *alpha, float *a0, int64_t n, float lo, float hi, uint64_t seed,

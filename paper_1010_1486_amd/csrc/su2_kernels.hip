@@ -186,6 +186,16 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
                                                    uint32_t k1, int remap, int reverse,
                                                    const float *__restrict__ table)
 {
+    // LEARNED: the spline table in LDS (filled once per workgroup), preceded
+    // by 4 floats of padding like the device copy
+    __shared__ float4 stab4[LEARNED ? 1 + kNNRows * kNNRow / 4 : 1];
+    if (LEARNED) {
+        const float4 *t4 = reinterpret_cast<const float4 *>(table);
+        for (int i = threadIdx.x; i < kNNRows * kNNRow / 4; i += blockDim.x) stab4[1 + i] = t4[i];
+        if (threadIdx.x == 0) stab4[0] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+        __syncthreads();
+    }
+    const float *ltab = reinterpret_cast<const float *>(stab4) + 4;
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
         const Rep &R = reps[bmap ? bmap[b] : 0u];
         const uint32_t local = b - R.first_block;
@@ -228,7 +238,7 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
             Q Un;
             if (LEARNED) {
                 const Q Uold = ld(arr(links, g.vh, MU, par), h);
-                Un = learned_link(V, Uold, table, R.beta, site, sweep, (uint32_t)MU, R.replica,
+                Un = learned_link(V, Uold, ltab, R.beta, site, sweep, (uint32_t)MU, R.replica,
                                   k0, k1, acc);
             } else {
                 Un = heatbath_link(V, R.beta, site, sweep,
@@ -239,11 +249,13 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
         }
         if (MEASURE) block_accumulate((double)meas, R.acc, ACC_PLAQ, b);
         if (LEARNED) {
-            const double np = block_sum(acc >= 0 ? 1.0 : 0.0);
-            const double na = block_sum(acc == 1 ? 1.0 : 0.0);
-            if (threadIdx.x == 0) {
-                atomicAdd(bucket(R.acc, ACC_PROPOSED, b), (unsigned long long)np);
-                atomicAdd(bucket(R.acc, ACC_ACCEPTED, b), (unsigned long long)na);
+            // per-wave counts (ballot) added by lane 0 of each wave
+            const unsigned long long mp = __ballot(acc >= 0);
+            const unsigned long long ma = __ballot(acc == 1);
+            if ((threadIdx.x & 63) == 0) {
+                const uint32_t wb = b * (blockDim.x >> 6) + (threadIdx.x >> 6);
+                if (mp) atomicAdd(bucket(R.acc, ACC_PROPOSED, wb), (unsigned long long)__popcll(mp));
+                if (ma) atomicAdd(bucket(R.acc, ACC_ACCEPTED, wb), (unsigned long long)__popcll(ma));
             }
         }
     }

@@ -1173,7 +1173,9 @@ struct su2_nn {
 static void nn_free(su2_nn *n)
 {
     // b.a0 lives inside the b.alpha allocation and b.loss inside b.act
-    float *bufs[] = {n->b.params, n->b.grad, n->b.m, n->b.v, n->b.alpha, n->b.act, n->b.table};
+    // (b.table points kNNTablePad floats into b.table_alloc)
+    float *bufs[] = {n->b.params, n->b.grad, n->b.m, n->b.v, n->b.alpha, n->b.act,
+                     n->b.table_alloc};
     for (float *p : bufs)
         if (p) (void)hipFree(p);
     if (n->dev_loss) (void)hipFree(n->dev_loss);
@@ -1212,7 +1214,10 @@ int su2_nn_create(su2_nn **out, const float *params_host, uint64_t seed, void *h
     float **bufs[] = {&n->b.params, &n->b.grad, &n->b.m, &n->b.v};
     for (float **pp : bufs)
         if (e == hipSuccess) e = hipMalloc(pp, kNNParams * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&n->b.table, (size_t)kNNRows * kNNRow * sizeof(float));
+    const size_t tab_bytes = ((size_t)su2dev::kNNTablePad + (size_t)kNNRows * kNNRow) * sizeof(float);
+    if (e == hipSuccess) e = hipMalloc(&n->b.table_alloc, tab_bytes);
+    if (e == hipSuccess) e = hipMemset(n->b.table_alloc, 0, tab_bytes);
+    if (e == hipSuccess) n->b.table = n->b.table_alloc + su2dev::kNNTablePad;
     std::vector<float> init;
     if (!params_host) nn_default_params(seed, init);
     const float *src = params_host ? params_host : init.data();

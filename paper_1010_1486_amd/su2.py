@@ -295,7 +295,7 @@ def su2_test_gauge_transform(h, seed):
     _check(lib().su2_test_gauge_transform(h, int(seed)))
 
 
-NN_NPARAM, NN_ROWS, NN_ROW = 2671, 256, 48
+NN_NPARAM, NN_ROWS, NN_ROW = 2671, 64, 48
 
 
 def su2_nn_create(params=None, seed=0, stream=None):

@@ -101,14 +101,16 @@ def test_gradient_matches_finite_differences():
 def test_table_rows(orc):
     p = random_params(10)
     t = orc.nn_table(p)
-    for j in (0, 17, 128, 255):
-        f = -1 + 2 * j / 255
+    last = orc.NN_ROWS - 1
+    assert t.shape == (orc.NN_ROWS, 48)
+    for j in (0, 17, 32, last):
+        f = -1 + 2 * j / last
         x, y, d = orc.spline_from_raw(orc.nn_forward(p, f))
         np.testing.assert_allclose(t[j, :16], x[1:], atol=0)
         np.testing.assert_allclose(t[j, 16:32], y[1:], atol=0)
         np.testing.assert_allclose(t[j, 32:48], d[1:], atol=0)
-    assert orc.table_row(0.5)[0] == 0 and orc.table_row(30.0)[0] == 255
-    a_mid = 0.5 * 60 ** (0.5 / 255)  # halfway between rows 0 and 1
+    assert orc.table_row(0.5)[0] == 0 and orc.table_row(30.0)[0] == last
+    a_mid = 0.5 * 60 ** (0.5 / last)  # halfway between rows 0 and 1
     assert orc.table_row(a_mid * 1.001)[0] == 1 and orc.table_row(a_mid / 1.001)[0] == 0
 
 
