@@ -10,7 +10,9 @@ The roofline object reports the dominant kernel (the heat-bath pass):
 128 algorithmic bytes per link update (the pass reads U_nu, nu != mu, at both
 parities plus the opposite-parity U_mu, 56 V bytes, and writes 8 V bytes, for
 V/2 updates), divided by its average launch duration measured here with HIP
-events on the lattice's stream.
+events on the lattice's stream.  floor_us is the duration of a streaming
+kernel that moves exactly the same bytes without the stencil (each plane read
+at the thread's own index), the practical bound for this traffic mix.
 
 cpu_baseline: the FP64 CPU oracle as it stands, timed on the host cores on a
 bounded sample (one sweep of the same 48^4 lattice).
@@ -252,15 +254,21 @@ def other_configs(su2, torch, dev, with_cpu):
 def cpu_baseline(sample_sweeps=1):
     from oracle import su2_oracle as orc
     threads = orc.max_threads()
-    U = orc.init(DIMS, 1, SEED)
-    t0 = time.perf_counter()
-    orc.sweeps(DIMS, U, sample_sweeps, 0, BETA, SEED, nthreads=threads, measure=True)
-    dt = time.perf_counter() - t0
     V = int(np.prod(DIMS))
-    return {"value": 4 * V * sample_sweeps / dt, "unit": "link updates/s", "cores": threads,
+    rates = {}
+    for nt in (threads, 1):
+        U = orc.init(DIMS, 1, SEED)
+        t0 = time.perf_counter()
+        orc.sweeps(DIMS, U, sample_sweeps, 0, BETA, SEED, nthreads=nt, measure=True)
+        dt = time.perf_counter() - t0
+        rates[nt] = (4 * V * sample_sweeps / dt, dt)
+    return {"value": rates[threads][0], "unit": "link updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{sample_sweeps} FP64 sweep(s) + plaquette + Polyakov of the 48^4 "
-                      f"beta=6.0 hot-start lattice, {threads} OpenMP threads, {dt:.1f} s"}
+                      f"beta=6.0 hot-start lattice, {threads} OpenMP threads, "
+                      f"{rates[threads][1]:.1f} s",
+            "single_thread": {"value": rates[1][0], "cores": 1,
+                              "sample": f"the same sweep on 1 thread, {rates[1][1]:.1f} s"}}
 
 
 def main():
@@ -331,6 +339,16 @@ def main():
         e1.record(stream)
     e1.synchronize()
     pass_ms = e0.elapsed_time(e1) / args.pass_launches
+    # bandwidth floor: the same bytes per launch without the stencil
+    out_buf = torch.empty(2 * V, dtype=torch.float32, device=dev)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for i in range(args.pass_launches):
+            lat.test_stream_pass((i // 2) % 4, i % 2, out_buf)
+        e1.record(stream)
+    e1.synchronize()
+    floor_ms = e0.elapsed_time(e1) / args.pass_launches
+    del out_buf
     achieved = BYTES_PER_UPDATE * (V // 2) / (pass_ms * 1e-3) / 1e9
     traffic = traffic_from_profile()
 
@@ -350,7 +368,10 @@ def main():
                                      "calibration + WRITE_SIZE)",
                      "traffic_gbs": None if traffic is None else traffic / (pass_ms * 1e-3) / 1e9,
                      "kernel": "pass_kernel", "avg_launch_us": pass_ms * 1e3,
-                     "bytes_per_update": BYTES_PER_UPDATE, "updates_per_launch": V // 2},
+                     "bytes_per_update": BYTES_PER_UPDATE, "updates_per_launch": V // 2,
+                     "floor_us": floor_ms * 1e3,
+                     "floor_gbs": BYTES_PER_UPDATE * (V // 2) / (floor_ms * 1e-3) / 1e9,
+                     "frac_of_floor": floor_ms / pass_ms},
         "plaquette_mean_last_half": float(h[args.steps // 2:, 0].mean()),
         "autotuned_us_per_sweep": tuned_us,
         "launch": lat.launch(),

@@ -14,11 +14,12 @@
  *   Lattice     periodic Nx x Ny x Nz x Nt, every extent even and >= 2; site
  *               s = x + Nx*(y + Ny*(z + Nz*t)); mu = 0:x 1:y 2:z 3:t; parity
  *               (x+y+z+t) & 1.
- *   Links       U = a0 + i a.sigma stored as 4 FP32 reals.  Device layout: 32
- *               planes of V/2 floats, plane ((mu*2 + parity)*4 + c) holding
- *               component c of U_mu at the half-site h = s >> 1 of every site
- *               of that parity (64*V bytes).  Host exchange layout (get/set):
- *               float[V][4 mu][4 c] in canonical site order.
+ *   Links       U = a0 + i a.sigma stored as 4 FP32 reals (a float4).
+ *               Device layout: 8 arrays of V/2 float4, array (mu*2 + parity)
+ *               holding U_mu at the half-site h = s >> 1 of every site of
+ *               that parity, i.e. float[8][V/2][4] (64*V bytes; float
+ *               ((mu*2 + parity)*V/2 + h)*4 + c).  Host exchange layout
+ *               (get/set): float[V][4 mu][4 c] in canonical site order.
  *   Randoms     Philox4x32-10, key = seed, counter = (site, sweep index,
  *               mu | tag<<2 | replica<<6, draw).  Results are bit-identical
  *               for identical (links, seed, sweep index, replica, beta).
@@ -51,7 +52,7 @@ enum {
     SU2_ENOMEM = -3, /* device allocation failed, or caller buffer too small */
     SU2_EHIP = -4,   /* a HIP runtime call failed (message has the HIP error string) */
     SU2_ESTATE = -5, /* call not valid in the context's state (e.g. no proposal loaded) */
-    SU2_ERANGE = -6  /* a size exceeds the library's index range (V/2 >= 2^30) */
+    SU2_ERANGE = -6  /* a size exceeds the library's index range (V/2 >= 2^28) */
 };
 
 enum { SU2_COLD = 0, SU2_HOT = 1 };
@@ -129,7 +130,7 @@ int su2_set_sweep(su2_ctx *ctx, uint32_t sweep);
 int su2_set_beta(su2_ctx *ctx, double beta);
 int su2_set_replica(su2_ctx *ctx, uint32_t replica);
 
-/* Device pointer of the link planes and the context's hipStream_t. */
+/* Device pointer of the link arrays and the context's hipStream_t. */
 int su2_links_device(su2_ctx *ctx, void **links_dev, void **hip_stream);
 
 /* Wait for all work enqueued on the context's stream. */
@@ -261,6 +262,13 @@ int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_
 /* Enqueue one (mu, parity) pass at the current sweep index (index unchanged);
  * mode SU2_KP or SU2_LEARNED. */
 int su2_test_pass(su2_ctx *ctx, int mu, int parity, int mode);
+/* Bandwidth floor of a (mu, parity) pass (measurement aid): enqueue a kernel
+ * that moves the same bytes as the pass -- the seven plane groups it reads,
+ * each at the thread's own half-site, no stencil -- and writes the
+ * per-half-site sum of those seven quaternions to out_dev (caller-owned
+ * device memory, 4 planes of V/2 floats: out[c * V/2 + h]).  No link or
+ * counter of ctx changes. */
+int su2_test_stream_pass(su2_ctx *ctx, int mu, int parity, void *out_dev);
 /* Host-side evaluation (no GPU needed) of the pass kernel's index map for
  * extents dims and traversal tile tile_z x tile_t (0 = default): for each of
  * the V/2 thread indices g of a pass over `parity`, out[9g] = canonical site of

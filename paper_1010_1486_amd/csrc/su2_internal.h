@@ -94,6 +94,8 @@ hipError_t launch_set_counter(const Ens &e, uint32_t sweep, uint32_t meas, int w
 // results[R_COUNTS..] = proposals, accepts (as uint64); reset if asked.
 hipError_t launch_counts(const Ens &e, int reset, hipStream_t stream);
 hipError_t launch_gauge(const Ens &e, float *G, uint64_t seed, hipStream_t stream);
+// Streaming floor of a pass (single lattice): see stream_kernel.
+hipError_t launch_test_stream(const Ens &e, int mu, int par, float *out, hipStream_t stream);
 hipError_t launch_test_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
                               hipStream_t stream);
 hipError_t launch_test_links(const float *V, int64_t n, float beta, uint64_t seed,

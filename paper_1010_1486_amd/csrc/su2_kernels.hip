@@ -111,45 +111,48 @@ __device__ __forceinline__ uint32_t logical_block(uint32_t b, uint32_t nb, int r
     return (b & 7u) * per + local;
 }
 
-// One (mu, parity) plane group of the link field: four component planes at
-// uniform byte addresses in the global address space (so loads use a scalar
-// base and a 32-bit vector offset), indexed by a 32-bit byte offset.
+// One (mu, parity) class of the link field: an array of V/2 quaternions
+// (16-byte float4, components a0..a3) at a uniform byte address in the global
+// address space, so that a load is one 16-byte access with a scalar base and
+// a 32-bit vector offset (V/2 < 2^28 keeps h * 16 in 32 bits).
 typedef __attribute__((address_space(1))) const char gchar;
 typedef __attribute__((address_space(1))) const float gfloat;
 typedef __attribute__((address_space(1))) float gfloat_w;
+struct __attribute__((aligned(16))) F4 {
+    float x, y, z, w;
+};
+typedef __attribute__((address_space(1))) const F4 gf4;
+typedef __attribute__((address_space(1))) F4 gf4_w;
 
 struct Arr {
-    gchar *c0, *c1, *c2, *c3;
+    gchar *base;
 };
 
 __device__ __forceinline__ Arr arr(const float *links, uint32_t vh, int mu, int par)
 {
-    const size_t pb = (size_t)vh * 4u;
-    gchar *b = (gchar *)links + (size_t)((mu * 2 + par) * 4) * pb;
-    return Arr{b, b + pb, b + 2 * pb, b + 3 * pb};
+    return Arr{(gchar *)links + (size_t)(mu * 2 + par) * vh * 16u};
 }
 
 __device__ __forceinline__ Q ld(const Arr &a, uint32_t h)
 {
-    const uint32_t off = h * 4u;
-    return Q{*(gfloat *)(a.c0 + off), *(gfloat *)(a.c1 + off), *(gfloat *)(a.c2 + off),
-             *(gfloat *)(a.c3 + off)};
+    gf4 *p = (gf4 *)(a.base + h * 16u);
+    return Q{p->x, p->y, p->z, p->w};
 }
 
 __device__ __forceinline__ void st(float *links, uint32_t vh, int mu, int par, uint32_t h,
                                    const Q &q)
 {
-    gfloat_w *p = (gfloat_w *)links + (size_t)((mu * 2 + par) * 4) * vh + h;
-    p[0] = q.w;
-    p[vh] = q.x;
-    p[2 * (size_t)vh] = q.y;
-    p[3 * (size_t)vh] = q.z;
+    gf4_w *p = (gf4_w *)links + (size_t)(mu * 2 + par) * vh + h;
+    p->x = q.w;
+    p->y = q.x;
+    p->z = q.y;
+    p->w = q.z;
 }
 
 __device__ __forceinline__ Q ldq(const float *links, uint32_t vh, int mu, int par, uint32_t h)
 {
-    gfloat *p = (gfloat *)links + (size_t)((mu * 2 + par) * 4) * vh + h;
-    return Q{p[0], p[vh], p[2 * (size_t)vh], p[3 * (size_t)vh]};
+    gf4 *p = (gf4 *)links + (size_t)(mu * 2 + par) * vh + h;
+    return Q{p->x, p->y, p->z, p->w};
 }
 
 // ------------------------------------------------------------------- init
@@ -259,6 +262,33 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
             }
         }
     }
+}
+
+// ------------------------------------------------------- streaming floor
+// The byte pattern of a (mu, parity) pass without its stencil: the seven
+// plane groups a pass reads (U_nu at both parities for nu != mu, U_mu at the
+// opposite parity), each at the thread's own half-site, and four planes
+// written to `out` (V/2 floats each).  Its duration is the bandwidth floor
+// of the pass's traffic; no link is touched.
+__global__ __launch_bounds__(256) void stream_kernel(const Rep *__restrict__ reps, int mu,
+                                                     int par, float *__restrict__ out)
+{
+    const Rep &R = reps[0];
+    const uint32_t vh = R.g.vh;
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    const int opp = par ^ 1;
+    Q a = ld(arr(R.links, vh, mu, opp), h);
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        a = qadd(a, ld(arr(R.links, vh, nu, par), h));
+        a = qadd(a, ld(arr(R.links, vh, nu, opp), h));
+    }
+    gfloat_w *p = (gfloat_w *)out + h;
+    p[0] = a.w;
+    p[vh] = a.x;
+    p[2 * (size_t)vh] = a.y;
+    p[3 * (size_t)vh] = a.z;
 }
 
 // -------------------------------------------------------------- plaquette
@@ -610,6 +640,13 @@ hipError_t launch_gauge(const Ens &e, float *G, uint64_t seed, hipStream_t strea
                        e.reps, (float4 *)G, lo32(seed), hi32(seed));
     hipLaunchKernelGGL(gauge_apply_kernel, dim3(nblk(e.max_vh, 256), 8), dim3(256), 0, stream,
                        e.reps, (const float4 *)G);
+    return hipGetLastError();
+}
+
+hipError_t launch_test_stream(const Ens &e, int mu, int par, float *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(stream_kernel, dim3(nblk(e.max_vh, 256)), dim3(256), 0, stream, e.reps, mu,
+                       par, out);
     return hipGetLastError();
 }
 

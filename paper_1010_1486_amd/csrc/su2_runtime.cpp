@@ -41,6 +41,12 @@ using namespace su2rt;
 
 namespace {
 
+// Device position of component k of U_mu at half-site h of parity par.
+inline size_t dev_index(int mu, int par, int k, int64_t h, int64_t vh)
+{
+    return ((size_t)(mu * 2 + par) * (size_t)vh + (size_t)h) * 4u + (size_t)k;
+}
+
 int fail(int code, const std::string &msg)
 {
     set_error(msg);
@@ -56,7 +62,7 @@ int check_dims(const int32_t *dims)
                                       std::to_string(dims[i]) + " in direction " +
                                       std::to_string(i) + ")");
     int64_t v = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
-    if (v / 2 >= (int64_t)1 << 30) return fail(SU2_ERANGE, "V/2 must be < 2^30");
+    if (v / 2 >= (int64_t)1 << 28) return fail(SU2_ERANGE, "V/2 must be < 2^28");
     return SU2_OK;
 }
 
@@ -413,7 +419,7 @@ public:
             const int par = (x + y + z + t) & 1;
             for (int mu = 0; mu < 4; ++mu)
                 for (int k = 0; k < 4; ++k)
-                    host[(s * 4 + mu) * 4 + k] = planes[((mu * 2 + par) * 4 + k) * vh + (s >> 1)];
+                    host[(s * 4 + mu) * 4 + k] = planes[dev_index(mu, par, k, s >> 1, vh)];
         }
         return SU2_OK;
     }
@@ -434,7 +440,7 @@ public:
             const int par = (x + y + z + t) & 1;
             for (int mu = 0; mu < 4; ++mu)
                 for (int k = 0; k < 4; ++k)
-                    planes[((mu * 2 + par) * 4 + k) * vh + (s >> 1)] = host[(s * 4 + mu) * 4 + k];
+                    planes[dev_index(mu, par, k, s >> 1, vh)] = host[(s * 4 + mu) * 4 + k];
         }
         HIP_TRY(hipMemcpyAsync(links[r], planes.data(), planes.size() * 4, hipMemcpyHostToDevice,
                                stream));
@@ -1117,6 +1123,16 @@ int su2_test_pass(su2_ctx *c, int mu, int parity, int mode)
     const float *tab = c->E.mode_table(mode, &rc);
     if (rc) return rc;
     HIP_TRY(launch_pass(c->E.ens(), mu, parity, c->E.seed, false, tab, c->E.cfg, c->E.stream));
+    return SU2_OK;
+}
+
+int su2_test_stream_pass(su2_ctx *c, int mu, int parity, void *out_dev)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (mu < 0 || mu > 3 || parity < 0 || parity > 1 || !out_dev)
+        return fail(SU2_EINVAL, "bad mu/parity or NULL output");
+    HIP_TRY(launch_test_stream(c->E.ens(), mu, parity, static_cast<float *>(out_dev), c->E.stream));
     return SU2_OK;
 }
 

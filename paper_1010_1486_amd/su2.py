@@ -81,6 +81,7 @@ _SIGS = {
     "su2_test_heatbath_links": (_int, [_vp, _i64, _d, _u64, _u32, _u32, _u32, _vp, _vp]),
     "su2_test_pass": (_int, [_vp, _int, _int, _int]),
     "su2_test_gauge_transform": (_int, [_vp, _u64]),
+    "su2_test_stream_pass": (_int, [_vp, _int, _int, _vp]),
     "su2_test_index_map": (_int, [_vp, _int, _int, _int, _vp]),
     "su2_nn_num_params": (_int, []),
     "su2_nn_create": (_int, [_vp, _vp, _u64, _vp]),
@@ -108,6 +109,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(there is no CPU fallback)")
+        # torch brings its own HIP runtime (same soname).  Loading it first
+        # makes libsu2 bind to that runtime, so tensors, streams and kernels
+        # share one runtime; loading libsu2 first would put a second HIP
+        # runtime into the process and torch's device initialisation fails.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         l = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(l, name)
@@ -289,6 +298,10 @@ def su2_test_index_map(dims, parity, tile_z=0, tile_t=0):
     out = np.empty((vh, 9), dtype=np.uint32)
     _check(lib().su2_test_index_map(_p(d), int(tile_z), int(tile_t), int(parity), _p(out)))
     return out
+
+
+def su2_test_stream_pass(h, mu, parity, out_ptr):
+    _check(lib().su2_test_stream_pass(h, int(mu), int(parity), _vp(out_ptr)))
 
 
 def su2_test_gauge_transform(h, seed):
@@ -533,6 +546,11 @@ class Lattice:
 
     def test_pass(self, mu, parity, mode=SU2_KP):
         su2_test_pass(self.h, mu, parity, mode)
+
+    def test_stream_pass(self, mu, parity, out):
+        """out: float32 device tensor of at least 2 V elements."""
+        assert out.dtype == self.torch.float32 and out.numel() >= 2 * int(np.prod(self.dims))
+        su2_test_stream_pass(self.h, mu, parity, out.data_ptr())
 
     def test_gauge_transform(self, seed):
         su2_test_gauge_transform(self.h, seed)

@@ -39,9 +39,10 @@ def test_bad_arguments_rejected():
     with pytest.raises(su2.SU2Error) as e:
         su2.su2_init([4, 4, 4, 4], 2.0, 1, 7)
     assert e.value.code == su2.SU2_EINVAL
-    with pytest.raises(su2.SU2Error) as e:
-        su2.su2_init([2048, 2048, 2048, 2], 2.0, 1, su2.SU2_COLD)
-    assert e.value.code == su2.SU2_ERANGE
+    for dims in ([2048, 2048, 2048, 2], [512, 512, 512, 4]):  # V/2 >= 2^28
+        with pytest.raises(su2.SU2Error) as e:
+            su2.su2_init(dims, 2.0, 1, su2.SU2_COLD)
+        assert e.value.code == su2.SU2_ERANGE
     lib = su2.lib()
     assert lib.su2_init(None, None, 1.0, 1, 0) == su2.SU2_EINVAL
     assert lib.su2_heatbath_sweep(None, 1, 0) == su2.SU2_EINVAL

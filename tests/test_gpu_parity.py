@@ -112,3 +112,29 @@ def test_plaquette_history_config1(su2, orc):
             assert abs(hist[0, 1] - orc.polyakov(dims, got)[0]) < 1e-6
             if np.abs(got - U).max() < 1e-5:
                 assert abs(hist[0, 0] - ph[0]) < 1e-6
+
+
+def test_stream_floor_kernel_moves_the_pass_bytes(su2, orc):
+    """The streaming reference of a pass writes, per half-site, the sum of the
+    seven plane groups the pass reads and leaves the lattice untouched."""
+    import torch
+    announce("stream floor kernel")
+    dims = [4, 6, 2, 8]
+    V = int(np.prod(dims))
+    par_of = parities(orc, dims)
+    with su2.Lattice(dims, 2.0, 5, su2.SU2_HOT) as lat:
+        before = lat.get_links().astype(np.float64)
+        out = torch.zeros(2 * V, dtype=torch.float32, device="cuda:0")
+        for mu, p in ((0, 0), (3, 1)):
+            lat.test_stream_pass(mu, p, out)
+            lat.synchronize()
+            got = out.cpu().numpy().reshape(4, V // 2).sum(axis=1)
+            want = before[:, [n for n in range(4) if n != mu]].sum(axis=(0, 1)) + \
+                before[par_of != p, mu].sum(axis=0)
+            np.testing.assert_allclose(got, want, atol=1e-3)
+        np.testing.assert_array_equal(lat.get_links(), before.astype(np.float32))
+    with su2.Lattice(dims, 2.0, 5, su2.SU2_COLD) as lat:
+        lat.test_stream_pass(1, 0, out)
+        lat.synchronize()
+        o = out.cpu().numpy().reshape(4, V // 2)
+        assert np.all(o[0] == 7.0) and np.all(o[1:] == 0.0)
