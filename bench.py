@@ -98,10 +98,11 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
         net = su2.NN(seed=5)
         t0 = time.perf_counter()
         net.sample_data(10_000_000, 0.5, 30.0, seed=5)
-        hist = net.train(3000, 8192, 3e-3)
+        hist = net.train(20000, 16384, 3e-3, lr_end=1e-5)
         net.build_table()
         torch.cuda.synchronize()
-        out["training"] = {"samples": 10_000_000, "steps": 3000, "batch": 8192, "lr": 3e-3,
+        out["training"] = {"samples": 10_000_000, "steps": 20000, "batch": 16384,
+                           "lr": "cosine 3e-3 -> 1e-5",
                            "seconds": time.perf_counter() - t0,
                            "nll_first_100": float(hist[:100].mean()),
                            "nll_last_100": float(hist[-100:].mean())}

@@ -239,6 +239,10 @@ int su2_nn_loss_grad(su2_nn *nn, int64_t offset, int32_t batch, double *loss, fl
 /* `steps` Adam steps on consecutive minibatches of the data (wrapping);
  * loss_history_host (may be NULL) receives each step's mean NLL.  Synchronous. */
 int su2_nn_train(su2_nn *nn, int32_t steps, int32_t batch, double lr, double *loss_history_host);
+/* As su2_nn_train with a cosine learning-rate schedule: step t (0-based) uses
+ * lr1 + (lr0 - lr1)(1 + cos(pi t / steps))/2, from lr0 down towards lr1. */
+int su2_nn_train_cosine(su2_nn *nn, int32_t steps, int32_t batch, double lr0, double lr1,
+                        double *loss_history_host);
 /* Evaluate the 64-row spline table from the current parameters / copy it
  * (host float[64 * 48]). */
 int su2_nn_build_table(su2_nn *nn);

@@ -1359,9 +1359,23 @@ int su2_nn_loss_grad(su2_nn *n, int64_t offset, int32_t batch, double *loss, flo
     return SU2_OK;
 }
 
-int su2_nn_train(su2_nn *n, int32_t steps, int32_t batch, double lr, double *loss_history_host)
+// Learning rate of Adam step t of `steps`: constant lr0, or a cosine from
+// lr0 down towards lr1.
+struct LRSchedule {
+    double lr0, lr1;
+    int32_t steps;
+    bool cosine;
+    double at(int32_t t) const
+    {
+        if (!cosine) return lr0;
+        const double pi = 3.14159265358979323846;
+        return lr1 + 0.5 * (lr0 - lr1) * (1.0 + std::cos(pi * (double)t / (double)steps));
+    }
+};
+
+static int nn_train_steps(su2_nn *n, int32_t steps, int32_t batch, const LRSchedule &sched,
+                          double *loss_history_host)
 {
-    if (!n || steps < 0 || batch <= 0 || !(lr > 0.0)) return fail(SU2_EINVAL, "bad arguments");
     if (!n->ndata) return fail(SU2_ESTATE, "no training data");
     int rc = nn_reserve_act(n, batch);
     if (rc) return rc;
@@ -1378,7 +1392,7 @@ int su2_nn_train(su2_nn *n, int32_t steps, int32_t batch, double lr, double *los
     for (int32_t t = 0; t < steps; ++t) {
         HIP_TRY(launch_nn_step(n->b, offset, batch, n->ndata,
                                loss_history_host ? n->dev_loss + t : nullptr, n->stream));
-        HIP_TRY(launch_nn_adam(n->b, (float)lr, ++n->step, n->stream));
+        HIP_TRY(launch_nn_adam(n->b, (float)sched.at(t), ++n->step, n->stream));
         offset = (offset + batch) % n->ndata;
     }
     n->table_ready = false;
@@ -1389,6 +1403,20 @@ int su2_nn_train(su2_nn *n, int32_t steps, int32_t batch, double lr, double *los
     }
     HIP_TRY(hipStreamSynchronize(n->stream));
     return SU2_OK;
+}
+
+int su2_nn_train(su2_nn *n, int32_t steps, int32_t batch, double lr, double *loss_history_host)
+{
+    if (!n || steps < 0 || batch <= 0 || !(lr > 0.0)) return fail(SU2_EINVAL, "bad arguments");
+    return nn_train_steps(n, steps, batch, LRSchedule{lr, lr, steps, false}, loss_history_host);
+}
+
+int su2_nn_train_cosine(su2_nn *n, int32_t steps, int32_t batch, double lr0, double lr1,
+                        double *loss_history_host)
+{
+    if (!n || steps < 0 || batch <= 0 || !(lr0 > 0.0) || !(lr1 > 0.0))
+        return fail(SU2_EINVAL, "bad arguments");
+    return nn_train_steps(n, steps, batch, LRSchedule{lr0, lr1, steps, true}, loss_history_host);
 }
 
 int su2_nn_build_table(su2_nn *n)

@@ -93,6 +93,7 @@ _SIGS = {
     "su2_nn_get_data": (_int, [_vp, _vp, _vp, _vp]),
     "su2_nn_loss_grad": (_int, [_vp, _i64, _i32, _vp, _vp]),
     "su2_nn_train": (_int, [_vp, _i32, _i32, _d, _vp]),
+    "su2_nn_train_cosine": (_int, [_vp, _i32, _i32, _d, _d, _vp]),
     "su2_nn_build_table": (_int, [_vp]),
     "su2_nn_get_table": (_int, [_vp, _vp]),
     "su2_set_proposal": (_int, [_vp, _vp]),
@@ -366,6 +367,12 @@ def su2_nn_train(h, steps, batch, lr):
     return hist[:steps]
 
 
+def su2_nn_train_cosine(h, steps, batch, lr0, lr1):
+    hist = np.empty(max(int(steps), 1), dtype=np.float64)
+    _check(lib().su2_nn_train_cosine(h, int(steps), int(batch), float(lr0), float(lr1), _p(hist)))
+    return hist[:steps]
+
+
 def su2_nn_build_table(h):
     _check(lib().su2_nn_build_table(h))
 
@@ -436,8 +443,11 @@ class NN:
     def loss_grad(self, offset, batch):
         return su2_nn_loss_grad(self.h, offset, batch)
 
-    def train(self, steps, batch, lr=1e-3):
-        return su2_nn_train(self.h, steps, batch, lr)
+    def train(self, steps, batch, lr=1e-3, lr_end=None):
+        """Adam steps; with lr_end, a cosine schedule from lr down to lr_end."""
+        if lr_end is None:
+            return su2_nn_train(self.h, steps, batch, lr)
+        return su2_nn_train_cosine(self.h, steps, batch, lr, lr_end)
 
     def build_table(self):
         su2_nn_build_table(self.h)

@@ -187,3 +187,15 @@ def test_learned_and_exact_ensembles_agree(su2):
                 means.append(stats.mean_err(h))
     (m1, e1), (m2, e2) = means
     assert abs(m1 - m2) < 3 * np.hypot(e1, e2), means
+
+
+def test_cosine_schedule_with_equal_ends_is_constant_lr(su2):
+    announce("cosine schedule")
+    params = []
+    for cos in (False, True):
+        with su2.NN(seed=4) as net:
+            net.sample_data(50_000, 0.5, 30.0, seed=8)
+            h = net.train(30, 1024, 2e-3, lr_end=2e-3 if cos else None)
+            params.append(net.params)
+            assert np.all(np.isfinite(h))
+    np.testing.assert_array_equal(params[0], params[1])
