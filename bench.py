@@ -2,9 +2,11 @@
 
 Workload (headline): 48^4 periodic lattice, beta = 6.0, hot start (Philox seed 3).
 One step = one full sweep (8 checkerboard passes, Sec. 4 schedule) with the
-mean plaquette fused into the sweep, the Polyakov loop measured after it, and
-reunitarisation after every 10th sweep.  Throughput = link updates per second
-(4 V per sweep) with the links resident in HBM.
+mean plaquette of every sweep fused into its passes (the workload measures the
+plaquette each sweep) and reunitarisation after every 10th sweep.  Throughput
+= link updates per second (4 V per sweep) with the links resident in HBM.
+Other workloads (4^4, beta scans, 32^3 x Nt with the Polyakov loop, the
+batched learned-vs-plain comparison) are reported in the same JSON line.
 
 The roofline object reports the dominant kernel (the heat-bath pass):
 128 algorithmic bytes per link update (the pass reads U_nu, nu != mu, at both
@@ -252,6 +254,62 @@ def other_configs(su2, torch, dev, with_cpu):
     return out
 
 
+def _beta_scan(L):
+    b = np.round(np.arange(1.5, 3.0001, 0.1), 2)
+    return [[L] * 4] * (2 * len(b)), np.concatenate([b, b]), [0] * len(b) + [1] * len(b)
+
+
+def _polyakov_grid():
+    b = np.round(np.arange(2.0, 2.6001, 0.05), 2)
+    return [[32, 32, 32, nt] for nt in (4, 6, 8) for _ in b], np.concatenate([b] * 3), 0
+
+
+def _replicas64():
+    L = [8 + 2 * (r % 7) for r in range(64)]
+    return [[l] * 4 for l in L], np.random.default_rng(5).uniform(1.8, 3.0, 64), 1
+
+
+COUNTER_WORKLOADS = ("headline", "beta16", "beta24", "polyakov", "replicas64", "replicas64_learned")
+
+
+def counters_run(su2, torch, dev, lat, name):
+    """Counter runs: the workload with its autotuned launch, then the pass
+    launches whose counters are read (the last `pass_launches` pass_kernel
+    dispatches of the run), each updating `updates_per_launch` links."""
+    if name == "headline":
+        lat.autotune(None, su2.SU2_KP)
+        lat.heatbath_sweep(2)
+        for i in range(16):
+            lat.test_pass((i // 2) % 4, i % 2)
+        torch.cuda.synchronize()
+        return {"pass_launches": 16, "updates_per_launch": int(np.prod(DIMS)) // 2}
+    dims, betas, starts = {"beta16": lambda: _beta_scan(16), "beta24": lambda: _beta_scan(24),
+                           "polyakov": _polyakov_grid, "replicas64": _replicas64,
+                           "replicas64_learned": _replicas64}[name]()
+    learned = name.endswith("learned")
+    mode = su2.SU2_LEARNED if learned else su2.SU2_KP
+    meas = su2.SU2_MEAS_PLAQ | (su2.SU2_MEAS_POLY if name == "polyakov" else 0)
+    with torch.cuda.stream(torch.cuda.Stream(device=dev)):
+        net = None
+        if learned:
+            net = su2.NN(seed=5)
+            net.sample_data(2_000_000, 0.5, 30.0, seed=5)
+            net.train(4000, 16384, 3e-3, lr_end=1e-5)
+            net.build_table()
+        b = su2.Batch(dims, betas, starts, seed=5, device=dev)
+        if net is not None:
+            b.set_proposal(net)
+        b.autotune(None, mode)
+        b.sweep_measure(20, mode, reunit_every=10, meas=meas)
+        b.sweep_measure(8, mode, reunit_every=0, meas=meas)
+        b.synchronize()
+        b.close()
+        if net is not None:
+            net.close()
+    torch.cuda.synchronize()
+    return {"pass_launches": 64, "updates_per_launch": sum(int(np.prod(d)) for d in dims) // 2}
+
+
 def cpu_baseline(sample_sweeps=1):
     from oracle import su2_oracle as orc
     threads = orc.max_threads()
@@ -283,10 +341,12 @@ def main():
                     help="skip the batched plain-vs-learned comparison")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 4^4, beta-scan and Polyakov workloads")
-    ap.add_argument("--counters", action="store_true",
-                    help="short program for rocprofv3 --pmc runs: 16 pass launches in sweep "
-                         "order, then 4 plain device copies of the field size (339.7 MB) "
-                         "that calibrate FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--counters", nargs="?", const="headline", default=None,
+                    choices=list(COUNTER_WORKLOADS),
+                    help="short program for rocprofv3 --pmc runs: the workload's autotuned "
+                         "launch, then its last pass launches (16 for the 48^4 headline, 8 "
+                         "sweeps otherwise), then 4 plain device copies of 339.7 MB that "
+                         "calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -300,19 +360,18 @@ def main():
     V = int(np.prod(DIMS))
     lat = su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT, device=dev)
     stream = lat.stream
-    meas = su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY
+    meas = su2.SU2_MEAS_PLAQ
     hist = torch.zeros((max(args.steps, args.warmup, 1), 3), dtype=torch.float64, device=dev)
 
     if args.counters:
-        lat.heatbath_sweep(2)
-        for i in range(16):
-            lat.test_pass((i // 2) % 4, i % 2)
+        info = counters_run(su2, torch, dev, lat, args.counters)
         x = torch.ones(su2.su2_links_bytes(DIMS) // 4, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
         for _ in range(4):
             y.copy_(x)
         torch.cuda.synchronize()
-        print(json.dumps({"counters_run": True, "pass_launches": 16, "copy_bytes": 4 * x.numel()}))
+        info.update({"counters_run": args.counters, "copy_bytes": 4 * x.numel()})
+        print(json.dumps(info))
         lat.close()
         return
 
@@ -360,7 +419,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "48^4 periodic, beta=6.0, hot start (Philox seed 3); step = 1 "
-                               "heat-bath sweep (8 passes) + fused plaquette + Polyakov loop, "
+                               "heat-bath sweep (8 passes) + fused plaquette, "
                                "reunitarise every 10 sweeps",
                    "dims": DIMS, "beta": BETA, "links": 4 * V, "mode": "plain KP"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -57,6 +57,8 @@ def test_bad_arguments_rejected():
     rc = lib.su2_init_ext(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), 2.0, 1, 0,
                           ctypes.c_void_p(4096), 16, ctypes.c_void_p(8192), 16, None)
     assert rc == su2.SU2_ENOMEM
+    assert lib.su2_test_stream_pass(None, 0, 0, None) == su2.SU2_EINVAL
+    assert lib.su2_nn_train_cosine(None, 10, 64, 1e-3, 1e-5, None) == su2.SU2_EINVAL
     assert lib.su2_test_philox(None, -1, 0, None) == su2.SU2_EINVAL
     assert lib.su2_test_philox(None, 0, 0, None) == su2.SU2_OK
 
