@@ -92,3 +92,38 @@ def test_full_size_sweep_measurements(su2, orc):
         assert abs(lat.plaquette() - p) < 1e-6
         s, a = lat.polyakov()
         assert abs(s - ls) < 1e-6 and abs(a - la) < 1e-6
+
+
+def test_full_size_learned_pass(su2, orc):
+    """The learned Metropolis pass at 48^4 in its autotuned launch, on sampled
+    links (a random network, so proposals are accepted, rejected and, for
+    alpha outside the table range, replaced by the exact sampler)."""
+    from tests.gpu_util import learned_flagged, max_learned_flags
+    announce("48^4 sampled learned pass parity")
+    p = (np.random.default_rng(12).standard_normal(orc.NN_NPARAM) * 0.2).astype(np.float32)
+    table = orc.nn_table(p)
+    with su2.NN(params=p) as net, su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT) as lat:
+        net.build_table()
+        lat.set_proposal(net)
+        lat.autotune(None, su2.SU2_LEARNED)
+        lat.heatbath_sweep(2)
+        before = lat.get_links()
+        sweep = lat.sweep
+        lat.test_pass(1, 0, su2.SU2_LEARNED)
+        got = lat.get_links()
+        U = before.astype(np.float64)
+        sites = sample_sites(orc, 0, NSAMPLE, 300)
+        nflag, kinds, worst = 0, {-1: 0, 0: 0, 1: 0}, 0.0
+        for s in sites:
+            s = int(s)
+            V = orc.staple(DIMS, U, s, 1)
+            want, m, a = orc.learned_link(V, U[s, 1], table, BETA, SEED, s, sweep, 1)
+            if learned_flagged(m)[0]:
+                nflag += 1
+                continue
+            kinds[a] += 1
+            worst = max(worst, float(np.abs(got[s, 1] - want).max()))
+        print(f"[gpu-test] learned pass max err {worst:.2e}, outcomes {kinds}", flush=True)
+        assert worst < 1e-5
+        assert nflag <= max_learned_flags(len(sites))
+        assert kinds[0] > 0 and kinds[1] > 0
