@@ -63,9 +63,9 @@ enum { SU2_MEAS_PLAQ = 1, SU2_MEAS_POLY = 2 };
 const char *su2_last_error(void);
 
 /* Device bytes the caller must provide to su2_init_ext for these extents:
- * links 64*V; scratch 256 (sweep counter, history index, the fixed-point
- * accumulators of the global sums, FP64 result slots).  Return 0 when the
- * extents are invalid. */
+ * links 64*V; scratch about 131 KB (descriptor, sweep counter, history index,
+ * the fixed-point accumulators of the global sums in 256 buckets, FP64 result
+ * slots).  Return 0 when the extents are invalid or out of range. */
 size_t su2_links_bytes(const int32_t dims[4]);
 size_t su2_scratch_bytes(const int32_t dims[4]);
 
@@ -161,8 +161,10 @@ int su2_autotune(su2_ctx *ctx, const char *cache_path, int mode, double *best_us
  * `count` times with su2_replay_sweeps (one graph launch per replay; the
  * sweep index and the history row index advance on the device, so replay k
  * appends rows k*nsweeps..).  With reunit_every > 0, nsweeps must be a
- * multiple of it and the current sweep index a multiple of it.  Needs a
- * non-null stream; later launch or proposal changes drop the recording. */
+ * multiple of it and the current sweep index a multiple of it, and a replay
+ * is refused (SU2_ESTATE) unless the sweep index is again a multiple of it.
+ * Needs a non-null stream; later launch or proposal changes drop the
+ * recording. */
 int su2_capture_sweeps(su2_ctx *ctx, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
                        double *dev_history);
 int su2_replay_sweeps(su2_ctx *ctx, int32_t count);

@@ -61,8 +61,12 @@ int check_dims(const int32_t *dims)
             return fail(SU2_EODD, "every extent must be even and >= 2 (got " +
                                       std::to_string(dims[i]) + " in direction " +
                                       std::to_string(i) + ")");
-    int64_t v = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
-    if (v / 2 >= (int64_t)1 << 28) return fail(SU2_ERANGE, "V/2 must be < 2^28");
+    // multiply step by step so that huge extents cannot overflow
+    int64_t v = 1;
+    for (int i = 0; i < 4; ++i) {
+        v *= dims[i];
+        if (v / 2 >= (int64_t)1 << 28) return fail(SU2_ERANGE, "V/2 must be < 2^28");
+    }
     return SU2_OK;
 }
 
@@ -175,6 +179,7 @@ public:
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int32_t g_nsweeps = 0;
+    int32_t g_reunit = 0;  // reunitarisation period baked into the graph (0: none)
 
     static size_t descr_bytes(int n) { return align_up((size_t)n * sizeof(Rep), 256); }
     static size_t bmap_bytes(int n, const std::vector<std::array<int32_t, 4>> &d)
@@ -218,6 +223,7 @@ public:
         gexec = nullptr;
         graph = nullptr;
         g_nsweeps = 0;
+        g_reunit = 0;
     }
 
     // Geometry, workgroup ranges and descriptors (uploaded synchronously).
@@ -354,6 +360,7 @@ public:
         }
         graph = gr;
         g_nsweeps = ns;
+        g_reunit = reunit_every > 0 ? reunit_every : 0;
         return SU2_OK;
     }
 
@@ -361,6 +368,11 @@ public:
     {
         if (!gexec) return fail(SU2_ESTATE, "no captured sweeps");
         if (count < 0) return fail(SU2_EINVAL, "count must be >= 0");
+        // the graph's reunitarisation sweeps sit at fixed positions: replaying
+        // off a period boundary would move them away from the schedule
+        if (g_reunit > 0 && sweep % (uint32_t)g_reunit)
+            return fail(SU2_ESTATE, "replay must start at a reunitarisation period boundary "
+                                    "(sweeps were run since the capture)");
         for (int32_t i = 0; i < count; ++i) HIP_TRY(hipGraphLaunch(gexec, stream));
         sweep += (uint32_t)(count * g_nsweeps);
         return SU2_OK;
@@ -561,66 +573,85 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
         if (best_us) *best_us = best.us;
         return set_launch(best.block, best.flags, best.tz, best.tt, best.grid);
     }
-    // snapshot of the state the trial sweeps change
+    // Snapshot of everything the trial sweeps change: the links and each
+    // replica's counters, accumulators (accept statistics included) and
+    // result slots.  Every failure below still restores it.
+    const size_t rb = rep_bytes();
     std::vector<void *> saved(n, nullptr);
-    std::vector<Counters> cnt_saved(n);
-    for (int r = 0; r < n; ++r) {
+    void *rep_saved = nullptr;
+    hipError_t e = hipMalloc(&rep_saved, (size_t)n * rb);
+    for (int r = 0; r < n && e == hipSuccess; ++r) {
         const size_t b = (size_t)volume_of(dims[r].data()) * 64;
-        HIP_TRY(hipMalloc(&saved[r], b));
-        HIP_TRY(hipMemcpyAsync(saved[r], links[r], b, hipMemcpyDeviceToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(&cnt_saved[r], cnt(r), sizeof(Counters), hipMemcpyDeviceToHost,
-                               stream));
+        e = hipMalloc(&saved[r], b);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(saved[r], links[r], b, hipMemcpyDeviceToDevice, stream);
     }
-    HIP_TRY(hipStreamSynchronize(stream));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(rep_saved, rep_scratch(0), (size_t)n * rb, hipMemcpyDeviceToDevice,
+                           stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        for (void *p : saved)
+            if (p) (void)hipFree(p);
+        if (rep_saved) (void)hipFree(rep_saved);
+        return fail(SU2_EHIP, std::string("autotune snapshot: ") + hipGetErrorString(e));
+    }
     const uint32_t sweep0 = sweep;
+    const LaunchCfg cfg0 = cfg;
+    const uint32_t lz0 = lg_tz, lt0 = lg_tt;
     const int blocks[] = {256, 128};
     const int flagset[] = {1, 3};  // remap + alternating order, remap only
     const int tiles[][2] = {{8, 8}, {4, 8}, {2, 16}, {1, 1}, {16, 16}};
     const int grids[] = {0, 2048, 4096};
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
     best.us = 1e30;
     const int trial_sweeps = 2;
-    for (int b : blocks) {
-        for (int fl : flagset) {
-            for (auto &t : tiles) {
+    rc = SU2_OK;
+    for (int b : blocks)
+        for (int fl : flagset)
+            for (auto &t : tiles)
                 for (int gc : grids) {
+                    if (rc || e != hipSuccess) break;
                     if ((rc = set_launch(b, fl, t[0], t[1], gc))) break;
                     if ((rc = enqueue(1, mode, 0, 0, nullptr))) break;  // warm-up
-                    HIP_TRY(hipEventRecord(e0, stream));
+                    if ((e = hipEventRecord(e0, stream)) != hipSuccess) break;
                     if ((rc = enqueue(trial_sweeps, mode, 0, 0, nullptr))) break;
-                    HIP_TRY(hipEventRecord(e1, stream));
-                    HIP_TRY(hipEventSynchronize(e1));
+                    if ((e = hipEventRecord(e1, stream)) != hipSuccess) break;
+                    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
                     float ms = 0.0f;
-                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
                     const double us = 1e3 * ms / trial_sweeps;
                     if (us < best.us) best = TuneEntry{b, fl, t[0], t[1], gc, us};
                 }
-                if (rc) break;
-            }
-            if (rc) break;
-        }
-        if (rc) break;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     // restore the state whatever happened
-    hipError_t e = hipSuccess;
+    hipError_t er = hipStreamSynchronize(stream);
     for (int r = 0; r < n; ++r) {
         const size_t b = (size_t)volume_of(dims[r].data()) * 64;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(links[r], saved[r], b, hipMemcpyDeviceToDevice, stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(cnt(r), &cnt_saved[r], sizeof(Counters), hipMemcpyHostToDevice,
-                               stream);
+        if (er == hipSuccess)
+            er = hipMemcpyAsync(links[r], saved[r], b, hipMemcpyDeviceToDevice, stream);
     }
-    if (e == hipSuccess) e = launch_set_counter(ens(), 0, 0, 4, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (er == hipSuccess)
+        er = hipMemcpyAsync(rep_scratch(0), rep_saved, (size_t)n * rb, hipMemcpyDeviceToDevice,
+                            stream);
+    if (er == hipSuccess) er = hipStreamSynchronize(stream);
     for (void *p : saved) (void)hipFree(p);
+    (void)hipFree(rep_saved);
     sweep = sweep0;
-    if (e != hipSuccess) return fail(SU2_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-    if (rc) return rc;
+    if (er != hipSuccess)
+        return fail(SU2_EHIP, std::string("autotune restore: ") + hipGetErrorString(er));
+    if (e != hipSuccess) rc = fail(SU2_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    if (rc) {
+        // keep the launch configuration the ensemble had before
+        cfg = cfg0;
+        lg_tz = lz0;
+        lg_tt = lt0;
+        const int rc2 = upload();
+        return rc2 ? rc2 : rc;
+    }
     cache_store(cache_path, key, best);
     if (best_us) *best_us = best.us;
     return set_launch(best.block, best.flags, best.tz, best.tt, best.grid);
@@ -658,8 +689,10 @@ const char *su2_last_error(void) { return g_last_error.c_str(); }
 size_t su2_links_bytes(const int32_t dims[4])
 {
     if (!dims) return 0;
-    for (int i = 0; i < 4; ++i)
-        if (dims[i] < 2 || (dims[i] & 1)) return 0;
+    const std::string keep = g_last_error;  // a size query is not a failure
+    const int rc = check_dims(dims);
+    g_last_error = keep;
+    if (rc) return 0;
     return (size_t)64 * (size_t)volume_of(dims);
 }
 
@@ -1092,7 +1125,8 @@ int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_
                             int32_t *ntrials_host)
 {
     if (n < 0 || (n > 0 && (!V_host || !out_host))) return fail(SU2_EINVAL, "bad arguments");
-    if (!std::isfinite(beta) || mu > 3) return fail(SU2_EINVAL, "bad beta or mu");
+    if (!std::isfinite(beta) || mu > 3 || replica >= (1u << 26))
+        return fail(SU2_EINVAL, "bad beta, mu or replica");
     if (n >= ((int64_t)1 << 32)) return fail(SU2_ERANGE, "n must be < 2^32");
     if (n == 0) return SU2_OK;
     void *d_v = nullptr, *d_o = nullptr, *d_t = nullptr;

@@ -21,6 +21,9 @@ def test_sizes():
     assert su2.su2_links_bytes([4, 4, 4, 4]) == 64 * 256
     assert su2.su2_links_bytes([48, 48, 48, 48]) == 64 * 48 ** 4
     assert su2.su2_links_bytes([3, 4, 4, 4]) == 0
+    assert su2.su2_links_bytes([512, 512, 512, 4]) == 0  # V/2 = 2^28: out of range
+    assert su2.su2_links_bytes([1 << 30] * 4) == 0  # no overflow
+    assert su2.su2_links_bytes([512, 512, 512, 2]) == 64 * 512 ** 3 * 2
     assert su2.su2_scratch_bytes([4, 4, 4, 4]) >= 256
 
 

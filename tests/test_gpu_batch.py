@@ -57,6 +57,14 @@ def test_graph_replay_equals_direct(su2):
             np.testing.assert_array_equal(hg.cpu().numpy(), ha)
             for r in range(len(DIMS)):
                 np.testing.assert_array_equal(g.get_links(r), a.get_links(r))
+            # off the reunitarisation period the recorded schedule would drift
+            g.sweep(1)
+            with pytest.raises(su2.SU2Error) as e:
+                g.replay(1)
+            assert e.value.code == su2.SU2_ESTATE
+            g.sweep(3)
+            g.replay(1)
+            g.synchronize()
         with su2.Lattice([8, 8, 8, 8], 2.2, 3, su2.SU2_HOT) as x, \
                 su2.Lattice([8, 8, 8, 8], 2.2, 3, su2.SU2_HOT) as y:
             x.heatbath_sweep(6)
@@ -152,3 +160,19 @@ def test_batch_errors(su2):
             b.replay(1)
         with pytest.raises(su2.SU2Error):
             b.capture(3)  # null stream
+
+
+def test_autotune_keeps_accept_statistics(su2):
+    """The trial sweeps of the autotuner leave the learned accept counts (and
+    every other accumulator) as they were."""
+    announce("autotune keeps accept statistics")
+    with su2.NN(seed=2) as net, su2.Batch(DIMS, BETAS, STARTS, 9) as b:
+        net.build_table()
+        b.set_proposal(net)
+        b.sweep(3, su2.SU2_LEARNED)
+        p0, a0 = b.accept_stats()
+        assert p0.sum() > 0
+        b.autotune(None, su2.SU2_LEARNED)
+        p1, a1 = b.accept_stats()
+        np.testing.assert_array_equal(p0, p1)
+        np.testing.assert_array_equal(a0, a1)
