@@ -86,7 +86,8 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
     exact-sampler draws (alpha log-uniform in [0.5, 30]).  Each mode: autotuned
     launch, then graph-captured chunks of batched sweeps with the plaquette
     measured every sweep.  Effective rate = sweeps/s / (2 tau_int(P)), averaged
-    over the replicas."""
+    over the replicas.  The untrained network (identity spline, i.e. a uniform
+    proposal) runs the same protocol for comparison."""
     n = 64
     L = [8 + 2 * (r % 7) for r in range(n)]
     dims = [[l] * 4 for l in L]
@@ -108,9 +109,12 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
                            "seconds": time.perf_counter() - t0,
                            "nll_first_100": float(hist[:100].mean()),
                            "nll_last_100": float(hist[-100:].mean())}
-        for name, mode in (("plain", su2.SU2_KP), ("learned", su2.SU2_LEARNED)):
+        untrained = su2.NN(seed=5)  # identity spline: the uniform proposal
+        untrained.build_table()
+        for name, mode, proposal in (("plain", su2.SU2_KP, net), ("learned", su2.SU2_LEARNED, net),
+                                     ("learned_untrained", su2.SU2_LEARNED, untrained)):
             b = su2.Batch(dims, betas, [1] * n, seed=5, device=dev)
-            b.set_proposal(net)
+            b.set_proposal(proposal)
             tuned_us = b.autotune(None, mode)
             b.sweep(therm, mode)
             b.accept_stats(reset=True)
@@ -133,6 +137,7 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
                          "mean_plaquette": float(P.mean())}
             b.close()
         net.close()
+        untrained.close()
     torch.cuda.synchronize()
     out["learned_over_plain_updates"] = (out["learned"]["link_updates_per_s"] /
                                          out["plain"]["link_updates_per_s"])

@@ -138,12 +138,16 @@ int su2_synchronize(su2_ctx *ctx);
 
 /* Launch configuration of the pass kernel: block size (64, 128, 192 or 256
  * threads); flags: bit 0 = XCD-contiguous workgroup remap, bit 1 = disable
- * the alternating (forward, backward) pass order; the traversal tile of
- * (z, t) planes, tile_z x tile_t (powers of two <= 256, clipped to divisors
- * of Nz and Nt; 0 keeps the current value); grid_cap > 0 runs the pass as a
- * persistent grid of at most grid_cap workgroups looping over the work (0 =
- * one workgroup per tile).  Results do not depend on it.  Drops captured
- * sweeps. */
+ * the alternating (forward, backward) pass order, bit 2 = disable the
+ * whole-sweep kernel for small lattices (by default, when every V/2 <= 2048,
+ * one launch runs whole sweeps with one workgroup per lattice); the traversal
+ * tile of (z, t) planes, tile_z x tile_t (powers of two <= 256, clipped to
+ * divisors of Nz and Nt; 0 keeps the current value); grid_cap > 0 runs the
+ * pass as a persistent grid of at most grid_cap workgroups looping over the
+ * work (0 = one workgroup per tile).  Links do not depend on it; the
+ * whole-sweep kernel rounds each site's plaquette and Polyakov value to the
+ * 2^-28 fixed point instead of each workgroup's sum (differences ~1e-9).
+ * Drops captured sweeps. */
 int su2_set_launch(su2_ctx *ctx, int block, int flags, int tile_z, int tile_t, int grid_cap);
 /* Current launch configuration (tiles as applied to this lattice's extents). */
 int su2_get_launch(su2_ctx *ctx, int *block, int *flags, int *tile_z, int *tile_t, int *grid_cap);
@@ -198,6 +202,9 @@ int su2_batch_get_links(su2_batch *b, int32_t replica, float *host);
 int su2_batch_set_links(su2_batch *b, int32_t replica, const float *host);
 int su2_batch_set_launch(su2_batch *b, int block, int flags, int tile_z, int tile_t,
                          int grid_cap);
+/* The batch's launch configuration (as su2_get_launch; tiles of replica 0). */
+int su2_batch_get_launch(su2_batch *b, int *block, int *flags, int *tile_z, int *tile_t,
+                         int *grid_cap);
 int su2_batch_autotune(su2_batch *b, const char *cache_path, int mode, double *best_us);
 int su2_batch_synchronize(su2_batch *b);
 /* Per-replica learned proposals made / accepted (host uint64[n] each). */

@@ -57,7 +57,12 @@ struct LaunchCfg {
     bool xcd_remap = true;
     bool snake = true;        // odd-parity passes traverse backwards
     uint32_t grid_cap = 0;    // > 0: persistent pass grid of at most this many workgroups
+    bool small = true;        // whole sweeps in one launch when every V/2 <= kSmallMaxVh
 };
+
+// Largest V/2 of the whole-sweep kernel (one workgroup per replica, up to
+// 1024 threads, 2 sites per thread).
+constexpr uint32_t kSmallMaxVh = 2048;
 
 // Everything a launch needs to address an ensemble on the device.
 struct Ens {
@@ -88,6 +93,13 @@ hipError_t launch_take(const Ens &e, int flags, hipStream_t stream);
 // hist[3 * (meas_idx * nrep + r)].  Resets the accumulators, advances sweep.
 hipError_t launch_sweep_end(const Ens &e, int flags, double *hist, hipStream_t stream);
 hipError_t launch_reunitarize(const Ens &e, hipStream_t stream);
+// ns whole sweeps of every replica (all V/2 <= kSmallMaxVh) in one launch:
+// passes, reunitarisation every reunit_every sweeps (absolute sweep index),
+// measurements (flags 1 plaquette, 2 Polyakov loop, 4 history rows at
+// hist[3 * (meas_idx * nrep + r)]); advances the sweep and row counters.
+// table != nullptr: learned-proposal Metropolis updates.
+hipError_t launch_small_sweeps(const Ens &e, int ns, uint64_t seed, int reunit_every, int flags,
+                               double *hist, const float *table, hipStream_t stream);
 // which: 1 set sweep, 2 set meas_idx, 4 zero all accumulators, 8 zero counts.
 hipError_t launch_set_counter(const Ens &e, uint32_t sweep, uint32_t meas, int which,
                               hipStream_t stream);

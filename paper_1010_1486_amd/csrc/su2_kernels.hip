@@ -175,6 +175,67 @@ __global__ void init_kernel(const Rep *__restrict__ reps, const int *__restrict_
 }
 
 // ------------------------------------------------------------------- pass
+// Update of the link U_MU at half-site index gid (pass order) of parity par:
+// the six-staple sum V (Sec. 2), then the exact heat bath or, with LEARNED,
+// the learned-proposal Metropolis step; the new link is stored.  With
+// MEASURE, meas = (1/2)Tr(U'_MU V_nu) summed over nu < MU.  acc: as
+// learned_link (-1 for the heat bath).
+template <int MU, bool MEASURE, bool LEARNED>
+__device__ __forceinline__ void update_site(const Rep &R, uint32_t gid, int par, uint32_t sweep,
+                                            uint32_t k0, uint32_t k1, const float *ltab,
+                                            float &meas, int &acc)
+{
+    const Geom &g = R.g;
+    const int opp = par ^ 1;
+    const float *links = R.links;
+    const PassSite s = pass_site(g, gid, par);
+    const Deltas d = neighbour_deltas(g, s);
+    const uint32_t h = s.h;
+    const Arr Umu_o = arr(links, g.vh, MU, opp);
+    Q V{0.0f, 0.0f, 0.0f, 0.0f};
+    Q Vlow{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == MU) continue;
+        const Arr Unu_p = arr(links, g.vh, nu, par);
+        const Arr Unu_o = arr(links, g.vh, nu, opp);
+        // forward: U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
+        const Q A = ld(Unu_o, h + d.p[MU]);
+        const Q B = ld(Umu_o, h + d.p[nu]);
+        const Q C = ld(Unu_p, h);
+        // backward: U_nu(s+mu-nu)^+ U_mu(s-nu)^+ U_nu(s-nu) = (E D)^+ F
+        const Q D = ld(Unu_p, h + d.p[MU] + d.m[nu]);
+        const Q E = ld(Umu_o, h + d.m[nu]);
+        const Q F = ld(Unu_o, h + d.m[nu]);
+        const Q st = qadd(qmul(qmul(A, qdag(B)), qdag(C)), qmul(qdag(qmul(E, D)), F));
+        V = qadd(V, st);
+        if (MEASURE && nu < MU) Vlow = qadd(Vlow, st);
+    }
+    const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
+    Q Un;
+    if (LEARNED) {
+        const Q Uold = ld(arr(links, g.vh, MU, par), h);
+        Un = learned_link(V, Uold, ltab, R.beta, site, sweep, (uint32_t)MU, R.replica, k0, k1,
+                          acc);
+    } else {
+        Un = heatbath_link(V, R.beta, site, sweep, word2((uint32_t)MU, TAG_TRIAL, R.replica), k0,
+                           k1);
+    }
+    st(R.links, g.vh, MU, par, h, Un);
+    if (MEASURE) meas = retr(Un, Vlow);
+}
+
+// Fill the LDS copy of the spline table (4 floats of padding first, like the
+// device copy); every thread of the workgroup takes part.
+__device__ __forceinline__ const float *load_table_lds(float4 *stab4, const float *table)
+{
+    const float4 *t4 = reinterpret_cast<const float4 *>(table);
+    for (int i = threadIdx.x; i < kNNRows * kNNRow / 4; i += blockDim.x) stab4[1 + i] = t4[i];
+    if (threadIdx.x == 0) stab4[0] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+    __syncthreads();
+    return reinterpret_cast<const float *>(stab4) + 4;
+}
+
 // One heat-bath pass over the sites of parity `par` in direction MU, for
 // every replica of the ensemble.  Workgroup ids b in [0, total) are mapped
 // to replicas by bmap (each replica's range starts at a multiple of 8, so
@@ -189,16 +250,9 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
                                                    uint32_t k1, int remap, int reverse,
                                                    const float *__restrict__ table)
 {
-    // LEARNED: the spline table in LDS (filled once per workgroup), preceded
-    // by 4 floats of padding like the device copy
+    // LEARNED: the spline table in LDS (filled once per workgroup)
     __shared__ float4 stab4[LEARNED ? 1 + kNNRows * kNNRow / 4 : 1];
-    if (LEARNED) {
-        const float4 *t4 = reinterpret_cast<const float4 *>(table);
-        for (int i = threadIdx.x; i < kNNRows * kNNRow / 4; i += blockDim.x) stab4[1 + i] = t4[i];
-        if (threadIdx.x == 0) stab4[0] = float4{0.0f, 0.0f, 0.0f, 0.0f};
-        __syncthreads();
-    }
-    const float *ltab = reinterpret_cast<const float *>(stab4) + 4;
+    const float *ltab = LEARNED ? load_table_lds(stab4, table) : nullptr;
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
         const Rep &R = reps[bmap ? bmap[b] : 0u];
         const uint32_t local = b - R.first_block;
@@ -212,43 +266,7 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
             // uniform: a scalar load through the constant address space
             const uint32_t sweep =
                 *(const __attribute__((address_space(4))) uint32_t *)&R.cnt->sweep;
-            const int opp = par ^ 1;
-            const float *links = R.links;
-            const PassSite s = pass_site(g, gid, par);
-            const Deltas d = neighbour_deltas(g, s);
-            const uint32_t h = s.h;
-            const Arr Umu_o = arr(links, g.vh, MU, opp);
-            Q V{0.0f, 0.0f, 0.0f, 0.0f};
-            Q Vlow{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int nu = 0; nu < 4; ++nu) {
-                if (nu == MU) continue;
-                const Arr Unu_p = arr(links, g.vh, nu, par);
-                const Arr Unu_o = arr(links, g.vh, nu, opp);
-                // forward: U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
-                const Q A = ld(Unu_o, h + d.p[MU]);
-                const Q B = ld(Umu_o, h + d.p[nu]);
-                const Q C = ld(Unu_p, h);
-                // backward: U_nu(s+mu-nu)^+ U_mu(s-nu)^+ U_nu(s-nu) = (E D)^+ F
-                const Q D = ld(Unu_p, h + d.p[MU] + d.m[nu]);
-                const Q E = ld(Umu_o, h + d.m[nu]);
-                const Q F = ld(Unu_o, h + d.m[nu]);
-                const Q st = qadd(qmul(qmul(A, qdag(B)), qdag(C)), qmul(qdag(qmul(E, D)), F));
-                V = qadd(V, st);
-                if (MEASURE && nu < MU) Vlow = qadd(Vlow, st);
-            }
-            const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
-            Q Un;
-            if (LEARNED) {
-                const Q Uold = ld(arr(links, g.vh, MU, par), h);
-                Un = learned_link(V, Uold, ltab, R.beta, site, sweep, (uint32_t)MU, R.replica,
-                                  k0, k1, acc);
-            } else {
-                Un = heatbath_link(V, R.beta, site, sweep,
-                                   word2((uint32_t)MU, TAG_TRIAL, R.replica), k0, k1);
-            }
-            st(R.links, g.vh, MU, par, h, Un);
-            if (MEASURE) meas = retr(Un, Vlow);
+            update_site<MU, MEASURE, LEARNED>(R, gid, par, sweep, k0, k1, ltab, meas, acc);
         }
         if (MEASURE) block_accumulate((double)meas, R.acc, ACC_PLAQ, b);
         if (LEARNED) {
@@ -292,6 +310,32 @@ __global__ __launch_bounds__(256) void stream_kernel(const Rep *__restrict__ rep
 }
 
 // -------------------------------------------------------------- plaquette
+// Sum of (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+ over mu < nu at
+// site i of [0, V) in pass order (parity 0 first), as (1/2)Tr(P Q^+) with
+// P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
+__device__ __forceinline__ float site_plaquettes(const Rep &R, uint32_t i)
+{
+    const Geom &g = R.g;
+    const int par = i >= g.vh ? 1 : 0;
+    const int opp = par ^ 1;
+    const float *links = R.links;
+    const PassSite s = pass_site(g, par ? i - g.vh : i, par);
+    const Deltas d = neighbour_deltas(g, s);
+    Q U[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) U[mu] = ld(arr(links, g.vh, mu, par), s.h);
+    float sum = 0.0f;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int nu = mu + 1; nu < 4; ++nu) {
+            const Q P = qmul(U[mu], ld(arr(links, g.vh, nu, opp), s.h + d.p[mu]));
+            const Q Qq = qmul(U[nu], ld(arr(links, g.vh, mu, opp), s.h + d.p[nu]));
+            sum += retr_adj(P, Qq);
+        }
+    return sum;
+}
+
 // grid (blocks over V, 1, replica).  One thread per site, both parities, in
 // the pass traversal order: (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
 // = (1/2)Tr(P Q^+) with P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
@@ -304,26 +348,7 @@ __global__ __launch_bounds__(256) void plaquette_kernel(const Rep *__restrict__ 
     const uint32_t blk = logical_block(blockIdx.x, nb, remap, 0);
     const uint32_t i = blk * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    if (i < 2u * g.vh) {
-        const int par = i >= g.vh ? 1 : 0;
-        const int opp = par ^ 1;
-        const float *links = R.links;
-        const PassSite s = pass_site(g, par ? i - g.vh : i, par);
-        const Deltas d = neighbour_deltas(g, s);
-        Q U[4];
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) U[mu] = ld(arr(links, g.vh, mu, par), s.h);
-        float sum = 0.0f;
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-            for (int nu = mu + 1; nu < 4; ++nu) {
-                const Q P = qmul(U[mu], ld(arr(links, g.vh, nu, opp), s.h + d.p[mu]));
-                const Q Qq = qmul(U[nu], ld(arr(links, g.vh, mu, opp), s.h + d.p[nu]));
-                sum += retr_adj(P, Qq);
-            }
-        acc = (double)sum;
-    }
+    if (i < 2u * g.vh) acc = (double)site_plaquettes(R, i);
     block_accumulate(acc, R.acc, ACC_PLAQ, blockIdx.x);
 }
 
@@ -453,12 +478,9 @@ __global__ __launch_bounds__(kBuckets) void set_counter_kernel(const Rep *__rest
 
 // --------------------------------------------------------------- reunit
 // grid (blocks over V/2, 8, replica).  U <- U / |U|, |U|^2 in FP64.
-__global__ __launch_bounds__(256) void reunit_kernel(const Rep *__restrict__ reps)
+// U <- U / |U| with the norm in FP64.
+__device__ __forceinline__ void reunit_link(const Rep &R, int mu, int par, uint32_t h)
 {
-    const Rep &R = reps[blockIdx.z];
-    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= R.g.vh) return;
-    const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
     const Q q = ldq(R.links, R.g.vh, mu, par, h);
     const double n2 = (double)q.w * q.w + (double)q.x * q.x + (double)q.y * q.y +
                       (double)q.z * q.z;
@@ -467,7 +489,147 @@ __global__ __launch_bounds__(256) void reunit_kernel(const Rep *__restrict__ rep
        Q{(float)(q.w * inv), (float)(q.x * inv), (float)(q.y * inv), (float)(q.z * inv)});
 }
 
+__global__ __launch_bounds__(256) void reunit_kernel(const Rep *__restrict__ reps)
+{
+    const Rep &R = reps[blockIdx.z];
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= R.g.vh) return;
+    reunit_link(R, blockIdx.y >> 1, blockIdx.y & 1, h);
+}
+
 // ---------------------------------------------------------- gauge (tests)
+
+// ----------------------------------------------------------- small lattices
+// Whole sweeps of small lattices in one launch: workgroup r runs replica r
+// alone -- the 8 passes of a sweep separated by workgroup barriers, the
+// plaquette (fused into the odd passes of mu = 1, 2, 3, or recomputed after
+// a reunitarisation), the Polyakov loop, the reunitarisation and the history
+// row -- for ns sweeps.  Link updates are the pass kernel's, bit for bit.
+// Each site's plaquette and Polyakov value is added in 64-bit fixed point,
+// so the sums do not depend on the workgroup size.
+template <int MU, bool LEARNED>
+__device__ __forceinline__ void small_pass(const Rep &R, int par, bool measure, uint32_t sweep,
+                                           uint32_t k0, uint32_t k1, const float *ltab,
+                                           unsigned long long &psum, unsigned long long &np,
+                                           unsigned long long &na)
+{
+    for (uint32_t gid = threadIdx.x; gid < R.g.vh; gid += blockDim.x) {
+        float m = 0.0f;
+        int a = -1;
+        if (measure) {
+            update_site<MU, true, LEARNED>(R, gid, par, sweep, k0, k1, ltab, m, a);
+            psum += to_fixed((double)m);
+        } else {
+            update_site<MU, false, LEARNED>(R, gid, par, sweep, k0, k1, ltab, m, a);
+        }
+        np += a >= 0 ? 1ull : 0ull;
+        na += a == 1 ? 1ull : 0ull;
+    }
+    __syncthreads();
+}
+
+// Exact sum over the workgroup of 64-bit integers (valid in thread 0).
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v)
+{
+    __shared__ unsigned long long wpart[16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) wpart[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long t = 0ull;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) t += wpart[i];
+    __syncthreads();
+    return t;
+}
+
+// flags: 1 plaquette, 2 Polyakov loop, 4 history rows.
+template <bool LEARNED>
+__global__ __launch_bounds__(1024) void small_sweeps_kernel(const Rep *__restrict__ reps, int nrep,
+                                                            int ns, uint32_t k0, uint32_t k1,
+                                                            int reunit_every, int flags,
+                                                            double *__restrict__ hist,
+                                                            const float *__restrict__ table)
+{
+    __shared__ float4 stab4[LEARNED ? 1 + kNNRows * kNNRow / 4 : 1];
+    const float *ltab = LEARNED ? load_table_lds(stab4, table) : nullptr;
+    const Rep &R = reps[blockIdx.x];
+    const Geom &g = R.g;
+    const uint32_t ns3 = (uint32_t)g.nx * g.ny * g.nz;
+    uint32_t sweep = R.cnt->sweep;  // written back by thread 0 at the end
+    uint32_t midx = R.cnt->meas_idx;
+    unsigned long long np = 0ull, na = 0ull;
+    const bool want_p = (flags & 1) != 0, want_l = (flags & 2) != 0;
+    const bool rows = (flags & 4) != 0 && hist != nullptr;
+    for (int i = 0; i < ns; ++i, ++sweep) {
+        const bool reunit = reunit_every > 0 && ((sweep + 1u) % (uint32_t)reunit_every) == 0u;
+        const bool fused = want_p && !reunit;
+        unsigned long long psum = 0ull, lsum = 0ull;
+        small_pass<0, LEARNED>(R, 0, false, sweep, k0, k1, ltab, psum, np, na);
+        small_pass<0, LEARNED>(R, 1, false, sweep, k0, k1, ltab, psum, np, na);
+        small_pass<1, LEARNED>(R, 0, false, sweep, k0, k1, ltab, psum, np, na);
+        small_pass<1, LEARNED>(R, 1, fused, sweep, k0, k1, ltab, psum, np, na);
+        small_pass<2, LEARNED>(R, 0, false, sweep, k0, k1, ltab, psum, np, na);
+        small_pass<2, LEARNED>(R, 1, fused, sweep, k0, k1, ltab, psum, np, na);
+        small_pass<3, LEARNED>(R, 0, false, sweep, k0, k1, ltab, psum, np, na);
+        small_pass<3, LEARNED>(R, 1, fused, sweep, k0, k1, ltab, psum, np, na);
+        if (reunit) {
+            for (uint32_t j = threadIdx.x; j < 8u * g.vh; j += blockDim.x) {
+                const uint32_t grp = j / g.vh;
+                reunit_link(R, (int)(grp >> 1), (int)(grp & 1u), j - grp * g.vh);
+            }
+            __syncthreads();
+            if (want_p)
+                for (uint32_t j = threadIdx.x; j < 2u * g.vh; j += blockDim.x)
+                    psum += to_fixed((double)site_plaquettes(R, j));
+        }
+        if (want_l) {
+            // L(x) = (1/2)Tr prod_t U_3(x, t), t = 0 leftmost
+            for (uint32_t xs = threadIdx.x; xs < ns3; xs += blockDim.x) {
+                const uint32_t x = xs % (uint32_t)g.nx, r = xs / (uint32_t)g.nx;
+                const uint32_t y = r % (uint32_t)g.ny, z = r / (uint32_t)g.ny;
+                const uint32_t pbase = (x + y + z) & 1u;
+                Q P{1.0f, 0.0f, 0.0f, 0.0f};
+                for (int t = 0; t < g.nt; ++t)
+                    P = qmul(P, ldq(R.links, g.vh, 3, (int)((pbase + (uint32_t)t) & 1u),
+                                    (xs >> 1) + (uint32_t)t * (ns3 >> 1)));
+                lsum += to_fixed((double)P.w);
+            }
+        }
+        const unsigned long long tp = block_sum_u64(psum);
+        const unsigned long long tl = block_sum_u64(lsum);
+        if (rows) {
+            if (threadIdx.x == 0) {
+                const double p = want_p ? from_fixed(tp) / (12.0 * (double)g.vh) : 0.0;
+                const double l = want_l ? from_fixed(tl) / (double)ns3 : 0.0;
+                double *row = hist + 3 * ((size_t)midx * nrep + blockIdx.x);
+                row[0] = p;
+                row[1] = l;
+                row[2] = fabs(l);
+            }
+            ++midx;
+        }
+    }
+    if (LEARNED) {
+        // per-wave totals added by lane 0 of each wave
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            np += __shfl_down(np, off, 64);
+            na += __shfl_down(na, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            const uint32_t wb = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+            if (np) atomicAdd(bucket(R.acc, ACC_PROPOSED, wb), np);
+            if (na) atomicAdd(bucket(R.acc, ACC_ACCEPTED, wb), na);
+        }
+    }
+    __syncthreads();  // every thread has read the counters before they change
+    if (threadIdx.x == 0) {
+        R.cnt->sweep = sweep;
+        R.cnt->meas_idx = midx;
+    }
+}
+
 // Replica 0 only (G holds one field of gauge rotations).
 __global__ void gauge_gen_kernel(const Rep *__restrict__ reps, float4 *__restrict__ G,
                                  uint32_t k0, uint32_t k1)
@@ -640,6 +802,20 @@ hipError_t launch_gauge(const Ens &e, float *G, uint64_t seed, hipStream_t strea
                        e.reps, (float4 *)G, lo32(seed), hi32(seed));
     hipLaunchKernelGGL(gauge_apply_kernel, dim3(nblk(e.max_vh, 256), 8), dim3(256), 0, stream,
                        e.reps, (const float4 *)G);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_sweeps(const Ens &e, int ns, uint64_t seed, int reunit_every, int flags,
+                               double *hist, const float *table, hipStream_t stream)
+{
+    if (ns <= 0) return hipSuccess;
+    const uint32_t block = std::min<uint32_t>(1024u, (e.max_vh + 63u) & ~63u);
+    if (table)
+        hipLaunchKernelGGL(small_sweeps_kernel<true>, dim3(e.nrep), dim3(block), 0, stream, e.reps,
+                           e.nrep, ns, lo32(seed), hi32(seed), reunit_every, flags, hist, table);
+    else
+        hipLaunchKernelGGL(small_sweeps_kernel<false>, dim3(e.nrep), dim3(block), 0, stream, e.reps,
+                           e.nrep, ns, lo32(seed), hi32(seed), reunit_every, flags, hist, table);
     return hipGetLastError();
 }
 

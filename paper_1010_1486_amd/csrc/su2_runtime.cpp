@@ -287,6 +287,9 @@ public:
         return SU2_OK;
     }
 
+    // Whole sweeps in one launch (small lattices only).
+    bool small_path() const { return cfg.small && max_vh <= kSmallMaxVh; }
+
     const float *mode_table(int mode, int *rc)
     {
         *rc = SU2_OK;
@@ -306,6 +309,13 @@ public:
         const float *tab = mode_table(mode, &rc);
         if (rc) return rc;
         if (hist && reset_rows) HIP_TRY(launch_set_counter(ens(), 0, 0, 2, stream));
+        if (small_path()) {
+            const int flags = (hist && (meas & SU2_MEAS_PLAQ) ? 1 : 0) |
+                              (hist && (meas & SU2_MEAS_POLY) ? 2 : 0) | (hist ? 4 : 0);
+            HIP_TRY(launch_small_sweeps(ens(), ns, seed, reunit_every, flags, hist, tab, stream));
+            sweep += (uint32_t)ns;
+            return SU2_OK;
+        }
         for (int32_t i = 0; i < ns; ++i) {
             const uint32_t j = sweep + (uint32_t)i;
             const bool reunit = reunit_every > 0 && ((j + 1u) % (uint32_t)reunit_every) == 0u;
@@ -479,6 +489,7 @@ public:
         cfg.pass_block = block;
         cfg.xcd_remap = (flags & 1) != 0;
         cfg.snake = (flags & 2) == 0;
+        cfg.small = (flags & 4) == 0;
         cfg.grid_cap = (uint32_t)grid_cap;
         lg_tz = lz;
         lg_tt = lt;
@@ -599,32 +610,39 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
     const uint32_t sweep0 = sweep;
     const LaunchCfg cfg0 = cfg;
     const uint32_t lz0 = lg_tz, lt0 = lg_tt;
-    const int blocks[] = {256, 128};
-    const int flagset[] = {1, 3};  // remap + alternating order, remap only
-    const int tiles[][2] = {{8, 8}, {4, 8}, {2, 16}, {1, 1}, {16, 16}};
-    const int grids[] = {0, 2048, 4096};
+    // candidates: the whole-sweep kernel when the lattices are small enough,
+    // then the pass kernels over block sizes, traversal flags, tiles and
+    // persistent grid sizes
+    struct Cand {
+        int block, flags, tz, tt, grid;
+    };
+    std::vector<Cand> cands;
+    const bool small_ok = max_vh <= kSmallMaxVh;
+    if (small_ok) cands.push_back({256, 1, 8, 8, 0});
+    const int no_small = small_ok ? 4 : 0;
+    for (int b : {256, 128})
+        for (int fl : {1, 3})  // remap + alternating order, remap only
+            for (auto t : {std::array<int, 2>{8, 8}, {4, 8}, {2, 16}, {1, 1}, {16, 16}})
+                for (int gc : {0, 2048, 4096}) cands.push_back({b, fl | no_small, t[0], t[1], gc});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     best.us = 1e30;
     const int trial_sweeps = 2;
     rc = SU2_OK;
-    for (int b : blocks)
-        for (int fl : flagset)
-            for (auto &t : tiles)
-                for (int gc : grids) {
-                    if (rc || e != hipSuccess) break;
-                    if ((rc = set_launch(b, fl, t[0], t[1], gc))) break;
-                    if ((rc = enqueue(1, mode, 0, 0, nullptr))) break;  // warm-up
-                    if ((e = hipEventRecord(e0, stream)) != hipSuccess) break;
-                    if ((rc = enqueue(trial_sweeps, mode, 0, 0, nullptr))) break;
-                    if ((e = hipEventRecord(e1, stream)) != hipSuccess) break;
-                    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-                    float ms = 0.0f;
-                    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-                    const double us = 1e3 * ms / trial_sweeps;
-                    if (us < best.us) best = TuneEntry{b, fl, t[0], t[1], gc, us};
-                }
+    for (const Cand &c : cands) {
+        if (rc || e != hipSuccess) break;
+        if ((rc = set_launch(c.block, c.flags, c.tz, c.tt, c.grid))) break;
+        if ((rc = enqueue(1, mode, 0, 0, nullptr))) break;  // warm-up
+        if ((e = hipEventRecord(e0, stream)) != hipSuccess) break;
+        if ((rc = enqueue(trial_sweeps, mode, 0, 0, nullptr))) break;
+        if ((e = hipEventRecord(e1, stream)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        const double us = 1e3 * ms / trial_sweeps;
+        if (us < best.us) best = TuneEntry{c.block, c.flags, c.tz, c.tt, c.grid, us};
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     // restore the state whatever happened
@@ -916,16 +934,21 @@ int su2_set_launch(su2_ctx *c, int block, int flags, int tile_z, int tile_t, int
     return c->E.set_launch(block, flags, tile_z, tile_t, grid_cap);
 }
 
+static void get_launch(const Ensemble &E, int *block, int *flags, int *tile_z, int *tile_t,
+                       int *grid_cap)
+{
+    if (block) *block = E.cfg.pass_block;
+    if (flags) *flags = (E.cfg.xcd_remap ? 1 : 0) | (E.cfg.snake ? 0 : 2) | (E.cfg.small ? 0 : 4);
+    if (tile_z) *tile_z = 1 << E.geom[0].lg_tz;
+    if (tile_t) *tile_t = 1 << E.geom[0].lg_tt;
+    if (grid_cap) *grid_cap = (int)E.cfg.grid_cap;
+}
+
 int su2_get_launch(su2_ctx *c, int *block, int *flags, int *tile_z, int *tile_t, int *grid_cap)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    const Ensemble &E = c->E;
-    if (block) *block = E.cfg.pass_block;
-    if (flags) *flags = (E.cfg.xcd_remap ? 1 : 0) | (E.cfg.snake ? 0 : 2);
-    if (tile_z) *tile_z = 1 << E.geom[0].lg_tz;
-    if (tile_t) *tile_t = 1 << E.geom[0].lg_tt;
-    if (grid_cap) *grid_cap = (int)E.cfg.grid_cap;
+    get_launch(c->E, block, flags, tile_z, tile_t, grid_cap);
     return SU2_OK;
 }
 
@@ -1077,6 +1100,15 @@ int su2_batch_set_launch(su2_batch *b, int block, int flags, int tile_z, int til
     int rc = check_batch(b);
     if (rc) return rc;
     return b->E.set_launch(block, flags, tile_z, tile_t, grid_cap);
+}
+
+int su2_batch_get_launch(su2_batch *b, int *block, int *flags, int *tile_z, int *tile_t,
+                         int *grid_cap)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    get_launch(b->E, block, flags, tile_z, tile_t, grid_cap);
+    return SU2_OK;
 }
 
 int su2_batch_autotune(su2_batch *b, const char *cache_path, int mode, double *best_us)

@@ -60,6 +60,7 @@ _SIGS = {
     "su2_set_launch": (_int, [_vp, _int, _int, _int, _int, _int]),
     "su2_autotune": (_int, [_vp, ctypes.c_char_p, _int, _vp]),
     "su2_get_launch": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "su2_batch_get_launch": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "su2_capture_sweeps": (_int, [_vp, _i32, _int, _i32, _int, _vp]),
     "su2_replay_sweeps": (_int, [_vp, _i32]),
     "su2_batch_init": (_int, [_vp, _i32, _vp, _vp, _vp, _u64, _vp]),
@@ -244,9 +245,10 @@ def su2_set_launch(h, block, flags, tile_z=0, tile_t=0, grid_cap=0):
                                 int(grid_cap)))
 
 
-def su2_get_launch(h):
+def su2_get_launch(h, batch=False):
     v = [ctypes.c_int() for _ in range(5)]
-    _check(lib().su2_get_launch(h, *[ctypes.byref(x) for x in v]))
+    fn = lib().su2_batch_get_launch if batch else lib().su2_get_launch
+    _check(fn(h, *[ctypes.byref(x) for x in v]))
     return dict(zip(("block", "flags", "tile_z", "tile_t", "grid_cap"), (x.value for x in v)))
 
 
@@ -535,7 +537,8 @@ class Lattice:
         su2_set_replica(self.h, r)
 
     def set_launch(self, block, flags=1, tile_z=0, tile_t=0, grid_cap=0):
-        """flags: bit 0 XCD remap, bit 1 disables the alternating pass order."""
+        """flags: bit 0 XCD remap, bit 1 disables the alternating pass order, bit 2
+        disables the whole-sweep kernel of small lattices."""
         su2_set_launch(self.h, block, flags, tile_z, tile_t, grid_cap)
 
     def autotune(self, cache_path=None, mode=SU2_KP):
@@ -648,6 +651,9 @@ class Batch:
     def set_launch(self, block, flags=1, tile_z=0, tile_t=0, grid_cap=0):
         _check(lib().su2_batch_set_launch(self.h, int(block), int(flags), int(tile_z),
                                           int(tile_t), int(grid_cap)))
+
+    def launch(self):
+        return su2_get_launch(self.h, batch=True)
 
     def autotune(self, cache_path=None, mode=SU2_KP):
         us = ctypes.c_double()

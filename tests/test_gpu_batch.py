@@ -35,9 +35,9 @@ def test_batch_replicas_match_single_lattices(su2):
             lat.set_links(init)
             hs = lat.sweep_measure(5, meas=3, reunit_every=2).cpu().numpy()
             np.testing.assert_array_equal(lat.get_links(), bl[r])
-        # plaquettes use the same workgroup partition: identical; the Polyakov
-        # kernel of a batch splits t into the segments common to every
-        # replica's Nt, so its FP32 product order may differ from a lone lattice
+        # plaquettes are summed in fixed point per site (whole-sweep kernel)
+        # or per workgroup of the same partition: identical; the Polyakov
+        # product order may differ between a batch and a lone lattice
         np.testing.assert_array_equal(h[:, r, 0], hs[:, 0])
         np.testing.assert_allclose(h[:, r, 1:], hs[:, 1:], atol=1e-6, rtol=0)
 
@@ -76,7 +76,8 @@ def test_graph_replay_equals_direct(su2):
 
 
 @pytest.mark.parametrize("cfg", [(256, 1, 8, 8, 0), (128, 3, 1, 1, 0), (64, 0, 2, 16, 0),
-                                 (256, 1, 4, 4, 64), (192, 1, 16, 2, 8)], ids=str)
+                                 (256, 1, 4, 4, 64), (192, 1, 16, 2, 8), (256, 5, 8, 8, 0),
+                                 (128, 7, 2, 4, 16)], ids=str)
 def test_launch_configuration_does_not_change_links(su2, cfg):
     announce(f"launch config {cfg}")
     dims = [8, 6, 8, 16]
@@ -176,3 +177,33 @@ def test_autotune_keeps_accept_statistics(su2):
         p1, a1 = b.accept_stats()
         np.testing.assert_array_equal(p0, p1)
         np.testing.assert_array_equal(a0, a1)
+
+
+def test_small_lattice_kernel_matches_pass_kernels(su2):
+    """The whole-sweep kernel of small lattices (one workgroup per replica)
+    gives the pass kernels' links bit for bit, in heat-bath and learned mode,
+    with measurements and reunitarisation inside the launch."""
+    announce("whole-sweep kernel == pass kernels")
+    p = (np.random.default_rng(21).standard_normal(2671) * 0.2).astype(np.float32)
+    runs = []
+    with su2.NN(params=p) as net:
+        net.build_table()
+        for flags in (1, 5):  # bit 2 disables the whole-sweep kernel
+            with su2.Batch(DIMS, BETAS, STARTS, 17) as b:
+                b.set_proposal(net)
+                b.set_launch(256, flags, 8, 8, 0)
+                assert b.launch()["flags"] == flags
+                h1 = b.sweep_measure(6, meas=3, reunit_every=4).cpu().numpy()
+                b.sweep(2, su2.SU2_LEARNED)
+                h2 = b.sweep_measure(3, su2.SU2_LEARNED, reunit_every=3, meas=3).cpu().numpy()
+                runs.append((h1, h2, [b.get_links(r) for r in range(len(DIMS))],
+                             b.accept_stats()))
+    (a1, a2, al, ac), (b1, b2, bl, bc) = runs
+    for r in range(len(DIMS)):
+        np.testing.assert_array_equal(al[r], bl[r])
+    for x, y in ((a1, b1), (a2, b2)):
+        np.testing.assert_allclose(x[..., 0], y[..., 0], atol=1e-8, rtol=0)
+        np.testing.assert_allclose(x[..., 1:], y[..., 1:], atol=1e-6, rtol=0)
+    np.testing.assert_array_equal(ac[0], bc[0])
+    np.testing.assert_array_equal(ac[1], bc[1])
+    assert ac[1].sum() > 0 and ac[1].sum() < ac[0].sum()
