@@ -140,7 +140,14 @@ int su2_synchronize(su2_ctx *ctx);
  * threads); flags: bit 0 = XCD-contiguous workgroup remap, bit 1 = disable
  * the alternating (forward, backward) pass order, bit 2 = disable the
  * whole-sweep kernel for small lattices (by default, when every V/2 <= 2048,
- * one launch runs whole sweeps with one workgroup per lattice); the traversal
+ * one launch runs whole sweeps with one workgroup per lattice), bit 3 = run
+ * sweeps as one persistent work-queue launch per call (every pass, the
+ * reunitarisation and the measurements of all replicas, ordered per replica
+ * by completion counters; each replica is served by one XCD, replicas spread
+ * over the XCDs by size; grid_cap = its workgroups, at least one per XCD,
+ * 0 = as many as the device holds at once), bits 4-5 = log2 of the items it
+ * takes per ticket;
+ * the traversal
  * tile of (z, t) planes, tile_z x tile_t (powers of two <= 256, clipped to
  * divisors of Nz and Nt; 0 keeps the current value); grid_cap > 0 runs the
  * pass as a persistent grid of at most grid_cap workgroups looping over the
@@ -288,6 +295,24 @@ int su2_test_stream_pass(su2_ctx *ctx, int mu, int parity, void *out_dev);
  * the thread, out[9g + 1 + 2d] / out[9g + 2 + 2d] = half-site index (s >> 1)
  * of its +1 / -1 neighbour in direction d.  out: host uint32[9 * V/2]. */
 int su2_test_index_map(const int32_t dims[4], int tile_z, int tile_t, int parity, uint32_t *out);
+/* Host-side run (no GPU needed) of the work-queue schedule of a batch of n
+ * lattices (dims: n x 4 extents) with `block`-thread workgroups and `queues`
+ * queues (one per XCD, 1..16): nsweeps sweeps starting at sweep index
+ * first_sweep, reunitarisation every reunit_every sweeps (0: none),
+ * measurements `meas` with history rows when rows != 0.  Checks that the
+ * replicas' slots tile the queues exactly, then runs each queue's items one
+ * at a time in ticket order, checking that every item's wait target counts
+ * exactly the replica's earlier items (so the queue can neither deadlock nor
+ * start an item early) and that every sweep of every replica ends.
+ * items_out (may be NULL): items run.  SU2_ERANGE with a message on the first
+ * violation. */
+int su2_test_queue_plan(int32_t n, const int32_t *dims, int block, int32_t queues,
+                        int32_t nsweeps, int32_t reunit_every, uint32_t first_sweep, int meas,
+                        int rows, int64_t *items_out);
+/* Polls allowed per bounded wait of the batch's work-queue launches (default
+ * 2^22).  A small value makes the waits run out on purpose: the launch then
+ * drains normally and the next synchronising call returns SU2_EHIP. */
+int su2_test_batch_spin_limit(su2_batch *b, uint32_t polls);
 /* Learned-proposal update of n independent links (host float[n][4] staples V
  * and old links Uold); link i uses site index i.  accepted_host (may be NULL):
  * 1 accepted, 0 rejected, -1 exact fallback. */

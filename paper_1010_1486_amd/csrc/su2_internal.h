@@ -32,7 +32,19 @@ enum Acc { ACC_PLAQ = 0, ACC_POLY = 1, ACC_PROPOSED = 2, ACC_ACCEPTED = 3 };
 struct Counters {
     uint32_t sweep;     // sweep index used by the next pass (Philox counter word 1)
     uint32_t meas_idx;  // next history row written by a measured sweep
-    uint32_t pad[14];
+    uint32_t done;      // work-queue items of this replica finished in the current launch
+    uint32_t pad[13];
+};
+
+// Shared state of the persistent work-queue launch: one queue per XCD.
+constexpr int kMaxQueues = 16;  // the XCC id is 4 bits
+struct QueueState {
+    uint32_t ticket[kMaxQueues][32];  // next item of queue q (own 128-byte line each)
+    uint32_t error;                   // nonzero: a bounded wait ran out or work was left over
+    uint32_t pad0[31];
+    int32_t rank[kMaxQueues];         // XCC id -> queue (-1: the XCD takes no work)
+    uint32_t slots[kMaxQueues];       // items per stage of queue q
+    uint32_t off[kMaxQueues];         // first entry of queue q in the slot -> replica map
 };
 
 // Device-resident descriptor of one lattice (replica) of an ensemble.  A
@@ -47,6 +59,7 @@ struct Rep {
     uint32_t replica;          // Philox replica id
     uint32_t first_block;      // first pass workgroup of this replica (multiple of 8)
     uint32_t nblocks;          // pass workgroups of this replica
+    uint32_t qfirst;           // first work-queue slot of this replica in its queue
 };
 
 // Per-replica scratch: counters, accumulators, result slots.
@@ -58,7 +71,98 @@ struct LaunchCfg {
     bool snake = true;        // odd-parity passes traverse backwards
     uint32_t grid_cap = 0;    // > 0: persistent pass grid of at most this many workgroups
     bool small = true;        // whole sweeps in one launch when every V/2 <= kSmallMaxVh
+    bool queue = false;       // whole sweeps in one persistent work-queue launch
+    int grain = 1;            // work-queue items per ticket
 };
+
+// ------------------------------------------------------------- work queue
+// A persistent launch runs ns sweeps of every replica.  Each replica belongs
+// to one queue, and each queue is served by the workgroups of one XCD only,
+// so a replica's links stay in that XCD's L2 and its items need ordering
+// only within the XCD.  A queue is a list of items in the order (sweep,
+// stage, slot).  Per sweep the stages are the 8 passes (mu = stage >> 1,
+// parity = stage & 1), then the reunitarisation (sweeps j with
+// (j + 1) mod reunit = 0), the plaquette after it (when measured) and the
+// Polyakov loop (when measured).  Every stage has one item per slot of the
+// queue, the slots of its replicas side by side, nblocks (pass workgroups of
+// the replica) slots each.  The end-of-sweep bookkeeping of a replica (sums,
+// history row) is done by the workgroup that finishes its last item of the
+// sweep and counts as one more item.
+struct QueuePlan {
+    uint32_t ns;      // sweeps in the launch
+    uint32_t reunit;  // reunitarisation period (0: none)
+    uint32_t phase;   // index of the first sweep mod reunit (0 without)
+    uint32_t want_p, want_l, rows;  // plaquette, Polyakov loop, history rows (0/1)
+};
+
+enum QueueKind { QK_PASS = 0, QK_REUNIT = 1, QK_PLAQ = 2, QK_POLY = 3 };
+
+struct QueueItem {
+    uint32_t sweep;  // sweep within the launch
+    uint32_t stage;  // stage within the sweep
+    uint32_t slot;   // pass workgroup slot
+    int kind;
+};
+
+__host__ __device__ inline bool queue_reunit_sweep(const QueuePlan &p, uint32_t i)
+{
+    return p.reunit > 0u && (p.phase + i + 1u) % p.reunit == 0u;
+}
+
+// Stages of the sweeps before sweep i (i <= ns).
+__host__ __device__ inline uint32_t queue_stages_before(const QueuePlan &p, uint32_t i)
+{
+    const uint32_t nre = p.reunit > 0u ? (p.phase + i) / p.reunit : 0u;
+    return (8u + p.want_l) * i + (1u + p.want_p) * nre;
+}
+
+__host__ __device__ inline uint32_t queue_total_stages(const QueuePlan &p)
+{
+    return queue_stages_before(p, p.ns);
+}
+
+// Item t of a queue with `slots` items per stage.
+__host__ __device__ inline QueueItem queue_decode(const QueuePlan &p, uint32_t t, uint32_t slots)
+{
+    QueueItem it;
+    const uint32_t gs = t / slots;
+    it.slot = t - gs * slots;
+    uint32_t lo = 0u, hi = p.ns;  // stages_before(lo) <= gs < stages_before(hi)
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (queue_stages_before(p, mid) <= gs) lo = mid;
+        else hi = mid;
+    }
+    it.sweep = lo;
+    it.stage = gs - queue_stages_before(p, lo);
+    if (it.stage < 8u) {
+        it.kind = QK_PASS;
+    } else {
+        const uint32_t k = it.stage - 8u;
+        if (queue_reunit_sweep(p, lo))
+            it.kind = k == 0u ? QK_REUNIT : (k == 1u && p.want_p ? QK_PLAQ : QK_POLY);
+        else
+            it.kind = QK_POLY;
+    }
+    return it;
+}
+
+// Items of a replica with n slots that must be finished before its items of
+// (sweep, stage) start: every item of the earlier stages plus one
+// bookkeeping item per earlier sweep.
+__host__ __device__ inline uint32_t queue_target(const QueuePlan &p, uint32_t n, uint32_t sweep,
+                                                 uint32_t stage)
+{
+    return (queue_stages_before(p, sweep) + stage) * n + sweep;
+}
+
+// Done count reached when the last item of `sweep` finishes (before its
+// bookkeeping item).
+__host__ __device__ inline uint32_t queue_sweep_last(const QueuePlan &p, uint32_t n,
+                                                     uint32_t sweep)
+{
+    return queue_stages_before(p, sweep + 1u) * n + sweep;
+}
 
 // Largest V/2 of the whole-sweep kernel (one workgroup per replica, up to
 // 1024 threads, 2 sites per thread).
@@ -100,9 +204,26 @@ hipError_t launch_reunitarize(const Ens &e, hipStream_t stream);
 // table != nullptr: learned-proposal Metropolis updates.
 hipError_t launch_small_sweeps(const Ens &e, int ns, uint64_t seed, int reunit_every, int flags,
                                double *hist, const float *table, hipStream_t stream);
-// which: 1 set sweep, 2 set meas_idx, 4 zero all accumulators, 8 zero counts.
+// ns sweeps of every replica in one persistent work-queue launch (see
+// QueuePlan; qs holds the queues, qmap their slot -> replica maps, nullptr
+// for a single replica), followed by a one-workgroup-per-replica launch that
+// checks that every item ran, advances the sweep and row counters and clears
+// the queue state.  grid workgroups of `block` threads (block = the pass
+// block of the slot layout).  spin_limit bounds every wait (polls); when it
+// runs out qs->error is raised and the launch drains without waiting.
+hipError_t launch_queue_sweeps(const Ens &e, const QueuePlan &plan, const uint32_t *qmap,
+                               uint64_t seed, int block, uint32_t grid, int grain, bool snake,
+                               double *hist, const float *table, QueueState *qs,
+                               uint32_t spin_limit, hipStream_t stream);
+// Bit mask of the XCC ids that run workgroups of a large launch (one-time
+// probe of the current device; synchronous).
+hipError_t probe_xcc_mask(uint32_t *mask);
+// Workgroups of `block` threads of the queue kernel the device holds at once.
+uint32_t queue_resident_grid(int block, bool learned);
+// which: 1 set sweep, 2 set meas_idx, 4 zero all accumulators, 8 zero counts,
+// 16 zero the work-queue state (done counters; qs ticket and error).
 hipError_t launch_set_counter(const Ens &e, uint32_t sweep, uint32_t meas, int which,
-                              hipStream_t stream);
+                              hipStream_t stream, QueueState *qs = nullptr);
 // results[R_COUNTS..] = proposals, accepts (as uint64); reset if asked.
 hipError_t launch_counts(const Ens &e, int reset, hipStream_t stream);
 hipError_t launch_gauge(const Ens &e, float *G, uint64_t seed, hipStream_t stream);

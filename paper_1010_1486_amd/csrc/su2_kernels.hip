@@ -463,9 +463,16 @@ __global__ __launch_bounds__(kBuckets) void counts_kernel(const Rep *__restrict_
 
 __global__ __launch_bounds__(kBuckets) void set_counter_kernel(const Rep *__restrict__ reps,
                                                                uint32_t sweep, uint32_t meas,
-                                                               int which)
+                                                               int which, QueueState *qs)
 {
     const Rep &R = reps[blockIdx.z];
+    if ((which & 16) && threadIdx.x == 0) {
+        R.cnt->done = 0u;
+        if (qs && blockIdx.z == 0) {
+            for (int k = 0; k < kMaxQueues; ++k) qs->ticket[k][0] = 0u;
+            qs->error = 0u;
+        }
+    }
     if (which & 4)
         for (int a = 0; a < kNumAcc; ++a) *bucket(R.acc, a, threadIdx.x) = 0ull;
     else if (which & 8)
@@ -496,8 +503,6 @@ __global__ __launch_bounds__(256) void reunit_kernel(const Rep *__restrict__ rep
     if (h >= R.g.vh) return;
     reunit_link(R, blockIdx.y >> 1, blockIdx.y & 1, h);
 }
-
-// ---------------------------------------------------------- gauge (tests)
 
 // ----------------------------------------------------------- small lattices
 // Whole sweeps of small lattices in one launch: workgroup r runs replica r
@@ -630,6 +635,241 @@ __global__ __launch_bounds__(1024) void small_sweeps_kernel(const Rep *__restric
     }
 }
 
+// ------------------------------------------------------------- work queue
+// Whole sweeps of every replica in one persistent launch (QueuePlan).  A
+// workgroup serves the queue of its XCD (hardware XCC id -> qs->rank) and
+// takes `grain` consecutive items per ticket; consecutive items of one
+// replica and stage form a run that waits once and signals once.  A run of
+// replica r waits until r's done counter reaches queue_target: every item of
+// r's earlier stages and the bookkeeping of r's earlier sweeps are finished.
+// Items wait only on items of their own queue with smaller tickets, which
+// running workgroups of the same XCD have already taken, so a queue cannot
+// deadlock; every wait is still bounded by spin_limit polls, after which
+// qs->error is raised and all workgroups drain without waiting.
+//
+// Ordering within one XCD: the L1 caches are write-through and the L2 is
+// shared by the XCD's compute units, so a producer only waits until its
+// stores have reached the L2 (vmcnt 0) before the done counter is
+// incremented; an agent-scope release, which also writes the L2 back to
+// memory, is not needed and costs about a microsecond per run.  The waiting
+// thread performs an agent-scope acquire after seeing the count (it
+// invalidates the compute unit's L1; a workgroup-scope L1 invalidation alone
+// left stale lines on gfx950 when producer and consumer ran on different
+// compute units).  The counters, the tickets and the measurement
+// accumulators are device-scope atomics.
+__device__ __forceinline__ uint32_t xcc_id()
+{
+    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;  // hwreg(HW_REG_XCC_ID, 0, 4)
+}
+
+// Invalidate this compute unit's L1 (vector data cache).
+__device__ __forceinline__ void l1_invalidate() { asm volatile("buffer_inv sc0" ::: "memory"); }
+
+__device__ __forceinline__ void queue_wait(const Rep &R, uint32_t target, QueueState *qs,
+                                           uint32_t spin_limit)
+{
+    if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&R.cnt->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               target) {
+            if (__hip_atomic_load(&qs->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (++spins > spin_limit) {
+                __hip_atomic_store(&qs->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    l1_invalidate();  // every wave (workgroup scope)
+}
+
+// Every wave's stores reach the L2, then thread 0 adds k to the done
+// counter; returns the counter's previous value in thread 0.
+__device__ __forceinline__ uint32_t queue_signal(const Rep &R, uint32_t k)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    uint32_t old = 0u;
+    if (threadIdx.x == 0)
+        old = __hip_atomic_fetch_add(&R.cnt->done, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return old;
+}
+
+template <bool LEARNED>
+__device__ __forceinline__ void queue_pass(const Rep &R, int mu, int par, bool measure,
+                                           uint32_t gid, uint32_t sweep, uint32_t k0, uint32_t k1,
+                                           const float *ltab, float &m, int &a)
+{
+#define SU2_QPASS(MU)                                                                      \
+    if (measure) update_site<MU, true, LEARNED>(R, gid, par, sweep, k0, k1, ltab, m, a);   \
+    else update_site<MU, false, LEARNED>(R, gid, par, sweep, k0, k1, ltab, m, a);
+    switch (mu) {
+    case 0: SU2_QPASS(0) break;
+    case 1: SU2_QPASS(1) break;
+    case 2: SU2_QPASS(2) break;
+    default: SU2_QPASS(3) break;
+    }
+#undef SU2_QPASS
+}
+
+// End of sweep i of replica r: totals of the plaquette and Polyakov
+// accumulators (taken and reset atomically), history row meas_idx + i.
+__device__ __forceinline__ void queue_sweep_end(const Rep &R, const QueuePlan &plan, uint32_t i,
+                                                double *hist, int nrep, uint32_t r)
+{
+    unsigned long long tp = 0ull, tl = 0ull;
+    for (uint32_t j = threadIdx.x; j < (uint32_t)kBuckets; j += blockDim.x) {
+        tp += __hip_atomic_exchange(bucket(R.acc, ACC_PLAQ, j), 0ull, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+        tl += __hip_atomic_exchange(bucket(R.acc, ACC_POLY, j), 0ull, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    }
+    tp = block_sum_u64(tp);
+    tl = block_sum_u64(tl);
+    if (plan.rows && hist && threadIdx.x == 0) {
+        const Geom &g = R.g;
+        const double p = plan.want_p ? from_fixed(tp) / (12.0 * (double)g.vh) : 0.0;
+        const double l = plan.want_l ? from_fixed(tl) / ((double)g.nx * g.ny * g.nz) : 0.0;
+        double *row = hist + 3 * ((size_t)(R.cnt->meas_idx + i) * nrep + r);
+        row[0] = p;
+        row[1] = l;
+        row[2] = fabs(l);
+    }
+}
+
+// One item: slot `local` of replica R in stage `it` of the sweep.
+template <bool LEARNED>
+__device__ __forceinline__ void queue_item(const Rep &R, const QueuePlan &plan, const QueueItem &it,
+                                           uint32_t local, uint32_t k0, uint32_t k1, int snake,
+                                           const float *ltab)
+{
+    const Geom &g = R.g;
+    const uint32_t B = blockDim.x, n = R.nblocks;
+    if (it.kind == QK_PASS) {
+        const int mu = (int)(it.stage >> 1), par = (int)(it.stage & 1u);
+        const bool measure =
+            plan.want_p && par == 1 && mu >= 1 && !queue_reunit_sweep(plan, it.sweep);
+        const uint32_t blk = (snake && par) ? n - 1u - local : local;
+        const uint32_t gid = blk * B + threadIdx.x;
+        float m = 0.0f;
+        int a = -1;
+        if (gid < g.vh) {
+            const uint32_t sweep =
+                *(const __attribute__((address_space(4))) uint32_t *)&R.cnt->sweep + it.sweep;
+            queue_pass<LEARNED>(R, mu, par, measure, gid, sweep, k0, k1, ltab, m, a);
+        }
+        if (measure) block_accumulate((double)m, R.acc, ACC_PLAQ, local);
+        if (LEARNED) {
+            const unsigned long long mp = __ballot(a >= 0);
+            const unsigned long long ma = __ballot(a == 1);
+            if ((threadIdx.x & 63) == 0) {
+                const uint32_t wb = local * (B >> 6) + (threadIdx.x >> 6);
+                if (mp) atomicAdd(bucket(R.acc, ACC_PROPOSED, wb), (unsigned long long)__popcll(mp));
+                if (ma) atomicAdd(bucket(R.acc, ACC_ACCEPTED, wb), (unsigned long long)__popcll(ma));
+            }
+        }
+    } else if (it.kind == QK_REUNIT) {
+        const uint32_t h = local * B + threadIdx.x;
+        if (h < g.vh)
+            for (int k = 0; k < 8; ++k) reunit_link(R, k >> 1, k & 1, h);
+    } else if (it.kind == QK_PLAQ) {
+        const uint32_t i = local * B + threadIdx.x;
+        double v = 0.0;
+        if (i < g.vh) v = (double)site_plaquettes(R, i) + (double)site_plaquettes(R, i + g.vh);
+        block_accumulate(v, R.acc, ACC_PLAQ, local);
+    } else {
+        // L(x) = (1/2)Tr prod_t U_3(x, t), t = 0 leftmost
+        const uint32_t ns3 = (uint32_t)g.nx * g.ny * g.nz;
+        if (local * B < ns3) {
+            const uint32_t xs = local * B + threadIdx.x;
+            double v = 0.0;
+            if (xs < ns3) {
+                const uint32_t x = xs % (uint32_t)g.nx, q = xs / (uint32_t)g.nx;
+                const uint32_t y = q % (uint32_t)g.ny, z = q / (uint32_t)g.ny;
+                const uint32_t pbase = (x + y + z) & 1u;
+                Q P{1.0f, 0.0f, 0.0f, 0.0f};
+                for (int tt = 0; tt < g.nt; ++tt)
+                    P = qmul(P, ldq(R.links, g.vh, 3, (int)((pbase + (uint32_t)tt) & 1u),
+                                    (xs >> 1) + (uint32_t)tt * (ns3 >> 1)));
+                v = (double)P.w;
+            }
+            block_accumulate(v, R.acc, ACC_POLY, local);
+        }
+    }
+}
+
+template <bool LEARNED>
+__global__ __launch_bounds__(256) void queue_sweeps_kernel(
+    const Rep *__restrict__ reps, const uint32_t *__restrict__ qmap, QueuePlan plan, int grain,
+    uint32_t k0, uint32_t k1, int snake, double *__restrict__ hist, int nrep, QueueState *qs,
+    uint32_t spin_limit, const float *__restrict__ table)
+{
+    __shared__ float4 stab4[LEARNED ? 1 + kNNRows * kNNRow / 4 : 1];
+    __shared__ uint32_t s_ticket, s_last;
+    const int q = qs->rank[xcc_id()];  // uniform over the workgroup
+    if (q < 0) return;
+    const uint32_t slots = qs->slots[q];
+    if (slots == 0u) return;
+    const uint32_t total = queue_total_stages(plan) * slots;
+    const uint32_t *map = qmap ? qmap + qs->off[q] : nullptr;
+    const float *ltab = LEARNED ? load_table_lds(stab4, table) : nullptr;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_ticket = __hip_atomic_fetch_add(&qs->ticket[q][0], (uint32_t)grain,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t t0 = s_ticket;
+        __syncthreads();  // every thread has read s_ticket
+        if (t0 >= total) break;
+        const uint32_t t1 = min(t0 + (uint32_t)grain, total);
+        for (uint32_t t = t0; t < t1;) {
+            const QueueItem it = queue_decode(plan, t, slots);
+            const uint32_t r = map ? map[it.slot] : 0u;
+            const Rep &R = reps[r];
+            const uint32_t local = it.slot - R.qfirst, n = R.nblocks;
+            // run: the following items of the same replica and stage
+            const uint32_t len = min(t1 - t, n - local);
+            queue_wait(R, queue_target(plan, n, it.sweep, it.stage), qs, spin_limit);
+            for (uint32_t k = 0; k < len; ++k)
+                queue_item<LEARNED>(R, plan, it, local + k, k0, k1, snake, ltab);
+            const uint32_t old = queue_signal(R, len);
+            if (threadIdx.x == 0) s_last = old + len == queue_sweep_last(plan, n, it.sweep);
+            __syncthreads();
+            if (s_last) {  // uniform: this workgroup finished the sweep of replica r
+                if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __syncthreads();
+                queue_sweep_end(R, plan, it.sweep, hist, nrep, r);
+                (void)queue_signal(R, 1u);
+            }
+            __syncthreads();  // s_last is rewritten by the next run
+            t += len;
+        }
+    }
+}
+
+// grid (1, 1, replica): check that every item of the replica ran (else raise
+// the error flag), advance the counters past the launch's sweeps and clear
+// the queue state for the next launch.
+__global__ void queue_epilogue_kernel(const Rep *__restrict__ reps, QueuePlan plan,
+                                      QueueState *qs)
+{
+    const Rep &R = reps[blockIdx.z];
+    if (R.cnt->done != queue_target(plan, R.nblocks, plan.ns, 0u)) qs->error = 2u;
+    R.cnt->sweep += plan.ns;
+    if (plan.rows) R.cnt->meas_idx += plan.ns;
+    R.cnt->done = 0u;
+    if (blockIdx.z == 0)
+        for (int k = 0; k < kMaxQueues; ++k) qs->ticket[k][0] = 0u;
+}
+
+__global__ void xcc_probe_kernel(uint32_t *mask)
+{
+    if (threadIdx.x == 0) atomicOr(mask, 1u << xcc_id());
+}
+
+// ---------------------------------------------------------- gauge (tests)
 // Replica 0 only (G holds one field of gauge rotations).
 __global__ void gauge_gen_kernel(const Rep *__restrict__ reps, float4 *__restrict__ G,
                                  uint32_t k0, uint32_t k1)
@@ -782,10 +1022,10 @@ hipError_t launch_counts(const Ens &e, int reset, hipStream_t stream)
 }
 
 hipError_t launch_set_counter(const Ens &e, uint32_t sweep, uint32_t meas, int which,
-                              hipStream_t stream)
+                              hipStream_t stream, QueueState *qs)
 {
     hipLaunchKernelGGL(set_counter_kernel, dim3(1, 1, e.nrep), dim3(kBuckets), 0, stream, e.reps,
-                       sweep, meas, which);
+                       sweep, meas, which, qs);
     return hipGetLastError();
 }
 
@@ -817,6 +1057,56 @@ hipError_t launch_small_sweeps(const Ens &e, int ns, uint64_t seed, int reunit_e
         hipLaunchKernelGGL(small_sweeps_kernel<false>, dim3(e.nrep), dim3(block), 0, stream, e.reps,
                            e.nrep, ns, lo32(seed), hi32(seed), reunit_every, flags, hist, table);
     return hipGetLastError();
+}
+
+hipError_t launch_queue_sweeps(const Ens &e, const QueuePlan &plan, const uint32_t *qmap,
+                               uint64_t seed, int block, uint32_t grid, int grain, bool snake,
+                               double *hist, const float *table, QueueState *qs,
+                               uint32_t spin_limit, hipStream_t stream)
+{
+    if (plan.ns == 0u) return hipSuccess;
+    if (grid == 0u) grid = 1u;
+    if (table)
+        hipLaunchKernelGGL(queue_sweeps_kernel<true>, dim3(grid), dim3(block), 0, stream, e.reps,
+                           qmap, plan, grain, lo32(seed), hi32(seed), (int)snake, hist, e.nrep, qs,
+                           spin_limit, table);
+    else
+        hipLaunchKernelGGL(queue_sweeps_kernel<false>, dim3(grid), dim3(block), 0, stream, e.reps,
+                           qmap, plan, grain, lo32(seed), hi32(seed), (int)snake, hist, e.nrep, qs,
+                           spin_limit, table);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(queue_epilogue_kernel, dim3(1, 1, e.nrep), dim3(1), 0, stream, e.reps, plan,
+                       qs);
+    return hipGetLastError();
+}
+
+hipError_t probe_xcc_mask(uint32_t *mask)
+{
+    uint32_t *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(uint32_t));
+    if (e != hipSuccess) return e;
+    e = hipMemset(d, 0, sizeof(uint32_t));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(xcc_probe_kernel, dim3(4096), dim3(64), 0, nullptr, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(mask, d, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return e;
+}
+
+uint32_t queue_resident_grid(int block, bool learned)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = learned ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                 &per_cu, queue_sweeps_kernel<true>, block, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                 &per_cu, queue_sweeps_kernel<false>, block, 0);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || per_cu <= 0 || cus <= 0) return 1024u;
+    return (uint32_t)(per_cu * cus);
 }
 
 hipError_t launch_test_stream(const Ens &e, int mu, int par, float *out, hipStream_t stream)

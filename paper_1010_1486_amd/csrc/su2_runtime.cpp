@@ -146,6 +146,73 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int64_t volume_of(const int32_t *d) { return (int64_t)d[0] * d[1] * d[2] * d[3]; }
 
+// Pass workgroup slots: replica r owns nblocks[r] = ceil(V/2 / block) slots
+// starting at first[r], a multiple of 8 (so that slot mod 8 is the XCD of a
+// one-workgroup-per-slot launch); a single lattice has no padding.
+uint32_t slot_layout(const std::vector<std::array<int32_t, 4>> &dims, int block,
+                     std::vector<uint32_t> &first, std::vector<uint32_t> &nblocks)
+{
+    const size_t n = dims.size();
+    first.resize(n);
+    nblocks.resize(n);
+    uint32_t fb = 0;
+    for (size_t r = 0; r < n; ++r) {
+        const uint32_t vh = (uint32_t)(volume_of(dims[r].data()) / 2);
+        nblocks[r] = (vh + (uint32_t)block - 1u) / (uint32_t)block;
+        first[r] = fb;
+        fb += (nblocks[r] + 7u) & ~7u;
+    }
+    return n > 1 ? fb : nblocks[0];
+}
+
+// Work-queue layout over nq queues (one per XCD): replicas in decreasing
+// order of slots (ties by index) go to the queue with the fewest slots so
+// far (ties: lowest queue); within a queue the replicas' slots are
+// contiguous in increasing replica order, qfirst[r] being r's first slot.
+void queue_layout(const std::vector<uint32_t> &nblocks, int nq, std::vector<int> &qof,
+                  std::vector<uint32_t> &qfirst, std::vector<uint32_t> &qslots)
+{
+    const size_t n = nblocks.size();
+    std::vector<size_t> order(n);
+    for (size_t r = 0; r < n; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return nblocks[a] > nblocks[b]; });
+    qof.assign(n, 0);
+    qslots.assign((size_t)nq, 0u);
+    for (size_t r : order) {
+        int best = 0;
+        for (int q = 1; q < nq; ++q)
+            if (qslots[q] < qslots[best]) best = q;
+        qof[r] = best;
+        qslots[best] += nblocks[r];
+    }
+    std::vector<uint32_t> fill((size_t)nq, 0u);
+    qfirst.assign(n, 0u);
+    for (size_t r = 0; r < n; ++r) {
+        qfirst[r] = fill[qof[r]];
+        fill[qof[r]] += nblocks[r];
+    }
+}
+
+// XCC ids that run workgroups on the current device (probed once).
+int xcc_ids(std::vector<int> &ids)
+{
+    static uint32_t masks[64] = {0};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(SU2_ERANGE, "device index out of range");
+    if (!masks[dev]) {
+        uint32_t m = 0;
+        HIP_TRY(probe_xcc_mask(&m));
+        if (!m) return fail(SU2_EHIP, "XCC probe found no XCD");
+        masks[dev] = m;
+    }
+    ids.clear();
+    for (int k = 0; k < kMaxQueues; ++k)
+        if (masks[dev] & (1u << k)) ids.push_back(k);
+    return SU2_OK;
+}
+
 }  // namespace
 
 // ================================================================ Ensemble
@@ -167,7 +234,7 @@ public:
     bool own_pool = false;
     unsigned char *scratch = nullptr;
     bool own_scratch = false;
-    size_t bmap_off = 0, rep_off = 0;
+    size_t bmap_off = 0, qmap_off = 0, rep_off = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     uint64_t seed = 0;
@@ -180,8 +247,15 @@ public:
     hipGraphExec_t gexec = nullptr;
     int32_t g_nsweeps = 0;
     int32_t g_reunit = 0;  // reunitarisation period baked into the graph (0: none)
+    // work queue
+    bool queue_used = false;           // queue launches since the last error check
+    uint32_t spin_limit = 1u << 22;    // polls per bounded wait
+    uint32_t queue_grid_auto[2] = {0, 0};  // resident workgroups (heat bath, learned)
+    int queue_nq = 1;                      // queues (XCDs)
 
-    static size_t descr_bytes(int n) { return align_up((size_t)n * sizeof(Rep), 256); }
+    // descriptors, then the work-queue state
+    static size_t qs_off(int n) { return align_up((size_t)n * sizeof(Rep), 256); }
+    static size_t descr_bytes(int n) { return qs_off(n) + align_up(sizeof(QueueState), 256); }
     static size_t bmap_bytes(int n, const std::vector<std::array<int32_t, 4>> &d)
     {
         if (n <= 1) return 0;
@@ -192,10 +266,15 @@ public:
     static size_t rep_bytes() { return align_up(kRepScratch, 256); }
     static size_t scratch_need(int n, const std::vector<std::array<int32_t, 4>> &d)
     {
-        return descr_bytes(n) + bmap_bytes(n, d) + (size_t)n * rep_bytes();
+        return descr_bytes(n) + 2 * bmap_bytes(n, d) + (size_t)n * rep_bytes();
     }
 
     Rep *d_reps() const { return reinterpret_cast<Rep *>(scratch); }
+    QueueState *d_qs() const { return reinterpret_cast<QueueState *>(scratch + qs_off(n)); }
+    uint32_t *d_qmap() const
+    {
+        return n > 1 ? reinterpret_cast<uint32_t *>(scratch + qmap_off) : nullptr;
+    }
     uint32_t *d_bmap() const
     {
         return n > 1 ? reinterpret_cast<uint32_t *>(scratch + bmap_off) : nullptr;
@@ -231,23 +310,17 @@ public:
     {
         drop_graph();
         geom.resize(n);
-        first_block.resize(n);
-        nblocks.resize(n);
-        uint32_t fb = 0;
+        total_blocks = slot_layout(dims, cfg.pass_block, first_block, nblocks);
         max_vh = max_ns3 = 0;
         poly_s = 8;
         for (int r = 0; r < n; ++r) {
             geom[r] = make_geom(dims[r].data(), lg_tz, lg_tt);
             if (!geom_selfcheck(geom[r]))
                 return fail(SU2_ERANGE, "index arithmetic self-check failed for these extents");
-            nblocks[r] = (geom[r].vh + cfg.pass_block - 1) / cfg.pass_block;
-            first_block[r] = fb;
-            fb += (nblocks[r] + 7u) & ~7u;
             max_vh = std::max(max_vh, geom[r].vh);
             max_ns3 = std::max(max_ns3, (uint32_t)(dims[r][0] * dims[r][1] * dims[r][2]));
             while (dims[r][3] % poly_s) poly_s /= 2;
         }
-        total_blocks = n > 1 ? fb : nblocks[0];
         std::vector<Rep> h(n);
         for (int r = 0; r < n; ++r) {
             h[r].g = geom[r];
@@ -259,6 +332,40 @@ public:
             h[r].replica = replica[r];
             h[r].first_block = first_block[r];
             h[r].nblocks = nblocks[r];
+            h[r].qfirst = 0u;
+        }
+        if (cfg.queue) {
+            std::vector<int> ids;
+            if (int rc = xcc_ids(ids)) return rc;
+            const int nq = (int)ids.size();
+            queue_nq = nq;
+            std::vector<int> qof;
+            std::vector<uint32_t> qfirst, qslots;
+            queue_layout(nblocks, nq, qof, qfirst, qslots);
+            QueueState hq;
+            std::fill(std::begin(hq.rank), std::end(hq.rank), -1);
+            std::fill(std::begin(hq.slots), std::end(hq.slots), 0u);
+            std::fill(std::begin(hq.off), std::end(hq.off), 0u);
+            uint32_t off = 0;
+            for (int q = 0; q < nq; ++q) {
+                hq.rank[ids[q]] = q;
+                hq.slots[q] = qslots[q];
+                hq.off[q] = off;
+                off += qslots[q];
+            }
+            for (int r = 0; r < n; ++r) h[r].qfirst = qfirst[r];
+            HIP_TRY(hipStreamSynchronize(stream));
+            const size_t a = offsetof(QueueState, rank), z = sizeof(QueueState);
+            HIP_TRY(hipMemcpy(reinterpret_cast<char *>(d_qs()) + a,
+                              reinterpret_cast<const char *>(&hq) + a, z - a,
+                              hipMemcpyHostToDevice));
+            if (n > 1) {
+                std::vector<uint32_t> qmap(off);
+                for (int r = 0; r < n; ++r)
+                    for (uint32_t k = 0; k < nblocks[r]; ++k)
+                        qmap[hq.off[qof[r]] + qfirst[r] + k] = (uint32_t)r;
+                HIP_TRY(hipMemcpy(d_qmap(), qmap.data(), qmap.size() * 4, hipMemcpyHostToDevice));
+            }
         }
         HIP_TRY(hipStreamSynchronize(stream));
         HIP_TRY(hipMemcpy(d_reps(), h.data(), n * sizeof(Rep), hipMemcpyHostToDevice));
@@ -278,7 +385,7 @@ public:
         int *d = nullptr;
         HIP_TRY(hipMalloc(&d, n * sizeof(int)));
         hipError_t e = hipMemcpy(d, starts.data(), n * sizeof(int), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = launch_set_counter(ens(), 0, 0, 7, stream);
+        if (e == hipSuccess) e = launch_set_counter(ens(), 0, 0, 7 | 16, stream, d_qs());
         if (e == hipSuccess) e = launch_init(ens(), d, seed, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         (void)hipFree(d);
@@ -288,7 +395,64 @@ public:
     }
 
     // Whole sweeps in one launch (small lattices only).
-    bool small_path() const { return cfg.small && max_vh <= kSmallMaxVh; }
+    bool small_path() const { return !cfg.queue && cfg.small && max_vh <= kSmallMaxVh; }
+
+    // Workgroups of the persistent queue launch: the grid cap if set, else
+    // as many as the device holds at once.
+    // (at least one workgroup per queue: workgroups go to the XCDs in turn)
+    uint32_t queue_grid(bool learned) const
+    {
+        const uint32_t g = cfg.grid_cap ? cfg.grid_cap : queue_grid_auto[learned ? 1 : 0];
+        return std::max(g, (uint32_t)queue_nq);
+    }
+
+    // ns sweeps as persistent work-queue launches of < 2^31 items each.
+    int enqueue_queue(int32_t ns, const float *tab, int32_t reunit_every, int meas, double *hist)
+    {
+        QueuePlan p{};
+        p.reunit = reunit_every > 0 ? (uint32_t)reunit_every : 0u;
+        p.want_p = hist && (meas & SU2_MEAS_PLAQ) ? 1u : 0u;
+        p.want_l = hist && (meas & SU2_MEAS_POLY) ? 1u : 0u;
+        p.rows = hist ? 1u : 0u;
+        const uint64_t per_sweep = (uint64_t)(8u + p.want_l + (p.reunit ? 1u + p.want_p : 0u)) *
+                                   total_blocks;
+        const int64_t max_ns = (int64_t)((((uint64_t)1 << 31) - 1u) / per_sweep);
+        if (max_ns < 1) return fail(SU2_ERANGE, "work-queue launch too large");
+        const uint32_t grid = queue_grid(tab != nullptr);
+        int32_t done = 0;
+        while (done < ns) {
+            const int32_t c = (int32_t)std::min<int64_t>(ns - done, max_ns);
+            p.ns = (uint32_t)c;
+            p.phase = p.reunit ? (sweep + (uint32_t)done) % p.reunit : 0u;
+            HIP_TRY(launch_queue_sweeps(ens(), p, d_qmap(), seed, cfg.pass_block, grid, cfg.grain,
+                                        cfg.snake, hist, tab, d_qs(), spin_limit, stream));
+            done += c;
+        }
+        sweep += (uint32_t)ns;
+        queue_used = true;
+        return SU2_OK;
+    }
+
+    // After queue launches: wait for the stream and report a wait that ran
+    // out (the flag is cleared).
+    int check_queue()
+    {
+        if (!queue_used) return SU2_OK;
+        uint32_t err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, &d_qs()->error, sizeof(err), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        queue_used = false;
+        if (err) {
+            HIP_TRY(launch_set_counter(ens(), 0, 0, 16, stream, d_qs()));
+            HIP_TRY(hipStreamSynchronize(stream));
+            return fail(SU2_EHIP, err == 1u ? "work-queue launch: a bounded wait ran out of polls; "
+                                              "the sweeps since the last check are invalid"
+                                            : "work-queue launch: an XCD queue was not served "
+                                              "(too few workgroups); the sweeps since the last "
+                                              "check are invalid");
+        }
+        return SU2_OK;
+    }
 
     const float *mode_table(int mode, int *rc)
     {
@@ -309,6 +473,7 @@ public:
         const float *tab = mode_table(mode, &rc);
         if (rc) return rc;
         if (hist && reset_rows) HIP_TRY(launch_set_counter(ens(), 0, 0, 2, stream));
+        if (cfg.queue) return enqueue_queue(ns, tab, reunit_every, meas, hist);
         if (small_path()) {
             const int flags = (hist && (meas & SU2_MEAS_PLAQ) ? 1 : 0) |
                               (hist && (meas & SU2_MEAS_POLY) ? 2 : 0) | (hist ? 4 : 0);
@@ -399,6 +564,7 @@ public:
             HIP_TRY(hipMemcpyAsync(&v[3 * r], results(r), 3 * sizeof(double),
                                    hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
+        if (int rc = check_queue()) return rc;
         for (int r = 0; r < n; ++r) {
             if (plaq) plaq[r] = v[3 * r + R_PLAQ];
             if (poly_s) poly_s[r] = v[3 * r + R_POLY_SIGNED];
@@ -430,6 +596,7 @@ public:
         HIP_TRY(hipMemcpyAsync(planes.data(), links[r], planes.size() * 4, hipMemcpyDeviceToHost,
                                stream));
         HIP_TRY(hipStreamSynchronize(stream));
+        if (int rc = check_queue()) return rc;
         for (int64_t s = 0; s < V; ++s) {
             int64_t q = s;
             const int x = (int)(q % d[0]);
@@ -481,6 +648,7 @@ public:
     {
         if (block < 64 || block > 256 || (block % 64) != 0)
             return fail(SU2_EINVAL, "block must be 64, 128, 192 or 256");
+        if (flags < 0 || flags > 63) return fail(SU2_EINVAL, "flags must be in [0, 63]");
         if (grid_cap < 0) return fail(SU2_EINVAL, "grid_cap must be >= 0");
         uint32_t lz, lt;
         int rc;
@@ -490,7 +658,13 @@ public:
         cfg.xcd_remap = (flags & 1) != 0;
         cfg.snake = (flags & 2) == 0;
         cfg.small = (flags & 4) == 0;
+        cfg.queue = (flags & 8) != 0;
+        cfg.grain = 1 << ((flags >> 4) & 3);
         cfg.grid_cap = (uint32_t)grid_cap;
+        if (cfg.queue) {  // device queries stay out of any stream capture
+            queue_grid_auto[0] = queue_resident_grid(block, false);
+            queue_grid_auto[1] = queue_resident_grid(block, true);
+        }
         lg_tz = lz;
         lg_tt = lt;
         return upload();
@@ -624,6 +798,10 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
         for (int fl : {1, 3})  // remap + alternating order, remap only
             for (auto t : {std::array<int, 2>{8, 8}, {4, 8}, {2, 16}, {1, 1}, {16, 16}})
                 for (int gc : {0, 2048, 4096}) cands.push_back({b, fl | no_small, t[0], t[1], gc});
+    // the persistent work queue (one item per ticket is always slower: the
+    // per-run synchronisation dominates)
+    for (int b : {256, 128})
+        for (int gr : {1, 2}) cands.push_back({b, 1 | 8 | (gr << 4), 8, 8, 0});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -640,6 +818,7 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
         if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0.0f;
         if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if ((rc = check_queue())) break;
         const double us = 1e3 * ms / trial_sweeps;
         if (us < best.us) best = TuneEntry{c.block, c.flags, c.tz, c.tt, c.grid, us};
     }
@@ -768,8 +947,7 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
         E.own_pool = E.own_scratch = E.own_stream = true;
     }
     E.links = {E.pool};
-    E.bmap_off = Ensemble::descr_bytes(1);
-    E.rep_off = E.bmap_off;
+    E.bmap_off = E.qmap_off = E.rep_off = Ensemble::descr_bytes(1);
     if ((rc = E.upload()) || (rc = E.init({start}))) {
         E.release();
         delete c;
@@ -924,7 +1102,7 @@ int su2_synchronize(su2_ctx *c)
     int rc = check_ctx(c);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(c->E.stream));
-    return SU2_OK;
+    return c->E.check_queue();
 }
 
 int su2_set_launch(su2_ctx *c, int block, int flags, int tile_z, int tile_t, int grid_cap)
@@ -938,7 +1116,12 @@ static void get_launch(const Ensemble &E, int *block, int *flags, int *tile_z, i
                        int *grid_cap)
 {
     if (block) *block = E.cfg.pass_block;
-    if (flags) *flags = (E.cfg.xcd_remap ? 1 : 0) | (E.cfg.snake ? 0 : 2) | (E.cfg.small ? 0 : 4);
+    if (flags) {
+        int lg = 0;
+        while ((1 << lg) < E.cfg.grain) ++lg;
+        *flags = (E.cfg.xcd_remap ? 1 : 0) | (E.cfg.snake ? 0 : 2) | (E.cfg.small ? 0 : 4) |
+                 (E.cfg.queue ? 8 : 0) | (lg << 4);
+    }
     if (tile_z) *tile_z = 1 << E.geom[0].lg_tz;
     if (tile_t) *tile_t = 1 << E.geom[0].lg_tt;
     if (grid_cap) *grid_cap = (int)E.cfg.grid_cap;
@@ -1005,7 +1188,8 @@ int su2_batch_init(su2_batch **out, int32_t n, const int32_t *dims, const double
     for (int r = 0; r < n; ++r)
         E.links.push_back(reinterpret_cast<float *>(reinterpret_cast<char *>(p) + off[r]));
     E.bmap_off = Ensemble::descr_bytes(n);
-    E.rep_off = E.bmap_off + Ensemble::bmap_bytes(n, E.dims);
+    E.qmap_off = E.bmap_off + Ensemble::bmap_bytes(n, E.dims);
+    E.rep_off = E.qmap_off + Ensemble::bmap_bytes(n, E.dims);
     if ((rc = E.upload()) || (rc = E.init(std::vector<int>(starts, starts + n)))) {
         E.release();
         delete b;
@@ -1123,7 +1307,7 @@ int su2_batch_synchronize(su2_batch *b)
     int rc = check_batch(b);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(b->E.stream));
-    return SU2_OK;
+    return b->E.check_queue();
 }
 
 int su2_batch_get_accept_stats(su2_batch *b, uint64_t *proposed, uint64_t *accepted, int reset)
@@ -1134,6 +1318,103 @@ int su2_batch_get_accept_stats(su2_batch *b, uint64_t *proposed, uint64_t *accep
 }
 
 /* ================================================================ tests */
+int su2_test_queue_plan(int32_t n, const int32_t *dims, int block, int32_t queues,
+                        int32_t nsweeps, int32_t reunit_every, uint32_t first_sweep, int meas,
+                        int rows, int64_t *items_out)
+{
+    if (n < 1 || !dims || nsweeps < 1 || reunit_every < 0 || (block % 64) || block < 64 ||
+        block > 256 || queues < 1 || queues > kMaxQueues)
+        return fail(SU2_EINVAL, "bad arguments");
+    std::vector<std::array<int32_t, 4>> d(n);
+    for (int r = 0; r < n; ++r) {
+        if (int rc = check_dims(dims + 4 * r)) return rc;
+        for (int k = 0; k < 4; ++k) d[r][k] = dims[4 * r + k];
+    }
+    std::vector<uint32_t> first, nb, qfirst, qslots;
+    std::vector<int> qof;
+    const uint32_t total_blocks = slot_layout(d, block, first, nb);
+    queue_layout(nb, queues, qof, qfirst, qslots);
+    QueuePlan p{};
+    p.ns = (uint32_t)nsweeps;
+    p.reunit = (uint32_t)reunit_every;
+    p.phase = reunit_every ? first_sweep % (uint32_t)reunit_every : 0u;
+    p.want_p = rows && (meas & SU2_MEAS_PLAQ) ? 1u : 0u;
+    p.want_l = rows && (meas & SU2_MEAS_POLY) ? 1u : 0u;
+    p.rows = rows ? 1u : 0u;
+    if ((uint64_t)queue_total_stages(p) * total_blocks >= ((uint64_t)1 << 31))
+        return fail(SU2_ERANGE, "too many items");
+    // every slot of every replica belongs to exactly one queue position
+    for (int q = 0; q < queues; ++q) {
+        std::vector<int> owner(qslots[q], -1);
+        for (int r = 0; r < n; ++r)
+            if (qof[r] == q)
+                for (uint32_t k = 0; k < nb[r]; ++k) {
+                    if (qfirst[r] + k >= qslots[q] || owner[qfirst[r] + k] >= 0)
+                        return fail(SU2_ERANGE, "queue layout overlaps");
+                    owner[qfirst[r] + k] = r;
+                }
+        for (int o : owner)
+            if (o < 0) return fail(SU2_ERANGE, "queue layout has a hole");
+    }
+    // Run each queue's items one at a time in ticket order, in runs of
+    // `grain` = 1.  Deadlock freedom and completeness: when an item starts,
+    // its replica's done count must equal its target plus the items of the
+    // same stage already run (the target covers every earlier item of the
+    // replica and nothing later).
+    std::vector<uint32_t> done(n, 0u), in_stage(n, 0u), last_gs(n, 0xFFFFFFFFu), ends(n, 0u);
+    int64_t items = 0;
+    for (int q = 0; q < queues; ++q) {
+        std::vector<int> owner(qslots[q]);
+        for (int r = 0; r < n; ++r)
+            if (qof[r] == q)
+                for (uint32_t k = 0; k < nb[r]; ++k) owner[qfirst[r] + k] = r;
+        const uint64_t total = (uint64_t)queue_total_stages(p) * qslots[q];
+        for (uint64_t t = 0; t < total; ++t) {
+            const QueueItem it = queue_decode(p, (uint32_t)t, qslots[q]);
+            const uint32_t gs = queue_stages_before(p, it.sweep) + it.stage;
+            if (gs != t / qslots[q] || it.slot != t % qslots[q] || it.sweep >= p.ns)
+                return fail(SU2_ERANGE, "decode mismatch at item " + std::to_string(t));
+            const int r = owner[it.slot];
+            const bool reunit = queue_reunit_sweep(p, it.sweep);
+            const int want_kind = it.stage < 8u ? QK_PASS
+                                  : (reunit && it.stage == 8u) ? QK_REUNIT
+                                  : (reunit && p.want_p && it.stage == 9u) ? QK_PLAQ : QK_POLY;
+            if (it.kind != want_kind || (it.kind == QK_POLY && !p.want_l))
+                return fail(SU2_ERANGE, "stage kind mismatch at item " + std::to_string(t));
+            if (gs != last_gs[r]) {
+                last_gs[r] = gs;
+                in_stage[r] = 0u;
+            }
+            const uint32_t target = queue_target(p, nb[r], it.sweep, it.stage);
+            if (done[r] != target + in_stage[r])
+                return fail(SU2_ERANGE, "item " + std::to_string(t) + " of replica " +
+                                            std::to_string(r) + ": done " +
+                                            std::to_string(done[r]) + ", target " +
+                                            std::to_string(target));
+            ++in_stage[r];
+            ++items;
+            if (++done[r] == queue_sweep_last(p, nb[r], it.sweep)) {
+                if (ends[r] != it.sweep) return fail(SU2_ERANGE, "sweep ends out of order");
+                ++ends[r];
+                ++done[r];  // the bookkeeping item
+            }
+        }
+    }
+    for (int r = 0; r < n; ++r)
+        if (ends[r] != p.ns || done[r] != queue_target(p, nb[r], p.ns, 0u))
+            return fail(SU2_ERANGE, "replica " + std::to_string(r) + " did not finish");
+    if (items_out) *items_out = items;
+    return SU2_OK;
+}
+
+int su2_test_batch_spin_limit(su2_batch *b, uint32_t polls)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    b->E.spin_limit = polls;
+    return SU2_OK;
+}
+
 int su2_test_philox(const uint32_t *ctr_host, int64_t n, uint64_t seed, uint32_t *out_host)
 {
     if (n < 0 || (n > 0 && (!ctr_host || !out_host))) return fail(SU2_EINVAL, "bad arguments");

@@ -84,6 +84,8 @@ _SIGS = {
     "su2_test_gauge_transform": (_int, [_vp, _u64]),
     "su2_test_stream_pass": (_int, [_vp, _int, _int, _vp]),
     "su2_test_index_map": (_int, [_vp, _int, _int, _int, _vp]),
+    "su2_test_queue_plan": (_int, [_i32, _vp, _int, _i32, _i32, _i32, _u32, _int, _int, _vp]),
+    "su2_test_batch_spin_limit": (_int, [_vp, _u32]),
     "su2_nn_num_params": (_int, []),
     "su2_nn_create": (_int, [_vp, _vp, _u64, _vp]),
     "su2_nn_destroy": (_int, [_vp]),
@@ -301,6 +303,17 @@ def su2_test_index_map(dims, parity, tile_z=0, tile_t=0):
     out = np.empty((vh, 9), dtype=np.uint32)
     _check(lib().su2_test_index_map(_p(d), int(tile_z), int(tile_t), int(parity), _p(out)))
     return out
+
+
+def su2_test_queue_plan(dims, block, nsweeps, reunit_every=0, first_sweep=0, meas=0,
+                        rows=False, queues=8):
+    """Host-side check of the work-queue schedule; returns the items run."""
+    d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 4))
+    items = ctypes.c_int64()
+    _check(lib().su2_test_queue_plan(len(d), _p(d), int(block), int(queues), int(nsweeps),
+                                     int(reunit_every), int(first_sweep), int(meas), int(rows),
+                                     ctypes.byref(items)))
+    return items.value
 
 
 def su2_test_stream_pass(h, mu, parity, out_ptr):
@@ -654,6 +667,9 @@ class Batch:
 
     def launch(self):
         return su2_get_launch(self.h, batch=True)
+
+    def test_spin_limit(self, polls):
+        _check(lib().su2_test_batch_spin_limit(self.h, int(polls)))
 
     def autotune(self, cache_path=None, mode=SU2_KP):
         us = ctypes.c_double()

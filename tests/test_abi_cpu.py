@@ -94,3 +94,43 @@ def test_index_map_rejects_bad_tiles():
         su2.su2_test_index_map([4, 4, 6, 4], 0, tile_z=4)
     with pytest.raises(su2.SU2Error):
         su2.su2_test_index_map([4, 4, 4, 4], 0, tile_t=3)
+
+
+REPLICAS64 = [[8 + 2 * (r % 7)] * 4 for r in range(64)]
+
+
+@pytest.mark.parametrize("queues", [1, 3, 8])
+@pytest.mark.parametrize("dims,block,ns,reunit,first,meas,rows", [
+    ([[4, 4, 4, 4]], 256, 7, 0, 0, 0, False),
+    ([[48, 48, 48, 48]], 256, 2, 2, 1, 3, True),
+    ([[8, 6, 8, 16], [4, 4, 4, 8], [6, 6, 6, 4]], 64, 13, 4, 3, 3, True),
+    ([[8, 6, 8, 16], [4, 4, 4, 8], [6, 6, 6, 4]], 128, 9, 3, 0, 1, True),
+    ([[2, 2, 2, 2], [16, 16, 16, 16]], 192, 6, 1, 0, 2, True),
+    (REPLICAS64, 256, 5, 10, 8, 1, True),
+    (REPLICAS64, 128, 3, 0, 0, 3, False),
+], ids=["4^4", "48^4", "three-mixed", "three-plaq", "reunit-every-sweep", "replicas64",
+        "replicas64-nomeas"])
+def test_work_queue_schedule(dims, block, ns, reunit, first, meas, rows, queues):
+    """The persistent work-queue launch run on the host one item at a time in
+    ticket order, queue by queue: the replicas' slots tile the queues, every
+    item's wait target counts exactly its replica's earlier items (no
+    deadlock, no early start), the stage kinds follow the sweep schedule and
+    every sweep of every replica ends."""
+    items = su2.su2_test_queue_plan(dims, block, ns, reunit, first, meas, rows, queues)
+    nb = [-(-int(np.prod(d)) // 2 // block) for d in dims]
+    per_sweep = 8 + (1 if rows and meas & 2 else 0)
+    n_reunit = sum(1 for j in range(first, first + ns) if reunit and (j + 1) % reunit == 0)
+    extra = n_reunit * (1 + (1 if rows and meas & 1 else 0))
+    assert items == sum(nb) * (per_sweep * ns + extra)
+
+
+def test_work_queue_schedule_rejects_bad_arguments():
+    with pytest.raises(su2.SU2Error):
+        su2.su2_test_queue_plan([[4, 4, 4, 4]], 100, 2)
+    with pytest.raises(su2.SU2Error):
+        su2.su2_test_queue_plan([[4, 4, 4, 5]], 256, 2)
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_test_queue_plan([[48, 48, 48, 48]], 64, 100000)
+    assert e.value.code == su2.SU2_ERANGE
+    with pytest.raises(su2.SU2Error):
+        su2.su2_test_queue_plan([[4, 4, 4, 4]], 256, 2, queues=17)
