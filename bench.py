@@ -36,6 +36,7 @@ METRIC = "SU(2) link updates/sec + % HBM roofline, plain vs learned-proposal, 1 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 128
 DIMS = [48, 48, 48, 48]
+OR_WIDTH = 0.02  # noise half-width of the over-relaxed learned proposal
 BETA = 6.0
 SEED = 3
 
@@ -87,7 +88,10 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
     launch, then graph-captured chunks of batched sweeps with the plaquette
     measured every sweep.  Effective rate = sweeps/s / (2 tau_int(P)), averaged
     over the replicas.  The untrained network (identity spline, i.e. a uniform
-    proposal) runs the same protocol for comparison."""
+    proposal) runs the same protocol for comparison, and so does the trained
+    flow used over-relaxed (proposal -g(x_old) + noise in the flow coordinate,
+    noise half-width OR_WIDTH, and without noise), which anticorrelates
+    successive plaquettes."""
     n = 64
     L = [8 + 2 * (r % 7) for r in range(n)]
     dims = [[l] * 4 for l in L]
@@ -111,10 +115,14 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
                            "nll_last_100": float(hist[-100:].mean())}
         untrained = su2.NN(seed=5)  # identity spline: the uniform proposal
         untrained.build_table()
-        for name, mode, proposal in (("plain", su2.SU2_KP, net), ("learned", su2.SU2_LEARNED, net),
-                                     ("learned_untrained", su2.SU2_LEARNED, untrained)):
+        for name, mode, proposal, width in (
+                ("plain", su2.SU2_KP, net, -1.0), ("learned", su2.SU2_LEARNED, net, -1.0),
+                ("learned_untrained", su2.SU2_LEARNED, untrained, -1.0),
+                ("learned_overrelaxed", su2.SU2_LEARNED, net, OR_WIDTH),
+                ("learned_reflection", su2.SU2_LEARNED, net, 0.0)):
             b = su2.Batch(dims, betas, [1] * n, seed=5, device=dev)
             b.set_proposal(proposal)
+            b.set_overrelax(width)
             tuned_us = b.autotune(None, mode)
             b.sweep(therm, mode)
             b.accept_stats(reset=True)
@@ -130,6 +138,7 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
             taus = np.array([tau_int(P[:, r]) for r in range(n)])
             sps = sweeps / dt
             out[name] = {"link_updates_per_s": links * sps, "sweeps_per_s": sps,
+                         "overrelax_width": None if width < 0 else width,
                          "tuned_us_per_sweep": tuned_us,
                          "tau_int_plaquette_mean": float(taus.mean()),
                          "effective_sweeps_per_s": float(np.mean(sps / (2 * taus))),
@@ -143,6 +152,9 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
                                          out["plain"]["link_updates_per_s"])
     out["learned_over_plain_effective"] = (out["learned"]["effective_sweeps_per_s"] /
                                            out["plain"]["effective_sweeps_per_s"])
+    out["overrelaxed_over_plain_effective"] = (
+        out["learned_overrelaxed"]["effective_sweeps_per_s"] /
+        out["plain"]["effective_sweeps_per_s"])
     return out
 
 

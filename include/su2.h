@@ -267,6 +267,20 @@ int su2_nn_get_table(su2_nn *nn, float *table_host);
  * outlive every sweep enqueued with it and its table must be built. */
 int su2_set_proposal(su2_ctx *ctx, su2_nn *nn);
 int su2_batch_set_proposal(su2_batch *b, su2_nn *nn);
+/* Over-relaxed use of the learned flow in SU2_LEARNED sweeps.  width < 0
+ * (default): the independence proposal u = 2z - 1 above.  0 <= width <= 1:
+ * the proposal u' = -g(x_old) + width (2z - 1), wrapped onto [-1, 1) with
+ * period 2 (the reflection of the old link's flow coordinate plus uniform
+ * noise), a0' = g^{-1}(u').  Its density in u is symmetric in (u, u'), so the
+ * same Metropolis ratio w(a0')/w(x_old) keeps the heat-bath distribution of
+ * Sec. 2 exact; width > 0 makes the chain irreducible, width = 1 is the
+ * independence proposal in distribution, and for an exact flow width -> 0 is
+ * ordered over-relaxation of a0 (Neal 1998): a0 moves to its opposite quantile
+ * and successive configurations anticorrelate.  The direction of X is drawn
+ * afresh as in the independence form.  SU2_EINVAL for width > 1 or NaN.
+ * Drops captured sweeps. */
+int su2_set_overrelax(su2_ctx *ctx, double width);
+int su2_batch_set_overrelax(su2_batch *b, double width);
 /* Learned proposals made and accepted since the last reset (synchronous). */
 int su2_get_accept_stats(su2_ctx *ctx, uint64_t *proposed, uint64_t *accepted, int reset);
 
@@ -314,11 +328,13 @@ int su2_test_queue_plan(int32_t n, const int32_t *dims, int block, int32_t queue
  * drains normally and the next synchronising call returns SU2_EHIP. */
 int su2_test_batch_spin_limit(su2_batch *b, uint32_t polls);
 /* Learned-proposal update of n independent links (host float[n][4] staples V
- * and old links Uold); link i uses site index i.  accepted_host (may be NULL):
- * 1 accepted, 0 rejected, -1 exact fallback. */
+ * and old links Uold); link i uses site index i; or_width as
+ * su2_set_overrelax (< 0: independence proposal).  accepted_host (may be
+ * NULL): 1 accepted, 0 rejected, -1 exact fallback. */
 int su2_test_learned_links(su2_nn *nn, const float *V_host, const float *Uold_host, int64_t n,
                            double beta, uint64_t seed, uint32_t sweep, uint32_t mu,
-                           uint32_t replica, float *out_host, int32_t *accepted_host);
+                           uint32_t replica, double or_width, float *out_host,
+                           int32_t *accepted_host);
 /* Enqueue U_mu(x) -> G(x) U_mu(x) G(x+mu)^+ with G Haar from Philox tag 3. */
 int su2_test_gauge_transform(su2_ctx *ctx, uint64_t seed);
 

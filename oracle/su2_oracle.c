@@ -645,7 +645,7 @@ static double log_weight(double alpha, double xv, double logderiv)
 
 void orc_learned_link(const double V[4], const double Uold[4], const double *table, double beta,
                       uint64_t seed, uint32_t site, uint32_t sweep, uint32_t mu, uint32_t replica,
-                      double out[4], double margin[3], int *accepted)
+                      double or_width, double out[4], double margin[3], int *accepted)
 {
     const double k = qnorm(V);
     const double alpha = beta * k;
@@ -670,15 +670,28 @@ void orc_learned_link(const double V[4], const double Uold[4], const double *tab
     double r[4];
     block(seed, site, sweep, word2_of(mu, ORC_TAG_LEARN, replica), 0u, r, NULL);
     double ld_new, ld_old, t[4];
-    const double a0n = orc_spline_inv(x, y, d, 2.0 * r[0] - 1.0, &ld_new);
+    /* the old link in the frame of the staple: x_old = (U_old U~)_0 */
     orc_qmul(Uold, Ut, t);
     double xo = t[0];
     if (xo > 1.0) xo = 1.0;
     if (xo < -1.0) xo = -1.0;
-    orc_spline_fwd(x, y, d, xo, &ld_old);
+    const double u_old = orc_spline_fwd(x, y, d, xo, &ld_old);
+    /* proposal in the flow coordinate u = g(a0): independent and uniform, or
+     * (over-relaxed) the reflection -u_old plus uniform noise of half-width
+     * or_width, taken modulo 2 into [-1, 1).  Both proposal densities are
+     * symmetric in (u_old, u), so the Metropolis ratio is w(a0')/w(x_old) with
+     * w = p / q, q = g'/2 the flow's density of a0. */
+    double u = 2.0 * r[0] - 1.0, wrap_margin = INFINITY;
+    if (or_width >= 0.0) {
+        u = or_width * u - u_old;
+        wrap_margin = fmin(fabs(u - 1.0), fabs(u + 1.0));
+        if (u >= 1.0) u -= 2.0;
+        else if (u < -1.0) u += 2.0;
+    }
+    const double a0n = orc_spline_inv(x, y, d, u, &ld_new);
     const double lw = log_weight(alpha, a0n, ld_new) - log_weight(alpha, xo, ld_old);
     const double dm = lw - log(r[1]);
-    m3[0] = fabs(dm);
+    m3[0] = fmin(fabs(dm), wrap_margin);
     if (dm > 0.0) {
         const double amag = sqrt((1.0 - a0n) * (1.0 + a0n));
         const double cth = 1.0 - 2.0 * r[2], sth = 2.0 * sqrt(r[2] * (1.0 - r[2]));
@@ -696,7 +709,7 @@ void orc_learned_link(const double V[4], const double Uold[4], const double *tab
 
 void orc_learned_pass(const int32_t dims[4], double *U, const double *table, int mu, int parity,
                       uint32_t sweep, double beta, uint64_t seed, uint32_t replica,
-                      double *margin, int32_t *accepted)
+                      double or_width, double *margin, int32_t *accepted)
 {
     const int64_t Vol = orc_volume(dims);
     for (int64_t s = 0; s < Vol; ++s) {
@@ -705,7 +718,7 @@ void orc_learned_pass(const int32_t dims[4], double *U, const double *table, int
         int acc;
         orc_staple(dims, U, s, mu, St);
         orc_learned_link(St, U + (s * 4 + mu) * 4, table, beta, seed, (uint32_t)s, sweep,
-                         (uint32_t)mu, replica, out, m, &acc);
+                         (uint32_t)mu, replica, or_width, out, m, &acc);
         memcpy(U + (s * 4 + mu) * 4, out, sizeof(out));
         if (margin) memcpy(margin + 3 * s, m, sizeof(m));
         if (accepted) accepted[s] = acc;

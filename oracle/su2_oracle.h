@@ -139,16 +139,21 @@ void orc_nn_table(const float *params, double *table /* 64 x 48 */);
 int orc_table_row(double alpha, double *margin);
 void orc_table_knots(const double *table, int row, double x[17], double y[17], double d[17]);
 /* Learned-proposal Metropolis update of one link (fallback: exact heat bath).
+ * or_width < 0: independence proposal u = 2 r0 - 1 in the flow coordinate;
+ * 0 <= or_width <= 1: over-relaxed proposal u = -g(x_old) + or_width (2 r0 - 1)
+ * modulo 2 into [-1, 1) (a symmetric proposal in u; ordered over-relaxation,
+ * Neal 1998, as or_width -> 0 for an exact flow).
  * accepted: 1 accepted, 0 rejected, -1 exact fallback.  margin[3]: the
- * Metropolis log-ratio margin (or the exact sampler's), the table-row
- * rounding margin in rows, the distance of alpha to the table range ends. */
+ * Metropolis log-ratio margin (or the exact sampler's; with over-relaxation
+ * also the distance of the unwrapped u to +-1), the table-row rounding margin
+ * in rows, the distance of alpha to the table range ends. */
 void orc_learned_link(const double V[4], const double Uold[4], const double *table, double beta,
                       uint64_t seed, uint32_t site, uint32_t sweep, uint32_t mu, uint32_t replica,
-                      double out[4], double margin[3], int *accepted);
+                      double or_width, double out[4], double margin[3], int *accepted);
 /* margin: 3 per site (as above), may be NULL. */
 void orc_learned_pass(const int32_t dims[4], double *U, const double *table, int mu, int parity,
                       uint32_t sweep, double beta, uint64_t seed, uint32_t replica,
-                      double *margin, int32_t *accepted);
+                      double or_width, double *margin, int32_t *accepted);
 
 void orc_nn_data(int64_t n, double lo, double hi, uint64_t seed, double *alpha, double *a0);
 

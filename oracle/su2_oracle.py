@@ -70,9 +70,9 @@ def _load():
         "orc_table_row": (c_int, [c_d, ctypes.POINTER(c_d)]),
         "orc_table_knots": (None, [_f64p, c_int, _f64p, _f64p, _f64p]),
         "orc_learned_link": (None, [_f64p, _f64p, _f64p, c_d, c_u64, c_u32, c_u32, c_u32, c_u32,
-                                    _f64p, _f64p, ctypes.POINTER(c_int)]),
+                                    c_d, _f64p, _f64p, ctypes.POINTER(c_int)]),
         "orc_learned_pass": (None, [_i32p, _f64p, _f64p, c_int, c_int, c_u32, c_d, c_u64, c_u32,
-                                    vp, vp]),
+                                    c_d, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -280,26 +280,27 @@ def table_knots(table, row):
     return x, y, d
 
 
-def learned_link(V, Uold, table, beta, seed, site, sweep, mu, replica=0):
-    """Returns (new link, margins (mh, row, range), accepted 1 / 0 / -1 fallback)."""
+def learned_link(V, Uold, table, beta, seed, site, sweep, mu, replica=0, or_width=-1.0):
+    """Returns (new link, margins (mh, row, range), accepted 1 / 0 / -1 fallback).
+    or_width < 0: independence proposal; else the over-relaxed proposal."""
     out = np.zeros(4)
     m = np.zeros(3)
     acc = ctypes.c_int()
     _load().orc_learned_link(np.ascontiguousarray(V, np.float64),
                              np.ascontiguousarray(Uold, np.float64),
                              np.ascontiguousarray(table, np.float64), float(beta),
-                             np.uint64(seed), int(site), int(sweep), int(mu), int(replica), out,
-                             m, ctypes.byref(acc))
+                             np.uint64(seed), int(site), int(sweep), int(mu), int(replica),
+                             float(or_width), out, m, ctypes.byref(acc))
     return out, m, acc.value
 
 
-def learned_pass(dims, U, table, mu, par, sweep, beta, seed, replica=0):
+def learned_pass(dims, U, table, mu, par, sweep, beta, seed, replica=0, or_width=-1.0):
     """Returns (margins (V, 3), accepted (V,)) for the updated sites."""
     margin = np.full((volume(dims), 3), np.inf)
     acc = np.full(volume(dims), -2, dtype=np.int32)
     _load().orc_learned_pass(_dims(dims), _c(U), np.ascontiguousarray(table, np.float64),
                              int(mu), int(par), int(sweep), float(beta), np.uint64(seed),
-                             int(replica), _ptr(margin), _ptr(acc))
+                             int(replica), float(or_width), _ptr(margin), _ptr(acc))
     return margin, acc
 
 

@@ -384,9 +384,19 @@ __device__ __forceinline__ void rq_deriv_parts(const RQBin &b, float s, float xi
 
 // Learned-proposal Metropolis update of one link.  acc: 1 accepted, 0
 // rejected (U' = Uold), -1 exact fallback (alpha outside the table range).
+//
+// orw < 0: independence proposal u = 2 z - 1.  orw >= 0: over-relaxed
+// proposal u = wrap(-g(x_old) + orw (2 z - 1)) with wrap onto [-1, 1) of
+// period 2 -- the reflection of the old link's flow coordinate plus uniform
+// noise of half-width orw.  Its density in u is symmetric, f(u + u_old), so
+// the Metropolis ratio is the same weight ratio w(a0') / w(x_old); any orw > 0
+// makes two steps a random walk on the circle (irreducible), and orw = 1 is
+// the independence proposal again.  With an exact flow the reflection maps
+// a0 to its opposite quantile (ordered over-relaxation, Neal 1998).
 __device__ __forceinline__ Q learned_link(const Q &V, const Q &Uold, const float *__restrict__ table,
                                           float beta, uint32_t site, uint32_t sweep, uint32_t mu,
-                                          uint32_t replica, uint32_t k0, uint32_t k1, int &acc)
+                                          uint32_t replica, uint32_t k0, uint32_t k1, int &acc,
+                                          float orw = -1.0f)
 {
     const float k2 = qdot(V, V);
     const float inv_k = k2 > 0.0f ? hw_rsq(k2) : 0.0f;
@@ -401,11 +411,21 @@ __device__ __forceinline__ Q learned_link(const Q &V, const Q &Uold, const float
     const float4 xa = r4[0], xb = r4[1], xc = r4[2], xd = r4[3];
     const float4 ya = r4[4], yb = r4[5], yc = r4[6], yd = r4[7];
     const U4 w = philox(site, sweep, word2(mu, TAG_LEARN, replica), 0u, k0, k1);
-    const float u = 2.0f * u01(w.a) - 1.0f;
     // current link in the frame of the staple: x_old = (U_old U~)_0
     const float xo = fminf(fmaxf(retr(Uold, Ut), -1.0f), 1.0f);
-    const RQBin bn = rq_bin_at(row, rq_bin_index(ya, yb, yc, yd, u));
     const RQBin bo = rq_bin_at(row, rq_bin_index(xa, xb, xc, xd, xo));
+    float u = 2.0f * u01(w.a) - 1.0f;
+    if (orw >= 0.0f) {  // uniform over the launch
+        // g(x_old) in its bin: y_l + H (s xi^2 + d_l xi (1 - xi)) / (s + (d_h + d_l - 2 s) xi (1 - xi))
+        const float rw = hw_rcp(bo.W);
+        const float s = bo.H * rw, xi = (xo - bo.xl) * rw, om = xi * (1.0f - xi);
+        const float yo = bo.yl + bo.H * (s * xi * xi + bo.dl * om) *
+                                     hw_rcp(s + (bo.dh + bo.dl - 2.0f * s) * om);
+        float v = orw * u - yo;
+        v = v >= 1.0f ? v - 2.0f : (v < -1.0f ? v + 2.0f : v);
+        u = v;
+    }
+    const RQBin bn = rq_bin_at(row, rq_bin_index(ya, yb, yc, yd, u));
     // proposal a0' = g^{-1}(u): root xi of qa xi^2 + qb xi + qc = 0 in the bin
     const float sn = bn.H * hw_rcp(bn.W);
     const float dy = u - bn.yl, tt = bn.dh + bn.dl - 2.0f * sn;

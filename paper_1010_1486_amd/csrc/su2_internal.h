@@ -60,6 +60,8 @@ struct Rep {
     uint32_t first_block;      // first pass workgroup of this replica (multiple of 8)
     uint32_t nblocks;          // pass workgroups of this replica
     uint32_t qfirst;           // first work-queue slot of this replica in its queue
+    float orw;                 // learned proposal: < 0 independence, else over-relaxed
+                               // with noise half-width orw (learned_link)
 };
 
 // Per-replica scratch: counters, accumulators, result slots.
@@ -257,7 +259,7 @@ hipError_t launch_nn_adam(const NNBuffers &nb, float lr, int step, hipStream_t s
 hipError_t launch_nn_table(const float *params, float *table, hipStream_t stream);
 hipError_t launch_test_learned(const float *table, const float *V, const float *Uold, int64_t n,
                                float beta, uint64_t seed, uint32_t sweep, uint32_t mu,
-                               uint32_t replica, float *out, int32_t *accepted,
+                               uint32_t replica, float orw, float *out, int32_t *accepted,
                                hipStream_t stream);
 
 }  // namespace su2rt

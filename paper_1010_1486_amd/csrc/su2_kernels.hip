@@ -216,7 +216,7 @@ __device__ __forceinline__ void update_site(const Rep &R, uint32_t gid, int par,
     if (LEARNED) {
         const Q Uold = ld(arr(links, g.vh, MU, par), h);
         Un = learned_link(V, Uold, ltab, R.beta, site, sweep, (uint32_t)MU, R.replica, k0, k1,
-                          acc);
+                          acc, R.orw);
     } else {
         Un = heatbath_link(V, R.beta, site, sweep, word2((uint32_t)MU, TAG_TRIAL, R.replica), k0,
                            k1);

@@ -320,7 +320,7 @@ __global__ void nn_table_kernel(const float *__restrict__ params, float *__restr
 __global__ void test_learned_kernel(const float *__restrict__ table, const float4 *__restrict__ V,
                                     const float4 *__restrict__ Uold, int64_t n, float beta,
                                     uint32_t k0, uint32_t k1, uint32_t sweep, uint32_t mu,
-                                    uint32_t replica, float4 *__restrict__ out,
+                                    uint32_t replica, float orw, float4 *__restrict__ out,
                                     int32_t *__restrict__ accepted)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -328,7 +328,7 @@ __global__ void test_learned_kernel(const float *__restrict__ table, const float
     const float4 v = V[i], u = Uold[i];
     int acc = 0;
     const Q r = learned_link(Q{v.x, v.y, v.z, v.w}, Q{u.x, u.y, u.z, u.w}, table, beta,
-                             (uint32_t)i, sweep, mu, replica, k0, k1, acc);
+                             (uint32_t)i, sweep, mu, replica, k0, k1, acc, orw);
     out[i] = make_float4(r.w, r.x, r.y, r.z);
     if (accepted) accepted[i] = acc;
 }
@@ -377,13 +377,13 @@ hipError_t launch_nn_table(const float *params, float *table, hipStream_t stream
 
 hipError_t launch_test_learned(const float *table, const float *V, const float *Uold, int64_t n,
                                float beta, uint64_t seed, uint32_t sweep, uint32_t mu,
-                               uint32_t replica, float *out, int32_t *accepted,
+                               uint32_t replica, float orw, float *out, int32_t *accepted,
                                hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(test_learned_kernel, dim3(nblk((uint64_t)n, 256)), dim3(256), 0, stream,
                        table, (const float4 *)V, (const float4 *)Uold, n, beta, (uint32_t)seed,
-                       (uint32_t)(seed >> 32), sweep, mu, replica, (float4 *)out, accepted);
+                       (uint32_t)(seed >> 32), sweep, mu, replica, orw, (float4 *)out, accepted);
     return hipGetLastError();
 }
 

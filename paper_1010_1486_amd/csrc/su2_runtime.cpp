@@ -239,6 +239,7 @@ public:
     bool own_stream = false;
     uint64_t seed = 0;
     uint32_t sweep = 0;  // host mirror of the (common) sweep counter
+    float orw = -1.0f;   // learned proposal: over-relaxation noise width (< 0: off)
     LaunchCfg cfg;
     uint32_t lg_tz = 3, lg_tt = 3;
     const float *table = nullptr;
@@ -333,6 +334,7 @@ public:
             h[r].first_block = first_block[r];
             h[r].nblocks = nblocks[r];
             h[r].qfirst = 0u;
+            h[r].orw = orw;
         }
         if (cfg.queue) {
             std::vector<int> ids;
@@ -1068,6 +1070,27 @@ int su2_set_sweep(su2_ctx *c, uint32_t sweep)
     int rc = check_ctx(c);
     if (rc) return rc;
     return c->E.set_sweep(sweep);
+}
+
+static int set_overrelax(Ensemble &E, double width)
+{
+    if (!(width <= 1.0)) return fail(SU2_EINVAL, "width must be <= 1 (< 0: off)");
+    E.orw = width < 0.0 ? -1.0f : (float)width;
+    return E.upload();
+}
+
+int su2_set_overrelax(su2_ctx *c, double width)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    return set_overrelax(c->E, width);
+}
+
+int su2_batch_set_overrelax(su2_batch *b, double width)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    return set_overrelax(b->E, width);
 }
 
 int su2_set_beta(su2_ctx *c, double beta)
@@ -1813,10 +1836,12 @@ int su2_get_accept_stats(su2_ctx *c, uint64_t *proposed, uint64_t *accepted, int
 
 int su2_test_learned_links(su2_nn *n, const float *V_host, const float *Uold_host, int64_t count,
                            double beta, uint64_t seed, uint32_t sweep, uint32_t mu,
-                           uint32_t replica, float *out_host, int32_t *accepted_host)
+                           uint32_t replica, double or_width, float *out_host,
+                           int32_t *accepted_host)
 {
     if (!n || count < 0 || (count > 0 && (!V_host || !Uold_host || !out_host)))
         return fail(SU2_EINVAL, "bad arguments");
+    if (!(or_width <= 1.0)) return fail(SU2_EINVAL, "or_width must be <= 1 (< 0: off)");
     if (!n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
     if (count >= ((int64_t)1 << 32) || mu > 3) return fail(SU2_EINVAL, "bad count or mu");
     if (count == 0) return SU2_OK;
@@ -1830,7 +1855,8 @@ int su2_test_learned_links(su2_nn *n, const float *V_host, const float *Uold_hos
     if (e == hipSuccess) e = hipMemcpy(du, Uold_host, bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = launch_test_learned(n->b.table, (const float *)dv, (const float *)du, count,
-                                (float)beta, seed, sweep, mu, replica, (float *)dout,
+                                (float)beta, seed, sweep, mu, replica,
+                                or_width < 0.0 ? -1.0f : (float)or_width, (float *)dout,
                                 (int32_t *)dacc, nullptr);
     if (e == hipSuccess) e = hipMemcpy(out_host, dout, bytes, hipMemcpyDeviceToHost);
     if (e == hipSuccess && accepted_host)

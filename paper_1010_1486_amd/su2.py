@@ -101,8 +101,10 @@ _SIGS = {
     "su2_nn_get_table": (_int, [_vp, _vp]),
     "su2_set_proposal": (_int, [_vp, _vp]),
     "su2_get_accept_stats": (_int, [_vp, _vp, _vp, _int]),
-    "su2_test_learned_links": (_int, [_vp, _vp, _vp, _i64, _d, _u64, _u32, _u32, _u32, _vp,
-                                      _vp]),
+    "su2_test_learned_links": (_int, [_vp, _vp, _vp, _i64, _d, _u64, _u32, _u32, _u32, _d,
+                                      _vp, _vp]),
+    "su2_set_overrelax": (_int, [_vp, _d]),
+    "su2_batch_set_overrelax": (_int, [_vp, _d]),
 }
 
 
@@ -408,13 +410,14 @@ def su2_get_accept_stats(ctx, reset=False):
     return p.value, a.value
 
 
-def su2_test_learned_links(nn, V, Uold, beta, seed, sweep, mu, replica=0):
+def su2_test_learned_links(nn, V, Uold, beta, seed, sweep, mu, replica=0, or_width=-1.0):
     v = np.ascontiguousarray(V, dtype=np.float32).reshape(-1, 4)
     u = np.ascontiguousarray(Uold, dtype=np.float32).reshape(-1, 4)
     out = np.empty_like(v)
     acc = np.empty(v.shape[0], dtype=np.int32)
     _check(lib().su2_test_learned_links(nn, _p(v), _p(u), v.shape[0], float(beta), int(seed),
-                                        int(sweep), int(mu), int(replica), _p(out), _p(acc)))
+                                        int(sweep), int(mu), int(replica), float(or_width),
+                                        _p(out), _p(acc)))
     return out, acc
 
 
@@ -470,8 +473,8 @@ class NN:
     def table(self):
         return su2_nn_get_table(self.h)
 
-    def test_links(self, V, Uold, beta, seed, sweep, mu, replica=0):
-        return su2_test_learned_links(self.h, V, Uold, beta, seed, sweep, mu, replica)
+    def test_links(self, V, Uold, beta, seed, sweep, mu, replica=0, or_width=-1.0):
+        return su2_test_learned_links(self.h, V, Uold, beta, seed, sweep, mu, replica, or_width)
 
 
 # ------------------------------------------------------------ convenience
@@ -584,6 +587,10 @@ class Lattice:
     def set_proposal(self, nn):
         su2_set_proposal(self.h, None if nn is None else nn.h)
 
+    def set_overrelax(self, width):
+        """width < 0: independence proposal; 0..1: over-relaxed learned proposal."""
+        _check(lib().su2_set_overrelax(self.h, float(width)))
+
     def accept_stats(self, reset=False):
         return su2_get_accept_stats(self.h, reset)
 
@@ -682,6 +689,10 @@ class Batch:
 
     def set_proposal(self, nn):
         _check(lib().su2_batch_set_proposal(self.h, None if nn is None else nn.h))
+
+    def set_overrelax(self, width):
+        """width < 0: independence proposal; 0..1: over-relaxed learned proposal."""
+        _check(lib().su2_batch_set_overrelax(self.h, float(width)))
 
     def accept_stats(self, reset=False):
         p = np.zeros(self.n, dtype=np.uint64)

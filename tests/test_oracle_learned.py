@@ -163,3 +163,97 @@ def test_mh_fallback_outside_range_is_heat_bath(orc):
     want, _ = orc.heatbath_link(V, 2.0, 5, 7, 3, 1)
     assert a == -1
     np.testing.assert_array_equal(out, want)
+
+
+# ------------------------------------------------------ over-relaxed proposal
+def _links_with_a0(x, Ut, seed):
+    """Links U with (U U~)_0 = x and a random direction of the vector part."""
+    rng = np.random.default_rng(seed)
+    n = rng.standard_normal((len(x), 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    X = np.concatenate([x[:, None], np.sqrt(1 - x * x)[:, None] * n], axis=1)
+    Utd = np.broadcast_to(Ut * np.array([1, -1, -1, -1]), X.shape)
+    return orc_qmul(X, Utd)
+
+
+def orc_qmul(a, b):
+    from oracle import su2_oracle
+    return su2_oracle.qmul(a, b)
+
+
+def _one_step(orc, table, V, beta, x, width, seed):
+    """One over-relaxed learned update of links whose a0 in the staple frame is
+    x; returns the new a0 values and the acceptance fraction."""
+    Ut = V / np.linalg.norm(V)
+    U = _links_with_a0(x, Ut, seed)
+    out, acc = np.empty(len(x)), 0
+    for i in range(len(x)):
+        Un, _, a = orc.learned_link(V, U[i], table, beta, seed, i, 0, 0, or_width=width)
+        acc += a == 1
+        out[i] = orc.qmul(Un, Ut)[0][0]
+    return out, acc / len(x)
+
+
+@pytest.mark.parametrize("width", [0.0, 0.3])
+def test_or_step_keeps_the_exact_distribution(orc, width):
+    """Starting from exact draws of p(a0) ~ sqrt(1 - a0^2) exp(alpha a0) (Sec.
+    2), one over-relaxed Metropolis step with a non-uniform learned proposal
+    leaves the distribution exact (chi-square against the quadrature CDF).  A
+    wrong reflection, a missing Jacobian or a proposal that is not symmetric in
+    the flow coordinate would bias it (accepting with p(a0')/p(x_old) alone,
+    i.e. without the proposal densities, gives p ~ 0 here)."""
+    params = identity_params()  # a non-uniform spline: perturbed output biases
+    params[2624:] += np.random.default_rng(3).normal(0, 0.6, 47).astype(np.float32)
+    table = orc.nn_table(params)
+    V = np.array([1.2, 0.3, -0.4, 0.2])
+    beta = 1.0
+    alpha = beta * np.linalg.norm(V)
+    n = 100_000
+    x = 1.0 - orc.sample_delta(np.full(n, alpha), 77, np.arange(n), 0, 0)[0]
+    xn, acc = _one_step(orc, table, V, beta, x, width, 21)
+    assert 0.2 < acc < 1.0
+    assert np.mean(np.abs(xn - x) > 1e-9) > 0.2  # the step moves most links
+    chi2, dof, p = stats.chi2_equiprobable(xn, alpha, nbins=40)
+    assert p > 1e-4, (chi2, dof)
+
+
+def test_or_identity_spline_reflects_a0_and_acceptance_matches_quadrature(orc):
+    """With the identity spline (u = a0) and no noise the proposal is a0' = -a0,
+    accepted with min(1, p(-x)/p(x)) = min(1, exp(-2 alpha x)); from exact
+    draws the acceptance is E_p[min(1, exp(-2 alpha x))] by quadrature."""
+    table = orc.nn_table(identity_params())
+    V = np.array([0.9, 0.3, -0.2, 0.1])
+    beta = 1.5
+    alpha = beta * np.linalg.norm(V)
+    n = 40_000
+    x = 1.0 - orc.sample_delta(np.full(n, alpha), 5, np.arange(n), 0, 0)[0]
+    xn, acc = _one_step(orc, table, V, beta, x, 0.0, 6)
+    moved = np.abs(xn - x) > 1e-9
+    np.testing.assert_allclose(xn[moved], -x[moved], atol=2e-7)  # FP32 table knots
+    grid = np.linspace(-1, 1, 20001)
+    A = np.trapezoid(stats.a0_pdf(grid, alpha) * np.minimum(1.0, np.exp(-2 * alpha * grid)), grid)
+    assert acc == pytest.approx(A, abs=0.01)
+
+
+def test_or_reflection_is_an_involution(orc):
+    """Without noise the proposal map a0 -> g^{-1}(-g(a0)) applied twice
+    returns the starting a0 (accepted steps of the same staple)."""
+    params = identity_params()
+    params[2624:] += np.random.default_rng(13).normal(0, 0.6, 47).astype(np.float32)
+    table = orc.nn_table(params)
+    V = np.array([1.2, 0.3, -0.4, 0.2])
+    beta = 0.6
+    Ut = V / np.linalg.norm(V)
+    x0 = np.random.default_rng(14).uniform(-0.9, 0.99, 300)
+    U0 = _links_with_a0(x0, Ut, 15)
+    checked = 0
+    for i in range(len(x0)):
+        U1, _, a1 = orc.learned_link(V, U0[i], table, beta, 3, i, 0, 0, or_width=0.0)
+        U2, _, a2 = orc.learned_link(V, U1, table, beta, 3, i, 1, 0, or_width=0.0)
+        if a1 == 1 and a2 == 1:
+            x1 = orc.qmul(U1, Ut)[0][0]
+            x2 = orc.qmul(U2, Ut)[0][0]
+            assert abs(x1 - x0[i]) > 1e-6
+            assert x2 == pytest.approx(x0[i], abs=1e-9)
+            checked += 1
+    assert checked > 60
