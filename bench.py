@@ -124,6 +124,7 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
             b.set_proposal(proposal)
             b.set_overrelax(width)
             tuned_us = b.autotune(None, mode)
+            launch = b.launch()
             b.sweep(therm, mode)
             b.accept_stats(reset=True)
             h = torch.zeros((sweeps, n, 3), dtype=torch.float64, device=dev)
@@ -138,7 +139,7 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
             taus = np.array([tau_int(P[:, r]) for r in range(n)])
             sps = sweeps / dt
             out[name] = {"link_updates_per_s": links * sps, "sweeps_per_s": sps,
-                         "overrelax_width": None if width < 0 else width,
+                         "overrelax_width": None if width < 0 else width, "launch": launch,
                          "tuned_us_per_sweep": tuned_us,
                          "tau_int_plaquette_mean": float(taus.mean()),
                          "effective_sweeps_per_s": float(np.mean(sps / (2 * taus))),
@@ -161,9 +162,11 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
 def run_batch(su2, torch, dev, dims, betas, starts, seed, therm, sweeps, meas, reunit,
               chunk=50):
     """Autotuned batch: `therm` sweeps, then `sweeps` measured sweeps replayed as
-    graph-captured chunks; returns (seconds of the measured part, history)."""
+    graph-captured chunks; returns (seconds of the measured part, history, the
+    autotuned launch)."""
     b = su2.Batch(dims, betas, starts, seed=seed, device=dev)
     b.autotune(None, su2.SU2_KP)
+    launch = b.launch()
     b.sweep_measure(therm, reunit_every=reunit, meas=meas)
     h = torch.zeros((sweeps, len(dims), 3), dtype=torch.float64, device=dev)
     b.capture(chunk, su2.SU2_KP, reunit_every=reunit, meas=meas, hist=h)
@@ -173,7 +176,7 @@ def run_batch(su2, torch, dev, dims, betas, starts, seed, therm, sweeps, meas, r
     b.synchronize()
     dt = time.perf_counter() - t0
     b.close()
-    return dt, h.cpu().numpy()
+    return dt, h.cpu().numpy(), launch
 
 
 def step_bytes(volumes, polyakov, reunit):
@@ -231,7 +234,7 @@ def other_configs(su2, torch, dev, with_cpu):
     for L in (16, 24):
         d = [[L] * 4] * (2 * len(betas))
         starts = [0] * len(betas) + [1] * len(betas)
-        dt, h = run_batch(su2, torch, dev, d, np.concatenate([betas, betas]), starts, 1000,
+        dt, h, launch = run_batch(su2, torch, dev, d, np.concatenate([betas, betas]), starts, 1000,
                              500, 1000, PL, 10)
         vols = [L ** 4] * len(d)
         ups = 4 * sum(vols) * 1000 / dt
@@ -242,7 +245,7 @@ def other_configs(su2, torch, dev, with_cpu):
                                 "500 + 1000 sweeps, reunitarise every 10, plaquette every sweep; "
                                 "one batch, graph-captured chunks of 50 sweeps",
                     "link_updates_per_s": ups, "algorithmic_gbs": gbs,
-                    "hbm_frac": gbs / HBM_PEAK_GBS,
+                    "hbm_frac": gbs / HBM_PEAK_GBS, "launch": launch,
                     "mean_plaquette_by_beta": [round(float(0.5 * (P[i] + P[i + len(betas)])), 6)
                                                for i in range(len(betas))]}
         if with_cpu:
@@ -251,7 +254,7 @@ def other_configs(su2, torch, dev, with_cpu):
     betas = np.round(np.arange(2.0, 2.6001, 0.05), 2)
     nts = (4, 6, 8)
     d = [[32, 32, 32, nt] for nt in nts for _ in betas]
-    dt, h = run_batch(su2, torch, dev, d, np.concatenate([betas] * 3), 0, 4000, 0, 5000,
+    dt, h, launch = run_batch(su2, torch, dev, d, np.concatenate([betas] * 3), 0, 4000, 0, 5000,
                          PL | su2.SU2_MEAS_POLY, 10)
     vols = [32 ** 3 * x[3] for x in d]
     ups = 4 * sum(vols) * 5000 / dt
@@ -262,6 +265,7 @@ def other_configs(su2, torch, dev, with_cpu):
                     "cold start, 5000 sweeps, plaquette and Polyakov loop every sweep, "
                     "reunitarise every 10; one batch, graph-captured chunks of 50 sweeps",
         "link_updates_per_s": ups, "algorithmic_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+        "launch": launch,
         "mean_abs_polyakov_by_nt": {str(nt): [round(float(x), 5) for x in
                                               absL[k * len(betas):(k + 1) * len(betas)]]
                                     for k, nt in enumerate(nts)}}
@@ -317,6 +321,9 @@ def counters_run(su2, torch, dev, lat, name):
         if net is not None:
             b.set_proposal(net)
         b.autotune(None, mode)
+        lc = b.launch()
+        if lc["flags"] & 8:  # the work queue won: read the pass kernel in its per-pass launch
+            b.set_launch(256, 1 | 4, 8, 8, 0)
         b.sweep_measure(20, mode, reunit_every=10, meas=meas)
         b.sweep_measure(8, mode, reunit_every=0, meas=meas)
         b.synchronize()
@@ -327,17 +334,17 @@ def counters_run(su2, torch, dev, lat, name):
     return {"pass_launches": 64, "updates_per_launch": sum(int(np.prod(d)) for d in dims) // 2}
 
 
-def cpu_baseline(sample_sweeps=1):
+def cpu_baseline(sample_sweeps=5):
     from oracle import su2_oracle as orc
     threads = orc.max_threads()
     V = int(np.prod(DIMS))
     rates = {}
-    for nt in (threads, 1):
+    for nt, ns in ((threads, sample_sweeps), (1, 1)):
         U = orc.init(DIMS, 1, SEED)
         t0 = time.perf_counter()
-        orc.sweeps(DIMS, U, sample_sweeps, 0, BETA, SEED, nthreads=nt, measure=True)
+        orc.sweeps(DIMS, U, ns, 0, BETA, SEED, nthreads=nt, measure=True)
         dt = time.perf_counter() - t0
-        rates[nt] = (4 * V * sample_sweeps / dt, dt)
+        rates[nt] = (4 * V * ns / dt, dt)
     return {"value": rates[threads][0], "unit": "link updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{sample_sweeps} FP64 sweep(s) + plaquette + Polyakov of the 48^4 "
