@@ -43,7 +43,7 @@ SEED = 3
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("su2_device.h", "su2_kernels.hip"):
+    for f in ("su2_device.h", "su2_kcommon.h", "su2_internal.h", "su2_kernels.hip"):
         with open(os.path.join(ROOT, "paper_1010_1486_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -334,6 +334,52 @@ def counters_run(su2, torch, dev, lat, name):
     return {"pass_launches": 64, "updates_per_launch": sum(int(np.prod(d)) for d in dims) // 2}
 
 
+def fp64_run(su2, torch, dev, steps=100, launches=80):
+    """The 48^4 headline workload with FP64 links and staples (the paper's
+    next step): autotuned launch, `steps` sweeps with the fused plaquette and
+    reunitarisation every 10, the pass kernel's average launch over
+    `launches` launches (256 algorithmic bytes per update: the FP32 pass's
+    seven reads and one write of 32-byte links), and the FP32-vs-FP64
+    difference of the plaquette and Polyakov loop after one sweep from the
+    same FP64 hot start."""
+    V = int(np.prod(DIMS))
+    out = {"workload": "48^4, beta=6.0, hot start (Philox seed 3), FP64 links and staples; "
+                       "step = 1 sweep + fused plaquette, reunitarise every 10"}
+    with su2.Lattice64(DIMS, BETA, SEED, su2.SU2_HOT, device=dev) as lat:
+        start = lat.get_links()
+        with su2.Lattice(DIMS, BETA, SEED, su2.SU2_COLD, device=dev) as l32:
+            l32.set_links(start.astype(np.float32))
+            l32.heatbath_sweep(1)
+            lat.heatbath_sweep(1)
+            out["fp32_minus_fp64_after_one_sweep"] = {
+                "plaquette": l32.plaquette() - lat.plaquette(),
+                "polyakov_signed": l32.polyakov()[0] - lat.polyakov()[0]}
+        del start
+        out["autotuned_us_per_sweep"] = lat.autotune(None, su2.SU2_KP)
+        out["launch"] = lat.launch()
+        hist = torch.zeros((steps, 3), dtype=torch.float64, device=dev)
+        lat.sweep_measure(10, reunit_every=10, meas=su2.SU2_MEAS_PLAQ, hist=hist)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.sweep_measure(steps, reunit_every=10, meas=su2.SU2_MEAS_PLAQ, hist=hist)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stream = lat.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(launches):
+            lat.test_pass((i // 2) % 4, i % 2)
+        e1.record(stream)
+        e1.synchronize()
+        pass_ms = e0.elapsed_time(e1) / launches
+    gbs = 256 * (V // 2) / (pass_ms * 1e-3) / 1e9
+    out.update({"link_updates_per_s": 4 * V * steps / dt, "ms_per_sweep": 1e3 * dt / steps,
+                "pass_avg_launch_us": pass_ms * 1e3, "bytes_per_update": 256,
+                "pass_algorithmic_gbs": gbs, "pass_hbm_frac": gbs / HBM_PEAK_GBS,
+                "mean_plaquette": float(hist.cpu().numpy()[:, 0].mean())})
+    return out
+
+
 def cpu_baseline(sample_sweeps=5):
     from oracle import su2_oracle as orc
     threads = orc.max_threads()
@@ -363,6 +409,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the batched plain-vs-learned comparison")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-link workload")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 4^4, beta-scan and Polyakov workloads")
     ap.add_argument("--counters", nargs="?", const="headline", default=None,
@@ -466,6 +513,9 @@ def main():
         with torch.cuda.stream(torch.cuda.Stream(device=dev)):  # graphs need a non-null stream
             out["other_configs"] = other_configs(su2, torch, dev, not args.no_cpu_baseline)
         torch.cuda.synchronize()
+    if not args.no_fp64:
+        print("[bench] FP64 links", file=sys.stderr, flush=True)
+        out["fp64"] = fp64_run(su2, torch, dev)
     if not args.no_learned:
         print("[bench] batched plain vs learned proposal", file=sys.stderr, flush=True)
         out["learned_vs_plain"] = learned_vs_plain(su2, torch, dev)

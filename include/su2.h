@@ -84,6 +84,29 @@ int su2_init_ext(su2_ctx **out, const int32_t dims[4], double beta, uint64_t see
                  void *links_dev, size_t links_bytes, void *scratch_dev, size_t scratch_bytes,
                  void *hip_stream);
 
+/* As su2_init with FP64 links and staples (library-owned memory, 128 V bytes;
+ * work runs on hip_stream, NULL being the null stream):
+ * the double-precision variant the paper names as its next step
+ * (Conclusions).  Every step of the update is FP64 -- staple sum, k, the a0
+ * sampler (same Philox trials as the FP32 path), direction, product, hot start
+ * (Box-Muller in FP64) and reunitarisation -- so at equal seeds the two
+ * precisions differ only by FP32 rounding and by the rare decisions that
+ * rounding flips.  Supported on such a context: the heat-bath sweeps
+ * (SU2_KP; SU2_LEARNED gives SU2_ESTATE), su2_sweep_measure, capture/replay,
+ * su2_reunitarize, su2_plaquette, su2_polyakov, get/set links (float or
+ * double host arrays), set_sweep/beta/replica, set_launch/autotune (block,
+ * remap, pass order and tiles; the whole-sweep and work-queue launches are
+ * FP32 only), su2_test_pass.  Device layout: 8 arrays (mu * 2 + parity) of
+ * V/2 links of 4 doubles (a0..a3). */
+int su2_init_f64(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
+                 void *hip_stream);
+/* *out = 1 for an FP64 context, else 0. */
+int su2_is_f64(su2_ctx *ctx, int *out);
+/* Links in the canonical host layout as FP64 (host double[V][4][4]); on an
+ * FP32 context the values are widened / rounded to FP32. */
+int su2_get_links_f64(su2_ctx *ctx, double *host);
+int su2_set_links_f64(su2_ctx *ctx, const double *host);
+
 /* Synchronise the stream and release the context (and library-owned memory). */
 int su2_destroy(su2_ctx *ctx);
 

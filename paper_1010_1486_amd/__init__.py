@@ -2,4 +2,4 @@
 on GPU's").  The compute path is libsu2.so (HIP kernels for gfx950 behind the
 C ABI of include/su2.h); this package is its Python binding."""
 from .su2 import *  # noqa: F401,F403
-from .su2 import NN, Batch, Lattice, SU2Error, lib, header_functions  # noqa: F401
+from .su2 import NN, Batch, Lattice, Lattice64, SU2Error, lib, header_functions  # noqa: F401

@@ -56,6 +56,7 @@ struct Rep {
     unsigned long long *acc;   // this replica's kNumAcc x kBuckets accumulators
     double *results;           // 8 FP64 result slots
     float beta;
+    double beta_d;             // beta for the FP64 path
     uint32_t replica;          // Philox replica id
     uint32_t first_block;      // first pass workgroup of this replica (multiple of 8)
     uint32_t nblocks;          // pass workgroups of this replica
@@ -220,6 +221,16 @@ hipError_t launch_queue_sweeps(const Ens &e, const QueuePlan &plan, const uint32
 // Bit mask of the XCC ids that run workgroups of a large launch (one-time
 // probe of the current device; synchronous).
 hipError_t probe_xcc_mask(uint32_t *mask);
+// FP64 links (single lattice; links point to 8 arrays of V/2 x 4 doubles):
+// start (hot != 0: Haar from Philox tag 2), one heat-bath pass (measure as
+// launch_pass), plaquette / Polyakov sums into the accumulators,
+// reunitarisation.
+hipError_t launch_init64(const Ens &e, int hot, uint64_t seed, hipStream_t stream);
+hipError_t launch_pass64(const Ens &e, int mu, int par, uint64_t seed, bool measure,
+                         const LaunchCfg &cfg, hipStream_t stream);
+hipError_t launch_plaquette64(const Ens &e, hipStream_t stream);
+hipError_t launch_polyakov64(const Ens &e, hipStream_t stream);
+hipError_t launch_reunitarize64(const Ens &e, hipStream_t stream);
 // Workgroups of `block` threads of the queue kernel the device holds at once.
 uint32_t queue_resident_grid(int block, bool learned);
 // which: 1 set sweep, 2 set meas_idx, 4 zero all accumulators, 8 zero counts,

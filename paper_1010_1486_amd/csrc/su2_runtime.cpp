@@ -240,6 +240,7 @@ public:
     uint64_t seed = 0;
     uint32_t sweep = 0;  // host mirror of the (common) sweep counter
     float orw = -1.0f;   // learned proposal: over-relaxation noise width (< 0: off)
+    bool f64 = false;    // FP64 links (single lattice): the su2_f64.hip kernels
     LaunchCfg cfg;
     uint32_t lg_tz = 3, lg_tt = 3;
     const float *table = nullptr;
@@ -330,6 +331,7 @@ public:
             h[r].acc = acc(r);
             h[r].results = results(r);
             h[r].beta = (float)beta[r];
+            h[r].beta_d = beta[r];
             h[r].replica = replica[r];
             h[r].first_block = first_block[r];
             h[r].nblocks = nblocks[r];
@@ -388,7 +390,8 @@ public:
         HIP_TRY(hipMalloc(&d, n * sizeof(int)));
         hipError_t e = hipMemcpy(d, starts.data(), n * sizeof(int), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = launch_set_counter(ens(), 0, 0, 7 | 16, stream, d_qs());
-        if (e == hipSuccess) e = launch_init(ens(), d, seed, stream);
+        if (e == hipSuccess)
+            e = f64 ? launch_init64(ens(), starts[0], seed, stream) : launch_init(ens(), d, seed, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         (void)hipFree(d);
         if (e != hipSuccess) return fail(SU2_EHIP, std::string("init: ") + hipGetErrorString(e));
@@ -397,7 +400,10 @@ public:
     }
 
     // Whole sweeps in one launch (small lattices only).
-    bool small_path() const { return !cfg.queue && cfg.small && max_vh <= kSmallMaxVh; }
+    bool small_path() const
+    {
+        return !f64 && !cfg.queue && cfg.small && max_vh <= kSmallMaxVh;
+    }
 
     // Workgroups of the persistent queue launch: the grid cap if set, else
     // as many as the device holds at once.
@@ -460,6 +466,8 @@ public:
     {
         *rc = SU2_OK;
         if (mode != SU2_KP && mode != SU2_LEARNED) *rc = fail(SU2_EINVAL, "unknown mode");
+        else if (mode == SU2_LEARNED && f64)
+            *rc = fail(SU2_ESTATE, "the learned proposal runs on FP32 links only");
         else if (mode == SU2_LEARNED && !table)
             *rc = fail(SU2_ESTATE, "no learned proposal loaded (su2_set_proposal)");
         return mode == SU2_LEARNED ? table : nullptr;
@@ -475,7 +483,7 @@ public:
         const float *tab = mode_table(mode, &rc);
         if (rc) return rc;
         if (hist && reset_rows) HIP_TRY(launch_set_counter(ens(), 0, 0, 2, stream));
-        if (cfg.queue) return enqueue_queue(ns, tab, reunit_every, meas, hist);
+        if (cfg.queue && !f64) return enqueue_queue(ns, tab, reunit_every, meas, hist);
         if (small_path()) {
             const int flags = (hist && (meas & SU2_MEAS_PLAQ) ? 1 : 0) |
                               (hist && (meas & SU2_MEAS_POLY) ? 2 : 0) | (hist ? 4 : 0);
@@ -490,12 +498,14 @@ public:
             const bool fused = want_p && !reunit;
             for (int mu = 0; mu < 4; ++mu)
                 for (int par = 0; par < 2; ++par)
-                    HIP_TRY(launch_pass(ens(), mu, par, seed, fused && par == 1 && mu >= 1, tab,
-                                        cfg, stream));
-            if (reunit) HIP_TRY(launch_reunitarize(ens(), stream));
-            if (want_p && !fused) HIP_TRY(launch_plaquette(ens(), stream));
+                    HIP_TRY(f64 ? launch_pass64(ens(), mu, par, seed, fused && par == 1 && mu >= 1,
+                                                cfg, stream)
+                                : launch_pass(ens(), mu, par, seed, fused && par == 1 && mu >= 1,
+                                              tab, cfg, stream));
+            if (reunit) HIP_TRY(reunitarize_launch());
+            if (want_p && !fused) HIP_TRY(plaquette_launch());
             const bool want_l = hist && (meas & SU2_MEAS_POLY);
-            if (want_l) HIP_TRY(launch_polyakov(ens(), stream));
+            if (want_l) HIP_TRY(polyakov_launch());
             const int flags = (want_p ? 1 : 0) | (want_l ? 2 : 0) | (hist ? 4 : 0);
             HIP_TRY(launch_sweep_end(ens(), flags, hist, stream));
         }
@@ -555,11 +565,25 @@ public:
         return SU2_OK;
     }
 
+    // Measurement and reunitarisation kernels of the ensemble's precision.
+    hipError_t plaquette_launch()
+    {
+        return f64 ? launch_plaquette64(ens(), stream) : launch_plaquette(ens(), stream);
+    }
+    hipError_t polyakov_launch()
+    {
+        return f64 ? launch_polyakov64(ens(), stream) : launch_polyakov(ens(), stream);
+    }
+    hipError_t reunitarize_launch()
+    {
+        return f64 ? launch_reunitarize64(ens(), stream) : launch_reunitarize(ens(), stream);
+    }
+
     // flags 1 plaquette, 2 Polyakov; results into host arrays (n entries).
     int observe(int flags, double *plaq, double *poly_s, double *poly_a)
     {
-        if (flags & 1) HIP_TRY(launch_plaquette(ens(), stream));
-        if (flags & 2) HIP_TRY(launch_polyakov(ens(), stream));
+        if (flags & 1) HIP_TRY(plaquette_launch());
+        if (flags & 2) HIP_TRY(polyakov_launch());
         HIP_TRY(launch_take(ens(), flags, stream));
         std::vector<double> v(3 * (size_t)n);
         for (int r = 0; r < n; ++r)
@@ -590,15 +614,13 @@ public:
         return SU2_OK;
     }
 
-    int get_links(int r, float *host)
+    // Host layout [t][z][y][x][mu][c] in H (float or double) <-> the device
+    // planes in the ensemble's precision.
+    template <typename D, typename H>
+    void gather(int r, const std::vector<D> &planes, H *host) const
     {
         const int32_t *d = dims[r].data();
         const int64_t V = volume_of(d), vh = V / 2;
-        std::vector<float> planes((size_t)V * 16);
-        HIP_TRY(hipMemcpyAsync(planes.data(), links[r], planes.size() * 4, hipMemcpyDeviceToHost,
-                               stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        if (int rc = check_queue()) return rc;
         for (int64_t s = 0; s < V; ++s) {
             int64_t q = s;
             const int x = (int)(q % d[0]);
@@ -610,33 +632,63 @@ public:
             const int par = (x + y + z + t) & 1;
             for (int mu = 0; mu < 4; ++mu)
                 for (int k = 0; k < 4; ++k)
-                    host[(s * 4 + mu) * 4 + k] = planes[dev_index(mu, par, k, s >> 1, vh)];
+                    host[(s * 4 + mu) * 4 + k] = (H)planes[dev_index(mu, par, k, s >> 1, vh)];
         }
+    }
+
+    template <typename D, typename H>
+    void scatter(int r, const H *host, std::vector<D> &planes) const
+    {
+        const int32_t *d = dims[r].data();
+        const int64_t V = volume_of(d), vh = V / 2;
+        for (int64_t s = 0; s < V; ++s) {
+            int64_t q = s;
+            const int x = (int)(q % d[0]);
+            q /= d[0];
+            const int y = (int)(q % d[1]);
+            q /= d[1];
+            const int z = (int)(q % d[2]);
+            const int t = (int)(q / d[2]);
+            const int par = (x + y + z + t) & 1;
+            for (int mu = 0; mu < 4; ++mu)
+                for (int k = 0; k < 4; ++k)
+                    planes[dev_index(mu, par, k, s >> 1, vh)] = (D)host[(s * 4 + mu) * 4 + k];
+        }
+    }
+
+    template <typename D, typename H>
+    int get_links_as(int r, H *host)
+    {
+        std::vector<D> planes((size_t)volume_of(dims[r].data()) * 16);
+        HIP_TRY(hipMemcpyAsync(planes.data(), links[r], planes.size() * sizeof(D),
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (int rc = check_queue()) return rc;
+        gather(r, planes, host);
         return SU2_OK;
     }
 
-    int set_links(int r, const float *host)
+    template <typename D, typename H>
+    int set_links_as(int r, const H *host)
     {
-        const int32_t *d = dims[r].data();
-        const int64_t V = volume_of(d), vh = V / 2;
-        std::vector<float> planes((size_t)V * 16);
-        for (int64_t s = 0; s < V; ++s) {
-            int64_t q = s;
-            const int x = (int)(q % d[0]);
-            q /= d[0];
-            const int y = (int)(q % d[1]);
-            q /= d[1];
-            const int z = (int)(q % d[2]);
-            const int t = (int)(q / d[2]);
-            const int par = (x + y + z + t) & 1;
-            for (int mu = 0; mu < 4; ++mu)
-                for (int k = 0; k < 4; ++k)
-                    planes[dev_index(mu, par, k, s >> 1, vh)] = host[(s * 4 + mu) * 4 + k];
-        }
-        HIP_TRY(hipMemcpyAsync(links[r], planes.data(), planes.size() * 4, hipMemcpyHostToDevice,
-                               stream));
+        std::vector<D> planes((size_t)volume_of(dims[r].data()) * 16);
+        scatter(r, host, planes);
+        HIP_TRY(hipMemcpyAsync(links[r], planes.data(), planes.size() * sizeof(D),
+                               hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         return SU2_OK;
+    }
+
+    template <typename H>
+    int get_links(int r, H *host)
+    {
+        return f64 ? get_links_as<double>(r, host) : get_links_as<float>(r, host);
+    }
+
+    template <typename H>
+    int set_links(int r, const H *host)
+    {
+        return f64 ? set_links_as<double>(r, host) : set_links_as<float>(r, host);
     }
 
     int set_sweep(uint32_t s)
@@ -793,7 +845,7 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
         int block, flags, tz, tt, grid;
     };
     std::vector<Cand> cands;
-    const bool small_ok = max_vh <= kSmallMaxVh;
+    const bool small_ok = !f64 && max_vh <= kSmallMaxVh;
     if (small_ok) cands.push_back({256, 1, 8, 8, 0});
     const int no_small = small_ok ? 4 : 0;
     for (int b : {256, 128})
@@ -802,8 +854,9 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
                 for (int gc : {0, 2048, 4096}) cands.push_back({b, fl | no_small, t[0], t[1], gc});
     // the persistent work queue (one item per ticket is always slower: the
     // per-run synchronisation dominates)
-    for (int b : {256, 128})
-        for (int gr : {1, 2}) cands.push_back({b, 1 | 8 | (gr << 4), 8, 8, 0});
+    if (!f64)
+        for (int b : {256, 128})
+            for (int gr : {1, 2}) cands.push_back({b, 1 | 8 | (gr << 4), 8, 8, 0});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -904,7 +957,7 @@ size_t su2_scratch_bytes(const int32_t dims[4])
 
 static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed,
                        int start, void *links_dev, size_t links_bytes, void *scratch_dev,
-                       size_t scratch_bytes, void *stream, bool ext)
+                       size_t scratch_bytes, void *stream, bool ext, bool f64 = false)
 {
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     *out = nullptr;
@@ -912,7 +965,7 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
     if (rc) return rc;
     if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
     if (start != SU2_COLD && start != SU2_HOT) return fail(SU2_EINVAL, "start must be COLD or HOT");
-    const size_t need_l = su2_links_bytes(dims), need_s = su2_scratch_bytes(dims);
+    const size_t need_l = su2_links_bytes(dims) * (f64 ? 2 : 1), need_s = su2_scratch_bytes(dims);
     if (ext) {
         if (!links_dev || !scratch_dev) return fail(SU2_EINVAL, "device buffer is NULL");
         if (links_bytes < need_l || scratch_bytes < need_s)
@@ -924,6 +977,7 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
     if (!c) return fail(SU2_ENOMEM, "host allocation failed");
     Ensemble &E = c->E;
     E.n = 1;
+    E.f64 = f64;
     E.dims = {{dims[0], dims[1], dims[2], dims[3]}};
     E.beta = {beta};
     E.replica = {0u};
@@ -936,7 +990,8 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
         void *l = nullptr, *s = nullptr;
         hipError_t e = hipMalloc(&l, need_l);
         if (e == hipSuccess) e = hipMalloc(&s, need_s);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking);
+        if (e == hipSuccess && f64) E.stream = static_cast<hipStream_t>(stream);
+        else if (e == hipSuccess) e = hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
             if (l) (void)hipFree(l);
             if (s) (void)hipFree(s);
@@ -946,7 +1001,8 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
         }
         E.pool = static_cast<float *>(l);
         E.scratch = static_cast<unsigned char *>(s);
-        E.own_pool = E.own_scratch = E.own_stream = true;
+        E.own_pool = E.own_scratch = true;
+        E.own_stream = !f64;
     }
     E.links = {E.pool};
     E.bmap_off = E.qmap_off = E.rep_off = Ensemble::descr_bytes(1);
@@ -962,6 +1018,38 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
 int su2_init(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start)
 {
     return init_common(out, dims, beta, seed, start, nullptr, 0, nullptr, 0, nullptr, false);
+}
+
+int su2_init_f64(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
+                 void *hip_stream)
+{
+    return init_common(out, dims, beta, seed, start, nullptr, 0, nullptr, 0, hip_stream, false,
+                       true);
+}
+
+int su2_is_f64(su2_ctx *c, int *out)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    *out = c->E.f64 ? 1 : 0;
+    return SU2_OK;
+}
+
+int su2_get_links_f64(su2_ctx *c, double *host)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!host) return fail(SU2_EINVAL, "host is NULL");
+    return c->E.get_links(0, host);
+}
+
+int su2_set_links_f64(su2_ctx *c, const double *host)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!host) return fail(SU2_EINVAL, "host is NULL");
+    return c->E.set_links(0, host);
 }
 
 int su2_init_ext(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
@@ -1021,7 +1109,7 @@ int su2_reunitarize(su2_ctx *c)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIP_TRY(launch_reunitarize(c->E.ens(), c->E.stream));
+    HIP_TRY(c->E.reunitarize_launch());
     return SU2_OK;
 }
 
@@ -1492,7 +1580,9 @@ int su2_test_pass(su2_ctx *c, int mu, int parity, int mode)
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1) return fail(SU2_EINVAL, "bad mu/parity");
     const float *tab = c->E.mode_table(mode, &rc);
     if (rc) return rc;
-    HIP_TRY(launch_pass(c->E.ens(), mu, parity, c->E.seed, false, tab, c->E.cfg, c->E.stream));
+    HIP_TRY(c->E.f64 ? launch_pass64(c->E.ens(), mu, parity, c->E.seed, false, c->E.cfg, c->E.stream)
+                     : launch_pass(c->E.ens(), mu, parity, c->E.seed, false, tab, c->E.cfg,
+                                   c->E.stream));
     return SU2_OK;
 }
 
@@ -1502,6 +1592,7 @@ int su2_test_stream_pass(su2_ctx *c, int mu, int parity, void *out_dev)
     if (rc) return rc;
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1 || !out_dev)
         return fail(SU2_EINVAL, "bad mu/parity or NULL output");
+    if (c->E.f64) return fail(SU2_ESTATE, "the streaming floor kernel covers FP32 links");
     HIP_TRY(launch_test_stream(c->E.ens(), mu, parity, static_cast<float *>(out_dev), c->E.stream));
     return SU2_OK;
 }
@@ -1535,6 +1626,7 @@ int su2_test_gauge_transform(su2_ctx *c, uint64_t seed)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
+    if (c->E.f64) return fail(SU2_ESTATE, "the gauge transformation covers FP32 links");
     void *G = nullptr;
     HIP_TRY(hipMalloc(&G, (size_t)volume_of(c->E.dims[0].data()) * 16));
     hipError_t e = launch_gauge(c->E.ens(), (float *)G, seed, c->E.stream);

@@ -43,6 +43,10 @@ _SIGS = {
     "su2_scratch_bytes": (_sz, [_vp]),
     "su2_init": (_int, [_vp, _vp, _d, _u64, _int]),
     "su2_init_ext": (_int, [_vp, _vp, _d, _u64, _int, _vp, _sz, _vp, _sz, _vp]),
+    "su2_init_f64": (_int, [_vp, _vp, _d, _u64, _int, _vp]),
+    "su2_is_f64": (_int, [_vp, _vp]),
+    "su2_get_links_f64": (_int, [_vp, _vp]),
+    "su2_set_links_f64": (_int, [_vp, _vp]),
     "su2_destroy": (_int, [_vp]),
     "su2_heatbath_sweep": (_int, [_vp, _i32, _int]),
     "su2_sweep_measure": (_int, [_vp, _i32, _int, _i32, _int, _vp]),
@@ -593,6 +597,32 @@ class Lattice:
 
     def accept_stats(self, reset=False):
         return su2_get_accept_stats(self.h, reset)
+
+
+class Lattice64(Lattice):
+    """A lattice with FP64 links (library-owned device memory) run on torch's
+    current stream of the device (su2_init_f64).  get_links returns float64."""
+
+    def __init__(self, dims, beta, seed, start=SU2_COLD, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.dims = [int(d) for d in dims]
+        self.volume = int(np.prod(self.dims))
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _vp()
+        _check(lib().su2_init_f64(ctypes.byref(h), _p(_dims(self.dims)), float(beta), int(seed),
+                                  int(start), _vp(self.stream.cuda_stream)))
+        self.h = h
+
+    def get_links(self):
+        out = np.empty((self.volume, 4, 4), dtype=np.float64)
+        _check(lib().su2_get_links_f64(self.h, _p(out)))
+        return out
+
+    def set_links(self, links):
+        a = np.ascontiguousarray(links, dtype=np.float64).reshape(self.volume, 4, 4)
+        _check(lib().su2_set_links_f64(self.h, _p(a)))
 
 
 class Batch:
