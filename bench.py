@@ -380,6 +380,47 @@ def fp64_run(su2, torch, dev, steps=100, launches=80):
     return out
 
 
+def creutz(W, R):
+    """chi(R, R) = -ln[W(R,R) W(R-1,R-1) / (W(R,R-1) W(R-1,R))], W(0, .) = 1."""
+    w = lambda r, t: 1.0 if r == 0 or t == 0 else W[r - 1, t - 1]
+    return -np.log(w(R, R) * w(R - 1, R - 1) / (w(R, R - 1) * w(R - 1, R)))
+
+
+def scale_setting(su2, torch, dev, betas=(2.3, 2.4, 2.5), therm=300, nmeas=60, every=5):
+    """Wilson loops W(R,T), R, T <= 4, on thermalised 16^4 lattices (hot start,
+    seed 1000 + i) measured every `every` sweeps, the Creutz ratios
+    chi(2,2), chi(3,3), chi(4,4) (the string tension sigma a^2 in lattice
+    units: the scale the T/Tc axis of the Polyakov loop needs), and the time
+    of one W(4,4) measurement on the 48^4 headline lattice."""
+    out = {"workload": f"16^4, beta {list(betas)}, hot start, {therm} thermalisation sweeps, "
+                       f"{nmeas} measurements of W(R,T) (R,T <= 4) every {every} sweeps"}
+    rows = []
+    for i, beta in enumerate(betas):
+        with su2.Lattice([16] * 4, beta, 1000 + i, su2.SU2_HOT, device=dev) as lat:
+            lat.sweep_measure(therm, reunit_every=10, meas=su2.SU2_MEAS_PLAQ)
+            W = []
+            for k in range(nmeas):
+                lat.sweep_measure(every, reunit_every=10, meas=su2.SU2_MEAS_PLAQ)
+                W.append(lat.wilson_loops(4, 4))
+        W = np.array(W)
+        mean = W.mean(axis=0)
+        chis = {f"chi_{R}{R}": float(creutz(mean, R)) for R in (2, 3, 4)}
+        # jackknife error of the Creutz ratios
+        jk = np.array([[creutz((W.sum(axis=0) - W[j]) / (len(W) - 1), R) for R in (2, 3, 4)]
+                       for j in range(len(W))])
+        err = np.sqrt((len(W) - 1) * jk.var(axis=0))
+        rows.append({"beta": beta, "W": np.round(mean, 7).tolist(), **chis,
+                     **{f"chi_{R}{R}_err": float(e) for R, e in zip((2, 3, 4), err)}})
+    out["by_beta"] = rows
+    with su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT, device=dev) as lat:
+        lat.wilson_loops(4, 4)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            lat.wilson_loops(4, 4)
+        out["wilson_4x4_48^4_ms"] = 1e3 * (time.perf_counter() - t0) / 5
+    return out
+
+
 def cpu_baseline(sample_sweeps=5):
     from oracle import su2_oracle as orc
     threads = orc.max_threads()
@@ -410,6 +451,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the batched plain-vs-learned comparison")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-link workload")
+    ap.add_argument("--no-wilson", action="store_true", help="skip the Wilson-loop workload")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 4^4, beta-scan and Polyakov workloads")
     ap.add_argument("--counters", nargs="?", const="headline", default=None,
@@ -516,6 +558,9 @@ def main():
     if not args.no_fp64:
         print("[bench] FP64 links", file=sys.stderr, flush=True)
         out["fp64"] = fp64_run(su2, torch, dev)
+    if not args.no_wilson:
+        print("[bench] Wilson loops and Creutz ratios", file=sys.stderr, flush=True)
+        out["scale_setting"] = scale_setting(su2, torch, dev)
     if not args.no_learned:
         print("[bench] batched plain vs learned proposal", file=sys.stderr, flush=True)
         out["learned_vs_plain"] = learned_vs_plain(su2, torch, dev)

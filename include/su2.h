@@ -84,6 +84,17 @@ int su2_init_ext(su2_ctx **out, const int32_t dims[4], double beta, uint64_t see
                  void *links_dev, size_t links_bytes, void *scratch_dev, size_t scratch_bytes,
                  void *hip_stream);
 
+/* Rectangular Wilson loops for scale setting (the T/Tc axis of the Polyakov
+ * loop needs a lattice spacing, which the paper does not give):
+ * out[(R - 1) tmax + (T - 1)] = (1/(12 V)) sum_s sum_{mu != nu}
+ * (1/2) Tr[L_mu(s,R) L_nu(s+R mu,T) L_mu(s+T nu,R)^+ L_nu(s,T)^+], with
+ * L_mu(x, n) = U_mu(x) U_mu(x+mu) ... U_mu(x+(n-1)mu), R = 1..rmax,
+ * T = 1..tmax; W(1,1) is the plaquette.  Per-site values FP32, sums FP64
+ * (deterministic order).  Synchronous; allocates a temporary device buffer.
+ * SU2_EINVAL unless 1 <= rmax, tmax <= 4 and both are below every extent;
+ * SU2_ESTATE on an FP64 context.  out: host double[rmax * tmax]. */
+int su2_wilson_loops(su2_ctx *ctx, int rmax, int tmax, double *out);
+
 /* As su2_init with FP64 links and staples (library-owned memory, 128 V bytes;
  * work runs on hip_stream, NULL being the null stream):
  * the double-precision variant the paper names as its next step

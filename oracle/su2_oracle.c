@@ -452,6 +452,51 @@ double orc_staple_action(const int32_t dims[4], const double *U)
 }
 
 /* L(x) = (1/2) Tr prod_{t=0}^{Nt-1} U_3(x, t), t = 0 leftmost; mean over x. */
+/* Rectangular Wilson loops: W(R, T) = (1/(12 V)) sum_s sum_{mu != nu}
+ * (1/2) Tr[ L_mu(s, R) L_nu(s + R mu, T) L_mu(s + T nu, R)^+ L_nu(s, T)^+ ],
+ * L_mu(s, n) = U_mu(s) U_mu(s + mu) ... U_mu(s + (n - 1) mu), for
+ * R = 1..rmax, T = 1..tmax; out[(R - 1) tmax + (T - 1)].  The loop is built
+ * link by link around the rectangle (no line products are reused). */
+void orc_wilson_loops(const int32_t dims[4], const double *U, int rmax, int tmax, double *out)
+{
+    const int64_t V = orc_volume(dims);
+    for (int i = 0; i < rmax * tmax; ++i) out[i] = 0.0;
+    for (int64_t s = 0; s < V; ++s)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = 0; nu < 4; ++nu) {
+                if (nu == mu) continue;
+                for (int R = 1; R <= rmax; ++R)
+                    for (int T = 1; T <= tmax; ++T) {
+                        double W[4] = {1.0, 0.0, 0.0, 0.0}, t[4], d[4];
+                        int64_t x = s;
+                        for (int i = 0; i < R; ++i) { /* forward along mu */
+                            orc_qmul(W, link(U, x, mu), t);
+                            memcpy(W, t, sizeof(t));
+                            x = orc_shift(dims, x, mu, 1);
+                        }
+                        for (int i = 0; i < T; ++i) { /* forward along nu */
+                            orc_qmul(W, link(U, x, nu), t);
+                            memcpy(W, t, sizeof(t));
+                            x = orc_shift(dims, x, nu, 1);
+                        }
+                        for (int i = 0; i < R; ++i) { /* back along mu */
+                            x = orc_shift(dims, x, mu, -1);
+                            orc_qdag(link(U, x, mu), d);
+                            orc_qmul(W, d, t);
+                            memcpy(W, t, sizeof(t));
+                        }
+                        for (int i = 0; i < T; ++i) { /* back along nu */
+                            x = orc_shift(dims, x, nu, -1);
+                            orc_qdag(link(U, x, nu), d);
+                            orc_qmul(W, d, t);
+                            memcpy(W, t, sizeof(t));
+                        }
+                        out[(R - 1) * tmax + (T - 1)] += W[0];
+                    }
+            }
+    for (int i = 0; i < rmax * tmax; ++i) out[i] /= 12.0 * (double)V;
+}
+
 void orc_polyakov(const int32_t dims[4], const double *U, double *mean_signed, double *abs_mean)
 {
     int64_t Ns3 = (int64_t)dims[0] * dims[1] * dims[2];

@@ -101,6 +101,9 @@ double orc_staple_action(const int32_t dims[4], const double *U);
 void orc_polyakov(const int32_t dims[4], const double *U, double *mean_signed,
                   double *abs_mean);
 void orc_gauge_transform(const int32_t dims[4], double *U, uint64_t seed, uint32_t replica);
+/* Rectangular Wilson loops averaged over sites and the 12 ordered planes,
+ * R = 1..rmax along mu, T = 1..tmax along nu: out[(R-1) tmax + (T-1)]. */
+void orc_wilson_loops(const int32_t dims[4], const double *U, int rmax, int tmax, double *out);
 /* Haar-random SU(2) element from one Philox block (Box-Muller + normalise). */
 void orc_haar_from_block(const uint32_t w[4], double out[4]);
 

@@ -58,6 +58,7 @@ def _load():
         "orc_staple_action": (c_d, [_i32p, _f64p]),
         "orc_polyakov": (None, [_i32p, _f64p, ctypes.POINTER(c_d), ctypes.POINTER(c_d)]),
         "orc_gauge_transform": (None, [_i32p, _f64p, c_u64, c_u32]),
+        "orc_wilson_loops": (None, [_i32p, _f64p, c_int, c_int, _f64p]),
         "orc_haar_from_block": (None, [_u32p, _f64p]),
         "orc_max_threads": (c_int, []),
         "orc_nn_feature": (c_d, [c_d]),
@@ -213,6 +214,13 @@ def polyakov(dims, U):
     s, a = ctypes.c_double(), ctypes.c_double()
     _load().orc_polyakov(_dims(dims), _c(U), ctypes.byref(s), ctypes.byref(a))
     return s.value, a.value
+
+
+def wilson_loops(dims, U, rmax, tmax):
+    """W(R, T), R = 1..rmax, T = 1..tmax, as an (rmax, tmax) array."""
+    out = np.zeros(rmax * tmax)
+    _load().orc_wilson_loops(_dims(dims), _c(U), int(rmax), int(tmax), out)
+    return out.reshape(rmax, tmax)
 
 
 def gauge_transform(dims, U, seed, replica=0):

@@ -231,6 +231,14 @@ hipError_t launch_pass64(const Ens &e, int mu, int par, uint64_t seed, bool meas
 hipError_t launch_plaquette64(const Ens &e, hipStream_t stream);
 hipError_t launch_polyakov64(const Ens &e, hipStream_t stream);
 hipError_t launch_reunitarize64(const Ens &e, hipStream_t stream);
+// Rectangular Wilson loops of a single FP32 lattice, R <= rmax, T <= tmax
+// (<= kWilsonMax): part holds wilson_blocks(e) * kWilsonMax^2 doubles, sums
+// receives kWilsonMax^2 sums over sites and the 12 ordered planes,
+// sums[(R - 1) kWilsonMax + (T - 1)] (divide by 12 V).
+constexpr int kWilsonMax = 4;
+inline uint32_t wilson_blocks(const Ens &e) { return (uint32_t)((2ull * e.max_vh + 255) / 256); }
+hipError_t launch_wilson(const Ens &e, int rmax, int tmax, double *part, double *sums,
+                         hipStream_t stream);
 // Workgroups of `block` threads of the queue kernel the device holds at once.
 uint32_t queue_resident_grid(int block, bool learned);
 // which: 1 set sweep, 2 set meas_idx, 4 zero all accumulators, 8 zero counts,

@@ -560,6 +560,94 @@ __global__ __launch_bounds__(1024) void small_sweeps_kernel(const Rep *__restric
     }
 }
 
+// ---------------------------------------------------------- Wilson loops
+// W(R, T) of the rectangle R along mu, T along nu at site s, for the 12
+// ordered planes: (1/2)Tr[A_R C_T (B_T D_T)^+] = qdot(A_R C_T, B_T D_T) with
+// A_R = L_mu(s, R), C_T = L_nu(s + R mu, T), B_T = L_nu(s, T),
+// D_T = L_mu(s + T nu, R), L_mu(x, n) = U_mu(x) ... U_mu(x + (n - 1) mu).
+// The lines are extended one link at a time (R outer, T inner), so a plane
+// costs R + T + 2RT link loads for all R <= rmax, T <= tmax.  One thread per
+// site (both parities); the per-site sums over the planes are FP32, the sum
+// over a workgroup FP64 into part[block * N * N + (R - 1) N + (T - 1)].
+
+// U_dir at c0 + da * e_a + db * e_b (a != b, 0 <= da, db < extent).
+__device__ __forceinline__ Q link_off(const Rep &R, const int *n, const int *c0, int a, int da,
+                                      int b, int db, int dir)
+{
+    int c[4] = {c0[0], c0[1], c0[2], c0[3]};
+    c[a] += da;
+    if (c[a] >= n[a]) c[a] -= n[a];
+    c[b] += db;
+    if (c[b] >= n[b]) c[b] -= n[b];
+    const Geom &g = R.g;
+    return ldq(R.links, g.vh, dir, (c[0] + c[1] + c[2] + c[3]) & 1, hidx(g, c[0], c[1], c[2], c[3]));
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void wilson_kernel(const Rep *__restrict__ reps, int rmax,
+                                                     int tmax, double *__restrict__ part)
+{
+    const Rep &R = reps[0];
+    const Geom &g = R.g;
+    const int n[4] = {g.nx, g.ny, g.nz, g.nt};
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    float w[N][N];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int t = 0; t < N; ++t) w[r][t] = 0.0f;
+    if (i < 2u * g.vh) {
+        const int par = i >= g.vh ? 1 : 0;
+        int c0[4];
+        decode(g, par ? i - g.vh : i, par, c0[0], c0[1], c0[2], c0[3]);
+        const Q one{1.0f, 0.0f, 0.0f, 0.0f};
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = 0; nu < 4; ++nu) {
+                if (nu == mu) continue;
+                Q B[N], D[N];
+                Q P = one;
+#pragma unroll
+                for (int t = 0; t < N; ++t) {
+                    if (t < tmax) P = qmul(P, link_off(R, n, c0, nu, t, mu, 0, nu));
+                    B[t] = P;
+                    D[t] = one;
+                }
+                Q A = one;
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    if (r >= rmax) continue;
+                    A = qmul(A, link_off(R, n, c0, mu, r, nu, 0, mu));
+                    Q C = one;
+#pragma unroll
+                    for (int t = 0; t < N; ++t) {
+                        if (t >= tmax) continue;
+                        D[t] = qmul(D[t], link_off(R, n, c0, mu, r, nu, t + 1, mu));
+                        C = qmul(C, link_off(R, n, c0, mu, r + 1, nu, t, nu));
+                        w[r][t] += qdot(qmul(A, C), qmul(B[t], D[t]));
+                    }
+                }
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+            const double bs = block_sum((double)w[r][t]);
+            if (threadIdx.x == 0) part[(size_t)blockIdx.x * N * N + r * N + t] = bs;
+        }
+}
+
+// Thread k: the sum of partial k over the workgroups, in workgroup order.
+__global__ void wilson_sum_kernel(const double *__restrict__ part, uint32_t nblocks, int nn,
+                                  double *__restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k >= nn) return;
+    double s = 0.0;
+    for (uint32_t b = 0; b < nblocks; ++b) s += part[(size_t)b * nn + k];
+    out[k] = s;
+}
+
 // ------------------------------------------------------------- work queue
 // Whole sweeps of every replica in one persistent launch (QueuePlan).  A
 // workgroup serves the queue of its XCD (hardware XCC id -> qs->rank) and
@@ -1032,6 +1120,19 @@ uint32_t queue_resident_grid(int block, bool learned)
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess || per_cu <= 0 || cus <= 0) return 1024u;
     return (uint32_t)(per_cu * cus);
+}
+
+hipError_t launch_wilson(const Ens &e, int rmax, int tmax, double *part, double *sums,
+                         hipStream_t stream)
+{
+    const uint32_t nb = nblk(2ull * e.max_vh, 256);
+    hipLaunchKernelGGL(wilson_kernel<kWilsonMax>, dim3(nb), dim3(256), 0, stream, e.reps, rmax,
+                       tmax, part);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(wilson_sum_kernel, dim3(1), dim3(64), 0, stream, part, nb,
+                       kWilsonMax * kWilsonMax, sums);
+    return hipGetLastError();
 }
 
 hipError_t launch_test_stream(const Ens &e, int mu, int par, float *out, hipStream_t stream)

@@ -1128,6 +1128,38 @@ int su2_polyakov(su2_ctx *c, double *out_signed, double *out_abs)
     return c->E.observe(2, nullptr, out_signed, out_abs);
 }
 
+int su2_wilson_loops(su2_ctx *c, int rmax, int tmax, double *out)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    Ensemble &E = c->E;
+    const int32_t *d = E.dims[0].data();
+    const int lmin = std::min(std::min(d[0], d[1]), std::min(d[2], d[3]));
+    if (rmax < 1 || tmax < 1 || rmax > kWilsonMax || tmax > kWilsonMax || rmax >= lmin ||
+        tmax >= lmin)
+        return fail(SU2_EINVAL, "rmax and tmax must be in [1, 4] and below every extent");
+    if (E.f64) return fail(SU2_ESTATE, "Wilson loops are measured on FP32 links");
+    const Ens e = E.ens();
+    void *part = nullptr, *sums = nullptr;
+    HIP_TRY(hipMalloc(&part, (size_t)wilson_blocks(e) * kWilsonMax * kWilsonMax * 8));
+    hipError_t er = hipMalloc(&sums, kWilsonMax * kWilsonMax * 8);
+    double hs[kWilsonMax * kWilsonMax];
+    if (er == hipSuccess)
+        er = launch_wilson(e, rmax, tmax, (double *)part, (double *)sums, E.stream);
+    if (er == hipSuccess)
+        er = hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, E.stream);
+    if (er == hipSuccess) er = hipStreamSynchronize(E.stream);
+    (void)hipFree(part);
+    if (sums) (void)hipFree(sums);
+    if (er != hipSuccess) return fail(SU2_EHIP, std::string("wilson: ") + hipGetErrorString(er));
+    if (int q = E.check_queue()) return q;
+    const double norm = 12.0 * (double)volume_of(d);
+    for (int r = 0; r < rmax; ++r)
+        for (int t = 0; t < tmax; ++t) out[r * tmax + t] = hs[r * kWilsonMax + t] / norm;
+    return SU2_OK;
+}
+
 int su2_get_links(su2_ctx *c, float *host)
 {
     int rc = check_ctx(c);

@@ -44,6 +44,7 @@ _SIGS = {
     "su2_init": (_int, [_vp, _vp, _d, _u64, _int]),
     "su2_init_ext": (_int, [_vp, _vp, _d, _u64, _int, _vp, _sz, _vp, _sz, _vp]),
     "su2_init_f64": (_int, [_vp, _vp, _d, _u64, _int, _vp]),
+    "su2_wilson_loops": (_int, [_vp, _int, _int, _vp]),
     "su2_is_f64": (_int, [_vp, _vp]),
     "su2_get_links_f64": (_int, [_vp, _vp]),
     "su2_set_links_f64": (_int, [_vp, _vp]),
@@ -590,6 +591,12 @@ class Lattice:
 
     def set_proposal(self, nn):
         su2_set_proposal(self.h, None if nn is None else nn.h)
+
+    def wilson_loops(self, rmax, tmax):
+        """W(R, T) for R = 1..rmax, T = 1..tmax as an (rmax, tmax) array."""
+        out = np.zeros(rmax * tmax)
+        _check(lib().su2_wilson_loops(self.h, int(rmax), int(tmax), _p(out)))
+        return out.reshape(rmax, tmax)
 
     def set_overrelax(self, width):
         """width < 0: independence proposal; 0..1: over-relaxed learned proposal."""
