@@ -81,7 +81,7 @@ def tau_int(x, c=6.0):
     return max(tau, 0.5)
 
 
-def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
+def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu=True):
     """64 replicas, L = 8 + 2 (r mod 7) (8^4 .. 20^4), beta uniform in [1.8, 3.0]
     (seeded), hot start; the learned proposal is trained on the GPU on 1e7
     exact-sampler draws (alpha log-uniform in [0.5, 30]).  Each mode: autotuned
@@ -138,7 +138,11 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
             P = h.cpu().numpy()[:, :, 0]
             taus = np.array([tau_int(P[:, r]) for r in range(n)])
             sps = sweeps / dt
+            bpu = 128 if mode == su2.SU2_KP else 144  # the learned update also reads the old link
+            gbs = bpu * links * sps / 1e9
             out[name] = {"link_updates_per_s": links * sps, "sweeps_per_s": sps,
+                         "algorithmic_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                         "bytes_per_update": bpu,
                          "overrelax_width": None if width < 0 else width, "launch": launch,
                          "tuned_us_per_sweep": tuned_us,
                          "tau_int_plaquette_mean": float(taus.mean()),
@@ -153,6 +157,13 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50):
                                          out["plain"]["link_updates_per_s"])
     out["learned_over_plain_effective"] = (out["learned"]["effective_sweeps_per_s"] /
                                            out["plain"]["effective_sweeps_per_s"])
+    if with_cpu:
+        out["oracle"] = {"plain_link_updates_per_s": oracle_rate([20] * 4, 1, 2.3),
+                         "plain_threads": oracle_threads(),
+                         "learned_link_updates_per_s": oracle_learned_rate([12] * 4, 2.3),
+                         "learned_threads": 1,
+                         "sample": "one sweep of a 20^4 replica (heat bath, all threads); one "
+                                   "sweep of learned passes on a 12^4 lattice (one thread)"}
     out["overrelaxed_over_plain_effective"] = (
         out["learned_overrelaxed"]["effective_sweeps_per_s"] /
         out["plain"]["effective_sweeps_per_s"])
@@ -185,6 +196,27 @@ def step_bytes(volumes, polyakov, reunit):
     reunitarisation (amortised); the plaquette is fused into the passes."""
     V = float(sum(volumes))
     return V * (512.0 + (16.0 if polyakov else 0.0) + (128.0 / reunit if reunit else 0.0))
+
+
+def oracle_threads():
+    from oracle import su2_oracle as orc
+    return orc.max_threads()
+
+
+def oracle_learned_rate(dims, beta, seed=5):
+    """The oracle's learned (independence) Metropolis passes on one lattice:
+    link updates/s on one thread (its learned pass is serial)."""
+    from oracle import su2_oracle as orc
+    from oracle import nn_oracle
+    p = np.zeros(nn_oracle.NPARAM, dtype=np.float32)
+    p[2624:] = nn_oracle.identity_raw_bias()
+    table = orc.nn_table(p)
+    U = orc.init(dims, 1, seed)
+    t0 = time.perf_counter()
+    for mu in range(4):
+        for par in range(2):
+            orc.learned_pass(dims, U, table, mu, par, 0, beta, seed)
+    return 4 * int(np.prod(dims)) / (time.perf_counter() - t0)
 
 
 def oracle_rate(dims, sweeps, beta):
@@ -226,9 +258,12 @@ def other_configs(su2, torch, dev, with_cpu):
                   "link_updates_per_s_direct": n / dt_direct,
                   "link_updates_per_s_graph": n / dt_graph,
                   "us_per_sweep_graph": 1e6 * dt_graph / 100,
+                  "algorithmic_gbs": step_bytes([256], False, 0) * 100 / dt_graph / 1e9,
+                  "hbm_frac": step_bytes([256], False, 0) * 100 / dt_graph / 1e9 / HBM_PEAK_GBS,
                   "mean_plaquette": float(h.cpu().numpy()[:, 0].mean())}
     if with_cpu:
         out["4^4"]["oracle_link_updates_per_s"] = oracle_rate(dims, 100, 2.3)
+        out["4^4"]["oracle_threads"] = oracle_threads()
     # beta scan 1.5..3.0 on 16^4 and 24^4, cold + hot, 500 + 1000 sweeps, reunit 10
     betas = np.round(np.arange(1.5, 3.0001, 0.1), 2)
     for L in (16, 24):
@@ -250,6 +285,7 @@ def other_configs(su2, torch, dev, with_cpu):
                                                for i in range(len(betas))]}
         if with_cpu:
             out[key]["oracle_link_updates_per_s"] = oracle_rate([L] * 4, 2, 2.3)
+            out[key]["oracle_threads"] = oracle_threads()
     # 32^3 x Nt, Nt in {4, 6, 8}, beta 2.00..2.60 step 0.05, cold, 5000 sweeps
     betas = np.round(np.arange(2.0, 2.6001, 0.05), 2)
     nts = (4, 6, 8)
@@ -270,6 +306,7 @@ def other_configs(su2, torch, dev, with_cpu):
                                               absL[k * len(betas):(k + 1) * len(betas)]]
                                     for k, nt in enumerate(nts)}}
     if with_cpu:
+        out["polyakov_32^3xNt"]["oracle_threads"] = oracle_threads()
         out["polyakov_32^3xNt"]["oracle_link_updates_per_s"] = oracle_rate([32, 32, 32, 4], 2,
                                                                            2.3)
     return out
@@ -563,7 +600,8 @@ def main():
         out["scale_setting"] = scale_setting(su2, torch, dev)
     if not args.no_learned:
         print("[bench] batched plain vs learned proposal", file=sys.stderr, flush=True)
-        out["learned_vs_plain"] = learned_vs_plain(su2, torch, dev)
+        out["learned_vs_plain"] = learned_vs_plain(su2, torch, dev,
+                                                   with_cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
