@@ -180,7 +180,9 @@ int su2_synchronize(su2_ctx *ctx);
  * by completion counters; each replica is served by one XCD, replicas spread
  * over the XCDs by size; grid_cap = its workgroups, at least one per XCD,
  * 0 = as many as the device holds at once), bits 4-5 = log2 of the items it
- * takes per ticket;
+ * takes per ticket, bit 6 = batches: all pass workgroups of a replica on one
+ * XCD (replicas spread over the XCDs by size, each replica's blocks in
+ * order on its XCD's L2; bit 0 is then unused);
  * the traversal
  * tile of (z, t) planes, tile_z x tile_t (powers of two <= 256, clipped to
  * divisors of Nz and Nt; 0 keeps the current value); grid_cap > 0 runs the

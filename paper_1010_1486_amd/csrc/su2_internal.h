@@ -75,6 +75,7 @@ struct LaunchCfg {
     uint32_t grid_cap = 0;    // > 0: persistent pass grid of at most this many workgroups
     bool small = true;        // whole sweeps in one launch when every V/2 <= kSmallMaxVh
     bool queue = false;       // whole sweeps in one persistent work-queue launch
+    bool affine = false;      // batches: each replica's pass workgroups on one XCD
     int grain = 1;            // work-queue items per ticket
 };
 
@@ -175,6 +176,10 @@ constexpr uint32_t kSmallMaxVh = 2048;
 struct Ens {
     const Rep *reps;          // device array of nrep descriptors
     const uint32_t *bmap;     // pass workgroup -> replica (nullptr when nrep == 1)
+    // XCD-affine pass launch (nullptr: off): workgroup b -> (replica, block of
+    // the replica), replica 0xFFFFFFFF for padding; amap_len workgroups
+    const uint2 *amap;
+    uint32_t amap_len;
     int nrep;
     uint32_t total_blocks;    // pass workgroups over all replicas (padded)
     uint32_t max_vh;          // largest V/2 over the replicas

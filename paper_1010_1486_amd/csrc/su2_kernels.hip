@@ -164,13 +164,15 @@ __device__ __forceinline__ const float *load_table_lds(float4 *stab4, const floa
 // One heat-bath pass over the sites of parity `par` in direction MU, for
 // every replica of the ensemble.  Workgroup ids b in [0, total) are mapped
 // to replicas by bmap (each replica's range starts at a multiple of 8, so
-// b mod 8 is still the XCD); with a capped grid the workgroups loop over b
-// (persistent).  With MEASURE, (1/2)Tr(U'_mu(s) V_nu(s)) summed over nu < mu
+// b mod 8 is still the XCD), or, XCD-affine, to (replica, block) by amap so
+// that all blocks of a replica run on one XCD; with a capped grid (a multiple
+// of 8) the workgroups loop over b (persistent).  With MEASURE, (1/2)Tr(U'_mu(s) V_nu(s)) summed over nu < mu
 // is accumulated: over the odd passes of mu = 1, 2, 3 this is every
 // plaquette of the end-of-sweep configuration exactly once.
 template <int MU, bool MEASURE, bool LEARNED>
 __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
                                                    const uint32_t *__restrict__ bmap,
+                                                   const uint2 *__restrict__ amap,
                                                    uint32_t total, int par, uint32_t k0,
                                                    uint32_t k1, int remap, int reverse,
                                                    const float *__restrict__ table)
@@ -179,11 +181,22 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
     __shared__ float4 stab4[LEARNED ? 1 + kNNRows * kNNRow / 4 : 1];
     const float *ltab = LEARNED ? load_table_lds(stab4, table) : nullptr;
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
-        const Rep &R = reps[bmap ? bmap[b] : 0u];
-        const uint32_t local = b - R.first_block;
+        uint32_t r, local;
+        if (amap) {
+            const uint2 a = amap[b];
+            if (a.x == 0xFFFFFFFFu) continue;  // padding workgroup (uniform)
+            r = a.x;
+            local = a.y;
+        } else {
+            r = bmap ? bmap[b] : 0u;
+            local = b - reps[r].first_block;
+        }
+        const Rep &R = reps[r];
         if (local >= R.nblocks) continue;  // padding workgroup (uniform)
         const Geom &g = R.g;
-        const uint32_t blk = logical_block(local, R.nblocks, remap, reverse);
+        // the blocks of an XCD-affine replica run in order on one XCD
+        const uint32_t blk = amap ? (reverse ? R.nblocks - 1u - local : local)
+                                  : logical_block(local, R.nblocks, remap, reverse);
         const uint32_t gid = blk * blockDim.x + threadIdx.x;
         float meas = 0.0f;
         int acc = -1;
@@ -950,17 +963,18 @@ template <int MU, bool LEARNED>
 void launch_pass_mu(const Ens &e, int par, uint64_t seed, bool measure, const float *table,
                     const LaunchCfg &cfg, hipStream_t stream)
 {
-    unsigned grid = e.total_blocks;
+    const unsigned total = e.amap ? e.amap_len : e.total_blocks;
+    unsigned grid = total;
     if (cfg.grid_cap && cfg.grid_cap < grid) grid = cfg.grid_cap & ~7u;
     if (grid == 0) grid = 8;
     const int rev = cfg.snake ? par : 0;
     if (measure)
         hipLaunchKernelGGL((pass_kernel<MU, true, LEARNED>), dim3(grid), dim3(cfg.pass_block), 0,
-                           stream, e.reps, e.bmap, e.total_blocks, par, lo32(seed), hi32(seed),
+                           stream, e.reps, e.bmap, e.amap, total, par, lo32(seed), hi32(seed),
                            (int)cfg.xcd_remap, rev, table);
     else
         hipLaunchKernelGGL((pass_kernel<MU, false, LEARNED>), dim3(grid), dim3(cfg.pass_block), 0,
-                           stream, e.reps, e.bmap, e.total_blocks, par, lo32(seed), hi32(seed),
+                           stream, e.reps, e.bmap, e.amap, total, par, lo32(seed), hi32(seed),
                            (int)cfg.xcd_remap, rev, table);
 }
 

@@ -241,6 +241,8 @@ public:
     uint32_t sweep = 0;  // host mirror of the (common) sweep counter
     float orw = -1.0f;   // learned proposal: over-relaxation noise width (< 0: off)
     bool f64 = false;    // FP64 links (single lattice): the su2_f64.hip kernels
+    uint2 *amap = nullptr;  // XCD-affine pass map (device, owned), see Ens
+    uint32_t amap_len = 0;
     LaunchCfg cfg;
     uint32_t lg_tz = 3, lg_tt = 3;
     const float *table = nullptr;
@@ -294,7 +296,7 @@ public:
 
     Ens ens() const
     {
-        return Ens{d_reps(), d_bmap(), n, total_blocks, max_vh, max_ns3, poly_s};
+        return Ens{d_reps(), d_bmap(), amap, amap_len, n, total_blocks, max_vh, max_ns3, poly_s};
     }
 
     void drop_graph()
@@ -337,6 +339,31 @@ public:
             h[r].nblocks = nblocks[r];
             h[r].qfirst = 0u;
             h[r].orw = orw;
+        }
+        if (amap) {
+            HIP_TRY(hipStreamSynchronize(stream));  // no pass may still read it
+            (void)hipFree(amap);
+        }
+        amap = nullptr;
+        amap_len = 0;
+        if (cfg.affine && n > 1 && !f64) {
+            // replicas spread over the XCDs by size (as the work queue); the
+            // blocks of replica r go, in order, to workgroups b = slot * nq + x
+            // of its XCD x (workgroups are dispatched to the XCDs in turn)
+            std::vector<int> ids;
+            if (int rc = xcc_ids(ids)) return rc;
+            const int nq = (int)ids.size();
+            std::vector<int> qof;
+            std::vector<uint32_t> qfirst, qslots;
+            queue_layout(nblocks, nq, qof, qfirst, qslots);
+            const uint32_t maxlen = *std::max_element(qslots.begin(), qslots.end());
+            std::vector<uint2> m((size_t)nq * maxlen, uint2{0xFFFFFFFFu, 0u});
+            for (int r = 0; r < n; ++r)
+                for (uint32_t k = 0; k < nblocks[r]; ++k)
+                    m[(size_t)(qfirst[r] + k) * nq + qof[r]] = uint2{(uint32_t)r, k};
+            HIP_TRY(hipMalloc(&amap, m.size() * sizeof(uint2)));
+            HIP_TRY(hipMemcpy(amap, m.data(), m.size() * sizeof(uint2), hipMemcpyHostToDevice));
+            amap_len = (uint32_t)m.size();
         }
         if (cfg.queue) {
             std::vector<int> ids;
@@ -702,7 +729,7 @@ public:
     {
         if (block < 64 || block > 256 || (block % 64) != 0)
             return fail(SU2_EINVAL, "block must be 64, 128, 192 or 256");
-        if (flags < 0 || flags > 63) return fail(SU2_EINVAL, "flags must be in [0, 63]");
+        if (flags < 0 || flags > 127) return fail(SU2_EINVAL, "flags must be in [0, 127]");
         if (grid_cap < 0) return fail(SU2_EINVAL, "grid_cap must be >= 0");
         uint32_t lz, lt;
         int rc;
@@ -713,6 +740,7 @@ public:
         cfg.snake = (flags & 2) == 0;
         cfg.small = (flags & 4) == 0;
         cfg.queue = (flags & 8) != 0;
+        cfg.affine = (flags & 64) != 0;
         cfg.grain = 1 << ((flags >> 4) & 3);
         cfg.grid_cap = (uint32_t)grid_cap;
         if (cfg.queue) {  // device queries stay out of any stream capture
@@ -734,6 +762,8 @@ public:
         if (stream) (void)hipStreamSynchronize(stream);
         if (own_pool && pool) (void)hipFree(pool);
         if (own_scratch && scratch) (void)hipFree(scratch);
+        if (amap) (void)hipFree(amap);
+        amap = nullptr;
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         pool = nullptr;
         scratch = nullptr;
@@ -857,6 +887,12 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
     if (!f64)
         for (int b : {256, 128})
             for (int gr : {1, 2}) cands.push_back({b, 1 | 8 | (gr << 4), 8, 8, 0});
+    // batches: every replica's pass workgroups on one XCD
+    if (n > 1 && !f64)
+        for (int b : {256, 128})
+            for (int fl : {64, 66})
+                for (auto t : {std::array<int, 2>{8, 8}, {4, 8}, {1, 1}})
+                    cands.push_back({b, fl | no_small, t[0], t[1], 0});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1263,7 +1299,7 @@ static void get_launch(const Ensemble &E, int *block, int *flags, int *tile_z, i
         int lg = 0;
         while ((1 << lg) < E.cfg.grain) ++lg;
         *flags = (E.cfg.xcd_remap ? 1 : 0) | (E.cfg.snake ? 0 : 2) | (E.cfg.small ? 0 : 4) |
-                 (E.cfg.queue ? 8 : 0) | (lg << 4);
+                 (E.cfg.queue ? 8 : 0) | (lg << 4) | (E.cfg.affine ? 64 : 0);
     }
     if (tile_z) *tile_z = 1 << E.geom[0].lg_tz;
     if (tile_t) *tile_t = 1 << E.geom[0].lg_tt;

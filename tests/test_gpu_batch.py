@@ -77,7 +77,8 @@ def test_graph_replay_equals_direct(su2):
 
 @pytest.mark.parametrize("cfg", [(256, 1, 8, 8, 0), (128, 3, 1, 1, 0), (64, 0, 2, 16, 0),
                                  (256, 1, 4, 4, 64), (192, 1, 16, 2, 8), (256, 5, 8, 8, 0),
-                                 (128, 7, 2, 4, 16)], ids=str)
+                                 (128, 7, 2, 4, 16), (256, 68, 8, 8, 0), (128, 70, 1, 1, 0),
+                                 (64, 68, 4, 4, 16)], ids=str)
 def test_launch_configuration_does_not_change_links(su2, cfg):
     announce(f"launch config {cfg}")
     dims = [8, 6, 8, 16]
@@ -207,3 +208,29 @@ def test_small_lattice_kernel_matches_pass_kernels(su2):
     np.testing.assert_array_equal(ac[0], bc[0])
     np.testing.assert_array_equal(ac[1], bc[1])
     assert ac[1].sum() > 0 and ac[1].sum() < ac[0].sum()
+
+
+def test_xcd_affine_launch_measurements_identical(su2):
+    """The XCD-affine pass launch (every replica's workgroups on one XCD)
+    partitions the sites into the same workgroups, so the fused plaquette is
+    identical and the Polyakov loop agrees; links bit for bit, both modes."""
+    announce("xcd-affine launch: measurements")
+    p = (np.random.default_rng(31).standard_normal(2671) * 0.2).astype(np.float32)
+    runs = []
+    with su2.NN(params=p) as net:
+        net.build_table()
+        for flags in (1 | 4, 64 | 4):
+            with su2.Batch(DIMS, BETAS, STARTS, 19) as b:
+                b.set_proposal(net)
+                b.set_launch(256, flags, 8, 8, 0)
+                h1 = b.sweep_measure(5, meas=3, reunit_every=0).cpu().numpy()
+                h2 = b.sweep_measure(3, su2.SU2_LEARNED, meas=3).cpu().numpy()
+                runs.append((h1, h2, [b.get_links(r) for r in range(len(DIMS))],
+                             b.accept_stats()))
+    (a1, a2, al, ac), (b1, b2, bl, bc) = runs
+    for r in range(len(DIMS)):
+        np.testing.assert_array_equal(al[r], bl[r])
+    for x, y in ((a1, b1), (a2, b2)):
+        np.testing.assert_array_equal(x[..., 0], y[..., 0])
+        np.testing.assert_allclose(x[..., 1:], y[..., 1:], atol=1e-6, rtol=0)
+    np.testing.assert_array_equal(ac[1], bc[1])
