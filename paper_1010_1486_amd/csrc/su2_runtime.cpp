@@ -888,11 +888,15 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
         for (int b : {256, 128})
             for (int gr : {1, 2}) cands.push_back({b, 1 | 8 | (gr << 4), 8, 8, 0});
     // batches: every replica's pass workgroups on one XCD
-    if (n > 1 && !f64)
+    if (n > 1 && !f64) {
         for (int b : {256, 128})
             for (int fl : {64, 66})
                 for (auto t : {std::array<int, 2>{8, 8}, {4, 8}, {1, 1}})
                     cands.push_back({b, fl | no_small, t[0], t[1], 0});
+        // persistent grids (a learned pass then loads its LDS table once per workgroup)
+        for (auto t : {std::array<int, 2>{8, 8}, {1, 1}})
+            for (int gc : {1024, 4096}) cands.push_back({256, 64 | no_small, t[0], t[1], gc});
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
