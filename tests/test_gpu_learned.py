@@ -208,3 +208,36 @@ def test_overrelaxed_ensemble_matches_heat_bath(su2):
     err = np.sqrt(means["or"].var(ddof=1) / n + means["kp"].var(ddof=1) / n)
     assert abs(d) < 3.5 * err, (d, err)
     torch.cuda.synchronize()
+
+
+def test_training_gain_over_untrained_proposal(su2):
+    """What training buys, measured on the GPU: the trained flow's NLL of
+    exact-sampler draws falls well below the untrained (identity spline,
+    uniform proposal) value ln 2, its Metropolis acceptance on a batch of
+    thermalised lattices rises from ~0.15 to > 0.95, and the plaquette's
+    integrated autocorrelation time drops by a large factor, so the trained
+    proposal delivers several times more independent samples per sweep."""
+    announce("learned: training gain")
+    n, dims, beta = 16, [8, 8, 8, 8], 2.3
+    res = {}
+    with su2.NN(seed=3) as trained, su2.NN(seed=3) as untrained:
+        trained.sample_data(1_000_000, 0.5, 30.0, seed=3)
+        untrained.sample_data(1_000_000, 0.5, 30.0, seed=3)
+        nll0, _ = untrained.loss_grad(0, 16384)
+        trained.train(3000, 8192, 3e-3, lr_end=1e-4)
+        nll1, _ = trained.loss_grad(0, 16384)
+        for name, net in (("untrained", untrained), ("trained", trained)):
+            net.build_table()
+            with su2.Batch([dims] * n, [beta] * n, [1] * n, seed=4) as b:
+                b.set_proposal(net)
+                b.sweep(150)  # heat-bath thermalisation
+                b.accept_stats(reset=True)
+                h = b.sweep_measure(800, su2.SU2_LEARNED, meas=su2.SU2_MEAS_PLAQ).cpu().numpy()
+                prop, acc = b.accept_stats()
+            taus = [stats.tau_int(h[:, r, 0]) for r in range(n)]
+            res[name] = (acc.sum() / prop.sum(), float(np.mean(taus)))
+    assert nll0 == pytest.approx(np.log(2.0), abs=1e-3)
+    assert nll1 < nll0 - 0.5, (nll0, nll1)
+    (a0, t0), (a1, t1) = res["untrained"], res["trained"]
+    assert a0 < 0.3 and a1 > 0.95, res
+    assert t0 > 4 * t1, res
