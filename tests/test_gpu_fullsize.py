@@ -127,3 +127,42 @@ def test_full_size_learned_pass(su2, orc):
         assert worst < 1e-5
         assert nflag <= max_learned_flags(len(sites))
         assert kinds[0] > 0 and kinds[1] > 0
+
+
+@pytest.mark.parametrize("workload", ["beta_scan_16", "beta_scan_24", "polyakov", "replicas64"])
+def test_batched_workload_in_autotuned_launch(su2, orc, workload):
+    """Each batched benchmark workload at its full size, in the launch the
+    autotuner picks for it (per-pass, XCD-affine, work queue or persistent, as
+    the benchmark times it): after one sweep from the batch's hot start, sampled
+    replicas equal the oracle's sweep of the same replica (replica id, beta,
+    seed) within 1e-5 per link component.  A decision the oracle takes within
+    2e-5 of its threshold may flip in FP32 and then also changes the links it
+    feeds later in the sweep, so each flagged decision may account for a few
+    hundred mismatched links; without flagged decisions every link matches."""
+    import bench
+    announce(f"full-size batch {workload}, autotuned launch")
+    dims, betas, starts, seed, pick = {
+        "beta_scan_16": (*bench._beta_scan(16), 1000, [0, 9, 20, 31]),
+        "beta_scan_24": (*bench._beta_scan(24), 1000, [3, 30]),
+        "polyakov": (*bench._polyakov_grid(), 4000, [0, 14, 38]),
+        "replicas64": (*bench._replicas64(), 5, [0, 1, 2, 7, 8, 9, 16, 6]),
+    }[workload]
+    n = len(dims)
+    starts = np.broadcast_to(np.asarray(starts), (n,))
+    with su2.Batch(dims, betas, starts, seed) as b:
+        b.autotune(None, su2.SU2_KP)
+        launch = b.launch()
+        b.sweep(1)
+        got = {r: b.get_links(r) for r in pick}
+    for r in pick:
+        d = dims[r]
+        U = orc.init(d, int(starts[r]), seed, replica=r)
+        nflag = 0
+        for mu in range(4):
+            for p in range(2):
+                m = orc.do_pass(d, U, mu, p, 0, float(betas[r]), seed, replica=r,
+                                want_margin=True)
+                nflag += int((m < MARGIN_FLAG).sum())
+        bad = int((np.abs(got[r] - U).max(axis=2) > 1e-5).sum())
+        assert bad <= 500 * nflag, (workload, r, launch, bad, nflag)
+        assert bad < 0.01 * U.shape[0] * 4, (workload, r, launch, bad)
