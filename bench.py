@@ -423,12 +423,33 @@ def creutz(W, R):
     return -np.log(w(R, R) * w(R - 1, R - 1) / (w(R, R - 1) * w(R - 1, R)))
 
 
-def scale_setting(su2, torch, dev, betas=(2.3, 2.4, 2.5), therm=300, nmeas=60, every=5):
+POLYAKOV_BETAS = tuple(np.round(np.arange(2.0, 2.6001, 0.05), 2))
+
+
+def beta_c(betas, absL):
+    """Deconfinement coupling of one N_t from <|L|>(beta): the midpoint of the
+    beta interval over which <|L|> rises most."""
+    betas, absL = np.asarray(betas, float), np.asarray(absL, float)
+    k = int(np.argmax(np.diff(absL)))
+    return 0.5 * (betas[k] + betas[k + 1])
+
+
+def t_over_tc(betas_sigma, sigma, bc, betas):
+    """T/Tc = a(beta_c)/a(beta) at fixed N_t, with a ~ sqrt(sigma a^2): the
+    string tension in lattice units, interpolated linearly in ln(sigma a^2)
+    between the measured couplings."""
+    ls = np.log(np.asarray(sigma, float))
+    f = lambda b: np.interp(b, betas_sigma, ls)
+    return np.exp(0.5 * (f(bc) - f(np.asarray(betas, float))))
+
+
+def scale_setting(su2, torch, dev, betas=POLYAKOV_BETAS, therm=300, nmeas=40, every=5):
     """Wilson loops W(R,T), R, T <= 4, on thermalised 16^4 lattices (hot start,
-    seed 1000 + i) measured every `every` sweeps, the Creutz ratios
-    chi(2,2), chi(3,3), chi(4,4) (the string tension sigma a^2 in lattice
-    units: the scale the T/Tc axis of the Polyakov loop needs), and the time
-    of one W(4,4) measurement on the 48^4 headline lattice."""
+    seed 1000 + i) at the couplings of the Polyakov workload, measured every
+    `every` sweeps; the Creutz ratios chi(2,2), chi(3,3), chi(4,4) (the string
+    tension sigma a^2 in lattice units: the scale the T/Tc axis of the
+    Polyakov loop needs), and the time of one W(4,4) measurement on the 48^4
+    headline lattice."""
     out = {"workload": f"16^4, beta {list(betas)}, hot start, {therm} thermalisation sweeps, "
                        f"{nmeas} measurements of W(R,T) (R,T <= 4) every {every} sweeps"}
     rows = []
@@ -441,12 +462,14 @@ def scale_setting(su2, torch, dev, betas=(2.3, 2.4, 2.5), therm=300, nmeas=60, e
                 W.append(lat.wilson_loops(4, 4))
         W = np.array(W)
         mean = W.mean(axis=0)
-        chis = {f"chi_{R}{R}": float(creutz(mean, R)) for R in (2, 3, 4)}
+        with np.errstate(invalid="ignore", divide="ignore"):
+            chis = {f"chi_{R}{R}": float(creutz(mean, R)) for R in (2, 3, 4)}
         # jackknife error of the Creutz ratios
-        jk = np.array([[creutz((W.sum(axis=0) - W[j]) / (len(W) - 1), R) for R in (2, 3, 4)]
-                       for j in range(len(W))])
+        with np.errstate(invalid="ignore", divide="ignore"):
+            jk = np.array([[creutz((W.sum(axis=0) - W[j]) / (len(W) - 1), R) for R in (2, 3, 4)]
+                           for j in range(len(W))])
         err = np.sqrt((len(W) - 1) * jk.var(axis=0))
-        rows.append({"beta": beta, "W": np.round(mean, 7).tolist(), **chis,
+        rows.append({"beta": float(beta), "W": np.round(mean, 7).tolist(), **chis,
                      **{f"chi_{R}{R}_err": float(e) for R, e in zip((2, 3, 4), err)}})
     out["by_beta"] = rows
     with su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT, device=dev) as lat:
@@ -598,6 +621,20 @@ def main():
     if not args.no_wilson:
         print("[bench] Wilson loops and Creutz ratios", file=sys.stderr, flush=True)
         out["scale_setting"] = scale_setting(su2, torch, dev)
+    if "scale_setting" in out and "other_configs" in out:
+        ss = out["scale_setting"]["by_beta"]
+        bs = [r["beta"] for r in ss]
+        sig = [r["chi_22"] for r in ss]
+        pol = out["other_configs"]["polyakov_32^3xNt"]["mean_abs_polyakov_by_nt"]
+        tt = {"scale": "sigma a^2 from the Creutz ratio chi(2,2) on 16^4, interpolated in "
+                       "ln(sigma a^2); beta_c per N_t where <|L|> rises most",
+              "by_nt": {}}
+        for nt, absL in pol.items():
+            bc = beta_c(POLYAKOV_BETAS, absL)
+            x = t_over_tc(bs, sig, bc, POLYAKOV_BETAS)
+            tt["by_nt"][nt] = {"beta_c": bc, "T_over_Tc": np.round(x, 4).tolist(),
+                               "mean_abs_polyakov": absL}
+        out["polyakov_vs_T_over_Tc"] = tt
     if not args.no_learned:
         print("[bench] batched plain vs learned proposal", file=sys.stderr, flush=True)
         out["learned_vs_plain"] = learned_vs_plain(su2, torch, dev,
