@@ -159,3 +159,32 @@ def test_polyakov_32x4_matches_oracle(su2, orc):
         p += [matched_pull(ph.mean(), gp), matched_pull(np.abs(lh).mean(), gl)]
     print(f"[gpu-test] oracle + matched GPU chains {time.time() - t0:.1f} s", flush=True)
     assert_pulls(p, "oracle vs gpu, P and |L|, Nt = 4, matched protocol")
+
+
+def test_learned_modes_match_oracle(su2, orc):
+    """The learned updates (independence and over-relaxed Metropolis, trained
+    flow) leave the heat-bath distribution of Sec. 2 exact: after the same
+    heat-bath thermalisation on both sides, the mean plaquette of 32 GPU
+    replicas measured with the learned update agrees with an independent FP64
+    oracle heat-bath chain (the oracle's error tau_int-corrected, the GPU's from
+    the spread of its replicas)."""
+    announce("ensemble: learned modes vs oracle heat bath")
+    dims, nrep, therm, nmeas, every = [12, 12, 12, 12], 32, 200, 150, 2
+    p = []
+    with su2.NN(seed=8) as net:
+        net.sample_data(1_000_000, 0.5, 30.0, seed=8)
+        net.train(2000, 8192, 3e-3, lr_end=1e-4)
+        net.build_table()
+        for i, beta in enumerate((2.1, 2.4)):
+            ph, _ = oracle_chain(orc, dims, beta, 8100 + i, 1, therm, nmeas, every)
+            o_mean, o_err = stats.mean_err(ph)
+            for width in (-1.0, 0.02):
+                with su2.Batch([dims] * nrep, beta, 1, seed=8200 + 10 * i + int(width > 0)) as b:
+                    b.set_proposal(net)
+                    b.set_overrelax(width)
+                    b.sweep_measure(therm, reunit_every=10)  # heat bath, as the oracle
+                    h = b.sweep_measure(nmeas * every, su2.SU2_LEARNED,
+                                        reunit_every=10).cpu().numpy()
+                g = h[every - 1::every, :, 0].mean(axis=0)
+                p.append((o_mean - g.mean()) / np.hypot(o_err, g.std(ddof=1) / np.sqrt(nrep)))
+    assert_pulls(p, "oracle heat bath vs gpu learned (independence, over-relaxed)")
