@@ -277,18 +277,25 @@ void orc_heatbath_link(const double V[4], double beta, uint64_t seed, uint32_t s
                        uint32_t sweep, uint32_t mu, uint32_t replica, double out[4],
                        double *margin)
 {
+    orc_heatbath_link_w2(V, beta, seed, site, sweep, word2_of(mu, ORC_TAG_TRIAL, replica), out,
+                         margin);
+}
+
+void orc_heatbath_link_w2(const double V[4], double beta, uint64_t seed, uint32_t site,
+                          uint32_t sweep, uint32_t w2, double out[4], double *margin)
+{
     /* k = sqrt(det V); for a quaternion sum det V = |V|^2 (Sec. 2). */
     double k = qnorm(V);
     double Ut[4] = {1.0, 0.0, 0.0, 0.0};
     if (k > 0.0)
         for (int c = 0; c < 4; ++c) Ut[c] = V[c] / k;
     double alpha = beta * k;
-    double delta = orc_sample_delta(alpha, seed, site, sweep, mu, replica, NULL, margin);
+    double delta = orc_sample_delta_w2(alpha, seed, site, sweep, w2, NULL, margin);
     /* Direction uniforms: the 9 low bits of each word of the first trial's
      * block are not used by the a0 uniforms (which take bits 9..31); they give
      * two independent 18-bit uniforms (2m+1) 2^-19. */
     uint32_t w[4];
-    block(seed, site, sweep, word2_of(mu, ORC_TAG_TRIAL, replica), 0u, NULL, w);
+    block(seed, site, sweep, w2, 0u, NULL, w);
     double rd[2];
     rd[0] = orc_uniform18((w[0] & 511u) | ((w[1] & 511u) << 9));
     rd[1] = orc_uniform18((w[2] & 511u) | ((w[3] & 511u) << 9));

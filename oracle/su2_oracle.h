@@ -20,7 +20,7 @@
  *           mu | tag<<2 | replica<<6, draw); tags: 0 a0 trials (the low 9 bits
  *           of the words of draw 0 give the direction), 1 reserved,
  *           2 hot start, 3 gauge transform, 4 learned proposal, 5 training data,
- *           6 replica beta
+ *           6 replica beta, 7..9 SU(3) subgroup trials, 10 SU(3) hot start
  */
 #ifndef SU2_ORACLE_H
 #define SU2_ORACLE_H
@@ -38,6 +38,8 @@ extern "C" {
 #define ORC_TAG_LEARN 4u
 #define ORC_TAG_TRAIN 5u
 #define ORC_TAG_BETA 6u
+#define ORC_TAG_SU3_SUB 7u /* SU(3) subgroups 0, 1, 2: tags 7, 8, 9 */
+#define ORC_TAG_SU3_HOT 10u
 
 /* Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -78,6 +80,10 @@ void orc_sample_delta_batch(int64_t n, const double *alpha, uint64_t seed,
 void orc_heatbath_link(const double V[4], double beta, uint64_t seed, uint32_t site,
                        uint32_t sweep, uint32_t mu, uint32_t replica, double out[4],
                        double *margin);
+/* The same with the third Philox counter word given directly (the SU(3)
+ * subgroup updates draw from their own tags). */
+void orc_heatbath_link_w2(const double V[4], double beta, uint64_t seed, uint32_t site,
+                          uint32_t sweep, uint32_t w2, double out[4], double *margin);
 
 /* One checkerboard pass over every site of the given parity, direction mu.
  * order: 0 lexicographic, 1 reversed, 2 shuffled (order_seed), 3 OpenMP.

@@ -28,7 +28,7 @@ def _load():
     if _lib is not None:
         return _lib
     path = _build.LIB
-    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+    if _build.stale():
         _build.build()
     lib = ctypes.CDLL(path)
     c_u64, c_u32, c_i64, c_int, c_d = (ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64,
