@@ -15,6 +15,7 @@
 
 #include "../../include/su2.h"
 #include "su2_internal.h"
+#include "su3_internal.h"
 
 using su2dev::Geom;
 using su2dev::kNNRow;
@@ -47,6 +48,11 @@ inline size_t dev_index(int mu, int par, int k, int64_t h, int64_t vh)
     return ((size_t)(mu * 2 + par) * (size_t)vh + (size_t)h) * 4u + (size_t)k;
 }
 
+}  // namespace
+
+// Argument checks and the lattice geometry, shared with the SU(3) runtime.
+namespace su2rt {
+
 int fail(int code, const std::string &msg)
 {
     set_error(msg);
@@ -70,6 +76,10 @@ int check_dims(const int32_t *dims)
     return SU2_OK;
 }
 
+}  // namespace su2rt
+
+namespace {
+
 // Multiplier and shift for exact division of 31-bit numerators by d
 // (Granlund & Montgomery 1994, Thm. 4.2 with N = 31).
 void magic(uint32_t d, uint32_t &m, uint32_t &s)
@@ -91,6 +101,10 @@ uint32_t pow2_divisor_log(int32_t n, uint32_t cap)
     while (l < cap && (n % (2 << l)) == 0) ++l;
     return l;
 }
+
+}  // namespace
+
+namespace su2rt {
 
 Geom make_geom(const int32_t *d, uint32_t lg_tz, uint32_t lg_tt)
 {
@@ -126,6 +140,10 @@ bool geom_selfcheck(const Geom &g)
     }
     return true;
 }
+
+}  // namespace su2rt
+
+namespace {
 
 // tile 0 keeps `cur`; else a power of two (the geometry clips it to a divisor).
 int lg_of_tile(int tile, uint32_t cur, uint32_t *out)

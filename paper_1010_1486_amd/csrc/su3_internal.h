@@ -1,0 +1,62 @@
+// su3_internal.h -- host/device declarations of the SU(3) heat bath of libsu2
+// (not part of the public C ABI).
+#pragma once
+
+#include "su2_internal.h"
+
+namespace su3rt {
+
+using su2dev::Geom;
+
+// Links of an SU(3) lattice: 24 planes of V/2 float4, plane
+// ((mu * 2 + parity) * 3 + c) holding float4 c of U_mu at every half-site of
+// that parity.  Only rows 0 and 1 are stored (12 floats):
+//   c = 0: (Re u00, Im u00, Re u01, Im u01)
+//   c = 1: (Re u02, Im u02, Re u10, Im u10)
+//   c = 2: (Re u11, Im u11, Re u12, Im u12)
+// and row 2 = conj(row0 x row1) is rebuilt on every load.
+constexpr int kPlanes3 = 24;
+constexpr int kHist3 = 1024;  // device history rows per measured call chunk
+
+struct Lat3 {
+    Geom g;
+    float4 *links;
+    unsigned long long *acc;  // kNumAcc x kBuckets fixed-point accumulators
+    double *results;          // kRes3 result slots
+    double *hist;             // kHist3 plaquette history rows
+    float beta;
+    uint32_t replica;
+};
+
+enum Acc3 { A3_PLAQ = 0, A3_POLY_RE = 1, A3_POLY_IM = 2, A3_POLY_ABS = 3 };
+enum Res3 { R3_PLAQ = 0, R3_POLY_RE = 1, R3_POLY_IM = 2, R3_POLY_ABS = 3, kRes3 = 8 };
+
+struct Launch3 {
+    int block = 256;
+    bool remap = true;     // XCD-aware workgroup -> tile mapping
+    bool snake = true;     // odd-parity passes traverse backwards
+};
+
+hipError_t launch_su3_init(const Lat3 &L, int start, uint64_t seed, hipStream_t s);
+// One heat-bath pass (direction mu, parity par); with measure, the plaquette
+// terms of the passes' nu < mu staples are accumulated (odd passes of mu >= 1
+// cover every plaquette of the end-of-sweep configuration once).
+hipError_t launch_su3_pass(const Lat3 &L, int mu, int par, uint32_t sweep, uint64_t seed,
+                           bool measure, const Launch3 &cfg, hipStream_t s);
+hipError_t launch_su3_reunit(const Lat3 &L, hipStream_t s);
+hipError_t launch_su3_plaquette(const Lat3 &L, hipStream_t s);
+hipError_t launch_su3_polyakov(const Lat3 &L, hipStream_t s);
+// Totals of the accumulators named by flags (1 plaquette, 2 Polyakov) into the
+// result slots (the accumulators are reset); flags & 4: the plaquette also
+// goes to hist[row].
+hipError_t launch_su3_finish(const Lat3 &L, int flags, int row, hipStream_t s);
+
+}  // namespace su3rt
+
+namespace su2rt {
+// Host helpers of the SU(2) runtime reused by the SU(3) one.
+int check_dims(const int32_t *dims);
+su2dev::Geom make_geom(const int32_t *d, uint32_t lg_tz, uint32_t lg_tt);
+bool geom_selfcheck(const su2dev::Geom &g);
+int fail(int code, const std::string &msg);
+}  // namespace su2rt

@@ -1,0 +1,345 @@
+// su3_runtime.cpp -- C ABI of the SU(3) heat bath in libsu2: argument checks,
+// device memory, the sweep schedule (Sec. 4: per direction, even sites then
+// odd sites), the measurements and the host exchange of links.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/su3.h"
+#include "su3_internal.h"
+
+using namespace su2rt;
+using namespace su3rt;
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));              \
+            return SU2_EHIP;                                                            \
+        }                                                                               \
+    } while (0)
+
+struct su3_ctx {
+    int32_t dims[4] = {0, 0, 0, 0};
+    Lat3 L{};
+    Launch3 cfg;
+    uint32_t lg_tz = 3, lg_tt = 3;
+    hipStream_t stream = nullptr;
+    uint64_t seed = 0;
+    uint32_t sweep = 0;
+    void *links_mem = nullptr;
+    void *scratch_mem = nullptr;
+};
+
+namespace {
+
+constexpr size_t kScratch3 = kAccBytes + (size_t)kRes3 * 8 + (size_t)kHist3 * 8;
+
+int64_t volume3(const int32_t *d) { return (int64_t)d[0] * d[1] * d[2] * d[3]; }
+
+int check3(su3_ctx *c)
+{
+    if (!c) return fail(SU2_EINVAL, "context is NULL");
+    return SU2_OK;
+}
+
+int lg_tile(int tile, uint32_t cur, uint32_t *out)
+{
+    if (tile == 0) {
+        *out = cur;
+        return SU2_OK;
+    }
+    if (tile < 0 || (tile & (tile - 1)) || tile > 256)
+        return fail(SU2_EINVAL, "tile sizes must be powers of two <= 256");
+    uint32_t l = 0;
+    while ((1 << l) < tile) ++l;
+    *out = l;
+    return SU2_OK;
+}
+
+// Totals of the accumulators (flags 1 plaquette, 2 Polyakov) into the result
+// slots, then nres slots from `first` copied to the host.
+int finish_to_host(su3_ctx *c, int flags, int first, int nres, double *host)
+{
+    HIP_TRY(launch_su3_finish(c->L, flags, 0, c->stream));
+    HIP_TRY(hipMemcpyAsync(host, c->L.results + first, sizeof(double) * (size_t)nres,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SU2_OK;
+}
+
+// Coordinates of canonical site s.
+void coords(const int32_t *d, int64_t s, int c[4])
+{
+    for (int i = 0; i < 4; ++i) {
+        c[i] = (int)(s % d[i]);
+        s /= d[i];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t su3_links_bytes(const int32_t dims[4])
+{
+    if (!dims) return 0;
+    const std::string keep = su2_last_error();  // a size query is not a failure
+    const int rc = check_dims(dims);
+    set_error(keep);
+    if (rc) return 0;
+    return (size_t)volume3(dims) * 192u;
+}
+
+int su3_init(su3_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
+             void *hip_stream)
+{
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
+    if (start != SU2_COLD && start != SU2_HOT) return fail(SU2_EINVAL, "start must be COLD or HOT");
+    su3_ctx *c = new (std::nothrow) su3_ctx();
+    if (!c) return fail(SU2_ENOMEM, "host allocation failed");
+    for (int i = 0; i < 4; ++i) c->dims[i] = dims[i];
+    c->L.g = make_geom(dims, c->lg_tz, c->lg_tt);
+    if (!geom_selfcheck(c->L.g)) {
+        delete c;
+        return fail(SU2_ERANGE, "index arithmetic self-check failed");
+    }
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->seed = seed;
+    c->L.beta = (float)beta;
+    c->L.replica = 0u;
+    hipError_t e = hipMalloc(&c->links_mem, su3_links_bytes(dims));
+    if (e == hipSuccess) e = hipMalloc(&c->scratch_mem, kScratch3);
+    if (e == hipSuccess) e = hipMemsetAsync(c->scratch_mem, 0, kScratch3, c->stream);
+    if (e == hipSuccess) {
+        c->L.links = static_cast<float4 *>(c->links_mem);
+        c->L.acc = static_cast<unsigned long long *>(c->scratch_mem);
+        c->L.results = reinterpret_cast<double *>(static_cast<unsigned char *>(c->scratch_mem) +
+                                                  kAccBytes);
+        c->L.hist = c->L.results + kRes3;
+        e = launch_su3_init(c->L, start, seed, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        if (c->links_mem) (void)hipFree(c->links_mem);
+        if (c->scratch_mem) (void)hipFree(c->scratch_mem);
+        delete c;
+        return fail(e == hipErrorOutOfMemory ? SU2_ENOMEM : SU2_EHIP,
+                    std::string("su3_init: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return SU2_OK;
+}
+
+int su3_destroy(su3_ctx *c)
+{
+    if (!c) return fail(SU2_EINVAL, "context is NULL");
+    (void)hipStreamSynchronize(c->stream);
+    if (c->links_mem) (void)hipFree(c->links_mem);
+    if (c->scratch_mem) (void)hipFree(c->scratch_mem);
+    delete c;
+    return SU2_OK;
+}
+
+int su3_heatbath_sweep(su3_ctx *c, int32_t nsweeps, int32_t reunit_every, double *plaq_hist)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (nsweeps < 0 || reunit_every < 0)
+        return fail(SU2_EINVAL, "nsweeps and reunit_every must be >= 0");
+    int32_t done = 0;
+    while (done < nsweeps) {
+        const int32_t chunk = plaq_hist ? std::min<int32_t>(nsweeps - done, kHist3)
+                                        : nsweeps - done;
+        for (int32_t j = 0; j < chunk; ++j) {
+            for (int mu = 0; mu < 4; ++mu)
+                for (int par = 0; par < 2; ++par)
+                    HIP_TRY(launch_su3_pass(c->L, mu, par, c->sweep, c->seed,
+                                            plaq_hist && par == 1 && mu >= 1, c->cfg, c->stream));
+            if (plaq_hist) HIP_TRY(launch_su3_finish(c->L, 1 | 4, j, c->stream));
+            if (reunit_every > 0 && (c->sweep + 1u) % (uint32_t)reunit_every == 0u)
+                HIP_TRY(launch_su3_reunit(c->L, c->stream));
+            ++c->sweep;
+        }
+        if (plaq_hist) {
+            HIP_TRY(hipMemcpyAsync(plaq_hist + done, c->L.hist, sizeof(double) * (size_t)chunk,
+                                   hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+        done += chunk;
+    }
+    return SU2_OK;
+}
+
+int su3_reunitarize(su3_ctx *c)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    HIP_TRY(launch_su3_reunit(c->L, c->stream));
+    return SU2_OK;
+}
+
+int su3_plaquette(su3_ctx *c, double *out)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    HIP_TRY(launch_su3_plaquette(c->L, c->stream));
+    return finish_to_host(c, 1, R3_PLAQ, 1, out);
+}
+
+int su3_polyakov(su3_ctx *c, double *out)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    HIP_TRY(launch_su3_polyakov(c->L, c->stream));
+    return finish_to_host(c, 2, R3_POLY_RE, 3, out);
+}
+
+int su3_get_links(su3_ctx *c, double *host)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (!host) return fail(SU2_EINVAL, "host is NULL");
+    const int64_t V = volume3(c->dims), vh = V / 2;
+    std::vector<float> dev((size_t)V * 48u);
+    HIP_TRY(hipMemcpyAsync(dev.data(), c->L.links, dev.size() * sizeof(float),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    typedef std::complex<double> cd;
+    for (int64_t s = 0; s < V; ++s) {
+        int x[4];
+        coords(c->dims, s, x);
+        const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+        const int64_t h = s >> 1;
+        for (int mu = 0; mu < 4; ++mu) {
+            float f[12];
+            for (int k = 0; k < 3; ++k)
+                for (int j = 0; j < 4; ++j)
+                    f[4 * k + j] = dev[(((size_t)(mu * 2 + par) * 3 + (size_t)k) * (size_t)vh +
+                                        (size_t)h) * 4u + (size_t)j];
+            cd m[3][3];
+            for (int e = 0; e < 6; ++e) m[e / 3][e % 3] = cd(f[2 * e], f[2 * e + 1]);
+            m[2][0] = std::conj(m[0][1] * m[1][2] - m[0][2] * m[1][1]);
+            m[2][1] = std::conj(m[0][2] * m[1][0] - m[0][0] * m[1][2]);
+            m[2][2] = std::conj(m[0][0] * m[1][1] - m[0][1] * m[1][0]);
+            double *o = host + ((size_t)s * 4 + (size_t)mu) * 18;
+            for (int e = 0; e < 9; ++e) {
+                o[2 * e] = m[e / 3][e % 3].real();
+                o[2 * e + 1] = m[e / 3][e % 3].imag();
+            }
+        }
+    }
+    return SU2_OK;
+}
+
+int su3_set_links(su3_ctx *c, const double *host)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (!host) return fail(SU2_EINVAL, "host is NULL");
+    const int64_t V = volume3(c->dims), vh = V / 2;
+    std::vector<float> dev((size_t)V * 48u);
+    for (int64_t s = 0; s < V; ++s) {
+        int x[4];
+        coords(c->dims, s, x);
+        const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+        const int64_t h = s >> 1;
+        for (int mu = 0; mu < 4; ++mu) {
+            const double *in = host + ((size_t)s * 4 + (size_t)mu) * 18;  // rows 0, 1 = 12 reals
+            for (int k = 0; k < 3; ++k)
+                for (int j = 0; j < 4; ++j)
+                    dev[(((size_t)(mu * 2 + par) * 3 + (size_t)k) * (size_t)vh + (size_t)h) * 4u +
+                        (size_t)j] = (float)in[4 * k + j];
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(c->L.links, dev.data(), dev.size() * sizeof(float),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SU2_OK;
+}
+
+int su3_get_sweep(su3_ctx *c, uint32_t *out)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    *out = c->sweep;
+    return SU2_OK;
+}
+
+int su3_set_sweep(su3_ctx *c, uint32_t sweep)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    c->sweep = sweep;
+    return SU2_OK;
+}
+
+int su3_set_beta(su3_ctx *c, double beta)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
+    c->L.beta = (float)beta;
+    return SU2_OK;
+}
+
+int su3_set_launch(su3_ctx *c, int block, int remap, int snake, int tile_z, int tile_t)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (block != 64 && block != 128 && block != 192 && block != 256)
+        return fail(SU2_EINVAL, "block must be 64, 128, 192 or 256");
+    uint32_t lz, lt;
+    if ((rc = lg_tile(tile_z, c->lg_tz, &lz)) || (rc = lg_tile(tile_t, c->lg_tt, &lt))) return rc;
+    const Geom g = make_geom(c->dims, lz, lt);
+    if (!geom_selfcheck(g)) return fail(SU2_ERANGE, "index arithmetic self-check failed");
+    HIP_TRY(hipStreamSynchronize(c->stream));  // passes already enqueued keep their launch
+    c->cfg.block = block;
+    c->cfg.remap = remap != 0;
+    c->cfg.snake = snake != 0;
+    c->lg_tz = lz;
+    c->lg_tt = lt;
+    c->L.g = g;
+    return SU2_OK;
+}
+
+int su3_links_device(su3_ctx *c, void **links_dev, void **hip_stream)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (links_dev) *links_dev = c->L.links;
+    if (hip_stream) *hip_stream = c->stream;
+    return SU2_OK;
+}
+
+int su3_synchronize(su3_ctx *c)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SU2_OK;
+}
+
+int su3_test_pass(su3_ctx *c, int mu, int parity)
+{
+    int rc = check3(c);
+    if (rc) return rc;
+    if (mu < 0 || mu > 3 || parity < 0 || parity > 1)
+        return fail(SU2_EINVAL, "mu must be 0..3 and parity 0..1");
+    HIP_TRY(launch_su3_pass(c->L, mu, parity, c->sweep, c->seed, false, c->cfg, c->stream));
+    return SU2_OK;
+}
+
+}  // extern "C"

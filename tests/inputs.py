@@ -43,3 +43,23 @@ def random_staples(n, seed, kmin=0.05, kmax=6.0):
 def log_uniform(n, lo, hi, seed):
     rng = np.random.default_rng(seed)
     return np.exp(rng.uniform(np.log(lo), np.log(hi), n))
+
+
+def random_su3_links(dims, seed, spread=None):
+    """SU(3) links as complex128 (V, 4, 3, 3).
+
+    spread=None: Haar (QR of a complex Gaussian matrix, phases of R's diagonal
+                 moved into Q, det divided out by a cube root).
+    spread=eps : the same decomposition of identity plus complex Gaussian noise
+                 of width eps; mimics an ordered configuration.
+    """
+    rng = np.random.default_rng(seed)
+    n = volume(dims) * 4
+    z = (rng.standard_normal((n, 3, 3)) + 1j * rng.standard_normal((n, 3, 3))) / np.sqrt(2)
+    if spread is not None:
+        z = np.eye(3) + spread * z
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r, axis1=1, axis2=2)
+    q = q * (d / np.abs(d))[:, None, :]
+    q = q * (np.linalg.det(q) ** (-1.0 / 3.0))[:, None, None]
+    return np.ascontiguousarray(q.reshape(volume(dims), 4, 3, 3))

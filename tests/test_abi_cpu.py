@@ -134,3 +134,34 @@ def test_work_queue_schedule_rejects_bad_arguments():
     assert e.value.code == su2.SU2_ERANGE
     with pytest.raises(su2.SU2Error):
         su2.su2_test_queue_plan([[4, 4, 4, 4]], 256, 2, queues=17)
+
+
+def test_library_exports_every_su3_function():
+    lib = su2.lib3()
+    names = su2.header_functions3()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_su3_sizes_and_bad_arguments():
+    from paper_1010_1486_amd import su3
+    assert su3.su3_links_bytes([4, 4, 4, 4]) == 192 * 256
+    assert su3.su3_links_bytes([48, 48, 48, 48]) == 192 * 48 ** 4
+    assert su3.su3_links_bytes([3, 4, 4, 4]) == 0
+    assert su3.su3_links_bytes([512, 512, 512, 4]) == 0
+    lib = su2.lib3()
+    h = ctypes.c_void_p()
+    d = np.array([4, 4, 4, 5], dtype=np.int32)
+    assert lib.su3_init(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), 6.0, 1, 0,
+                        None) == su2.SU2_EODD
+    d = np.array([4, 4, 4, 4], dtype=np.int32)
+    assert lib.su3_init(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), float("nan"), 1, 0,
+                        None) == su2.SU2_EINVAL
+    assert lib.su3_init(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), 6.0, 1, 7,
+                        None) == su2.SU2_EINVAL
+    assert lib.su3_init(None, d.ctypes.data_as(ctypes.c_void_p), 6.0, 1, 0, None) == su2.SU2_EINVAL
+    for call in (lambda: lib.su3_destroy(None), lambda: lib.su3_reunitarize(None),
+                 lambda: lib.su3_heatbath_sweep(None, 1, 0, None),
+                 lambda: lib.su3_test_pass(None, 0, 0), lambda: lib.su3_synchronize(None)):
+        assert call() == su2.SU2_EINVAL

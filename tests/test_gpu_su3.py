@@ -1,0 +1,243 @@
+"""SU(3) heat bath (Cabibbo-Marinari subgroups on the SU(2) step of Sec. 2) on
+the GPU against the FP64 SU(3) oracle.
+
+Both sides draw the same Philox streams, so each link agrees to FP32 rounding.
+The FP32 error of an a0 decision is larger than for SU(2) (six staples of three
+SU(3) factors, then W = U A and two earlier subgroup rotations feed each
+subgroup's k), so links whose smallest oracle decision margin is below
+FLAG3 = 2e-4 are excluded and counted against a bound; every flagged link must
+still be in SU(3).
+"""
+import numpy as np
+import pytest
+
+from tests import inputs
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+FLAG3 = 2e-4
+TOL3 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def o3():
+    from oracle import su3_oracle
+    su3_oracle._load()
+    return su3_oracle
+
+
+def parities(dims):
+    V = int(np.prod(dims))
+    s = np.arange(V)
+    x = s % dims[0]
+    y = (s // dims[0]) % dims[1]
+    z = (s // (dims[0] * dims[1])) % dims[2]
+    t = s // (dims[0] * dims[1] * dims[2])
+    return (x + y + z + t) & 1
+
+
+def su3_defect(U):
+    M = U.reshape(-1, 3, 3)
+    return max(np.abs(M @ np.conj(np.swapaxes(M, 1, 2)) - np.eye(3)).max(),
+               np.abs(np.linalg.det(M) - 1.0).max())
+
+
+def max_flags3(n_links):
+    return int(10 * 3 * 2 * FLAG3 * n_links) + 3
+
+
+@pytest.mark.parametrize("dims", [[4, 4, 4, 6], [6, 6, 6, 10]], ids=lambda d: "x".join(map(str, d)))
+def test_su3_starts_match_oracle(su2, o3, dims):
+    announce(f"su3 hot/cold start dims={dims}")
+    with su2.Lattice3(dims, 6.0, 9, su2.SU2_HOT) as lat:
+        got = lat.get_links()
+        plaq = lat.plaquette()
+    want = o3.init(dims, 1, 9)
+    assert np.abs(got - want).max() < 2e-5
+    assert su3_defect(got) < 2e-6
+    assert plaq == pytest.approx(o3.plaquette(dims, got), abs=1e-6)
+    with su2.Lattice3(dims, 6.0, 9, su2.SU2_COLD) as lat:
+        assert lat.plaquette() == 1.0
+        assert lat.polyakov() == (1.0, 0.0, 1.0)
+        assert np.array_equal(lat.get_links(), o3.init(dims, 0, 9))
+
+
+@pytest.mark.parametrize("dims,spread,beta", [([4, 4, 4, 4], None, 5.7), ([6, 6, 6, 10], 0.3, 6.0),
+                                              ([8, 4, 6, 4], 0.15, 8.0)],
+                         ids=["4^4-haar", "6^3x10-ordered", "8x4x6x4-cold"])
+def test_su3_every_pass_matches_oracle(su2, o3, dims, spread, beta):
+    """All eight (mu, parity) passes from the same links; V/2 = 1080 for
+    6^3 x 10 spans four full workgroups and a ragged tail."""
+    announce(f"su3 per-pass parity dims={dims} spread={spread} beta={beta}")
+    links = inputs.random_su3_links(dims, 40 + sum(dims), spread=spread)
+    seed, sweep = 4242, 5
+    par_of = parities(dims)
+    V = int(np.prod(dims))
+    flagged, worst = 0, 0.0
+    with su2.Lattice3(dims, beta, seed) as lat:
+        lat.set_sweep(sweep)
+        lat.set_links(links)
+        for mu in range(4):
+            for p in range(2):
+                before = lat.get_links()
+                U = before.copy()
+                margin = np.zeros(V)
+                o3.pass_(dims, U, mu, p, sweep, beta, seed, margin=margin)
+                lat.test_pass(mu, p)
+                got = lat.get_links()
+                upd = par_of == p
+                ok = upd & (margin >= FLAG3)
+                flagged += int((upd & (margin < FLAG3)).sum())
+                err = np.abs(got[ok, mu] - U[ok, mu]).max()
+                worst = max(worst, err)
+                assert err < TOL3, (mu, p, err)
+                assert su3_defect(got[upd, mu]) < 5e-6
+                mask = np.ones(got.shape[:2], bool)
+                mask[upd, mu] = False
+                np.testing.assert_array_equal(got[mask], before[mask])
+    announce(f"  max |gpu - oracle| = {worst:.2e}, flagged {flagged} of {4 * V}")
+    assert flagged <= max_flags3(4 * V)
+
+
+def test_su3_sweeps_match_oracle_with_measurements(su2, o3):
+    """Three sweeps (reunitarisation after sweep 2) from the GPU's hot start:
+    per-sweep plaquette history (fused into the odd passes) and final links
+    against the oracle's sweeps from the same links; Polyakov loop and the
+    standalone plaquette on the final links."""
+    dims, beta, seed = [6, 4, 6, 8], 5.9, 31
+    announce(f"su3 sweeps dims={dims}")
+    with su2.Lattice3(dims, beta, seed, su2.SU2_HOT) as lat:
+        start = lat.get_links()
+        hist = lat.heatbath_sweep(3, reunit_every=2, history=True)
+        got = lat.get_links()
+        plaq = lat.plaquette()
+        poly = lat.polyakov()
+        assert lat.sweep == 3
+    U = start.copy()
+    ph, _ = o3.sweeps(dims, U, 3, 0, beta, seed, reunit_every=2, history=True)
+    assert np.allclose(hist, ph, atol=2e-6), (hist, ph)
+    diff = np.abs(got - U).reshape(-1, 9).max(axis=1)
+    assert np.mean(diff > TOL3) < 0.02, np.mean(diff > TOL3)
+    assert plaq == pytest.approx(o3.plaquette(dims, got), abs=1e-6)
+    want = o3.polyakov(dims, got)
+    assert np.allclose(poly, want, atol=2e-6), (poly, want)
+
+
+def test_su3_fused_plaquette_equals_standalone(su2):
+    dims = [8, 8, 8, 8]
+    announce("su3 fused vs standalone plaquette")
+    with su2.Lattice3(dims, 6.0, 5, su2.SU2_HOT) as lat:
+        h = lat.heatbath_sweep(4, history=True)
+        assert h[-1] == pytest.approx(lat.plaquette(), abs=1e-6)
+        assert np.all(np.diff(h) > 0)  # ordering from a hot start at beta = 6
+
+
+def test_su3_links_stay_unitary_without_reunitarisation(su2):
+    """Only rows 0 and 1 are stored and the subgroup rotations mix the rebuilt
+    row 2 back into them, so an unnormalised FP32 update would let deviations
+    from unitarity grow from sweep to sweep.  The pass re-orthonormalises every
+    link it stores: after 120 sweeps with no reunitarisation call the links are
+    unitary to FP32 rounding, and the thermalised plaquette agrees with that of
+    a run reunitarised after every sweep (the two chains separate after a few
+    sweeps, since reunitarisation moves links by FP32 rounding, so only their
+    means are compared)."""
+    dims = [8, 8, 8, 8]
+    announce("su3 stability without reunitarisation")
+    with su2.Lattice3(dims, 6.0, 3, su2.SU2_HOT) as lat:
+        h = lat.heatbath_sweep(120, reunit_every=0, history=True)
+        links = lat.get_links()
+    with su2.Lattice3(dims, 6.0, 3, su2.SU2_HOT) as lat:
+        r = lat.heatbath_sweep(120, reunit_every=1, history=True)
+    assert su3_defect(links) < 2e-6
+    assert abs(h[60:].mean() - r[60:].mean()) < 3e-3, (h[60:].mean(), r[60:].mean())
+    assert min(h[60:].mean(), r[60:].mean()) > 0.585
+
+
+def test_su3_reunitarize_matches_oracle(su2, o3):
+    dims = [4, 6, 4, 4]
+    announce("su3 reunitarisation")
+    rng = np.random.default_rng(12)
+    links = inputs.random_su3_links(dims, 12, spread=0.4)
+    links += 3e-3 * (rng.standard_normal(links.shape) + 1j * rng.standard_normal(links.shape))
+    with su2.Lattice3(dims, 6.0, 1) as lat:
+        lat.set_links(links)
+        stored = lat.get_links()  # rows 0, 1 rounded to FP32, row 2 rebuilt
+        lat.reunitarize()
+        got = lat.get_links()
+    want = stored.copy()
+    o3.reunitarize(dims, want)
+    assert np.abs(got - want).max() < 2e-6
+    assert su3_defect(got) < 2e-6
+
+
+@pytest.mark.parametrize("launch", [(64, 0, 0, 1, 1), (128, 1, 1, 2, 4), (192, 1, 0, 0, 0),
+                                    (256, 0, 1, 8, 8)])
+def test_su3_launch_shape_does_not_change_results(su2, launch):
+    """Every site's update reads only links the pass does not write, so the
+    traversal (block, remap, snake, tiles) cannot change any bit."""
+    dims = [8, 6, 8, 8]
+    announce(f"su3 launch {launch}")
+    with su2.Lattice3(dims, 5.8, 17, su2.SU2_HOT) as ref:
+        ref.heatbath_sweep(2)
+        want = ref.get_links()
+    with su2.Lattice3(dims, 5.8, 17, su2.SU2_HOT) as lat:
+        lat.set_launch(*launch)
+        lat.heatbath_sweep(2)
+        assert np.array_equal(lat.get_links(), want)
+
+
+def test_su3_ensemble_matches_oracle_chains(su2, o3):
+    """Mean plaquette at beta = 6.0 on 6^4 from 8 GPU chains against 4 oracle
+    chains (independent seeds, 100 thermalisation sweeps from cold, 200
+    measured sweeps, reunitarisation every 10); each side's error is the spread
+    of its chain means, which also covers slow modes a batch-means error
+    within one chain would miss."""
+    dims, beta, therm, nmeas = [6, 6, 6, 6], 6.0, 100, 200
+    announce("su3 ensemble vs oracle")
+    g = []
+    for r in range(8):
+        with su2.Lattice3(dims, beta, 600 + r, su2.SU2_COLD) as lat:
+            h = lat.heatbath_sweep(therm + nmeas, reunit_every=10, history=True)
+            g.append(h[therm:].mean())
+    o = []
+    for r in range(4):
+        U = o3.init(dims, 0, 0)
+        ph, _ = o3.sweeps(dims, U, therm + nmeas, 0, beta, 700 + r, reunit_every=10,
+                          nthreads=8, history=True)
+        o.append(ph[therm:].mean())
+    g, o = np.array(g), np.array(o)
+    dg, do = g.std(ddof=1) / np.sqrt(len(g)), o.std(ddof=1) / np.sqrt(len(o))
+    pull = (g.mean() - o.mean()) / np.hypot(dg, do)
+    announce(f"  gpu {g.mean():.5f}({dg:.5f}) oracle {o.mean():.5f}({do:.5f}) pull {pull:.2f}")
+    assert abs(pull) < 4
+
+
+def test_su3_full_size_pass_sampled_against_oracle(su2, o3):
+    """48^4 at beta = 6.0 (the benchmarked workload, default launch): after 3
+    sweeps from a hot start, one odd pass of mu = 2, then 3000 sampled updated
+    sites recomputed by the oracle from the pre-pass links."""
+    dims, beta, seed = [48, 48, 48, 48], 6.0, 2010
+    announce("su3 full-size 48^4 sampled pass")
+    with su2.Lattice3(dims, beta, seed, su2.SU2_HOT) as lat:
+        lat.heatbath_sweep(3, reunit_every=3)
+        sweep = lat.sweep
+        pre = lat.get_links()
+        lat.test_pass(2, 1)
+        post = lat.get_links()
+    par_of = parities(dims)
+    odd = np.nonzero(par_of == 1)[0]
+    rng = np.random.default_rng(1)
+    sites = rng.choice(odd, 3000, replace=False)
+    flagged, worst = 0, 0.0
+    for s in sites:
+        A = o3.staple(dims, pre, s, 2)
+        want, m = o3.heatbath_link(pre[s, 2], A, beta, seed, int(s), sweep, 2)
+        if m < FLAG3:
+            flagged += 1
+            continue
+        worst = max(worst, np.abs(post[s, 2] - want).max())
+    announce(f"  max |gpu - oracle| = {worst:.2e}, flagged {flagged}")
+    assert worst < TOL3
+    assert flagged <= max_flags3(3000)
+    assert np.array_equal(post[par_of == 0], pre[par_of == 0])
