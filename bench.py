@@ -49,6 +49,32 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+SU3_BYTES_PER_UPDATE = 432  # 9 links of 48 B: 8 read (7 neighbours' classes + the link), 1 written
+SU3_PROFILE = os.path.join(ROOT, "profiles", "su3_pass_kernel_48x48x48x48.md")
+
+
+def su3_source_hash():
+    h = hashlib.sha256()
+    for f in ("su2_device.h", "su2_kcommon.h", "su2_internal.h", "su3_internal.h",
+              "su3_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1010_1486_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profile_value(path, key, source_hash):
+    """A figure from a committed rocprofv3 summary, if it was taken on the
+    current kernel source (else None)."""
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    t = re.search(key + r":\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != source_hash:
+        return None
+    return float(t.group(1))
+
+
 def traffic_from_profile():
     """HBM bytes per pass launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source (else None)."""
@@ -327,7 +353,8 @@ def _replicas64():
     return [[l] * 4 for l in L], np.random.default_rng(5).uniform(1.8, 3.0, 64), 1
 
 
-COUNTER_WORKLOADS = ("headline", "beta16", "beta24", "polyakov", "replicas64", "replicas64_learned")
+COUNTER_WORKLOADS = ("headline", "beta16", "beta24", "polyakov", "replicas64", "replicas64_learned",
+                     "su3")
 
 
 def counters_run(su2, torch, dev, lat, name):
@@ -340,6 +367,13 @@ def counters_run(su2, torch, dev, lat, name):
         for i in range(16):
             lat.test_pass((i // 2) % 4, i % 2)
         torch.cuda.synchronize()
+        return {"pass_launches": 16, "updates_per_launch": int(np.prod(DIMS)) // 2}
+    if name == "su3":
+        with su2.Lattice3(DIMS, BETA, SEED, su2.SU2_HOT, device=dev) as l3:
+            l3.heatbath_sweep(2)
+            for i in range(16):
+                l3.test_pass((i // 2) % 4, i % 2)
+            l3.synchronize()
         return {"pass_launches": 16, "updates_per_launch": int(np.prod(DIMS)) // 2}
     dims, betas, starts = {"beta16": lambda: _beta_scan(16), "beta24": lambda: _beta_scan(24),
                            "polyakov": _polyakov_grid, "replicas64": _replicas64,
@@ -415,6 +449,78 @@ def fp64_run(su2, torch, dev, steps=100, launches=80):
                 "pass_algorithmic_gbs": gbs, "pass_hbm_frac": gbs / HBM_PEAK_GBS,
                 "mean_plaquette": float(hist.cpu().numpy()[:, 0].mean())})
     return out
+
+
+def su3_run(su2, torch, dev, steps=100, launches=80, with_cpu=True):
+    """SU(3) (Cabibbo-Marinari subgroups on the SU(2) sampler) on the 48^4
+    lattice at beta = 6.0 from a hot start: `steps` sweeps with the fused
+    plaquette and reunitarisation every 10 after 10 warm-up sweeps, and the
+    pass kernel's average launch over `launches` launches.  Algorithmic bytes
+    per update: 432 (nine 48-byte links: the updated link read and written,
+    the opposite-parity U_mu and U_nu, nu != mu, at both parities read).  The
+    ALU side of the roofline: VALU instructions per update from the committed
+    counter profile, against 256 CUs x 4 SIMDs issuing one 64-lane FP32 VALU
+    instruction per 4 cycles at 2.4 GHz (packed FP32 is not used)."""
+    V = int(np.prod(DIMS))
+    out = {"workload": "SU(3) 48^4, beta=6.0, hot start (Philox seed 3); step = 1 sweep "
+                       "(8 passes, 3 SU(2) subgroup heat-bath draws per link) + fused "
+                       "plaquette, reunitarise every 10"}
+    with su2.Lattice3(DIMS, BETA, SEED, su2.SU2_HOT, device=dev) as lat:
+        lat.heatbath_sweep(10, reunit_every=10, history=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = lat.heatbath_sweep(steps, reunit_every=10, history=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stream = lat.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(launches):
+            lat.test_pass((i // 2) % 4, i % 2)
+        e1.record(stream)
+        e1.synchronize()
+        pass_ms = e0.elapsed_time(e1) / launches
+        poly = lat.polyakov()
+    gbs = SU3_BYTES_PER_UPDATE * (V // 2) / (pass_ms * 1e-3) / 1e9
+    h_ = su3_source_hash()
+    traffic = profile_value(SU3_PROFILE, "hbm_bytes_per_launch", h_)
+    valu = profile_value(SU3_PROFILE, "valu_instructions_per_update", h_)
+    # one wave64 VALU instruction per SIMD per 4 cycles: 256 * 4 * 2.4e9 / 4 per s
+    valu_peak = 256 * 4 * 2.4e9 / 4 * 64  # lane-instructions per second
+    out.update({
+        "link_updates_per_s": 4 * V * steps / dt, "ms_per_sweep": 1e3 * dt / steps,
+        "pass_avg_launch_us": pass_ms * 1e3, "updates_per_launch": V // 2,
+        "mean_plaquette": float(np.mean(h)), "polyakov": poly,
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_update": SU3_BYTES_PER_UPDATE, "kernel": "su3_pass_kernel"},
+        "alu": None if valu is None else {
+            "bound": "alu", "valu_instructions_per_update": valu,
+            "achieved": valu * (V // 2) / (pass_ms * 1e-3), "peak": valu_peak,
+            "unit": "VALU lane-instructions/s",
+            "frac": valu * (V // 2) / (pass_ms * 1e-3) / valu_peak}})
+    if with_cpu:
+        out["cpu_baseline"] = su3_oracle_rate()
+    return out
+
+
+def su3_oracle_rate(L=24, beta=BETA):
+    """The FP64 SU(3) oracle as it stands: one sweep of an L^4 hot start on all
+    host threads, and one pass single-threaded (link updates per second)."""
+    from oracle import su2_oracle as o2, su3_oracle as o3
+    dims = [L] * 4
+    U = o3.init(dims, 1, SEED)
+    n = oracle_threads()
+    t0 = time.perf_counter()
+    o3.sweeps(dims, U, 1, 0, beta, SEED, nthreads=n)
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o3.pass_(dims, U, 0, 0, 1, beta, SEED, nthreads=1)
+    d1 = time.perf_counter() - t0
+    V = o2.volume(dims)
+    return {"value": 4 * V / dt, "unit": "link updates/s", "cores": n, "kind": "oracle",
+            "sample": f"one SU(3) sweep of a {L}^4 hot start at beta {beta} (4 x {V} updates)",
+            "single_thread_value": (V // 2) / d1}
 
 
 def creutz(W, R):
@@ -512,6 +618,7 @@ def main():
                     help="skip the batched plain-vs-learned comparison")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-link workload")
     ap.add_argument("--no-wilson", action="store_true", help="skip the Wilson-loop workload")
+    ap.add_argument("--no-su3", action="store_true", help="skip the SU(3) workload")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 4^4, beta-scan and Polyakov workloads")
     ap.add_argument("--counters", nargs="?", const="headline", default=None,
@@ -618,6 +725,9 @@ def main():
     if not args.no_fp64:
         print("[bench] FP64 links", file=sys.stderr, flush=True)
         out["fp64"] = fp64_run(su2, torch, dev)
+    if not args.no_su3:
+        print("[bench] SU(3) subgroup heat bath", file=sys.stderr, flush=True)
+        out["su3"] = su3_run(su2, torch, dev, with_cpu=not args.no_cpu_baseline)
     if not args.no_wilson:
         print("[bench] Wilson loops and Creutz ratios", file=sys.stderr, flush=True)
         out["scale_setting"] = scale_setting(su2, torch, dev)
