@@ -215,16 +215,21 @@ def test_su3_ensemble_matches_oracle_chains(su2, o3):
 
 def test_su3_full_size_pass_sampled_against_oracle(su2, o3):
     """48^4 at beta = 6.0 (the benchmarked workload, default launch): after 3
-    sweeps from a hot start, one odd pass of mu = 2, then 3000 sampled updated
-    sites recomputed by the oracle from the pre-pass links."""
+    sweeps from a hot start, the plaquette and Polyakov loop against FP64
+    recomputation from the same links, then one odd pass of mu = 2 and 3000
+    sampled updated sites recomputed by the oracle from the pre-pass links."""
     dims, beta, seed = [48, 48, 48, 48], 6.0, 2010
     announce("su3 full-size 48^4 sampled pass")
     with su2.Lattice3(dims, beta, seed, su2.SU2_HOT) as lat:
         lat.heatbath_sweep(3, reunit_every=3)
         sweep = lat.sweep
         pre = lat.get_links()
+        plaq, poly = lat.plaquette(), lat.polyakov()
         lat.test_pass(2, 1)
         post = lat.get_links()
+    # observables of the 48^4 field against FP64 recomputation from the same links
+    assert plaq == pytest.approx(o3.plaquette(dims, pre), abs=1e-7)
+    assert np.allclose(poly, o3.polyakov(dims, pre), atol=1e-7)
     par_of = parities(dims)
     odd = np.nonzero(par_of == 1)[0]
     rng = np.random.default_rng(1)
