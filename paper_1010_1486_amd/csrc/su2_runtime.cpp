@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -662,7 +663,7 @@ public:
     // Host layout [t][z][y][x][mu][c] in H (float or double) <-> the device
     // planes in the ensemble's precision.
     template <typename D, typename H>
-    void gather(int r, const std::vector<D> &planes, H *host) const
+    void gather(int r, const D *planes, H *host) const
     {
         const int32_t *d = dims[r].data();
         const int64_t V = volume_of(d), vh = V / 2;
@@ -682,7 +683,7 @@ public:
     }
 
     template <typename D, typename H>
-    void scatter(int r, const H *host, std::vector<D> &planes) const
+    void scatter(int r, const H *host, D *planes) const
     {
         const int32_t *d = dims[r].data();
         const int64_t V = volume_of(d), vh = V / 2;
@@ -704,22 +705,24 @@ public:
     template <typename D, typename H>
     int get_links_as(int r, H *host)
     {
-        std::vector<D> planes((size_t)volume_of(dims[r].data()) * 16);
-        HIP_TRY(hipMemcpyAsync(planes.data(), links[r], planes.size() * sizeof(D),
-                               hipMemcpyDeviceToHost, stream));
+        const size_t n = (size_t)volume_of(dims[r].data()) * 16;
+        std::unique_ptr<D[]> planes(new (std::nothrow) D[n]);
+        if (!planes) return fail(SU2_ENOMEM, "host staging buffer of " + std::to_string(n * sizeof(D)) + " B");
+        HIP_TRY(hipMemcpyAsync(planes.get(), links[r], n * sizeof(D), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         if (int rc = check_queue()) return rc;
-        gather(r, planes, host);
+        gather(r, planes.get(), host);
         return SU2_OK;
     }
 
     template <typename D, typename H>
     int set_links_as(int r, const H *host)
     {
-        std::vector<D> planes((size_t)volume_of(dims[r].data()) * 16);
-        scatter(r, host, planes);
-        HIP_TRY(hipMemcpyAsync(links[r], planes.data(), planes.size() * sizeof(D),
-                               hipMemcpyHostToDevice, stream));
+        const size_t n = (size_t)volume_of(dims[r].data()) * 16;
+        std::unique_ptr<D[]> planes(new (std::nothrow) D[n]);
+        if (!planes) return fail(SU2_ENOMEM, "host staging buffer of " + std::to_string(n * sizeof(D)) + " B");
+        scatter(r, host, planes.get());
+        HIP_TRY(hipMemcpyAsync(links[r], planes.get(), n * sizeof(D), hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         return SU2_OK;
     }

@@ -3,11 +3,12 @@
 // odd sites), the measurements and the host exchange of links.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
+#include <memory>
 #include <new>
 #include <string>
-#include <vector>
 
 #include "../../include/su3.h"
 #include "su3_internal.h"
@@ -212,9 +213,11 @@ int su3_get_links(su3_ctx *c, double *host)
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
     const int64_t V = volume3(c->dims), vh = V / 2;
-    std::vector<float> dev((size_t)V * 48u);
-    HIP_TRY(hipMemcpyAsync(dev.data(), c->L.links, dev.size() * sizeof(float),
-                           hipMemcpyDeviceToHost, c->stream));
+    const size_t n = (size_t)V * 48u;
+    std::unique_ptr<float[]> dev(new (std::nothrow) float[n]);
+    if (!dev) return fail(SU2_ENOMEM, "host staging buffer of " + std::to_string(4 * n) + " B");
+    HIP_TRY(hipMemcpyAsync(dev.get(), c->L.links, n * sizeof(float), hipMemcpyDeviceToHost,
+                           c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     typedef std::complex<double> cd;
     for (int64_t s = 0; s < V; ++s) {
@@ -249,7 +252,9 @@ int su3_set_links(su3_ctx *c, const double *host)
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
     const int64_t V = volume3(c->dims), vh = V / 2;
-    std::vector<float> dev((size_t)V * 48u);
+    const size_t n = (size_t)V * 48u;
+    std::unique_ptr<float[]> dev(new (std::nothrow) float[n]);
+    if (!dev) return fail(SU2_ENOMEM, "host staging buffer of " + std::to_string(4 * n) + " B");
     for (int64_t s = 0; s < V; ++s) {
         int x[4];
         coords(c->dims, s, x);
@@ -263,8 +268,8 @@ int su3_set_links(su3_ctx *c, const double *host)
                         (size_t)j] = (float)in[4 * k + j];
         }
     }
-    HIP_TRY(hipMemcpyAsync(c->L.links, dev.data(), dev.size() * sizeof(float),
-                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->L.links, dev.get(), n * sizeof(float), hipMemcpyHostToDevice,
+                           c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return SU2_OK;
 }
