@@ -246,3 +246,19 @@ def test_su3_full_size_pass_sampled_against_oracle(su2, o3):
     assert worst < TOL3
     assert flagged <= max_flags3(3000)
     assert np.array_equal(post[par_of == 0], pre[par_of == 0])
+
+
+def test_su3_argument_errors(su2):
+    """Bad arguments on a live context are refused with SU2_EINVAL before any
+    device work, and the context stays usable."""
+    announce("su3 argument errors")
+    with su2.Lattice3([4, 4, 4, 4], 6.0, 1, su2.SU2_COLD) as lat:
+        for call in (lambda: lat.set_launch(96), lambda: lat.set_launch(256, 1, 1, 3, 0),
+                     lambda: lat.test_pass(4, 0), lambda: lat.test_pass(0, 2),
+                     lambda: lat.heatbath_sweep(-1), lambda: lat.heatbath_sweep(1, -2),
+                     lambda: lat.set_beta(float("nan"))):
+            with pytest.raises(su2.SU2Error) as e:
+                call()
+            assert e.value.code == su2.SU2_EINVAL
+        lat.heatbath_sweep(1)
+        assert 0.0 < lat.plaquette() < 1.0
