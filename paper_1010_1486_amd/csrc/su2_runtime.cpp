@@ -17,6 +17,7 @@
 #include "../../include/su2.h"
 #include "su2_internal.h"
 #include "su3_internal.h"
+#include "su2_api.h"
 
 using su2dev::Geom;
 using su2dev::kNNRow;
@@ -27,6 +28,24 @@ namespace su2rt {
 static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
+
+int api_nomem() noexcept
+{
+    try {
+        g_last_error = "host allocation failed";
+    } catch (...) {
+    }
+    return SU2_ENOMEM;
+}
+
+int api_unexpected() noexcept
+{
+    try {
+        g_last_error = "unexpected host-side exception";
+    } catch (...) {
+    }
+    return SU2_EINVAL;
+}
 
 }  // namespace su2rt
 
@@ -1001,19 +1020,23 @@ const char *su2_last_error(void) { return g_last_error.c_str(); }
 
 size_t su2_links_bytes(const int32_t dims[4])
 {
+    SU2_API_BEGIN
     if (!dims) return 0;
     const std::string keep = g_last_error;  // a size query is not a failure
     const int rc = check_dims(dims);
     g_last_error = keep;
     if (rc) return 0;
     return (size_t)64 * (size_t)volume_of(dims);
+    SU2_API_END_SIZE
 }
 
 size_t su2_scratch_bytes(const int32_t dims[4])
 {
+    SU2_API_BEGIN
     if (!su2_links_bytes(dims)) return 0;
     std::vector<std::array<int32_t, 4>> d{{dims[0], dims[1], dims[2], dims[3]}};
     return Ensemble::scratch_need(1, d);
+    SU2_API_END_SIZE
 }
 
 static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed,
@@ -1078,119 +1101,148 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
 
 int su2_init(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start)
 {
+    SU2_API_BEGIN
     return init_common(out, dims, beta, seed, start, nullptr, 0, nullptr, 0, nullptr, false);
+    SU2_API_END
 }
 
 int su2_init_f64(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
                  void *hip_stream)
 {
+    SU2_API_BEGIN
     return init_common(out, dims, beta, seed, start, nullptr, 0, nullptr, 0, hip_stream, false,
                        true);
+    SU2_API_END
 }
 
 int su2_is_f64(su2_ctx *c, int *out)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     *out = c->E.f64 ? 1 : 0;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_get_links_f64(su2_ctx *c, double *host)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
     return c->E.get_links(0, host);
+    SU2_API_END
 }
 
 int su2_set_links_f64(su2_ctx *c, const double *host)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
     return c->E.set_links(0, host);
+    SU2_API_END
 }
 
 int su2_init_ext(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
                  void *links_dev, size_t links_bytes, void *scratch_dev, size_t scratch_bytes,
                  void *hip_stream)
 {
+    SU2_API_BEGIN
     return init_common(out, dims, beta, seed, start, links_dev, links_bytes, scratch_dev,
                        scratch_bytes, hip_stream, true);
+    SU2_API_END
 }
 
 int su2_destroy(su2_ctx *c)
 {
+    SU2_API_BEGIN
     if (!c) return fail(SU2_EINVAL, "context is NULL");
     c->E.release();
     delete c;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_heatbath_sweep(su2_ctx *c, int32_t nsweeps, int mode)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (nsweeps < 0) return fail(SU2_EINVAL, "nsweeps must be >= 0");
     return c->E.enqueue(nsweeps, mode, 0, 0, nullptr);
+    SU2_API_END
 }
 
 int su2_sweep_measure(su2_ctx *c, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
                       double *dev_history)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (nsweeps < 0 || reunit_every < 0) return fail(SU2_EINVAL, "negative count");
     if (!dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
     if (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)) return fail(SU2_EINVAL, "bad meas flags");
     return c->E.enqueue(nsweeps, mode, reunit_every, meas, dev_history);
+    SU2_API_END
 }
 
 int su2_capture_sweeps(su2_ctx *c, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
                        double *dev_history)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (reunit_every < 0 || (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)))
         return fail(SU2_EINVAL, "bad arguments");
     if (meas && !dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
     return c->E.capture(nsweeps, mode, reunit_every, meas, meas ? dev_history : nullptr);
+    SU2_API_END
 }
 
 int su2_replay_sweeps(su2_ctx *c, int32_t count)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     return c->E.replay(count);
+    SU2_API_END
 }
 
 int su2_reunitarize(su2_ctx *c)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     HIP_TRY(c->E.reunitarize_launch());
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_plaquette(su2_ctx *c, double *out)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     return c->E.observe(1, out, nullptr, nullptr);
+    SU2_API_END
 }
 
 int su2_polyakov(su2_ctx *c, double *out_signed, double *out_abs)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     return c->E.observe(2, nullptr, out_signed, out_abs);
+    SU2_API_END
 }
 
 int su2_wilson_loops(su2_ctx *c, int rmax, int tmax, double *out)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
@@ -1219,38 +1271,47 @@ int su2_wilson_loops(su2_ctx *c, int rmax, int tmax, double *out)
     for (int r = 0; r < rmax; ++r)
         for (int t = 0; t < tmax; ++t) out[r * tmax + t] = hs[r * kWilsonMax + t] / norm;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_get_links(su2_ctx *c, float *host)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
     return c->E.get_links(0, host);
+    SU2_API_END
 }
 
 int su2_set_links(su2_ctx *c, const float *host)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
     return c->E.set_links(0, host);
+    SU2_API_END
 }
 
 int su2_get_sweep(su2_ctx *c, uint32_t *out)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     *out = c->E.sweep;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_set_sweep(su2_ctx *c, uint32_t sweep)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     return c->E.set_sweep(sweep);
+    SU2_API_END
 }
 
 static int set_overrelax(Ensemble &E, double width)
@@ -1262,58 +1323,72 @@ static int set_overrelax(Ensemble &E, double width)
 
 int su2_set_overrelax(su2_ctx *c, double width)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     return set_overrelax(c->E, width);
+    SU2_API_END
 }
 
 int su2_batch_set_overrelax(su2_batch *b, double width)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     return set_overrelax(b->E, width);
+    SU2_API_END
 }
 
 int su2_set_beta(su2_ctx *c, double beta)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
     c->E.beta[0] = beta;
     return c->E.upload();
+    SU2_API_END
 }
 
 int su2_set_replica(su2_ctx *c, uint32_t replica)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (replica >= (1u << 26)) return fail(SU2_EINVAL, "replica id must be < 2^26");
     c->E.replica[0] = replica;
     return c->E.upload();
+    SU2_API_END
 }
 
 int su2_links_device(su2_ctx *c, void **links_dev, void **hip_stream)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (links_dev) *links_dev = c->E.links[0];
     if (hip_stream) *hip_stream = c->E.stream;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_synchronize(su2_ctx *c)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(c->E.stream));
     return c->E.check_queue();
+    SU2_API_END
 }
 
 int su2_set_launch(su2_ctx *c, int block, int flags, int tile_z, int tile_t, int grid_cap)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     return c->E.set_launch(block, flags, tile_z, tile_t, grid_cap);
+    SU2_API_END
 }
 
 static void get_launch(const Ensemble &E, int *block, int *flags, int *tile_z, int *tile_t,
@@ -1333,23 +1408,28 @@ static void get_launch(const Ensemble &E, int *block, int *flags, int *tile_z, i
 
 int su2_get_launch(su2_ctx *c, int *block, int *flags, int *tile_z, int *tile_t, int *grid_cap)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     get_launch(c->E, block, flags, tile_z, tile_t, grid_cap);
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_autotune(su2_ctx *c, const char *cache_path, int mode, double *best_us_per_sweep)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     return c->E.autotune(cache_path, mode, best_us_per_sweep);
+    SU2_API_END
 }
 
 /* ============================================================== batches */
 int su2_batch_init(su2_batch **out, int32_t n, const int32_t *dims, const double *betas,
                    const int *starts, uint64_t seed, void *hip_stream)
 {
+    SU2_API_BEGIN
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     *out = nullptr;
     if (n <= 0 || n > 65535 || !dims || !betas || !starts)
@@ -1401,124 +1481,153 @@ int su2_batch_init(su2_batch **out, int32_t n, const int32_t *dims, const double
     }
     *out = b;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_batch_destroy(su2_batch *b)
 {
+    SU2_API_BEGIN
     if (!b) return fail(SU2_EINVAL, "batch is NULL");
     b->E.release();
     delete b;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_batch_size(su2_batch *b, int32_t *n)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     if (!n) return fail(SU2_EINVAL, "n is NULL");
     *n = b->E.n;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_batch_sweep(su2_batch *b, int32_t nsweeps, int mode)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     if (nsweeps < 0) return fail(SU2_EINVAL, "nsweeps must be >= 0");
     return b->E.enqueue(nsweeps, mode, 0, 0, nullptr);
+    SU2_API_END
 }
 
 int su2_batch_sweep_measure(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_every,
                             int meas, double *dev_history)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     if (nsweeps < 0 || reunit_every < 0) return fail(SU2_EINVAL, "negative count");
     if (!dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
     if (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)) return fail(SU2_EINVAL, "bad meas flags");
     return b->E.enqueue(nsweeps, mode, reunit_every, meas, dev_history);
+    SU2_API_END
 }
 
 int su2_batch_capture(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
                       double *dev_history)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     if (reunit_every < 0 || (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)))
         return fail(SU2_EINVAL, "bad arguments");
     if (meas && !dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
     return b->E.capture(nsweeps, mode, reunit_every, meas, meas ? dev_history : nullptr);
+    SU2_API_END
 }
 
 int su2_batch_replay(su2_batch *b, int32_t count)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     return b->E.replay(count);
+    SU2_API_END
 }
 
 int su2_batch_observables(su2_batch *b, double *plaq, double *poly_signed, double *poly_abs)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     const int flags = (plaq ? 1 : 0) | ((poly_signed || poly_abs) ? 2 : 0);
     if (!flags) return SU2_OK;
     return b->E.observe(flags, plaq, poly_signed, poly_abs);
+    SU2_API_END
 }
 
 int su2_batch_get_links(su2_batch *b, int32_t r, float *host)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     if (r < 0 || r >= b->E.n || !host) return fail(SU2_EINVAL, "bad replica or NULL");
     return b->E.get_links(r, host);
+    SU2_API_END
 }
 
 int su2_batch_set_links(su2_batch *b, int32_t r, const float *host)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     if (r < 0 || r >= b->E.n || !host) return fail(SU2_EINVAL, "bad replica or NULL");
     return b->E.set_links(r, host);
+    SU2_API_END
 }
 
 int su2_batch_set_launch(su2_batch *b, int block, int flags, int tile_z, int tile_t,
                          int grid_cap)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     return b->E.set_launch(block, flags, tile_z, tile_t, grid_cap);
+    SU2_API_END
 }
 
 int su2_batch_get_launch(su2_batch *b, int *block, int *flags, int *tile_z, int *tile_t,
                          int *grid_cap)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     get_launch(b->E, block, flags, tile_z, tile_t, grid_cap);
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_batch_autotune(su2_batch *b, const char *cache_path, int mode, double *best_us)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     return b->E.autotune(cache_path, mode, best_us);
+    SU2_API_END
 }
 
 int su2_batch_synchronize(su2_batch *b)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(b->E.stream));
     return b->E.check_queue();
+    SU2_API_END
 }
 
 int su2_batch_get_accept_stats(su2_batch *b, uint64_t *proposed, uint64_t *accepted, int reset)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     return b->E.counts(reset, proposed, accepted);
+    SU2_API_END
 }
 
 /* ================================================================ tests */
@@ -1526,6 +1635,7 @@ int su2_test_queue_plan(int32_t n, const int32_t *dims, int block, int32_t queue
                         int32_t nsweeps, int32_t reunit_every, uint32_t first_sweep, int meas,
                         int rows, int64_t *items_out)
 {
+    SU2_API_BEGIN
     if (n < 1 || !dims || nsweeps < 1 || reunit_every < 0 || (block % 64) || block < 64 ||
         block > 256 || queues < 1 || queues > kMaxQueues)
         return fail(SU2_EINVAL, "bad arguments");
@@ -1609,18 +1719,22 @@ int su2_test_queue_plan(int32_t n, const int32_t *dims, int block, int32_t queue
             return fail(SU2_ERANGE, "replica " + std::to_string(r) + " did not finish");
     if (items_out) *items_out = items;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_test_batch_spin_limit(su2_batch *b, uint32_t polls)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     b->E.spin_limit = polls;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_test_philox(const uint32_t *ctr_host, int64_t n, uint64_t seed, uint32_t *out_host)
 {
+    SU2_API_BEGIN
     if (n < 0 || (n > 0 && (!ctr_host || !out_host))) return fail(SU2_EINVAL, "bad arguments");
     if (n == 0) return SU2_OK;
     void *d_in = nullptr, *d_out = nullptr;
@@ -1635,12 +1749,14 @@ int su2_test_philox(const uint32_t *ctr_host, int64_t n, uint64_t seed, uint32_t
     if (d_out) (void)hipFree(d_out);
     if (e != hipSuccess) return fail(SU2_EHIP, std::string("test_philox: ") + hipGetErrorString(e));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_t seed,
                             uint32_t sweep, uint32_t mu, uint32_t replica, float *out_host,
                             int32_t *ntrials_host)
 {
+    SU2_API_BEGIN
     if (n < 0 || (n > 0 && (!V_host || !out_host))) return fail(SU2_EINVAL, "bad arguments");
     if (!std::isfinite(beta) || mu > 3 || replica >= (1u << 26))
         return fail(SU2_EINVAL, "bad beta, mu or replica");
@@ -1664,10 +1780,12 @@ int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_
     if (e != hipSuccess)
         return fail(SU2_EHIP, std::string("test_heatbath_links: ") + hipGetErrorString(e));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_test_pass(su2_ctx *c, int mu, int parity, int mode)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1) return fail(SU2_EINVAL, "bad mu/parity");
@@ -1677,10 +1795,12 @@ int su2_test_pass(su2_ctx *c, int mu, int parity, int mode)
                      : launch_pass(c->E.ens(), mu, parity, c->E.seed, false, tab, c->E.cfg,
                                    c->E.stream));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_test_stream_pass(su2_ctx *c, int mu, int parity, void *out_dev)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1 || !out_dev)
@@ -1688,10 +1808,12 @@ int su2_test_stream_pass(su2_ctx *c, int mu, int parity, void *out_dev)
     if (c->E.f64) return fail(SU2_ESTATE, "the streaming floor kernel covers FP32 links");
     HIP_TRY(launch_test_stream(c->E.ens(), mu, parity, static_cast<float *>(out_dev), c->E.stream));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_test_index_map(const int32_t dims[4], int tile_z, int tile_t, int parity, uint32_t *out)
 {
+    SU2_API_BEGIN
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!out || (parity != 0 && parity != 1)) return fail(SU2_EINVAL, "bad arguments");
@@ -1713,10 +1835,12 @@ int su2_test_index_map(const int32_t dims[4], int tile_z, int tile_t, int parity
         }
     }
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_test_gauge_transform(su2_ctx *c, uint64_t seed)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (c->E.f64) return fail(SU2_ESTATE, "the gauge transformation covers FP32 links");
@@ -1727,6 +1851,7 @@ int su2_test_gauge_transform(su2_ctx *c, uint64_t seed)
     (void)hipFree(G);
     if (e != hipSuccess) return fail(SU2_EHIP, std::string("gauge: ") + hipGetErrorString(e));
     return SU2_OK;
+    SU2_API_END
 }
 
 /* ===================================================== learned proposal */
@@ -1776,6 +1901,7 @@ int su2_nn_num_params(void) { return kNNParams; }
 
 int su2_nn_create(su2_nn **out, const float *params_host, uint64_t seed, void *hip_stream)
 {
+    SU2_API_BEGIN
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     *out = nullptr;
     su2_nn *n = new (std::nothrow) su2_nn();
@@ -1803,32 +1929,39 @@ int su2_nn_create(su2_nn **out, const float *params_host, uint64_t seed, void *h
     }
     *out = n;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_nn_destroy(su2_nn *n)
 {
+    SU2_API_BEGIN
     if (!n) return fail(SU2_EINVAL, "nn is NULL");
     (void)hipStreamSynchronize(n->stream);
     nn_free(n);
     delete n;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_nn_get_params(su2_nn *n, float *host)
 {
+    SU2_API_BEGIN
     if (!n || !host) return fail(SU2_EINVAL, "NULL argument");
     HIP_TRY(hipStreamSynchronize(n->stream));
     HIP_TRY(hipMemcpy(host, n->b.params, kNNParams * sizeof(float), hipMemcpyDeviceToHost));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_nn_set_params(su2_nn *n, const float *host)
 {
+    SU2_API_BEGIN
     if (!n || !host) return fail(SU2_EINVAL, "NULL argument");
     HIP_TRY(hipStreamSynchronize(n->stream));
     HIP_TRY(hipMemcpy(n->b.params, host, kNNParams * sizeof(float), hipMemcpyHostToDevice));
     n->table_ready = false;
     return SU2_OK;
+    SU2_API_END
 }
 
 static int nn_reserve_data(su2_nn *n, int64_t count)
@@ -1846,6 +1979,7 @@ static int nn_reserve_data(su2_nn *n, int64_t count)
 
 int su2_nn_sample_data(su2_nn *n, int64_t count, double alpha_lo, double alpha_hi, uint64_t seed)
 {
+    SU2_API_BEGIN
     if (!n) return fail(SU2_EINVAL, "nn is NULL");
     if (count <= 0 || count >= ((int64_t)1 << 32)) return fail(SU2_EINVAL, "count out of range");
     if (!(alpha_lo > 0.0) || !(alpha_hi > alpha_lo) || !std::isfinite(alpha_hi))
@@ -1856,20 +1990,24 @@ int su2_nn_sample_data(su2_nn *n, int64_t count, double alpha_lo, double alpha_h
                            n->stream));
     HIP_TRY(hipStreamSynchronize(n->stream));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_nn_set_data(su2_nn *n, int64_t count, const float *alpha_host, const float *a0_host)
 {
+    SU2_API_BEGIN
     if (!n || !alpha_host || !a0_host || count <= 0) return fail(SU2_EINVAL, "bad arguments");
     int rc = nn_reserve_data(n, count);
     if (rc) return rc;
     HIP_TRY(hipMemcpy(n->b.alpha, alpha_host, count * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(n->b.a0, a0_host, count * sizeof(float), hipMemcpyHostToDevice));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_nn_get_data(su2_nn *n, int64_t *count, float *alpha_host, float *a0_host)
 {
+    SU2_API_BEGIN
     if (!n || !count) return fail(SU2_EINVAL, "bad arguments");
     *count = n->ndata;
     HIP_TRY(hipStreamSynchronize(n->stream));
@@ -1878,6 +2016,7 @@ int su2_nn_get_data(su2_nn *n, int64_t *count, float *alpha_host, float *a0_host
     if (a0_host && n->ndata)
         HIP_TRY(hipMemcpy(a0_host, n->b.a0, n->ndata * sizeof(float), hipMemcpyDeviceToHost));
     return SU2_OK;
+    SU2_API_END
 }
 
 static int nn_reserve_act(su2_nn *n, int batch)
@@ -1896,6 +2035,7 @@ static int nn_reserve_act(su2_nn *n, int batch)
 
 int su2_nn_loss_grad(su2_nn *n, int64_t offset, int32_t batch, double *loss, float *grad_host)
 {
+    SU2_API_BEGIN
     if (!n || batch <= 0 || offset < 0) return fail(SU2_EINVAL, "bad arguments");
     if (!n->ndata) return fail(SU2_ESTATE, "no training data");
     int rc = nn_reserve_act(n, batch);
@@ -1912,6 +2052,7 @@ int su2_nn_loss_grad(su2_nn *n, int64_t offset, int32_t batch, double *loss, flo
     if (grad_host)
         HIP_TRY(hipMemcpy(grad_host, n->b.grad, kNNParams * sizeof(float), hipMemcpyDeviceToHost));
     return SU2_OK;
+    SU2_API_END
 }
 
 // Learning rate of Adam step t of `steps`: constant lr0, or a cosine from
@@ -1962,61 +2103,75 @@ static int nn_train_steps(su2_nn *n, int32_t steps, int32_t batch, const LRSched
 
 int su2_nn_train(su2_nn *n, int32_t steps, int32_t batch, double lr, double *loss_history_host)
 {
+    SU2_API_BEGIN
     if (!n || steps < 0 || batch <= 0 || !(lr > 0.0)) return fail(SU2_EINVAL, "bad arguments");
     return nn_train_steps(n, steps, batch, LRSchedule{lr, lr, steps, false}, loss_history_host);
+    SU2_API_END
 }
 
 int su2_nn_train_cosine(su2_nn *n, int32_t steps, int32_t batch, double lr0, double lr1,
                         double *loss_history_host)
 {
+    SU2_API_BEGIN
     if (!n || steps < 0 || batch <= 0 || !(lr0 > 0.0) || !(lr1 > 0.0))
         return fail(SU2_EINVAL, "bad arguments");
     return nn_train_steps(n, steps, batch, LRSchedule{lr0, lr1, steps, true}, loss_history_host);
+    SU2_API_END
 }
 
 int su2_nn_build_table(su2_nn *n)
 {
+    SU2_API_BEGIN
     if (!n) return fail(SU2_EINVAL, "nn is NULL");
     HIP_TRY(launch_nn_table(n->b.params, n->b.table, n->stream));
     HIP_TRY(hipStreamSynchronize(n->stream));
     n->table_ready = true;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_nn_get_table(su2_nn *n, float *host)
 {
+    SU2_API_BEGIN
     if (!n || !host) return fail(SU2_EINVAL, "NULL argument");
     if (!n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
     HIP_TRY(hipMemcpy(host, n->b.table, (size_t)kNNRows * kNNRow * sizeof(float),
                       hipMemcpyDeviceToHost));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_set_proposal(su2_ctx *c, su2_nn *n)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     if (n && !n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
     c->E.drop_graph();
     c->E.table = n ? n->b.table : nullptr;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_batch_set_proposal(su2_batch *b, su2_nn *n)
 {
+    SU2_API_BEGIN
     int rc = check_batch(b);
     if (rc) return rc;
     if (n && !n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
     b->E.drop_graph();
     b->E.table = n ? n->b.table : nullptr;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su2_get_accept_stats(su2_ctx *c, uint64_t *proposed, uint64_t *accepted, int reset)
 {
+    SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
     return c->E.counts(reset, proposed, accepted);
+    SU2_API_END
 }
 
 int su2_test_learned_links(su2_nn *n, const float *V_host, const float *Uold_host, int64_t count,
@@ -2024,6 +2179,7 @@ int su2_test_learned_links(su2_nn *n, const float *V_host, const float *Uold_hos
                            uint32_t replica, double or_width, float *out_host,
                            int32_t *accepted_host)
 {
+    SU2_API_BEGIN
     if (!n || count < 0 || (count > 0 && (!V_host || !Uold_host || !out_host)))
         return fail(SU2_EINVAL, "bad arguments");
     if (!(or_width <= 1.0)) return fail(SU2_EINVAL, "or_width must be <= 1 (< 0: off)");
@@ -2051,6 +2207,7 @@ int su2_test_learned_links(su2_nn *n, const float *V_host, const float *Uold_hos
         if (p) (void)hipFree(p);
     if (e != hipSuccess) return fail(SU2_EHIP, std::string("test_learned: ") + hipGetErrorString(e));
     return SU2_OK;
+    SU2_API_END
 }
 
 }  // extern "C"

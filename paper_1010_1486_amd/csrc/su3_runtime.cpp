@@ -12,6 +12,7 @@
 
 #include "../../include/su3.h"
 #include "su3_internal.h"
+#include "su2_api.h"
 
 using namespace su2rt;
 using namespace su3rt;
@@ -89,17 +90,20 @@ extern "C" {
 
 size_t su3_links_bytes(const int32_t dims[4])
 {
+    SU2_API_BEGIN
     if (!dims) return 0;
     const std::string keep = su2_last_error();  // a size query is not a failure
     const int rc = check_dims(dims);
     set_error(keep);
     if (rc) return 0;
     return (size_t)volume3(dims) * 192u;
+    SU2_API_END_SIZE
 }
 
 int su3_init(su3_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
              void *hip_stream)
 {
+    SU2_API_BEGIN
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     *out = nullptr;
     int rc = check_dims(dims);
@@ -139,20 +143,24 @@ int su3_init(su3_ctx **out, const int32_t dims[4], double beta, uint64_t seed, i
     }
     *out = c;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_destroy(su3_ctx *c)
 {
+    SU2_API_BEGIN
     if (!c) return fail(SU2_EINVAL, "context is NULL");
     (void)hipStreamSynchronize(c->stream);
     if (c->links_mem) (void)hipFree(c->links_mem);
     if (c->scratch_mem) (void)hipFree(c->scratch_mem);
     delete c;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_heatbath_sweep(su3_ctx *c, int32_t nsweeps, int32_t reunit_every, double *plaq_hist)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (nsweeps < 0 || reunit_every < 0)
@@ -179,36 +187,44 @@ int su3_heatbath_sweep(su3_ctx *c, int32_t nsweeps, int32_t reunit_every, double
         done += chunk;
     }
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_reunitarize(su3_ctx *c)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     HIP_TRY(launch_su3_reunit(c->L, c->stream));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_plaquette(su3_ctx *c, double *out)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     HIP_TRY(launch_su3_plaquette(c->L, c->stream));
     return finish_to_host(c, 1, R3_PLAQ, 1, out);
+    SU2_API_END
 }
 
 int su3_polyakov(su3_ctx *c, double *out)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     HIP_TRY(launch_su3_polyakov(c->L, c->stream));
     return finish_to_host(c, 2, R3_POLY_RE, 3, out);
+    SU2_API_END
 }
 
 int su3_get_links(su3_ctx *c, double *host)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
@@ -244,10 +260,12 @@ int su3_get_links(su3_ctx *c, double *host)
         }
     }
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_set_links(su3_ctx *c, const double *host)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (!host) return fail(SU2_EINVAL, "host is NULL");
@@ -272,36 +290,44 @@ int su3_set_links(su3_ctx *c, const double *host)
                            c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_get_sweep(su3_ctx *c, uint32_t *out)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     *out = c->sweep;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_set_sweep(su3_ctx *c, uint32_t sweep)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     c->sweep = sweep;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_set_beta(su3_ctx *c, double beta)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
     c->L.beta = (float)beta;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_set_launch(su3_ctx *c, int block, int remap, int snake, int tile_z, int tile_t)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (block != 64 && block != 128 && block != 192 && block != 256)
@@ -318,33 +344,40 @@ int su3_set_launch(su3_ctx *c, int block, int remap, int snake, int tile_z, int 
     c->lg_tt = lt;
     c->L.g = g;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_links_device(su3_ctx *c, void **links_dev, void **hip_stream)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (links_dev) *links_dev = c->L.links;
     if (hip_stream) *hip_stream = c->stream;
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_synchronize(su3_ctx *c)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream));
     return SU2_OK;
+    SU2_API_END
 }
 
 int su3_test_pass(su3_ctx *c, int mu, int parity)
 {
+    SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1)
         return fail(SU2_EINVAL, "mu must be 0..3 and parity 0..1");
     HIP_TRY(launch_su3_pass(c->L, mu, parity, c->sweep, c->seed, false, c->cfg, c->stream));
     return SU2_OK;
+    SU2_API_END
 }
 
 }  // extern "C"

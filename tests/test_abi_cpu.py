@@ -165,3 +165,24 @@ def test_su3_sizes_and_bad_arguments():
                  lambda: lib.su3_heatbath_sweep(None, 1, 0, None),
                  lambda: lib.su3_test_pass(None, 0, 0), lambda: lib.su3_synchronize(None)):
         assert call() == su2.SU2_EINVAL
+
+
+def test_no_exception_leaves_the_c_abi():
+    """Every extern "C" entry point defined in the runtime sources runs its body
+    inside the exception barrier (SU2_API_BEGIN ... SU2_API_END), so host-side
+    allocation failures come back as SU2_ENOMEM, never as an exception."""
+    import os
+    import re
+    csrc = os.path.join(os.path.dirname(su2.__file__), "csrc")
+    seen = 0
+    for f in ("su2_runtime.cpp", "su3_runtime.cpp"):
+        lines = open(os.path.join(csrc, f)).read().split("\n")
+        for i, l in enumerate(lines):
+            if re.match(r"^(int|size_t) (su2_|su3_)\w+\(", l):
+                j = lines.index("{", i)
+                k = lines.index("}", j)
+                assert lines[j + 1].strip() == "SU2_API_BEGIN", (f, l)
+                assert lines[k - 1].strip().startswith("SU2_API_END"), (f, l)
+                seen += 1
+    exported = set(su2.header_functions()) | set(su2.header_functions3())
+    assert seen >= len(exported) - 1  # su2_last_error only reads a string
