@@ -504,6 +504,38 @@ def su3_run(su2, torch, dev, steps=100, launches=80, with_cpu=True):
     return out
 
 
+SU3_SCAN_BETAS = [round(5.40 + 0.05 * i, 2) for i in range(13)]
+
+
+def su3_polyakov_scan(su2, torch, dev, dims=(16, 16, 16, 4), therm=300, nmeas=300, every=2):
+    """The SU(3) counterpart of the Polyakov-loop scan: 16^3 x 4 from a cold
+    start at 13 couplings 5.40..6.00, `therm` sweeps, then the Polyakov loop
+    (and the fused plaquette) every `every` sweeps for `nmeas` measurements.
+    beta_c is where <|L|> rises most (the same estimator as for SU(2))."""
+    rows = []
+    t0 = time.perf_counter()
+    for i, b in enumerate(SU3_SCAN_BETAS):
+        with su2.Lattice3(list(dims), b, 9000 + i, su2.SU2_COLD, device=dev) as lat:
+            lat.heatbath_sweep(therm, reunit_every=10)
+            absL, plaq = [], []
+            for _ in range(nmeas):
+                h = lat.heatbath_sweep(every, reunit_every=10, history=True)
+                plaq.append(h[-1])
+                absL.append(abs(complex(*lat.polyakov()[:2])))
+        rows.append({"beta": b, "mean_abs_polyakov": float(np.mean(absL)),
+                     "err_abs_polyakov": float(np.std(absL, ddof=1) * np.sqrt(2 * tau_int(absL)
+                                                                                / len(absL))),
+                     "mean_plaquette": float(np.mean(plaq))})
+    dt = time.perf_counter() - t0
+    absl = [r["mean_abs_polyakov"] for r in rows]
+    V = int(np.prod(dims))
+    return {"workload": f"SU(3) {dims[0]}^3 x {dims[3]}, cold start, {len(SU3_SCAN_BETAS)} couplings "
+                        f"{SU3_SCAN_BETAS[0]}..{SU3_SCAN_BETAS[-1]}, {therm} + {nmeas} x {every} "
+                        "sweeps, |mean Polyakov loop| every measurement",
+            "by_beta": rows, "beta_c": beta_c(SU3_SCAN_BETAS, absl),
+            "link_updates_per_s": 4 * V * len(SU3_SCAN_BETAS) * (therm + nmeas * every) / dt}
+
+
 def su3_oracle_rate(L=24, beta=BETA):
     """The FP64 SU(3) oracle as it stands: one sweep of an L^4 hot start on all
     host threads, and one pass single-threaded (link updates per second)."""
@@ -728,6 +760,7 @@ def main():
     if not args.no_su3:
         print("[bench] SU(3) subgroup heat bath", file=sys.stderr, flush=True)
         out["su3"] = su3_run(su2, torch, dev, with_cpu=not args.no_cpu_baseline)
+        out["su3"]["polyakov_scan_nt4"] = su3_polyakov_scan(su2, torch, dev)
     if not args.no_wilson:
         print("[bench] Wilson loops and Creutz ratios", file=sys.stderr, flush=True)
         out["scale_setting"] = scale_setting(su2, torch, dev)

@@ -262,3 +262,25 @@ def test_su3_argument_errors(su2):
             assert e.value.code == su2.SU2_EINVAL
         lat.heatbath_sweep(1)
         assert 0.0 < lat.plaquette() < 1.0
+
+
+def test_su3_deconfinement_at_nt4(su2):
+    """Physics beyond the oracle comparison: on 12^3 x 4 the centre symmetry is
+    restored below the deconfinement coupling (beta_c = 5.69 for N_t = 4) and
+    broken above it, so <|mean Polyakov loop|> is several times larger at
+    beta = 5.9 than at beta = 5.5 (it falls like 1/sqrt(N_s^3) in the confined
+    phase)."""
+    announce("su3 deconfinement 12^3 x 4")
+    absL = {}
+    for b in (5.5, 5.9):
+        with su2.Lattice3([12, 12, 12, 4], b, 77, su2.SU2_COLD) as lat:
+            lat.heatbath_sweep(200, reunit_every=10)
+            v = []
+            for _ in range(100):
+                lat.heatbath_sweep(2, reunit_every=10)
+                re, im, _ = lat.polyakov()
+                v.append(abs(complex(re, im)))
+            absL[b] = float(np.mean(v))
+    announce(f"  <|L|> beta 5.5: {absL[5.5]:.4f}, beta 5.9: {absL[5.9]:.4f}")
+    assert absL[5.9] > 4 * absL[5.5]
+    assert absL[5.5] < 0.1
