@@ -116,15 +116,20 @@ def test_autotune_preserves_state_and_caches(su2, tmp_path):
 
 
 def test_batch_observables_match_oracle(su2, orc):
+    """Per-replica plaquette and Polyakov loop of seeded configurations (one
+    per replica, given to both sides) against the oracle."""
     announce("batch observables vs oracle")
+    links = [inputs.random_links(d, 300 + r, spread=0.6) for r, d in enumerate(DIMS)]
     with su2.Batch(DIMS, BETAS, STARTS, 8) as b:
         b.sweep(3)
+        for r in range(len(DIMS)):
+            b.set_links(r, links[r])
         p, ls, la = b.observables()
-        for r, d in enumerate(DIMS):
-            U = b.get_links(r).astype(np.float64)
-            assert abs(p[r] - orc.plaquette(d, U)) < 1e-6
-            wl, wa = orc.polyakov(d, U)
-            assert abs(ls[r] - wl) < 1e-6 and abs(la[r] - wa) < 1e-6
+    for r, d in enumerate(DIMS):
+        U = links[r].astype(np.float64)
+        assert abs(p[r] - orc.plaquette(d, U)) < 1e-6
+        wl, wa = orc.polyakov(d, U)
+        assert abs(ls[r] - wl) < 1e-6 and abs(la[r] - wa) < 1e-6
 
 
 def test_batch_learned_matches_single(su2):

@@ -39,12 +39,12 @@ def test_f64_every_pass_matches_oracle(su2, orc, dims):
     par_of = parities(orc, dims)
     with su2.Lattice64(dims, beta, seed) as lat:
         lat.set_sweep(4)
-        lat.set_links(links)
         flagged = 0
         for mu in range(4):
             for p in range(2):
-                before = lat.get_links()
-                U = before.copy()
+                lat.set_links(links)
+                before = links
+                U = links.copy()
                 margin = orc.do_pass(dims, U, mu, p, 4, beta, seed, want_margin=True)
                 lat.test_pass(mu, p)
                 got = lat.get_links()
@@ -86,7 +86,7 @@ def test_f64_sweeps_and_measurements_match_oracle(su2, orc):
 
 def test_f32_against_f64_at_equal_seeds(su2, orc):
     """24^4, beta 2.0, the same FP64 hot start in both precisions.  Pass by
-    pass from identical inputs (the FP32 lattice gets the FP64 links rounded)
+    pass from a seeded configuration (the FP32 lattice gets it rounded)
     the FP32 links differ from the FP64 ones by FP32 rounding, decisions the
     oracle places within 2e-5 of their threshold excluded.  Over one whole
     sweep without resynchronisation a flipped decision also changes the
@@ -108,16 +108,16 @@ def test_f32_against_f64_at_equal_seeds(su2, orc):
         (s64, a64), (s32, a32) = l64.polyakov(), l32.polyakov()
         dl = np.abs(g32 - g64).max(axis=-1)
         big = float(np.mean(dl > 1e-4))
-        # pass by pass, resynchronised
-        l64.set_links(start)
+        # pass by pass from a seeded configuration given to both precisions and the oracle
+        links = inputs.as_f64(inputs.random_links(dims, 91, spread=0.8))
         l64.set_sweep(0)
         l32.set_sweep(0)
         worst, nflag = 0.0, 0
         for mu in range(4):
             for p in range(2):
-                U = l64.get_links()
-                l32.set_links(U.astype(np.float32))
-                W = U.copy()
+                l64.set_links(links)
+                l32.set_links(links.astype(np.float32))
+                W = links.copy()
                 margin = orc.do_pass(dims, W, mu, p, 0, beta, seed, want_margin=True)
                 l64.test_pass(mu, p)
                 l32.test_pass(mu, p)

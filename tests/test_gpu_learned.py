@@ -98,12 +98,12 @@ def test_learned_pass_matches_oracle(su2, orc, dims, width):
         net.build_table()
         lat.set_proposal(net)
         lat.set_overrelax(width)
-        lat.set_links(links)
         lat.set_sweep(5)
         total_flag = 0
         for mu in range(4):
             for par in range(2):
-                U = lat.get_links().astype(np.float64)
+                lat.set_links(links)
+                U = links.astype(np.float64)
                 margin, acc = orc.learned_pass(dims, U, table, mu, par, 5, beta, seed,
                                                or_width=width)
                 lat.test_pass(mu, par, su2.SU2_LEARNED)

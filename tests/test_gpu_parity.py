@@ -1,5 +1,9 @@
 """GPU heat bath vs the FP64 CPU oracle from identical inputs (through the C ABI).
 
+Inputs reach the oracle only from the seeded generators (tests/inputs.py) or the
+oracle's own hot start; the GPU's links are only ever compared, never fed to
+the oracle.
+
 Link-level parity holds because both sides draw the same Philox streams and
 follow the same sampler; FP32-vs-FP64 can flip only decisions whose margin is
 below the flag threshold, which are excluded and counted (expected ~1e-6 per
@@ -47,18 +51,19 @@ def test_single_link_updates(su2, orc):
 
 @pytest.mark.parametrize("dims", DIMS, ids=lambda d: "x".join(map(str, d)))
 def test_every_pass_matches_oracle(su2, orc, dims):
+    """Each of the eight (mu, parity) passes from the same seeded links on
+    both sides."""
     announce(f"per-pass parity dims={dims}")
     links = inputs.random_links(dims, 10 + sum(dims), spread=0.6)
     beta, seed = 2.4, 12345
     par_of = parities(orc, dims)
     with su2.Lattice(dims, beta, seed) as lat:
         lat.set_sweep(3)
-        lat.set_links(links)
         total_flag = 0
         for mu in range(4):
             for p in range(2):
-                before = lat.get_links()
-                U = before.astype(np.float64)
+                lat.set_links(links)
+                U = links.astype(np.float64)
                 margin = orc.do_pass(dims, U, mu, p, 3, beta, seed, want_margin=True)
                 lat.test_pass(mu, p)
                 got = lat.get_links()
@@ -68,24 +73,28 @@ def test_every_pass_matches_oracle(su2, orc, dims):
                 # everything else untouched, bit for bit
                 mask = np.ones(got.shape[:2], bool)
                 mask[par_of == p, mu] = False
-                np.testing.assert_array_equal(got[mask], before[mask])
+                np.testing.assert_array_equal(got[mask], links[mask])
         assert total_flag <= max_flags(4 * int(np.prod(dims)))
 
 
 @pytest.mark.parametrize("dims", [[4, 4, 4, 4], [4, 6, 2, 8]], ids=lambda d: "x".join(map(str, d)))
 def test_hot_start_and_sweeps_match_oracle(su2, orc, dims):
-    """Config-1 style: hot start (Philox seed 1), beta 2.3, sweeps compared one
-    at a time from the GPU's own links (resynchronised each sweep)."""
+    """Config-1 style: the hot start (Philox seed 1) against the oracle's; then
+    twelve whole sweeps at beta 2.3, sweep index sw, each from a fresh seeded
+    configuration given to both sides (the eight passes of a sweep chain on
+    each side independently)."""
     announce(f"hot start + sweeps dims={dims}")
     beta, seed = 2.3, 1
     with su2.Lattice(dims, beta, seed, su2.SU2_HOT) as lat:
-        start = lat.get_links()
-        np.testing.assert_allclose(start, orc.init(dims, 1, seed), atol=2e-6, rtol=0)
+        np.testing.assert_allclose(lat.get_links(), orc.init(dims, 1, seed), atol=2e-6, rtol=0)
         skipped = 0
         for sw in range(12):
-            U = lat.get_links().astype(np.float64)
+            links = inputs.random_links(dims, 500 + sw)
+            U = links.astype(np.float64)
             margins = [orc.do_pass(dims, U, mu, p, sw, beta, seed, want_margin=True)
                        for mu in range(4) for p in range(2)]
+            lat.set_links(links)
+            lat.set_sweep(sw)
             lat.heatbath_sweep(1)
             got = lat.get_links()
             if min(np.min(m) for m in margins) < MARGIN_FLAG:
@@ -97,21 +106,36 @@ def test_hot_start_and_sweeps_match_oracle(su2, orc, dims):
 
 
 def test_plaquette_history_config1(su2, orc):
-    """4^4, hot start seed 1, beta 2.3: per-sweep plaquette history (fused into
-    the sweep) against the oracle's, sweep by sweep from identical links."""
+    """4^4, hot start seed 1, beta 2.3: the GPU's and the oracle's trajectories
+    from their own hot starts (the same Philox recipe), run side by side for 20
+    sweeps with the plaquette and Polyakov loop measured every sweep (fused into
+    the GPU's passes).  The two starts differ by FP32 rounding (~1e-6) and the
+    dynamics amplifies a difference by about 1.5x per sweep, so the chains are
+    compared while their links agree within 1e-3 and until the oracle meets a
+    decision within the flag margin: links, plaquette and Polyakov loop
+    sweep by sweep (the observables within 1e-6 plus a tenth of the link
+    difference); at least the first 10 sweeps must be compared."""
     announce("config-1 plaquette history")
     dims, beta, seed = [4, 4, 4, 4], 2.3, 1
+    U = orc.init(dims, 1, seed)
+    compared = 0
     with su2.Lattice(dims, beta, seed, su2.SU2_HOT) as lat:
         for sw in range(20):
-            U = lat.get_links().astype(np.float64)
-            ph, _ = orc.sweeps(dims, U, 1, sw, beta, seed, measure=True)
+            m = min(float(np.min(orc.do_pass(dims, U, mu, p, sw, beta, seed, want_margin=True)))
+                    for mu in range(4) for p in range(2))
             hist = lat.sweep_measure(1, meas=su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY).cpu().numpy()
+            if m < MARGIN_FLAG:
+                break
             got = lat.get_links().astype(np.float64)
-            # observables of the GPU's own configuration, FP64 oracle sums
-            assert abs(hist[0, 0] - orc.plaquette(dims, got)) < 1e-6
-            assert abs(hist[0, 1] - orc.polyakov(dims, got)[0]) < 1e-6
-            if np.abs(got - U).max() < 1e-5:
-                assert abs(hist[0, 0] - ph[0]) < 1e-6
+            du = float(np.abs(got - U).max())
+            dp = abs(hist[0, 0] - orc.plaquette(dims, U))
+            dl = abs(hist[0, 1] - orc.polyakov(dims, U)[0])
+            announce(f"  sweep {sw}: max |dU| {du:.2e}, |dP| {dp:.2e}, |dL| {dl:.2e}")
+            if du > 1e-3:
+                break
+            assert dp < 1e-6 + 0.1 * du and dl < 1e-6 + 0.1 * du, sw
+            compared += 1
+    assert compared >= 10, compared
 
 
 def test_stream_floor_kernel_moves_the_pass_bytes(su2, orc):
@@ -122,8 +146,10 @@ def test_stream_floor_kernel_moves_the_pass_bytes(su2, orc):
     dims = [4, 6, 2, 8]
     V = int(np.prod(dims))
     par_of = parities(orc, dims)
-    with su2.Lattice(dims, 2.0, 5, su2.SU2_HOT) as lat:
-        before = lat.get_links().astype(np.float64)
+    links = inputs.random_links(dims, 77)
+    with su2.Lattice(dims, 2.0, 5) as lat:
+        lat.set_links(links)
+        before = links.astype(np.float64)
         out = torch.zeros(2 * V, dtype=torch.float32, device="cuda:0")
         for mu, p in ((0, 0), (3, 1)):
             lat.test_stream_pass(mu, p, out)
@@ -132,7 +158,7 @@ def test_stream_floor_kernel_moves_the_pass_bytes(su2, orc):
             want = before[:, [n for n in range(4) if n != mu]].sum(axis=(0, 1)) + \
                 before[par_of != p, mu].sum(axis=0)
             np.testing.assert_allclose(got, want, atol=1e-3)
-        np.testing.assert_array_equal(lat.get_links(), before.astype(np.float32))
+        np.testing.assert_array_equal(lat.get_links(), links)
     with su2.Lattice(dims, 2.0, 5, su2.SU2_COLD) as lat:
         lat.test_stream_pass(1, 0, out)
         lat.synchronize()
