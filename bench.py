@@ -662,7 +662,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "t-slab decomposition is a design, not part of this build", file=sys.stderr)
+              "t-slab decomposition is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
