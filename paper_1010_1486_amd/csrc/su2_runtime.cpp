@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -235,19 +236,21 @@ void queue_layout(const std::vector<uint32_t> &nblocks, int nq, std::vector<int>
 // XCC ids that run workgroups on the current device (probed once).
 int xcc_ids(std::vector<int> &ids)
 {
-    static uint32_t masks[64] = {0};
+    // one probe per device; contexts on several host threads may race to fill
+    // an entry, which is harmless (every probe finds the same mask)
+    static std::atomic<uint32_t> masks[64];
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(SU2_ERANGE, "device index out of range");
-    if (!masks[dev]) {
-        uint32_t m = 0;
-        HIP_TRY(probe_xcc_mask(&m));
-        if (!m) return fail(SU2_EHIP, "XCC probe found no XCD");
-        masks[dev] = m;
+    uint32_t mask = masks[dev].load(std::memory_order_acquire);
+    if (!mask) {
+        HIP_TRY(probe_xcc_mask(&mask));
+        if (!mask) return fail(SU2_EHIP, "XCC probe found no XCD");
+        masks[dev].store(mask, std::memory_order_release);
     }
     ids.clear();
     for (int k = 0; k < kMaxQueues; ++k)
-        if (masks[dev] & (1u << k)) ids.push_back(k);
+        if (mask & (1u << k)) ids.push_back(k);
     return SU2_OK;
 }
 
