@@ -33,7 +33,8 @@
  *               mu | tag<<2, draw): tag 7 + g for subgroup g's a0 trials (the
  *               low 9 bits of draw 0's words give the direction), tag 10 for
  *               the hot start.  Results are bit-identical for identical
- *               (links, seed, sweep index, beta, launch).
+ *               (links, seed, sweep index, beta), whatever the launch
+ *               configuration (su3_set_launch).
  *
  * Errors: the SU2_* codes of su2.h; su2_last_error() gives the message.  Calls
  * documented as "enqueue" return after launching work on the context's stream;
