@@ -480,6 +480,12 @@ def su3_run(su2, torch, dev, steps=100, launches=80, with_cpu=True):
         e1.record(stream)
         e1.synchronize()
         pass_ms = e0.elapsed_time(e1) / launches
+        e0.record(stream)
+        for i in range(launches):
+            lat.test_or_pass((i // 2) % 4, i % 2)
+        e1.record(stream)
+        e1.synchronize()
+        or_ms = e0.elapsed_time(e1) / launches
         poly = lat.polyakov()
     gbs = SU3_BYTES_PER_UPDATE * (V // 2) / (pass_ms * 1e-3) / 1e9
     h_ = su3_source_hash()
@@ -490,6 +496,7 @@ def su3_run(su2, torch, dev, steps=100, launches=80, with_cpu=True):
     out.update({
         "link_updates_per_s": 4 * V * steps / dt, "ms_per_sweep": 1e3 * dt / steps,
         "pass_avg_launch_us": pass_ms * 1e3, "updates_per_launch": V // 2,
+        "overrelaxation_pass_avg_launch_us": or_ms * 1e3,
         "mean_plaquette": float(np.mean(h)), "polyakov": poly,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
@@ -534,6 +541,49 @@ def su3_polyakov_scan(su2, torch, dev, dims=(16, 16, 16, 4), therm=300, nmeas=30
                         "sweeps, |mean Polyakov loop| every measurement",
             "by_beta": rows, "beta_c": beta_c(SU3_SCAN_BETAS, absl),
             "link_updates_per_s": 4 * V * len(SU3_SCAN_BETAS) * (therm + nmeas * every) / dt}
+
+
+def su3_overrelaxation_gain(su2, torch, dev, dims=(16, 16, 16, 4), beta=5.69, budget=6000,
+                           n_or=3, therm=300):
+    """Heat bath alone against one heat-bath sweep followed by `n_or`
+    over-relaxation sweeps, at equal numbers of sweeps (`budget`), near the
+    N_t = 4 deconfinement coupling where the Polyakov loop decorrelates
+    slowly: tau_int of |mean Polyakov loop| and of the plaquette (measured after
+    every group) and the effective rate groups/s / (2 tau)."""
+    out = {"workload": f"SU(3) {dims[0]}^3 x {dims[3]}, beta {beta}, cold start, {therm} "
+                       f"thermalisation groups, {budget} sweeps each way"}
+    for nor in (0, n_or):
+        with su2.Lattice3(list(dims), beta, 5, su2.SU2_COLD, device=dev) as lat:
+            for _ in range(therm):
+                lat.heatbath_sweep(1, reunit_every=10)
+                if nor:
+                    lat.overrelax(nor)
+            groups = budget // (1 + nor)
+            L, P = [], []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(groups):
+                h = lat.heatbath_sweep(1, reunit_every=10, history=True)
+                if nor:
+                    lat.overrelax(nor)
+                re, im, _ = lat.polyakov()
+                L.append(abs(complex(re, im)))
+                P.append(h[0])
+            dt = time.perf_counter() - t0
+        tl, tp = tau_int(np.array(L)), tau_int(np.array(P))
+        out[f"hb+{nor}or"] = {"groups": groups, "seconds": dt, "mean_abs_polyakov": float(np.mean(L)),
+                              "tau_int_abs_polyakov": tl, "tau_int_plaquette": tp,
+                              "effective_rate_polyakov": groups / dt / (2 * tl),
+                              "effective_rate_plaquette": groups / dt / (2 * tp)}
+    a, b = out["hb+0or"], out[f"hb+{n_or}or"]
+    # wall clock on this small, launch-bound lattice
+    out["gain_polyakov"] = b["effective_rate_polyakov"] / a["effective_rate_polyakov"]
+    out["gain_plaquette"] = b["effective_rate_plaquette"] / a["effective_rate_plaquette"]
+    # per sweep of work: at 48^4 an over-relaxation pass costs what a heat-bath pass
+    # costs (both move the same bytes), so this is the gain where the passes are HBM-bound
+    out["gain_per_sweep_polyakov"] = a["tau_int_abs_polyakov"] / ((1 + n_or) * b["tau_int_abs_polyakov"])
+    out["gain_per_sweep_plaquette"] = a["tau_int_plaquette"] / ((1 + n_or) * b["tau_int_plaquette"])
+    return out
 
 
 def su3_oracle_rate(L=24, beta=BETA):
@@ -761,6 +811,7 @@ def main():
         print("[bench] SU(3) subgroup heat bath", file=sys.stderr, flush=True)
         out["su3"] = su3_run(su2, torch, dev, with_cpu=not args.no_cpu_baseline)
         out["su3"]["polyakov_scan_nt4"] = su3_polyakov_scan(su2, torch, dev)
+        out["su3"]["overrelaxation"] = su3_overrelaxation_gain(su2, torch, dev)
     if not args.no_wilson:
         print("[bench] Wilson loops and Creutz ratios", file=sys.stderr, flush=True)
         out["scale_setting"] = scale_setting(su2, torch, dev)

@@ -81,6 +81,16 @@ int su3_destroy(su3_ctx *ctx);
  * sweep index advances by nsweeps. */
 int su3_heatbath_sweep(su3_ctx *ctx, int32_t nsweeps, int32_t reunit_every, double *plaq_hist);
 
+/* Enqueue nsweeps (>= 0) microcanonical over-relaxation sweeps (Brown & Woch,
+ * Phys. Rev. Lett. 58 (1987) 2394; Creutz, Phys. Rev. D 36 (1987) 515): the
+ * same schedule and subgroups as the heat bath, each subgroup element replaced
+ * by r = (v^+)^2, v = a/|a|, which reflects it about the element the staple
+ * prefers.  Re Tr(U A) of every updated link, hence the action and the
+ * plaquette, is unchanged; no randoms are drawn and the sweep index does not
+ * advance.  Interleaved with heat-bath sweeps it shortens autocorrelations
+ * without changing the equilibrium distribution. */
+int su3_overrelax(su3_ctx *ctx, int32_t nsweeps);
+
 /* Enqueue Gram-Schmidt of rows 0 and 1 of every link (row 2 stays implied). */
 int su3_reunitarize(su3_ctx *ctx);
 
@@ -122,6 +132,8 @@ int su3_synchronize(su3_ctx *ctx);
 /* Test hook: enqueue one pass (direction mu, parity) at the current sweep
  * index, which does not advance. */
 int su3_test_pass(su3_ctx *ctx, int mu, int parity);
+/* Test hook: enqueue one over-relaxation pass (direction mu, parity). */
+int su3_test_or_pass(su3_ctx *ctx, int mu, int parity);
 
 #ifdef __cplusplus
 }

@@ -187,6 +187,54 @@ void orc3_heatbath_link(const double *Uin, const double *Ain, double beta, uint6
     if (margin) *margin = mmin;
 }
 
+/* Microcanonical over-relaxation of a link (Brown & Woch, Phys. Rev. Lett. 58
+ * (1987) 2394; Creutz, Phys. Rev. D 36 (1987) 515) in the same subgroups and
+ * order: with v = a/|a| the subgroup element r = (v^+)^2 reflects the link
+ * about the direction the staple prefers, so Re Tr(R W) = Re Tr(W) (the
+ * action is unchanged) and applying it twice gives the identity.  |a| = 0
+ * leaves the link alone.  No randoms. */
+void orc3_overrelax_link(const double *Uin, const double *Ain, double *out)
+{
+    cplx U[9], A[9];
+    memcpy(U, Uin, sizeof(U));
+    memcpy(A, Ain, sizeof(A));
+    for (int g = 0; g < 3; ++g) {
+        const int i = SUBGROUP[g][0], j = SUBGROUP[g][1];
+        cplx W[9];
+        m3_mul(U, A, W);
+        const cplx wii = W[3 * i + i], wij = W[3 * i + j], wji = W[3 * j + i], wjj = W[3 * j + j];
+        double a[4] = {0.5 * creal(wii + wjj), 0.5 * cimag(wij + wji), 0.5 * creal(wij - wji),
+                       0.5 * cimag(wii - wjj)};
+        double k = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
+        if (!(k > 0.0)) continue;
+        double vd[4] = {a[0] / k, -a[1] / k, -a[2] / k, -a[3] / k}, r[4];
+        orc_qmul(vd, vd, r);
+        const cplx r00 = r[0] + I * r[3], r01 = r[2] + I * r[1];
+        const cplx r10 = -r[2] + I * r[1], r11 = r[0] - I * r[3];
+        for (int c = 0; c < 3; ++c) {
+            const cplx ui = U[3 * i + c], uj = U[3 * j + c];
+            U[3 * i + c] = r00 * ui + r01 * uj;
+            U[3 * j + c] = r10 * ui + r11 * uj;
+        }
+    }
+    memcpy(out, U, sizeof(U));
+}
+
+void orc3_or_pass(const int32_t dims[4], double *U, int mu, int parity, int nthreads)
+{
+    int64_t V = orc_volume(dims);
+#ifdef _OPENMP
+    if (nthreads > 1) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(static) if (nthreads > 1)
+    for (int64_t s = 0; s < V; ++s) {
+        if (orc_parity(dims, s) != parity) continue;
+        double A[18];
+        orc3_staple(dims, U, s, mu, A);
+        orc3_overrelax_link((const double *)clink(U, s, mu), A, (double *)mlink(U, s, mu));
+    }
+}
+
 /* ------------------------------------------------------------------ passes */
 static void update_site(const int32_t dims[4], double *U, int64_t s, int mu, uint32_t sweep,
                         double beta, uint64_t seed, uint32_t replica, double *margin)
@@ -221,11 +269,22 @@ void orc3_sweeps(const int32_t dims[4], double *U, int32_t nsweeps, uint32_t swe
                  double beta, uint64_t seed, uint32_t replica, int32_t reunit_every,
                  int nthreads, double *plaq_hist, double *poly_hist)
 {
+    orc3_sweeps_or(dims, U, nsweeps, 0, sweep0, beta, seed, replica, reunit_every, nthreads,
+                   plaq_hist, poly_hist);
+}
+
+void orc3_sweeps_or(const int32_t dims[4], double *U, int32_t nsweeps, int32_t n_or,
+                    uint32_t sweep0, double beta, uint64_t seed, uint32_t replica,
+                    int32_t reunit_every, int nthreads, double *plaq_hist, double *poly_hist)
+{
     for (int32_t n = 0; n < nsweeps; ++n) {
         uint32_t sw = sweep0 + (uint32_t)n;
         for (int mu = 0; mu < 4; ++mu)
             for (int p = 0; p < 2; ++p)
                 orc3_pass(dims, U, mu, p, sw, beta, seed, replica, nthreads, NULL);
+        for (int32_t o = 0; o < n_or; ++o)
+            for (int mu = 0; mu < 4; ++mu)
+                for (int p = 0; p < 2; ++p) orc3_or_pass(dims, U, mu, p, nthreads);
         if (reunit_every > 0 && ((sw + 1u) % (uint32_t)reunit_every) == 0u)
             orc3_reunitarize(dims, U);
         if (plaq_hist) plaq_hist[n] = orc3_plaquette(dims, U);

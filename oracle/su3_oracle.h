@@ -54,6 +54,19 @@ void orc3_sweeps(const int32_t dims[4], double *U, int32_t nsweeps, uint32_t swe
                  double beta, uint64_t seed, uint32_t replica, int32_t reunit_every,
                  int nthreads, double *plaq_hist, double *poly_hist);
 
+/* Microcanonical over-relaxation of one link with staple sum A (the subgroups
+ * and order of the heat bath; r = (v^+)^2 with v = a/|a|): Re Tr(U A) is
+ * unchanged and the map is its own inverse.  No randoms. */
+void orc3_overrelax_link(const double *U, const double *A, double *out);
+/* One over-relaxation pass (direction mu, sites of the given parity). */
+void orc3_or_pass(const int32_t dims[4], double *U, int mu, int parity, int nthreads);
+/* As orc3_sweeps, each heat-bath sweep followed by n_or over-relaxation sweeps
+ * (eight passes each, same schedule) before the reunitarisation and the
+ * measurements; the sweep index counts heat-bath sweeps only. */
+void orc3_sweeps_or(const int32_t dims[4], double *U, int32_t nsweeps, int32_t n_or,
+                    uint32_t sweep0, double beta, uint64_t seed, uint32_t replica,
+                    int32_t reunit_every, int nthreads, double *plaq_hist, double *poly_hist);
+
 /* start 0: every link 1; start 1: Haar-random links (Gram-Schmidt of two
  * complex Gaussian rows, third row the conjugate cross product). */
 void orc3_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint32_t replica);

@@ -41,6 +41,10 @@ def _load():
         "orc3_staple_action": (c_d, [_i32p, _c128p]),
         "orc3_gauge_transform": (None, [_i32p, _c128p, c_u64, c_u32]),
         "orc3_link_chain": (None, [_c128p, c_d, c_i64, c_u64, _c128p, vp]),
+        "orc3_overrelax_link": (None, [_c128p, _c128p, _c128p]),
+        "orc3_or_pass": (None, [_i32p, _c128p, c_int, c_int, c_int]),
+        "orc3_sweeps_or": (None, [_i32p, _c128p, ctypes.c_int32, ctypes.c_int32, c_u32, c_d,
+                                  c_u64, c_u32, ctypes.c_int32, c_int, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -112,6 +116,30 @@ def sweeps(dims, U, nsweeps, sweep0, beta, seed, replica=0, reunit_every=0, nthr
                         np.uint64(seed), replica, reunit_every, int(nthreads),
                         None if ph is None else ph.ctypes.data_as(ctypes.c_void_p),
                         None if lh is None else lh.ctypes.data_as(ctypes.c_void_p))
+    return (ph, lh) if history else None
+
+
+def overrelax_link(U, A):
+    """Microcanonical over-relaxation of one link with staple sum A."""
+    out = np.zeros((3, 3), dtype=np.complex128)
+    _load().orc3_overrelax_link(_m3(U), _m3(A), out)
+    return out
+
+
+def or_pass(dims, U, mu, parity, nthreads=1):
+    _load().orc3_or_pass(_dims(dims), _links(U, dims), mu, parity, int(nthreads))
+
+
+def sweeps_or(dims, U, nsweeps, n_or, sweep0, beta, seed, replica=0, reunit_every=0, nthreads=1,
+              history=False):
+    """nsweeps heat-bath sweeps, each followed by n_or over-relaxation sweeps;
+    with history, returns (plaquette, Re Polyakov) after each heat-bath sweep's group."""
+    ph = np.zeros(nsweeps) if history else None
+    lh = np.zeros(nsweeps) if history else None
+    _load().orc3_sweeps_or(_dims(dims), _links(U, dims), nsweeps, n_or, sweep0, float(beta),
+                           np.uint64(seed), replica, reunit_every, int(nthreads),
+                           None if ph is None else ph.ctypes.data_as(ctypes.c_void_p),
+                           None if lh is None else lh.ctypes.data_as(ctypes.c_void_p))
     return (ph, lh) if history else None
 
 

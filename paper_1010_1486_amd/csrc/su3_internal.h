@@ -38,11 +38,13 @@ struct Launch3 {
 };
 
 hipError_t launch_su3_init(const Lat3 &L, int start, uint64_t seed, hipStream_t s);
-// One heat-bath pass (direction mu, parity par); with measure, the plaquette
+// One heat-bath pass (direction mu, parity par), or with overrelax one
+// microcanonical over-relaxation pass (no randoms); with measure, the plaquette
 // terms of the passes' nu < mu staples are accumulated (odd passes of mu >= 1
 // cover every plaquette of the end-of-sweep configuration once).
 hipError_t launch_su3_pass(const Lat3 &L, int mu, int par, uint32_t sweep, uint64_t seed,
-                           bool measure, const Launch3 &cfg, hipStream_t s);
+                           bool measure, const Launch3 &cfg, hipStream_t s,
+                           bool overrelax = false);
 hipError_t launch_su3_reunit(const Lat3 &L, hipStream_t s);
 hipError_t launch_su3_plaquette(const Lat3 &L, hipStream_t s);
 hipError_t launch_su3_polyakov(const Lat3 &L, hipStream_t s);

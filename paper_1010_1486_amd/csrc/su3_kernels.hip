@@ -236,17 +236,20 @@ __device__ __forceinline__ void gram_schmidt(M3 &u)
 }
 
 // ------------------------------------------------------------ subgroup step
-// Heat-bath draw in the SU(2) subgroup of rows (I, J): quaternion part a of
-// the (I, J) block of W, r = X (a/|a|)^+ from the SU(2) sampler with
-// beta -> 2 beta / 3, then rows I, J of U (and of W, when it is used again)
-// are multiplied by M(r) = [[r0 + i r3, r2 + i r1], [-r2 + i r1, r0 - i r3]].
-template <int I, int J, bool UPDATE_W>
-__device__ __forceinline__ void subgroup(M3 &U, M3 &W, float beta23, uint32_t site,
-                                         uint32_t sweep, uint32_t w2, uint32_t k0, uint32_t k1)
+// Quaternion part a of the (I, J) block of W: the block is M(a) + i M(c) with
+// M(a) = a0 + i a.sigma, and Re Tr(r w) for r in SU(2) only sees M(a).
+template <int I, int J>
+__device__ __forceinline__ Q block_quaternion(const M3 &W)
 {
-    const Q a{0.5f * (W.e[I][I].r + W.e[J][J].r), 0.5f * (W.e[I][J].i + W.e[J][I].i),
-              0.5f * (W.e[I][J].r - W.e[J][I].r), 0.5f * (W.e[I][I].i - W.e[J][J].i)};
-    const Q r = heatbath_link(a, beta23, site, sweep, w2, k0, k1);
+    return Q{0.5f * (W.e[I][I].r + W.e[J][J].r), 0.5f * (W.e[I][J].i + W.e[J][I].i),
+             0.5f * (W.e[I][J].r - W.e[J][I].r), 0.5f * (W.e[I][I].i - W.e[J][J].i)};
+}
+
+// Rows I, J of U (and of W, when it is used again) multiplied from the left by
+// M(r) = [[r0 + i r3, r2 + i r1], [-r2 + i r1, r0 - i r3]].
+template <int I, int J, bool UPDATE_W>
+__device__ __forceinline__ void rotate(M3 &U, M3 &W, const Q &r)
+{
     const Cx r00{r.w, r.z}, r01{r.y, r.x}, r10{-r.y, r.x}, r11{r.w, -r.z};
     const Cx zero{0.0f, 0.0f};
 #pragma unroll
@@ -262,10 +265,35 @@ __device__ __forceinline__ void subgroup(M3 &U, M3 &W, float beta23, uint32_t si
     }
 }
 
+// Heat-bath draw in the SU(2) subgroup of rows (I, J): r = X (a/|a|)^+ from the
+// SU(2) sampler with beta -> 2 beta / 3.
+template <int I, int J, bool UPDATE_W>
+__device__ __forceinline__ void subgroup(M3 &U, M3 &W, float beta23, uint32_t site,
+                                         uint32_t sweep, uint32_t w2, uint32_t k0, uint32_t k1)
+{
+    const Q r = heatbath_link(block_quaternion<I, J>(W), beta23, site, sweep, w2, k0, k1);
+    rotate<I, J, UPDATE_W>(U, W, r);
+}
+
+// Microcanonical over-relaxation in the subgroup of rows (I, J) (Brown & Woch
+// 1987; Creutz 1987): r = (v^+)^2 with v = a/|a| reflects the subgroup
+// element about the one the staple prefers (v^+), so Re Tr(R W) is unchanged;
+// |a| = 0 leaves the link alone.  No randoms.
+template <int I, int J, bool UPDATE_W>
+__device__ __forceinline__ void or_subgroup(M3 &U, M3 &W)
+{
+    const Q a = block_quaternion<I, J>(W);
+    const float k2 = qdot(a, a);
+    if (!(k2 > 0.0f)) return;
+    const float ik = hw_rsq(k2);
+    const Q vd{a.w * ik, -a.x * ik, -a.y * ik, -a.z * ik};
+    rotate<I, J, UPDATE_W>(U, W, qmul(vd, vd));
+}
+
 // ------------------------------------------------------------------ pass
 // Update of U_MU at half-site gid (pass order) of parity par.  With MEASURE
 // returns Re Tr(U'_MU A_low) / 3, A_low the staples with nu < MU.
-template <int MU, bool MEASURE>
+template <int MU, bool MEASURE, bool OR>
 __device__ __forceinline__ float update_site3(const Lat3 &L, uint32_t gid, int par,
                                               uint32_t sweep, uint32_t k0, uint32_t k1)
 {
@@ -308,12 +336,18 @@ __device__ __forceinline__ float update_site3(const Lat3 &L, uint32_t gid, int p
     }
     M3 U = ld3(cls(L.links, g.vh, MU, par), h);
     M3 W = mul_full(U, A);
-    const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
-    const float beta23 = L.beta * (2.0f / 3.0f);
-    const uint32_t w2 = word2((uint32_t)MU, TAG_SU3_SUB, L.replica);
-    subgroup<0, 1, true>(U, W, beta23, site, sweep, w2, k0, k1);
-    subgroup<1, 2, true>(U, W, beta23, site, sweep, w2 + (1u << 2), k0, k1);
-    subgroup<0, 2, false>(U, W, beta23, site, sweep, w2 + (2u << 2), k0, k1);
+    if (OR) {
+        or_subgroup<0, 1, true>(U, W);
+        or_subgroup<1, 2, true>(U, W);
+        or_subgroup<0, 2, false>(U, W);
+    } else {
+        const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
+        const float beta23 = L.beta * (2.0f / 3.0f);
+        const uint32_t w2 = word2((uint32_t)MU, TAG_SU3_SUB, L.replica);
+        subgroup<0, 1, true>(U, W, beta23, site, sweep, w2, k0, k1);
+        subgroup<1, 2, true>(U, W, beta23, site, sweep, w2 + (1u << 2), k0, k1);
+        subgroup<0, 2, false>(U, W, beta23, site, sweep, w2 + (2u << 2), k0, k1);
+    }
     // The rotations of the (1,2) and (0,2) subgroups mix the rebuilt row 2 into
     // the stored rows, so an FP32 deviation from unitarity would be fed back
     // and grow from update to update; re-orthonormalising the stored rows (a
@@ -324,7 +358,7 @@ __device__ __forceinline__ float update_site3(const Lat3 &L, uint32_t gid, int p
     return MEASURE ? retr_mul(U, Alow) * (1.0f / 3.0f) : 0.0f;
 }
 
-template <int MU, bool MEASURE>
+template <int MU, bool MEASURE, bool OR>
 __global__ __launch_bounds__(256) void su3_pass_kernel(Lat3 L, int par, uint32_t sweep,
                                                        uint32_t k0, uint32_t k1,
                                                        uint32_t nblocks, int remap, int reverse)
@@ -332,7 +366,7 @@ __global__ __launch_bounds__(256) void su3_pass_kernel(Lat3 L, int par, uint32_t
     const uint32_t blk = logical_block(blockIdx.x, nblocks, remap, reverse);
     const uint32_t gid = blk * blockDim.x + threadIdx.x;
     float meas = 0.0f;
-    if (gid < L.g.vh) meas = update_site3<MU, MEASURE>(L, gid, par, sweep, k0, k1);
+    if (gid < L.g.vh) meas = update_site3<MU, MEASURE, OR>(L, gid, par, sweep, k0, k1);
     if (MEASURE) block_accumulate((double)meas, L.acc, A3_PLAQ, blockIdx.x);
 }
 
@@ -481,7 +515,7 @@ __global__ __launch_bounds__(256) void su3_init_kernel(Lat3 L, int start, uint32
 
 uint32_t nblk(uint64_t n, int b) { return (uint32_t)((n + (uint64_t)b - 1) / (uint64_t)b); }
 
-template <int MU>
+template <int MU, bool OR>
 void launch_pass_mu(const Lat3 &L, int par, uint32_t sweep, uint32_t k0, uint32_t k1,
                     bool measure, const Launch3 &cfg, hipStream_t s)
 {
@@ -489,11 +523,23 @@ void launch_pass_mu(const Lat3 &L, int par, uint32_t sweep, uint32_t k0, uint32_
     const int reverse = (cfg.snake && par == 1) ? 1 : 0;
     const int remap = cfg.remap ? 1 : 0;
     if (measure)
-        hipLaunchKernelGGL((su3_pass_kernel<MU, true>), dim3(nb), dim3(cfg.block), 0, s, L, par,
-                           sweep, k0, k1, nb, remap, reverse);
-    else
-        hipLaunchKernelGGL((su3_pass_kernel<MU, false>), dim3(nb), dim3(cfg.block), 0, s, L,
+        hipLaunchKernelGGL((su3_pass_kernel<MU, true, OR>), dim3(nb), dim3(cfg.block), 0, s, L,
                            par, sweep, k0, k1, nb, remap, reverse);
+    else
+        hipLaunchKernelGGL((su3_pass_kernel<MU, false, OR>), dim3(nb), dim3(cfg.block), 0, s, L,
+                           par, sweep, k0, k1, nb, remap, reverse);
+}
+
+template <bool OR>
+void launch_pass_or(const Lat3 &L, int mu, int par, uint32_t sweep, uint32_t k0, uint32_t k1,
+                    bool measure, const Launch3 &cfg, hipStream_t s)
+{
+    switch (mu) {
+    case 0: launch_pass_mu<0, OR>(L, par, sweep, k0, k1, measure, cfg, s); break;
+    case 1: launch_pass_mu<1, OR>(L, par, sweep, k0, k1, measure, cfg, s); break;
+    case 2: launch_pass_mu<2, OR>(L, par, sweep, k0, k1, measure, cfg, s); break;
+    default: launch_pass_mu<3, OR>(L, par, sweep, k0, k1, measure, cfg, s); break;
+    }
 }
 
 }  // namespace
@@ -506,15 +552,13 @@ hipError_t launch_su3_init(const Lat3 &L, int start, uint64_t seed, hipStream_t 
 }
 
 hipError_t launch_su3_pass(const Lat3 &L, int mu, int par, uint32_t sweep, uint64_t seed,
-                           bool measure, const Launch3 &cfg, hipStream_t s)
+                           bool measure, const Launch3 &cfg, hipStream_t s, bool overrelax)
 {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    switch (mu) {
-    case 0: launch_pass_mu<0>(L, par, sweep, k0, k1, measure, cfg, s); break;
-    case 1: launch_pass_mu<1>(L, par, sweep, k0, k1, measure, cfg, s); break;
-    case 2: launch_pass_mu<2>(L, par, sweep, k0, k1, measure, cfg, s); break;
-    default: launch_pass_mu<3>(L, par, sweep, k0, k1, measure, cfg, s); break;
-    }
+    if (overrelax)
+        launch_pass_or<true>(L, mu, par, sweep, k0, k1, measure, cfg, s);
+    else
+        launch_pass_or<false>(L, mu, par, sweep, k0, k1, measure, cfg, s);
     return hipGetLastError();
 }
 

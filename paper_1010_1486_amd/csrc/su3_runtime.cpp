@@ -190,6 +190,21 @@ int su3_heatbath_sweep(su3_ctx *c, int32_t nsweeps, int32_t reunit_every, double
     SU2_API_END
 }
 
+int su3_overrelax(su3_ctx *c, int32_t nsweeps)
+{
+    SU2_API_BEGIN
+    int rc = check3(c);
+    if (rc) return rc;
+    if (nsweeps < 0) return fail(SU2_EINVAL, "nsweeps must be >= 0");
+    for (int32_t j = 0; j < nsweeps; ++j)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int par = 0; par < 2; ++par)
+                HIP_TRY(launch_su3_pass(c->L, mu, par, c->sweep, c->seed, false, c->cfg,
+                                        c->stream, true));
+    return SU2_OK;
+    SU2_API_END
+}
+
 int su3_reunitarize(su3_ctx *c)
 {
     SU2_API_BEGIN
@@ -376,6 +391,19 @@ int su3_test_pass(su3_ctx *c, int mu, int parity)
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1)
         return fail(SU2_EINVAL, "mu must be 0..3 and parity 0..1");
     HIP_TRY(launch_su3_pass(c->L, mu, parity, c->sweep, c->seed, false, c->cfg, c->stream));
+    return SU2_OK;
+    SU2_API_END
+}
+
+int su3_test_or_pass(su3_ctx *c, int mu, int parity)
+{
+    SU2_API_BEGIN
+    int rc = check3(c);
+    if (rc) return rc;
+    if (mu < 0 || mu > 3 || parity < 0 || parity > 1)
+        return fail(SU2_EINVAL, "mu must be 0..3 and parity 0..1");
+    HIP_TRY(launch_su3_pass(c->L, mu, parity, c->sweep, c->seed, false, c->cfg, c->stream,
+                            true));
     return SU2_OK;
     SU2_API_END
 }

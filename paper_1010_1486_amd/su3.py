@@ -35,6 +35,8 @@ _SIGS3 = {
     "su3_links_device": (_int, [_vp, _vp, _vp]),
     "su3_synchronize": (_int, [_vp]),
     "su3_test_pass": (_int, [_vp, _int, _int]),
+    "su3_test_or_pass": (_int, [_vp, _int, _int]),
+    "su3_overrelax": (_int, [_vp, _i32]),
 }
 _bound = False
 
@@ -110,6 +112,10 @@ class Lattice3:
                                          None if hist is None else _p(hist)))
         return hist[:n] if history else None
 
+    def overrelax(self, n):
+        """n microcanonical over-relaxation sweeps (the action is unchanged)."""
+        _check(lib3().su3_overrelax(self.h, int(n)))
+
     def reunitarize(self):
         _check(lib3().su3_reunitarize(self.h))
 
@@ -154,3 +160,6 @@ class Lattice3:
 
     def test_pass(self, mu, parity):
         _check(lib3().su3_test_pass(self.h, int(mu), int(parity)))
+
+    def test_or_pass(self, mu, parity):
+        _check(lib3().su3_test_or_pass(self.h, int(mu), int(parity)))

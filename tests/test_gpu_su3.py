@@ -290,3 +290,72 @@ def test_su3_deconfinement_at_nt4(su2):
     announce(f"  <|L|> beta 5.5: {absL[5.5]:.4f}, beta 5.9: {absL[5.9]:.4f}")
     assert absL[5.9] > 4 * absL[5.5]
     assert absL[5.5] < 0.1
+
+
+@pytest.mark.parametrize("dims,spread", [([4, 4, 4, 4], None), ([6, 6, 6, 10], 0.3)],
+                         ids=["4^4-haar", "6^3x10-ordered"])
+def test_su3_overrelaxation_pass_matches_oracle(su2, o3, dims, spread):
+    """Every (mu, parity) over-relaxation pass from the same seeded links on
+    both sides (deterministic: no decisions to flag)."""
+    announce(f"su3 over-relaxation pass parity dims={dims}")
+    links = inputs.random_su3_links(dims, 60 + sum(dims), spread=spread)
+    par_of = parities(dims)
+    worst = 0.0
+    with su2.Lattice3(dims, 6.0, 1) as lat:
+        for mu in range(4):
+            for p in range(2):
+                lat.set_links(links)
+                lat.test_or_pass(mu, p)
+                got = lat.get_links()
+                U = links.copy()
+                o3.or_pass(dims, U, mu, p)
+                upd = par_of == p
+                worst = max(worst, float(np.abs(got[upd, mu] - U[upd, mu]).max()))
+                assert np.abs(got[upd, mu] - links[upd, mu]).max() > 0.05
+    announce(f"  max |gpu - oracle| = {worst:.2e}")
+    assert worst < 1e-5
+
+
+def test_su3_overrelaxation_keeps_the_action(su2):
+    """Over-relaxation sweeps leave every link's Re Tr(U A), hence the
+    plaquette, unchanged (to FP32 rounding) while moving the links by O(1); the
+    sweep index does not advance."""
+    announce("su3 over-relaxation keeps the action")
+    dims = [8, 8, 8, 8]
+    with su2.Lattice3(dims, 6.0, 4, su2.SU2_HOT) as lat:
+        lat.heatbath_sweep(20, reunit_every=10)
+        p0, before, sw = lat.plaquette(), lat.get_links(), lat.sweep
+        lat.overrelax(3)
+        assert abs(lat.plaquette() - p0) < 1e-6
+        assert np.abs(lat.get_links() - before).max() > 0.5
+        assert lat.sweep == sw
+        with pytest.raises(su2.SU2Error):
+            lat.overrelax(-1)
+
+
+def test_su3_heatbath_with_overrelaxation_matches_oracle_chains(su2, o3):
+    """Chains of one heat-bath and three over-relaxation sweeps (8 on the GPU)
+    against the oracle's heat-bath chains (4): the same equilibrium plaquette at
+    beta = 6.0 on 6^4 (100 + 200 groups, reunitarisation every 10)."""
+    dims, beta, therm, nmeas = [6, 6, 6, 6], 6.0, 100, 200
+    announce("su3 heat bath + over-relaxation vs oracle")
+    g = []
+    for r in range(8):
+        with su2.Lattice3(dims, beta, 800 + r, su2.SU2_COLD) as lat:
+            h = []
+            for i in range(therm + nmeas):
+                h.append(lat.heatbath_sweep(1, reunit_every=10, history=True)[0])
+                lat.overrelax(3)
+            g.append(np.mean(h[therm:]))
+    o = []
+    for r in range(4):
+        U = o3.init(dims, 0, 0)
+        ph, _ = o3.sweeps(dims, U, therm + nmeas, 0, beta, 900 + r, reunit_every=10,
+                          nthreads=8, history=True)
+        o.append(ph[therm:].mean())
+    g, o = np.array(g), np.array(o)
+    dg, do = g.std(ddof=1) / np.sqrt(len(g)), o.std(ddof=1) / np.sqrt(len(o))
+    pull = (g.mean() - o.mean()) / np.hypot(dg, do)
+    announce(f"  gpu HB+3OR {g.mean():.5f}({dg:.5f}) oracle HB {o.mean():.5f}({do:.5f}) "
+             f"pull {pull:.2f}")
+    assert abs(pull) < 4
