@@ -64,9 +64,10 @@ def test_su3_starts_match_oracle(su2, o3, dims):
         assert np.array_equal(lat.get_links(), o3.init(dims, 0, 9))
 
 
-@pytest.mark.parametrize("dims,spread,beta", [([4, 4, 4, 4], None, 5.7), ([6, 6, 6, 10], 0.3, 6.0),
+@pytest.mark.parametrize("dims,spread,beta", [([2, 2, 2, 2], None, 5.7), ([2, 4, 2, 6], 0.4, 6.0),
+                                              ([4, 4, 4, 4], None, 5.7), ([6, 6, 6, 10], 0.3, 6.0),
                                               ([8, 4, 6, 4], 0.15, 8.0)],
-                         ids=["4^4-haar", "6^3x10-ordered", "8x4x6x4-cold"])
+                         ids=["2^4-haar", "2x4x2x6", "4^4-haar", "6^3x10-ordered", "8x4x6x4-cold"])
 def test_su3_every_pass_matches_oracle(su2, o3, dims, spread, beta):
     """All eight (mu, parity) passes from the same links; V/2 = 1080 for
     6^3 x 10 spans four full workgroups and a ragged tail."""
@@ -292,8 +293,9 @@ def test_su3_deconfinement_at_nt4(su2):
     assert absL[5.5] < 0.1
 
 
-@pytest.mark.parametrize("dims,spread", [([4, 4, 4, 4], None), ([6, 6, 6, 10], 0.3)],
-                         ids=["4^4-haar", "6^3x10-ordered"])
+@pytest.mark.parametrize("dims,spread", [([2, 2, 2, 2], None), ([4, 4, 4, 4], None),
+                                         ([6, 6, 6, 10], 0.3)],
+                         ids=["2^4-haar", "4^4-haar", "6^3x10-ordered"])
 def test_su3_overrelaxation_pass_matches_oracle(su2, o3, dims, spread):
     """Every (mu, parity) over-relaxation pass from the same seeded links on
     both sides (deterministic: no decisions to flag)."""
