@@ -174,7 +174,12 @@ static const double *link(const double *U, int64_t s, int mu)
  * is the sum of the six plaquettes containing U_mu(s):
  *   forward  U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
  *   backward U_nu(s+mu-nu)^+ U_mu(s-nu)^+ U_nu(s-nu)                        */
-void orc_staple(const int32_t dims[4], const double *U, int64_t s, int mu, double V[4])
+/* The staple sum with the links supplied by `get` (a stored lattice, or the
+ * hot start computed link by link). */
+typedef void (*link_fn)(const void *ctx, int64_t s, int mu, double out[4]);
+
+static void staple_with(const int32_t dims[4], link_fn get, const void *ctx, int64_t s, int mu,
+                        double V[4])
 {
     V[0] = V[1] = V[2] = V[3] = 0.0;
     int64_t s_pmu = orc_shift(dims, s, mu, +1);
@@ -183,20 +188,36 @@ void orc_staple(const int32_t dims[4], const double *U, int64_t s, int mu, doubl
         int64_t s_pnu = orc_shift(dims, s, nu, +1);
         int64_t s_mnu = orc_shift(dims, s, nu, -1);
         int64_t s_pmu_mnu = orc_shift(dims, s_pmu, nu, -1);
-        double a[4], b[4], t[4], f[4];
+        double a[4], b[4], t[4], f[4], l[4];
 
-        orc_qdag(link(U, s_pnu, mu), b);
-        orc_qmul(link(U, s_pmu, nu), b, t);
-        orc_qdag(link(U, s, nu), a);
+        get(ctx, s_pnu, mu, l);
+        orc_qdag(l, b);
+        get(ctx, s_pmu, nu, l);
+        orc_qmul(l, b, t);
+        get(ctx, s, nu, l);
+        orc_qdag(l, a);
         orc_qmul(t, a, f);
         for (int c = 0; c < 4; ++c) V[c] += f[c];
 
-        orc_qdag(link(U, s_pmu_mnu, nu), a);
-        orc_qdag(link(U, s_mnu, mu), b);
+        get(ctx, s_pmu_mnu, nu, l);
+        orc_qdag(l, a);
+        get(ctx, s_mnu, mu, l);
+        orc_qdag(l, b);
         orc_qmul(a, b, t);
-        orc_qmul(t, link(U, s_mnu, nu), f);
+        get(ctx, s_mnu, nu, l);
+        orc_qmul(t, l, f);
         for (int c = 0; c < 4; ++c) V[c] += f[c];
     }
+}
+
+static void stored_link(const void *ctx, int64_t s, int mu, double out[4])
+{
+    memcpy(out, link((const double *)ctx, s, mu), 4 * sizeof(double));
+}
+
+void orc_staple(const int32_t dims[4], const double *U, int64_t s, int mu, double V[4])
+{
+    staple_with(dims, stored_link, U, s, mu, V);
 }
 
 /* ----------------------------------------------------------------- sampler */
@@ -398,6 +419,13 @@ void orc_haar_from_block(const uint32_t w[4], double out[4])
     for (int i = 0; i < 4; ++i) out[i] = g[i] / n;
 }
 
+void orc_hot_link(int64_t s, int mu, uint64_t seed, uint32_t replica, double out[4])
+{
+    uint32_t w[4];
+    block(seed, (uint32_t)s, 0u, word2_of((uint32_t)mu, ORC_TAG_HOT, replica), 0u, NULL, w);
+    orc_haar_from_block(w, out);
+}
+
 void orc_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint32_t replica)
 {
     int64_t V = orc_volume(dims);
@@ -407,12 +435,27 @@ void orc_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint32
             if (start == 0) {
                 l[0] = 1.0; l[1] = l[2] = l[3] = 0.0;
             } else {
-                uint32_t w[4];
-                block(seed, (uint32_t)s, 0u, word2_of((uint32_t)mu, ORC_TAG_HOT, replica), 0u,
-                      NULL, w);
-                orc_haar_from_block(w, l);
+                orc_hot_link(s, mu, seed, replica, l);
             }
         }
+}
+
+struct hot_key {
+    uint64_t seed;
+    uint32_t replica;
+};
+
+static void hot_link_of(const void *ctx, int64_t s, int mu, double out[4])
+{
+    const struct hot_key *k = (const struct hot_key *)ctx;
+    orc_hot_link(s, mu, k->seed, k->replica, out);
+}
+
+void orc_hot_staple(const int32_t dims[4], int64_t s, int mu, uint64_t seed, uint32_t replica,
+                    double V[4])
+{
+    struct hot_key k = {seed, replica};
+    staple_with(dims, hot_link_of, &k, s, mu, V);
 }
 
 void orc_reunitarize(const int32_t dims[4], double *U)

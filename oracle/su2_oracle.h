@@ -63,6 +63,12 @@ int64_t orc_shift(const int32_t dims[4], int64_t s, int mu, int step);
 
 /* Sum of the six staples around U_mu(s) (Sec. 2). */
 void orc_staple(const int32_t dims[4], const double *U, int64_t s, int mu, double V[4]);
+/* U_mu(s) of the hot start (the orc_init recipe), computed on its own, and the
+ * staple sum of the hot-start configuration at (s, mu) without building the
+ * lattice: for lattices too large to hold in FP64 on the host. */
+void orc_hot_link(int64_t s, int mu, uint64_t seed, uint32_t replica, double out[4]);
+void orc_hot_staple(const int32_t dims[4], int64_t s, int mu, uint64_t seed, uint32_t replica,
+                    double V[4]);
 
 /* Exact a0 sampler for density ~ sqrt(1-a0^2) exp(alpha a0).  Returns
  * delta = 1 - a0; *ntrials = trials used; *margin = smallest |decision margin|

@@ -45,6 +45,8 @@ def _load():
         "orc_parity": (c_int, [_i32p, c_i64]),
         "orc_shift": (c_i64, [_i32p, c_i64, c_int, c_int]),
         "orc_staple": (None, [_i32p, _f64p, c_i64, c_int, _f64p]),
+        "orc_hot_link": (None, [c_i64, c_int, c_u64, c_u32, _f64p]),
+        "orc_hot_staple": (None, [_i32p, c_i64, c_int, c_u64, c_u32, _f64p]),
         "orc_sample_delta_batch": (None, [c_i64, _f64p, c_u64, _u32p, c_u32, c_u32, c_u32,
                                           _f64p, vp, vp]),
         "orc_heatbath_link": (None, [_f64p, c_d, c_u64, c_u32, c_u32, c_u32, c_u32, _f64p, vp]),
@@ -150,6 +152,20 @@ def init(dims, start, seed, replica=0):
 def staple(dims, U, s, mu):
     out = np.zeros(4)
     _load().orc_staple(_dims(dims), _c(U), int(s), int(mu), out)
+    return out
+
+
+def hot_link(s, mu, seed, replica=0):
+    """U_mu(s) of the hot start, computed on its own."""
+    out = np.zeros(4)
+    _load().orc_hot_link(int(s), int(mu), np.uint64(seed), int(replica), out)
+    return out
+
+
+def hot_staple(dims, s, mu, seed, replica=0):
+    """Staple sum at (s, mu) of the hot-start configuration, without the lattice."""
+    out = np.zeros(4)
+    _load().orc_hot_staple(_dims(dims), int(s), int(mu), np.uint64(seed), int(replica), out)
     return out
 
 

@@ -189,3 +189,16 @@ def test_unitarity_and_reunitarize(orc):
     U *= 1.01
     orc.reunitarize(dims, U)
     assert np.abs(np.linalg.norm(U, axis=2) - 1).max() < 1e-15
+
+
+def test_hot_link_and_staple_without_the_lattice(orc):
+    """The per-link hot start and the hot-start staple equal the full
+    lattice's (used where the lattice is too large to hold on the host)."""
+    dims = [4, 6, 2, 8]
+    U = orc.init(dims, 1, 13, replica=2)
+    rng = np.random.default_rng(1)
+    for s in rng.integers(0, orc.volume(dims), 20):
+        for mu in range(4):
+            np.testing.assert_array_equal(orc.hot_link(s, mu, 13, 2), U[s, mu])
+            np.testing.assert_allclose(orc.hot_staple(dims, s, mu, 13, 2),
+                                       orc.staple(dims, U, s, mu), atol=1e-15, rtol=0)
