@@ -132,6 +132,10 @@ int su3_synchronize(su3_ctx *ctx);
 /* Test hook: enqueue one pass (direction mu, parity) at the current sweep
  * index, which does not advance. */
 int su3_test_pass(su3_ctx *ctx, int mu, int parity);
+/* Test hook: read U_mu at n sites (canonical indices, host array) into host
+ * double[n][3][3][2] (row 2 rebuilt in FP64) without copying the whole field;
+ * synchronous.  SU2_EINVAL for a site outside the lattice. */
+int su3_test_read_links(su3_ctx *ctx, int64_t n, const int64_t *sites, int mu, double *out);
 /* Test hook: enqueue one over-relaxation pass (direction mu, parity). */
 int su3_test_or_pass(su3_ctx *ctx, int mu, int parity);
 

@@ -128,30 +128,50 @@ static uint32_t word2(uint32_t mu, uint32_t tag, uint32_t replica)
 }
 
 /* ----------------------------------------------------------------- staples */
-void orc3_staple(const int32_t dims[4], const double *U, int64_t s, int mu, double *Aout)
+/* The staple sum with the links supplied by `get` (a stored lattice, or the
+ * hot start computed link by link). */
+typedef void (*link3_fn)(const void *ctx, int64_t s, int mu, cplx out[9]);
+
+static void staple_with(const int32_t dims[4], link3_fn get, const void *ctx, int64_t s, int mu,
+                        cplx A[9])
 {
-    cplx A[9] = {0};
+    for (int e = 0; e < 9; ++e) A[e] = 0.0;
     int64_t sp = orc_shift(dims, s, mu, +1);
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == mu) continue;
         int64_t snp = orc_shift(dims, s, nu, +1);
         int64_t snm = orc_shift(dims, s, nu, -1);
         int64_t spnm = orc_shift(dims, sp, nu, -1);
-        cplx d1[9], d2[9], t[9], st[9];
+        cplx l[9], d1[9], d2[9], t[9], st[9];
         /* forward: U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+ */
-        m3_adj(clink(U, snp, mu), d1);
-        m3_mul(clink(U, sp, nu), d1, t);
-        m3_adj(clink(U, s, nu), d2);
+        get(ctx, snp, mu, l);
+        m3_adj(l, d1);
+        get(ctx, sp, nu, l);
+        m3_mul(l, d1, t);
+        get(ctx, s, nu, l);
+        m3_adj(l, d2);
         m3_mul(t, d2, st);
         for (int e = 0; e < 9; ++e) A[e] += st[e];
         /* backward: U_nu(s+mu-nu)^+ U_mu(s-nu)^+ U_nu(s-nu) */
-        m3_adj(clink(U, spnm, nu), d1);
-        m3_adj(clink(U, snm, mu), d2);
+        get(ctx, spnm, nu, l);
+        m3_adj(l, d1);
+        get(ctx, snm, mu, l);
+        m3_adj(l, d2);
         m3_mul(d1, d2, t);
-        m3_mul(t, clink(U, snm, nu), st);
+        get(ctx, snm, nu, l);
+        m3_mul(t, l, st);
         for (int e = 0; e < 9; ++e) A[e] += st[e];
     }
-    memcpy(Aout, A, sizeof(A));
+}
+
+static void stored_link3(const void *ctx, int64_t s, int mu, cplx out[9])
+{
+    memcpy(out, clink((const double *)ctx, s, mu), 9 * sizeof(cplx));
+}
+
+void orc3_staple(const int32_t dims[4], const double *U, int64_t s, int mu, double *Aout)
+{
+    staple_with(dims, stored_link3, U, s, mu, (cplx *)Aout);
 }
 
 /* ---------------------------------------------------------- link update */
@@ -297,6 +317,11 @@ void orc3_sweeps_or(const int32_t dims[4], double *U, int32_t nsweeps, int32_t n
 }
 
 /* ------------------------------------------------------------ init / misc */
+void orc3_hot_link(int64_t s, int mu, uint64_t seed, uint32_t replica, double *out)
+{
+    haar3(seed, (uint32_t)s, word2((uint32_t)mu, ORC_TAG_SU3_HOT, replica), (cplx *)out);
+}
+
 void orc3_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint32_t replica)
 {
     int64_t V = orc_volume(dims);
@@ -306,9 +331,27 @@ void orc3_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint3
             if (start == 0) {
                 for (int e = 0; e < 9; ++e) m[e] = (e % 4 == 0) ? 1.0 : 0.0;
             } else {
-                haar3(seed, (uint32_t)s, word2((uint32_t)mu, ORC_TAG_SU3_HOT, replica), m);
+                orc3_hot_link(s, mu, seed, replica, (double *)m);
             }
         }
+}
+
+struct hot_key3 {
+    uint64_t seed;
+    uint32_t replica;
+};
+
+static void hot_link3_of(const void *ctx, int64_t s, int mu, cplx out[9])
+{
+    const struct hot_key3 *k = (const struct hot_key3 *)ctx;
+    orc3_hot_link(s, mu, k->seed, k->replica, (double *)out);
+}
+
+void orc3_hot_staple(const int32_t dims[4], int64_t s, int mu, uint64_t seed, uint32_t replica,
+                     double *A)
+{
+    struct hot_key3 k = {seed, replica};
+    staple_with(dims, hot_link3_of, &k, s, mu, (cplx *)A);
 }
 
 void orc3_reunitarize(const int32_t dims[4], double *U)

@@ -71,6 +71,13 @@ void orc3_sweeps_or(const int32_t dims[4], double *U, int32_t nsweeps, int32_t n
  * complex Gaussian rows, third row the conjugate cross product). */
 void orc3_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint32_t replica);
 
+/* U_mu(s) of the hot start (the orc3_init recipe), computed on its own, and the
+ * staple sum of the hot-start configuration at (s, mu) without building the
+ * lattice: for lattices too large to hold in FP64 on the host. */
+void orc3_hot_link(int64_t s, int mu, uint64_t seed, uint32_t replica, double *out);
+void orc3_hot_staple(const int32_t dims[4], int64_t s, int mu, uint64_t seed, uint32_t replica,
+                     double *A);
+
 /* Gram-Schmidt of rows 0 and 1, row 2 = conj(row0 x row1), for every link. */
 void orc3_reunitarize(const int32_t dims[4], double *U);
 

@@ -42,6 +42,8 @@ def _load():
         "orc3_gauge_transform": (None, [_i32p, _c128p, c_u64, c_u32]),
         "orc3_link_chain": (None, [_c128p, c_d, c_i64, c_u64, _c128p, vp]),
         "orc3_overrelax_link": (None, [_c128p, _c128p, _c128p]),
+        "orc3_hot_link": (None, [c_i64, c_int, c_u64, c_u32, _c128p]),
+        "orc3_hot_staple": (None, [_i32p, c_i64, c_int, c_u64, c_u32, _c128p]),
         "orc3_or_pass": (None, [_i32p, _c128p, c_int, c_int, c_int]),
         "orc3_sweeps_or": (None, [_i32p, _c128p, ctypes.c_int32, ctypes.c_int32, c_u32, c_d,
                                   c_u64, c_u32, ctypes.c_int32, c_int, vp, vp]),
@@ -117,6 +119,20 @@ def sweeps(dims, U, nsweeps, sweep0, beta, seed, replica=0, reunit_every=0, nthr
                         None if ph is None else ph.ctypes.data_as(ctypes.c_void_p),
                         None if lh is None else lh.ctypes.data_as(ctypes.c_void_p))
     return (ph, lh) if history else None
+
+
+def hot_link(s, mu, seed, replica=0):
+    """U_mu(s) of the hot start, computed on its own."""
+    out = np.zeros((3, 3), dtype=np.complex128)
+    _load().orc3_hot_link(int(s), int(mu), np.uint64(seed), int(replica), out)
+    return out
+
+
+def hot_staple(dims, s, mu, seed, replica=0):
+    """Staple sum at (s, mu) of the hot-start configuration, without the lattice."""
+    out = np.zeros((3, 3), dtype=np.complex128)
+    _load().orc3_hot_staple(_dims(dims), int(s), int(mu), np.uint64(seed), int(replica), out)
+    return out
 
 
 def overrelax_link(U, A):

@@ -395,6 +395,46 @@ int su3_test_pass(su3_ctx *c, int mu, int parity)
     SU2_API_END
 }
 
+int su3_test_read_links(su3_ctx *c, int64_t n, const int64_t *sites, int mu, double *out)
+{
+    SU2_API_BEGIN
+    int rc = check3(c);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!sites || !out)) || mu < 0 || mu > 3)
+        return fail(SU2_EINVAL, "n >= 0, non-NULL sites and out, mu 0..3");
+    const int64_t V = volume3(c->dims), vh = V / 2;
+    std::unique_ptr<float[]> buf(new (std::nothrow) float[(size_t)n * 12u + 1u]);
+    if (!buf) return fail(SU2_ENOMEM, "host buffer for the sampled links");
+    for (int64_t i = 0; i < n; ++i) {
+        if (sites[i] < 0 || sites[i] >= V) return fail(SU2_EINVAL, "site out of range");
+        int x[4];
+        coords(c->dims, sites[i], x);
+        const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+        for (int k = 0; k < 3; ++k) {
+            const float4 *src = c->L.links + ((size_t)(mu * 2 + par) * 3 + (size_t)k) * (size_t)vh +
+                                (size_t)(sites[i] >> 1);
+            HIP_TRY(hipMemcpyAsync(buf.get() + 12 * i + 4 * k, src, sizeof(float4),
+                                   hipMemcpyDeviceToHost, c->stream));
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    typedef std::complex<double> cd;
+    for (int64_t i = 0; i < n; ++i) {
+        const float *f = buf.get() + 12 * i;
+        cd m[3][3];
+        for (int e = 0; e < 6; ++e) m[e / 3][e % 3] = cd(f[2 * e], f[2 * e + 1]);
+        m[2][0] = std::conj(m[0][1] * m[1][2] - m[0][2] * m[1][1]);
+        m[2][1] = std::conj(m[0][2] * m[1][0] - m[0][0] * m[1][2]);
+        m[2][2] = std::conj(m[0][0] * m[1][1] - m[0][1] * m[1][0]);
+        for (int e = 0; e < 9; ++e) {
+            out[18 * i + 2 * e] = m[e / 3][e % 3].real();
+            out[18 * i + 2 * e + 1] = m[e / 3][e % 3].imag();
+        }
+    }
+    return SU2_OK;
+    SU2_API_END
+}
+
 int su3_test_or_pass(su3_ctx *c, int mu, int parity)
 {
     SU2_API_BEGIN

@@ -37,6 +37,7 @@ _SIGS3 = {
     "su3_test_pass": (_int, [_vp, _int, _int]),
     "su3_test_or_pass": (_int, [_vp, _int, _int]),
     "su3_overrelax": (_int, [_vp, _i32]),
+    "su3_test_read_links": (_int, [_vp, ctypes.c_int64, _vp, _int, _vp]),
 }
 _bound = False
 
@@ -160,6 +161,13 @@ class Lattice3:
 
     def test_pass(self, mu, parity):
         _check(lib3().su3_test_pass(self.h, int(mu), int(parity)))
+
+    def test_read_links(self, sites, mu):
+        """U_mu at the given sites as complex128 (n, 3, 3), without the whole field."""
+        s = np.ascontiguousarray(sites, dtype=np.int64)
+        out = np.empty((s.size, 3, 3), dtype=np.complex128)
+        _check(lib3().su3_test_read_links(self.h, s.size, _p(s), int(mu), _p(out)))
+        return out
 
     def test_or_pass(self, mu, parity):
         _check(lib3().su3_test_or_pass(self.h, int(mu), int(parity)))

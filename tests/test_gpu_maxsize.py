@@ -47,7 +47,7 @@ def sample_sites(n, seed):
     return np.unique(np.asarray(s, dtype=np.int64))
 
 
-def test_maximum_size_hot_start_pass_and_observables(su2, orc):
+def test_su2_maximum_size_hot_start_pass_and_observables(su2, orc):
     import torch
     announce(f"maximum size {DIMS}: hot start, one pass, observables")
     V = int(np.prod(DIMS))
@@ -88,3 +88,45 @@ def test_maximum_size_hot_start_pass_and_observables(su2, orc):
     # links (in half of all plaquettes) with their staples; it leaves U_3 alone
     assert abs(P0) < 0.01 and 0.05 < P < 0.5
     assert abs(Ls) < 0.01 and 0 <= La < 0.01
+
+
+def test_su3_maximum_size_hot_start_pass_and_observables(su2):
+    """The same for SU(3) (192 B per site: 103 GB of links): hot start, one
+    heat-bath pass against the SU(3) oracle's link-by-link hot start and
+    staples, the untouched links, plaquette and Polyakov loop."""
+    import torch
+    from oracle import su3_oracle as o3
+    torch.cuda.empty_cache()  # the SU(2) test's 34 GB
+    announce(f"SU(3) maximum size {DIMS}: hot start, one pass, observables")
+    V = int(np.prod(DIMS))
+    assert V // 2 < 2 ** 28
+    beta, seed = 6.0, 43
+    flag3, tol3 = 2e-4, 1e-4
+    sites = sample_sites(600, 5)
+    with su2.Lattice3(DIMS, beta, seed, su2.SU2_HOT) as lat:
+        for mu in range(4):
+            want = np.array([o3.hot_link(s, mu, seed) for s in sites])
+            assert np.abs(lat.test_read_links(sites, mu) - want).max() < 2e-5, mu
+        P0 = lat.plaquette()
+        lat.test_pass(2, 1)
+        odd, even = sites[parity(sites) == 1], sites[parity(sites) == 0]
+        got = lat.test_read_links(odd, 2)
+        nflag, worst = 0, 0.0
+        for i, s in enumerate(odd):
+            want, m = o3.heatbath_link(o3.hot_link(s, 2, seed), o3.hot_staple(DIMS, s, 2, seed),
+                                       beta, seed, int(s), 0, 2)
+            if m < flag3:
+                nflag += 1
+                continue
+            worst = max(worst, float(np.abs(got[i] - want).max()))
+        untouched = np.array([o3.hot_link(s, 2, seed) for s in even])
+        assert np.abs(lat.test_read_links(even, 2) - untouched).max() < 2e-5
+        P = lat.plaquette()
+        re, im, mag = lat.polyakov()
+    announce(f"  {len(odd)} updated links: max |gpu - oracle| {worst:.2e}, flagged {nflag}; "
+             f"plaquette {P0:.3e} -> {P:.3e}, Polyakov ({re:.2e}, {im:.2e}), mean |L| {mag:.3f}")
+    assert worst < tol3
+    assert nflag <= int(60 * flag3 * len(odd)) + 3
+    assert abs(P0) < 0.01 and 0.01 < P < 0.5
+    # U_3 untouched: Haar lines of length 4, <|Tr L / 3|> ~ 0.29 per site, mean ~ 0
+    assert abs(re) < 0.01 and abs(im) < 0.01 and 0.2 < mag < 0.4

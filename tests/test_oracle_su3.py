@@ -259,3 +259,15 @@ def test_overrelaxed_chain_keeps_the_plaquette_distribution():
     hb, orl = np.array(hb), np.array(orl)
     err = np.hypot(hb.std(ddof=1), orl.std(ddof=1)) / np.sqrt(6)
     assert abs(hb.mean() - orl.mean()) < 4 * err, (hb.mean(), orl.mean(), err)
+
+
+def test_hot_link_and_staple_without_the_lattice():
+    """The per-link hot start and the hot-start staple equal the full lattice's."""
+    dims = [4, 2, 6, 4]
+    U = o3.init(dims, 1, 17, replica=1)
+    rng = np.random.default_rng(2)
+    for s in rng.integers(0, o2.volume(dims), 15):
+        for mu in range(4):
+            np.testing.assert_array_equal(o3.hot_link(s, mu, 17, 1), U[s, mu])
+            np.testing.assert_allclose(o3.hot_staple(dims, s, mu, 17, 1), o3.staple(dims, U, s, mu),
+                                       atol=1e-14, rtol=0)
