@@ -263,10 +263,17 @@ def test_su3_argument_errors(su2):
         for call in (lambda: lat.set_launch(96), lambda: lat.set_launch(256, 1, 1, 3, 0),
                      lambda: lat.test_pass(4, 0), lambda: lat.test_pass(0, 2),
                      lambda: lat.heatbath_sweep(-1), lambda: lat.heatbath_sweep(1, -2),
-                     lambda: lat.set_beta(float("nan"))):
+                     lambda: lat.set_beta(float("nan")), lambda: lat.overrelax(-2),
+                     lambda: lat.test_read_links([256], 0), lambda: lat.test_read_links([0], 4)):
             with pytest.raises(su2.SU2Error) as e:
                 call()
             assert e.value.code == su2.SU2_EINVAL
+        # empty work: nothing changes, the sweep index stays
+        before = lat.get_links()
+        assert lat.heatbath_sweep(0, history=True).size == 0
+        lat.heatbath_sweep(0)
+        lat.overrelax(0)
+        assert lat.sweep == 0 and np.array_equal(lat.get_links(), before)
         lat.heatbath_sweep(1)
         assert 0.0 < lat.plaquette() < 1.0
 
