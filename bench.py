@@ -798,7 +798,23 @@ def main():
         "autotuned_us_per_sweep": tuned_us,
         "launch": lat.launch(),
     }
+    # the same workload from a cold start, in the same launch
+    launch = lat.launch()
     lat.close()
+    with su2.Lattice(DIMS, BETA, SEED, su2.SU2_COLD, device=dev) as cold:
+        cold.set_launch(launch["block"], launch["flags"], launch["tile_z"], launch["tile_t"],
+                        launch["grid_cap"])
+        cold.sweep_measure(args.warmup, reunit_every=10, meas=meas, hist=hist)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cold.sweep_measure(args.steps, reunit_every=10, meas=meas, hist=hist)
+        torch.cuda.synchronize()
+        dc = time.perf_counter() - t0
+        hc = hist[:args.steps].cpu().numpy()
+    out["cold_start"] = {"workload": "48^4, beta=6.0, cold start; same step and launch as the "
+                                     "headline", "link_updates_per_s": 4 * V * args.steps / dc,
+                         "ms_per_step": 1e3 * dc / args.steps,
+                         "plaquette_mean_last_half": float(hc[args.steps // 2:, 0].mean())}
     if not args.no_configs:
         print("[bench] other workloads", file=sys.stderr, flush=True)
         with torch.cuda.stream(torch.cuda.Stream(device=dev)):  # graphs need a non-null stream
