@@ -686,7 +686,23 @@ def cpu_baseline(sample_sweeps=5):
                       f"beta=6.0 hot-start lattice, {threads} OpenMP threads, "
                       f"{rates[threads][1]:.1f} s",
             "single_thread": {"value": rates[1][0], "cores": 1,
-                              "sample": f"the same sweep on 1 thread, {rates[1][1]:.1f} s"}}
+                              "sample": f"the same sweep on 1 thread, {rates[1][1]:.1f} s"},
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and logical CPUs of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
 
 
 def main():
