@@ -61,6 +61,18 @@ using namespace su2rt;
         }                                                                               \
     } while (0)
 
+// HIP_TRY for one of several asynchronous copies into a host buffer: on failure
+// the copies already enqueued are waited for before the buffer goes away.
+#define HIP_TRY_DRAIN(expr, strm)                                                       \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));              \
+            (void)hipStreamSynchronize(strm);                                           \
+            return SU2_EHIP;                                                            \
+        }                                                                               \
+    } while (0)
+
 namespace {
 
 // Device position of component k of U_mu at half-site h of parity par.
@@ -655,8 +667,8 @@ public:
         HIP_TRY(launch_take(ens(), flags, stream));
         std::vector<double> v(3 * (size_t)n);
         for (int r = 0; r < n; ++r)
-            HIP_TRY(hipMemcpyAsync(&v[3 * r], results(r), 3 * sizeof(double),
-                                   hipMemcpyDeviceToHost, stream));
+            HIP_TRY_DRAIN(hipMemcpyAsync(&v[3 * r], results(r), 3 * sizeof(double),
+                                         hipMemcpyDeviceToHost, stream), stream);
         HIP_TRY(hipStreamSynchronize(stream));
         if (int rc = check_queue()) return rc;
         for (int r = 0; r < n; ++r) {
@@ -672,8 +684,8 @@ public:
         HIP_TRY(launch_counts(ens(), reset, stream));
         std::vector<unsigned long long> v(2 * (size_t)n);
         for (int r = 0; r < n; ++r)
-            HIP_TRY(hipMemcpyAsync(&v[2 * r], results(r) + R_COUNTS, 2 * sizeof(uint64_t),
-                                   hipMemcpyDeviceToHost, stream));
+            HIP_TRY_DRAIN(hipMemcpyAsync(&v[2 * r], results(r) + R_COUNTS, 2 * sizeof(uint64_t),
+                                         hipMemcpyDeviceToHost, stream), stream);
         HIP_TRY(hipStreamSynchronize(stream));
         for (int r = 0; r < n; ++r) {
             if (proposed) proposed[r] = v[2 * r];

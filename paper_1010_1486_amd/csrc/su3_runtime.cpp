@@ -26,6 +26,18 @@ using namespace su3rt;
         }                                                                               \
     } while (0)
 
+// HIP_TRY for one of several asynchronous copies into a host buffer: on failure
+// the copies already enqueued are waited for before the buffer goes away.
+#define HIP_TRY_DRAIN(expr, strm)                                                       \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));              \
+            (void)hipStreamSynchronize(strm);                                           \
+            return SU2_EHIP;                                                            \
+        }                                                                               \
+    } while (0)
+
 struct su3_ctx {
     int32_t dims[4] = {0, 0, 0, 0};
     Lat3 L{};
@@ -405,16 +417,17 @@ int su3_test_read_links(su3_ctx *c, int64_t n, const int64_t *sites, int mu, dou
     const int64_t V = volume3(c->dims), vh = V / 2;
     std::unique_ptr<float[]> buf(new (std::nothrow) float[(size_t)n * 12u + 1u]);
     if (!buf) return fail(SU2_ENOMEM, "host buffer for the sampled links");
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < n; ++i)
         if (sites[i] < 0 || sites[i] >= V) return fail(SU2_EINVAL, "site out of range");
+    for (int64_t i = 0; i < n; ++i) {
         int x[4];
         coords(c->dims, sites[i], x);
         const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
         for (int k = 0; k < 3; ++k) {
             const float4 *src = c->L.links + ((size_t)(mu * 2 + par) * 3 + (size_t)k) * (size_t)vh +
                                 (size_t)(sites[i] >> 1);
-            HIP_TRY(hipMemcpyAsync(buf.get() + 12 * i + 4 * k, src, sizeof(float4),
-                                   hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY_DRAIN(hipMemcpyAsync(buf.get() + 12 * i + 4 * k, src, sizeof(float4),
+                                         hipMemcpyDeviceToHost, c->stream), c->stream);
         }
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
