@@ -210,6 +210,42 @@ __device__ __forceinline__ void st3(float4 *links, uint32_t vh, int mu, int par,
     p2->w = u.e[1][2].i;
 }
 
+// The updated class is read once and written once per pass and by no other
+// site of it: its loads and stores carry the nontemporal hint, which keeps the
+// neighbour classes (read by up to six sites each) resident in the L2.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4f gv4;
+typedef __attribute__((address_space(1))) const v4f gv4c;
+
+__device__ __forceinline__ M3 ld3_stream(const Cls &c, uint32_t h)
+{
+    const uint32_t off = h * 16u;
+    const v4f a = __builtin_nontemporal_load((gv4c *)(c.p0 + off));
+    const v4f b = __builtin_nontemporal_load((gv4c *)(c.p1 + off));
+    const v4f d = __builtin_nontemporal_load((gv4c *)(c.p2 + off));
+    M3 u;
+    u.e[0][0] = Cx{a.x, a.y};
+    u.e[0][1] = Cx{a.z, a.w};
+    u.e[0][2] = Cx{b.x, b.y};
+    u.e[1][0] = Cx{b.z, b.w};
+    u.e[1][1] = Cx{d.x, d.y};
+    u.e[1][2] = Cx{d.z, d.w};
+    complete(u);
+    return u;
+}
+
+__device__ __forceinline__ void st3_stream(float4 *links, uint32_t vh, int mu, int par, uint32_t h,
+                                           const M3 &u)
+{
+    gchar_w *b = (gchar_w *)links + (size_t)((mu * 2 + par) * 3) * vh * 16u + h * 16u;
+    const v4f x0 = {u.e[0][0].r, u.e[0][0].i, u.e[0][1].r, u.e[0][1].i};
+    const v4f x1 = {u.e[0][2].r, u.e[0][2].i, u.e[1][0].r, u.e[1][0].i};
+    const v4f x2 = {u.e[1][1].r, u.e[1][1].i, u.e[1][2].r, u.e[1][2].i};
+    __builtin_nontemporal_store(x0, (gv4 *)b);
+    __builtin_nontemporal_store(x1, (gv4 *)(b + (size_t)vh * 16u));
+    __builtin_nontemporal_store(x2, (gv4 *)(b + (size_t)vh * 32u));
+}
+
 // Rows 0, 1 orthonormalised (Gram-Schmidt in FP32); row 2 stays implied.
 __device__ __forceinline__ void gram_schmidt(M3 &u)
 {
@@ -334,7 +370,7 @@ __device__ __forceinline__ float update_site3(const Lat3 &L, uint32_t gid, int p
             if (MEASURE && nu < MU) add_to(Alow, S);
         }
     }
-    M3 U = ld3(cls(L.links, g.vh, MU, par), h);
+    M3 U = ld3_stream(cls(L.links, g.vh, MU, par), h);
     M3 W = mul_full(U, A);
     if (OR) {
         or_subgroup<0, 1, true>(U, W);
@@ -354,7 +390,7 @@ __device__ __forceinline__ float update_site3(const Lat3 &L, uint32_t gid, int p
     // no-op in exact arithmetic) keeps every link unitary to FP32 rounding.
     gram_schmidt(U);
     complete(U);
-    st3(L.links, g.vh, MU, par, h, U);
+    st3_stream(L.links, g.vh, MU, par, h, U);
     return MEASURE ? retr_mul(U, Alow) * (1.0f / 3.0f) : 0.0f;
 }
 
