@@ -47,7 +47,7 @@ typedef struct su2_ctx su2_ctx;
 
 enum {
     SU2_OK = 0,
-    SU2_EINVAL = -1, /* null pointer, negative count, non-finite beta, bad enum */
+    SU2_EINVAL = -1, /* null pointer, negative count, beta not finite or < 0, bad enum */
     SU2_EODD = -2,   /* an extent is odd or < 2 (the checkerboard needs even extents) */
     SU2_ENOMEM = -3, /* device allocation failed, or caller buffer too small */
     SU2_EHIP = -4,   /* a HIP runtime call failed (message has the HIP error string) */
@@ -71,8 +71,10 @@ size_t su2_scratch_bytes(const int32_t dims[4]);
 
 /* Create a context with library-owned device memory and stream, and write the
  * cold (all links 1) or hot (Haar-random, Philox tag 2) start (Sec. 4: the
- * initialisation kernels).  dims: host array of 4 extents.  The sweep index
- * starts at 0.  Free with su2_destroy. */
+ * initialisation kernels).  dims: host array of 4 extents.  beta: finite and
+ * >= 0 (beta = 4/g^2 of Sec. 2; 0 makes every update Haar-random); the same
+ * range holds for every beta argument of this header.  The sweep index starts
+ * at 0.  Free with su2_destroy. */
 int su2_init(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start);
 
 /* As su2_init, but on caller-owned device memory and stream: links_dev

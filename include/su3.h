@@ -64,7 +64,7 @@ size_t su3_links_bytes(const int32_t dims[4]);
  * link 1; SU2_HOT: Haar-random links (rows 0 and 1 by Gram-Schmidt of complex
  * Gaussian rows from Box-Muller on three Philox blocks).  The sweep index
  * starts at 0.  SU2_EODD / SU2_ERANGE for bad extents, SU2_EINVAL for a NULL
- * pointer, a non-finite beta or a bad start. */
+ * pointer, a beta that is not finite or is negative, or a bad start. */
 int su3_init(su3_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
              void *hip_stream);
 

@@ -1,4 +1,5 @@
-// su2_api.h -- exception barrier of the C ABI (host code only).
+// su2_api.h -- exception barrier and shared argument checks of the C ABI
+// (host code only).
 //
 // No C++ exception may leave an extern "C" entry point: every entry point's
 // body runs inside SU2_API_BEGIN / SU2_API_END (or SU2_API_END_SIZE for the
@@ -9,6 +10,11 @@
 namespace su2rt {
 int api_nomem() noexcept;
 int api_unexpected() noexcept;
+
+// The samplers draw a0 from sqrt(1 - a0^2) exp(alpha a0) with alpha = beta k
+// >= 0 (their alpha < 1 branch accepts with probability exp(alpha (a0 - 1)),
+// which is no probability for alpha < 0): beta must be finite and >= 0.
+inline bool beta_ok(double beta) { return beta >= 0.0 && beta <= 1.7976931348623157e308; }
 }  // namespace su2rt
 
 #define SU2_API_BEGIN try {

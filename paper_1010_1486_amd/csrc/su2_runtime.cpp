@@ -1062,7 +1062,7 @@ static int init_common(su2_ctx **out, const int32_t dims[4], double beta, uint64
     *out = nullptr;
     int rc = check_dims(dims);
     if (rc) return rc;
-    if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
+    if (!beta_ok(beta)) return fail(SU2_EINVAL, "beta must be finite and >= 0");
     if (start != SU2_COLD && start != SU2_HOT) return fail(SU2_EINVAL, "start must be COLD or HOT");
     const size_t need_l = su2_links_bytes(dims) * (f64 ? 2 : 1), need_s = su2_scratch_bytes(dims);
     if (ext) {
@@ -1359,7 +1359,7 @@ int su2_set_beta(su2_ctx *c, double beta)
     SU2_API_BEGIN
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
+    if (!beta_ok(beta)) return fail(SU2_EINVAL, "beta must be finite and >= 0");
     c->E.beta[0] = beta;
     return c->E.upload();
     SU2_API_END
@@ -1452,7 +1452,7 @@ int su2_batch_init(su2_batch **out, int32_t n, const int32_t *dims, const double
     int rc;
     for (int r = 0; r < n; ++r) {
         if ((rc = check_dims(dims + 4 * r))) return rc;
-        if (!std::isfinite(betas[r])) return fail(SU2_EINVAL, "betas must be finite");
+        if (!beta_ok(betas[r])) return fail(SU2_EINVAL, "betas must be finite and >= 0");
         if (starts[r] != SU2_COLD && starts[r] != SU2_HOT)
             return fail(SU2_EINVAL, "start must be COLD or HOT");
     }
@@ -1773,7 +1773,7 @@ int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_
 {
     SU2_API_BEGIN
     if (n < 0 || (n > 0 && (!V_host || !out_host))) return fail(SU2_EINVAL, "bad arguments");
-    if (!std::isfinite(beta) || mu > 3 || replica >= (1u << 26))
+    if (!beta_ok(beta) || mu > 3 || replica >= (1u << 26))
         return fail(SU2_EINVAL, "bad beta, mu or replica");
     if (n >= ((int64_t)1 << 32)) return fail(SU2_ERANGE, "n must be < 2^32");
     if (n == 0) return SU2_OK;
@@ -2198,6 +2198,7 @@ int su2_test_learned_links(su2_nn *n, const float *V_host, const float *Uold_hos
     if (!n || count < 0 || (count > 0 && (!V_host || !Uold_host || !out_host)))
         return fail(SU2_EINVAL, "bad arguments");
     if (!(or_width <= 1.0)) return fail(SU2_EINVAL, "or_width must be <= 1 (< 0: off)");
+    if (!beta_ok(beta)) return fail(SU2_EINVAL, "beta must be finite and >= 0");
     if (!n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
     if (count >= ((int64_t)1 << 32) || mu > 3) return fail(SU2_EINVAL, "bad count or mu");
     if (count == 0) return SU2_OK;

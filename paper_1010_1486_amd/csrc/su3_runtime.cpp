@@ -120,7 +120,7 @@ int su3_init(su3_ctx **out, const int32_t dims[4], double beta, uint64_t seed, i
     *out = nullptr;
     int rc = check_dims(dims);
     if (rc) return rc;
-    if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
+    if (!beta_ok(beta)) return fail(SU2_EINVAL, "beta must be finite and >= 0");
     if (start != SU2_COLD && start != SU2_HOT) return fail(SU2_EINVAL, "start must be COLD or HOT");
     su3_ctx *c = new (std::nothrow) su3_ctx();
     if (!c) return fail(SU2_ENOMEM, "host allocation failed");
@@ -346,7 +346,7 @@ int su3_set_beta(su3_ctx *c, double beta)
     SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
-    if (!std::isfinite(beta)) return fail(SU2_EINVAL, "beta must be finite");
+    if (!beta_ok(beta)) return fail(SU2_EINVAL, "beta must be finite and >= 0");
     c->L.beta = (float)beta;
     return SU2_OK;
     SU2_API_END

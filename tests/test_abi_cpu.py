@@ -35,10 +35,14 @@ def test_odd_or_small_extents_rejected(dims):
 
 
 def test_bad_arguments_rejected():
-    for beta in (float("nan"), float("inf")):
+    # the samplers need alpha = beta k >= 0
+    for beta in (float("nan"), float("inf"), -0.5, -1e-300):
         with pytest.raises(su2.SU2Error) as e:
             su2.su2_init([4, 4, 4, 4], beta, 1, su2.SU2_COLD)
         assert e.value.code == su2.SU2_EINVAL
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_test_heatbath_links(np.ones((2, 4), np.float32), -1.0, 1, 0, 0)
+    assert e.value.code == su2.SU2_EINVAL
     with pytest.raises(su2.SU2Error) as e:
         su2.su2_init([4, 4, 4, 4], 2.0, 1, 7)
     assert e.value.code == su2.SU2_EINVAL
@@ -156,8 +160,9 @@ def test_su3_sizes_and_bad_arguments():
     assert lib.su3_init(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), 6.0, 1, 0,
                         None) == su2.SU2_EODD
     d = np.array([4, 4, 4, 4], dtype=np.int32)
-    assert lib.su3_init(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), float("nan"), 1, 0,
-                        None) == su2.SU2_EINVAL
+    for beta in (float("nan"), -6.0):
+        assert lib.su3_init(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), beta, 1, 0,
+                            None) == su2.SU2_EINVAL
     assert lib.su3_init(ctypes.byref(h), d.ctypes.data_as(ctypes.c_void_p), 6.0, 1, 7,
                         None) == su2.SU2_EINVAL
     assert lib.su3_init(None, d.ctypes.data_as(ctypes.c_void_p), 6.0, 1, 0, None) == su2.SU2_EINVAL

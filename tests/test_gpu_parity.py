@@ -77,6 +77,35 @@ def test_every_pass_matches_oracle(su2, orc, dims):
         assert total_flag <= max_flags(4 * int(np.prod(dims)))
 
 
+@pytest.mark.parametrize("beta", [0.0, 60.0], ids=["beta0-haar", "beta60"])
+def test_pass_at_extreme_couplings(su2, orc, beta):
+    """The degenerate couplings: beta = 0 (alpha = 0 at every site, so every
+    updated link is Haar-random: only the alpha < 1 branch, which then accepts
+    every trial) and beta = 60 (alpha up to ~400: Kennedy-Pendleton with
+    1 - a0 ~ 1e-3), every pass from the same seeded links on both sides."""
+    dims = [4, 6, 2, 8]
+    announce(f"per-pass parity at beta={beta}")
+    links = inputs.random_links(dims, 77, spread=0.6)
+    seed = 4711
+    par_of = parities(orc, dims)
+    with su2.Lattice(dims, beta, seed) as lat:
+        lat.set_sweep(11)
+        total_flag = 0
+        for mu in range(4):
+            for p in range(2):
+                lat.set_links(links)
+                U = links.astype(np.float64)
+                margin = orc.do_pass(dims, U, mu, p, 11, beta, seed, want_margin=True)
+                lat.test_pass(mu, p)
+                got = lat.get_links()
+                err, nflag = compare_pass(got, U, margin, p, mu, par_of)
+                total_flag += nflag
+                assert err < 1e-5, (mu, p, err)
+                upd = got[par_of == p, mu].astype(np.float64)
+                assert np.abs((upd ** 2).sum(axis=1) - 1.0).max() < 2e-6
+        assert total_flag <= max_flags(4 * int(np.prod(dims)))
+
+
 @pytest.mark.parametrize("dims", [[4, 4, 4, 4], [4, 6, 2, 8]], ids=lambda d: "x".join(map(str, d)))
 def test_hot_start_and_sweeps_match_oracle(su2, orc, dims):
     """Config-1 style: the hot start (Philox seed 1) against the oracle's; then

@@ -66,8 +66,10 @@ def test_su3_starts_match_oracle(su2, o3, dims):
 
 @pytest.mark.parametrize("dims,spread,beta", [([2, 2, 2, 2], None, 5.7), ([2, 4, 2, 6], 0.4, 6.0),
                                               ([4, 4, 4, 4], None, 5.7), ([6, 6, 6, 10], 0.3, 6.0),
-                                              ([8, 4, 6, 4], 0.15, 8.0)],
-                         ids=["2^4-haar", "2x4x2x6", "4^4-haar", "6^3x10-ordered", "8x4x6x4-cold"])
+                                              ([8, 4, 6, 4], 0.15, 8.0), ([4, 4, 4, 4], None, 0.0),
+                                              ([4, 6, 2, 8], 0.15, 40.0)],
+                         ids=["2^4-haar", "2x4x2x6", "4^4-haar", "6^3x10-ordered", "8x4x6x4-cold",
+                              "4^4-beta0", "4x6x2x8-beta40"])
 def test_su3_every_pass_matches_oracle(su2, o3, dims, spread, beta):
     """All eight (mu, parity) passes from the same links; V/2 = 1080 for
     6^3 x 10 spans four full workgroups and a ragged tail."""
