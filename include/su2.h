@@ -32,6 +32,9 @@
  * the context's stream; functions returning host values synchronise it.
  * Threading: contexts are independent; one context must not be used from two
  * host threads at once.
+ * Device: a context (lattice, batch, network) lives on the HIP device that was
+ * current when it was created; every later call on it must be made with that
+ * device current again (hipSetDevice), as its stream and memory belong to it.
  */
 #ifndef SU2_H
 #define SU2_H

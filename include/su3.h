@@ -39,7 +39,8 @@
  * Errors: the SU2_* codes of su2.h; su2_last_error() gives the message.  Calls
  * documented as "enqueue" return after launching work on the context's stream;
  * calls returning host values synchronise it.  One context must not be used
- * from two host threads at once.
+ * from two host threads at once, and every call on it must be made with the
+ * device that was current at su3_init current again.
  */
 #ifndef SU3_H
 #define SU3_H
