@@ -677,8 +677,8 @@ def scale_setting(su2, torch, dev, betas=POLYAKOV_BETAS, therm=300, nmeas=40, ev
         "fp32_tflops": flop / dt / 1e12, "fp32_frac": flop / dt / 1e12 / FP32_PEAK_TFLOPS,
         "gathered_bytes_per_site": 12 * 40 * 16, "gathered_tbs": gathered / dt / 1e12,
         "hbm_algorithmic_frac": 64 * V / dt / 1e9 / HBM_PEAK_GBS,
-        "note": "one thread per site builds every loop link by link: a small fraction of both "
-                "the HBM and the FP32 peaks, with 480 16-byte gathers per site served by L1/L2"}
+        "note": "one thread per site and plane; the links of each stage of the loop lines "
+                "are gathered together (480 16-byte gathers per site, served by L1/L2)"}
     return out
 
 

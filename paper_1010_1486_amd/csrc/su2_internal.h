@@ -241,7 +241,7 @@ hipError_t launch_reunitarize64(const Ens &e, hipStream_t stream);
 // receives kWilsonMax^2 sums over sites and the 12 ordered planes,
 // sums[(R - 1) kWilsonMax + (T - 1)] (divide by 12 V).
 constexpr int kWilsonMax = 4;
-inline uint32_t wilson_blocks(const Ens &e) { return (uint32_t)((2ull * e.max_vh + 255) / 256); }
+inline uint32_t wilson_blocks(const Ens &e) { return 12u * (uint32_t)((2ull * e.max_vh + 255) / 256); }
 hipError_t launch_wilson(const Ens &e, int rmax, int tmax, double *part, double *sums,
                          hipStream_t stream);
 // Workgroups of `block` threads of the queue kernel the device holds at once.

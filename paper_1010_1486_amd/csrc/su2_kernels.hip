@@ -579,31 +579,32 @@ __global__ __launch_bounds__(1024) void small_sweeps_kernel(const Rep *__restric
 // A_R = L_mu(s, R), C_T = L_nu(s + R mu, T), B_T = L_nu(s, T),
 // D_T = L_mu(s + T nu, R), L_mu(x, n) = U_mu(x) ... U_mu(x + (n - 1) mu).
 // The lines are extended one link at a time (R outer, T inner), so a plane
-// costs R + T + 2RT link loads for all R <= rmax, T <= tmax.  One thread per
-// site (both parities); the per-site sums over the planes are FP32, the sum
-// over a workgroup FP64 into part[block * N * N + (R - 1) N + (T - 1)].
+// costs R + T + 2RT link loads for all R, T <= N.  One thread per site (both
+// parities) and plane; per-site values FP32, the sum over a workgroup FP64
+// into part[slot * N * N + (R - 1) N + (T - 1)], slot = plane * blocks + block.
 
-// U_dir at c0 + da * e_a + db * e_b (a != b, 0 <= da, db < extent).
-__device__ __forceinline__ Q link_off(const Rep &R, const int *n, const int *c0, int a, int da,
-                                      int b, int db, int dir)
+// Site-index offset of k steps along a direction from coordinate c (extent n,
+// canonical stride st), periodic for any k >= 0.
+__device__ __forceinline__ int32_t step_off(int c, int k, int n, int32_t st)
 {
-    int c[4] = {c0[0], c0[1], c0[2], c0[3]};
-    c[a] += da;
-    if (c[a] >= n[a]) c[a] -= n[a];
-    c[b] += db;
-    if (c[b] >= n[b]) c[b] -= n[b];
-    const Geom &g = R.g;
-    return ldq(R.links, g.vh, dir, (c[0] + c[1] + c[2] + c[3]) & 1, hidx(g, c[0], c[1], c[2], c[3]));
+    return ((c + k) % n - c) * st;
 }
 
+__device__ __forceinline__ int pick4(int a, int v0, int v1, int v2, int v3)
+{
+    return a == 0 ? v0 : a == 1 ? v1 : a == 2 ? v2 : v3;
+}
+
+// grid (blocks over the V sites, 12 ordered planes): one thread per site and
+// plane, partial sums per (plane, workgroup).
 template <int N>
 __global__ __launch_bounds__(256) void wilson_kernel(const Rep *__restrict__ reps, int rmax,
                                                      int tmax, double *__restrict__ part)
 {
     const Rep &R = reps[0];
     const Geom &g = R.g;
-    const int n[4] = {g.nx, g.ny, g.nz, g.nt};
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int o = (int)blockIdx.y, mu = o / 3, nu = o % 3 < mu ? o % 3 : o % 3 + 1;
     float w[N][N];
 #pragma unroll
     for (int r = 0; r < N; ++r)
@@ -613,52 +614,88 @@ __global__ __launch_bounds__(256) void wilson_kernel(const Rep *__restrict__ rep
         const int par = i >= g.vh ? 1 : 0;
         int c0[4];
         decode(g, par ? i - g.vh : i, par, c0[0], c0[1], c0[2], c0[3]);
+        const int32_t sy = g.nx, sz = g.nx * g.ny, stt = g.nx * g.ny * g.nz;
+        // canonical index of the site; the link k steps along mu and l along nu
+        // from it lies at s0 + oa[k] + ob[l] and has parity par + k + l
+        const uint32_t s0 = (uint32_t)c0[0] + (uint32_t)sy * (uint32_t)c0[1] +
+                            (uint32_t)sz * (uint32_t)c0[2] + (uint32_t)stt * (uint32_t)c0[3];
+        const int ca = pick4(mu, c0[0], c0[1], c0[2], c0[3]);
+        const int na = pick4(mu, g.nx, g.ny, g.nz, g.nt);
+        const int32_t sa = pick4(mu, 1, sy, sz, stt);
+        const int cb = pick4(nu, c0[0], c0[1], c0[2], c0[3]);
+        const int nb = pick4(nu, g.nx, g.ny, g.nz, g.nt);
+        const int32_t sb = pick4(nu, 1, sy, sz, stt);
+        int32_t oa[N + 1], ob[N + 1];
+#pragma unroll
+        for (int k = 0; k <= N; ++k) {
+            oa[k] = step_off(ca, k, na, sa);
+            ob[k] = step_off(cb, k, nb, sb);
+        }
+        // the two parities of each direction's class
+        const Arr Amu[2] = {arr(R.links, g.vh, mu, par), arr(R.links, g.vh, mu, par ^ 1)};
+        const Arr Anu[2] = {arr(R.links, g.vh, nu, par), arr(R.links, g.vh, nu, par ^ 1)};
+#define SU2_WL(A, k, l) ld(A[((k) + (l)) & 1], (s0 + (uint32_t)(oa[k] + ob[l])) >> 1)
+        // every size up to N x N is computed without branches, so that the loads
+        // can be issued ahead of the products; sizes beyond (rmax, tmax) are not
+        // reported (the offsets wrap periodically, so every load stays inside)
+        // the links of each stage are loaded together (the scheduling barrier
+        // keeps them ahead of the products that use them)
         const Q one{1.0f, 0.0f, 0.0f, 0.0f};
-        for (int mu = 0; mu < 4; ++mu)
-            for (int nu = 0; nu < 4; ++nu) {
-                if (nu == mu) continue;
-                Q B[N], D[N];
-                Q P = one;
+        Q B[N], D[N], L[2 * N + 1];
 #pragma unroll
-                for (int t = 0; t < N; ++t) {
-                    if (t < tmax) P = qmul(P, link_off(R, n, c0, nu, t, mu, 0, nu));
-                    B[t] = P;
-                    D[t] = one;
-                }
-                Q A = one;
+        for (int t = 0; t < N; ++t) L[t] = SU2_WL(Anu, 0, t);
+        __builtin_amdgcn_sched_barrier(0);
+        Q P = one;
 #pragma unroll
-                for (int r = 0; r < N; ++r) {
-                    if (r >= rmax) continue;
-                    A = qmul(A, link_off(R, n, c0, mu, r, nu, 0, mu));
-                    Q C = one;
+        for (int t = 0; t < N; ++t) {
+            P = qmul(P, L[t]);
+            B[t] = P;
+            D[t] = one;
+        }
+        Q A = one;
 #pragma unroll
-                    for (int t = 0; t < N; ++t) {
-                        if (t >= tmax) continue;
-                        D[t] = qmul(D[t], link_off(R, n, c0, mu, r, nu, t + 1, mu));
-                        C = qmul(C, link_off(R, n, c0, mu, r + 1, nu, t, nu));
-                        w[r][t] += qdot(qmul(A, C), qmul(B[t], D[t]));
-                    }
-                }
+        for (int r = 0; r < N; ++r) {
+            L[2 * N] = SU2_WL(Amu, r, 0);
+#pragma unroll
+            for (int t = 0; t < N; ++t) {
+                L[2 * t] = SU2_WL(Amu, r, t + 1);
+                L[2 * t + 1] = SU2_WL(Anu, r + 1, t);
             }
+            __builtin_amdgcn_sched_barrier(0);
+            A = qmul(A, L[2 * N]);
+            Q C = one;
+#pragma unroll
+            for (int t = 0; t < N; ++t) {
+                D[t] = qmul(D[t], L[2 * t]);
+                C = qmul(C, L[2 * t + 1]);
+                w[r][t] = qdot(qmul(A, C), qmul(B[t], D[t]));
+            }
+        }
+        (void)rmax;
+        (void)tmax;
+#undef SU2_WL
     }
+    const uint32_t slot = blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
         for (int t = 0; t < N; ++t) {
             const double bs = block_sum((double)w[r][t]);
-            if (threadIdx.x == 0) part[(size_t)blockIdx.x * N * N + r * N + t] = bs;
+            if (threadIdx.x == 0) part[(size_t)slot * N * N + r * N + t] = bs;
         }
 }
 
-// Thread k: the sum of partial k over the workgroups, in workgroup order.
-__global__ void wilson_sum_kernel(const double *__restrict__ part, uint32_t nblocks, int nn,
-                                  double *__restrict__ out)
+// Workgroup k: the sum of partial k over all slots in a fixed order (thread j
+// takes slots j, j + 256, ... in turn, then the fixed-order block sum).
+__global__ __launch_bounds__(256) void wilson_sum_kernel(const double *__restrict__ part,
+                                                         uint32_t nslots, int nn,
+                                                         double *__restrict__ out)
 {
-    const int k = threadIdx.x;
-    if (k >= nn) return;
+    const int k = (int)blockIdx.x;
     double s = 0.0;
-    for (uint32_t b = 0; b < nblocks; ++b) s += part[(size_t)b * nn + k];
-    out[k] = s;
+    for (uint32_t b = threadIdx.x; b < nslots; b += blockDim.x) s += part[(size_t)b * nn + k];
+    s = block_sum(s);
+    if (threadIdx.x == 0) out[k] = s;
 }
 
 // ------------------------------------------------------------- work queue
@@ -1140,12 +1177,12 @@ hipError_t launch_wilson(const Ens &e, int rmax, int tmax, double *part, double 
                          hipStream_t stream)
 {
     const uint32_t nb = nblk(2ull * e.max_vh, 256);
-    hipLaunchKernelGGL(wilson_kernel<kWilsonMax>, dim3(nb), dim3(256), 0, stream, e.reps, rmax,
-                       tmax, part);
+    hipLaunchKernelGGL(wilson_kernel<kWilsonMax>, dim3(nb, 12), dim3(256), 0, stream, e.reps,
+                       rmax, tmax, part);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(wilson_sum_kernel, dim3(1), dim3(64), 0, stream, part, nb,
-                       kWilsonMax * kWilsonMax, sums);
+    hipLaunchKernelGGL(wilson_sum_kernel, dim3(kWilsonMax * kWilsonMax), dim3(256), 0, stream,
+                       part, 12u * nb, kWilsonMax * kWilsonMax, sums);
     return hipGetLastError();
 }
 

@@ -12,8 +12,10 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("dims,rt", [([8, 6, 8, 10], (4, 4)), ([4, 4, 4, 6], (3, 2)),
-                                     ([16, 16, 16, 16], (4, 4))],
-                         ids=["8x6x8x10", "4x4x4x6", "16^4"])
+                                     ([16, 16, 16, 16], (4, 4)), ([2, 4, 6, 8], (1, 1)),
+                                     ([6, 10, 8, 6], (4, 2)), ([10, 6, 6, 8], (2, 4))],
+                         ids=["8x6x8x10", "4x4x4x6", "16^4", "2x4x6x8", "6x10x8x6-r4t2",
+                              "10x6x6x8-r2t4"])
 def test_wilson_loops_match_oracle(su2, orc, dims, rt):
     announce(f"wilson loops dims={dims} rt={rt}")
     links = inputs.random_links(dims, 40 + sum(dims), spread=0.6)
