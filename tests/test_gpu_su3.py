@@ -179,6 +179,54 @@ def test_su3_reunitarize_matches_oracle(su2, o3):
     assert su3_defect(got) < 2e-6
 
 
+def test_su3_history_longer_than_one_chunk(su2):
+    """The plaquette history of one call crosses the 1024-entry device
+    history (the call copies it out in chunks) and equals that of two
+    shorter calls over the same sweeps, entry for entry."""
+    dims = [2, 2, 2, 2]
+    announce("su3 history across the 1024-sweep chunk")
+    with su2.Lattice3(dims, 5.5, 31, su2.SU2_HOT) as a:
+        ha = a.heatbath_sweep(1030, reunit_every=10, history=True)
+        la = a.get_links()
+    with su2.Lattice3(dims, 5.5, 31, su2.SU2_HOT) as b:
+        hb = np.concatenate([b.heatbath_sweep(1000, reunit_every=10, history=True),
+                             b.heatbath_sweep(30, reunit_every=10, history=True)])
+        assert np.array_equal(b.get_links(), la)
+    assert ha.shape == (1030,) and np.array_equal(ha, hb)
+    assert np.all(np.abs(ha) <= 1.0) and len(np.unique(ha[1000:])) > 20
+
+
+def test_su3_checkpoint_and_resume_is_bitwise(su2):
+    """A run stopped after a heat-bath sweep, two over-relaxation sweeps and a
+    reunitarisation, saved through the host exchange (FP32 rows widened to FP64
+    and rounded back exactly) and the sweep index, and resumed in a new
+    context, ends bit for bit where the uninterrupted run does."""
+    dims = [6, 4, 8, 6]
+    announce("su3 checkpoint / resume")
+
+    def tail(lat):
+        lat.heatbath_sweep(3, reunit_every=2)
+        lat.overrelax(1)
+        lat.heatbath_sweep(1)
+
+    with su2.Lattice3(dims, 5.9, 23, su2.SU2_HOT) as ref:
+        ref.heatbath_sweep(1)
+        ref.overrelax(2)
+        ref.reunitarize()
+        saved, sweep = ref.get_links(), ref.sweep
+        tail(ref)
+        want, want_sweep = ref.get_links(), ref.sweep
+        want_p = ref.plaquette()
+    assert sweep == 1 and want_sweep == 5
+    with su2.Lattice3(dims, 5.9, 23, su2.SU2_COLD) as lat:
+        lat.set_links(saved)
+        lat.set_sweep(sweep)
+        tail(lat)
+        assert lat.sweep == want_sweep
+        assert np.array_equal(lat.get_links(), want)
+        assert lat.plaquette() == want_p
+
+
 @pytest.mark.parametrize("launch", [(64, 0, 0, 1, 1), (128, 1, 1, 2, 4), (192, 1, 0, 0, 0),
                                     (256, 0, 1, 8, 8)])
 def test_su3_launch_shape_does_not_change_results(su2, launch):
