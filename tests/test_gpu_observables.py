@@ -132,6 +132,24 @@ def test_resume_and_determinism(su2):
     np.testing.assert_array_equal(hs[0], hs[1])
 
 
+def test_set_beta_applies_to_later_sweeps(su2):
+    """Sweeps after su2_set_beta equal those of a lattice created at the new
+    coupling from the same links and sweep index, bit for bit."""
+    announce("set_beta")
+    dims = [6, 4, 4, 8]
+    with su2.Lattice(dims, 1.7, 9, su2.SU2_HOT) as a:
+        a.heatbath_sweep(2)
+        mid = a.get_links()
+        a.set_beta(2.6)
+        a.heatbath_sweep(3)
+        got = a.get_links()
+    with su2.Lattice(dims, 2.6, 9, su2.SU2_COLD) as b:
+        b.set_links(mid)
+        b.set_sweep(2)
+        b.heatbath_sweep(3)
+        np.testing.assert_array_equal(b.get_links(), got)
+
+
 def test_replica_changes_stream(su2):
     dims = [4, 4, 4, 4]
     with su2.Lattice(dims, 2.2, 5, su2.SU2_HOT) as a, su2.Lattice(dims, 2.2, 5, su2.SU2_HOT) as b:

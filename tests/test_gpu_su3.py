@@ -196,6 +196,28 @@ def test_su3_history_longer_than_one_chunk(su2):
     assert np.all(np.abs(ha) <= 1.0) and len(np.unique(ha[1000:])) > 20
 
 
+def test_su3_set_beta_applies_to_later_sweeps(su2):
+    """Sweeps after su3_set_beta are those of a lattice created at the new
+    coupling from the same links and sweep index, bit for bit; sweeps before
+    it are untouched by it."""
+    dims = [4, 6, 4, 4]
+    announce("su3 set_beta")
+    with su2.Lattice3(dims, 5.0, 41, su2.SU2_HOT) as a:
+        a.heatbath_sweep(2)
+        mid = a.get_links()
+        a.set_beta(6.2)
+        a.heatbath_sweep(2)
+        got = a.get_links()
+    with su2.Lattice3(dims, 6.2, 41, su2.SU2_COLD) as b:
+        b.set_links(mid)
+        b.set_sweep(2)
+        b.heatbath_sweep(2)
+        assert np.array_equal(b.get_links(), got)
+    with su2.Lattice3(dims, 5.0, 41, su2.SU2_HOT) as c:
+        c.heatbath_sweep(2)
+        assert np.array_equal(c.get_links(), mid)
+
+
 def test_su3_checkpoint_and_resume_is_bitwise(su2):
     """A run stopped after a heat-bath sweep, two over-relaxation sweeps and a
     reunitarisation, saved through the host exchange (FP32 rows widened to FP64
