@@ -485,7 +485,9 @@ class NN:
 # ------------------------------------------------------------ convenience
 class Lattice:
     """A lattice whose links and scratch are torch tensors on a GPU, run on
-    torch's current stream of that device (su2_init_ext)."""
+    torch's current stream of that device (su2_init_ext).  The context is
+    created with `device` current; later calls expect it to be the current
+    device (as on a one-GPU machine, or inside torch.cuda.device(device))."""
 
     def __init__(self, dims, beta, seed, start=SU2_COLD, device="cuda:0"):
         import torch
@@ -499,8 +501,9 @@ class Lattice:
         self.links_t = torch.empty(lb, dtype=torch.uint8, device=self.device)
         self.scratch_t = torch.empty(sb, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
-        self.h = su2_init_ext(self.dims, beta, seed, start, self.links_t.data_ptr(), lb,
-                              self.scratch_t.data_ptr(), sb, self.stream.cuda_stream)
+        with torch.cuda.device(self.device):  # the context belongs to this device
+            self.h = su2_init_ext(self.dims, beta, seed, start, self.links_t.data_ptr(), lb,
+                                  self.scratch_t.data_ptr(), sb, self.stream.cuda_stream)
 
     def close(self):
         if getattr(self, "h", None) is not None:
@@ -618,8 +621,9 @@ class Lattice64(Lattice):
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
         h = _vp()
-        _check(lib().su2_init_f64(ctypes.byref(h), _p(_dims(self.dims)), float(beta), int(seed),
-                                  int(start), _vp(self.stream.cuda_stream)))
+        with torch.cuda.device(self.device):  # the context belongs to this device
+            _check(lib().su2_init_f64(ctypes.byref(h), _p(_dims(self.dims)), float(beta),
+                                      int(seed), int(start), _vp(self.stream.cuda_stream)))
         self.h = h
 
     def get_links(self):
@@ -647,8 +651,9 @@ class Batch:
         self.betas = b.copy()
         self.stream = torch.cuda.current_stream(self.device)
         h = _vp()
-        _check(lib().su2_batch_init(ctypes.byref(h), self.n, _p(d), _p(b), _p(st), int(seed),
-                                    _vp(self.stream.cuda_stream)))
+        with torch.cuda.device(self.device):  # the batch belongs to this device
+            _check(lib().su2_batch_init(ctypes.byref(h), self.n, _p(d), _p(b), _p(st),
+                                        int(seed), _vp(self.stream.cuda_stream)))
         self.h = h
 
     def close(self):

@@ -76,7 +76,9 @@ def su3_links_bytes(dims):
 
 class Lattice3:
     """An SU(3) lattice (library-owned device memory) on torch's current stream
-    of the device.  Links are exchanged as complex128 arrays (V, 4, 3, 3)."""
+    of the device.  Links are exchanged as complex128 arrays (V, 4, 3, 3).  The
+    lattice is created on `device`; later calls expect it to be the current
+    device (as on a one-GPU machine, or inside torch.cuda.device(device))."""
 
     def __init__(self, dims, beta, seed, start=SU2_COLD, device="cuda:0"):
         import torch
@@ -85,8 +87,9 @@ class Lattice3:
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
         h = _vp()
-        _check(lib3().su3_init(ctypes.byref(h), _p(_su2._dims(self.dims)), float(beta),
-                               int(seed), int(start), _vp(self.stream.cuda_stream)))
+        with torch.cuda.device(self.device):  # the context belongs to this device
+            _check(lib3().su3_init(ctypes.byref(h), _p(_su2._dims(self.dims)), float(beta),
+                                   int(seed), int(start), _vp(self.stream.cuda_stream)))
         self.h = h
 
     def close(self):
