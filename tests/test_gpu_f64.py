@@ -134,3 +134,28 @@ def test_f32_against_f64_at_equal_seeds(su2, orc):
     assert 1e-9 < worst < 1e-5
     assert big < 1e-3
     assert abs(p32 - p64) < 1e-5 and abs(s32 - s64) < 1e-4
+
+
+def test_f64_graph_replay_equals_direct_sweeps(su2):
+    """FP64 sweeps with reunitarisation and the fused plaquette, captured once
+    and replayed several times with eager work and synchronisation between the
+    replays, end bit for bit where the same sweeps run directly, and so do
+    their measurement histories."""
+    import torch
+    announce("fp64 graph replay == direct")
+    dims = [8, 6, 4, 8]
+    side = torch.cuda.Stream()  # capture needs a non-null stream
+    with torch.cuda.stream(side):
+        with su2.Lattice64(dims, 2.4, 51, su2.SU2_HOT) as a, \
+                su2.Lattice64(dims, 2.4, 51, su2.SU2_HOT) as g:
+            ha = a.sweep_measure(12, reunit_every=4, meas=3).cpu().numpy()
+            hg = torch.zeros((12, 3), dtype=torch.float64, device="cuda")
+            g.capture(4, reunit_every=4, meas=3, hist=hg)
+            for k in range(3):
+                g.replay(1)
+                g.synchronize()
+                assert g.sweep == 4 * (k + 1)
+                _ = g.plaquette()  # eager work between the replays
+            np.testing.assert_array_equal(hg.cpu().numpy(), ha)
+            np.testing.assert_array_equal(g.get_links(), a.get_links())
+    torch.cuda.synchronize()
