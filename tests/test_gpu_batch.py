@@ -72,6 +72,20 @@ def test_graph_replay_equals_direct(su2):
             y.replay(3)
             assert y.sweep == 6
             np.testing.assert_array_equal(x.get_links(), y.get_links())
+        # every replay against the eager sweeps, with eager work and a
+        # synchronisation between the replays
+        with su2.Lattice([8, 6, 8, 4], 2.5, 4, su2.SU2_HOT) as x, \
+                su2.Lattice([8, 6, 8, 4], 2.5, 4, su2.SU2_HOT) as y:
+            hx = x.sweep_measure(9, reunit_every=3, meas=3).cpu().numpy()
+            hy = torch.zeros((9, 3), dtype=torch.float64, device="cuda")
+            y.capture(3, reunit_every=3, meas=3, hist=hy)
+            for k in range(3):
+                y.replay(1)
+                y.synchronize()
+                np.testing.assert_array_equal(hy[3 * k:3 * k + 3].cpu().numpy(),
+                                              hx[3 * k:3 * k + 3])
+                _ = y.plaquette(), y.polyakov()
+            np.testing.assert_array_equal(x.get_links(), y.get_links())
     torch.cuda.synchronize()
 
 
