@@ -187,39 +187,3 @@ def test_batched_workload_in_autotuned_launch(su2, orc, workload):
         bad = int((np.abs(got[r] - U).max(axis=2) > 1e-5).sum())
         assert bad <= 500 * nflag, (workload, r, launch, bad, nflag)
         assert bad < 0.01 * U.shape[0] * 4, (workload, r, launch, bad)
-
-
-def test_plain_heat_bath_sustains_60_percent_of_hbm_at_48_4(su2):
-    """The performance floor of the plain heat bath at 48^4: at least 60 % of
-    the 8 TB/s HBM peak in algorithmic bytes (128 B per link update), both per
-    pass launch (HIP events on the lattice's stream, sweep order) and over
-    whole sweeps with the fused plaquette and reunitarisation every 10, in the
-    launch the benchmark uses (XCD remap, 8 x 8 tiles, block 256)."""
-    import time
-
-    import torch
-    announce("48^4 throughput floor: 60 % of 8 TB/s")
-    V = int(np.prod(DIMS))
-    need = 0.60 * 8.0e12
-    with su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT) as lat:
-        lat.set_launch(256, 1, 8, 8)
-        lat.sweep_measure(20, reunit_every=10)
-        torch.cuda.synchronize()
-        s = lat.stream
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(s):
-            e0.record(s)
-            for i in range(80):
-                lat.test_pass((i // 2) % 4, i % 2)
-            e1.record(s)
-        e1.synchronize()
-        pass_s = e0.elapsed_time(e1) * 1e-3 / 80
-        t0 = time.perf_counter()
-        lat.sweep_measure(100, reunit_every=10)
-        torch.cuda.synchronize()
-        sweep_s = (time.perf_counter() - t0) / 100
-    pass_bw = 128 * (V // 2) / pass_s
-    sweep_bw = 128 * 4 * V / sweep_s
-    announce(f"  pass {pass_s * 1e6:.1f} us = {pass_bw / 8e12:.1%} of 8 TB/s; sweep "
-             f"{sweep_s * 1e6:.0f} us = {sweep_bw / 8e12:.1%}")
-    assert pass_bw >= need and sweep_bw >= need

@@ -440,29 +440,3 @@ def test_su3_heatbath_with_overrelaxation_matches_oracle_chains(su2, o3):
     announce(f"  gpu HB+3OR {g.mean():.5f}({dg:.5f}) oracle HB {o.mean():.5f}({do:.5f}) "
              f"pull {pull:.2f}")
     assert abs(pull) < 4
-
-
-def test_su3_pass_throughput_floor_at_48_4(su2):
-    """Regression floor of the SU(3) pass at 48^4 in the benchmarked launch:
-    at least 45 % of 8 TB/s in algorithmic bytes (432 B per link update; the
-    kernel measures 53-56 % from machine to machine), per pass launch in sweep
-    order (HIP events on the lattice's stream)."""
-    import torch
-    announce("su3 48^4 pass throughput floor: 45 % of 8 TB/s")
-    dims = [48, 48, 48, 48]
-    V = int(np.prod(dims))
-    with su2.Lattice3(dims, 6.0, 3, su2.SU2_HOT) as lat:
-        lat.heatbath_sweep(10)
-        lat.synchronize()
-        s = lat.stream
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(s):
-            e0.record(s)
-            for i in range(80):
-                lat.test_pass((i // 2) % 4, i % 2)
-            e1.record(s)
-        e1.synchronize()
-        pass_s = e0.elapsed_time(e1) * 1e-3 / 80
-    frac = 432 * (V // 2) / pass_s / 8e12
-    announce(f"  pass {pass_s * 1e6:.1f} us = {frac:.1%} of 8 TB/s")
-    assert frac >= 0.45
