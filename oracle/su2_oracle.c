@@ -384,17 +384,29 @@ void orc_pass(const int32_t dims[4], double *U, int mu, int parity, uint32_t swe
 
 void orc_sweeps(const int32_t dims[4], double *U, int32_t nsweeps, uint32_t sweep0,
                 double beta, uint64_t seed, uint32_t replica, int32_t reunit_every,
-                int nthreads, double *plaq_hist, double *poly_hist)
+                int nthreads, double *plaq_hist, double *poly_hist, double *margin)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
     int order = nthreads > 1 ? 3 : 0;
+    const int64_t Vol = orc_volume(dims);
+    double *pm = NULL;
+    if (margin) {
+        pm = (double *)malloc(sizeof(double) * (size_t)Vol);
+        if (!pm) abort();
+    }
     for (int32_t i = 0; i < nsweeps; ++i) {
         uint32_t sw = sweep0 + (uint32_t)i;
         for (int mu = 0; mu < 4; ++mu)
-            for (int p = 0; p < 2; ++p)
-                orc_pass(dims, U, mu, p, sw, beta, seed, replica, order, 0, NULL);
+            for (int p = 0; p < 2; ++p) {
+                if (pm)
+                    for (int64_t s = 0; s < Vol; ++s) pm[s] = INFINITY;
+                orc_pass(dims, U, mu, p, sw, beta, seed, replica, order, 0, pm);
+                if (pm)
+                    for (int64_t s = 0; s < Vol; ++s)
+                        if (pm[s] < margin[s * 4 + mu]) margin[s * 4 + mu] = pm[s];
+            }
         if (reunit_every > 0 && ((sw + 1u) % (uint32_t)reunit_every) == 0u)
             orc_reunitarize(dims, U);
         if (plaq_hist) plaq_hist[i] = orc_plaquette(dims, U);
@@ -404,6 +416,7 @@ void orc_sweeps(const int32_t dims[4], double *U, int32_t nsweeps, uint32_t swee
             poly_hist[i] = ls;
         }
     }
+    free(pm);
 }
 
 /* ------------------------------------------------------------ init / misc */

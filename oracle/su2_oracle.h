@@ -100,10 +100,12 @@ void orc_pass(const int32_t dims[4], double *U, int mu, int parity, uint32_t swe
 /* nsweeps full sweeps (mu 0..3, even then odd) starting at sweep index sweep0.
  * reunit_every > 0 reunitarises after every sweep whose 1-based count is a
  * multiple of it.  plaq_hist (may be NULL) receives the plaquette after every
- * sweep.  nthreads > 1 uses OpenMP inside each pass. */
+ * sweep.  nthreads > 1 uses OpenMP inside each pass.  margin (length 4V,
+ * [site][mu], may be NULL) receives each link's smallest accept-decision
+ * margin over the call's updates of it (the caller fills it with +inf). */
 void orc_sweeps(const int32_t dims[4], double *U, int32_t nsweeps, uint32_t sweep0,
                 double beta, uint64_t seed, uint32_t replica, int32_t reunit_every,
-                int nthreads, double *plaq_hist, double *poly_hist);
+                int nthreads, double *plaq_hist, double *poly_hist, double *margin);
 
 void orc_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint32_t replica);
 void orc_reunitarize(const int32_t dims[4], double *U);

@@ -53,7 +53,7 @@ def _load():
         "orc_pass": (None, [_i32p, _f64p, c_int, c_int, c_u32, c_d, c_u64, c_u32, c_int, c_u64,
                             vp]),
         "orc_sweeps": (None, [_i32p, _f64p, ctypes.c_int32, c_u32, c_d, c_u64, c_u32,
-                              ctypes.c_int32, c_int, vp, vp]),
+                              ctypes.c_int32, c_int, vp, vp, vp]),
         "orc_init": (None, [_i32p, _f64p, c_int, c_u64, c_u32]),
         "orc_reunitarize": (None, [_i32p, _f64p]),
         "orc_plaquette": (c_d, [_i32p, _f64p]),
@@ -205,13 +205,17 @@ def do_pass(dims, U, mu, par, sweep, beta, seed, replica=0, order=0, order_seed=
 
 
 def sweeps(dims, U, nsweeps, sweep0, beta, seed, replica=0, reunit_every=0, nthreads=1,
-           measure=False):
+           measure=False, want_margin=False):
+    """Returns (plaquette, Polyakov) histories with measure=True, then, with
+    want_margin=True, each link's smallest decision margin ((V, 4) array)."""
     ph = np.zeros(nsweeps) if measure else None
     lh = np.zeros(nsweeps) if measure else None
+    margin = np.full((volume(dims), 4), np.inf) if want_margin else None
     _load().orc_sweeps(_dims(dims), _c(U), int(nsweeps), int(sweep0), float(beta),
                        np.uint64(seed), int(replica), int(reunit_every), int(nthreads),
-                       _ptr(ph), _ptr(lh))
-    return (ph, lh) if measure else None
+                       _ptr(ph), _ptr(lh), _ptr(margin))
+    out = ((ph, lh) if measure else ()) + ((margin,) if want_margin else ())
+    return out if len(out) > 1 else (out[0] if out else None)
 
 
 def reunitarize(dims, U):

@@ -38,6 +38,20 @@ def a0_cdf(x, alpha):
     return integrate.quad(f, lo, x, limit=400, epsabs=1e-15, epsrel=1e-12)[0] / z
 
 
+def a0_cdf_vec(x, alpha, nodes=128):
+    """a0_cdf for arrays of (x, alpha) pairs: with t = -cos(phi) the integral
+    over [-1, x] becomes int_0^arccos(-x) sin^2(phi) exp(-alpha (1 + cos phi))
+    dphi, a smooth integrand, taken by Gauss-Legendre quadrature per pair."""
+    x = np.clip(np.asarray(x, dtype=np.float64), -1.0, 1.0)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    g, w = np.polynomial.legendre.leggauss(nodes)
+    top = np.arccos(-x)[..., None]
+    phi = 0.5 * top * (g + 1.0)
+    f = np.sin(phi) ** 2 * np.exp(-alpha[..., None] * (1.0 + np.cos(phi)))
+    integral = 0.5 * top[..., 0] * (f * w).sum(axis=-1)
+    return integral / (np.pi * special.ive(1, alpha) / alpha)
+
+
 @functools.lru_cache(maxsize=None)
 def a0_quantile_edges(alpha, nbins):
     edges = [-1.0]

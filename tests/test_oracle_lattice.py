@@ -202,3 +202,30 @@ def test_hot_link_and_staple_without_the_lattice(orc):
             np.testing.assert_array_equal(orc.hot_link(s, mu, 13, 2), U[s, mu])
             np.testing.assert_allclose(orc.hot_staple(dims, s, mu, 13, 2),
                                        orc.staple(dims, U, s, mu), atol=1e-15, rtol=0)
+
+
+def test_sweep_margins_are_the_pass_margins(orc):
+    """orc.sweeps(want_margin=True) reports, per link, the smallest decision
+    margin of the single-link heat bath over the sweeps' updates of it, the
+    same numbers the passes report one at a time; reunitarisation and the
+    measurements leave them alone."""
+    dims = D4
+    U1 = orc.init(dims, 1, 8)
+    U2 = U1.copy()
+    ph, lh, m = orc.sweeps(dims, U1, 2, 5, 2.2, 8, reunit_every=2, measure=True,
+                           want_margin=True)
+    want = np.full((orc.volume(dims), 4), np.inf)
+    for sw in (5, 6):
+        for mu in range(4):
+            for p in range(2):
+                pm = orc.do_pass(dims, U2, mu, p, sw, 2.2, 8, want_margin=True)
+                want[:, mu] = np.minimum(want[:, mu], pm)
+        if (sw + 1) % 2 == 0:
+            orc.reunitarize(dims, U2)
+    np.testing.assert_array_equal(U1, U2)
+    np.testing.assert_array_equal(m, want)
+    assert np.all(np.isfinite(m)) and np.all(m >= 0)
+    # a margin is the distance of an accept test from its threshold: some
+    # decisions of 2 x 4 x V updates land close to it, none below zero
+    assert m.min() < 1e-2
+    assert orc.sweeps(dims, U2.copy(), 1, 7, 2.2, 8, want_margin=True).shape == (orc.volume(dims), 4)

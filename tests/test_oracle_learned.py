@@ -257,3 +257,52 @@ def test_or_reflection_is_an_involution(orc):
             assert x2 == pytest.approx(x0[i], abs=1e-9)
             checked += 1
     assert checked > 60
+
+
+def _training_data_checks(alpha, a0, lo, hi):
+    """p-values of the checks on training pairs: ln(alpha) uniform on
+    [ln lo, ln hi] (KS), and the probability integral transform F(a0; alpha)
+    of Sec. 2's a0 density uniform (KS) and uniform within each of five alpha
+    bins (chi-square, 20 equal bins)."""
+    from scipy import stats as sst
+    p_alpha = sst.kstest(np.log(alpha / lo) / np.log(hi / lo), "uniform").pvalue
+    u = stats.a0_cdf_vec(a0, alpha)
+    p_pit = sst.kstest(u, "uniform").pvalue
+    edges = np.quantile(alpha, np.linspace(0, 1, 6))
+    p_bins = []
+    for b in range(5):
+        sel = (alpha >= edges[b]) & (alpha <= edges[b + 1])
+        counts, _ = np.histogram(u[sel], bins=20, range=(0, 1))
+        exp = sel.sum() / 20
+        p_bins.append(sst.chi2.sf(((counts - exp) ** 2 / exp).sum(), 19))
+    return p_alpha, p_pit, min(p_bins)
+
+
+def test_training_data_distribution(orc):
+    """orc_nn_data, the proposal's training pairs: alpha log-uniform on [0.5, 30]
+    and each a0 an exact draw from sqrt(1 - a0^2) exp(alpha a0) at its own alpha
+    (Sec. 2).  The same statistics reject a linear-in-alpha map and a0 paired with
+    alpha off by 10 % (their power, shown on the oracle's own samples)."""
+    n = 120_000
+    a, x = orc.nn_data(n, 0.5, 30.0, seed=77)
+    assert a.min() >= 0.5 and a.max() <= 30.0 and np.all(np.abs(x) <= 1.0)
+    p_alpha, p_pit, p_bin = _training_data_checks(a, x, 0.5, 30.0)
+    assert p_alpha > 1e-3 and p_pit > 1e-3 and p_bin > 1e-4, (p_alpha, p_pit, p_bin)
+    # power: a uniform (not log-uniform) alpha map, and a0 judged at 1.1 alpha
+    lin = 0.5 + (np.log(a / 0.5) / np.log(60.0)) * 29.5
+    assert _training_data_checks(lin, x, 0.5, 30.0)[0] < 1e-10
+    assert min(_training_data_checks(a * 1.1, x, 0.5, 30.0)[1:]) < 1e-6
+    # other seeds give other pairs; the same seed the same pairs
+    a2, x2 = orc.nn_data(1000, 0.5, 30.0, seed=77)
+    np.testing.assert_array_equal(a2, a[:1000])
+    np.testing.assert_array_equal(x2, x[:1000])
+    a3, _ = orc.nn_data(1000, 0.5, 30.0, seed=78)
+    assert np.mean(a3 != a[:1000]) > 0.99
+
+
+def test_training_data_range_argument(orc):
+    """The range arguments are honoured: log-uniform on [2, 8]."""
+    a, x = orc.nn_data(40_000, 2.0, 8.0, seed=5)
+    assert a.min() >= 2.0 and a.max() <= 8.0
+    p_alpha, p_pit, p_bin = _training_data_checks(a, x, 2.0, 8.0)
+    assert p_alpha > 1e-3 and p_pit > 1e-3 and p_bin > 1e-4, (p_alpha, p_pit, p_bin)
