@@ -15,8 +15,10 @@ is that ensemble averages agree.  Two kinds of comparison:
   cold and hot starts must agree (tau_int-corrected errors) where both
   thermalise, and the Polyakov loop must show the deconfinement signal.
 
-Criterion for a set of pulls: every pull within 3, at least 75% within 2, mean
-squared pull at most 2.
+Criterion for a set of pulls (the oracle comparisons of every ensemble
+workload pooled): none beyond 3, at least 90% within 2, and chi-square per
+degree of freedom (the mean squared pull) at most 1.5.  GPU-only checks
+(cold against hot starts) use the same rule.
 
 Cold and hot starts are compared with each other only for beta <= 2.4.  At
 weaker coupling a hot start on 16^4 can relax into long-lived metastable
@@ -26,11 +28,17 @@ the 500 thermalisation sweeps (a 3.9 sigma cold/hot difference was seen at
 beta 2.8).
 
 Workloads:
-* beta scan 1.5..3.0 (step 0.1) on 16^4, cold and hot starts, 500
+* beta scan 1.5..3.0 (step 0.1) on 16^4 and 24^4, cold and hot starts, 500
   thermalisation + 1000 measured sweeps, reunitarisation every 10 sweeps,
-  plaquette every sweep (Sec. 4 beta scans);
+  plaquette every sweep (Sec. 4 beta scans, the plaquette-against-beta figure);
 * 32^3 x Nt, Nt in {4, 6, 8}, beta 2.00..2.60 (step 0.05), cold start, 5000
-  sweeps, plaquette and Polyakov loop every sweep (Sec. 4, Polyakov loop).
+  sweeps, plaquette and Polyakov loop every sweep (Sec. 4, the Polyakov-loop
+  figure at several Nt).
+The oracle comparisons take 8 couplings of the 16^4 scan, 3 of the 24^4 scan
+and 2 of each Nt (plaquette and |L|), each in the workload's start, plus the
+learned updates on 12^4; the matched protocol there is shorter than the
+workload's (the oracle finishes it in seconds), which the matched design
+allows because both sides run the same protocol.
 """
 import time
 
@@ -51,10 +59,11 @@ def pulls(gpu, orc):
 
 def assert_pulls(p, what):
     p = np.asarray(p)
-    print(f"[gpu-test] {what}: pulls {np.round(p, 2).tolist()}", flush=True)
+    print(f"[gpu-test] {what}: {len(p)} pulls {np.round(p, 2).tolist()}; within 2: "
+          f"{np.mean(np.abs(p) <= 2.0):.0%}, chi2/dof {np.mean(p * p):.2f}", flush=True)
     assert np.all(np.abs(p) <= 3.0), (what, p)
-    assert np.mean(np.abs(p) <= 2.0) >= 0.75, (what, p)
-    assert np.mean(p * p) <= 2.0, (what, p)
+    assert np.mean(np.abs(p) <= 2.0) >= 0.9, (what, p)
+    assert np.mean(p * p) <= 1.5, (what, p)
 
 
 def oracle_chain(orc, dims, beta, seed, start, therm, nmeas, every, reunit=10):
@@ -89,86 +98,52 @@ def matched_pull(orc_mean, gpu_means):
     return (orc_mean - gpu_means.mean()) / (gpu_means.std(ddof=1) * np.sqrt(1 + 1 / n))
 
 
-def test_beta_scan_16_matches_oracle(su2, orc):
-    announce("ensemble: beta scan 16^4")
-    betas = np.round(np.arange(1.5, 3.0001, 0.1), 2)
-    nb = len(betas)
-    dims = [[16, 16, 16, 16]] * (2 * nb)
-    bet = np.concatenate([betas, betas])
-    starts = np.array([su2.SU2_COLD] * nb + [su2.SU2_HOT] * nb, np.int32)
+# (dims, beta, start, thermalisation sweeps, measurements, sweeps between them,
+#  with |L|): the couplings of each ensemble workload compared with the oracle
+MATCHED = (
+    [([16, 16, 16, 16], b, st, 60, 60, 2, False)
+     for b, st in ((1.5, 1), (1.7, 0), (1.9, 1), (2.1, 0), (2.3, 1), (2.5, 0), (2.7, 0),
+                   (3.0, 0))]
+    + [([24, 24, 24, 24], b, st, 40, 40, 2, False) for b, st in ((1.8, 1), (2.4, 0), (3.0, 0))]
+    + [([32, 32, 32, nt], b, 0, 60, 40, 2, True)
+       for nt, bs in ((4, (2.0, 2.6)), (6, (2.2, 2.6)), (8, (2.3, 2.6))) for b in bs])
+
+
+def test_ensembles_match_oracle_chains(su2, orc):
+    """Every ensemble workload against independent oracle chains, matched
+    protocol (64 GPU replicas per point), pulls of the mean plaquette and, at
+    finite temperature, of the mean |L|; then the learned updates (independence
+    and over-relaxed Metropolis, trained flow) against oracle heat-bath chains.
+    The rule is applied to all pulls together."""
+    announce("ensemble: oracle chains vs GPU replicas, every ensemble workload")
     t0 = time.time()
-    with su2.Batch(dims, bet, starts, seed=1000) as b:
-        b.sweep_measure(500, reunit_every=10)
-        hist = b.sweep_measure(1000, reunit_every=10).cpu().numpy()
-    print(f"[gpu-test] gpu batch {time.time() - t0:.1f} s", flush=True)
-    P = hist[:, :, 0]
-    gpu = np.array([stats.mean_err(P[:, r]) for r in range(2 * nb)])
-    # cold and hot chains of the GPU are independent and must agree (beta <= 2.4)
-    strong = int(np.sum(betas <= 2.4 + 1e-9))
-    assert_pulls(pulls(gpu[:strong], gpu[nb:nb + strong]), "gpu cold vs hot, beta <= 2.4")
-    # matched protocol (100 sweeps, then 150 measurements 2 sweeps apart): the
-    # oracle's chain against 32 GPU replicas; hot starts at beta 1.5 and 2.1,
-    # cold starts at beta 2.7 and 3.0
-    t0 = time.time()
-    p = []
-    for i, start in ((0, 1), (6, 1), (12, 0), (15, 0)):
-        ph, _ = oracle_chain(orc, [16, 16, 16, 16], betas[i], 7000 + i, start, 100, 150, 2)
-        gp, _ = gpu_matched(su2, [16, 16, 16, 16], betas[i], start, 100, 150, 2, 32, 1100 + i)
+    p, labels = [], []
+    for k, (dims, beta, start, therm, nmeas, every, with_l) in enumerate(MATCHED):
+        t1 = time.time()
+        ph, lh = oracle_chain(orc, dims, beta, 7000 + k, start, therm, nmeas, every)
+        gp, gl = gpu_matched(su2, dims, beta, start, therm, nmeas, every, 64, 1100 + k)
+        name = "x".join(map(str, dims)) + f" b{beta} {'hot' if start else 'cold'}"
         p.append(matched_pull(ph.mean(), gp))
-    print(f"[gpu-test] oracle + matched GPU chains {time.time() - t0:.1f} s", flush=True)
-    assert_pulls(p, "oracle vs gpu, plaquette, matched protocol")
-    # monotone in beta, between the strong- and weak-coupling limits
-    m = 0.5 * (gpu[:nb, 0] + gpu[nb:, 0])
-    assert np.all(np.diff(m) > 0)
-    assert np.all(m < 1 - 3 / (4 * betas) + 0.02)
+        labels.append(name + " P")
+        if with_l:
+            p.append(matched_pull(np.abs(lh).mean(), gl))
+            labels.append(name + " |L|")
+        print(f"[gpu-test] {name}: P oracle {ph.mean():.5f} gpu {gp.mean():.5f}"
+              f"({gp.std(ddof=1):.5f}) pull {p[-1 - with_l]:+.2f}"
+              + (f"; |L| oracle {np.abs(lh).mean():.4f} gpu {gl.mean():.4f} pull {p[-1]:+.2f}"
+                 if with_l else "") + f" [{time.time() - t1:.1f} s]", flush=True)
+    print(f"[gpu-test] matched heat-bath comparisons {time.time() - t0:.1f} s", flush=True)
+    p += learned_pulls(su2, orc, labels)
+    print(f"[gpu-test] all comparisons {time.time() - t0:.1f} s", flush=True)
+    assert_pulls(p, "oracle vs gpu, every ensemble workload and the learned updates")
 
 
-def test_polyakov_32x4_matches_oracle(su2, orc):
-    announce("ensemble: 32^3 x Nt Polyakov loop")
-    betas = np.round(np.arange(2.0, 2.6001, 0.05), 2)
-    nts = [4, 6, 8]
-    dims = [[32, 32, 32, nt] for nt in nts for _ in betas]
-    bet = np.concatenate([betas] * len(nts))
-    t0 = time.time()
-    with su2.Batch(dims, bet, su2.SU2_COLD, seed=4000) as b:
-        hist = b.sweep_measure(5000, reunit_every=10,
-                               meas=su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY).cpu().numpy()
-    print(f"[gpu-test] gpu batch {time.time() - t0:.1f} s", flush=True)
-    therm = 1000
-    nb = len(betas)
-    absL = np.abs(hist[therm:, :, 1])
-    P = hist[therm:, :, 0]
-    gL = np.array([stats.mean_err(absL[:, r]) for r in range(len(dims))])
-    gP = np.array([stats.mean_err(P[:, r]) for r in range(len(dims))])
-    # the |L| signal: small and flat in the confined phase, rising through the
-    # transition; larger Nt deconfines at larger beta
-    for k in range(len(nts)):
-        L = gL[k * nb:(k + 1) * nb, 0]
-        assert L[-1] > 4 * L[0], (nts[k], L)
-    assert gL[nb - 1, 0] > gL[2 * nb - 1, 0] > gL[3 * nb - 1, 0]  # beta 2.6: Nt 4 > 6 > 8
-    for k in range(len(nts)):
-        assert np.all(np.diff(gP[k * nb:(k + 1) * nb, 0]) > 0)
-    # matched protocol at Nt = 4, beta 2.0 and 2.6: cold start, 200 sweeps,
-    # then 150 measurements 2 sweeps apart; the oracle's chain against 32 GPU
-    # replicas
-    t0 = time.time()
-    p = []
-    for i in (0, nb - 1):
-        ph, lh = oracle_chain(orc, [32, 32, 32, 4], betas[i], 4100 + i, 0, 200, 150, 2)
-        gp, gl = gpu_matched(su2, [32, 32, 32, 4], betas[i], 0, 200, 150, 2, 32, 4200 + i)
-        p += [matched_pull(ph.mean(), gp), matched_pull(np.abs(lh).mean(), gl)]
-    print(f"[gpu-test] oracle + matched GPU chains {time.time() - t0:.1f} s", flush=True)
-    assert_pulls(p, "oracle vs gpu, P and |L|, Nt = 4, matched protocol")
-
-
-def test_learned_modes_match_oracle(su2, orc):
-    """The learned updates (independence and over-relaxed Metropolis, trained
-    flow) leave the heat-bath distribution of Sec. 2 exact: after the same
-    heat-bath thermalisation on both sides, the mean plaquette of 32 GPU
-    replicas measured with the learned update agrees with an independent FP64
-    oracle heat-bath chain (the oracle's error tau_int-corrected, the GPU's from
-    the spread of its replicas)."""
-    announce("ensemble: learned modes vs oracle heat bath")
+def learned_pulls(su2, orc, labels):
+    """The learned updates leave the heat-bath distribution of Sec. 2 exact:
+    after the same heat-bath thermalisation on both sides, the mean plaquette
+    of 32 GPU replicas measured with the learned update against an independent
+    FP64 oracle heat-bath chain (the oracle's error tau_int-corrected, the
+    GPU's from the spread of its replicas)."""
     dims, nrep, therm, nmeas, every = [12, 12, 12, 12], 32, 200, 150, 2
     p = []
     with su2.NN(seed=8) as net:
@@ -187,4 +162,62 @@ def test_learned_modes_match_oracle(su2, orc):
                                         reunit_every=10).cpu().numpy()
                 g = h[every - 1::every, :, 0].mean(axis=0)
                 p.append((o_mean - g.mean()) / np.hypot(o_err, g.std(ddof=1) / np.sqrt(nrep)))
-    assert_pulls(p, "oracle heat bath vs gpu learned (independence, over-relaxed)")
+                labels.append(f"12^4 b{beta} learned w={width}")
+                print(f"[gpu-test] {labels[-1]}: pull {p[-1]:+.2f}", flush=True)
+    return p
+
+
+def test_beta_scans_full_protocol(su2):
+    """The beta scans at their full protocol on the GPU: cold and hot starts
+    agree where both thermalise (beta <= 2.4), the plaquette rises with beta
+    between the strong- and weak-coupling limits."""
+    for L in (16, 24):
+        announce(f"ensemble: beta scan {L}^4, full protocol")
+        betas = np.round(np.arange(1.5, 3.0001, 0.1), 2)
+        nb = len(betas)
+        dims = [[L, L, L, L]] * (2 * nb)
+        bet = np.concatenate([betas, betas])
+        starts = np.array([su2.SU2_COLD] * nb + [su2.SU2_HOT] * nb, np.int32)
+        t0 = time.time()
+        with su2.Batch(dims, bet, starts, seed=1000) as b:
+            b.sweep_measure(500, reunit_every=10)
+            hist = b.sweep_measure(1000, reunit_every=10).cpu().numpy()
+        print(f"[gpu-test] gpu batch {time.time() - t0:.1f} s", flush=True)
+        P = hist[:, :, 0]
+        gpu = np.array([stats.mean_err(P[:, r]) for r in range(2 * nb)])
+        # cold and hot chains of the GPU are independent and must agree (beta <= 2.4)
+        strong = int(np.sum(betas <= 2.4 + 1e-9))
+        assert_pulls(pulls(gpu[:strong], gpu[nb:nb + strong]),
+                     f"gpu cold vs hot, {L}^4, beta <= 2.4")
+        # monotone in beta, between the strong- and weak-coupling limits
+        m = 0.5 * (gpu[:nb, 0] + gpu[nb:, 0])
+        assert np.all(np.diff(m) > 0)
+        assert np.all(m < 1 - 3 / (4 * betas) + 0.02)
+
+
+def test_polyakov_grid_full_protocol(su2):
+    """The 32^3 x Nt grid at its full protocol on the GPU: the |L| signal is
+    small in the confined phase and rises through the transition, larger Nt
+    deconfines at larger beta, and the plaquette rises with beta."""
+    announce("ensemble: 32^3 x Nt Polyakov loop, full protocol")
+    betas = np.round(np.arange(2.0, 2.6001, 0.05), 2)
+    nts = [4, 6, 8]
+    dims = [[32, 32, 32, nt] for nt in nts for _ in betas]
+    bet = np.concatenate([betas] * len(nts))
+    t0 = time.time()
+    with su2.Batch(dims, bet, su2.SU2_COLD, seed=4000) as b:
+        hist = b.sweep_measure(5000, reunit_every=10,
+                               meas=su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY).cpu().numpy()
+    print(f"[gpu-test] gpu batch {time.time() - t0:.1f} s", flush=True)
+    therm = 1000
+    nb = len(betas)
+    absL = np.abs(hist[therm:, :, 1])
+    P = hist[therm:, :, 0]
+    gL = np.array([stats.mean_err(absL[:, r]) for r in range(len(dims))])
+    gP = np.array([stats.mean_err(P[:, r]) for r in range(len(dims))])
+    for k in range(len(nts)):
+        L = gL[k * nb:(k + 1) * nb, 0]
+        assert L[-1] > 4 * L[0], (nts[k], L)
+    assert gL[nb - 1, 0] > gL[2 * nb - 1, 0] > gL[3 * nb - 1, 0]  # beta 2.6: Nt 4 > 6 > 8
+    for k in range(len(nts)):
+        assert np.all(np.diff(gP[k * nb:(k + 1) * nb, 0]) > 0)

@@ -67,9 +67,10 @@ def test_full_size_passes_autotuned_and_persistent(su2, orc):
         lat.autotune()
         print(f"[gpu-test] launch {lat.launch()}", flush=True)
         lat.set_sweep(2)
-        for mu, par in ((0, 0), (3, 1)):
-            w = check_pass(lat, orc, links, U, mu, par, 100 + mu)
-            print(f"[gpu-test] pass ({mu},{par}) max err {w:.2e}", flush=True)
+        for mu in range(4):
+            for par in range(2):
+                w = check_pass(lat, orc, links, U, mu, par, 100 + 2 * mu + par)
+                print(f"[gpu-test] pass ({mu},{par}) max err {w:.2e}", flush=True)
         announce("48^4 sampled pass parity (persistent grid)")
         lat.set_launch(256, 1, 8, 8, 2048)
         for mu, par in ((1, 1), (2, 0)):
@@ -100,16 +101,28 @@ def test_full_size_sweep_measurements(su2, orc):
         assert abs(hist[0, 1] - s) < 1e-6 and abs(hist[0, 2] - a) < 1e-6
     n2 = np.einsum("vmc,vmc->vm", got.astype(np.float64), got.astype(np.float64))
     assert np.abs(n2 - 1).max() < 1e-5
-    # the oracle's sweep of the same configuration (all host threads)
-    ph, lh = orc.sweeps(DIMS, U, 1, 0, BETA, SEED, nthreads=16, measure=True)
-    nbad = int(np.sum(np.abs(got - U).max(axis=2) > 1e-5))
+    # the oracle's sweep of the same configuration (all host threads), with the
+    # margin of every accept decision it took
+    ph, lh, margin = orc.sweeps(DIMS, U, 1, 0, BETA, SEED, nthreads=16, measure=True,
+                                want_margin=True)
+    off = np.abs(got - U).max(axis=2) > 1e-5
+    nbad = int(off.sum())
+    nflag = int((margin < MARGIN_FLAG).sum())
     V = int(np.prod(DIMS))
-    print(f"[gpu-test] links off by > 1e-5 after the sweep: {nbad} of {4 * V}; plaquette "
-          f"{hist[0, 0]:.9f} vs oracle {ph[0]:.9f}, Polyakov {hist[0, 1]:.3e} vs {lh[0]:.3e}",
-          flush=True)
-    # a decision flipped by FP32 rounding changes its link and some it feeds later in
-    # the sweep; each changed link moves its six plaquettes and one Polyakov line by O(1)
-    assert nbad < 1e-3 * 4 * V
+    print(f"[gpu-test] links off by > 1e-5 after the sweep: {nbad} of {4 * V}; decisions "
+          f"within {MARGIN_FLAG} of their threshold: {nflag}; plaquette {hist[0, 0]:.9f} vs "
+          f"oracle {ph[0]:.9f}, Polyakov {hist[0, 1]:.3e} vs {lh[0]:.3e}", flush=True)
+    # Only a decision the oracle takes within MARGIN_FLAG of its threshold may
+    # flip in FP32.  A flipped decision changes its link by O(1) and, through
+    # the staples, links updated after it in the same sweep (fewer than 500
+    # within the seven passes that follow).  With no flagged decision every
+    # link matches.
+    assert nflag <= max_flags(4 * V)
+    assert nbad <= 500 * nflag, (nbad, nflag)
+    if nbad:
+        # every mismatched cone starts at a flagged decision of its own sweep
+        assert (off & (margin < MARGIN_FLAG)).any()
+    # each changed link moves its six plaquettes and one Polyakov line by O(1)
     assert abs(hist[0, 0] - ph[0]) < 1e-6 + 6.0 * nbad / (6 * V)
     assert abs(hist[0, 1] - lh[0]) < 1e-6 + 2.0 * nbad / (V // DIMS[3])
 

@@ -7,7 +7,7 @@ The FP32 error of an a0 decision is larger than for SU(2) (six staples of three
 SU(3) factors, then W = U A and two earlier subgroup rotations feed each
 subgroup's k), so links whose smallest oracle decision margin is below
 FLAG3 = 2e-4 are excluded and counted against a bound; every flagged link must
-still be in SU(3).
+still be in SU(3).  Every other link agrees within TOL3 = 1e-5 per component.
 """
 import numpy as np
 import pytest
@@ -18,7 +18,7 @@ from tests.gpu_util import announce
 pytestmark = pytest.mark.gpu
 
 FLAG3 = 2e-4
-TOL3 = 1e-4
+TOL3 = 1e-5
 
 
 @pytest.fixture(scope="module")
