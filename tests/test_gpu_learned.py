@@ -39,9 +39,17 @@ def test_loss_and_gradient_match_oracle(su2, batch):
         loss, g = net.loss_grad(0, batch)
     wl, wg = nn.loss_and_grad(p.astype(np.float64), al.astype(np.float64), x.astype(np.float64))
     assert loss == pytest.approx(wl, rel=1e-5)
-    # per tensor relative error of the FP32 gradient
+    # element by element, per tensor (W1, b1, W2, b2, W3, b3): the FP32 gradient
+    # within 1e-3 relative of the FP64 one, with an absolute floor of 1e-4 times
+    # the tensor's norm for entries that nearly cancel over the batch
     for lo, hi in ((0, 32), (32, 64), (64, 1088), (1088, 1120), (1120, 2624), (2624, 2671)):
-        err = np.linalg.norm(g[lo:hi] - wg[lo:hi]) / np.linalg.norm(wg[lo:hi])
+        w = wg[lo:hi]
+        bound = 1e-3 * np.abs(w) + 1e-4 * np.linalg.norm(w)
+        excess = np.abs(g[lo:hi] - w) / bound
+        print(f"[gpu-test] gradient [{lo}:{hi}] worst error / bound {excess.max():.3f}",
+              flush=True)
+        assert np.all(excess <= 1.0), (lo, hi, int(np.argmax(excess)), excess.max())
+        err = np.linalg.norm(g[lo:hi] - w) / np.linalg.norm(w)
         assert err < 1e-3, (lo, hi, err)
 
 
@@ -241,3 +249,36 @@ def test_training_gain_over_untrained_proposal(su2):
     (a0, t0), (a1, t1) = res["untrained"], res["trained"]
     assert a0 < 0.3 and a1 > 0.95, res
     assert t0 > 4 * t1, res
+
+
+def test_proposal_cannot_be_destroyed_while_attached(su2):
+    """A context or batch holds its learned proposal: su2_nn_destroy refuses
+    (SU2_ESTATE, nothing freed) while any of them has it attached, and
+    succeeds once they have detached or been destroyed.  The binding keeps the
+    network alive while attached, so dropping the caller's reference is safe."""
+    announce("proposal lifetime")
+    import gc
+    with su2.NN(seed=4) as net:
+        net.build_table()
+        lat = su2.Lattice([4, 4, 4, 4], 2.3, 1, su2.SU2_HOT)
+        b = su2.Batch([[4, 4, 4, 4], [6, 4, 4, 4]], [2.0, 2.5], [1, 1], 2)
+        lat.set_proposal(net)
+        b.set_proposal(net)
+        for holders in (2, 1):
+            with pytest.raises(su2.SU2Error) as e:
+                su2.su2_nn_destroy(net.h)
+            assert e.value.code == su2.SU2_ESTATE
+            assert f"{holders} lattice" in str(e.value)
+            if holders == 2:
+                lat.set_proposal(None)  # detach
+        b.close()  # destroying the batch detaches it
+        net2 = su2.NN(seed=5)
+        net2.build_table()
+        lat.set_proposal(net2)
+        del net2
+        gc.collect()
+        lat.heatbath_sweep(2, su2.SU2_LEARNED)  # the lattice kept net2 alive
+        assert np.all(np.isfinite(lat.get_links()))
+        lat.close()
+    # net was destroyed by the context manager: nothing held it any more
+    assert net.h is None
