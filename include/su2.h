@@ -210,15 +210,19 @@ int su2_autotune(su2_ctx *ctx, const char *cache_path, int mode, double *best_us
 
 /* hipGraph capture: record nsweeps sweeps exactly as su2_sweep_measure (meas
  * = 0: as su2_heatbath_sweep) would enqueue them, then replay the recording
- * `count` times with su2_replay_sweeps (one graph launch per replay; the
- * sweep index and the history row index advance on the device, so replay k
- * appends rows k*nsweeps..).  With reunit_every > 0, nsweeps must be a
- * multiple of it and the current sweep index a multiple of it, and a replay
- * is refused (SU2_ESTATE) unless the sweep index is again a multiple of it.
- * Needs a non-null stream; later launch or proposal changes drop the
- * recording. */
+ * `count` times with su2_replay_sweeps (one graph launch per replay).  The
+ * sweep index and the graph's own history row index advance on the device:
+ * the k-th replay since the capture (k = 0, 1, ...) writes rows
+ * k*nsweeps..(k+1)*nsweeps-1 of dev_history, whatever direct calls run between
+ * replays (they count their rows separately).  history_rows: rows (3 doubles
+ * each) dev_history holds (>= nsweeps when meas != 0, else SU2_EINVAL); a
+ * replay that would write past them is refused with SU2_EINVAL and enqueues
+ * nothing.  With reunit_every > 0, nsweeps must be a multiple of it and the
+ * current sweep index a multiple of it, and a replay is refused (SU2_ESTATE)
+ * unless the sweep index is again a multiple of it.  Needs a non-null
+ * stream; later launch or proposal changes drop the recording. */
 int su2_capture_sweeps(su2_ctx *ctx, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
-                       double *dev_history);
+                       double *dev_history, int64_t history_rows);
 int su2_replay_sweeps(su2_ctx *ctx, int32_t count);
 
 /* ============================================================== batches
@@ -240,8 +244,9 @@ int su2_batch_sweep(su2_batch *b, int32_t nsweeps, int mode);
 /* As su2_sweep_measure; dev_history is FP64[nsweeps][n][3]. */
 int su2_batch_sweep_measure(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_every,
                             int meas, double *dev_history);
+/* As su2_capture_sweeps; dev_history is FP64[history_rows][n][3]. */
 int su2_batch_capture(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
-                      double *dev_history);
+                      double *dev_history, int64_t history_rows);
 int su2_batch_replay(su2_batch *b, int32_t count);
 /* Plaquette and Polyakov loop of every replica into host arrays of n (any may
  * be NULL).  Synchronous. */
@@ -279,6 +284,7 @@ int su2_nn_num_params(void);
  * biases giving the identity spline, i.e. a uniform proposal).  hip_stream:
  * stream for the object's work (NULL = null stream).  Library-owned memory. */
 int su2_nn_create(su2_nn **out, const float *params_host, uint64_t seed, void *hip_stream);
+/* SU2_ESTATE (nothing freed) while a context or batch has it attached. */
 int su2_nn_destroy(su2_nn *nn);
 int su2_nn_get_params(su2_nn *nn, float *params_host);
 int su2_nn_set_params(su2_nn *nn, const float *params_host);
@@ -304,8 +310,11 @@ int su2_nn_train_cosine(su2_nn *nn, int32_t steps, int32_t batch, double lr0, do
  * (host float[64 * 48]). */
 int su2_nn_build_table(su2_nn *nn);
 int su2_nn_get_table(su2_nn *nn, float *table_host);
-/* Use nn's table for SU2_LEARNED sweeps of ctx (NULL unsets).  The su2_nn must
- * outlive every sweep enqueued with it and its table must be built. */
+/* Use nn's table for SU2_LEARNED sweeps of ctx (NULL unsets); its table must
+ * be built (SU2_ESTATE otherwise).  While attached, the context or batch holds
+ * the su2_nn: su2_nn_destroy returns SU2_ESTATE until every context and batch
+ * using it has detached (set_proposal with NULL or another su2_nn) or been
+ * destroyed.  Rebuilding the table of an attached su2_nn changes later sweeps. */
 int su2_set_proposal(su2_ctx *ctx, su2_nn *nn);
 int su2_batch_set_proposal(su2_batch *b, su2_nn *nn);
 /* Over-relaxed use of the learned flow in SU2_LEARNED sweeps.  width < 0

@@ -33,8 +33,17 @@ struct Counters {
     uint32_t sweep;     // sweep index used by the next pass (Philox counter word 1)
     uint32_t meas_idx;  // next history row written by a measured sweep
     uint32_t done;      // work-queue items of this replica finished in the current launch
-    uint32_t pad[13];
+    uint32_t graph_row; // next history row written by a replay of captured sweeps
+    uint32_t pad[12];
 };
+
+// History-row counter of a measured sweep: direct calls count rows from the
+// start of each call (meas_idx); the sweeps of a captured graph count on
+// across replays (graph_row, reset at capture), untouched by direct calls.
+__host__ __device__ inline uint32_t *row_counter(Counters *c, bool graph)
+{
+    return graph ? &c->graph_row : &c->meas_idx;
+}
 
 // Shared state of the persistent work-queue launch: one queue per XCD.
 constexpr int kMaxQueues = 16;  // the XCC id is 4 bits
@@ -97,6 +106,7 @@ struct QueuePlan {
     uint32_t reunit;  // reunitarisation period (0: none)
     uint32_t phase;   // index of the first sweep mod reunit (0 without)
     uint32_t want_p, want_l, rows;  // plaquette, Polyakov loop, history rows (0/1)
+    uint32_t graph_rows;            // rows counted by the graph's counter (row_counter)
 };
 
 enum QueueKind { QK_PASS = 0, QK_REUNIT = 1, QK_PLAQ = 2, QK_POLY = 3 };
@@ -202,13 +212,15 @@ hipError_t launch_polyakov(const Ens &e, hipStream_t stream);
 hipError_t launch_take(const Ens &e, int flags, hipStream_t stream);
 // End of a sweep.  flags: 1 plaquette in acc[ACC_PLAQ], 2 Polyakov in
 // acc[ACC_POLY], 4 append a history row (P, L, |L|) per replica at
-// hist[3 * (meas_idx * nrep + r)].  Resets the accumulators, advances sweep.
+// hist[3 * (row * nrep + r)] with row from row_counter (8: the graph's
+// counter).  Resets the accumulators, advances sweep.
 hipError_t launch_sweep_end(const Ens &e, int flags, double *hist, hipStream_t stream);
 hipError_t launch_reunitarize(const Ens &e, hipStream_t stream);
 // ns whole sweeps of every replica (all V/2 <= kSmallMaxVh) in one launch:
 // passes, reunitarisation every reunit_every sweeps (absolute sweep index),
 // measurements (flags 1 plaquette, 2 Polyakov loop, 4 history rows at
-// hist[3 * (meas_idx * nrep + r)]); advances the sweep and row counters.
+// hist[3 * (row * nrep + r)], 8 rows from the graph's counter); advances the
+// sweep and row counters.
 // table != nullptr: learned-proposal Metropolis updates.
 hipError_t launch_small_sweeps(const Ens &e, int ns, uint64_t seed, int reunit_every, int flags,
                                double *hist, const float *table, hipStream_t stream);
@@ -247,7 +259,8 @@ hipError_t launch_wilson(const Ens &e, int rmax, int tmax, double *part, double 
 // Workgroups of `block` threads of the queue kernel the device holds at once.
 uint32_t queue_resident_grid(int block, bool learned);
 // which: 1 set sweep, 2 set meas_idx, 4 zero all accumulators, 8 zero counts,
-// 16 zero the work-queue state (done counters; qs ticket and error).
+// 16 zero the work-queue state (done counters; qs ticket and error), 32 set
+// graph_row.
 hipError_t launch_set_counter(const Ens &e, uint32_t sweep, uint32_t meas, int which,
                               hipStream_t stream, QueueState *qs = nullptr);
 // results[R_COUNTS..] = proposals, accepts (as uint64); reset if asked.

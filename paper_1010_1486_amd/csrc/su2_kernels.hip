@@ -74,6 +74,19 @@ __device__ __forceinline__ void st(float *links, uint32_t vh, int mu, int par, u
     p->w = q.z;
 }
 
+// Store with the nontemporal hint: the class a pass writes is read by no
+// other site of that pass, so its lines need not displace the neighbour
+// classes the pass re-reads from L2.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4f gv4f;
+__device__ __forceinline__ void st_nt(float *links, uint32_t vh, int mu, int par, uint32_t h,
+                                      const Q &q)
+{
+    gv4f *p = (gv4f *)links + (size_t)(mu * 2 + par) * vh + h;
+    const v4f v = {q.w, q.x, q.y, q.z};
+    __builtin_nontemporal_store(v, p);
+}
+
 __device__ __forceinline__ Q ldq(const float *links, uint32_t vh, int mu, int par, uint32_t h)
 {
     gf4 *p = (gf4 *)links + (size_t)(mu * 2 + par) * vh + h;
@@ -106,14 +119,13 @@ __global__ void init_kernel(const Rep *__restrict__ reps, const int *__restrict_
 // MEASURE, meas = (1/2)Tr(U'_MU V_nu) summed over nu < MU.  acc: as
 // learned_link (-1 for the heat bath).
 template <int MU, bool MEASURE, bool LEARNED>
-__device__ __forceinline__ void update_site(const Rep &R, uint32_t gid, int par, uint32_t sweep,
-                                            uint32_t k0, uint32_t k1, const float *ltab,
-                                            float &meas, int &acc)
+__device__ __forceinline__ void update_at(const Rep &R, const PassSite &s, int par,
+                                          uint32_t sweep, uint32_t k0, uint32_t k1,
+                                          const float *ltab, float &meas, int &acc)
 {
     const Geom &g = R.g;
     const int opp = par ^ 1;
     const float *links = R.links;
-    const PassSite s = pass_site(g, gid, par);
     const Deltas d = neighbour_deltas(g, s);
     const uint32_t h = s.h;
     const Arr Umu_o = arr(links, g.vh, MU, opp);
@@ -146,8 +158,17 @@ __device__ __forceinline__ void update_site(const Rep &R, uint32_t gid, int par,
         Un = heatbath_link(V, R.beta, site, sweep, word2((uint32_t)MU, TAG_TRIAL, R.replica), k0,
                            k1);
     }
-    st(R.links, g.vh, MU, par, h, Un);
+    st_nt(R.links, g.vh, MU, par, h, Un);
     if (MEASURE) meas = retr(Un, Vlow);
+}
+
+template <int MU, bool MEASURE, bool LEARNED>
+__device__ __forceinline__ void update_site(const Rep &R, uint32_t gid, int par, uint32_t sweep,
+                                            uint32_t k0, uint32_t k1, const float *ltab,
+                                            float &meas, int &acc)
+{
+    update_at<MU, MEASURE, LEARNED>(R, pass_site(R.g, gid, par), par, sweep, k0, k1, ltab, meas,
+                                    acc);
 }
 
 // Fill the LDS copy of the spline table (4 floats of padding first, like the
@@ -362,14 +383,15 @@ __global__ __launch_bounds__(kBuckets) void sweep_end_kernel(const Rep *__restri
         Counters *c = R.cnt;
         const Geom &g = R.g;
         if ((flags & 4) && hist) {
-            const uint32_t m = c->meas_idx;
+            uint32_t *rc = row_counter(c, (flags & 8) != 0);
+            const uint32_t m = *rc;
             const double p = (flags & 1) ? from_fixed(tp) / (12.0 * (double)g.vh) : 0.0;
             const double l = (flags & 2) ? from_fixed(tl) / ((double)g.nx * g.ny * g.nz) : 0.0;
             double *row = hist + 3 * ((size_t)m * nrep + blockIdx.z);
             row[0] = p;
             row[1] = l;
             row[2] = fabs(l);
-            c->meas_idx = m + 1;
+            *rc = m + 1;
         }
         c->sweep = c->sweep + 1;
     }
@@ -418,6 +440,7 @@ __global__ __launch_bounds__(kBuckets) void set_counter_kernel(const Rep *__rest
     if (threadIdx.x == 0) {
         if (which & 1) R.cnt->sweep = sweep;
         if (which & 2) R.cnt->meas_idx = meas;
+        if (which & 32) R.cnt->graph_row = meas;
     }
 }
 
@@ -486,7 +509,8 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
     return t;
 }
 
-// flags: 1 plaquette, 2 Polyakov loop, 4 history rows.
+// flags: 1 plaquette, 2 Polyakov loop, 4 history rows, 8 rows from the
+// graph's row counter.
 template <bool LEARNED>
 __global__ __launch_bounds__(1024) void small_sweeps_kernel(const Rep *__restrict__ reps, int nrep,
                                                             int ns, uint32_t k0, uint32_t k1,
@@ -500,7 +524,8 @@ __global__ __launch_bounds__(1024) void small_sweeps_kernel(const Rep *__restric
     const Geom &g = R.g;
     const uint32_t ns3 = (uint32_t)g.nx * g.ny * g.nz;
     uint32_t sweep = R.cnt->sweep;  // written back by thread 0 at the end
-    uint32_t midx = R.cnt->meas_idx;
+    uint32_t *const row_ctr = row_counter(R.cnt, (flags & 8) != 0);
+    uint32_t midx = *row_ctr;
     unsigned long long np = 0ull, na = 0ull;
     const bool want_p = (flags & 1) != 0, want_l = (flags & 2) != 0;
     const bool rows = (flags & 4) != 0 && hist != nullptr;
@@ -569,7 +594,7 @@ __global__ __launch_bounds__(1024) void small_sweeps_kernel(const Rep *__restric
     __syncthreads();  // every thread has read the counters before they change
     if (threadIdx.x == 0) {
         R.cnt->sweep = sweep;
-        R.cnt->meas_idx = midx;
+        *row_ctr = midx;
     }
 }
 
@@ -778,7 +803,7 @@ __device__ __forceinline__ void queue_pass(const Rep &R, int mu, int par, bool m
 }
 
 // End of sweep i of replica r: totals of the plaquette and Polyakov
-// accumulators (taken and reset atomically), history row meas_idx + i.
+// accumulators (taken and reset atomically), history row (row counter) + i.
 __device__ __forceinline__ void queue_sweep_end(const Rep &R, const QueuePlan &plan, uint32_t i,
                                                 double *hist, int nrep, uint32_t r)
 {
@@ -795,7 +820,8 @@ __device__ __forceinline__ void queue_sweep_end(const Rep &R, const QueuePlan &p
         const Geom &g = R.g;
         const double p = plan.want_p ? from_fixed(tp) / (12.0 * (double)g.vh) : 0.0;
         const double l = plan.want_l ? from_fixed(tl) / ((double)g.nx * g.ny * g.nz) : 0.0;
-        double *row = hist + 3 * ((size_t)(R.cnt->meas_idx + i) * nrep + r);
+        double *row = hist + 3 * ((size_t)(*row_counter(R.cnt, plan.graph_rows != 0u) + i) *
+                                      nrep + r);
         row[0] = p;
         row[1] = l;
         row[2] = fabs(l);
@@ -921,7 +947,7 @@ __global__ void queue_epilogue_kernel(const Rep *__restrict__ reps, QueuePlan pl
     const Rep &R = reps[blockIdx.z];
     if (R.cnt->done != queue_target(plan, R.nblocks, plan.ns, 0u)) qs->error = 2u;
     R.cnt->sweep += plan.ns;
-    if (plan.rows) R.cnt->meas_idx += plan.ns;
+    if (plan.rows) *row_counter(R.cnt, plan.graph_rows != 0u) += plan.ns;
     R.cnt->done = 0u;
     if (blockIdx.z == 0)
         for (int k = 0; k < kMaxQueues; ++k) qs->ticket[k][0] = 0u;

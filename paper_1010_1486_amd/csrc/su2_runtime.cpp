@@ -304,6 +304,9 @@ public:
     hipGraphExec_t gexec = nullptr;
     int32_t g_nsweeps = 0;
     int32_t g_reunit = 0;  // reunitarisation period baked into the graph (0: none)
+    bool rows_graph = false;  // enqueue() is being captured: rows on the graph's counter
+    int64_t g_rows_cap = 0;   // history rows the capture's buffer holds (0: no history)
+    int64_t g_rows_next = 0;  // first row the next replay writes
     // work queue
     bool queue_used = false;           // queue launches since the last error check
     uint32_t spin_limit = 1u << 22;    // polls per bounded wait
@@ -360,6 +363,7 @@ public:
         graph = nullptr;
         g_nsweeps = 0;
         g_reunit = 0;
+        g_rows_cap = g_rows_next = 0;
     }
 
     // Geometry, workgroup ranges and descriptors (uploaded synchronously).
@@ -502,6 +506,7 @@ public:
         p.want_p = hist && (meas & SU2_MEAS_PLAQ) ? 1u : 0u;
         p.want_l = hist && (meas & SU2_MEAS_POLY) ? 1u : 0u;
         p.rows = hist ? 1u : 0u;
+        p.graph_rows = rows_graph ? 1u : 0u;
         const uint64_t per_sweep = (uint64_t)(8u + p.want_l + (p.reunit ? 1u + p.want_p : 0u)) *
                                    total_blocks;
         const int64_t max_ns = (int64_t)((((uint64_t)1 << 31) - 1u) / per_sweep);
@@ -564,9 +569,10 @@ public:
         if (rc) return rc;
         if (hist && reset_rows) HIP_TRY(launch_set_counter(ens(), 0, 0, 2, stream));
         if (cfg.queue && !f64) return enqueue_queue(ns, tab, reunit_every, meas, hist);
+        const int gflag = rows_graph ? 8 : 0;
         if (small_path()) {
             const int flags = (hist && (meas & SU2_MEAS_PLAQ) ? 1 : 0) |
-                              (hist && (meas & SU2_MEAS_POLY) ? 2 : 0) | (hist ? 4 : 0);
+                              (hist && (meas & SU2_MEAS_POLY) ? 2 : 0) | (hist ? 4 | gflag : 0);
             HIP_TRY(launch_small_sweeps(ens(), ns, seed, reunit_every, flags, hist, tab, stream));
             sweep += (uint32_t)ns;
             return SU2_OK;
@@ -586,7 +592,7 @@ public:
             if (want_p && !fused) HIP_TRY(plaquette_launch());
             const bool want_l = hist && (meas & SU2_MEAS_POLY);
             if (want_l) HIP_TRY(polyakov_launch());
-            const int flags = (want_p ? 1 : 0) | (want_l ? 2 : 0) | (hist ? 4 : 0);
+            const int flags = (want_p ? 1 : 0) | (want_l ? 2 : 0) | (hist ? 4 | gflag : 0);
             HIP_TRY(launch_sweep_end(ens(), flags, hist, stream));
         }
         sweep += (uint32_t)ns;
@@ -594,10 +600,15 @@ public:
     }
 
     // Capture `ns` sweeps (as enqueue) into a graph replayed by replay().  The
-    // history rows continue across replays (the row index lives on the device).
-    int capture(int32_t ns, int mode, int32_t reunit_every, int meas, double *hist)
+    // history rows continue across replays: the graph's sweeps count rows on
+    // their own device counter (graph_row), reset here and advanced only by
+    // replays, so direct measured sweeps between replays do not move them.
+    int capture(int32_t ns, int mode, int32_t reunit_every, int meas, double *hist,
+                int64_t hist_rows)
     {
         if (ns <= 0) return fail(SU2_EINVAL, "nsweeps must be > 0");
+        if (hist && hist_rows < ns)
+            return fail(SU2_EINVAL, "dev_history must hold at least nsweeps rows");
         if (reunit_every > 0 && (ns % reunit_every || sweep % (uint32_t)reunit_every))
             return fail(SU2_EINVAL, "with reunitarisation the captured sweeps must span whole "
                                     "periods starting at a period boundary");
@@ -606,11 +617,13 @@ public:
         if (rc) return rc;
         if (!stream) return fail(SU2_ESTATE, "graph capture needs a non-null stream");
         drop_graph();
-        if (hist) HIP_TRY(launch_set_counter(ens(), 0, 0, 2, stream));
+        if (hist) HIP_TRY(launch_set_counter(ens(), 0, 0, 32, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         const uint32_t s0 = sweep;
         HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        rows_graph = true;
         rc = enqueue(ns, mode, reunit_every, meas, hist, false);
+        rows_graph = false;
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(stream, &gr);
         sweep = s0;  // capturing ran nothing
@@ -628,6 +641,8 @@ public:
         graph = gr;
         g_nsweeps = ns;
         g_reunit = reunit_every > 0 ? reunit_every : 0;
+        g_rows_cap = hist ? hist_rows : 0;
+        g_rows_next = 0;
         return SU2_OK;
     }
 
@@ -640,8 +655,14 @@ public:
         if (g_reunit > 0 && sweep % (uint32_t)g_reunit)
             return fail(SU2_ESTATE, "replay must start at a reunitarisation period boundary "
                                     "(sweeps were run since the capture)");
+        if (g_rows_cap > 0 && g_rows_next + (int64_t)count * g_nsweeps > g_rows_cap)
+            return fail(SU2_EINVAL, "the replays would write history rows " +
+                                        std::to_string(g_rows_next) + ".." +
+                                        std::to_string(g_rows_next + (int64_t)count * g_nsweeps - 1) +
+                                        " but dev_history holds " + std::to_string(g_rows_cap));
         for (int32_t i = 0; i < count; ++i) HIP_TRY(hipGraphLaunch(gexec, stream));
         sweep += (uint32_t)(count * g_nsweeps);
+        if (g_rows_cap > 0) g_rows_next += (int64_t)count * g_nsweeps;
         return SU2_OK;
     }
 
@@ -1005,13 +1026,40 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
 }
 
 // ===================================================== single lattice (C ABI)
+struct su2_nn {
+    NNBuffers b;
+    int64_t ndata = 0;     // training samples held
+    int64_t act_cap = 0;   // batch capacity of the per-sample record
+    int step = 0;          // Adam step counter
+    bool table_ready = false;
+    hipStream_t stream = nullptr;
+    double *dev_loss = nullptr;  // per-step losses of the last train call
+    int loss_cap = 0;
+    std::atomic<int> users{0};   // contexts and batches whose sweeps read the table
+};
+
 struct su2_ctx {
     Ensemble E;
+    su2_nn *proposal = nullptr;  // attached learned proposal (its table is E.table)
 };
 
 struct su2_batch {
     Ensemble E;
+    su2_nn *proposal = nullptr;
 };
+
+namespace {
+
+// Point `slot` at n: the previous proposal loses a user, n gains one, so
+// su2_nn_destroy can refuse while any lattice still reads its table.
+void attach_proposal(su2_nn *&slot, su2_nn *n)
+{
+    if (slot) slot->users.fetch_sub(1);
+    slot = n;
+    if (n) n->users.fetch_add(1);
+}
+
+}  // namespace
 
 namespace {
 
@@ -1176,6 +1224,7 @@ int su2_destroy(su2_ctx *c)
     SU2_API_BEGIN
     if (!c) return fail(SU2_EINVAL, "context is NULL");
     c->E.release();
+    attach_proposal(c->proposal, nullptr);
     delete c;
     return SU2_OK;
     SU2_API_END
@@ -1205,7 +1254,7 @@ int su2_sweep_measure(su2_ctx *c, int32_t nsweeps, int mode, int32_t reunit_ever
 }
 
 int su2_capture_sweeps(su2_ctx *c, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
-                       double *dev_history)
+                       double *dev_history, int64_t history_rows)
 {
     SU2_API_BEGIN
     int rc = check_ctx(c);
@@ -1213,7 +1262,8 @@ int su2_capture_sweeps(su2_ctx *c, int32_t nsweeps, int mode, int32_t reunit_eve
     if (reunit_every < 0 || (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)))
         return fail(SU2_EINVAL, "bad arguments");
     if (meas && !dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
-    return c->E.capture(nsweeps, mode, reunit_every, meas, meas ? dev_history : nullptr);
+    return c->E.capture(nsweeps, mode, reunit_every, meas, meas ? dev_history : nullptr,
+                        history_rows);
     SU2_API_END
 }
 
@@ -1504,6 +1554,7 @@ int su2_batch_destroy(su2_batch *b)
     SU2_API_BEGIN
     if (!b) return fail(SU2_EINVAL, "batch is NULL");
     b->E.release();
+    attach_proposal(b->proposal, nullptr);
     delete b;
     return SU2_OK;
     SU2_API_END
@@ -1544,7 +1595,7 @@ int su2_batch_sweep_measure(su2_batch *b, int32_t nsweeps, int mode, int32_t reu
 }
 
 int su2_batch_capture(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
-                      double *dev_history)
+                      double *dev_history, int64_t history_rows)
 {
     SU2_API_BEGIN
     int rc = check_batch(b);
@@ -1552,7 +1603,8 @@ int su2_batch_capture(su2_batch *b, int32_t nsweeps, int mode, int32_t reunit_ev
     if (reunit_every < 0 || (meas & ~(SU2_MEAS_PLAQ | SU2_MEAS_POLY)))
         return fail(SU2_EINVAL, "bad arguments");
     if (meas && !dev_history) return fail(SU2_EINVAL, "dev_history is NULL");
-    return b->E.capture(nsweeps, mode, reunit_every, meas, meas ? dev_history : nullptr);
+    return b->E.capture(nsweeps, mode, reunit_every, meas, meas ? dev_history : nullptr,
+                        history_rows);
     SU2_API_END
 }
 
@@ -1870,16 +1922,6 @@ int su2_test_gauge_transform(su2_ctx *c, uint64_t seed)
 }
 
 /* ===================================================== learned proposal */
-struct su2_nn {
-    NNBuffers b;
-    int64_t ndata = 0;     // training samples held
-    int64_t act_cap = 0;   // batch capacity of the per-sample record
-    int step = 0;          // Adam step counter
-    bool table_ready = false;
-    hipStream_t stream = nullptr;
-    double *dev_loss = nullptr;  // per-step losses of the last train call
-    int loss_cap = 0;
-};
 
 static void nn_free(su2_nn *n)
 {
@@ -1951,6 +1993,10 @@ int su2_nn_destroy(su2_nn *n)
 {
     SU2_API_BEGIN
     if (!n) return fail(SU2_EINVAL, "nn is NULL");
+    if (const int u = n->users.load())
+        return fail(SU2_ESTATE, "the proposal is still attached to " + std::to_string(u) +
+                                    " lattice(s) or batch(es); detach it with "
+                                    "su2_set_proposal(..., NULL) or destroy them first");
     (void)hipStreamSynchronize(n->stream);
     nn_free(n);
     delete n;
@@ -2164,6 +2210,7 @@ int su2_set_proposal(su2_ctx *c, su2_nn *n)
     if (n && !n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
     c->E.drop_graph();
     c->E.table = n ? n->b.table : nullptr;
+    attach_proposal(c->proposal, n);
     return SU2_OK;
     SU2_API_END
 }
@@ -2176,6 +2223,7 @@ int su2_batch_set_proposal(su2_batch *b, su2_nn *n)
     if (n && !n->table_ready) return fail(SU2_ESTATE, "table not built (su2_nn_build_table)");
     b->E.drop_graph();
     b->E.table = n ? n->b.table : nullptr;
+    attach_proposal(b->proposal, n);
     return SU2_OK;
     SU2_API_END
 }

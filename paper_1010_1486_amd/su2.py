@@ -66,14 +66,14 @@ _SIGS = {
     "su2_autotune": (_int, [_vp, ctypes.c_char_p, _int, _vp]),
     "su2_get_launch": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "su2_batch_get_launch": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
-    "su2_capture_sweeps": (_int, [_vp, _i32, _int, _i32, _int, _vp]),
+    "su2_capture_sweeps": (_int, [_vp, _i32, _int, _i32, _int, _vp, _i64]),
     "su2_replay_sweeps": (_int, [_vp, _i32]),
     "su2_batch_init": (_int, [_vp, _i32, _vp, _vp, _vp, _u64, _vp]),
     "su2_batch_destroy": (_int, [_vp]),
     "su2_batch_size": (_int, [_vp, _vp]),
     "su2_batch_sweep": (_int, [_vp, _i32, _int]),
     "su2_batch_sweep_measure": (_int, [_vp, _i32, _int, _i32, _int, _vp]),
-    "su2_batch_capture": (_int, [_vp, _i32, _int, _i32, _int, _vp]),
+    "su2_batch_capture": (_int, [_vp, _i32, _int, _i32, _int, _vp, _i64]),
     "su2_batch_replay": (_int, [_vp, _i32]),
     "su2_batch_observables": (_int, [_vp, _vp, _vp, _vp]),
     "su2_batch_get_links": (_int, [_vp, _i32, _vp]),
@@ -268,9 +268,10 @@ def su2_autotune(h, cache_path=None, mode=SU2_KP):
     return us.value
 
 
-def su2_capture_sweeps(h, nsweeps, mode=SU2_KP, reunit_every=0, meas=0, dev_history_ptr=None):
+def su2_capture_sweeps(h, nsweeps, mode=SU2_KP, reunit_every=0, meas=0, dev_history_ptr=None,
+                       history_rows=0):
     _check(lib().su2_capture_sweeps(h, int(nsweeps), int(mode), int(reunit_every), int(meas),
-                                    _vp(dev_history_ptr)))
+                                    _vp(dev_history_ptr), int(history_rows)))
 
 
 def su2_replay_sweeps(h, count):
@@ -509,6 +510,7 @@ class Lattice:
         if getattr(self, "h", None) is not None:
             su2_destroy(self.h)
             self.h = None
+        self._proposal = None
 
     def __del__(self):
         try:
@@ -572,8 +574,14 @@ class Lattice:
         return su2_get_launch(self.h)
 
     def capture(self, nsweeps, mode=SU2_KP, reunit_every=0, meas=0, hist=None):
+        """hist: FP64 device tensor of shape (rows, 3); the k-th replay writes rows
+        k*nsweeps.. and replays past its last row are refused."""
+        rows = 0
+        if hist is not None:
+            assert hist.dtype == self.torch.float64 and hist.is_contiguous()
+            rows = hist.numel() // 3
         su2_capture_sweeps(self.h, nsweeps, mode, reunit_every, meas,
-                           None if hist is None else hist.data_ptr())
+                           None if hist is None else hist.data_ptr(), rows)
 
     def replay(self, count):
         su2_replay_sweeps(self.h, count)
@@ -593,7 +601,9 @@ class Lattice:
         su2_test_gauge_transform(self.h, seed)
 
     def set_proposal(self, nn):
+        """Attach nn (None detaches); the lattice keeps nn alive while attached."""
         su2_set_proposal(self.h, None if nn is None else nn.h)
+        self._proposal = nn
 
     def wilson_loops(self, rmax, tmax):
         """W(R, T) for R = 1..rmax, T = 1..tmax as an (rmax, tmax) array."""
@@ -660,6 +670,7 @@ class Batch:
         if getattr(self, "h", None) is not None:
             _check(lib().su2_batch_destroy(self.h))
             self.h = None
+        self._proposal = None
 
     def __del__(self):
         try:
@@ -689,8 +700,16 @@ class Batch:
         return hist
 
     def capture(self, n, mode=SU2_KP, reunit_every=0, meas=0, hist=None):
+        """hist: FP64 device tensor of shape (rows, replicas, 3); the k-th replay
+        writes rows k*n.. and replays past its last row are refused."""
+        rows = 0
+        if hist is not None:
+            import torch
+            assert hist.dtype == torch.float64 and hist.is_contiguous()
+            rows = hist.numel() // (3 * self.n)
         _check(lib().su2_batch_capture(self.h, int(n), int(mode), int(reunit_every), int(meas),
-                                       None if hist is None else _vp(hist.data_ptr())))
+                                       None if hist is None else _vp(hist.data_ptr()),
+                                       int(rows)))
 
     def replay(self, count):
         _check(lib().su2_batch_replay(self.h, int(count)))
@@ -730,7 +749,9 @@ class Batch:
         _check(lib().su2_batch_synchronize(self.h))
 
     def set_proposal(self, nn):
+        """Attach nn (None detaches); the batch keeps nn alive while attached."""
         _check(lib().su2_batch_set_proposal(self.h, None if nn is None else nn.h))
+        self._proposal = nn
 
     def set_overrelax(self, width):
         """width < 0: independence proposal; 0..1: over-relaxed learned proposal."""

@@ -50,11 +50,11 @@ def test_graph_replay_equals_direct(su2):
     with torch.cuda.stream(side):
         with su2.Batch(DIMS, BETAS, STARTS, seed) as a, su2.Batch(DIMS, BETAS, STARTS, seed) as g:
             ha = a.sweep_measure(12, meas=3, reunit_every=4).cpu().numpy()
-            hg = torch.zeros((12, len(DIMS), 3), dtype=torch.float64, device="cuda")
+            hg = torch.zeros((16, len(DIMS), 3), dtype=torch.float64, device="cuda")
             g.capture(4, meas=3, reunit_every=4, hist=hg)
             g.replay(3)
             g.synchronize()
-            np.testing.assert_array_equal(hg.cpu().numpy(), ha)
+            np.testing.assert_array_equal(hg[:12].cpu().numpy(), ha)
             for r in range(len(DIMS)):
                 np.testing.assert_array_equal(g.get_links(r), a.get_links(r))
             # off the reunitarisation period the recorded schedule would drift
@@ -63,8 +63,14 @@ def test_graph_replay_equals_direct(su2):
                 g.replay(1)
             assert e.value.code == su2.SU2_ESTATE
             g.sweep(3)
-            g.replay(1)
+            g.replay(1)  # the fourth replay since the capture: rows 12..15
             g.synchronize()
+            assert np.all(hg[12:, :, 0].cpu().numpy() != 0)
+            # a fifth replay would write past the 16 rows: refused, nothing enqueued
+            g.sweep(4)
+            with pytest.raises(su2.SU2Error) as e:
+                g.replay(1)
+            assert e.value.code == su2.SU2_EINVAL
         with su2.Lattice([8, 8, 8, 8], 2.2, 3, su2.SU2_HOT) as x, \
                 su2.Lattice([8, 8, 8, 8], 2.2, 3, su2.SU2_HOT) as y:
             x.heatbath_sweep(6)
@@ -253,3 +259,47 @@ def test_xcd_affine_launch_measurements_identical(su2):
         np.testing.assert_array_equal(x[..., 0], y[..., 0])
         np.testing.assert_allclose(x[..., 1:], y[..., 1:], atol=1e-6, rtol=0)
     np.testing.assert_array_equal(ac[1], bc[1])
+
+
+def test_graph_rows_with_direct_measurements_between_replays(su2):
+    """The k-th replay since a capture writes rows k*ns.. of the capture's
+    history buffer even when direct measured sweeps run between the replays
+    (they count their rows from the start of each call), for a lattice and a
+    batch; a replay past the buffer's rows is refused."""
+    announce("graph rows with direct measurements between replays")
+    import torch
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with su2.Lattice([8, 6, 8, 4], 2.5, 4, su2.SU2_HOT) as x, \
+                su2.Lattice([8, 6, 8, 4], 2.5, 4, su2.SU2_HOT) as y:
+            hy = torch.zeros((6, 3), dtype=torch.float64, device="cuda")
+            y.capture(3, meas=3, hist=hy)
+            want = []
+            for k in range(2):
+                y.replay(1)
+                want.append(x.sweep_measure(3, meas=3).cpu().numpy())
+                # direct measured sweeps on both lattices between the replays
+                ey = y.sweep_measure(2 + k, meas=3).cpu().numpy()
+                ex = x.sweep_measure(2 + k, meas=3).cpu().numpy()
+                np.testing.assert_array_equal(ey, ex)
+            y.synchronize()
+            np.testing.assert_array_equal(hy.cpu().numpy(), np.concatenate(want))
+            np.testing.assert_array_equal(x.get_links(), y.get_links())
+            with pytest.raises(su2.SU2Error) as e:
+                y.replay(1)
+            assert e.value.code == su2.SU2_EINVAL
+        with su2.Batch(DIMS, BETAS, STARTS, 7) as a, su2.Batch(DIMS, BETAS, STARTS, 7) as g:
+            hg = torch.zeros((4, len(DIMS), 3), dtype=torch.float64, device="cuda")
+            g.capture(2, meas=3, hist=hg)
+            want = []
+            for k in range(2):
+                g.replay(1)
+                want.append(a.sweep_measure(2, meas=3).cpu().numpy())
+                np.testing.assert_array_equal(g.sweep_measure(1, meas=3).cpu().numpy(),
+                                              a.sweep_measure(1, meas=3).cpu().numpy())
+            g.synchronize()
+            np.testing.assert_array_equal(hg.cpu().numpy(), np.concatenate(want))
+            with pytest.raises(su2.SU2Error) as e:
+                g.replay(1)
+            assert e.value.code == su2.SU2_EINVAL
+    torch.cuda.synchronize()
