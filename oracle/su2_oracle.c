@@ -419,6 +419,61 @@ void orc_sweeps(const int32_t dims[4], double *U, int32_t nsweeps, uint32_t swee
     free(pm);
 }
 
+/* ------------------------------------------------------- over-relaxation */
+void orc_overrelax_link(const double V[4], const double U[4], double out[4])
+{
+    double k = qnorm(V);
+    if (!(k > 0.0)) {
+        memcpy(out, U, 4 * sizeof(double));
+        return;
+    }
+    double Utd[4] = {V[0] / k, -V[1] / k, -V[2] / k, -V[3] / k}; /* U~^+ */
+    double Ud[4], T[4];
+    orc_qdag(U, Ud);
+    orc_qmul(Utd, Ud, T);
+    orc_qmul(T, Utd, out);
+}
+
+void orc_or_pass(const int32_t dims[4], double *U, int mu, int parity)
+{
+    const int64_t Vol = orc_volume(dims);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < Vol; ++s) {
+        if (orc_parity(dims, s) != parity) continue;
+        double V[4], out[4];
+        orc_staple(dims, U, s, mu, V);
+        orc_overrelax_link(V, U + (s * 4 + mu) * 4, out);
+        memcpy(U + (s * 4 + mu) * 4, out, sizeof(out));
+    }
+}
+
+void orc_sweeps_or(const int32_t dims[4], double *U, int32_t nsweeps, int32_t n_or,
+                   uint32_t sweep0, double beta, uint64_t seed, uint32_t replica,
+                   int32_t reunit_every, int nthreads, double *plaq_hist, double *poly_hist)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int order = nthreads > 1 ? 3 : 0;
+    for (int32_t i = 0; i < nsweeps; ++i) {
+        uint32_t sw = sweep0 + (uint32_t)i;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int p = 0; p < 2; ++p)
+                orc_pass(dims, U, mu, p, sw, beta, seed, replica, order, 0, NULL);
+        for (int32_t k = 0; k < n_or; ++k)
+            for (int mu = 0; mu < 4; ++mu)
+                for (int p = 0; p < 2; ++p) orc_or_pass(dims, U, mu, p);
+        if (reunit_every > 0 && ((sw + 1u) % (uint32_t)reunit_every) == 0u)
+            orc_reunitarize(dims, U);
+        if (plaq_hist) plaq_hist[i] = orc_plaquette(dims, U);
+        if (poly_hist) {
+            double ls, la;
+            orc_polyakov(dims, U, &ls, &la);
+            poly_hist[i] = ls;
+        }
+    }
+}
+
 /* ------------------------------------------------------------ init / misc */
 void orc_haar_from_block(const uint32_t w[4], double out[4])
 {

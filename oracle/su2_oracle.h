@@ -107,6 +107,20 @@ void orc_sweeps(const int32_t dims[4], double *U, int32_t nsweeps, uint32_t swee
                 double beta, uint64_t seed, uint32_t replica, int32_t reunit_every,
                 int nthreads, double *plaq_hist, double *poly_hist, double *margin);
 
+/* Microcanonical over-relaxation of one link (not in the paper; Brown & Woch
+ * 1987, Creutz 1987): with U~ = V/|V| and X = U U~, the reflection X -> X^+
+ * keeps x0 = (1/2)Tr(U V)/|V|, hence the Sec. 2 weight exp[(beta/2) Tr(U V)],
+ * and the Haar measure; U' = X^+ U~^+ = U~^+ U^+ U~^+.  V = 0 leaves U. */
+void orc_overrelax_link(const double V[4], const double U[4], double out[4]);
+/* One over-relaxation pass (direction mu, sites of the given parity). */
+void orc_or_pass(const int32_t dims[4], double *U, int mu, int parity);
+/* nsweeps compound sweeps: the heat-bath sweep of index sweep0 + i, then n_or
+ * over-relaxation sweeps (mu 0..3, even then odd), then reunitarisation and
+ * the measurements as orc_sweeps (reunit_every counts compound sweeps). */
+void orc_sweeps_or(const int32_t dims[4], double *U, int32_t nsweeps, int32_t n_or,
+                   uint32_t sweep0, double beta, uint64_t seed, uint32_t replica,
+                   int32_t reunit_every, int nthreads, double *plaq_hist, double *poly_hist);
+
 void orc_init(const int32_t dims[4], double *U, int start, uint64_t seed, uint32_t replica);
 void orc_reunitarize(const int32_t dims[4], double *U);
 double orc_plaquette(const int32_t dims[4], const double *U);

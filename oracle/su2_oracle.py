@@ -55,6 +55,10 @@ def _load():
         "orc_sweeps": (None, [_i32p, _f64p, ctypes.c_int32, c_u32, c_d, c_u64, c_u32,
                               ctypes.c_int32, c_int, vp, vp, vp]),
         "orc_init": (None, [_i32p, _f64p, c_int, c_u64, c_u32]),
+        "orc_overrelax_link": (None, [_f64p, _f64p, _f64p]),
+        "orc_or_pass": (None, [_i32p, _f64p, c_int, c_int]),
+        "orc_sweeps_or": (None, [_i32p, _f64p, ctypes.c_int32, ctypes.c_int32, c_u32, c_d, c_u64,
+                                 c_u32, ctypes.c_int32, c_int, vp, vp]),
         "orc_reunitarize": (None, [_i32p, _f64p]),
         "orc_plaquette": (c_d, [_i32p, _f64p]),
         "orc_staple_action": (c_d, [_i32p, _f64p]),
@@ -216,6 +220,28 @@ def sweeps(dims, U, nsweeps, sweep0, beta, seed, replica=0, reunit_every=0, nthr
                        _ptr(ph), _ptr(lh), _ptr(margin))
     out = ((ph, lh) if measure else ()) + ((margin,) if want_margin else ())
     return out if len(out) > 1 else (out[0] if out else None)
+
+
+def overrelax_link(V, U):
+    out = np.zeros(4)
+    _load().orc_overrelax_link(np.ascontiguousarray(V, np.float64),
+                               np.ascontiguousarray(U, np.float64), out)
+    return out
+
+
+def or_pass(dims, U, mu, par):
+    _load().orc_or_pass(_dims(dims), _c(U), int(mu), int(par))
+
+
+def sweeps_or(dims, U, nsweeps, n_or, sweep0, beta, seed, replica=0, reunit_every=0, nthreads=1,
+              measure=False):
+    """Compound sweeps (heat bath, then n_or over-relaxation sweeps)."""
+    ph = np.zeros(nsweeps) if measure else None
+    lh = np.zeros(nsweeps) if measure else None
+    _load().orc_sweeps_or(_dims(dims), _c(U), int(nsweeps), int(n_or), int(sweep0), float(beta),
+                          np.uint64(seed), int(replica), int(reunit_every), int(nthreads),
+                          _ptr(ph), _ptr(lh))
+    return (ph, lh) if measure else None
 
 
 def reunitarize(dims, U):
