@@ -108,6 +108,20 @@ def tau_int(x, c=6.0):
     return max(tau, 0.5)
 
 
+def tau_int_err(tau, n, c=6.0):
+    """Madras-Sokal error of an integrated autocorrelation time measured with
+    window c tau on n samples: tau sqrt(2 (2 W + 1) / n), W = c tau."""
+    return tau * np.sqrt(2.0 * (2.0 * c * tau + 1.0) / n)
+
+
+def jackknife_mean(x):
+    """Mean over the replicas and its leave-one-out (jackknife) error."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    loo = (x.sum() - x) / (n - 1)
+    return float(x.mean()), float(np.sqrt((n - 1) / n * ((loo - loo.mean()) ** 2).sum()))
+
+
 def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu=True):
     """64 replicas, L = 8 + 2 (r mod 7) (8^4 .. 20^4), beta uniform in [1.8, 3.0]
     (seeded), hot start; the learned proposal is trained on the GPU on 1e7
@@ -118,7 +132,13 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu
     proposal) runs the same protocol for comparison, and so does the trained
     flow used over-relaxed (proposal -g(x_old) + noise in the flow coordinate,
     noise half-width OR_WIDTH, and without noise), which anticorrelates
-    successive plaquettes."""
+    successive plaquettes.  The baselines without learning are the plain heat
+    bath and the heat bath followed by 1 or 3 microcanonical over-relaxation
+    sweeps (compound sweeps; rates count every link update, tau_int counts
+    compound sweeps).  Error bars: tau_int and the effective rates as means
+    over the replicas with jackknife errors; the ratio to the plain heat bath
+    as the replica-paired mean ratio with its jackknife error; per replica the
+    Madras-Sokal error of tau_int as well."""
     n = 64
     L = [8 + 2 * (r % 7) for r in range(n)]
     dims = [[l] * 4 for l in L]
@@ -142,14 +162,19 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu
                            "nll_last_100": float(hist[-100:].mean())}
         untrained = su2.NN(seed=5)  # identity spline: the uniform proposal
         untrained.build_table()
-        for name, mode, proposal, width in (
-                ("plain", su2.SU2_KP, net, -1.0), ("learned", su2.SU2_LEARNED, net, -1.0),
-                ("learned_untrained", su2.SU2_LEARNED, untrained, -1.0),
-                ("learned_overrelaxed", su2.SU2_LEARNED, net, OR_WIDTH),
-                ("learned_reflection", su2.SU2_LEARNED, net, 0.0)):
+        eff_r = {}
+        for name, mode, proposal, width, n_or in (
+                ("plain", su2.SU2_KP, net, -1.0, 0),
+                ("plain_overrelaxed", su2.SU2_KP_OR, net, -1.0, 1),
+                ("plain_overrelaxed3", su2.SU2_KP_OR, net, -1.0, 3),
+                ("learned", su2.SU2_LEARNED, net, -1.0, 0),
+                ("learned_untrained", su2.SU2_LEARNED, untrained, -1.0, 0),
+                ("learned_overrelaxed", su2.SU2_LEARNED, net, OR_WIDTH, 0),
+                ("learned_reflection", su2.SU2_LEARNED, net, 0.0, 0)):
             b = su2.Batch(dims, betas, [1] * n, seed=5, device=dev)
             b.set_proposal(proposal)
             b.set_overrelax(width)
+            b.set_hb_overrelax(n_or)
             tuned_us = b.autotune(None, mode)
             launch = b.launch()
             b.sweep(therm, mode)
@@ -164,18 +189,32 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu
             prop, acc = b.accept_stats()
             P = h.cpu().numpy()[:, :, 0]
             taus = np.array([tau_int(P[:, r]) for r in range(n)])
-            sps = sweeps / dt
-            bpu = 128 if mode == su2.SU2_KP else 144  # the learned update also reads the old link
-            gbs = bpu * links * sps / 1e9
-            out[name] = {"link_updates_per_s": links * sps, "sweeps_per_s": sps,
+            sps = sweeps / dt  # (compound) sweeps per second
+            # bytes per update: the heat bath 128; the learned and over-relaxation
+            # updates also read the old link (144)
+            bpu = ((128 + 144 * n_or) / (1 + n_or) if mode == su2.SU2_KP_OR else
+                   (128 if mode == su2.SU2_KP else 144))
+            ups = links * (1 + n_or) * sps
+            gbs = bpu * ups / 1e9
+            eff_r[name] = sps / (2 * taus)
+            tau_m, tau_e = jackknife_mean(taus)
+            eff_m, eff_e = jackknife_mean(eff_r[name])
+            out[name] = {"link_updates_per_s": ups, "sweeps_per_s": sps,
                          "algorithmic_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                          "bytes_per_update": bpu,
-                         "overrelax_width": None if width < 0 else width, "launch": launch,
-                         "tuned_us_per_sweep": tuned_us,
-                         "tau_int_plaquette_mean": float(taus.mean()),
-                         "effective_sweeps_per_s": float(np.mean(sps / (2 * taus))),
+                         "overrelax_width": None if width < 0 else width,
+                         "or_sweeps_per_heatbath": n_or if mode == su2.SU2_KP_OR else None,
+                         "launch": launch, "tuned_us_per_sweep": tuned_us,
+                         "tau_int_plaquette_mean": tau_m, "tau_int_plaquette_err": tau_e,
+                         "tau_int_madras_sokal_err_per_replica_mean":
+                             float(np.mean(tau_int_err(taus, sweeps))),
+                         "effective_sweeps_per_s": eff_m, "effective_sweeps_per_s_err": eff_e,
                          "acceptance": (float(acc.sum() / prop.sum()) if prop.sum() else None),
                          "mean_plaquette": float(P.mean())}
+            if name != "plain":
+                r_m, r_e = jackknife_mean(eff_r[name] / eff_r["plain"])
+                out[name]["effective_over_plain"] = r_m
+                out[name]["effective_over_plain_err"] = r_e
             b.close()
         net.close()
         untrained.close()
@@ -194,6 +233,12 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu
     out["overrelaxed_over_plain_effective"] = (
         out["learned_overrelaxed"]["effective_sweeps_per_s"] /
         out["plain"]["effective_sweeps_per_s"])
+    # the fair comparison of the over-relaxed learned form: against the heat
+    # bath with the standard over-relaxation (replica-paired ratio)
+    for base in ("plain_overrelaxed", "plain_overrelaxed3"):
+        r_m, r_e = jackknife_mean(eff_r["learned_overrelaxed"] / eff_r[base])
+        out[f"learned_overrelaxed_over_{base}_effective"] = r_m
+        out[f"learned_overrelaxed_over_{base}_effective_err"] = r_e
     return out
 
 

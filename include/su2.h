@@ -59,7 +59,7 @@ enum {
 };
 
 enum { SU2_COLD = 0, SU2_HOT = 1 };
-enum { SU2_KP = 0, SU2_LEARNED = 1 };
+enum { SU2_KP = 0, SU2_LEARNED = 1, SU2_KP_OR = 2 };
 enum { SU2_MEAS_PLAQ = 1, SU2_MEAS_POLY = 2 };
 
 /* Message for the last failing call on this host thread ("" if none). */
@@ -129,7 +129,12 @@ int su2_destroy(su2_ctx *ctx);
 /* Enqueue nsweeps (>= 0) heat-bath sweeps (Sec. 2 update, Sec. 4 schedule: for
  * mu = 0..3, even sites then odd sites).  mode SU2_KP uses the exact sampler;
  * SU2_LEARNED the learned proposal with an exact Metropolis step (needs
- * su2_set_proposal).  The sweep index advances by nsweeps. */
+ * su2_set_proposal); SU2_KP_OR makes each sweep a compound sweep: the SU2_KP
+ * sweep, then n_or microcanonical over-relaxation sweeps (su2_set_hb_overrelax;
+ * default 1) in the same order, each link U -> U~^+ U^+ U~^+ with U~ = V/|V|
+ * (keeps (1/2)Tr(U V) and the Haar measure, draws no randoms; V = 0 leaves
+ * U), always as per-pass launches.  The sweep index advances by nsweeps
+ * (one per compound sweep).  FP64 contexts: SU2_KP only. */
 int su2_heatbath_sweep(su2_ctx *ctx, int32_t nsweeps, int mode);
 
 /* Enqueue nsweeps sweeps and measure after each one.  reunit_every > 0
@@ -317,6 +322,12 @@ int su2_nn_get_table(su2_nn *nn, float *table_host);
  * destroyed.  Rebuilding the table of an attached su2_nn changes later sweeps. */
 int su2_set_proposal(su2_ctx *ctx, su2_nn *nn);
 int su2_batch_set_proposal(su2_batch *b, su2_nn *nn);
+/* Over-relaxation sweeps after each heat-bath sweep of an SU2_KP_OR sweep
+ * (0 <= n_or <= 16, else SU2_EINVAL; 0 makes SU2_KP_OR the plain heat bath;
+ * default 1).  Not in the paper: the standard companion of a heat bath that
+ * the learned proposal is compared with.  Drops captured sweeps. */
+int su2_set_hb_overrelax(su2_ctx *ctx, int32_t n_or);
+int su2_batch_set_hb_overrelax(su2_batch *b, int32_t n_or);
 /* Over-relaxed use of the learned flow in SU2_LEARNED sweeps.  width < 0
  * (default): the independence proposal u = 2z - 1 above.  0 <= width <= 1:
  * the proposal u' = -g(x_old) + width (2z - 1), wrapped onto [-1, 1) with
@@ -344,7 +355,7 @@ int su2_test_heatbath_links(const float *V_host, int64_t n, double beta, uint64_
                             uint32_t sweep, uint32_t mu, uint32_t replica, float *out_host,
                             int32_t *ntrials_host);
 /* Enqueue one (mu, parity) pass at the current sweep index (index unchanged);
- * mode SU2_KP or SU2_LEARNED. */
+ * mode SU2_KP or SU2_LEARNED, or SU2_KP_OR for one over-relaxation pass. */
 int su2_test_pass(su2_ctx *ctx, int mu, int parity, int mode);
 /* Bandwidth floor of a (mu, parity) pass (measurement aid): enqueue a kernel
  * that moves the same bytes as the pass -- the seven plane groups it reads,

@@ -299,6 +299,19 @@ __device__ __forceinline__ Q heatbath_link(const Q &V, float beta, uint32_t site
 }
 
 
+// Microcanonical over-relaxation of one link (not in the paper; Brown & Woch
+// 1987, Creutz 1987): with U~ = V/k and X = U U~, the reflection X -> X^+
+// keeps x0 = (1/2)Tr(U V)/k and so the weight exp(beta k x0) of Sec. 2, and it
+// keeps the Haar measure: U' = X^+ U~^+ = U~^+ U^+ U~^+.  k = 0 leaves U.
+__device__ __forceinline__ Q overrelax_link(const Q &V, const Q &U)
+{
+    const float k2 = qdot(V, V);
+    if (!(k2 > 0.0f)) return U;
+    const float inv_k = hw_rsq(k2);
+    const Q Utd{V.w * inv_k, -V.x * inv_k, -V.y * inv_k, -V.z * inv_k};
+    return qmul(qmul(Utd, qdag(U)), Utd);
+}
+
 // ---------------------------------------------------------- learned proposal
 // A monotone rational-quadratic spline flow g on [-1, 1] (Durkan et al. 2019)
 // maps a0 to u = g(a0), uniform on [-1, 1]; its density q(a0) = g'(a0)/2 is

@@ -64,6 +64,18 @@ __device__ __forceinline__ void std4(double *links, uint32_t vh, int mu, int par
     p[1] = make_double2(q.y, q.z);
 }
 
+// Store with the nontemporal hint (the pass writes a class no other site of
+// the pass reads).
+__device__ __forceinline__ void std4_nt(double *links, uint32_t vh, int mu, int par, uint32_t h,
+                                        const QD &q)
+{
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    v2d *p = reinterpret_cast<v2d *>(links) + 2 * ((size_t)(mu * 2 + par) * vh + h);
+    const v2d a = {q.w, q.x}, b = {q.y, q.z};
+    __builtin_nontemporal_store(a, p);
+    __builtin_nontemporal_store(b, p + 1);
+}
+
 // The uniform of a Philox word, (2 (w >> 9) + 1) 2^-24 (exact in FP64).
 __device__ __forceinline__ double ud(uint32_t w) { return (double)(2u * (w >> 9) + 1u) * 0x1p-24; }
 
@@ -200,36 +212,47 @@ __global__ __launch_bounds__(256) void pass64_kernel(const Rep *__restrict__ rep
         const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
         const QD Un = heatbath_link_d(V, R.beta_d, site, sweep,
                                       word2((uint32_t)MU, TAG_TRIAL, R.replica), k0, k1);
-        std4(links, g.vh, MU, par, h, Un);
+        std4_nt(links, g.vh, MU, par, h, Un);
         if (MEASURE) meas = dretr(Un, Vlow);
     }
     if (MEASURE) block_accumulate(meas, R.acc, ACC_PLAQ, blockIdx.x);
 }
 
-// One thread per site (both parities): the six plaquettes at the site,
-// (1/2)Tr(P Q^+) with P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
+// The six plaquettes rooted at the site of parity par at traversal position
+// gid: (1/2)Tr(P Q^+) with P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
+__device__ __forceinline__ double site_plaquettes64(const Geom &g, const double *links,
+                                                    uint32_t gid, int par)
+{
+    const int opp = par ^ 1;
+    const PassSite s = pass_site(g, gid, par);
+    const Deltas d = neighbour_deltas(g, s);
+    QD U[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) U[mu] = ldd(links, g.vh, mu, par, s.h);
+    double acc = 0.0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int nu = mu + 1; nu < 4; ++nu) {
+            const QD P = dmul(U[mu], ldd(links, g.vh, nu, opp, s.h + d.p[mu]));
+            const QD Qq = dmul(U[nu], ldd(links, g.vh, mu, opp, s.h + d.p[nu]));
+            acc += ddot(P, Qq);  // (1/2) Tr(P Q^+)
+        }
+    return acc;
+}
+
+// One thread per half-site: the plaquettes rooted at both of its sites (the
+// two parities), so that each link class is read as own and as neighbour
+// links by the same workgroup.
 __global__ __launch_bounds__(256) void plaquette64_kernel(const Rep *__restrict__ reps)
 {
     const Rep &R = reps[0];
     const Geom &g = R.g;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    if (i < 2u * g.vh) {
-        const int par = i >= g.vh ? 1 : 0, opp = par ^ 1;
+    if (i < g.vh) {
         const double *links = reinterpret_cast<const double *>(R.links);
-        const PassSite s = pass_site(g, par ? i - g.vh : i, par);
-        const Deltas d = neighbour_deltas(g, s);
-        QD U[4];
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) U[mu] = ldd(links, g.vh, mu, par, s.h);
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-            for (int nu = mu + 1; nu < 4; ++nu) {
-                const QD P = dmul(U[mu], ldd(links, g.vh, nu, opp, s.h + d.p[mu]));
-                const QD Qq = dmul(U[nu], ldd(links, g.vh, mu, opp, s.h + d.p[nu]));
-                acc += ddot(P, Qq);  // (1/2) Tr(P Q^+)
-            }
+        acc = site_plaquettes64(g, links, i, 0) + site_plaquettes64(g, links, i, 1);
     }
     block_accumulate(acc, R.acc, ACC_PLAQ, blockIdx.x);
 }
@@ -310,7 +333,7 @@ hipError_t launch_pass64(const Ens &e, int mu, int par, uint64_t seed, bool meas
 
 hipError_t launch_plaquette64(const Ens &e, hipStream_t stream)
 {
-    hipLaunchKernelGGL(plaquette64_kernel, dim3(nblk(2ull * e.max_vh, 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(plaquette64_kernel, dim3(nblk(e.max_vh, 256)), dim3(256), 0, stream,
                        e.reps);
     return hipGetLastError();
 }

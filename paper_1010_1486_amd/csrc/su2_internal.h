@@ -204,6 +204,10 @@ hipError_t launch_init(const Ens &e, const int *starts_dev, uint64_t seed, hipSt
 // acc[ACC_PROPOSED] / acc[ACC_ACCEPTED]); else the exact heat bath.
 hipError_t launch_pass(const Ens &e, int mu, int par, uint64_t seed, bool measure,
                        const float *table, const LaunchCfg &cfg, hipStream_t stream);
+// One microcanonical over-relaxation pass (U' = U~^+ U^+ U~^+, no randoms),
+// in the workgroup layout of launch_pass; measure as launch_pass.
+hipError_t launch_or_pass(const Ens &e, int mu, int par, bool measure, const LaunchCfg &cfg,
+                          hipStream_t stream);
 // Sum of all plaquettes into acc[ACC_PLAQ]; sum of L(x) into acc[ACC_POLY].
 hipError_t launch_plaquette(const Ens &e, hipStream_t stream);
 hipError_t launch_polyakov(const Ens &e, hipStream_t stream);

@@ -118,7 +118,7 @@ __global__ void init_kernel(const Rep *__restrict__ reps, const int *__restrict_
 // the learned-proposal Metropolis step; the new link is stored.  With
 // MEASURE, meas = (1/2)Tr(U'_MU V_nu) summed over nu < MU.  acc: as
 // learned_link (-1 for the heat bath).
-template <int MU, bool MEASURE, bool LEARNED>
+template <int MU, bool MEASURE, bool LEARNED, bool OR = false>
 __device__ __forceinline__ void update_at(const Rep &R, const PassSite &s, int par,
                                           uint32_t sweep, uint32_t k0, uint32_t k1,
                                           const float *ltab, float &meas, int &acc)
@@ -150,7 +150,9 @@ __device__ __forceinline__ void update_at(const Rep &R, const PassSite &s, int p
     }
     const uint32_t site = 2u * h + (uint32_t)(s.x & 1);
     Q Un;
-    if (LEARNED) {
+    if (OR) {
+        Un = overrelax_link(V, ld(arr(links, g.vh, MU, par), h));
+    } else if (LEARNED) {
         const Q Uold = ld(arr(links, g.vh, MU, par), h);
         Un = learned_link(V, Uold, ltab, R.beta, site, sweep, (uint32_t)MU, R.replica, k0, k1,
                           acc, R.orw);
@@ -162,13 +164,13 @@ __device__ __forceinline__ void update_at(const Rep &R, const PassSite &s, int p
     if (MEASURE) meas = retr(Un, Vlow);
 }
 
-template <int MU, bool MEASURE, bool LEARNED>
+template <int MU, bool MEASURE, bool LEARNED, bool OR = false>
 __device__ __forceinline__ void update_site(const Rep &R, uint32_t gid, int par, uint32_t sweep,
                                             uint32_t k0, uint32_t k1, const float *ltab,
                                             float &meas, int &acc)
 {
-    update_at<MU, MEASURE, LEARNED>(R, pass_site(R.g, gid, par), par, sweep, k0, k1, ltab, meas,
-                                    acc);
+    update_at<MU, MEASURE, LEARNED, OR>(R, pass_site(R.g, gid, par), par, sweep, k0, k1, ltab,
+                                        meas, acc);
 }
 
 // Fill the LDS copy of the spline table (4 floats of padding first, like the
@@ -190,7 +192,7 @@ __device__ __forceinline__ const float *load_table_lds(float4 *stab4, const floa
 // of 8) the workgroups loop over b (persistent).  With MEASURE, (1/2)Tr(U'_mu(s) V_nu(s)) summed over nu < mu
 // is accumulated: over the odd passes of mu = 1, 2, 3 this is every
 // plaquette of the end-of-sweep configuration exactly once.
-template <int MU, bool MEASURE, bool LEARNED>
+template <int MU, bool MEASURE, bool LEARNED, bool OR = false>
 __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
                                                    const uint32_t *__restrict__ bmap,
                                                    const uint2 *__restrict__ amap,
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
             // uniform: a scalar load through the constant address space
             const uint32_t sweep =
                 *(const __attribute__((address_space(4))) uint32_t *)&R.cnt->sweep;
-            update_site<MU, MEASURE, LEARNED>(R, gid, par, sweep, k0, k1, ltab, meas, acc);
+            update_site<MU, MEASURE, LEARNED, OR>(R, gid, par, sweep, k0, k1, ltab, meas, acc);
         }
         if (MEASURE) block_accumulate((double)meas, R.acc, ACC_PLAQ, b);
         if (LEARNED) {
@@ -295,19 +297,23 @@ __device__ __forceinline__ float site_plaquettes(const Rep &R, uint32_t i)
     return sum;
 }
 
-// grid (blocks over V, 1, replica).  One thread per site, both parities, in
-// the pass traversal order: (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+
-// = (1/2)Tr(P Q^+) with P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
+// grid (blocks over V/2, 1, replica).  One thread per half-site in the pass
+// traversal order, taking the plaquettes rooted at both of its sites (the two
+// parities, x-neighbours of each other), so that one workgroup reads each
+// link class of its stretch once as the sites' own links and once as their
+// neighbours', close together in time:
+// (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+ = (1/2)Tr(P Q^+) with
+// P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
 __global__ __launch_bounds__(256) void plaquette_kernel(const Rep *__restrict__ reps, int remap)
 {
     const Rep &R = reps[blockIdx.z];
     const Geom &g = R.g;
-    const uint32_t nb = (2u * g.vh + blockDim.x - 1) / blockDim.x;
+    const uint32_t nb = (g.vh + blockDim.x - 1) / blockDim.x;
     if (blockIdx.x >= nb) return;  // uniform: whole workgroup
     const uint32_t blk = logical_block(blockIdx.x, nb, remap, 0);
     const uint32_t i = blk * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    if (i < 2u * g.vh) acc = (double)site_plaquettes(R, i);
+    if (i < g.vh) acc = (double)site_plaquettes(R, i) + (double)site_plaquettes(R, i + g.vh);
     block_accumulate(acc, R.acc, ACC_PLAQ, blockIdx.x);
 }
 
@@ -1022,7 +1028,7 @@ inline uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
 inline unsigned nblk(uint64_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 inline unsigned round8(unsigned n) { return (n + 7u) & ~7u; }
 
-template <int MU, bool LEARNED>
+template <int MU, bool LEARNED, bool OR = false>
 void launch_pass_mu(const Ens &e, int par, uint64_t seed, bool measure, const float *table,
                     const LaunchCfg &cfg, hipStream_t stream)
 {
@@ -1032,11 +1038,11 @@ void launch_pass_mu(const Ens &e, int par, uint64_t seed, bool measure, const fl
     if (grid == 0) grid = 8;
     const int rev = cfg.snake ? par : 0;
     if (measure)
-        hipLaunchKernelGGL((pass_kernel<MU, true, LEARNED>), dim3(grid), dim3(cfg.pass_block), 0,
+        hipLaunchKernelGGL((pass_kernel<MU, true, LEARNED, OR>), dim3(grid), dim3(cfg.pass_block), 0,
                            stream, e.reps, e.bmap, e.amap, total, par, lo32(seed), hi32(seed),
                            (int)cfg.xcd_remap, rev, table);
     else
-        hipLaunchKernelGGL((pass_kernel<MU, false, LEARNED>), dim3(grid), dim3(cfg.pass_block), 0,
+        hipLaunchKernelGGL((pass_kernel<MU, false, LEARNED, OR>), dim3(grid), dim3(cfg.pass_block), 0,
                            stream, e.reps, e.bmap, e.amap, total, par, lo32(seed), hi32(seed),
                            (int)cfg.xcd_remap, rev, table);
 }
@@ -1072,9 +1078,21 @@ hipError_t launch_pass(const Ens &e, int mu, int par, uint64_t seed, bool measur
     return hipGetLastError();
 }
 
+hipError_t launch_or_pass(const Ens &e, int mu, int par, bool measure, const LaunchCfg &cfg,
+                          hipStream_t stream)
+{
+    switch (mu) {
+    case 0: launch_pass_mu<0, false, true>(e, par, 0, measure, nullptr, cfg, stream); break;
+    case 1: launch_pass_mu<1, false, true>(e, par, 0, measure, nullptr, cfg, stream); break;
+    case 2: launch_pass_mu<2, false, true>(e, par, 0, measure, nullptr, cfg, stream); break;
+    default: launch_pass_mu<3, false, true>(e, par, 0, measure, nullptr, cfg, stream); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_plaquette(const Ens &e, hipStream_t stream)
 {
-    hipLaunchKernelGGL(plaquette_kernel, dim3(round8(nblk(2ull * e.max_vh, 256)), 1, e.nrep),
+    hipLaunchKernelGGL(plaquette_kernel, dim3(round8(nblk(e.max_vh, 256)), 1, e.nrep),
                        dim3(256), 0, stream, e.reps, 1);
     return hipGetLastError();
 }

@@ -293,6 +293,7 @@ public:
     uint64_t seed = 0;
     uint32_t sweep = 0;  // host mirror of the (common) sweep counter
     float orw = -1.0f;   // learned proposal: over-relaxation noise width (< 0: off)
+    int n_or = 1;        // SU2_KP_OR: over-relaxation sweeps after each heat-bath sweep
     bool f64 = false;    // FP64 links (single lattice): the su2_f64.hip kernels
     uint2 *amap = nullptr;  // XCD-affine pass map (device, owned), see Ens
     uint32_t amap_len = 0;
@@ -550,9 +551,12 @@ public:
     const float *mode_table(int mode, int *rc)
     {
         *rc = SU2_OK;
-        if (mode != SU2_KP && mode != SU2_LEARNED) *rc = fail(SU2_EINVAL, "unknown mode");
+        if (mode != SU2_KP && mode != SU2_LEARNED && mode != SU2_KP_OR)
+            *rc = fail(SU2_EINVAL, "unknown mode");
         else if (mode == SU2_LEARNED && f64)
             *rc = fail(SU2_ESTATE, "the learned proposal runs on FP32 links only");
+        else if (mode == SU2_KP_OR && f64)
+            *rc = fail(SU2_ESTATE, "over-relaxation runs on FP32 links only");
         else if (mode == SU2_LEARNED && !table)
             *rc = fail(SU2_ESTATE, "no learned proposal loaded (su2_set_proposal)");
         return mode == SU2_LEARNED ? table : nullptr;
@@ -568,9 +572,12 @@ public:
         const float *tab = mode_table(mode, &rc);
         if (rc) return rc;
         if (hist && reset_rows) HIP_TRY(launch_set_counter(ens(), 0, 0, 2, stream));
-        if (cfg.queue && !f64) return enqueue_queue(ns, tab, reunit_every, meas, hist);
+        // heat bath + over-relaxation: per-pass launches whatever the configuration
+        const int nor = mode == SU2_KP_OR ? n_or : 0;
+        if (cfg.queue && !f64 && mode != SU2_KP_OR)
+            return enqueue_queue(ns, tab, reunit_every, meas, hist);
         const int gflag = rows_graph ? 8 : 0;
-        if (small_path()) {
+        if (small_path() && mode != SU2_KP_OR) {
             const int flags = (hist && (meas & SU2_MEAS_PLAQ) ? 1 : 0) |
                               (hist && (meas & SU2_MEAS_POLY) ? 2 : 0) | (hist ? 4 | gflag : 0);
             HIP_TRY(launch_small_sweeps(ens(), ns, seed, reunit_every, flags, hist, tab, stream));
@@ -582,12 +589,19 @@ public:
             const bool reunit = reunit_every > 0 && ((j + 1u) % (uint32_t)reunit_every) == 0u;
             const bool want_p = hist && (meas & SU2_MEAS_PLAQ);
             const bool fused = want_p && !reunit;
+            // the plaquette is fused into the odd passes of mu >= 1 of the last stage
             for (int mu = 0; mu < 4; ++mu)
-                for (int par = 0; par < 2; ++par)
-                    HIP_TRY(f64 ? launch_pass64(ens(), mu, par, seed, fused && par == 1 && mu >= 1,
-                                                cfg, stream)
-                                : launch_pass(ens(), mu, par, seed, fused && par == 1 && mu >= 1,
-                                              tab, cfg, stream));
+                for (int par = 0; par < 2; ++par) {
+                    const bool m = fused && par == 1 && mu >= 1 && nor == 0;
+                    HIP_TRY(f64 ? launch_pass64(ens(), mu, par, seed, m, cfg, stream)
+                                : launch_pass(ens(), mu, par, seed, m, tab, cfg, stream));
+                }
+            for (int k = 0; k < nor; ++k)
+                for (int mu = 0; mu < 4; ++mu)
+                    for (int par = 0; par < 2; ++par)
+                        HIP_TRY(launch_or_pass(ens(), mu, par,
+                                               fused && par == 1 && mu >= 1 && k == nor - 1, cfg,
+                                               stream));
             if (reunit) HIP_TRY(reunitarize_launch());
             if (want_p && !fused) HIP_TRY(plaquette_launch());
             const bool want_l = hist && (meas & SU2_MEAS_POLY);
@@ -951,7 +965,7 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
         int block, flags, tz, tt, grid;
     };
     std::vector<Cand> cands;
-    const bool small_ok = !f64 && max_vh <= kSmallMaxVh;
+    const bool small_ok = !f64 && max_vh <= kSmallMaxVh && mode != SU2_KP_OR;
     if (small_ok) cands.push_back({256, 1, 8, 8, 0});
     const int no_small = small_ok ? 4 : 0;
     for (int b : {256, 128})
@@ -960,7 +974,7 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
                 for (int gc : {0, 2048, 4096}) cands.push_back({b, fl | no_small, t[0], t[1], gc});
     // the persistent work queue (one item per ticket is always slower: the
     // per-run synchronisation dominates)
-    if (!f64)
+    if (!f64 && mode != SU2_KP_OR)
         for (int b : {256, 128})
             for (int gr : {1, 2}) cands.push_back({b, 1 | 8 | (gr << 4), 8, 8, 0});
     // batches: every replica's pass workgroups on one XCD
@@ -1401,6 +1415,30 @@ int su2_batch_set_overrelax(su2_batch *b, double width)
     int rc = check_batch(b);
     if (rc) return rc;
     return set_overrelax(b->E, width);
+    SU2_API_END
+}
+
+int su2_set_hb_overrelax(su2_ctx *c, int32_t n_or)
+{
+    SU2_API_BEGIN
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (n_or < 0 || n_or > 16) return fail(SU2_EINVAL, "n_or must be in [0, 16]");
+    c->E.drop_graph();
+    c->E.n_or = n_or;
+    return SU2_OK;
+    SU2_API_END
+}
+
+int su2_batch_set_hb_overrelax(su2_batch *b, int32_t n_or)
+{
+    SU2_API_BEGIN
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (n_or < 0 || n_or > 16) return fail(SU2_EINVAL, "n_or must be in [0, 16]");
+    b->E.drop_graph();
+    b->E.n_or = n_or;
+    return SU2_OK;
     SU2_API_END
 }
 
@@ -1858,6 +1896,10 @@ int su2_test_pass(su2_ctx *c, int mu, int parity, int mode)
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1) return fail(SU2_EINVAL, "bad mu/parity");
     const float *tab = c->E.mode_table(mode, &rc);
     if (rc) return rc;
+    if (mode == SU2_KP_OR) {  // one over-relaxation pass
+        HIP_TRY(launch_or_pass(c->E.ens(), mu, parity, false, c->E.cfg, c->E.stream));
+        return SU2_OK;
+    }
     HIP_TRY(c->E.f64 ? launch_pass64(c->E.ens(), mu, parity, c->E.seed, false, c->E.cfg, c->E.stream)
                      : launch_pass(c->E.ens(), mu, parity, c->E.seed, false, tab, c->E.cfg,
                                    c->E.stream));

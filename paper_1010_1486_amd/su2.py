@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "su2.h")
 
 SU2_OK, SU2_EINVAL, SU2_EODD, SU2_ENOMEM, SU2_EHIP, SU2_ESTATE, SU2_ERANGE = 0, -1, -2, -3, -4, -5, -6
 SU2_COLD, SU2_HOT = 0, 1
-SU2_KP, SU2_LEARNED = 0, 1
+SU2_KP, SU2_LEARNED, SU2_KP_OR = 0, 1, 2
 SU2_MEAS_PLAQ, SU2_MEAS_POLY = 1, 2
 
 _ERR_NAMES = {SU2_EINVAL: "SU2_EINVAL", SU2_EODD: "SU2_EODD", SU2_ENOMEM: "SU2_ENOMEM",
@@ -61,6 +61,8 @@ _SIGS = {
     "su2_set_beta": (_int, [_vp, _d]),
     "su2_set_replica": (_int, [_vp, _u32]),
     "su2_links_device": (_int, [_vp, _vp, _vp]),
+    "su2_set_hb_overrelax": (_int, [_vp, _i32]),
+    "su2_batch_set_hb_overrelax": (_int, [_vp, _i32]),
     "su2_synchronize": (_int, [_vp]),
     "su2_set_launch": (_int, [_vp, _int, _int, _int, _int, _int]),
     "su2_autotune": (_int, [_vp, ctypes.c_char_p, _int, _vp]),
@@ -615,6 +617,10 @@ class Lattice:
         """width < 0: independence proposal; 0..1: over-relaxed learned proposal."""
         _check(lib().su2_set_overrelax(self.h, float(width)))
 
+    def set_hb_overrelax(self, n_or):
+        """Over-relaxation sweeps after each heat-bath sweep in SU2_KP_OR mode."""
+        _check(lib().su2_set_hb_overrelax(self.h, int(n_or)))
+
     def accept_stats(self, reset=False):
         return su2_get_accept_stats(self.h, reset)
 
@@ -756,6 +762,10 @@ class Batch:
     def set_overrelax(self, width):
         """width < 0: independence proposal; 0..1: over-relaxed learned proposal."""
         _check(lib().su2_batch_set_overrelax(self.h, float(width)))
+
+    def set_hb_overrelax(self, n_or):
+        """Over-relaxation sweeps after each heat-bath sweep in SU2_KP_OR mode."""
+        _check(lib().su2_batch_set_hb_overrelax(self.h, int(n_or)))
 
     def accept_stats(self, reset=False):
         p = np.zeros(self.n, dtype=np.uint64)

@@ -66,28 +66,36 @@ def assert_pulls(p, what):
     assert np.mean(p * p) <= 1.5, (what, p)
 
 
-def oracle_chain(orc, dims, beta, seed, start, therm, nmeas, every, reunit=10):
+def oracle_chain(orc, dims, beta, seed, start, therm, nmeas, every, reunit=10, n_or=0):
     """Independent oracle chain: `therm` sweeps, then `nmeas` measurements of
-    (P, signed L) taken every `every` sweeps."""
+    (P, signed L) taken every `every` sweeps.  n_or > 0: compound sweeps (heat
+    bath, then n_or over-relaxation sweeps)."""
     nt = orc.max_threads()
     U = orc.init(dims, start, seed)
-    orc.sweeps(dims, U, therm, 0, beta, seed, reunit_every=reunit, nthreads=nt)
+
+    def run(n, sw):
+        if n_or:
+            orc.sweeps_or(dims, U, n, n_or, sw, beta, seed, reunit_every=reunit, nthreads=nt)
+        else:
+            orc.sweeps(dims, U, n, sw, beta, seed, reunit_every=reunit, nthreads=nt)
+    run(therm, 0)
     sw = therm
     P, L = [], []
     for _ in range(nmeas):
-        orc.sweeps(dims, U, every, sw, beta, seed, reunit_every=reunit, nthreads=nt)
+        run(every, sw)
         sw += every
         P.append(orc.plaquette(dims, U))
         L.append(orc.polyakov(dims, U)[0])
     return np.array(P), np.array(L)
 
 
-def gpu_matched(su2, dims, beta, start, therm, nmeas, every, nrep, seed, reunit=10):
+def gpu_matched(su2, dims, beta, start, therm, nmeas, every, nrep, seed, reunit=10, n_or=0):
     """nrep independent GPU replicas of the oracle_chain protocol.  Returns the
     replicas' chain means of P and |L| as arrays of shape (nrep,)."""
     n = therm + nmeas * every
     with su2.Batch([dims] * nrep, beta, start, seed=seed) as b:
-        h = b.sweep_measure(n, reunit_every=reunit,
+        b.set_hb_overrelax(n_or)
+        h = b.sweep_measure(n, su2.SU2_KP_OR if n_or else su2.SU2_KP, reunit_every=reunit,
                             meas=su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY).cpu().numpy()
     rows = therm + every * np.arange(1, nmeas + 1) - 1  # after sweep therm + every (i + 1)
     return h[rows, :, 0].mean(axis=0), np.abs(h[rows, :, 1]).mean(axis=0)
@@ -99,30 +107,36 @@ def matched_pull(orc_mean, gpu_means):
 
 
 # (dims, beta, start, thermalisation sweeps, measurements, sweeps between them,
-#  with |L|): the couplings of each ensemble workload compared with the oracle
+#  with |L|, over-relaxation sweeps per heat-bath sweep): the couplings of each
+#  ensemble workload compared with the oracle, and the heat bath with
+#  over-relaxation (the baseline of the learned comparison)
 MATCHED = (
-    [([16, 16, 16, 16], b, st, 60, 60, 2, False)
+    [([16, 16, 16, 16], b, st, 60, 60, 2, False, 0)
      for b, st in ((1.5, 1), (1.7, 0), (1.9, 1), (2.1, 0), (2.3, 1), (2.5, 0), (2.7, 0),
                    (3.0, 0))]
-    + [([24, 24, 24, 24], b, st, 40, 40, 2, False) for b, st in ((1.8, 1), (2.4, 0), (3.0, 0))]
-    + [([32, 32, 32, nt], b, 0, 60, 40, 2, True)
-       for nt, bs in ((4, (2.0, 2.6)), (6, (2.2, 2.6)), (8, (2.3, 2.6))) for b in bs])
+    + [([24, 24, 24, 24], b, st, 40, 40, 2, False, 0) for b, st in ((1.8, 1), (2.4, 0), (3.0, 0))]
+    + [([32, 32, 32, nt], b, 0, 60, 40, 2, True, 0)
+       for nt, bs in ((4, (2.0, 2.6)), (6, (2.2, 2.6)), (8, (2.3, 2.6))) for b in bs]
+    + [([16, 16, 16, 16], 2.2, 1, 60, 60, 2, False, 1),
+       ([16, 16, 16, 16], 2.6, 0, 60, 60, 2, False, 2)])
 
 
 def test_ensembles_match_oracle_chains(su2, orc):
     """Every ensemble workload against independent oracle chains, matched
     protocol (64 GPU replicas per point), pulls of the mean plaquette and, at
-    finite temperature, of the mean |L|; then the learned updates (independence
-    and over-relaxed Metropolis, trained flow) against oracle heat-bath chains.
+    finite temperature, of the mean |L|; the heat bath with over-relaxation
+    against the oracle's; then the learned updates (independence and
+    over-relaxed Metropolis, trained flow) against oracle heat-bath chains.
     The rule is applied to all pulls together."""
     announce("ensemble: oracle chains vs GPU replicas, every ensemble workload")
     t0 = time.time()
     p, labels = [], []
-    for k, (dims, beta, start, therm, nmeas, every, with_l) in enumerate(MATCHED):
+    for k, (dims, beta, start, therm, nmeas, every, with_l, n_or) in enumerate(MATCHED):
         t1 = time.time()
-        ph, lh = oracle_chain(orc, dims, beta, 7000 + k, start, therm, nmeas, every)
-        gp, gl = gpu_matched(su2, dims, beta, start, therm, nmeas, every, 64, 1100 + k)
-        name = "x".join(map(str, dims)) + f" b{beta} {'hot' if start else 'cold'}"
+        ph, lh = oracle_chain(orc, dims, beta, 7000 + k, start, therm, nmeas, every, n_or=n_or)
+        gp, gl = gpu_matched(su2, dims, beta, start, therm, nmeas, every, 64, 1100 + k, n_or=n_or)
+        name = ("x".join(map(str, dims)) + f" b{beta} {'hot' if start else 'cold'}"
+                + (f" hb+{n_or}or" if n_or else ""))
         p.append(matched_pull(ph.mean(), gp))
         labels.append(name + " P")
         if with_l:

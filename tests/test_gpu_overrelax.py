@@ -1,0 +1,107 @@
+"""Heat bath with microcanonical over-relaxation (SU2_KP_OR) on the GPU
+against the FP64 oracle: every over-relaxation pass on seeded links (no
+randoms, no decisions: every link within 1e-5), the plaquette kept by a pass,
+and compound sweeps with measurements and reunitarisation, the heat-bath
+decisions' margins bounding the mismatched links."""
+import numpy as np
+import pytest
+
+from tests import inputs
+from tests.gpu_util import MARGIN_FLAG, announce, max_flags, parities
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dims", [[4, 4, 4, 4], [6, 4, 8, 2], [12, 10, 8, 6]],
+                         ids=lambda d: "x".join(map(str, d)))
+def test_every_overrelaxation_pass_matches_oracle(su2, orc, dims):
+    announce(f"over-relaxation passes dims={dims}")
+    links = inputs.random_links(dims, 70 + dims[0], spread=0.7)
+    U0 = links.astype(np.float64)
+    par_of = parities(orc, dims)
+    worst = 0.0
+    with su2.Lattice(dims, 2.3, 5) as lat:
+        for mu in range(4):
+            for p in range(2):
+                lat.set_links(links)
+                p0 = lat.plaquette()
+                lat.test_pass(mu, p, su2.SU2_KP_OR)
+                got = lat.get_links()
+                assert abs(lat.plaquette() - p0) < 2e-6  # the action is kept
+                U = U0.copy()
+                orc.or_pass(dims, U, mu, p)
+                err = np.abs(got - U).max()
+                worst = max(worst, err)
+                assert err < 1e-5, (mu, p, err)
+                # only the pass's links moved
+                moved = np.abs(got - links).max(axis=2) > 0
+                assert not moved[:, [m for m in range(4) if m != mu]].any()
+                assert moved[par_of == p, mu].mean() > 0.99
+    announce(f"  max |gpu - oracle| = {worst:.2e}")
+
+
+def oracle_compound(orc, dims, U, ns, n_or, sweep0, beta, seed, reunit):
+    """orc.sweeps_or step by step, keeping the heat-bath margins."""
+    nflag = 0
+    P = []
+    for j in range(sweep0, sweep0 + ns):
+        for mu in range(4):
+            for p in range(2):
+                m = orc.do_pass(dims, U, mu, p, j, beta, seed, want_margin=True)
+                nflag += int((m < MARGIN_FLAG).sum())
+        for _ in range(n_or):
+            for mu in range(4):
+                for p in range(2):
+                    orc.or_pass(dims, U, mu, p)
+        if reunit and (j + 1) % reunit == 0:
+            orc.reunitarize(dims, U)
+        P.append(orc.plaquette(dims, U))
+    return np.array(P), nflag
+
+
+@pytest.mark.parametrize("dims,n_or", [([4, 4, 4, 4], 1), ([6, 4, 8, 2], 2),
+                                       ([16, 16, 16, 16], 1)],
+                         ids=["4^4-or1", "6x4x8x2-or2", "16^4-or1"])
+def test_compound_sweeps_match_oracle(su2, orc, dims, n_or):
+    announce(f"heat bath + over-relaxation sweeps dims={dims} n_or={n_or}")
+    beta, seed, sweep0, ns, reunit = 2.4, 17, 4, 3, 2
+    links = inputs.random_links(dims, 90 + dims[2], spread=0.6)
+    with su2.Lattice(dims, beta, seed) as lat:
+        lat.set_links(links)
+        lat.set_sweep(sweep0)
+        lat.set_hb_overrelax(n_or)
+        h = lat.sweep_measure(ns, su2.SU2_KP_OR, reunit_every=reunit,
+                              meas=su2.SU2_MEAS_PLAQ).cpu().numpy()
+        got = lat.get_links()
+        assert lat.sweep == sweep0 + ns
+        assert abs(lat.plaquette() - h[-1, 0]) < 1e-6  # fused == standalone
+    U = links.astype(np.float64)
+    P, nflag = oracle_compound(orc, dims, U, ns, n_or, sweep0, beta, seed, reunit)
+    bad = int((np.abs(got - U).max(axis=2) > 1e-5).sum())
+    V = int(np.prod(dims))
+    announce(f"  links off by > 1e-5: {bad} of {4 * V}; flagged decisions {nflag}")
+    assert nflag <= max_flags(4 * V * ns)
+    assert bad <= 500 * nflag, (bad, nflag)
+    if bad == 0:
+        np.testing.assert_allclose(h[:, 0], P, atol=1e-6, rtol=0)
+
+
+def test_hb_overrelax_arguments(su2):
+    with su2.Lattice([4, 4, 4, 4], 2.0, 1) as lat:
+        for n in (-1, 17):
+            with pytest.raises(su2.SU2Error) as e:
+                lat.set_hb_overrelax(n)
+            assert e.value.code == su2.SU2_EINVAL
+        # n_or = 0: the plain heat bath, bit for bit
+        lat.set_hb_overrelax(0)
+        start = lat.get_links()
+        lat.heatbath_sweep(2, su2.SU2_KP_OR)
+        a = lat.get_links()
+        lat.set_links(start)
+        lat.set_sweep(0)
+        lat.heatbath_sweep(2, su2.SU2_KP)
+        np.testing.assert_array_equal(a, lat.get_links())
+    with su2.Lattice64([4, 4, 4, 4], 2.0, 1) as l64:
+        with pytest.raises(su2.SU2Error) as e:
+            l64.heatbath_sweep(1, su2.SU2_KP_OR)
+        assert e.value.code == su2.SU2_ESTATE
