@@ -7,6 +7,12 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+// Products and sums are fused into FMAs only within one source expression
+// (never across statements after inlining), so every kernel built on these
+// functions rounds the update identically whatever surrounds it: the plain and
+// the LDS-staged pass give bit-identical links.
+#pragma clang fp contract(on)
 #include <stdint.h>
 
 namespace su2dev {

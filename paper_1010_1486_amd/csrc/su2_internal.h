@@ -86,6 +86,8 @@ struct LaunchCfg {
     bool queue = false;       // whole sweeps in one persistent work-queue launch
     bool affine = false;      // batches: each replica's pass workgroups on one XCD
     int grain = 1;            // work-queue items per ticket
+    uint32_t march_R = 0;     // > 0: single lattices run the LDS-staged march pass
+    uint32_t march_T = 0;     //      (tiles of march_R rows, march_T planes per workgroup)
 };
 
 // ------------------------------------------------------------- work queue
@@ -204,6 +206,19 @@ hipError_t launch_init(const Ens &e, const int *starts_dev, uint64_t seed, hipSt
 // acc[ACC_PROPOSED] / acc[ACC_ACCEPTED]); else the exact heat bath.
 hipError_t launch_pass(const Ens &e, int mu, int par, uint64_t seed, bool measure,
                        const float *table, const LaunchCfg &cfg, hipStream_t stream);
+// The pass with LDS-staged neighbour planes (su2_march.hip), single lattice:
+// workgroups of `block` threads own R full x-rows of an (x, y) plane at one z
+// and walk T planes along t; nunits workgroups (ntile = Ny / R tiles per
+// plane), per = nunits / 8 when that divides (XCD-contiguous ranges, else 0);
+// an LDS slot holds (R + 2) Nx/2 links.  march_shape fills m and returns
+// false when the lattice does not fit (Ny % R, Nt % T, Nx/2 R > 256 or
+// < Nx, LDS over 64 KiB).
+struct MarchShape {
+    uint32_t R, T, block, ntile, nunits, per, slot_elems;
+};
+bool march_shape(const int32_t dims[4], uint32_t R, uint32_t T, MarchShape *m);
+hipError_t launch_pass_march(const Ens &e, int mu, int par, uint64_t seed, bool measure, bool orx,
+                             const MarchShape &m, int rev, hipStream_t stream);
 // One microcanonical over-relaxation pass (U' = U~^+ U^+ U~^+, no randoms),
 // in the workgroup layout of launch_pass; measure as launch_pass.
 hipError_t launch_or_pass(const Ens &e, int mu, int par, bool measure, const LaunchCfg &cfg,

@@ -306,6 +306,7 @@ public:
     int32_t g_nsweeps = 0;
     int32_t g_reunit = 0;  // reunitarisation period baked into the graph (0: none)
     bool rows_graph = false;  // enqueue() is being captured: rows on the graph's counter
+    MarchShape march{};       // the LDS-staged pass's layout (cfg.march_R > 0)
     int64_t g_rows_cap = 0;   // history rows the capture's buffer holds (0: no history)
     int64_t g_rows_next = 0;  // first row the next replay writes
     // work queue
@@ -562,6 +563,19 @@ public:
         return mode == SU2_LEARNED ? table : nullptr;
     }
 
+    // One (mu, parity) pass in the configured kernel: the LDS-staged march
+    // for single FP32 lattices when configured (heat bath and
+    // over-relaxation), else the plain pass kernels.
+    hipError_t pass_launch(int mu, int par, bool measure, const float *tab, bool orx)
+    {
+        if (f64) return launch_pass64(ens(), mu, par, seed, measure, cfg, stream);
+        if (cfg.march_R && !tab)
+            return launch_pass_march(ens(), mu, par, seed, measure, orx, march,
+                                     cfg.snake ? par : 0, stream);
+        return orx ? launch_or_pass(ens(), mu, par, measure, cfg, stream)
+                   : launch_pass(ens(), mu, par, seed, measure, tab, cfg, stream);
+    }
+
     // Enqueue n sweeps; the sweep index the device uses comes from the
     // device counters, and the host mirror decides the reunitarisation
     // schedule.  hist rows restart at 0 for this call.
@@ -591,17 +605,14 @@ public:
             const bool fused = want_p && !reunit;
             // the plaquette is fused into the odd passes of mu >= 1 of the last stage
             for (int mu = 0; mu < 4; ++mu)
-                for (int par = 0; par < 2; ++par) {
-                    const bool m = fused && par == 1 && mu >= 1 && nor == 0;
-                    HIP_TRY(f64 ? launch_pass64(ens(), mu, par, seed, m, cfg, stream)
-                                : launch_pass(ens(), mu, par, seed, m, tab, cfg, stream));
-                }
+                for (int par = 0; par < 2; ++par)
+                    HIP_TRY(pass_launch(mu, par, fused && par == 1 && mu >= 1 && nor == 0, tab,
+                                        false));
             for (int k = 0; k < nor; ++k)
                 for (int mu = 0; mu < 4; ++mu)
                     for (int par = 0; par < 2; ++par)
-                        HIP_TRY(launch_or_pass(ens(), mu, par,
-                                               fused && par == 1 && mu >= 1 && k == nor - 1, cfg,
-                                               stream));
+                        HIP_TRY(pass_launch(mu, par, fused && par == 1 && mu >= 1 && k == nor - 1,
+                                            nullptr, true));
             if (reunit) HIP_TRY(reunitarize_launch());
             if (want_p && !fused) HIP_TRY(plaquette_launch());
             const bool want_l = hist && (meas & SU2_MEAS_POLY);
@@ -819,12 +830,25 @@ public:
     {
         if (block < 64 || block > 256 || (block % 64) != 0)
             return fail(SU2_EINVAL, "block must be 64, 128, 192 or 256");
-        if (flags < 0 || flags > 127) return fail(SU2_EINVAL, "flags must be in [0, 127]");
+        if (flags < 0 || flags > 255) return fail(SU2_EINVAL, "flags must be in [0, 255]");
         if (grid_cap < 0) return fail(SU2_EINVAL, "grid_cap must be >= 0");
-        uint32_t lz, lt;
+        const bool march_on = (flags & 128) != 0;
+        MarchShape ms{};
+        if (march_on) {
+            if (n != 1 || f64 || (flags & 8))
+                return fail(SU2_EINVAL, "the LDS-staged pass (flag 128) runs single FP32 lattices "
+                                        "without the work queue");
+            if (tile_z <= 0 || tile_t <= 0 || !march_shape(dims[0].data(), (uint32_t)tile_z,
+                                                            (uint32_t)tile_t, &ms))
+                return fail(SU2_EINVAL, "the LDS-staged pass needs rows R = tile_z dividing Ny "
+                                        "and T = tile_t dividing Nt, with 2 <= R, R Nx/2 <= 256");
+        }
+        uint32_t lz = lg_tz, lt = lg_tt;
         int rc;
-        if ((rc = lg_of_tile(tile_z, lg_tz, &lz))) return rc;
-        if ((rc = lg_of_tile(tile_t, lg_tt, &lt))) return rc;
+        if (!march_on) {
+            if ((rc = lg_of_tile(tile_z, lg_tz, &lz))) return rc;
+            if ((rc = lg_of_tile(tile_t, lg_tt, &lt))) return rc;
+        }
         cfg.pass_block = block;
         cfg.xcd_remap = (flags & 1) != 0;
         cfg.snake = (flags & 2) == 0;
@@ -833,6 +857,10 @@ public:
         cfg.affine = (flags & 64) != 0;
         cfg.grain = 1 << ((flags >> 4) & 3);
         cfg.grid_cap = (uint32_t)grid_cap;
+        cfg.march_R = march_on ? (uint32_t)tile_z : 0u;
+        cfg.march_T = march_on ? (uint32_t)tile_t : 0u;
+        if (march_on) cfg.small = false;
+        march = ms;
         if (cfg.queue) {  // device queries stay out of any stream capture
             queue_grid_auto[0] = queue_resident_grid(block, false);
             queue_grid_auto[1] = queue_resident_grid(block, true);
@@ -977,6 +1005,14 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
     if (!f64 && mode != SU2_KP_OR)
         for (int b : {256, 128})
             for (int gr : {1, 2}) cands.push_back({b, 1 | 8 | (gr << 4), 8, 8, 0});
+    // single lattices: the LDS-staged march pass (heat bath and over-relaxation)
+    if (n == 1 && !f64 && mode != SU2_LEARNED)
+        for (int R : {4, 8, 16})
+            for (int T : {4, 8, 16}) {
+                MarchShape ms;
+                if (march_shape(dims[0].data(), (uint32_t)R, (uint32_t)T, &ms))
+                    cands.push_back({256, 1 | 4 | 128, R, T, 0});
+            }
     // batches: every replica's pass workgroups on one XCD
     if (n > 1 && !f64) {
         for (int b : {256, 128})
@@ -1502,10 +1538,11 @@ static void get_launch(const Ensemble &E, int *block, int *flags, int *tile_z, i
         int lg = 0;
         while ((1 << lg) < E.cfg.grain) ++lg;
         *flags = (E.cfg.xcd_remap ? 1 : 0) | (E.cfg.snake ? 0 : 2) | (E.cfg.small ? 0 : 4) |
-                 (E.cfg.queue ? 8 : 0) | (lg << 4) | (E.cfg.affine ? 64 : 0);
+                 (E.cfg.queue ? 8 : 0) | (lg << 4) | (E.cfg.affine ? 64 : 0) |
+                 (E.cfg.march_R ? 128 : 0);
     }
-    if (tile_z) *tile_z = 1 << E.geom[0].lg_tz;
-    if (tile_t) *tile_t = 1 << E.geom[0].lg_tt;
+    if (tile_z) *tile_z = E.cfg.march_R ? (int)E.cfg.march_R : 1 << E.geom[0].lg_tz;
+    if (tile_t) *tile_t = E.cfg.march_R ? (int)E.cfg.march_T : 1 << E.geom[0].lg_tt;
     if (grid_cap) *grid_cap = (int)E.cfg.grid_cap;
 }
 
@@ -1896,13 +1933,7 @@ int su2_test_pass(su2_ctx *c, int mu, int parity, int mode)
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1) return fail(SU2_EINVAL, "bad mu/parity");
     const float *tab = c->E.mode_table(mode, &rc);
     if (rc) return rc;
-    if (mode == SU2_KP_OR) {  // one over-relaxation pass
-        HIP_TRY(launch_or_pass(c->E.ens(), mu, parity, false, c->E.cfg, c->E.stream));
-        return SU2_OK;
-    }
-    HIP_TRY(c->E.f64 ? launch_pass64(c->E.ens(), mu, parity, c->E.seed, false, c->E.cfg, c->E.stream)
-                     : launch_pass(c->E.ens(), mu, parity, c->E.seed, false, tab, c->E.cfg,
-                                   c->E.stream));
+    HIP_TRY(c->E.pass_launch(mu, parity, false, tab, mode == SU2_KP_OR));
     return SU2_OK;
     SU2_API_END
 }
