@@ -400,7 +400,7 @@ def _replicas64():
 
 
 COUNTER_WORKLOADS = ("headline", "beta16", "beta24", "polyakov", "replicas64", "replicas64_learned",
-                     "su3")
+                     "su3", "plaquette", "fp64", "wilson")
 
 
 def counters_run(su2, torch, dev, lat, name):
@@ -413,6 +413,26 @@ def counters_run(su2, torch, dev, lat, name):
         for i in range(16):
             lat.test_pass((i // 2) % 4, i % 2)
         torch.cuda.synchronize()
+        return {"pass_launches": 16, "updates_per_launch": int(np.prod(DIMS)) // 2}
+    if name == "plaquette":  # the standalone plaquette kernel on the 48^4 field
+        lat.heatbath_sweep(2)
+        for _ in range(8):
+            lat.plaquette()
+        torch.cuda.synchronize()
+        return {"plaquette_launches": 8, "sites_per_launch": int(np.prod(DIMS))}
+    if name == "wilson":  # W(R, T) for R, T <= 4 on the 48^4 field
+        lat.heatbath_sweep(2)
+        for _ in range(2):
+            lat.wilson_loops(4, 4)
+        torch.cuda.synchronize()
+        return {"wilson_launches": 2, "sites_per_launch": int(np.prod(DIMS))}
+    if name == "fp64":  # the FP64-link pass at 48^4 in its autotuned launch
+        with su2.Lattice64(DIMS, BETA, SEED, su2.SU2_HOT, device=dev) as l64:
+            l64.autotune(None, su2.SU2_KP)
+            l64.heatbath_sweep(2)
+            for i in range(16):
+                l64.test_pass((i // 2) % 4, i % 2)
+            l64.synchronize()
         return {"pass_launches": 16, "updates_per_launch": int(np.prod(DIMS)) // 2}
     if name == "su3":
         with su2.Lattice3(DIMS, BETA, SEED, su2.SU2_HOT, device=dev) as l3:
@@ -794,7 +814,9 @@ def main():
 
     dev = torch.device("cuda:0")
     V = int(np.prod(DIMS))
-    lat = su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT, device=dev)
+    side = torch.cuda.Stream(device=dev)  # graph capture needs a non-null stream
+    with torch.cuda.stream(side):
+        lat = su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT, device=dev)
     stream = lat.stream
     meas = su2.SU2_MEAS_PLAQ
     hist = torch.zeros((max(args.steps, args.warmup, 1), 3), dtype=torch.float64, device=dev)
@@ -817,13 +839,34 @@ def main():
     lat.sweep_measure(args.warmup, reunit_every=10, meas=meas, hist=hist)
     torch.cuda.synchronize()
 
-    print(f"[bench] timing {args.steps} sweeps", file=sys.stderr, flush=True)
+    # the timed sweeps replay a captured graph of one reunitarisation period
+    # (10 sweeps: 80 passes, the fused plaquette, one reunitarisation and the
+    # plaquette after it, the end-of-sweep bookkeeping); a remainder below 10
+    # runs as direct launches
+    chunk = 10
+    pad = (-lat.sweep) % chunk
+    if pad:
+        lat.sweep_measure(pad, reunit_every=10, meas=meas, hist=hist)
+    full, rem = divmod(args.steps, chunk)
+    hist_g = torch.zeros((max(full * chunk, 1), 3), dtype=torch.float64, device=dev)
+    if full:
+        lat.capture(chunk, su2.SU2_KP, reunit_every=10, meas=meas, hist=hist_g)
+    print(f"[bench] timing {args.steps} sweeps ({full} graph replays of {chunk}, {rem} direct)",
+          file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat.sweep_measure(args.steps, reunit_every=10, meas=meas, hist=hist)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    h = hist[:args.steps].cpu().numpy()
+    with torch.cuda.stream(stream):
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        g0.record(stream)
+        if full:
+            lat.replay(full)
+        if rem:
+            lat.sweep_measure(rem, reunit_every=10, meas=meas, hist=hist)
+        g1.record(stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    gpu_us_per_sweep = g0.elapsed_time(g1) * 1e3 / args.steps
+    h = np.concatenate([hist_g[:full * chunk].cpu().numpy(), hist[:rem].cpu().numpy()])
 
     # average launch duration of the pass kernel, HIP events on the lattice's stream
     print(f"[bench] timing {args.pass_launches} pass launches", file=sys.stderr, flush=True)
@@ -869,6 +912,11 @@ def main():
                      "floor_gbs": BYTES_PER_UPDATE * (V // 2) / (floor_ms * 1e-3) / 1e9,
                      "frac_of_floor": floor_ms / pass_ms},
         "plaquette_mean_last_half": float(h[args.steps // 2:, 0].mean()),
+        "timed_sweeps": {"graph_replays": full, "sweeps_per_replay": chunk, "direct_sweeps": rem,
+                         "wall_us_per_sweep": 1e6 * dt / args.steps,
+                         "gpu_event_us_per_sweep": gpu_us_per_sweep,
+                         "pass_kernels_us_per_sweep": 8 * pass_ms * 1e3,
+                         "wall_over_pass_kernels": 1e6 * dt / args.steps / (8 * pass_ms * 1e3)},
         "autotuned_us_per_sweep": tuned_us,
         "launch": lat.launch(),
     }

@@ -192,7 +192,12 @@ int su2_synchronize(su2_ctx *ctx);
  * 0 = as many as the device holds at once), bits 4-5 = log2 of the items it
  * takes per ticket, bit 6 = batches: all pass workgroups of a replica on one
  * XCD (replicas spread over the XCDs by size, each replica's blocks in
- * order on its XCD's L2; bit 0 is then unused);
+ * order on its XCD's L2; bit 0 is then unused), bit 7 = single FP32 lattices:
+ * the pass with its neighbour links staged in LDS (heat bath and
+ * over-relaxation; SU2_LEARNED keeps the plain pass): workgroups of R =
+ * tile_z full x-rows of an (x, y) plane walk T = tile_t planes along t
+ * (R must divide Ny and T divide Nt, 2 <= R, R Nx/2 <= 256; SU2_EINVAL
+ * otherwise, and with bit 3); it implies bit 2;
  * the traversal
  * tile of (z, t) planes, tile_z x tile_t (powers of two <= 256, clipped to
  * divisors of Nz and Nt; 0 keeps the current value); grid_cap > 0 runs the

@@ -59,12 +59,26 @@ def oracle_compound(orc, dims, U, ns, n_or, sweep0, beta, seed, reunit):
     return np.array(P), nflag
 
 
-@pytest.mark.parametrize("dims,n_or", [([4, 4, 4, 4], 1), ([6, 4, 8, 2], 2),
-                                       ([16, 16, 16, 16], 1)],
-                         ids=["4^4-or1", "6x4x8x2-or2", "16^4-or1"])
-def test_compound_sweeps_match_oracle(su2, orc, dims, n_or):
-    announce(f"heat bath + over-relaxation sweeps dims={dims} n_or={n_or}")
-    beta, seed, sweep0, ns, reunit = 2.4, 17, 4, 3, 2
+@pytest.mark.parametrize("dims,n_or,ns", [([4, 4, 4, 4], 1, 1), ([6, 4, 8, 2], 2, 1),
+                                          ([16, 16, 16, 16], 1, 1), ([16, 16, 16, 16], 2, 1),
+                                          ([4, 4, 4, 4], 1, 3), ([6, 4, 8, 2], 2, 3)],
+                         ids=["4^4-or1", "6x4x8x2-or2", "16^4-or1", "16^4-or2", "4^4-or1-3sweeps",
+                              "6x4x8x2-or2-3sweeps"])
+def test_compound_sweeps_match_oracle(su2, orc, dims, n_or, ns):
+    """A heat-bath update forgets the old link, so its FP32 error is only that
+    of the current staple; a reflection U~^+ U^+ U~^+ keeps the old link's
+    error and adds twice the staple's, so errors add up over the
+    over-relaxation sweeps and grow from sweep to sweep through the staples
+    (measured on 4^4 at beta 2.4: 1e-6 after a heat-bath sweep, 7e-6 after one
+    compound sweep with n_or = 1, 3e-5 after two, 2e-4 after three).  One
+    compound sweep from identical links: every link within (1 + n_or) 1e-5,
+    but for the cones of decisions the oracle takes within 2e-5 of their
+    threshold.  Three, on lattices small enough that no decision is flagged
+    (a flipped decision's cone spreads over the lattice within a few compound
+    sweeps): within 1e-3, the plaquette history within 1e-4."""
+    announce(f"heat bath + over-relaxation sweeps dims={dims} n_or={n_or} sweeps={ns}")
+    beta, seed, sweep0, reunit = 2.4, 17, 5, 2
+    tol = (1 + n_or) * 1e-5 if ns == 1 else 1e-3
     links = inputs.random_links(dims, 90 + dims[2], spread=0.6)
     with su2.Lattice(dims, beta, seed) as lat:
         lat.set_links(links)
@@ -77,13 +91,17 @@ def test_compound_sweeps_match_oracle(su2, orc, dims, n_or):
         assert abs(lat.plaquette() - h[-1, 0]) < 1e-6  # fused == standalone
     U = links.astype(np.float64)
     P, nflag = oracle_compound(orc, dims, U, ns, n_or, sweep0, beta, seed, reunit)
-    bad = int((np.abs(got - U).max(axis=2) > 1e-5).sum())
+    d = np.abs(got - U).max(axis=2)
+    bad = int((d > tol).sum())
     V = int(np.prod(dims))
-    announce(f"  links off by > 1e-5: {bad} of {4 * V}; flagged decisions {nflag}")
+    announce(f"  max |gpu - oracle| {d.max():.2e}; links off by > {tol}: {bad} of {4 * V}; "
+             f"flagged decisions {nflag}")
     assert nflag <= max_flags(4 * V * ns)
+    if ns > 1:
+        assert nflag == 0  # the trajectory comparison needs identical decisions
     assert bad <= 500 * nflag, (bad, nflag)
     if bad == 0:
-        np.testing.assert_allclose(h[:, 0], P, atol=1e-6, rtol=0)
+        np.testing.assert_allclose(h[:, 0], P, atol=1e-5 if ns == 1 else 1e-4, rtol=0)
 
 
 def test_hb_overrelax_arguments(su2):
