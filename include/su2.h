@@ -149,6 +149,29 @@ int su2_heatbath_sweep(su2_ctx *ctx, int32_t nsweeps, int mode);
 int su2_sweep_measure(su2_ctx *ctx, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
                       double *dev_history);
 
+/* For callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): su2_sweep_measure
+ * (SU2_KP) without a context.  Enqueues on hip_stream (NULL: the null stream)
+ * nsweeps heat-bath sweeps of the lattice whose links the caller holds at
+ * links_dev, starting at sweep index sweep0, with reunit_every and meas as in
+ * su2_sweep_measure, and writes FP64[nsweeps][3] history rows to dev_history.
+ * links_dev: su2_links_bytes(dims) bytes in the device layout of su2.h (the
+ * buffer su2_init_ext takes; su2_links_device of a context of the same
+ * extents points at one); both buffers stay the caller's.  The links and
+ * history are bit for bit those of su2_sweep_measure on a context in its
+ * default launch configuration with the same links, beta, seed and sweep
+ * index.  The descriptor, counters and fixed-point accumulators live in a
+ * fixed 160 KiB device array each GPU holds until the process ends; nothing is
+ * allocated.  Every call on a GPU shares that array: calls that overlap on one
+ * GPU (other streams, other threads) race and give wrong results; each call
+ * clears what must start at zero.  Errors: SU2_EINVAL (NULL buffer, negative
+ * count, bad meas, beta not finite or < 0), SU2_EODD / SU2_ERANGE (extents as
+ * su2_init; SU2_ERANGE also if the array could not hold the lattice's scratch),
+ * SU2_EHIP (device lookup or launch failed).  Asynchronous. */
+int su2_sweep_measure_static(float *links_dev, const int32_t dims[4], double beta, uint64_t seed,
+                             uint32_t sweep0, int32_t nsweeps, int32_t reunit_every, int meas,
+                             double *dev_history, void *hip_stream);
+
 /* Enqueue U <- U/|U| for every link, |U|^2 in FP64. */
 int su2_reunitarize(su2_ctx *ctx);
 

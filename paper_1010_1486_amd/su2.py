@@ -63,6 +63,7 @@ _SIGS = {
     "su2_links_device": (_int, [_vp, _vp, _vp]),
     "su2_set_hb_overrelax": (_int, [_vp, _i32]),
     "su2_batch_set_hb_overrelax": (_int, [_vp, _i32]),
+    "su2_sweep_measure_static": (_int, [_vp, _vp, _d, _u64, _u32, _i32, _i32, _int, _vp, _vp]),
     "su2_synchronize": (_int, [_vp]),
     "su2_set_launch": (_int, [_vp, _int, _int, _int, _int, _int]),
     "su2_autotune": (_int, [_vp, ctypes.c_char_p, _int, _vp]),
@@ -278,6 +279,28 @@ def su2_capture_sweeps(h, nsweeps, mode=SU2_KP, reunit_every=0, meas=0, dev_hist
 
 def su2_replay_sweeps(h, count):
     _check(lib().su2_replay_sweeps(h, int(count)))
+
+
+def su2_sweep_measure_static(links, dims, beta, seed, sweep0, nsweeps, reunit_every=0,
+                             meas=SU2_MEAS_PLAQ, hist=None, stream=None):
+    """Allocation-free sweeps on caller-owned device links (torch uint8 or
+    float32 tensor of su2_links_bytes(dims) bytes in the library's device
+    layout): returns the FP64 (nsweeps, 3) history tensor.  hist, if given,
+    is used instead of a new tensor (nothing is then allocated)."""
+    import torch
+    d = np.ascontiguousarray(dims, np.int32)
+    assert links.is_cuda and links.numel() * links.element_size() >= su2_links_bytes(dims)
+    if hist is None:
+        hist = torch.zeros((max(int(nsweeps), 1), 3), dtype=torch.float64, device=links.device)
+    assert hist.dtype == torch.float64 and hist.is_contiguous() and hist.numel() >= 3 * nsweeps
+    if stream is None:
+        stream = torch.cuda.current_stream(links.device)
+    with torch.cuda.device(links.device):
+        _check(lib().su2_sweep_measure_static(_vp(links.data_ptr()), _p(d), float(beta),
+                                              int(seed), int(sweep0), int(nsweeps),
+                                              int(reunit_every), int(meas),
+                                              _vp(hist.data_ptr()), _vp(stream.cuda_stream)))
+    return hist
 
 
 def su2_links_device(h):

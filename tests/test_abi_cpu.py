@@ -180,7 +180,7 @@ def test_no_exception_leaves_the_c_abi():
     import re
     csrc = os.path.join(os.path.dirname(su2.__file__), "csrc")
     seen = 0
-    for f in ("su2_runtime.cpp", "su3_runtime.cpp"):
+    for f in ("su2_runtime.cpp", "su3_runtime.cpp", "su2_static.hip"):
         lines = open(os.path.join(csrc, f)).read().split("\n")
         for i, l in enumerate(lines):
             if re.match(r"^(int|size_t) (su2_|su3_)\w+\(", l):
@@ -191,3 +191,22 @@ def test_no_exception_leaves_the_c_abi():
                 seen += 1
     exported = set(su2.header_functions()) | set(su2.header_functions3())
     assert seen >= len(exported) - 1  # su2_last_error only reads a string
+
+
+def test_static_sweeps_reject_bad_arguments_before_device_work():
+    """su2_sweep_measure_static checks its arguments before it touches a
+    device (these calls need no GPU)."""
+    lib = su2.lib()
+    fake = ctypes.c_void_p(16)  # never dereferenced: the checks come first
+    good = np.array([4, 4, 4, 4], np.int32)
+    odd = np.array([4, 4, 4, 5], np.int32)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    f = lib.su2_sweep_measure_static
+    assert f(None, p(good), 2.0, 1, 0, 1, 0, 1, fake, None) == su2.SU2_EINVAL
+    assert f(fake, p(good), 2.0, 1, 0, 1, 0, 1, None, None) == su2.SU2_EINVAL
+    assert f(fake, p(odd), 2.0, 1, 0, 1, 0, 1, fake, None) == su2.SU2_EODD
+    assert f(fake, p(good), -1.0, 1, 0, 1, 0, 1, fake, None) == su2.SU2_EINVAL
+    assert f(fake, p(good), 2.0, 1, 0, -1, 0, 1, fake, None) == su2.SU2_EINVAL
+    assert f(fake, p(good), 2.0, 1, 0, 1, 0, 8, fake, None) == su2.SU2_EINVAL
+    big = np.array([512, 512, 512, 4], np.int32)  # V/2 = 2^28
+    assert f(fake, p(big), 2.0, 1, 0, 1, 0, 1, fake, None) == su2.SU2_ERANGE
