@@ -50,6 +50,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def f64_source_hash():
+    h = hashlib.sha256()
+    for f in ("su2_device.h", "su2_kcommon.h", "su2_internal.h", "su2_f64.hip"):
+        with open(os.path.join(ROOT, "paper_1010_1486_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+F64_PROFILE = os.path.join(ROOT, "profiles", "pass64_kernel_48x48x48x48_counters.md")
+
 SU3_BYTES_PER_UPDATE = 432  # 9 links of 48 B: 8 read (7 neighbours' classes + the link), 1 written
 SU3_PROFILE = os.path.join(ROOT, "profiles", "su3_pass_kernel_48x48x48x48.md")
 
@@ -63,13 +73,13 @@ def su3_source_hash():
     return h.hexdigest()[:16]
 
 
-def profile_value(path, key, source_hash):
+def profile_value(path, key, source_hash, key_name="kernel_source_hash"):
     """A figure from a committed rocprofv3 summary, if it was taken on the
     current kernel source (else None)."""
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    m = re.search(key_name + r":\s*([0-9a-f]+)", text)
     t = re.search(key + r":\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != source_hash:
         return None
@@ -127,8 +137,9 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu
     (seeded), hot start; the learned proposal is trained on the GPU on 1e7
     exact-sampler draws (alpha log-uniform in [0.5, 30]).  Each mode: autotuned
     launch, then graph-captured chunks of batched sweeps with the plaquette
-    measured every sweep.  Effective rate = sweeps/s / (2 tau_int(P)), averaged
-    over the replicas.  The untrained network (identity spline, i.e. a uniform
+    and the Polyakov loop measured every sweep.  Effective rate = sweeps/s /
+    (2 tau_int(P)), averaged over the replicas (and the same with tau_int of
+    the absolute Polyakov loop, the long-distance observable).  The untrained network (identity spline, i.e. a uniform
     proposal) runs the same protocol for comparison, and so does the trained
     flow used over-relaxed (proposal -g(x_old) + noise in the flow coordinate,
     noise half-width OR_WIDTH, and without noise), which anticorrelates
@@ -162,7 +173,7 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu
                            "nll_last_100": float(hist[-100:].mean())}
         untrained = su2.NN(seed=5)  # identity spline: the uniform proposal
         untrained.build_table()
-        eff_r = {}
+        eff_r, eff_l = {}, {}
         for name, mode, proposal, width, n_or in (
                 ("plain", su2.SU2_KP, net, -1.0, 0),
                 ("plain_overrelaxed", su2.SU2_KP_OR, net, -1.0, 1),
@@ -180,15 +191,17 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu
             b.sweep(therm, mode)
             b.accept_stats(reset=True)
             h = torch.zeros((sweeps, n, 3), dtype=torch.float64, device=dev)
-            b.capture(chunk, mode, meas=su2.SU2_MEAS_PLAQ, hist=h)
+            b.capture(chunk, mode, meas=su2.SU2_MEAS_PLAQ | su2.SU2_MEAS_POLY, hist=h)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             b.replay(sweeps // chunk)
             b.synchronize()
             dt = time.perf_counter() - t0
             prop, acc = b.accept_stats()
-            P = h.cpu().numpy()[:, :, 0]
+            hh = h.cpu().numpy()
+            P, AL = hh[:, :, 0], hh[:, :, 2]
             taus = np.array([tau_int(P[:, r]) for r in range(n)])
+            taus_l = np.array([tau_int(AL[:, r]) for r in range(n)])
             sps = sweeps / dt  # (compound) sweeps per second
             # bytes per update: the heat bath 128; the learned and over-relaxation
             # updates also read the old link (144)
@@ -197,8 +210,10 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu
             ups = links * (1 + n_or) * sps
             gbs = bpu * ups / 1e9
             eff_r[name] = sps / (2 * taus)
+            eff_l[name] = sps / (2 * taus_l)
             tau_m, tau_e = jackknife_mean(taus)
             eff_m, eff_e = jackknife_mean(eff_r[name])
+            taul_m, taul_e = jackknife_mean(taus_l)
             out[name] = {"link_updates_per_s": ups, "sweeps_per_s": sps,
                          "algorithmic_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                          "bytes_per_update": bpu,
@@ -209,12 +224,17 @@ def learned_vs_plain(su2, torch, dev, sweeps=2000, therm=300, chunk=50, with_cpu
                          "tau_int_madras_sokal_err_per_replica_mean":
                              float(np.mean(tau_int_err(taus, sweeps))),
                          "effective_sweeps_per_s": eff_m, "effective_sweeps_per_s_err": eff_e,
+                         "tau_int_abs_polyakov_mean": taul_m,
+                         "tau_int_abs_polyakov_err": taul_e,
                          "acceptance": (float(acc.sum() / prop.sum()) if prop.sum() else None),
                          "mean_plaquette": float(P.mean())}
             if name != "plain":
                 r_m, r_e = jackknife_mean(eff_r[name] / eff_r["plain"])
                 out[name]["effective_over_plain"] = r_m
                 out[name]["effective_over_plain_err"] = r_e
+                r_m, r_e = jackknife_mean(eff_l[name] / eff_l["plain"])
+                out[name]["effective_over_plain_abs_polyakov"] = r_m
+                out[name]["effective_over_plain_abs_polyakov_err"] = r_e
             b.close()
         net.close()
         untrained.close()
@@ -510,9 +530,14 @@ def fp64_run(su2, torch, dev, steps=100, launches=80):
         e1.synchronize()
         pass_ms = e0.elapsed_time(e1) / launches
     gbs = 256 * (V // 2) / (pass_ms * 1e-3) / 1e9
+    traffic = profile_value(F64_PROFILE, "hbm_bytes_per_launch", f64_source_hash(),
+                            key_name="f64_source_hash")
     out.update({"link_updates_per_s": 4 * V * steps / dt, "ms_per_sweep": 1e3 * dt / steps,
                 "pass_avg_launch_us": pass_ms * 1e3, "bytes_per_update": 256,
                 "pass_algorithmic_gbs": gbs, "pass_hbm_frac": gbs / HBM_PEAK_GBS,
+                "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                             "kernel": "pass64_kernel"},
                 "mean_plaquette": float(hist.cpu().numpy()[:, 0].mean())})
     return out
 

@@ -18,9 +18,9 @@
 namespace su2dev {
 
 // ------------------------------------------------------------------ layout
-// Links live in 32 planes of V/2 floats: plane (mu, parity, c) holds
-// component c of U_mu at every site of that parity, indexed by the half-site
-// h = s >> 1 of the canonical site s = x + Nx*(y + Ny*(z + Nz*t)).
+// Links live in 8 classes (mu, parity), each an array of V/2 quaternions
+// (float4, components a0..a3) indexed by the half-site h = s >> 1 of the
+// canonical site s = x + Nx*(y + Ny*(z + Nz*t)).
 struct Geom {
     int32_t nx, ny, nz, nt;
     uint32_t vh;  // V/2
@@ -90,16 +90,6 @@ __host__ __device__ __forceinline__ Deltas neighbour_deltas(const Geom &g, const
     d.p[3] = s.t == g.nt - 1 ? 0u - g.wt : g.PZ;
     d.m[3] = s.t == 0 ? g.wt : 0u - g.PZ;
     return d;
-}
-
-__device__ __forceinline__ const float *plane(const float *base, uint32_t vh, int mu, int par,
-                                              int c)
-{
-    return base + (size_t)(((mu * 2 + par) * 4 + c)) * vh;
-}
-__device__ __forceinline__ float *plane(float *base, uint32_t vh, int mu, int par, int c)
-{
-    return base + (size_t)(((mu * 2 + par) * 4 + c)) * vh;
 }
 
 // ------------------------------------------------------------- quaternions

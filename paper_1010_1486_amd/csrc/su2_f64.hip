@@ -8,8 +8,11 @@
 // (direction, parity), plaquette, Polyakov loop) and the reunitarisation.  The
 // Philox streams, the traversal of the lattice and the fixed-point global sums
 // are those of the FP32 path, so the two precisions differ at equal seeds only
-// by the FP32 rounding.  Layout: 8 arrays (mu * 2 + parity) of V/2 links, 32
-// bytes each (a0, a1, a2, a3 in FP64), indexed by the half-site h = s >> 1.
+// by the FP32 rounding.  Layout: 8 classes (mu * 2 + parity), each two arrays
+// of V/2 double pairs -- (a0, a1), then (a2, a3) -- indexed by the half-site
+// h = s >> 1, so that every wave-wide 16-byte load reads one contiguous
+// kilobyte (a 32-byte link per lane would spread each load over twice the
+// cache lines).
 #include "su2_internal.h"
 #include "su2_kcommon.h"
 
@@ -48,20 +51,30 @@ __device__ __forceinline__ double dretr(const QD &a, const QD &b)
     return a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z;
 }
 
+// Class (mu, par) starts at byte 32 vh (mu * 2 + par); its (a2, a3) half
+// 16 vh bytes further.  Uniform bases and one 32-bit offset h * 16 per link
+// (V/2 < 2^28).
+typedef __attribute__((address_space(1))) const char gcd;
+typedef __attribute__((address_space(1))) char gcd_w;
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const v2d gv2d;
+typedef __attribute__((address_space(1))) v2d gv2d_w;
+
 __device__ __forceinline__ QD ldd(const double *links, uint32_t vh, int mu, int par, uint32_t h)
 {
-    const double2 *p =
-        reinterpret_cast<const double2 *>(links) + 2 * ((size_t)(mu * 2 + par) * vh + h);
-    const double2 a = p[0], b = p[1];
+    gcd *lo = (gcd *)links + (size_t)(mu * 2 + par) * vh * 32u;
+    gcd *hi = lo + (size_t)vh * 16u;
+    const v2d a = *(gv2d *)(lo + h * 16u), b = *(gv2d *)(hi + h * 16u);
     return QD{a.x, a.y, b.x, b.y};
 }
 
 __device__ __forceinline__ void std4(double *links, uint32_t vh, int mu, int par, uint32_t h,
                                      const QD &q)
 {
-    double2 *p = reinterpret_cast<double2 *>(links) + 2 * ((size_t)(mu * 2 + par) * vh + h);
-    p[0] = make_double2(q.w, q.x);
-    p[1] = make_double2(q.y, q.z);
+    gcd_w *lo = (gcd_w *)links + (size_t)(mu * 2 + par) * vh * 32u;
+    gcd_w *hi = lo + (size_t)vh * 16u;
+    *(gv2d_w *)(lo + h * 16u) = v2d{q.w, q.x};
+    *(gv2d_w *)(hi + h * 16u) = v2d{q.y, q.z};
 }
 
 // Store with the nontemporal hint (the pass writes a class no other site of
@@ -69,11 +82,10 @@ __device__ __forceinline__ void std4(double *links, uint32_t vh, int mu, int par
 __device__ __forceinline__ void std4_nt(double *links, uint32_t vh, int mu, int par, uint32_t h,
                                         const QD &q)
 {
-    typedef double v2d __attribute__((ext_vector_type(2)));
-    v2d *p = reinterpret_cast<v2d *>(links) + 2 * ((size_t)(mu * 2 + par) * vh + h);
-    const v2d a = {q.w, q.x}, b = {q.y, q.z};
-    __builtin_nontemporal_store(a, p);
-    __builtin_nontemporal_store(b, p + 1);
+    v2d *lo = reinterpret_cast<v2d *>(links) + (size_t)(mu * 2 + par) * 2u * vh;
+    v2d *hi = lo + vh;
+    __builtin_nontemporal_store(v2d{q.w, q.x}, lo + h);
+    __builtin_nontemporal_store(v2d{q.y, q.z}, hi + h);
 }
 
 // The uniform of a Philox word, (2 (w >> 9) + 1) 2^-24 (exact in FP64).

@@ -197,6 +197,7 @@ struct Ens {
     uint32_t max_vh;          // largest V/2 over the replicas
     uint32_t max_ns3;         // largest spatial volume
     int poly_s;               // Polyakov segments (common divisor of every Nt)
+    uint32_t plane_hs = 0;    // half-sites per (x, y) plane if every replica has the same, else 0
 };
 
 // Kernel launchers (all asynchronous on `stream`; return hipError_t).

@@ -297,23 +297,94 @@ __device__ __forceinline__ float site_plaquettes(const Rep &R, uint32_t i)
     return sum;
 }
 
-// grid (blocks over V/2, 1, replica).  One thread per half-site in the pass
-// traversal order, taking the plaquettes rooted at both of its sites (the two
-// parities, x-neighbours of each other), so that one workgroup reads each
-// link class of its stretch once as the sites' own links and once as their
-// neighbours', close together in time:
-// (1/2)Tr U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+ = (1/2)Tr(P Q^+) with
-// P = U_mu(s) U_nu(s+mu), Q = U_nu(s) U_mu(s+nu).
-__global__ __launch_bounds__(256) void plaquette_kernel(const Rep *__restrict__ reps, int remap)
+// Sum of the six plaquettes rooted at a site with own links S and +a
+// neighbours F[a][b] = U_b(s + a) (F[a][a] unused), in the order of
+// site_plaquettes.
+__device__ __forceinline__ float plaquettes_from(const Q S[4], const Q F[4][4])
+{
+    float sum = 0.0f;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int nu = mu + 1; nu < 4; ++nu)
+            sum += retr_adj(qmul(S[mu], F[mu][nu]), qmul(S[nu], F[nu][mu]));
+    return sum;
+}
+
+// grid (multiple of 8 workgroups, 1, replica), blockDim.x threads; T divides
+// every replica's Nt.  A unit is a tile of blockDim.x consecutive half-sites
+// of an (x, y) plane at one z over T consecutive t; units are numbered z
+// fastest, then t-chunk, then tile (the +z unit is the next one and the +t
+// chunk nz units on), each XCD walks one contiguous stretch of them, and
+// workgroups loop while units remain.  A thread takes both sites of
+// its half-site (x even and x odd) on every plane of its chunk: the links of
+// plane t + 1, loaded once, serve as the +t neighbours at t and as the own
+// links at t + 1, the odd site is the even site's +x neighbour, and only the
+// odd site's +x and both sites' +y and +z neighbours are further loads (the
+// z + 1 unit is the next unit of the same XCD, so those come from its L2).
+// Per half-site and plane: 23 loads, plus the 8 own links of a chunk's first
+// plane (reading the 4 own and 12 neighbour links of both sites
+// independently takes 28, 6 of them from plane t + 1).
+__global__ __launch_bounds__(256) void plaquette_march_kernel(const Rep *__restrict__ reps,
+                                                              uint32_t T)
 {
     const Rep &R = reps[blockIdx.z];
     const Geom &g = R.g;
-    const uint32_t nb = (g.vh + blockDim.x - 1) / blockDim.x;
-    if (blockIdx.x >= nb) return;  // uniform: whole workgroup
-    const uint32_t blk = logical_block(blockIdx.x, nb, remap, 0);
-    const uint32_t i = blk * blockDim.x + threadIdx.x;
+    const float *links = R.links;
+    const uint32_t B = blockDim.x;
+    const uint32_t ntile = (g.P + B - 1u) / B;
+    const uint32_t nchunk = (uint32_t)g.nt / T;
+    const uint32_t nunits = ntile * (uint32_t)g.nz * nchunk;
     double acc = 0.0;
-    if (i < g.vh) acc = (double)site_plaquettes(R, i) + (double)site_plaquettes(R, i + g.vh);
+    for (uint32_t b = blockIdx.x; b < nunits; b += gridDim.x) {
+        const uint32_t u = logical_block(b, nunits, 1, 0);
+        const uint32_t z = u % (uint32_t)g.nz, rest = u / (uint32_t)g.nz;
+        const uint32_t tc = rest % nchunk, tile = rest / nchunk;
+        const uint32_t r = tile * B + threadIdx.x;
+        if (r >= g.P) continue;
+        const uint32_t y = fdiv(r, g.m_hx, g.s_hx), xh = r - y * g.hx;
+        const uint32_t dx = xh == g.hx - 1u ? 1u - g.hx : 1u;
+        const uint32_t dy = y == (uint32_t)g.ny - 1u ? 0u - g.wy : g.hx;
+        const uint32_t dz = z == (uint32_t)g.nz - 1u ? 0u - g.wz : g.P;
+        uint32_t t = tc * T;
+        uint32_t h = r + g.P * z + g.PZ * t;
+        int pe = (int)((y + z + t) & 1u);  // parity of the even-x site
+        Q S0[4], S1[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            S0[mu] = ld(arr(links, g.vh, mu, pe), h);
+            S1[mu] = ld(arr(links, g.vh, mu, pe ^ 1), h);
+        }
+        for (uint32_t j = 0; j < T; ++j, ++t) {
+            const uint32_t dt = t == (uint32_t)g.nt - 1u ? 0u - g.wt : g.PZ;
+            Q F0[4][4], F1[4][4];
+#pragma unroll
+            for (int nu = 0; nu < 4; ++nu) {
+                // +t: the sites of plane t + 1 (x even there has parity pe ^ 1)
+                F0[3][nu] = ld(arr(links, g.vh, nu, pe ^ 1), h + dt);
+                F1[3][nu] = ld(arr(links, g.vh, nu, pe), h + dt);
+                // +x: the odd site for the even one, the next half-site's even site
+                F0[0][nu] = S1[nu];
+                if (nu != 0) F1[0][nu] = ld(arr(links, g.vh, nu, pe), h + dx);
+                if (nu != 1) {
+                    F0[1][nu] = ld(arr(links, g.vh, nu, pe ^ 1), h + dy);
+                    F1[1][nu] = ld(arr(links, g.vh, nu, pe), h + dy);
+                }
+                if (nu != 2) {
+                    F0[2][nu] = ld(arr(links, g.vh, nu, pe ^ 1), h + dz);
+                    F1[2][nu] = ld(arr(links, g.vh, nu, pe), h + dz);
+                }
+            }
+            acc += (double)plaquettes_from(S0, F0) + (double)plaquettes_from(S1, F1);
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                S0[mu] = F0[3][mu];
+                S1[mu] = F1[3][mu];
+            }
+            h += dt;
+            pe ^= 1;
+        }
+    }
     block_accumulate(acc, R.acc, ACC_PLAQ, blockIdx.x);
 }
 
@@ -1090,10 +1161,19 @@ hipError_t launch_or_pass(const Ens &e, int mu, int par, bool measure, const Lau
     return hipGetLastError();
 }
 
+// Standalone plaquette launch: t-chunks of 2 planes; workgroups of
+// 256 threads, or of 192 or 128 where that size divides the (x, y) plane of
+// every replica and 256 does not (no idle lanes in the last tile).
 hipError_t launch_plaquette(const Ens &e, hipStream_t stream)
 {
-    hipLaunchKernelGGL(plaquette_kernel, dim3(round8(nblk(e.max_vh, 256)), 1, e.nrep),
-                       dim3(256), 0, stream, e.reps, 1);
+    const uint32_t T = (uint32_t)std::min(e.poly_s, 2);  // poly_s divides every Nt
+    uint32_t B = 256;
+    if (e.plane_hs && e.plane_hs % 256u) {
+        if (e.plane_hs % 192u == 0) B = 192;
+        else if (e.plane_hs % 128u == 0) B = 128;
+    }
+    hipLaunchKernelGGL(plaquette_march_kernel, dim3(round8(nblk(e.max_vh, B * T)), 1, e.nrep),
+                       dim3(B), 0, stream, e.reps, T);
     return hipGetLastError();
 }
 

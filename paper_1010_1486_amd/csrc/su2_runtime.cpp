@@ -75,9 +75,15 @@ using namespace su2rt;
 
 namespace {
 
-// Device position of component k of U_mu at half-site h of parity par.
+// Device position of component k of U_mu at half-site h of parity par: FP32
+// links are one array of V/2 float4 per class (mu * 2 + parity); FP64 links
+// two arrays of V/2 double pairs per class, (a0, a1) then (a2, a3).
+template <typename D>
 inline size_t dev_index(int mu, int par, int k, int64_t h, int64_t vh)
 {
+    if (sizeof(D) == sizeof(double))
+        return (((size_t)(mu * 2 + par) * 2u + (size_t)(k >> 1)) * (size_t)vh + (size_t)h) * 2u +
+               (size_t)(k & 1);
     return ((size_t)(mu * 2 + par) * (size_t)vh + (size_t)h) * 4u + (size_t)k;
 }
 
@@ -283,6 +289,7 @@ public:
     std::vector<uint32_t> first_block, nblocks;
     uint32_t total_blocks = 0, max_vh = 0, max_ns3 = 0;
     int poly_s = 1;
+    uint32_t plane_hs = 0;  // common (x, y)-plane half-sites, 0 if they differ
     float *pool = nullptr;
     bool own_pool = false;
     unsigned char *scratch = nullptr;
@@ -354,7 +361,8 @@ public:
 
     Ens ens() const
     {
-        return Ens{d_reps(), d_bmap(), amap, amap_len, n, total_blocks, max_vh, max_ns3, poly_s};
+        return Ens{d_reps(), d_bmap(), amap, amap_len, n,
+                   total_blocks, max_vh, max_ns3, poly_s, plane_hs};
     }
 
     void drop_graph()
@@ -383,6 +391,7 @@ public:
             max_vh = std::max(max_vh, geom[r].vh);
             max_ns3 = std::max(max_ns3, (uint32_t)(dims[r][0] * dims[r][1] * dims[r][2]));
             while (dims[r][3] % poly_s) poly_s /= 2;
+            plane_hs = (r == 0 || plane_hs == geom[r].P) ? geom[r].P : 0u;
         }
         std::vector<Rep> h(n);
         for (int r = 0; r < n; ++r) {
@@ -758,7 +767,7 @@ public:
             const int par = (x + y + z + t) & 1;
             for (int mu = 0; mu < 4; ++mu)
                 for (int k = 0; k < 4; ++k)
-                    host[(s * 4 + mu) * 4 + k] = (H)planes[dev_index(mu, par, k, s >> 1, vh)];
+                    host[(s * 4 + mu) * 4 + k] = (H)planes[dev_index<D>(mu, par, k, s >> 1, vh)];
         }
     }
 
@@ -778,7 +787,7 @@ public:
             const int par = (x + y + z + t) & 1;
             for (int mu = 0; mu < 4; ++mu)
                 for (int k = 0; k < 4; ++k)
-                    planes[dev_index(mu, par, k, s >> 1, vh)] = (D)host[(s * 4 + mu) * 4 + k];
+                    planes[dev_index<D>(mu, par, k, s >> 1, vh)] = (D)host[(s * 4 + mu) * 4 + k];
         }
     }
 

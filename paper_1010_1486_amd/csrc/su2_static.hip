@@ -106,7 +106,7 @@ int sweep_measure_static(float *links, const int32_t dims[4], double beta, uint6
     int poly_s = 8;
     while (dims[3] % poly_s) poly_s /= 2;
     const Ens e{reps, nullptr, nullptr, 0u, 1, r.nblocks, g.vh,
-                (uint32_t)(dims[0] * dims[1] * dims[2]), poly_s};
+                (uint32_t)(dims[0] * dims[1] * dims[2]), poly_s, g.P};
 
     hipLaunchKernelGGL(put_rep_kernel, dim3(1), dim3(1), 0, stream, r, reps);
     STATIC_TRY(hipGetLastError());

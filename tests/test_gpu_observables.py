@@ -8,7 +8,10 @@ from tests.gpu_util import announce, parities
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dims", [[2, 2, 2, 2], [4, 6, 2, 8], [8, 6, 8, 10], [16, 16, 16, 16]],
+# (x, y)-plane half-sites 2, 12, 24 and 128, then 192 (workgroups of 192), 170
+# (256 with a ragged last tile) and 512 (two full tiles of 256); Nt 2 to 10
+@pytest.mark.parametrize("dims", [[2, 2, 2, 2], [4, 6, 2, 8], [8, 6, 8, 10], [16, 16, 16, 16],
+                                  [24, 16, 4, 6], [34, 10, 6, 4], [32, 32, 4, 2]],
                          ids=lambda d: "x".join(map(str, d)))
 def test_plaquette_polyakov_on_identical_links(su2, orc, dims):
     announce(f"observables dims={dims}")
@@ -169,3 +172,19 @@ def test_zero_sweeps_and_errors(su2):
         with pytest.raises(su2.SU2Error) as e:
             lat.heatbath_sweep(1, su2.SU2_LEARNED)
         assert e.value.code == su2.SU2_ESTATE
+
+
+def test_batch_plaquettes_with_different_planes(su2, orc):
+    """The standalone plaquette of a batch whose replicas have different (x, y)
+    planes (one workgroup size for all, ragged tiles) and Nt (t-chunks of a
+    common divisor), against the oracle per replica."""
+    dims = [[6, 4, 8, 2], [10, 8, 6, 4], [32, 32, 4, 4], [2, 2, 2, 2], [24, 16, 2, 6]]
+    announce(f"batch plaquettes dims={dims}")
+    with su2.Batch(dims, [2.0] * len(dims), [0] * len(dims), 3) as b:
+        want = []
+        for r, d in enumerate(dims):
+            links = inputs.random_links(d, 10 + r, spread=0.5)
+            b.set_links(r, links)
+            want.append(orc.plaquette(d, links.astype(np.float64)))
+        p, _, _ = b.observables()
+        np.testing.assert_allclose(p, want, atol=1e-6, rtol=0)

@@ -44,3 +44,10 @@ def test_every_summary_states_its_commands():
         text = read(name)
         assert "rocprofv3" in text and "bench.py" in text, name
         assert len(text) < 16384, name  # summaries, not raw output
+
+
+def test_fp64_profile_matches_the_kernel_source():
+    v = bench.profile_value(bench.F64_PROFILE, "hbm_bytes_per_launch", bench.f64_source_hash(),
+                            key_name="f64_source_hash")
+    algorithmic = 256 * 48 ** 4 // 2
+    assert v is not None and algorithmic <= v < 2 * algorithmic
