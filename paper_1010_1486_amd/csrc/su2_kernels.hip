@@ -263,11 +263,12 @@ __global__ __launch_bounds__(256) void stream_kernel(const Rep *__restrict__ rep
         a = qadd(a, ld(arr(R.links, vh, nu, par), h));
         a = qadd(a, ld(arr(R.links, vh, nu, opp), h));
     }
-    gfloat_w *p = (gfloat_w *)out + h;
-    p[0] = a.w;
-    p[vh] = a.x;
-    p[2 * (size_t)vh] = a.y;
-    p[3 * (size_t)vh] = a.z;
+    // nontemporal, as the pass stores its updated class
+    float *p = out + h;
+    __builtin_nontemporal_store(a.w, p);
+    __builtin_nontemporal_store(a.x, p + vh);
+    __builtin_nontemporal_store(a.y, p + 2 * (size_t)vh);
+    __builtin_nontemporal_store(a.z, p + 3 * (size_t)vh);
 }
 
 // -------------------------------------------------------------- plaquette
