@@ -224,7 +224,9 @@ def test_training_gain_over_untrained_proposal(su2):
     uniform proposal) value ln 2, its Metropolis acceptance on a batch of
     thermalised lattices rises from ~0.15 to > 0.95, and the plaquette's
     integrated autocorrelation time drops by a large factor, so the trained
-    proposal delivers several times more independent samples per sweep."""
+    proposal delivers several times more independent samples per sweep.  The
+    untrained chains have tau_int of tens of sweeps, so they run 4000 sweeps:
+    a windowed estimate from a run only ~15 tau long comes out biased low."""
     announce("learned: training gain")
     n, dims, beta = 16, [8, 8, 8, 8], 2.3
     res = {}
@@ -240,7 +242,7 @@ def test_training_gain_over_untrained_proposal(su2):
                 b.set_proposal(net)
                 b.sweep(150)  # heat-bath thermalisation
                 b.accept_stats(reset=True)
-                h = b.sweep_measure(800, su2.SU2_LEARNED, meas=su2.SU2_MEAS_PLAQ).cpu().numpy()
+                h = b.sweep_measure(4000, su2.SU2_LEARNED, meas=su2.SU2_MEAS_PLAQ).cpu().numpy()
                 prop, acc = b.accept_stats()
             taus = [stats.tau_int(h[:, r, 0]) for r in range(n)]
             res[name] = (acc.sum() / prop.sum(), float(np.mean(taus)))
