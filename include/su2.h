@@ -160,9 +160,9 @@ int su2_sweep_measure(su2_ctx *ctx, int32_t nsweeps, int mode, int32_t reunit_ev
  * extents points at one); both buffers stay the caller's.  The links and
  * history are bit for bit those of su2_sweep_measure on a context in its
  * default launch configuration with the same links, beta, seed and sweep
- * index.  The descriptor, counters and fixed-point accumulators live in a
- * fixed 160 KiB device array each GPU holds until the process ends; nothing is
- * allocated.  Every call on a GPU shares that array: calls that overlap on one
+ * index.  The descriptor, counters and fixed-point accumulators (about
+ * 131 KiB, whatever the lattice's size) live in a fixed 160 KiB device array
+ * each GPU holds until the process ends; nothing is allocated.  Every call on a GPU shares that array: calls that overlap on one
  * GPU (other streams, other threads) race and give wrong results; each call
  * clears what must start at zero.  Errors: SU2_EINVAL (NULL buffer, negative
  * count, bad meas, beta not finite or < 0), SU2_EODD / SU2_ERANGE (extents as
