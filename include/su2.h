@@ -111,8 +111,8 @@ int su2_wilson_loops(su2_ctx *ctx, int rmax, int tmax, double *out);
  * (SU2_KP; SU2_LEARNED gives SU2_ESTATE), su2_sweep_measure, capture/replay,
  * su2_reunitarize, su2_plaquette, su2_polyakov, get/set links (float or
  * double host arrays), set_sweep/beta/replica, set_launch/autotune (block,
- * remap, pass order and tiles; the whole-sweep and work-queue launches are
- * FP32 only), su2_test_pass.  Device layout: 8 classes (mu * 2 + parity),
+ * remap, pass order and tiles; the whole-sweep, work-queue and persistent
+ * grid-cap launches are FP32 only, a grid cap is ignored), su2_test_pass.  Device layout: 8 classes (mu * 2 + parity),
  * each two arrays of V/2 double pairs, (a0, a1) then (a2, a3). */
 int su2_init_f64(su2_ctx **out, const int32_t dims[4], double beta, uint64_t seed, int start,
                  void *hip_stream);

@@ -1008,7 +1008,10 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
     for (int b : {256, 128})
         for (int fl : {1, 3})  // remap + alternating order, remap only
             for (auto t : {std::array<int, 2>{8, 8}, {4, 8}, {2, 16}, {1, 1}, {16, 16}})
-                for (int gc : {0, 2048, 4096}) cands.push_back({b, fl | no_small, t[0], t[1], gc});
+                for (int gc : {0, 2048, 4096}) {
+                    if (f64 && gc) continue;  // the FP64 pass always launches its full grid
+                    cands.push_back({b, fl | no_small, t[0], t[1], gc});
+                }
     // the persistent work queue (one item per ticket is always slower: the
     // per-run synchronisation dominates)
     if (!f64 && mode != SU2_KP_OR)
