@@ -977,7 +977,7 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
     void *rep_saved = nullptr;
     hipError_t e = hipMalloc(&rep_saved, (size_t)n * rb);
     for (int r = 0; r < n && e == hipSuccess; ++r) {
-        const size_t b = (size_t)volume_of(dims[r].data()) * 64;
+        const size_t b = (size_t)volume_of(dims[r].data()) * (f64 ? 128 : 64);  // 16 reals per site
         e = hipMalloc(&saved[r], b);
         if (e == hipSuccess)
             e = hipMemcpyAsync(saved[r], links[r], b, hipMemcpyDeviceToDevice, stream);
@@ -1060,7 +1060,7 @@ int Ensemble::autotune(const char *cache_path, int mode, double *best_us)
     // restore the state whatever happened
     hipError_t er = hipStreamSynchronize(stream);
     for (int r = 0; r < n; ++r) {
-        const size_t b = (size_t)volume_of(dims[r].data()) * 64;
+        const size_t b = (size_t)volume_of(dims[r].data()) * (f64 ? 128 : 64);
         if (er == hipSuccess)
             er = hipMemcpyAsync(links[r], saved[r], b, hipMemcpyDeviceToDevice, stream);
     }

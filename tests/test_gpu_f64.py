@@ -159,3 +159,26 @@ def test_f64_graph_replay_equals_direct_sweeps(su2):
             np.testing.assert_array_equal(hg.cpu().numpy(), ha)
             np.testing.assert_array_equal(g.get_links(), a.get_links())
     torch.cuda.synchronize()
+
+
+def test_f64_autotune_keeps_state_and_links(su2):
+    """The FP64 autotuner restores links, sweep index and measurements after its
+    trial sweeps, picks a launch the FP64 pass supports (no grid cap, no
+    whole-sweep or work-queue launch), and sweeps in that launch give the links
+    of the default launch bit for bit (every update depends only on its
+    neighbours and its Philox stream, not on the workgroup partition)."""
+    announce("fp64 autotune")
+    dims = [12, 8, 10, 6]
+    with su2.Lattice64(dims, 2.2, 61, su2.SU2_HOT) as t, \
+            su2.Lattice64(dims, 2.2, 61, su2.SU2_HOT) as d:
+        before = t.get_links()
+        us = t.autotune(None, su2.SU2_KP)
+        assert us > 0
+        np.testing.assert_array_equal(t.get_links(), before)
+        assert t.sweep == 0
+        cfg = t.launch()
+        assert cfg["grid_cap"] == 0 and not cfg["flags"] & (4 | 8 | 64 | 128), cfg
+        t.heatbath_sweep(3)
+        d.heatbath_sweep(3)
+        np.testing.assert_array_equal(t.get_links(), d.get_links())
+        assert abs(t.plaquette() - d.plaquette()) < 1e-12
