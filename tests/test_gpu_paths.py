@@ -1,0 +1,93 @@
+"""Combinations of entry points that the per-feature tests do not reach on
+their own: the float link exchange of an FP64 context, and the heat bath with
+over-relaxation (SU2_KP_OR) under graph capture, the autotuner and the
+batched launch shapes.  Each compares two routes that must agree bit for bit."""
+import numpy as np
+import pytest
+
+from tests import inputs
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+def test_f64_context_exchanges_float_links(su2):
+    """On an FP64 context, su2_get_links (float host array) returns the FP64
+    links rounded to FP32, and su2_set_links (float host array) stores them
+    widened exactly."""
+    announce("fp64 context, float link exchange")
+    dims = [6, 4, 8, 2]
+    V = int(np.prod(dims))
+    with su2.Lattice64(dims, 2.0, 17, su2.SU2_HOT) as lat:
+        d = lat.get_links()
+        f = su2.su2_get_links(lat.h, V)
+        np.testing.assert_array_equal(f, d.astype(np.float32))
+        g = inputs.random_links(dims, 18)
+        su2.su2_set_links(lat.h, g)
+        np.testing.assert_array_equal(lat.get_links(), g.astype(np.float64))
+
+
+def test_overrelaxed_sweeps_replayed_from_a_graph_equal_direct(su2):
+    """Heat bath plus two over-relaxation sweeps per sweep, reunitarised every
+    third sweep and measured every sweep: a captured graph of three sweeps
+    replayed twice (with eager work between the replays) gives the links and
+    history rows of six direct sweeps bit for bit."""
+    import torch
+    announce("KP_OR capture/replay == direct")
+    dims = [8, 6, 4, 8]
+    side = torch.cuda.Stream()  # capture needs a non-null stream
+    with torch.cuda.stream(side):
+        with su2.Lattice(dims, 2.3, 21, su2.SU2_HOT) as a, \
+                su2.Lattice(dims, 2.3, 21, su2.SU2_HOT) as g:
+            for lat in (a, g):
+                lat.set_hb_overrelax(2)
+            ha = a.sweep_measure(6, su2.SU2_KP_OR, reunit_every=3, meas=3).cpu().numpy()
+            hg = torch.zeros((6, 3), dtype=torch.float64, device="cuda")
+            g.capture(3, su2.SU2_KP_OR, reunit_every=3, meas=3, hist=hg)
+            for k in range(2):
+                g.replay(1)
+                g.synchronize()
+                assert g.sweep == 3 * (k + 1)
+                _ = g.plaquette()
+            np.testing.assert_array_equal(hg.cpu().numpy(), ha)
+            np.testing.assert_array_equal(g.get_links(), a.get_links())
+    torch.cuda.synchronize()
+
+
+def test_overrelaxed_autotune_keeps_state_and_links(su2):
+    """Autotuning for SU2_KP_OR restores the links and the sweep index, and the
+    launch it picks sweeps the links of the default launch bit for bit."""
+    announce("KP_OR autotune")
+    dims = [16, 16, 16, 16]
+    with su2.Lattice(dims, 2.4, 23, su2.SU2_HOT) as t, \
+            su2.Lattice(dims, 2.4, 23, su2.SU2_HOT) as d:
+        for lat in (t, d):
+            lat.set_hb_overrelax(1)
+        before = t.get_links()
+        assert t.autotune(None, su2.SU2_KP_OR) > 0
+        np.testing.assert_array_equal(t.get_links(), before)
+        assert t.sweep == 0
+        t.heatbath_sweep(2, su2.SU2_KP_OR)
+        d.heatbath_sweep(2, su2.SU2_KP_OR)
+        np.testing.assert_array_equal(t.get_links(), d.get_links())
+
+
+@pytest.mark.parametrize("flags", [1 | 4, 64 | 1, 64 | 2, 3 | 4], ids=["per-pass", "xcd-affine",
+                                                                       "xcd-affine-no-snake",
+                                                                       "remap-no-snake"])
+def test_overrelaxed_batch_launch_shapes_are_bitwise_neutral(su2, flags):
+    """A batch of unequal replicas swept in SU2_KP_OR mode gives the same links
+    bit for bit in every launch shape (per-pass, XCD-affine, pass order)."""
+    announce(f"KP_OR batch launch flags={flags}")
+    dims = [[8, 8, 8, 8], [6, 4, 8, 2], [10, 8, 6, 4]]
+    betas, starts = [2.2, 1.9, 2.6], [1, 0, 1]
+    out = []
+    for fl in (None, flags):
+        with su2.Batch(dims, betas, starts, 29) as b:
+            b.set_hb_overrelax(1)
+            if fl is not None:
+                b.set_launch(256, fl, 4, 4, 0)
+            b.sweep(3, su2.SU2_KP_OR)
+            out.append([b.get_links(r) for r in range(len(dims))])
+    for r in range(len(dims)):
+        np.testing.assert_array_equal(out[0][r], out[1][r])
