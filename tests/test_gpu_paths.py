@@ -1,7 +1,8 @@
 """Combinations of entry points that the per-feature tests do not reach on
-their own: the float link exchange of an FP64 context, and the heat bath with
+their own: the float link exchange of an FP64 context, the heat bath with
 over-relaxation (SU2_KP_OR) under graph capture, the autotuner and the
-batched launch shapes.  Each compares two routes that must agree bit for bit."""
+batched launch shapes, and learned batches under graph capture.  Each compares
+two routes that must agree bit for bit."""
 import numpy as np
 import pytest
 
@@ -91,3 +92,44 @@ def test_overrelaxed_batch_launch_shapes_are_bitwise_neutral(su2, flags):
             out.append([b.get_links(r) for r in range(len(dims))])
     for r in range(len(dims)):
         np.testing.assert_array_equal(out[0][r], out[1][r])
+
+
+@pytest.mark.parametrize("width", [-1.0, 0.02], ids=["independence", "overrelaxed"])
+def test_learned_sweeps_replayed_from_a_graph_equal_direct(su2, width):
+    """Learned Metropolis sweeps of a batch (independence or over-relaxed
+    proposal) captured once and replayed twice give the links, history rows and
+    accept counts of the same sweeps run directly, bit for bit."""
+    import torch
+    announce(f"learned capture/replay == direct width={width}")
+    p = (np.random.default_rng(31).standard_normal(2671) * 0.2).astype(np.float32)
+    dims = [[8, 8, 8, 8], [6, 4, 8, 2], [12, 10, 8, 6]]
+    betas, starts = [2.2, 1.9, 2.6], [1, 0, 1]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side), su2.NN(params=p) as net:
+        net.build_table()
+        res = []
+        for graph in (False, True):
+            with su2.Batch(dims, betas, starts, 33) as b:
+                b.set_proposal(net)
+                b.set_overrelax(width)
+                b.sweep(3)  # heat-bath start (the capture starts at a reunitarisation boundary)
+                b.accept_stats(reset=True)
+                if graph:
+                    h = torch.zeros((6, len(dims), 3), dtype=torch.float64, device="cuda")
+                    b.capture(3, su2.SU2_LEARNED, reunit_every=3, meas=3, hist=h)
+                    for _ in range(2):
+                        b.replay(1)
+                        b.synchronize()
+                        _ = b.observables()  # eager work between the replays
+                else:
+                    h = b.sweep_measure(6, su2.SU2_LEARNED, reunit_every=3, meas=3)
+                b.synchronize()
+                res.append((h.cpu().numpy(), [b.get_links(r) for r in range(len(dims))],
+                            b.accept_stats()))
+    (ha, la, aa), (hg, lg, ag) = res
+    np.testing.assert_array_equal(hg, ha)
+    for r in range(len(dims)):
+        np.testing.assert_array_equal(lg[r], la[r])
+    np.testing.assert_array_equal(ag[0], aa[0])
+    np.testing.assert_array_equal(ag[1], aa[1])
+    assert aa[1].sum() > 0
