@@ -253,7 +253,10 @@ int su2_autotune(su2_ctx *ctx, const char *cache_path, int mode, double *best_us
  * nothing.  With reunit_every > 0, nsweeps must be a multiple of it and the
  * current sweep index a multiple of it, and a replay is refused (SU2_ESTATE)
  * unless the sweep index is again a multiple of it.  Needs a non-null
- * stream; later launch or proposal changes drop the recording. */
+ * stream.  Later changes of the launch configuration, the proposal, either
+ * over-relaxation setting, beta or the replica id drop the recording
+ * (su2_replay_sweeps then returns SU2_ESTATE); su2_set_sweep does not (the
+ * replays read the sweep index on the device and continue from it). */
 int su2_capture_sweeps(su2_ctx *ctx, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
                        double *dev_history, int64_t history_rows);
 int su2_replay_sweeps(su2_ctx *ctx, int32_t count);

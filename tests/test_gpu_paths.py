@@ -133,3 +133,50 @@ def test_learned_sweeps_replayed_from_a_graph_equal_direct(su2, width):
     np.testing.assert_array_equal(ag[0], aa[0])
     np.testing.assert_array_equal(ag[1], aa[1])
     assert aa[1].sum() > 0
+
+
+@pytest.mark.parametrize("change", ["beta", "replica", "overrelax", "launch"])
+def test_settings_changed_after_capture_drop_the_recording(su2, change):
+    """A captured graph holds the settings of its capture: changing beta, the
+    replica id, an over-relaxation setting or the launch drops it, and a
+    replay is refused (SU2_ESTATE) with nothing enqueued."""
+    import torch
+    announce(f"capture dropped by a {change} change")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side), su2.Lattice([8, 8, 8, 8], 2.3, 41, su2.SU2_HOT) as g:
+        g.capture(2)
+        g.replay(1)
+        g.synchronize()
+        {"beta": lambda: g.set_beta(2.5), "replica": lambda: g.set_replica(3), "overrelax": lambda: g.set_hb_overrelax(1),
+         "launch": lambda: g.set_launch(128, 1 | 4, 4, 4)}[change]()
+        before = g.get_links()
+        s0 = g.sweep
+        with pytest.raises(su2.SU2Error) as ei:
+            g.replay(1)
+        assert ei.value.code == su2.SU2_ESTATE
+        g.synchronize()
+        np.testing.assert_array_equal(g.get_links(), before)
+        assert g.sweep == s0
+    torch.cuda.synchronize()
+
+
+def test_replays_continue_from_a_set_sweep_index(su2):
+    """su2_set_sweep keeps the recording: replays read the sweep index on the
+    device, so after set_sweep(10) the next replay runs sweeps 10 and 11, as a
+    context that runs them directly."""
+    import torch
+    announce("replay after set_sweep")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side), su2.Lattice([8, 8, 8, 8], 2.3, 43, su2.SU2_HOT) as g, \
+            su2.Lattice([8, 8, 8, 8], 2.3, 43, su2.SU2_HOT) as d:
+        g.capture(2)
+        g.replay(1)
+        g.set_sweep(10)
+        g.replay(1)
+        g.synchronize()
+        d.heatbath_sweep(2)
+        d.set_sweep(10)
+        d.heatbath_sweep(2)
+        assert g.sweep == d.sweep == 12
+        np.testing.assert_array_equal(g.get_links(), d.get_links())
+    torch.cuda.synchronize()
