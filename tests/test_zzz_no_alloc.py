@@ -2,7 +2,8 @@
 su2_sweep_measure on a context (su2_init_ext, default launch): the same links,
 beta, seed and sweep index give bit-identical links and history, for two calls
 in a row on one GPU, the second on a smaller lattice (the static scratch keeps
-the first call's counters and sums, which the second must clear)."""
+the first call's counters and sums, which the second must clear); and the
+entry point recorded into a graph and replayed equals direct calls."""
 import numpy as np
 import pytest
 
@@ -42,3 +43,35 @@ def test_static_sweeps_equal_context_sweeps(su2):
     with pytest.raises(su2.SU2Error) as e:
         su2.su2_sweep_measure_static(links, [4, 4, 4, 4], -1.0, 1, 0, 1)
     assert e.value.code == su2.SU2_EINVAL
+
+
+def test_static_sweeps_under_graph_capture(su2):
+    """The use the entry point is for: recorded into a graph (torch.cuda.graph;
+    nothing is allocated inside the capture) and replayed three times with eager
+    work in between, it gives the links and history of three direct calls with
+    the same arguments, bit for bit."""
+    import torch
+    announce("allocation-free sweeps under graph capture")
+    dims, beta, seed = [8, 8, 8, 8], 2.3, 24
+    with su2.Lattice(dims, beta, seed, su2.SU2_HOT) as ref:
+        a = ref.links_t.clone()
+        b = ref.links_t.clone()
+    ha = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    hb = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    # a first call outside the capture looks up the device array's address
+    warm = a.clone()
+    su2.su2_sweep_measure_static(warm, dims, beta, seed, 0, 1, 0, 1,
+                                 torch.zeros((1, 3), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        su2.su2_sweep_measure_static(b, dims, beta, seed, 5, 4, 2, 3, hb)
+    for _ in range(3):
+        su2.su2_sweep_measure_static(a, dims, beta, seed, 5, 4, 2, 3, ha)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(hb.cpu().numpy(), ha.cpu().numpy())
+        np.testing.assert_array_equal(b.cpu().numpy(), a.cpu().numpy())
+    assert np.all(ha.cpu().numpy()[:, 0] > 0)
