@@ -180,3 +180,30 @@ def test_replays_continue_from_a_set_sweep_index(su2):
         assert g.sweep == d.sweep == 12
         np.testing.assert_array_equal(g.get_links(), d.get_links())
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("flags", [64 | 1, 1 | 4], ids=["xcd-affine", "per-pass"])
+def test_batch_graph_in_each_launch_shape_equals_direct(su2, flags):
+    """Batched heat-bath sweeps captured in the XCD-affine or the per-pass launch
+    and replayed twice give the links of direct sweeps in the default launch bit
+    for bit, and their history within the rounding of the FP64 partial sums."""
+    import torch
+    announce(f"batch graph in launch flags={flags}")
+    dims = [[16, 16, 16, 16], [12, 12, 12, 12], [8, 8, 8, 8]]
+    betas, starts = [2.4, 2.1, 2.7], [1, 1, 0]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with su2.Batch(dims, betas, starts, 37) as a, su2.Batch(dims, betas, starts, 37) as g:
+            ha = a.sweep_measure(8, reunit_every=4, meas=3).cpu().numpy()
+            g.set_launch(256, flags, 8, 8, 0)
+            hg = torch.zeros((8, len(dims), 3), dtype=torch.float64, device="cuda")
+            g.capture(4, reunit_every=4, meas=3, hist=hg)
+            for _ in range(2):
+                g.replay(1)
+                g.synchronize()
+            for r in range(len(dims)):
+                np.testing.assert_array_equal(g.get_links(r), a.get_links(r))
+            hg = hg.cpu().numpy()
+            np.testing.assert_allclose(hg[..., 0], ha[..., 0], atol=1e-9, rtol=0)
+            np.testing.assert_allclose(hg[..., 1:], ha[..., 1:], atol=1e-6, rtol=0)
+    torch.cuda.synchronize()
