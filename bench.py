@@ -556,13 +556,26 @@ def su3_run(su2, torch, dev, steps=100, launches=80, with_cpu=True):
     out = {"workload": "SU(3) 48^4, beta=6.0, hot start (Philox seed 3); step = 1 sweep "
                        "(8 passes, 3 SU(2) subgroup heat-bath draws per link) + fused "
                        "plaquette, reunitarise every 10"}
-    with su2.Lattice3(DIMS, BETA, SEED, su2.SU2_HOT, device=dev) as lat:
+    side = torch.cuda.Stream(device=dev)  # graph capture needs a non-null stream
+    with torch.cuda.stream(side), su2.Lattice3(DIMS, BETA, SEED, su2.SU2_HOT, device=dev) as lat:
         lat.heatbath_sweep(10, reunit_every=10, history=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = lat.heatbath_sweep(steps, reunit_every=10, history=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        # the same sweeps as graph replays of one reunitarisation period
+        graph_ms = None
+        if lat.sweep % 10 == 0:
+            reps = max(1, steps // 10)
+            hg = torch.zeros(10 * (reps + 1), dtype=torch.float64, device=dev)
+            lat.capture(10, reunit_every=10, hist=hg)
+            lat.replay(1)
+            lat.synchronize()
+            t0 = time.perf_counter()
+            lat.replay(reps)
+            lat.synchronize()
+            graph_ms = 1e3 * (time.perf_counter() - t0) / (10 * reps)
         stream = lat.stream
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -586,6 +599,8 @@ def su3_run(su2, torch, dev, steps=100, launches=80, with_cpu=True):
     valu_peak = 256 * 4 * 2.4e9 / 4 * 64  # lane-instructions per second
     out.update({
         "link_updates_per_s": 4 * V * steps / dt, "ms_per_sweep": 1e3 * dt / steps,
+        "graph_ms_per_sweep": graph_ms,
+        "graph_link_updates_per_s": None if graph_ms is None else 4 * V / (graph_ms * 1e-3),
         "pass_avg_launch_us": pass_ms * 1e3, "updates_per_launch": V // 2,
         "overrelaxation_pass_avg_launch_us": or_ms * 1e3,
         "mean_plaquette": float(np.mean(h)), "polyakov": poly,
@@ -599,7 +614,35 @@ def su3_run(su2, torch, dev, steps=100, launches=80, with_cpu=True):
             "frac": valu * (V // 2) / (pass_ms * 1e-3) / valu_peak}})
     if with_cpu:
         out["cpu_baseline"] = su3_oracle_rate()
+    out["small_lattice_graph"] = su3_small_graph(su2, torch, dev)
     return out
+
+
+def su3_small_graph(su2, torch, dev, dims=(16, 16, 16, 4), sweeps=200):
+    """A launch-bound SU(3) lattice (16^3 x 4, beta 5.7, hot start, reunitarise
+    every 10): sweeps enqueued directly against the same sweeps replayed from a
+    graph of one reunitarisation period (su3_capture_sweeps)."""
+    V = int(np.prod(dims))
+    side = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(side), su2.Lattice3(list(dims), 5.7, 9, su2.SU2_HOT, device=dev) as lat:
+        lat.heatbath_sweep(10, reunit_every=10)
+        lat.synchronize()
+        t0 = time.perf_counter()
+        lat.heatbath_sweep(sweeps, reunit_every=10)
+        lat.synchronize()
+        direct = (time.perf_counter() - t0) / sweeps
+        lat.capture(10, reunit_every=10)
+        lat.replay(1)
+        lat.synchronize()
+        t0 = time.perf_counter()
+        lat.replay(sweeps // 10)
+        lat.synchronize()
+        graph = (time.perf_counter() - t0) / (10 * (sweeps // 10))
+    return {"workload": f"SU(3) {dims[0]}^3 x {dims[3]}, beta 5.7, hot start, {sweeps} sweeps, "
+                        "reunitarise every 10",
+            "us_per_sweep_direct": 1e6 * direct, "us_per_sweep_graph": 1e6 * graph,
+            "link_updates_per_s_direct": 4 * V / direct,
+            "link_updates_per_s_graph": 4 * V / graph}
 
 
 SU3_SCAN_BETAS = [round(5.40 + 0.05 * i, 2) for i in range(13)]

@@ -118,6 +118,26 @@ int su3_get_sweep(su3_ctx *ctx, uint32_t *out);
 int su3_set_sweep(su3_ctx *ctx, uint32_t sweep);
 int su3_set_beta(su3_ctx *ctx, double beta);
 
+/* hipGraph capture of heat-bath sweeps, for loops over many short calls
+ * (small lattices are bound by launch overhead): record nsweeps sweeps exactly
+ * as su3_heatbath_sweep enqueues them (meas 1: with the fused plaquette, into
+ * the caller's device buffer dev_history of history_rows doubles; meas 0:
+ * none), then replay the recording `count` times with su3_replay_sweeps, one
+ * graph launch each.  The sweep index lives on the device, so every replay
+ * continues the chain: links and plaquettes are bit for bit those of the same
+ * sweeps run by su3_heatbath_sweep, and the k-th replay since the capture
+ * writes history rows k*nsweeps..(k+1)*nsweeps-1.  With reunit_every > 0,
+ * nsweeps must be a multiple of it and the sweep index at capture a multiple
+ * of it (else SU2_EINVAL), and a replay is refused (SU2_ESTATE) unless the
+ * sweep index is again a multiple of it; a replay that would write past
+ * history_rows is refused (SU2_EINVAL); nothing is enqueued then.  Needs a
+ * non-null stream (SU2_ESTATE).  su3_set_beta and su3_set_launch drop the
+ * recording (replay: SU2_ESTATE); su3_set_sweep does not (replays continue
+ * from the new index). */
+int su3_capture_sweeps(su3_ctx *ctx, int32_t nsweeps, int32_t reunit_every, int meas,
+                       double *dev_history, int64_t history_rows);
+int su3_replay_sweeps(su3_ctx *ctx, int32_t count);
+
 /* Pass-kernel launch: block 64, 128, 192 or 256 threads; remap 1 maps
  * workgroups to contiguous lattice stretches per XCD; snake 1 runs odd-parity
  * passes backwards; tile_z, tile_t (powers of two <= 256, 0 = keep) set the

@@ -24,6 +24,7 @@ struct Lat3 {
     unsigned long long *acc;  // kNumAcc x kBuckets fixed-point accumulators
     double *results;          // kRes3 result slots
     double *hist;             // kHist3 plaquette history rows
+    uint32_t *ctr;            // device counters: [0] sweep index, [1] history row of captured sweeps
     float beta;
     uint32_t replica;
 };
@@ -42,16 +43,19 @@ hipError_t launch_su3_init(const Lat3 &L, int start, uint64_t seed, hipStream_t 
 // microcanonical over-relaxation pass (no randoms); with measure, the plaquette
 // terms of the passes' nu < mu staples are accumulated (odd passes of mu >= 1
 // cover every plaquette of the end-of-sweep configuration once).
-hipError_t launch_su3_pass(const Lat3 &L, int mu, int par, uint32_t sweep, uint64_t seed,
-                           bool measure, const Launch3 &cfg, hipStream_t s,
-                           bool overrelax = false);
+// The sweep index is read from L.ctr[0] on the device.
+hipError_t launch_su3_pass(const Lat3 &L, int mu, int par, uint64_t seed, bool measure,
+                           const Launch3 &cfg, hipStream_t s, bool overrelax = false);
 hipError_t launch_su3_reunit(const Lat3 &L, hipStream_t s);
 hipError_t launch_su3_plaquette(const Lat3 &L, hipStream_t s);
 hipError_t launch_su3_polyakov(const Lat3 &L, hipStream_t s);
 // Totals of the accumulators named by flags (1 plaquette, 2 Polyakov) into the
 // result slots (the accumulators are reset); flags & 4: the plaquette also
-// goes to hist[row].
+// goes to hist[row] (flags & 16: to hist[ctr[1]++] instead); flags & 8: the
+// sweep index ctr[0] advances by one.
 hipError_t launch_su3_finish(const Lat3 &L, int flags, int row, hipStream_t s);
+// ctr[which] = value (a kernel, so that it can sit in a captured graph).
+hipError_t launch_su3_set_counter(const Lat3 &L, uint32_t value, int which, hipStream_t s);
 
 }  // namespace su3rt
 

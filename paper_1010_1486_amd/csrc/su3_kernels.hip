@@ -395,14 +395,19 @@ __device__ __forceinline__ float update_site3(const Lat3 &L, uint32_t gid, int p
 }
 
 template <int MU, bool MEASURE, bool OR>
-__global__ __launch_bounds__(256) void su3_pass_kernel(Lat3 L, int par, uint32_t sweep,
-                                                       uint32_t k0, uint32_t k1,
-                                                       uint32_t nblocks, int remap, int reverse)
+__global__ __launch_bounds__(256) void su3_pass_kernel(Lat3 L, int par, uint32_t k0,
+                                                       uint32_t k1, uint32_t nblocks, int remap,
+                                                       int reverse)
 {
     const uint32_t blk = logical_block(blockIdx.x, nblocks, remap, reverse);
     const uint32_t gid = blk * blockDim.x + threadIdx.x;
     float meas = 0.0f;
-    if (gid < L.g.vh) meas = update_site3<MU, MEASURE, OR>(L, gid, par, sweep, k0, k1);
+    if (gid < L.g.vh) {
+        // the sweep index lives on the device (uniform: a scalar load through
+        // the constant address space), so captured sweeps replay correctly
+        const uint32_t sweep = *(const __attribute__((address_space(4))) uint32_t *)L.ctr;
+        meas = update_site3<MU, MEASURE, OR>(L, gid, par, sweep, k0, k1);
+    }
     if (MEASURE) block_accumulate((double)meas, L.acc, A3_PLAQ, blockIdx.x);
 }
 
@@ -480,9 +485,14 @@ __global__ __launch_bounds__(kBuckets) void su3_finish_kernel(Lat3 L, int flags,
         if (threadIdx.x == 0) {
             const double p = from_fixed(t) / (12.0 * (double)g.vh);
             L.results[R3_PLAQ] = p;
-            if (flags & 4) L.hist[row] = p;
+            if (flags & 4) {
+                // flags 16: the row comes from the device row counter (captured sweeps)
+                const uint32_t r = (flags & 16) ? L.ctr[1]++ : (uint32_t)row;
+                L.hist[r] = p;
+            }
         }
     }
+    if ((flags & 8) && threadIdx.x == 0) L.ctr[0] += 1u;  // the sweep is complete
     if (flags & 2) {
         const unsigned long long tr = take_total(L.acc, A3_POLY_RE);
         const unsigned long long ti = take_total(L.acc, A3_POLY_IM);
@@ -552,7 +562,7 @@ __global__ __launch_bounds__(256) void su3_init_kernel(Lat3 L, int start, uint32
 uint32_t nblk(uint64_t n, int b) { return (uint32_t)((n + (uint64_t)b - 1) / (uint64_t)b); }
 
 template <int MU, bool OR>
-void launch_pass_mu(const Lat3 &L, int par, uint32_t sweep, uint32_t k0, uint32_t k1,
+void launch_pass_mu(const Lat3 &L, int par, uint32_t k0, uint32_t k1,
                     bool measure, const Launch3 &cfg, hipStream_t s)
 {
     const uint32_t nb = nblk(L.g.vh, cfg.block);
@@ -560,21 +570,21 @@ void launch_pass_mu(const Lat3 &L, int par, uint32_t sweep, uint32_t k0, uint32_
     const int remap = cfg.remap ? 1 : 0;
     if (measure)
         hipLaunchKernelGGL((su3_pass_kernel<MU, true, OR>), dim3(nb), dim3(cfg.block), 0, s, L,
-                           par, sweep, k0, k1, nb, remap, reverse);
+                           par, k0, k1, nb, remap, reverse);
     else
         hipLaunchKernelGGL((su3_pass_kernel<MU, false, OR>), dim3(nb), dim3(cfg.block), 0, s, L,
-                           par, sweep, k0, k1, nb, remap, reverse);
+                           par, k0, k1, nb, remap, reverse);
 }
 
 template <bool OR>
-void launch_pass_or(const Lat3 &L, int mu, int par, uint32_t sweep, uint32_t k0, uint32_t k1,
+void launch_pass_or(const Lat3 &L, int mu, int par, uint32_t k0, uint32_t k1,
                     bool measure, const Launch3 &cfg, hipStream_t s)
 {
     switch (mu) {
-    case 0: launch_pass_mu<0, OR>(L, par, sweep, k0, k1, measure, cfg, s); break;
-    case 1: launch_pass_mu<1, OR>(L, par, sweep, k0, k1, measure, cfg, s); break;
-    case 2: launch_pass_mu<2, OR>(L, par, sweep, k0, k1, measure, cfg, s); break;
-    default: launch_pass_mu<3, OR>(L, par, sweep, k0, k1, measure, cfg, s); break;
+    case 0: launch_pass_mu<0, OR>(L, par, k0, k1, measure, cfg, s); break;
+    case 1: launch_pass_mu<1, OR>(L, par, k0, k1, measure, cfg, s); break;
+    case 2: launch_pass_mu<2, OR>(L, par, k0, k1, measure, cfg, s); break;
+    default: launch_pass_mu<3, OR>(L, par, k0, k1, measure, cfg, s); break;
     }
 }
 
@@ -587,14 +597,14 @@ hipError_t launch_su3_init(const Lat3 &L, int start, uint64_t seed, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_su3_pass(const Lat3 &L, int mu, int par, uint32_t sweep, uint64_t seed,
-                           bool measure, const Launch3 &cfg, hipStream_t s, bool overrelax)
+hipError_t launch_su3_pass(const Lat3 &L, int mu, int par, uint64_t seed, bool measure,
+                           const Launch3 &cfg, hipStream_t s, bool overrelax)
 {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     if (overrelax)
-        launch_pass_or<true>(L, mu, par, sweep, k0, k1, measure, cfg, s);
+        launch_pass_or<true>(L, mu, par, k0, k1, measure, cfg, s);
     else
-        launch_pass_or<false>(L, mu, par, sweep, k0, k1, measure, cfg, s);
+        launch_pass_or<false>(L, mu, par, k0, k1, measure, cfg, s);
     return hipGetLastError();
 }
 
@@ -614,6 +624,17 @@ hipError_t launch_su3_polyakov(const Lat3 &L, hipStream_t s)
 {
     const uint64_t vs = (uint64_t)L.g.nx * L.g.ny * L.g.nz;
     hipLaunchKernelGGL(su3_polyakov_kernel, dim3(nblk(vs, 256)), dim3(256), 0, s, L);
+    return hipGetLastError();
+}
+
+__global__ void su3_set_counter_kernel(uint32_t *ctr, uint32_t value, int which)
+{
+    ctr[which] = value;
+}
+
+hipError_t launch_su3_set_counter(const Lat3 &L, uint32_t value, int which, hipStream_t s)
+{
+    hipLaunchKernelGGL(su3_set_counter_kernel, dim3(1), dim3(1), 0, s, L.ctr, value, which);
     return hipGetLastError();
 }
 

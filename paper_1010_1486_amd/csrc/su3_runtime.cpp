@@ -45,20 +45,54 @@ struct su3_ctx {
     uint32_t lg_tz = 3, lg_tt = 3;
     hipStream_t stream = nullptr;
     uint64_t seed = 0;
-    uint32_t sweep = 0;
+    uint32_t sweep = 0;  // host copy of the device sweep index L.ctr[0]
     void *links_mem = nullptr;
     void *scratch_mem = nullptr;
+    // captured sweeps (su3_capture_sweeps): the graph, its sweeps per replay,
+    // reunitarisation period, and history rows written / available
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int32_t g_ns = 0, g_reunit = 0;
+    bool g_meas = false;
+    int64_t g_rows_cap = 0, g_rows_next = 0;
 };
 
 namespace {
 
-constexpr size_t kScratch3 = kAccBytes + (size_t)kRes3 * 8 + (size_t)kHist3 * 8;
+constexpr size_t kScratch3 = kAccBytes + (size_t)kRes3 * 8 + (size_t)kHist3 * 8 + 256;
 
 int64_t volume3(const int32_t *d) { return (int64_t)d[0] * d[1] * d[2] * d[3]; }
 
 int check3(su3_ctx *c)
 {
     if (!c) return fail(SU2_EINVAL, "context is NULL");
+    return SU2_OK;
+}
+
+void drop_graph(su3_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->g_ns = c->g_reunit = 0;
+    c->g_meas = false;
+    c->g_rows_cap = c->g_rows_next = 0;
+}
+
+// The eight passes of one heat-bath sweep, its end-of-sweep kernel (history
+// row, sweep index) and the reunitarisation when the sweep completes a period.
+// flags: as launch_su3_finish (8 is always added).
+int enqueue_sweep(su3_ctx *c, const Lat3 &L, bool measure, int flags, int row,
+                  int32_t reunit_every, uint32_t sweep)
+{
+    for (int mu = 0; mu < 4; ++mu)
+        for (int par = 0; par < 2; ++par)
+            HIP_TRY(launch_su3_pass(L, mu, par, c->seed, measure && par == 1 && mu >= 1, c->cfg,
+                                    c->stream));
+    HIP_TRY(launch_su3_finish(L, flags | 8, row, c->stream));
+    if (reunit_every > 0 && (sweep + 1u) % (uint32_t)reunit_every == 0u)
+        HIP_TRY(launch_su3_reunit(L, c->stream));
     return SU2_OK;
 }
 
@@ -143,6 +177,7 @@ int su3_init(su3_ctx **out, const int32_t dims[4], double beta, uint64_t seed, i
         c->L.results = reinterpret_cast<double *>(static_cast<unsigned char *>(c->scratch_mem) +
                                                   kAccBytes);
         c->L.hist = c->L.results + kRes3;
+        c->L.ctr = reinterpret_cast<uint32_t *>(c->L.hist + kHist3);  // zeroed above
         e = launch_su3_init(c->L, start, seed, c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -163,6 +198,7 @@ int su3_destroy(su3_ctx *c)
     SU2_API_BEGIN
     if (!c) return fail(SU2_EINVAL, "context is NULL");
     (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
     if (c->links_mem) (void)hipFree(c->links_mem);
     if (c->scratch_mem) (void)hipFree(c->scratch_mem);
     delete c;
@@ -182,13 +218,9 @@ int su3_heatbath_sweep(su3_ctx *c, int32_t nsweeps, int32_t reunit_every, double
         const int32_t chunk = plaq_hist ? std::min<int32_t>(nsweeps - done, kHist3)
                                         : nsweeps - done;
         for (int32_t j = 0; j < chunk; ++j) {
-            for (int mu = 0; mu < 4; ++mu)
-                for (int par = 0; par < 2; ++par)
-                    HIP_TRY(launch_su3_pass(c->L, mu, par, c->sweep, c->seed,
-                                            plaq_hist && par == 1 && mu >= 1, c->cfg, c->stream));
-            if (plaq_hist) HIP_TRY(launch_su3_finish(c->L, 1 | 4, j, c->stream));
-            if (reunit_every > 0 && (c->sweep + 1u) % (uint32_t)reunit_every == 0u)
-                HIP_TRY(launch_su3_reunit(c->L, c->stream));
+            if ((rc = enqueue_sweep(c, c->L, plaq_hist != nullptr, plaq_hist ? 1 | 4 : 0, j,
+                                    reunit_every, c->sweep)))
+                return rc;
             ++c->sweep;
         }
         if (plaq_hist) {
@@ -211,8 +243,7 @@ int su3_overrelax(su3_ctx *c, int32_t nsweeps)
     for (int32_t j = 0; j < nsweeps; ++j)
         for (int mu = 0; mu < 4; ++mu)
             for (int par = 0; par < 2; ++par)
-                HIP_TRY(launch_su3_pass(c->L, mu, par, c->sweep, c->seed, false, c->cfg,
-                                        c->stream, true));
+                HIP_TRY(launch_su3_pass(c->L, mu, par, c->seed, false, c->cfg, c->stream, true));
     return SU2_OK;
     SU2_API_END
 }
@@ -336,6 +367,7 @@ int su3_set_sweep(su3_ctx *c, uint32_t sweep)
     SU2_API_BEGIN
     int rc = check3(c);
     if (rc) return rc;
+    HIP_TRY(launch_su3_set_counter(c->L, sweep, 0, c->stream));
     c->sweep = sweep;
     return SU2_OK;
     SU2_API_END
@@ -348,6 +380,7 @@ int su3_set_beta(su3_ctx *c, double beta)
     if (rc) return rc;
     if (!beta_ok(beta)) return fail(SU2_EINVAL, "beta must be finite and >= 0");
     c->L.beta = (float)beta;
+    drop_graph(c);  // the captured kernels hold the old coupling
     return SU2_OK;
     SU2_API_END
 }
@@ -370,6 +403,7 @@ int su3_set_launch(su3_ctx *c, int block, int remap, int snake, int tile_z, int 
     c->lg_tz = lz;
     c->lg_tt = lt;
     c->L.g = g;
+    drop_graph(c);
     return SU2_OK;
     SU2_API_END
 }
@@ -402,7 +436,7 @@ int su3_test_pass(su3_ctx *c, int mu, int parity)
     if (rc) return rc;
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1)
         return fail(SU2_EINVAL, "mu must be 0..3 and parity 0..1");
-    HIP_TRY(launch_su3_pass(c->L, mu, parity, c->sweep, c->seed, false, c->cfg, c->stream));
+    HIP_TRY(launch_su3_pass(c->L, mu, parity, c->seed, false, c->cfg, c->stream));
     return SU2_OK;
     SU2_API_END
 }
@@ -455,8 +489,76 @@ int su3_test_or_pass(su3_ctx *c, int mu, int parity)
     if (rc) return rc;
     if (mu < 0 || mu > 3 || parity < 0 || parity > 1)
         return fail(SU2_EINVAL, "mu must be 0..3 and parity 0..1");
-    HIP_TRY(launch_su3_pass(c->L, mu, parity, c->sweep, c->seed, false, c->cfg, c->stream,
-                            true));
+    HIP_TRY(launch_su3_pass(c->L, mu, parity, c->seed, false, c->cfg, c->stream, true));
+    return SU2_OK;
+    SU2_API_END
+}
+
+int su3_capture_sweeps(su3_ctx *c, int32_t nsweeps, int32_t reunit_every, int meas,
+                       double *dev_history, int64_t history_rows)
+{
+    SU2_API_BEGIN
+    int rc = check3(c);
+    if (rc) return rc;
+    if (nsweeps <= 0 || reunit_every < 0)
+        return fail(SU2_EINVAL, "nsweeps must be > 0 and reunit_every >= 0");
+    if (meas != 0 && meas != 1) return fail(SU2_EINVAL, "meas must be 0 or 1 (plaquette)");
+    if (meas && (!dev_history || history_rows < nsweeps))
+        return fail(SU2_EINVAL, "a measured capture needs dev_history with >= nsweeps rows");
+    if (reunit_every > 0 &&
+        (nsweeps % reunit_every != 0 || c->sweep % (uint32_t)reunit_every != 0u))
+        return fail(SU2_EINVAL, "with reunitarisation the captured sweeps must span whole "
+                                "periods starting at a period boundary");
+    if (!c->stream) return fail(SU2_ESTATE, "capture needs a non-null stream");
+    drop_graph(c);
+    HIP_TRY(launch_su3_set_counter(c->L, 0u, 1, c->stream));  // history row of the replays
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    Lat3 Lg = c->L;
+    if (meas) Lg.hist = dev_history;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    for (int32_t j = 0; j < nsweeps && rc == SU2_OK; ++j)
+        rc = enqueue_sweep(c, Lg, meas != 0, meas ? 1 | 4 | 16 : 0, 0, reunit_every,
+                           c->sweep + (uint32_t)j);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (ee != hipSuccess) return fail(SU2_EHIP, std::string("hipStreamEndCapture: ") +
+                                                    hipGetErrorString(ee));
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(SU2_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    c->graph = g;
+    c->gexec = x;
+    c->g_ns = nsweeps;
+    c->g_reunit = reunit_every;
+    c->g_meas = meas != 0;
+    c->g_rows_cap = meas ? history_rows : 0;
+    c->g_rows_next = 0;
+    return SU2_OK;
+    SU2_API_END
+}
+
+int su3_replay_sweeps(su3_ctx *c, int32_t count)
+{
+    SU2_API_BEGIN
+    int rc = check3(c);
+    if (rc) return rc;
+    if (!c->gexec) return fail(SU2_ESTATE, "no captured sweeps");
+    if (count < 0) return fail(SU2_EINVAL, "count must be >= 0");
+    if (c->g_reunit > 0 && c->sweep % (uint32_t)c->g_reunit != 0u)
+        return fail(SU2_ESTATE, "replay must start at a reunitarisation period boundary");
+    if (c->g_meas && c->g_rows_next + (int64_t)count * c->g_ns > c->g_rows_cap)
+        return fail(SU2_EINVAL, "the replays would write history rows past the " +
+                                    std::to_string(c->g_rows_cap) + " captured rows");
+    for (int32_t i = 0; i < count; ++i) HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+    c->sweep += (uint32_t)count * (uint32_t)c->g_ns;
+    if (c->g_meas) c->g_rows_next += (int64_t)count * c->g_ns;
     return SU2_OK;
     SU2_API_END
 }

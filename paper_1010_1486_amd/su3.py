@@ -38,6 +38,8 @@ _SIGS3 = {
     "su3_test_or_pass": (_int, [_vp, _int, _int]),
     "su3_overrelax": (_int, [_vp, _i32]),
     "su3_test_read_links": (_int, [_vp, ctypes.c_int64, _vp, _int, _vp]),
+    "su3_capture_sweeps": (_int, [_vp, _i32, _i32, _int, _vp, ctypes.c_int64]),
+    "su3_replay_sweeps": (_int, [_vp, _i32]),
 }
 _bound = False
 
@@ -115,6 +117,23 @@ class Lattice3:
         _check(lib3().su3_heatbath_sweep(self.h, int(n), int(reunit_every),
                                          None if hist is None else _p(hist)))
         return hist[:n] if history else None
+
+    def capture(self, n, reunit_every=0, hist=None):
+        """Record n heat-bath sweeps as a graph (su3_capture_sweeps); hist: FP64
+        device tensor of plaquette rows (None: no measurement).  The k-th replay
+        writes rows k*n.. and replays past its last row are refused."""
+        rows = 0
+        if hist is not None:
+            import torch
+            assert hist.dtype == torch.float64 and hist.is_contiguous()
+            rows = hist.numel()
+        _check(lib3().su3_capture_sweeps(self.h, int(n), int(reunit_every),
+                                         0 if hist is None else 1,
+                                         None if hist is None else _vp(hist.data_ptr()),
+                                         int(rows)))
+
+    def replay(self, count):
+        _check(lib3().su3_replay_sweeps(self.h, int(count)))
 
     def overrelax(self, n):
         """n microcanonical over-relaxation sweeps (the action is unchanged)."""

@@ -440,3 +440,56 @@ def test_su3_heatbath_with_overrelaxation_matches_oracle_chains(su2, o3):
     announce(f"  gpu HB+3OR {g.mean():.5f}({dg:.5f}) oracle HB {o.mean():.5f}({do:.5f}) "
              f"pull {pull:.2f}")
     assert abs(pull) < 4
+
+
+def test_su3_graph_replay_equals_direct_sweeps(su2):
+    """Heat-bath sweeps recorded as a graph (su3_capture_sweeps, fused plaquette
+    into a device history, reunitarisation every second sweep) and replayed
+    three times with eager work between the replays give the links and
+    plaquettes of the same sweeps run directly, bit for bit; replays past the
+    history rows or off a reunitarisation boundary are refused, a coupling
+    change drops the recording, and a recording without measurements replays
+    like direct sweeps too."""
+    import torch
+    announce("su3 graph replay == direct")
+    dims = [8, 6, 4, 8]
+    side = torch.cuda.Stream()  # capture needs a non-null stream
+    with torch.cuda.stream(side):
+        with su2.Lattice3(dims, 5.8, 61, su2.SU2_HOT) as a, \
+                su2.Lattice3(dims, 5.8, 61, su2.SU2_HOT) as g:
+            ha = a.heatbath_sweep(12, reunit_every=2, history=True)
+            hg = torch.full((12,), -1.0, dtype=torch.float64, device="cuda")
+            with pytest.raises(su2.SU2Error) as e:
+                g.capture(3, reunit_every=2, hist=hg)  # not whole periods
+            assert e.value.code == su2.SU2_EINVAL
+            g.capture(4, reunit_every=2, hist=hg)
+            for k in range(3):
+                g.replay(1)
+                g.synchronize()
+                assert g.sweep == 4 * (k + 1)
+                _ = g.plaquette()  # eager work between the replays
+            np.testing.assert_array_equal(hg.cpu().numpy(), ha)
+            np.testing.assert_array_equal(g.get_links(), a.get_links())
+            with pytest.raises(su2.SU2Error) as e:
+                g.replay(1)  # would write rows 12..15 of 12
+            assert e.value.code == su2.SU2_EINVAL
+            g.set_sweep(13)
+            with pytest.raises(su2.SU2Error) as e:
+                g.replay(1)  # sweep 13 is not a period boundary
+            assert e.value.code == su2.SU2_ESTATE
+            g.set_beta(5.9)
+            g.set_sweep(14)
+            with pytest.raises(su2.SU2Error) as e:
+                g.replay(1)  # dropped by the coupling change
+            assert e.value.code == su2.SU2_ESTATE
+            before = g.get_links()
+            np.testing.assert_array_equal(before, a.get_links())  # nothing ran
+        with su2.Lattice3(dims, 6.1, 62, su2.SU2_HOT) as a, \
+                su2.Lattice3(dims, 6.1, 62, su2.SU2_HOT) as g:
+            a.heatbath_sweep(6)
+            g.capture(2)
+            g.replay(3)
+            g.synchronize()
+            assert g.sweep == 6
+            np.testing.assert_array_equal(g.get_links(), a.get_links())
+    torch.cuda.synchronize()
