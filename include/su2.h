@@ -234,8 +234,10 @@ int su2_set_launch(su2_ctx *ctx, int block, int flags, int tile_z, int tile_t, i
 int su2_get_launch(su2_ctx *ctx, int *block, int *flags, int *tile_z, int *tile_t, int *grid_cap);
 
 /* Autotuner: times candidate launch configurations (block size, order flags,
- * traversal tile, persistent grid) on this lattice with sweeps of `mode`,
- * restores links and counters afterwards, and applies the fastest.  With a
+ * traversal tile, persistent grid) on this lattice with sweeps of `mode` that
+ * measure the plaquette (every candidate on 2 sweeps, the three fastest again
+ * on 8; the faster of two timings each), restores links and counters
+ * afterwards, and applies the fastest.  With a
  * cache_path (JSON lines, one entry per device and set of extents), a cached
  * choice is applied without timing and new choices are appended.
  * *best_us_per_sweep (may be NULL) receives its time per sweep. */
