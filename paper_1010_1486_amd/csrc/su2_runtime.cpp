@@ -909,7 +909,10 @@ std::string tune_key(const Ensemble &E, int mode)
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) k += prop.gcnArchName;
     std::vector<std::array<int32_t, 4>> d = E.dims;
     std::sort(d.begin(), d.end());
-    k += ";mode=" + std::to_string(mode) + ";n=" + std::to_string(E.n) + ";dims=";
+    k += ";mode=" + std::to_string(mode) + ";n=" + std::to_string(E.n);
+    if (E.f64) k += ";f64";  // another kernel: its own choice
+    if (mode == SU2_KP_OR) k += ";n_or=" + std::to_string(E.n_or);
+    k += ";dims=";
     for (auto &x : d)
         k += std::to_string(x[0]) + "x" + std::to_string(x[1]) + "x" + std::to_string(x[2]) +
              "x" + std::to_string(x[3]) + ",";

@@ -207,3 +207,31 @@ def test_batch_graph_in_each_launch_shape_equals_direct(su2, flags):
             np.testing.assert_allclose(hg[..., 0], ha[..., 0], atol=1e-9, rtol=0)
             np.testing.assert_allclose(hg[..., 1:], ha[..., 1:], atol=1e-6, rtol=0)
     torch.cuda.synchronize()
+
+
+def test_autotune_cache_keeps_precisions_and_modes_apart(su2, tmp_path):
+    """The autotuner's cache distinguishes an FP64 context from an FP32 one of
+    the same extents, and over-relaxation settings: each tunes and records its
+    own entry, and a second FP64 context reuses the FP64 entry."""
+    announce("autotune cache keys")
+    cache = str(tmp_path / "tune.jsonl")
+    dims = [12, 8, 10, 6]
+    with su2.Lattice(dims, 2.2, 71, su2.SU2_HOT) as a:
+        a.autotune(cache)
+    with su2.Lattice64(dims, 2.2, 71, su2.SU2_HOT) as b:
+        us64 = b.autotune(cache)
+        cfg = b.launch()
+        assert cfg["grid_cap"] == 0 and not cfg["flags"] & (4 | 8 | 64 | 128), cfg
+    with su2.Lattice(dims, 2.2, 71, su2.SU2_HOT) as c:
+        c.set_hb_overrelax(1)
+        c.autotune(cache, su2.SU2_KP_OR)
+        c.set_hb_overrelax(2)
+        c.autotune(cache, su2.SU2_KP_OR)
+    with open(cache) as f:
+        lines = [l for l in f if l.strip()]
+    assert len(lines) == 4, lines
+    with su2.Lattice64(dims, 2.2, 72, su2.SU2_HOT) as d:
+        assert d.autotune(cache) == pytest.approx(us64, abs=1e-3)  # cached
+        assert d.launch() == cfg
+    with open(cache) as f:
+        assert len([l for l in f if l.strip()]) == 4
