@@ -94,15 +94,19 @@ def test_overrelaxed_batch_launch_shapes_are_bitwise_neutral(su2, flags):
         np.testing.assert_array_equal(out[0][r], out[1][r])
 
 
+@pytest.mark.parametrize("small", [False, True], ids=["per-pass", "whole-sweep-kernel"])
 @pytest.mark.parametrize("width", [-1.0, 0.02], ids=["independence", "overrelaxed"])
-def test_learned_sweeps_replayed_from_a_graph_equal_direct(su2, width):
+def test_learned_sweeps_replayed_from_a_graph_equal_direct(su2, width, small):
     """Learned Metropolis sweeps of a batch (independence or over-relaxed
-    proposal) captured once and replayed twice give the links, history rows and
-    accept counts of the same sweeps run directly, bit for bit."""
+    proposal; replicas large enough for per-pass launches, or all small enough
+    for the whole-sweep kernel) captured once and replayed twice give the links,
+    history rows and accept counts of the same sweeps run directly, bit for
+    bit."""
     import torch
-    announce(f"learned capture/replay == direct width={width}")
+    announce(f"learned capture/replay == direct width={width} small={small}")
     p = (np.random.default_rng(31).standard_normal(2671) * 0.2).astype(np.float32)
-    dims = [[8, 8, 8, 8], [6, 4, 8, 2], [12, 10, 8, 6]]
+    dims = ([[8, 8, 8, 8], [6, 4, 8, 2], [4, 6, 2, 8]] if small else
+            [[8, 8, 8, 8], [6, 4, 8, 2], [12, 10, 8, 6]])
     betas, starts = [2.2, 1.9, 2.6], [1, 0, 1]
     side = torch.cuda.Stream()
     with torch.cuda.stream(side), su2.NN(params=p) as net:
