@@ -3,7 +3,10 @@
 Workload (headline): 48^4 periodic lattice, beta = 6.0, hot start (Philox seed 3).
 One step = one full sweep (8 checkerboard passes, Sec. 4 schedule) with the
 mean plaquette of every sweep fused into its passes (the workload measures the
-plaquette each sweep) and reunitarisation after every 10th sweep.  Throughput
+plaquette each sweep) and reunitarisation of every link in every 10th sweep,
+fused into that sweep's passes (each link is reunitarised as it is stored; the
+time of the same sweeps with a separate reunitarisation pass and plaquette is
+reported beside it).  Throughput
 = link updates per second (4 V per sweep) with the links resident in HBM.
 Other workloads (4^4, beta scans, 32^3 x Nt with the Polyakov loop, the
 batched learned-vs-plain comparison) are reported in the same JSON line.
@@ -885,6 +888,7 @@ def main():
     side = torch.cuda.Stream(device=dev)  # graph capture needs a non-null stream
     with torch.cuda.stream(side):
         lat = su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT, device=dev)
+    lat.set_reunit_fused(True)
     stream = lat.stream
     meas = su2.SU2_MEAS_PLAQ
     hist = torch.zeros((max(args.steps, args.warmup, 1), 3), dtype=torch.float64, device=dev)
@@ -908,9 +912,9 @@ def main():
     torch.cuda.synchronize()
 
     # the timed sweeps replay a captured graph of one reunitarisation period
-    # (10 sweeps: 80 passes, the fused plaquette, one reunitarisation and the
-    # plaquette after it, the end-of-sweep bookkeeping); a remainder below 10
-    # runs as direct launches
+    # (10 sweeps: 80 passes with the fused plaquette, the last sweep's passes
+    # reunitarising the links they store, the end-of-sweep bookkeeping); a
+    # remainder below 10 runs as direct launches
     chunk = 10
     pad = (-lat.sweep) % chunk
     if pad:
@@ -935,6 +939,23 @@ def main():
         dt = time.perf_counter() - t0
     gpu_us_per_sweep = g0.elapsed_time(g1) * 1e3 / args.steps
     h = np.concatenate([hist_g[:full * chunk].cpu().numpy(), hist[:rem].cpu().numpy()])
+
+    # the same sweeps with the reunitarisation as a separate pass over the
+    # field followed by a standalone plaquette (graph replays of 10 sweeps)
+    lat.set_reunit_fused(False)
+    pad = (-lat.sweep) % chunk
+    if pad:
+        lat.sweep_measure(pad, reunit_every=10, meas=meas, hist=hist)
+    nrep_s = 10
+    hist_s = torch.zeros(((nrep_s + 1) * chunk, 3), dtype=torch.float64, device=dev)
+    lat.capture(chunk, su2.SU2_KP, reunit_every=10, meas=meas, hist=hist_s)
+    lat.replay(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.replay(nrep_s)
+    torch.cuda.synchronize()
+    sep_us_per_sweep = (time.perf_counter() - t0) * 1e6 / (nrep_s * chunk)
+    lat.set_reunit_fused(True)
 
     # average launch duration of the pass kernel, HIP events on the lattice's stream
     print(f"[bench] timing {args.pass_launches} pass launches", file=sys.stderr, flush=True)
@@ -967,7 +988,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "48^4 periodic, beta=6.0, hot start (Philox seed 3); step = 1 "
                                "heat-bath sweep (8 passes) + fused plaquette, "
-                               "reunitarise every 10 sweeps",
+                               "reunitarise every 10 sweeps (fused into that sweep's passes)",
                    "dims": DIMS, "beta": BETA, "links": 4 * V, "mode": "plain KP"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -984,7 +1005,9 @@ def main():
                          "wall_us_per_sweep": 1e6 * dt / args.steps,
                          "gpu_event_us_per_sweep": gpu_us_per_sweep,
                          "pass_kernels_us_per_sweep": 8 * pass_ms * 1e3,
-                         "wall_over_pass_kernels": 1e6 * dt / args.steps / (8 * pass_ms * 1e3)},
+                         "wall_over_pass_kernels": 1e6 * dt / args.steps / (8 * pass_ms * 1e3),
+                         "reunitarisation": "fused into the passes of every 10th sweep",
+                         "separate_reunitarisation_wall_us_per_sweep": sep_us_per_sweep},
         "autotuned_us_per_sweep": tuned_us,
         "launch": lat.launch(),
     }
@@ -992,6 +1015,7 @@ def main():
     launch = lat.launch()
     lat.close()
     with su2.Lattice(DIMS, BETA, SEED, su2.SU2_COLD, device=dev) as cold:
+        cold.set_reunit_fused(True)
         cold.set_launch(launch["block"], launch["flags"], launch["tile_z"], launch["tile_t"],
                         launch["grid_cap"])
         cold.sweep_measure(args.warmup, reunit_every=10, meas=meas, hist=hist)

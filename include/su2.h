@@ -143,7 +143,8 @@ int su2_heatbath_sweep(su2_ctx *ctx, int32_t nsweeps, int mode);
  * device FP64 buffer of 3*nsweeps entries, receiving (plaquette, signed mean
  * Polyakov loop, its absolute value) per sweep (0 where not measured).  The
  * plaquette is fused into the odd passes of mu = 1, 2, 3 (no extra read of the
- * field) except on reunitarisation sweeps, where it is measured afterwards.
+ * field) except on reunitarisation sweeps, where it is measured afterwards
+ * (unless the reunitarisation is fused, su2_set_reunit_fused).
  * Global sums: FP64 within each workgroup, then 64-bit fixed point (2^-28)
  * across workgroups, so results are bit-reproducible. */
 int su2_sweep_measure(su2_ctx *ctx, int32_t nsweeps, int mode, int32_t reunit_every, int meas,
@@ -361,6 +362,23 @@ int su2_batch_set_proposal(su2_batch *b, su2_nn *nn);
  * the learned proposal is compared with.  Drops captured sweeps. */
 int su2_set_hb_overrelax(su2_ctx *ctx, int32_t n_or);
 int su2_batch_set_hb_overrelax(su2_batch *b, int32_t n_or);
+/* Where the reunitarisation of su2_sweep_measure / su2_capture_sweeps (and
+ * the batch forms) happens.  on = 0 (default): a separate pass over the field
+ * after each reunitarisation sweep, then the plaquette measured afresh.
+ * on = 1: the last pass stage of a reunitarisation sweep (the heat bath, or
+ * the last over-relaxation sweep of SU2_KP_OR) reunitarises each link as it
+ * stores it (the same U/|U| with |U|^2 in FP64), and the plaquette stays fused
+ * into the odd passes, so the sweep costs no extra read or write of the field.
+ * Every link of the configuration after the sweep is reunitarised in both
+ * forms; they differ in rounding only, because the passes of that sweep after
+ * the first read the reunitarised links of the passes before (in exact
+ * arithmetic a heat-bath link is unit and the reunitarisation is the
+ * identity).  Calls with reunit_every > 0 then run as per-pass launches (no
+ * work queue, no whole-sweep kernel for small lattices).  on not 0 or 1:
+ * SU2_EINVAL; on = 1 on an FP64 context: SU2_ESTATE.  Not in the paper.
+ * Drops captured sweeps. */
+int su2_set_reunit_fused(su2_ctx *ctx, int on);
+int su2_batch_set_reunit_fused(su2_batch *b, int on);
 /* Over-relaxed use of the learned flow in SU2_LEARNED sweeps.  width < 0
  * (default): the independence proposal u = 2z - 1 above.  0 <= width <= 1:
  * the proposal u' = -g(x_old) + width (2z - 1), wrapped onto [-1, 1) with

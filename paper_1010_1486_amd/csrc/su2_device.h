@@ -310,6 +310,17 @@ __device__ __forceinline__ Q overrelax_link(const Q &V, const Q &U)
     return qmul(qmul(Utd, qdag(U)), Utd);
 }
 
+// Reunitarisation of one link: U / |U| with |U|^2 summed in FP64 and each
+// component rounded once to FP32.  The reunitarisation kernels and the passes
+// that normalise the links they store share it, so both give the same bits.
+__device__ __forceinline__ Q unit_q(const Q &q)
+{
+    const double n2 = (double)q.w * q.w + (double)q.x * q.x + (double)q.y * q.y +
+                      (double)q.z * q.z;
+    const double inv = 1.0 / sqrt(n2);
+    return Q{(float)(q.w * inv), (float)(q.x * inv), (float)(q.y * inv), (float)(q.z * inv)};
+}
+
 // ---------------------------------------------------------- learned proposal
 // A monotone rational-quadratic spline flow g on [-1, 1] (Durkan et al. 2019)
 // maps a0 to u = g(a0), uniform on [-1, 1]; its density q(a0) = g'(a0)/2 is

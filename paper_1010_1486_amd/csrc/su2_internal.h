@@ -204,9 +204,11 @@ struct Ens {
 hipError_t launch_init(const Ens &e, const int *starts_dev, uint64_t seed, hipStream_t stream);
 // measure: accumulate (1/2)Tr(U' V_nu), nu < mu, into acc[ACC_PLAQ].
 // table != nullptr: learned-proposal Metropolis update (counts into
-// acc[ACC_PROPOSED] / acc[ACC_ACCEPTED]); else the exact heat bath.
+// acc[ACC_PROPOSED] / acc[ACC_ACCEPTED]); else the exact heat bath.  norm:
+// reunitarise each new link before it is stored (and measured).
 hipError_t launch_pass(const Ens &e, int mu, int par, uint64_t seed, bool measure,
-                       const float *table, const LaunchCfg &cfg, hipStream_t stream);
+                       const float *table, const LaunchCfg &cfg, hipStream_t stream,
+                       bool norm = false);
 // The pass with LDS-staged neighbour planes (su2_march.hip), single lattice:
 // workgroups of `block` threads own R full x-rows of an (x, y) plane at one z
 // and walk T planes along t; nunits workgroups (ntile = Ny / R tiles per
@@ -221,9 +223,9 @@ bool march_shape(const int32_t dims[4], uint32_t R, uint32_t T, MarchShape *m);
 hipError_t launch_pass_march(const Ens &e, int mu, int par, uint64_t seed, bool measure, bool orx,
                              const MarchShape &m, int rev, hipStream_t stream);
 // One microcanonical over-relaxation pass (U' = U~^+ U^+ U~^+, no randoms),
-// in the workgroup layout of launch_pass; measure as launch_pass.
+// in the workgroup layout of launch_pass; measure and norm as launch_pass.
 hipError_t launch_or_pass(const Ens &e, int mu, int par, bool measure, const LaunchCfg &cfg,
-                          hipStream_t stream);
+                          hipStream_t stream, bool norm = false);
 // Sum of all plaquettes into acc[ACC_PLAQ]; sum of L(x) into acc[ACC_POLY].
 hipError_t launch_plaquette(const Ens &e, hipStream_t stream);
 hipError_t launch_polyakov(const Ens &e, hipStream_t stream);

@@ -117,8 +117,9 @@ __global__ void init_kernel(const Rep *__restrict__ reps, const int *__restrict_
 // the six-staple sum V (Sec. 2), then the exact heat bath or, with LEARNED,
 // the learned-proposal Metropolis step; the new link is stored.  With
 // MEASURE, meas = (1/2)Tr(U'_MU V_nu) summed over nu < MU.  acc: as
-// learned_link (-1 for the heat bath).
-template <int MU, bool MEASURE, bool LEARNED, bool OR = false>
+// learned_link (-1 for the heat bath).  With NORM the new link is
+// reunitarised (unit_q) before it is stored and measured.
+template <int MU, bool MEASURE, bool LEARNED, bool OR = false, bool NORM = false>
 __device__ __forceinline__ void update_at(const Rep &R, const PassSite &s, int par,
                                           uint32_t sweep, uint32_t k0, uint32_t k1,
                                           const float *ltab, float &meas, int &acc)
@@ -160,17 +161,18 @@ __device__ __forceinline__ void update_at(const Rep &R, const PassSite &s, int p
         Un = heatbath_link(V, R.beta, site, sweep, word2((uint32_t)MU, TAG_TRIAL, R.replica), k0,
                            k1);
     }
+    if (NORM) Un = unit_q(Un);
     st_nt(R.links, g.vh, MU, par, h, Un);
     if (MEASURE) meas = retr(Un, Vlow);
 }
 
-template <int MU, bool MEASURE, bool LEARNED, bool OR = false>
+template <int MU, bool MEASURE, bool LEARNED, bool OR = false, bool NORM = false>
 __device__ __forceinline__ void update_site(const Rep &R, uint32_t gid, int par, uint32_t sweep,
                                             uint32_t k0, uint32_t k1, const float *ltab,
                                             float &meas, int &acc)
 {
-    update_at<MU, MEASURE, LEARNED, OR>(R, pass_site(R.g, gid, par), par, sweep, k0, k1, ltab,
-                                        meas, acc);
+    update_at<MU, MEASURE, LEARNED, OR, NORM>(R, pass_site(R.g, gid, par), par, sweep, k0, k1,
+                                              ltab, meas, acc);
 }
 
 // Fill the LDS copy of the spline table (4 floats of padding first, like the
@@ -191,8 +193,10 @@ __device__ __forceinline__ const float *load_table_lds(float4 *stab4, const floa
 // that all blocks of a replica run on one XCD; with a capped grid (a multiple
 // of 8) the workgroups loop over b (persistent).  With MEASURE, (1/2)Tr(U'_mu(s) V_nu(s)) summed over nu < mu
 // is accumulated: over the odd passes of mu = 1, 2, 3 this is every
-// plaquette of the end-of-sweep configuration exactly once.
-template <int MU, bool MEASURE, bool LEARNED, bool OR = false>
+// plaquette of the end-of-sweep configuration exactly once.  With NORM every
+// stored link is reunitarised first (the last pass stage of a
+// reunitarisation sweep when the reunitarisation is fused into the passes).
+template <int MU, bool MEASURE, bool LEARNED, bool OR = false, bool NORM = false>
 __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
                                                    const uint32_t *__restrict__ bmap,
                                                    const uint2 *__restrict__ amap,
@@ -227,7 +231,8 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
             // uniform: a scalar load through the constant address space
             const uint32_t sweep =
                 *(const __attribute__((address_space(4))) uint32_t *)&R.cnt->sweep;
-            update_site<MU, MEASURE, LEARNED, OR>(R, gid, par, sweep, k0, k1, ltab, meas, acc);
+            update_site<MU, MEASURE, LEARNED, OR, NORM>(R, gid, par, sweep, k0, k1, ltab, meas,
+                                                        acc);
         }
         if (MEASURE) block_accumulate((double)meas, R.acc, ACC_PLAQ, b);
         if (LEARNED) {
@@ -523,17 +528,13 @@ __global__ __launch_bounds__(kBuckets) void set_counter_kernel(const Rep *__rest
 }
 
 // --------------------------------------------------------------- reunit
-// grid (blocks over V/2, 8, replica).  U <- U / |U|, |U|^2 in FP64.
-// U <- U / |U| with the norm in FP64.
+// U <- U / |U| with the norm in FP64 (unit_q).
 __device__ __forceinline__ void reunit_link(const Rep &R, int mu, int par, uint32_t h)
 {
-    const Q q = ldq(R.links, R.g.vh, mu, par, h);
-    const double n2 = (double)q.w * q.w + (double)q.x * q.x + (double)q.y * q.y +
-                      (double)q.z * q.z;
-    const double inv = 1.0 / sqrt(n2);
-    st(R.links, R.g.vh, mu, par, h,
-       Q{(float)(q.w * inv), (float)(q.x * inv), (float)(q.y * inv), (float)(q.z * inv)});
+    st(R.links, R.g.vh, mu, par, h, unit_q(ldq(R.links, R.g.vh, mu, par, h)));
 }
+
+// grid (blocks over V/2, 8, replica)
 
 __global__ __launch_bounds__(256) void reunit_kernel(const Rep *__restrict__ reps)
 {
@@ -1100,8 +1101,8 @@ inline uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
 inline unsigned nblk(uint64_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 inline unsigned round8(unsigned n) { return (n + 7u) & ~7u; }
 
-template <int MU, bool LEARNED, bool OR = false>
-void launch_pass_mu(const Ens &e, int par, uint64_t seed, bool measure, const float *table,
+template <int MU, bool LEARNED, bool OR, bool NORM>
+void launch_pass_mn(const Ens &e, int par, uint64_t seed, bool measure, const float *table,
                     const LaunchCfg &cfg, hipStream_t stream)
 {
     const unsigned total = e.amap ? e.amap_len : e.total_blocks;
@@ -1110,24 +1111,34 @@ void launch_pass_mu(const Ens &e, int par, uint64_t seed, bool measure, const fl
     if (grid == 0) grid = 8;
     const int rev = cfg.snake ? par : 0;
     if (measure)
-        hipLaunchKernelGGL((pass_kernel<MU, true, LEARNED, OR>), dim3(grid), dim3(cfg.pass_block), 0,
-                           stream, e.reps, e.bmap, e.amap, total, par, lo32(seed), hi32(seed),
-                           (int)cfg.xcd_remap, rev, table);
+        hipLaunchKernelGGL((pass_kernel<MU, true, LEARNED, OR, NORM>), dim3(grid),
+                           dim3(cfg.pass_block), 0, stream, e.reps, e.bmap, e.amap, total, par,
+                           lo32(seed), hi32(seed), (int)cfg.xcd_remap, rev, table);
     else
-        hipLaunchKernelGGL((pass_kernel<MU, false, LEARNED, OR>), dim3(grid), dim3(cfg.pass_block), 0,
-                           stream, e.reps, e.bmap, e.amap, total, par, lo32(seed), hi32(seed),
-                           (int)cfg.xcd_remap, rev, table);
+        hipLaunchKernelGGL((pass_kernel<MU, false, LEARNED, OR, NORM>), dim3(grid),
+                           dim3(cfg.pass_block), 0, stream, e.reps, e.bmap, e.amap, total, par,
+                           lo32(seed), hi32(seed), (int)cfg.xcd_remap, rev, table);
+}
+
+template <int MU, bool LEARNED, bool OR = false>
+void launch_pass_mu(const Ens &e, int par, uint64_t seed, bool measure, const float *table,
+                    const LaunchCfg &cfg, bool norm, hipStream_t stream)
+{
+    if (norm)
+        launch_pass_mn<MU, LEARNED, OR, true>(e, par, seed, measure, table, cfg, stream);
+    else
+        launch_pass_mn<MU, LEARNED, OR, false>(e, par, seed, measure, table, cfg, stream);
 }
 
 template <bool LEARNED>
 void launch_pass_l(const Ens &e, int mu, int par, uint64_t seed, bool measure,
-                   const float *table, const LaunchCfg &cfg, hipStream_t stream)
+                   const float *table, const LaunchCfg &cfg, bool norm, hipStream_t stream)
 {
     switch (mu) {
-    case 0: launch_pass_mu<0, LEARNED>(e, par, seed, measure, table, cfg, stream); break;
-    case 1: launch_pass_mu<1, LEARNED>(e, par, seed, measure, table, cfg, stream); break;
-    case 2: launch_pass_mu<2, LEARNED>(e, par, seed, measure, table, cfg, stream); break;
-    default: launch_pass_mu<3, LEARNED>(e, par, seed, measure, table, cfg, stream); break;
+    case 0: launch_pass_mu<0, LEARNED>(e, par, seed, measure, table, cfg, norm, stream); break;
+    case 1: launch_pass_mu<1, LEARNED>(e, par, seed, measure, table, cfg, norm, stream); break;
+    case 2: launch_pass_mu<2, LEARNED>(e, par, seed, measure, table, cfg, norm, stream); break;
+    default: launch_pass_mu<3, LEARNED>(e, par, seed, measure, table, cfg, norm, stream); break;
     }
 }
 
@@ -1141,23 +1152,23 @@ hipError_t launch_init(const Ens &e, const int *starts_dev, uint64_t seed, hipSt
 }
 
 hipError_t launch_pass(const Ens &e, int mu, int par, uint64_t seed, bool measure,
-                       const float *table, const LaunchCfg &cfg, hipStream_t stream)
+                       const float *table, const LaunchCfg &cfg, hipStream_t stream, bool norm)
 {
     if (table)
-        launch_pass_l<true>(e, mu, par, seed, measure, table, cfg, stream);
+        launch_pass_l<true>(e, mu, par, seed, measure, table, cfg, norm, stream);
     else
-        launch_pass_l<false>(e, mu, par, seed, measure, nullptr, cfg, stream);
+        launch_pass_l<false>(e, mu, par, seed, measure, nullptr, cfg, norm, stream);
     return hipGetLastError();
 }
 
 hipError_t launch_or_pass(const Ens &e, int mu, int par, bool measure, const LaunchCfg &cfg,
-                          hipStream_t stream)
+                          hipStream_t stream, bool norm)
 {
     switch (mu) {
-    case 0: launch_pass_mu<0, false, true>(e, par, 0, measure, nullptr, cfg, stream); break;
-    case 1: launch_pass_mu<1, false, true>(e, par, 0, measure, nullptr, cfg, stream); break;
-    case 2: launch_pass_mu<2, false, true>(e, par, 0, measure, nullptr, cfg, stream); break;
-    default: launch_pass_mu<3, false, true>(e, par, 0, measure, nullptr, cfg, stream); break;
+    case 0: launch_pass_mu<0, false, true>(e, par, 0, measure, nullptr, cfg, norm, stream); break;
+    case 1: launch_pass_mu<1, false, true>(e, par, 0, measure, nullptr, cfg, norm, stream); break;
+    case 2: launch_pass_mu<2, false, true>(e, par, 0, measure, nullptr, cfg, norm, stream); break;
+    default: launch_pass_mu<3, false, true>(e, par, 0, measure, nullptr, cfg, norm, stream); break;
     }
     return hipGetLastError();
 }

@@ -301,6 +301,7 @@ public:
     uint32_t sweep = 0;  // host mirror of the (common) sweep counter
     float orw = -1.0f;   // learned proposal: over-relaxation noise width (< 0: off)
     int n_or = 1;        // SU2_KP_OR: over-relaxation sweeps after each heat-bath sweep
+    bool reunit_fused = false;  // reunitarise in the last pass stage of a reunitarisation sweep
     bool f64 = false;    // FP64 links (single lattice): the su2_f64.hip kernels
     uint2 *amap = nullptr;  // XCD-affine pass map (device, owned), see Ens
     uint32_t amap_len = 0;
@@ -575,19 +576,23 @@ public:
     // One (mu, parity) pass in the configured kernel: the LDS-staged march
     // for single FP32 lattices when configured (heat bath and
     // over-relaxation), else the plain pass kernels.
-    hipError_t pass_launch(int mu, int par, bool measure, const float *tab, bool orx)
+    // norm: the plain pass kernel that reunitarises each link it stores.
+    hipError_t pass_launch(int mu, int par, bool measure, const float *tab, bool orx,
+                           bool norm = false)
     {
         if (f64) return launch_pass64(ens(), mu, par, seed, measure, cfg, stream);
-        if (cfg.march_R && !tab)
+        if (cfg.march_R && !tab && !norm)
             return launch_pass_march(ens(), mu, par, seed, measure, orx, march,
                                      cfg.snake ? par : 0, stream);
-        return orx ? launch_or_pass(ens(), mu, par, measure, cfg, stream)
-                   : launch_pass(ens(), mu, par, seed, measure, tab, cfg, stream);
+        return orx ? launch_or_pass(ens(), mu, par, measure, cfg, stream, norm)
+                   : launch_pass(ens(), mu, par, seed, measure, tab, cfg, stream, norm);
     }
 
     // Enqueue n sweeps; the sweep index the device uses comes from the
     // device counters, and the host mirror decides the reunitarisation
-    // schedule.  hist rows restart at 0 for this call.
+    // schedule.  hist rows restart at 0 for this call.  With reunit_fused
+    // the links of a reunitarisation sweep are reunitarised by the passes
+    // that store them last, and the plaquette stays fused into the passes.
     int enqueue(int32_t ns, int mode, int32_t reunit_every, int meas, double *hist,
                 bool reset_rows = true)
     {
@@ -595,12 +600,14 @@ public:
         const float *tab = mode_table(mode, &rc);
         if (rc) return rc;
         if (hist && reset_rows) HIP_TRY(launch_set_counter(ens(), 0, 0, 2, stream));
-        // heat bath + over-relaxation: per-pass launches whatever the configuration
+        // heat bath + over-relaxation, and fused reunitarisation: per-pass
+        // launches whatever the configuration
         const int nor = mode == SU2_KP_OR ? n_or : 0;
-        if (cfg.queue && !f64 && mode != SU2_KP_OR)
+        const bool per_pass = mode == SU2_KP_OR || (reunit_fused && reunit_every > 0);
+        if (cfg.queue && !f64 && !per_pass)
             return enqueue_queue(ns, tab, reunit_every, meas, hist);
         const int gflag = rows_graph ? 8 : 0;
-        if (small_path() && mode != SU2_KP_OR) {
+        if (small_path() && !per_pass) {
             const int flags = (hist && (meas & SU2_MEAS_PLAQ) ? 1 : 0) |
                               (hist && (meas & SU2_MEAS_POLY) ? 2 : 0) | (hist ? 4 | gflag : 0);
             HIP_TRY(launch_small_sweeps(ens(), ns, seed, reunit_every, flags, hist, tab, stream));
@@ -610,19 +617,20 @@ public:
         for (int32_t i = 0; i < ns; ++i) {
             const uint32_t j = sweep + (uint32_t)i;
             const bool reunit = reunit_every > 0 && ((j + 1u) % (uint32_t)reunit_every) == 0u;
+            const bool norm = reunit && reunit_fused;
             const bool want_p = hist && (meas & SU2_MEAS_PLAQ);
-            const bool fused = want_p && !reunit;
+            const bool fused = want_p && (!reunit || norm);
             // the plaquette is fused into the odd passes of mu >= 1 of the last stage
             for (int mu = 0; mu < 4; ++mu)
                 for (int par = 0; par < 2; ++par)
                     HIP_TRY(pass_launch(mu, par, fused && par == 1 && mu >= 1 && nor == 0, tab,
-                                        false));
+                                        false, norm && nor == 0));
             for (int k = 0; k < nor; ++k)
                 for (int mu = 0; mu < 4; ++mu)
                     for (int par = 0; par < 2; ++par)
                         HIP_TRY(pass_launch(mu, par, fused && par == 1 && mu >= 1 && k == nor - 1,
-                                            nullptr, true));
-            if (reunit) HIP_TRY(reunitarize_launch());
+                                            nullptr, true, norm && k == nor - 1));
+            if (reunit && !norm) HIP_TRY(reunitarize_launch());
             if (want_p && !fused) HIP_TRY(plaquette_launch());
             const bool want_l = hist && (meas & SU2_MEAS_POLY);
             if (want_l) HIP_TRY(polyakov_launch());
@@ -1504,6 +1512,33 @@ int su2_set_hb_overrelax(su2_ctx *c, int32_t n_or)
     c->E.drop_graph();
     c->E.n_or = n_or;
     return SU2_OK;
+    SU2_API_END
+}
+
+static int set_reunit_fused(Ensemble &E, int on)
+{
+    if (on != 0 && on != 1) return fail(SU2_EINVAL, "on must be 0 or 1");
+    if (on && E.f64) return fail(SU2_ESTATE, "the fused reunitarisation runs on FP32 links only");
+    E.drop_graph();
+    E.reunit_fused = on != 0;
+    return SU2_OK;
+}
+
+int su2_set_reunit_fused(su2_ctx *c, int on)
+{
+    SU2_API_BEGIN
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    return set_reunit_fused(c->E, on);
+    SU2_API_END
+}
+
+int su2_batch_set_reunit_fused(su2_batch *b, int on)
+{
+    SU2_API_BEGIN
+    int rc = check_batch(b);
+    if (rc) return rc;
+    return set_reunit_fused(b->E, on);
     SU2_API_END
 }
 

@@ -63,6 +63,8 @@ _SIGS = {
     "su2_links_device": (_int, [_vp, _vp, _vp]),
     "su2_set_hb_overrelax": (_int, [_vp, _i32]),
     "su2_batch_set_hb_overrelax": (_int, [_vp, _i32]),
+    "su2_set_reunit_fused": (_int, [_vp, _int]),
+    "su2_batch_set_reunit_fused": (_int, [_vp, _int]),
     "su2_sweep_measure_static": (_int, [_vp, _vp, _d, _u64, _u32, _i32, _i32, _int, _vp, _vp]),
     "su2_synchronize": (_int, [_vp]),
     "su2_set_launch": (_int, [_vp, _int, _int, _int, _int, _int]),
@@ -644,6 +646,10 @@ class Lattice:
         """Over-relaxation sweeps after each heat-bath sweep in SU2_KP_OR mode."""
         _check(lib().su2_set_hb_overrelax(self.h, int(n_or)))
 
+    def set_reunit_fused(self, on=True):
+        """Reunitarise inside the last pass stage of a reunitarisation sweep."""
+        _check(lib().su2_set_reunit_fused(self.h, int(on)))
+
     def accept_stats(self, reset=False):
         return su2_get_accept_stats(self.h, reset)
 
@@ -789,6 +795,10 @@ class Batch:
     def set_hb_overrelax(self, n_or):
         """Over-relaxation sweeps after each heat-bath sweep in SU2_KP_OR mode."""
         _check(lib().su2_batch_set_hb_overrelax(self.h, int(n_or)))
+
+    def set_reunit_fused(self, on=True):
+        """Reunitarise inside the last pass stage of a reunitarisation sweep."""
+        _check(lib().su2_batch_set_reunit_fused(self.h, int(on)))
 
     def accept_stats(self, reset=False):
         p = np.zeros(self.n, dtype=np.uint64)
