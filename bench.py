@@ -618,6 +618,7 @@ def su3_run(su2, torch, dev, steps=100, launches=80, with_cpu=True):
     if with_cpu:
         out["cpu_baseline"] = su3_oracle_rate()
     out["small_lattice_graph"] = su3_small_graph(su2, torch, dev)
+    out["small_lattice_batch"] = su3_small_batch(su2, torch, dev)
     return out
 
 
@@ -653,31 +654,52 @@ SU3_SCAN_BETAS = [round(5.40 + 0.05 * i, 2) for i in range(13)]
 
 def su3_polyakov_scan(su2, torch, dev, dims=(16, 16, 16, 4), therm=300, nmeas=300, every=2):
     """The SU(3) counterpart of the Polyakov-loop scan: 16^3 x 4 from a cold
-    start at 13 couplings 5.40..6.00, `therm` sweeps, then the Polyakov loop
-    (and the fused plaquette) every `every` sweeps for `nmeas` measurements.
-    beta_c is where <|L|> rises most (the same estimator as for SU(2))."""
-    rows = []
+    start at 13 couplings 5.40..6.00 run as one batch (replica r at coupling
+    r), `therm` sweeps, then the Polyakov loop (and the fused plaquette) every
+    `every` sweeps for `nmeas` measurements.  beta_c is where <|L|> rises most
+    (the same estimator as for SU(2))."""
+    nb = len(SU3_SCAN_BETAS)
     t0 = time.perf_counter()
-    for i, b in enumerate(SU3_SCAN_BETAS):
-        with su2.Lattice3(list(dims), b, 9000 + i, su2.SU2_COLD, device=dev) as lat:
-            lat.heatbath_sweep(therm, reunit_every=10)
-            absL, plaq = [], []
-            for _ in range(nmeas):
-                h = lat.heatbath_sweep(every, reunit_every=10, history=True)
-                plaq.append(h[-1])
-                absL.append(abs(complex(*lat.polyakov()[:2])))
-        rows.append({"beta": b, "mean_abs_polyakov": float(np.mean(absL)),
-                     "err_abs_polyakov": float(np.std(absL, ddof=1) * np.sqrt(2 * tau_int(absL)
-                                                                                / len(absL))),
-                     "mean_plaquette": float(np.mean(plaq))})
+    with su2.Batch3(list(dims), SU3_SCAN_BETAS, 9000, su2.SU2_COLD, device=dev) as b:
+        b.heatbath_sweep(therm, reunit_every=10)
+        absL, plaq = np.zeros((nmeas, nb)), np.zeros((nmeas, nb))
+        for m in range(nmeas):
+            plaq[m] = b.heatbath_sweep(every, reunit_every=10, history=True)[-1]
+            pl = b.polyakov()
+            absL[m] = np.hypot(pl[:, 0], pl[:, 1])
     dt = time.perf_counter() - t0
+    rows = []
+    for i, beta in enumerate(SU3_SCAN_BETAS):
+        a = absL[:, i]
+        rows.append({"beta": beta, "mean_abs_polyakov": float(np.mean(a)),
+                     "err_abs_polyakov": float(np.std(a, ddof=1) * np.sqrt(2 * tau_int(a) / len(a))),
+                     "mean_plaquette": float(np.mean(plaq[:, i]))})
     absl = [r["mean_abs_polyakov"] for r in rows]
     V = int(np.prod(dims))
-    return {"workload": f"SU(3) {dims[0]}^3 x {dims[3]}, cold start, {len(SU3_SCAN_BETAS)} couplings "
-                        f"{SU3_SCAN_BETAS[0]}..{SU3_SCAN_BETAS[-1]}, {therm} + {nmeas} x {every} "
-                        "sweeps, |mean Polyakov loop| every measurement",
+    return {"workload": f"SU(3) {dims[0]}^3 x {dims[3]}, cold start, {nb} couplings "
+                        f"{SU3_SCAN_BETAS[0]}..{SU3_SCAN_BETAS[-1]} as one batch, {therm} + "
+                        f"{nmeas} x {every} sweeps, |mean Polyakov loop| every measurement",
             "by_beta": rows, "beta_c": beta_c(SU3_SCAN_BETAS, absl),
-            "link_updates_per_s": 4 * V * len(SU3_SCAN_BETAS) * (therm + nmeas * every) / dt}
+            "link_updates_per_s": 4 * V * nb * (therm + nmeas * every) / dt}
+
+
+def su3_small_batch(su2, torch, dev, dims=(16, 16, 16, 4), n=64, sweeps=100):
+    """64 replicas of the launch-bound 16^3 x 4 lattice (beta 5.7, hot start,
+    reunitarise every 10) as one SU(3) batch: one launch per pass for all of
+    them, against the single lattice's graph-replayed sweeps."""
+    V = int(np.prod(dims))
+    with su2.Batch3(list(dims), [5.7] * n, 9, su2.SU2_HOT, device=dev) as b:
+        b.heatbath_sweep(10, reunit_every=10)
+        b.synchronize()
+        t0 = time.perf_counter()
+        b.heatbath_sweep(sweeps, reunit_every=10)
+        b.synchronize()
+        dt = (time.perf_counter() - t0) / sweeps
+        plaq = b.plaquette()
+    return {"workload": f"SU(3) {n} replicas of {dims[0]}^3 x {dims[3]}, beta 5.7, hot start, "
+                        f"{sweeps} sweeps, reunitarise every 10, one batch",
+            "us_per_sweep_all_replicas": 1e6 * dt, "link_updates_per_s": 4 * V * n / dt,
+            "plaquette_mean_over_replicas": float(np.mean(plaq))}
 
 
 def su3_overrelaxation_gain(su2, torch, dev, dims=(16, 16, 16, 4), beta=5.69, budget=6000,

@@ -55,6 +55,7 @@ extern "C" {
 #endif
 
 typedef struct su3_ctx su3_ctx;
+typedef struct su3_batch su3_batch;
 
 /* Device bytes of the link arrays of a lattice (0 for invalid dims). */
 size_t su3_links_bytes(const int32_t dims[4]);
@@ -117,6 +118,10 @@ int su3_set_links(su3_ctx *ctx, const double *host);
 int su3_get_sweep(su3_ctx *ctx, uint32_t *out);
 int su3_set_sweep(su3_ctx *ctx, uint32_t sweep);
 int su3_set_beta(su3_ctx *ctx, double beta);
+/* Philox replica id (< 2^26, else SU2_EINVAL; default 0) of later sweeps: a
+ * lattice with replica id r draws the randoms of replica r of a batch.  Drops
+ * captured sweeps. */
+int su3_set_replica(su3_ctx *ctx, uint32_t replica);
 
 /* hipGraph capture of heat-bath sweeps, for loops over many short calls
  * (small lattices are bound by launch overhead): record nsweeps sweeps exactly
@@ -149,6 +154,37 @@ int su3_links_device(su3_ctx *ctx, void **links_dev, void **hip_stream);
 
 /* Wait for all work enqueued on the context's stream. */
 int su3_synchronize(su3_ctx *ctx);
+
+/* Batches: n replicas (1 <= n <= 65535, else SU2_EINVAL) of one lattice
+ * size, run by the same kernels with one launch per pass for all of them
+ * (grid z = replica), for workloads of many small lattices (coupling scans,
+ * ensembles) that would leave most of the GPU idle one lattice at a time.
+ * Replica r has coupling betas[r] (host double[n], each finite and >= 0, else
+ * SU2_EINVAL), Philox replica id r (its hot start and every draw are those of
+ * a single lattice with su3_set_replica(r)), its own links, accumulators and
+ * history, and follows that single lattice bit for bit.  Memory: n times a
+ * single lattice's (su3_links_bytes plus about 140 KiB of scratch).  Calls
+ * match the single-lattice ones (same arguments, errors and synchronisation)
+ * with these differences: plaq_hist of su3_batch_heatbath_sweep is host
+ * double[nsweeps][n]; su3_batch_plaquette writes double[n] and
+ * su3_batch_polyakov double[n][3]; get/set_links take the replica r (0 <= r <
+ * n, else SU2_EINVAL).  The sweep index is common to all replicas. */
+int su3_batch_init(su3_batch **out, int32_t n, const int32_t dims[4], const double *betas,
+                   uint64_t seed, int start, void *hip_stream);
+int su3_batch_destroy(su3_batch *b);
+int su3_batch_size(su3_batch *b, int32_t *n);
+int su3_batch_heatbath_sweep(su3_batch *b, int32_t nsweeps, int32_t reunit_every,
+                             double *plaq_hist);
+int su3_batch_overrelax(su3_batch *b, int32_t nsweeps);
+int su3_batch_reunitarize(su3_batch *b);
+int su3_batch_plaquette(su3_batch *b, double *out);
+int su3_batch_polyakov(su3_batch *b, double *out);
+int su3_batch_get_links(su3_batch *b, int32_t r, double *host);
+int su3_batch_set_links(su3_batch *b, int32_t r, const double *host);
+int su3_batch_get_sweep(su3_batch *b, uint32_t *out);
+int su3_batch_set_sweep(su3_batch *b, uint32_t sweep);
+int su3_batch_set_launch(su3_batch *b, int block, int remap, int snake, int tile_z, int tile_t);
+int su3_batch_synchronize(su3_batch *b);
 
 /* Test hook: enqueue one pass (direction mu, parity) at the current sweep
  * index, which does not advance. */

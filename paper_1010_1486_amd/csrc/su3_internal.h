@@ -27,6 +27,15 @@ struct Lat3 {
     uint32_t *ctr;            // device counters: [0] sweep index, [1] history row of captured sweeps
     float beta;
     uint32_t replica;
+    // Batches of replicas with the extents of g: every launch has grid z =
+    // nrep, and replica r = blockIdx.z uses links + r * link_stride (float4),
+    // the acc, results, hist and ctr of its own scratch (r * scratch_stride
+    // bytes on), coupling betas[r] (device array; nullptr: beta) and Philox
+    // replica id replica + r.  A single lattice is a batch of one.
+    const float *betas;
+    size_t link_stride;
+    size_t scratch_stride;
+    uint32_t nrep;
 };
 
 enum Acc3 { A3_PLAQ = 0, A3_POLY_RE = 1, A3_POLY_IM = 2, A3_POLY_ABS = 3 };

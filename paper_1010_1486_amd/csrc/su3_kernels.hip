@@ -31,6 +31,22 @@ namespace {
 constexpr uint32_t TAG_SU3_SUB = 7;  // subgroup g draws with Philox tag 7 + g
 constexpr uint32_t TAG_SU3_HOT = 10;
 
+// The lattice of replica blockIdx.z of a batch (uniform: scalar arithmetic).
+__device__ __forceinline__ Lat3 rep3(const Lat3 &L0)
+{
+    Lat3 L = L0;
+    const uint32_t r = blockIdx.z;
+    const size_t off = (size_t)r * L0.scratch_stride;
+    L.links = L0.links + (size_t)r * L0.link_stride;
+    L.acc = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(L0.acc) + off);
+    L.results = reinterpret_cast<double *>(reinterpret_cast<char *>(L0.results) + off);
+    L.hist = reinterpret_cast<double *>(reinterpret_cast<char *>(L0.hist) + off);
+    L.ctr = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(L0.ctr) + off);
+    if (L0.betas) L.beta = L0.betas[r];
+    L.replica = L0.replica + r;
+    return L;
+}
+
 // ----------------------------------------------------------- complex algebra
 struct Cx {
     float r, i;
@@ -395,10 +411,11 @@ __device__ __forceinline__ float update_site3(const Lat3 &L, uint32_t gid, int p
 }
 
 template <int MU, bool MEASURE, bool OR>
-__global__ __launch_bounds__(256) void su3_pass_kernel(Lat3 L, int par, uint32_t k0,
+__global__ __launch_bounds__(256) void su3_pass_kernel(Lat3 L0, int par, uint32_t k0,
                                                        uint32_t k1, uint32_t nblocks, int remap,
                                                        int reverse)
 {
+    const Lat3 L = rep3(L0);
     const uint32_t blk = logical_block(blockIdx.x, nblocks, remap, reverse);
     const uint32_t gid = blk * blockDim.x + threadIdx.x;
     float meas = 0.0f;
@@ -414,9 +431,10 @@ __global__ __launch_bounds__(256) void su3_pass_kernel(Lat3 L, int par, uint32_t
 // ------------------------------------------------------------ observables
 // Re Tr(U_mu(s) U_nu(s+mu) U_mu(s+nu)^+ U_nu(s)^+) / 3 over the six planes of
 // every site, as Re sum_ab P_ab conj(Q_ab) with P = U_mu(s) U_nu(s+mu) and
-// Q = U_nu(s) U_mu(s+nu).  grid (blocks over V/2, parity)
-__global__ __launch_bounds__(256) void su3_plaquette_kernel(Lat3 L)
+// Q = U_nu(s) U_mu(s+nu).  grid (blocks over V/2, parity, replica)
+__global__ __launch_bounds__(256) void su3_plaquette_kernel(Lat3 L0)
 {
+    const Lat3 L = rep3(L0);
     const Geom &g = L.g;
     const int par = blockIdx.y, opp = par ^ 1;
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -448,8 +466,9 @@ __global__ __launch_bounds__(256) void su3_plaquette_kernel(Lat3 L)
 }
 
 // Tr L / 3, L = U_3(x, 0) U_3(x, 1) ... U_3(x, Nt-1), one thread per spatial site.
-__global__ __launch_bounds__(256) void su3_polyakov_kernel(Lat3 L)
+__global__ __launch_bounds__(256) void su3_polyakov_kernel(Lat3 L0)
 {
+    const Lat3 L = rep3(L0);
     const Geom &g = L.g;
     const uint32_t vs = (uint32_t)g.nx * (uint32_t)g.ny * (uint32_t)g.nz;
     const uint32_t xs = blockIdx.x * blockDim.x + threadIdx.x;
@@ -477,8 +496,9 @@ __global__ __launch_bounds__(256) void su3_polyakov_kernel(Lat3 L)
     block_accumulate(ab, L.acc, A3_POLY_ABS, blockIdx.x);
 }
 
-__global__ __launch_bounds__(kBuckets) void su3_finish_kernel(Lat3 L, int flags, int row)
+__global__ __launch_bounds__(kBuckets) void su3_finish_kernel(Lat3 L0, int flags, int row)
 {
+    const Lat3 L = rep3(L0);
     const Geom &g = L.g;
     if (flags & 1) {
         const unsigned long long t = take_total(L.acc, A3_PLAQ);
@@ -507,9 +527,10 @@ __global__ __launch_bounds__(kBuckets) void su3_finish_kernel(Lat3 L, int flags,
 }
 
 // ------------------------------------------------------- init / reunitarise
-// grid (blocks over V/2, 8 = mu * 2 + parity)
-__global__ __launch_bounds__(256) void su3_reunit_kernel(Lat3 L)
+// grid (blocks over V/2, 8 = mu * 2 + parity, replica)
+__global__ __launch_bounds__(256) void su3_reunit_kernel(Lat3 L0)
 {
+    const Lat3 L = rep3(L0);
     const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= L.g.vh) return;
     const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
@@ -520,9 +541,10 @@ __global__ __launch_bounds__(256) void su3_reunit_kernel(Lat3 L)
 
 // Haar SU(3): rows 0, 1 of complex Gaussians (Box-Muller on the Philox blocks
 // (site, 0, mu | 10<<2 | replica<<6, d), d = 0, 1, 2) by Gram-Schmidt; row 2
-// is implied.  grid (blocks over V/2, 8 = mu * 2 + parity)
-__global__ __launch_bounds__(256) void su3_init_kernel(Lat3 L, int start, uint32_t k0, uint32_t k1)
+// is implied.  grid (blocks over V/2, 8 = mu * 2 + parity, replica)
+__global__ __launch_bounds__(256) void su3_init_kernel(Lat3 L0, int start, uint32_t k0, uint32_t k1)
 {
+    const Lat3 L = rep3(L0);
     const Geom &g = L.g;
     const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= g.vh) return;
@@ -569,10 +591,10 @@ void launch_pass_mu(const Lat3 &L, int par, uint32_t k0, uint32_t k1,
     const int reverse = (cfg.snake && par == 1) ? 1 : 0;
     const int remap = cfg.remap ? 1 : 0;
     if (measure)
-        hipLaunchKernelGGL((su3_pass_kernel<MU, true, OR>), dim3(nb), dim3(cfg.block), 0, s, L,
+        hipLaunchKernelGGL((su3_pass_kernel<MU, true, OR>), dim3(nb, 1, L.nrep), dim3(cfg.block), 0, s, L,
                            par, k0, k1, nb, remap, reverse);
     else
-        hipLaunchKernelGGL((su3_pass_kernel<MU, false, OR>), dim3(nb), dim3(cfg.block), 0, s, L,
+        hipLaunchKernelGGL((su3_pass_kernel<MU, false, OR>), dim3(nb, 1, L.nrep), dim3(cfg.block), 0, s, L,
                            par, k0, k1, nb, remap, reverse);
 }
 
@@ -592,7 +614,7 @@ void launch_pass_or(const Lat3 &L, int mu, int par, uint32_t k0, uint32_t k1,
 
 hipError_t launch_su3_init(const Lat3 &L, int start, uint64_t seed, hipStream_t s)
 {
-    hipLaunchKernelGGL(su3_init_kernel, dim3(nblk(L.g.vh, 256), 8), dim3(256), 0, s, L, start,
+    hipLaunchKernelGGL(su3_init_kernel, dim3(nblk(L.g.vh, 256), 8, L.nrep), dim3(256), 0, s, L, start,
                        (uint32_t)seed, (uint32_t)(seed >> 32));
     return hipGetLastError();
 }
@@ -610,37 +632,39 @@ hipError_t launch_su3_pass(const Lat3 &L, int mu, int par, uint64_t seed, bool m
 
 hipError_t launch_su3_reunit(const Lat3 &L, hipStream_t s)
 {
-    hipLaunchKernelGGL(su3_reunit_kernel, dim3(nblk(L.g.vh, 256), 8), dim3(256), 0, s, L);
+    hipLaunchKernelGGL(su3_reunit_kernel, dim3(nblk(L.g.vh, 256), 8, L.nrep), dim3(256), 0, s, L);
     return hipGetLastError();
 }
 
 hipError_t launch_su3_plaquette(const Lat3 &L, hipStream_t s)
 {
-    hipLaunchKernelGGL(su3_plaquette_kernel, dim3(nblk(L.g.vh, 256), 2), dim3(256), 0, s, L);
+    hipLaunchKernelGGL(su3_plaquette_kernel, dim3(nblk(L.g.vh, 256), 2, L.nrep), dim3(256), 0, s,
+                       L);
     return hipGetLastError();
 }
 
 hipError_t launch_su3_polyakov(const Lat3 &L, hipStream_t s)
 {
     const uint64_t vs = (uint64_t)L.g.nx * L.g.ny * L.g.nz;
-    hipLaunchKernelGGL(su3_polyakov_kernel, dim3(nblk(vs, 256)), dim3(256), 0, s, L);
+    hipLaunchKernelGGL(su3_polyakov_kernel, dim3(nblk(vs, 256), 1, L.nrep), dim3(256), 0, s, L);
     return hipGetLastError();
 }
 
-__global__ void su3_set_counter_kernel(uint32_t *ctr, uint32_t value, int which)
+// grid (1, 1, replica)
+__global__ void su3_set_counter_kernel(Lat3 L0, uint32_t value, int which)
 {
-    ctr[which] = value;
+    rep3(L0).ctr[which] = value;
 }
 
 hipError_t launch_su3_set_counter(const Lat3 &L, uint32_t value, int which, hipStream_t s)
 {
-    hipLaunchKernelGGL(su3_set_counter_kernel, dim3(1), dim3(1), 0, s, L.ctr, value, which);
+    hipLaunchKernelGGL(su3_set_counter_kernel, dim3(1, 1, L.nrep), dim3(1), 0, s, L, value, which);
     return hipGetLastError();
 }
 
 hipError_t launch_su3_finish(const Lat3 &L, int flags, int row, hipStream_t s)
 {
-    hipLaunchKernelGGL(su3_finish_kernel, dim3(1), dim3(kBuckets), 0, s, L, flags, row);
+    hipLaunchKernelGGL(su3_finish_kernel, dim3(1, 1, L.nrep), dim3(kBuckets), 0, s, L, flags, row);
     return hipGetLastError();
 }
 

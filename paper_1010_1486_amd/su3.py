@@ -40,6 +40,21 @@ _SIGS3 = {
     "su3_test_read_links": (_int, [_vp, ctypes.c_int64, _vp, _int, _vp]),
     "su3_capture_sweeps": (_int, [_vp, _i32, _i32, _int, _vp, ctypes.c_int64]),
     "su3_replay_sweeps": (_int, [_vp, _i32]),
+    "su3_set_replica": (_int, [_vp, _u32]),
+    "su3_batch_init": (_int, [_vp, _i32, _vp, _vp, _u64, _int, _vp]),
+    "su3_batch_destroy": (_int, [_vp]),
+    "su3_batch_size": (_int, [_vp, _vp]),
+    "su3_batch_heatbath_sweep": (_int, [_vp, _i32, _i32, _vp]),
+    "su3_batch_overrelax": (_int, [_vp, _i32]),
+    "su3_batch_reunitarize": (_int, [_vp]),
+    "su3_batch_plaquette": (_int, [_vp, _vp]),
+    "su3_batch_polyakov": (_int, [_vp, _vp]),
+    "su3_batch_get_links": (_int, [_vp, _i32, _vp]),
+    "su3_batch_set_links": (_int, [_vp, _i32, _vp]),
+    "su3_batch_get_sweep": (_int, [_vp, _vp]),
+    "su3_batch_set_sweep": (_int, [_vp, _u32]),
+    "su3_batch_set_launch": (_int, [_vp, _int, _int, _int, _int, _int]),
+    "su3_batch_synchronize": (_int, [_vp]),
 }
 _bound = False
 
@@ -174,6 +189,9 @@ class Lattice3:
     def set_beta(self, b):
         _check(lib3().su3_set_beta(self.h, float(b)))
 
+    def set_replica(self, r):
+        _check(lib3().su3_set_replica(self.h, int(r)))
+
     def set_launch(self, block=256, remap=1, snake=1, tile_z=0, tile_t=0):
         _check(lib3().su3_set_launch(self.h, int(block), int(remap), int(snake), int(tile_z),
                                      int(tile_t)))
@@ -193,3 +211,90 @@ class Lattice3:
 
     def test_or_pass(self, mu, parity):
         _check(lib3().su3_test_or_pass(self.h, int(mu), int(parity)))
+
+
+class Batch3:
+    """n SU(3) replicas of one lattice size (su3_batch), coupling betas[r] and
+    Philox replica id r, on torch's current stream of the device; every pass
+    is one launch for all replicas."""
+
+    def __init__(self, dims, betas, seed, start=SU2_COLD, device="cuda:0"):
+        import torch
+        self.dims = [int(d) for d in dims]
+        self.volume = int(np.prod(self.dims))
+        b = np.ascontiguousarray(betas, dtype=np.float64).ravel()
+        self.n = int(b.size)
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(lib3().su3_batch_init(ctypes.byref(h), self.n, _p(_su2._dims(self.dims)),
+                                         _p(b), int(seed), int(start),
+                                         _vp(self.stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lib3().su3_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def heatbath_sweep(self, n, reunit_every=0, history=False):
+        """n sweeps of every replica; with history, the plaquettes (n, replicas)."""
+        hist = np.zeros((max(int(n), 1), self.n)) if history else None
+        _check(lib3().su3_batch_heatbath_sweep(self.h, int(n), int(reunit_every),
+                                               None if hist is None else _p(hist)))
+        return hist[:n] if history else None
+
+    def overrelax(self, n):
+        _check(lib3().su3_batch_overrelax(self.h, int(n)))
+
+    def reunitarize(self):
+        _check(lib3().su3_batch_reunitarize(self.h))
+
+    def plaquette(self):
+        out = np.zeros(self.n)
+        _check(lib3().su3_batch_plaquette(self.h, _p(out)))
+        return out
+
+    def polyakov(self):
+        """(replicas, 3): Re and Im of the mean of Tr L / 3, mean of |Tr L / 3|."""
+        out = np.zeros((self.n, 3))
+        _check(lib3().su3_batch_polyakov(self.h, _p(out)))
+        return out
+
+    def get_links(self, r):
+        out = np.empty((self.volume, 4, 3, 3), dtype=np.complex128)
+        _check(lib3().su3_batch_get_links(self.h, int(r), _p(out)))
+        return out
+
+    def set_links(self, r, links):
+        a = np.ascontiguousarray(links, dtype=np.complex128).reshape(self.volume, 4, 3, 3)
+        _check(lib3().su3_batch_set_links(self.h, int(r), _p(a)))
+
+    @property
+    def sweep(self):
+        out = ctypes.c_uint32()
+        _check(lib3().su3_batch_get_sweep(self.h, ctypes.byref(out)))
+        return out.value
+
+    def set_sweep(self, s):
+        _check(lib3().su3_batch_set_sweep(self.h, int(s)))
+
+    def set_launch(self, block=256, remap=1, snake=1, tile_z=0, tile_t=0):
+        _check(lib3().su3_batch_set_launch(self.h, int(block), int(remap), int(snake),
+                                           int(tile_z), int(tile_t)))
+
+    def synchronize(self):
+        _check(lib3().su3_batch_synchronize(self.h))

@@ -168,7 +168,45 @@ def test_su3_sizes_and_bad_arguments():
     assert lib.su3_init(None, d.ctypes.data_as(ctypes.c_void_p), 6.0, 1, 0, None) == su2.SU2_EINVAL
     for call in (lambda: lib.su3_destroy(None), lambda: lib.su3_reunitarize(None),
                  lambda: lib.su3_heatbath_sweep(None, 1, 0, None),
-                 lambda: lib.su3_test_pass(None, 0, 0), lambda: lib.su3_synchronize(None)):
+                 lambda: lib.su3_test_pass(None, 0, 0), lambda: lib.su3_synchronize(None),
+                 lambda: lib.su3_set_replica(None, 1)):
+        assert call() == su2.SU2_EINVAL
+
+
+def test_su3_batch_bad_arguments():
+    """su3_batch_init checks n, the couplings, the extents and its pointers
+    before any device work (no GPU needed), and every batch call refuses a
+    NULL batch."""
+    lib = su2.lib3()
+    h = ctypes.c_void_p()
+    d = np.array([4, 4, 4, 4], dtype=np.int32)
+    dp = d.ctypes.data_as(ctypes.c_void_p)
+    betas = np.array([5.5, 5.7, 6.0])
+    bp = betas.ctypes.data_as(ctypes.c_void_p)
+    for n in (0, -1, 65536):
+        assert lib.su3_batch_init(ctypes.byref(h), n, dp, bp, 1, 0, None) == su2.SU2_EINVAL
+    assert lib.su3_batch_init(ctypes.byref(h), 3, dp, None, 1, 0, None) == su2.SU2_EINVAL
+    assert lib.su3_batch_init(None, 3, dp, bp, 1, 0, None) == su2.SU2_EINVAL
+    assert lib.su3_batch_init(ctypes.byref(h), 3, dp, bp, 1, 7, None) == su2.SU2_EINVAL
+    for bad in (float("nan"), -1.0, float("inf")):
+        b2 = np.array([5.5, bad, 6.0])
+        assert lib.su3_batch_init(ctypes.byref(h), 3, dp, b2.ctypes.data_as(ctypes.c_void_p),
+                                  1, 0, None) == su2.SU2_EINVAL
+    d5 = np.array([4, 4, 4, 5], dtype=np.int32)
+    assert lib.su3_batch_init(ctypes.byref(h), 3, d5.ctypes.data_as(ctypes.c_void_p), bp, 1, 0,
+                              None) == su2.SU2_EODD
+    assert h.value is None
+    out = np.zeros(8)
+    op = out.ctypes.data_as(ctypes.c_void_p)
+    for call in (lambda: lib.su3_batch_destroy(None), lambda: lib.su3_batch_size(None, op),
+                 lambda: lib.su3_batch_heatbath_sweep(None, 1, 0, None),
+                 lambda: lib.su3_batch_overrelax(None, 1), lambda: lib.su3_batch_reunitarize(None),
+                 lambda: lib.su3_batch_plaquette(None, op), lambda: lib.su3_batch_polyakov(None, op),
+                 lambda: lib.su3_batch_get_links(None, 0, op),
+                 lambda: lib.su3_batch_set_links(None, 0, op),
+                 lambda: lib.su3_batch_get_sweep(None, op), lambda: lib.su3_batch_set_sweep(None, 0),
+                 lambda: lib.su3_batch_set_launch(None, 256, 1, 1, 0, 0),
+                 lambda: lib.su3_batch_synchronize(None)):
         assert call() == su2.SU2_EINVAL
 
 
