@@ -32,6 +32,22 @@ def sample_sites(orc, par, n, seed):
     return np.unique(np.concatenate([s, ends]))
 
 
+def staple_norms_at_update(orc, links, sweep, mask):
+    """k = |V| of each link in mask ((V, 4) booleans, row-major order) when the
+    oracle's sweep from `links` updates it: the passes are replayed in sweep
+    order and each link's staple is taken just before its pass."""
+    U = links.astype(np.float64)
+    idx = [(int(s), int(m)) for s, m in np.argwhere(mask)]
+    k = {}
+    for mu in range(4):
+        for p in range(2):
+            for s, m in idx:
+                if m == mu and orc.parity(DIMS, s) == p:
+                    k[(s, m)] = float(np.linalg.norm(orc.staple(DIMS, U, s, mu)))
+            orc.do_pass(DIMS, U, mu, p, sweep, BETA, SEED, order=3)
+    return np.array([k[i] for i in idx])
+
+
 def check_pass(lat, orc, links, U, mu, par, seed):
     """One pass from the seeded configuration `links` (U: the same in FP64)."""
     lat.set_links(links)
@@ -78,16 +94,23 @@ def test_full_size_passes_autotuned_and_persistent(su2, orc):
             print(f"[gpu-test] pass ({mu},{par}) max err {w:.2e}", flush=True)
 
 
-def test_full_size_sweep_measurements(su2, orc):
-    announce("48^4 fused sweep measurements")
+@pytest.mark.parametrize("fused", [False, True], ids=["sweep0", "reunit-sweep-fused"])
+def test_full_size_sweep_measurements(su2, orc, fused):
+    """sweep0: sweep 0 (no reunitarisation).  reunit-sweep-fused: sweep 9 with
+    reunit_every 10 and the reunitarisation fused into the passes, as the
+    benchmark runs it; the oracle reunitarises after its sweep, and every link
+    must come out unit to FP32 rounding."""
+    announce(f"48^4 fused sweep measurements fused_reunit={fused}")
+    sweep0 = 9 if fused else 0
     links = inputs.random_links(DIMS, 32, spread=0.6)
     U = links.astype(np.float64)
     p0 = orc.plaquette(DIMS, U)
     ls0, la0 = orc.polyakov(DIMS, U)
     with su2.Lattice(DIMS, BETA, SEED, su2.SU2_HOT) as lat:
         lat.autotune()
+        lat.set_reunit_fused(fused)
         lat.set_links(links)
-        lat.set_sweep(0)
+        lat.set_sweep(sweep0)
         # standalone kernels on the seeded configuration
         assert abs(lat.plaquette() - p0) < 1e-6
         s, a = lat.polyakov()
@@ -100,11 +123,11 @@ def test_full_size_sweep_measurements(su2, orc):
         s, a = lat.polyakov()
         assert abs(hist[0, 1] - s) < 1e-6 and abs(hist[0, 2] - a) < 1e-6
     n2 = np.einsum("vmc,vmc->vm", got.astype(np.float64), got.astype(np.float64))
-    assert np.abs(n2 - 1).max() < 1e-5
+    assert np.abs(n2 - 1).max() < (3e-7 if fused else 1e-5)
     # the oracle's sweep of the same configuration (all host threads), with the
     # margin of every accept decision it took
-    ph, lh, margin = orc.sweeps(DIMS, U, 1, 0, BETA, SEED, nthreads=16, measure=True,
-                                want_margin=True)
+    ph, lh, margin = orc.sweeps(DIMS, U, 1, sweep0, BETA, SEED, reunit_every=10, nthreads=16,
+                                measure=True, want_margin=True)
     off = np.abs(got - U).max(axis=2) > 1e-5
     nbad = int(off.sum())
     nflag = int((margin < MARGIN_FLAG).sum())
@@ -118,10 +141,25 @@ def test_full_size_sweep_measurements(su2, orc):
     # within the seven passes that follow).  With no flagged decision every
     # link matches.
     assert nflag <= max_flags(4 * V)
-    assert nbad <= 500 * nflag, (nbad, nflag)
-    if nbad:
+    dev = np.abs(got - U).max(axis=2)
+    moved = dev > 1e-3  # flipped decisions and the links updated after them
+    assert int(moved.sum()) <= 500 * nflag, (int(moved.sum()), nflag)
+    if moved.any():
         # every mismatched cone starts at a flagged decision of its own sweep
-        assert (off & (margin < MARGIN_FLAG)).any()
+        assert (moved & (margin < MARGIN_FLAG)).any()
+    lone = off & ~moved
+    if lone.any():
+        # U~ = V/k carries the FP32 error of the staple sum V (a few 1e-6
+        # absolute over six products of unit quaternions) divided by k, so a
+        # link whose staple nearly cancels can miss 1e-5 without any decision
+        # moving: each such link's k at its update (the oracle's staple, pass
+        # by pass from the seeded links) must explain its deviation
+        ks = staple_norms_at_update(orc, links, sweep0, lone)
+        d = dev[lone]
+        print(f"[gpu-test] links off by 1e-5..1e-3: deviation {d.tolist()}, k at the update "
+              f"{ks.tolist()}, margins {margin[lone].tolist()}", flush=True)
+        assert int(lone.sum()) <= 20
+        assert np.all(d * ks < 5e-6), (d, ks)
     # each changed link moves its six plaquettes and one Polyakov line by O(1)
     assert abs(hist[0, 0] - ph[0]) < 1e-6 + 6.0 * nbad / (6 * V)
     assert abs(hist[0, 1] - lh[0]) < 1e-6 + 2.0 * nbad / (V // DIMS[3])
