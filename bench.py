@@ -269,10 +269,13 @@ def run_batch(su2, torch, dev, dims, betas, starts, seed, therm, sweeps, meas, r
               chunk=50):
     """Autotuned batch: `therm` sweeps, then `sweeps` measured sweeps replayed as
     graph-captured chunks; returns (seconds of the measured part, history, the
-    autotuned launch)."""
+    autotuned launch).  When the autotuner picks per-pass launches, the
+    reunitarisation is fused into the passes (launch["reunit_fused"])."""
     b = su2.Batch(dims, betas, starts, seed=seed, device=dev)
     b.autotune(None, su2.SU2_KP)
     launch = b.launch()
+    launch["reunit_fused"] = bool(reunit > 0 and not launch["flags"] & 8)
+    b.set_reunit_fused(launch["reunit_fused"])
     b.sweep_measure(therm, reunit_every=reunit, meas=meas)
     h = torch.zeros((sweeps, len(dims), 3), dtype=torch.float64, device=dev)
     b.capture(chunk, su2.SU2_KP, reunit_every=reunit, meas=meas, hist=h)
@@ -287,8 +290,9 @@ def run_batch(su2, torch, dev, dims, betas, starts, seed, therm, sweeps, meas, r
 
 def step_bytes(volumes, polyakov, reunit):
     """Algorithmic HBM bytes of one sweep over lattices of these volumes:
-    8 passes x 64 V, plus 16 V for the Polyakov loop, plus 128 V per
-    reunitarisation (amortised); the plaquette is fused into the passes."""
+    8 passes x 64 V, plus 16 V for the Polyakov loop, plus 128 V per separate
+    reunitarisation (amortised; reunit 0 when there is none or it is fused
+    into the passes); the plaquette is fused into the passes."""
     V = float(sum(volumes))
     return V * (512.0 + (16.0 if polyakov else 0.0) + (128.0 / reunit if reunit else 0.0))
 
@@ -368,7 +372,7 @@ def other_configs(su2, torch, dev, with_cpu):
                              500, 1000, PL, 10)
         vols = [L ** 4] * len(d)
         ups = 4 * sum(vols) * 1000 / dt
-        gbs = step_bytes(vols, False, 10) * 1000 / dt / 1e9
+        gbs = step_bytes(vols, False, 0 if launch["reunit_fused"] else 10) * 1000 / dt / 1e9
         P = h[:, :, 0].mean(axis=0)
         key = f"beta_scan_{L}^4"
         out[key] = {"workload": f"{len(d)} chains of {L}^4 (beta 1.5..3.0 step 0.1, cold and hot), "
@@ -389,7 +393,7 @@ def other_configs(su2, torch, dev, with_cpu):
                          PL | su2.SU2_MEAS_POLY, 10)
     vols = [32 ** 3 * x[3] for x in d]
     ups = 4 * sum(vols) * 5000 / dt
-    gbs = step_bytes(vols, True, 10) * 5000 / dt / 1e9
+    gbs = step_bytes(vols, True, 0 if launch["reunit_fused"] else 10) * 5000 / dt / 1e9
     absL = np.abs(h[1000:, :, 1]).mean(axis=0)
     out["polyakov_32^3xNt"] = {
         "workload": f"{len(d)} chains of 32^3 x Nt (Nt 4, 6, 8; beta 2.00..2.60 step 0.05), "
