@@ -412,8 +412,8 @@ int su2_test_pass(su2_ctx *ctx, int mu, int parity, int mode);
  * that moves the same bytes as the pass -- the seven plane groups it reads,
  * each at the thread's own half-site, no stencil -- and writes the
  * per-half-site sum of those seven quaternions to out_dev (caller-owned
- * device memory, 4 planes of V/2 floats: out[c * V/2 + h]).  No link or
- * counter of ctx changes. */
+ * device memory of V/2 quaternions, one 16-byte nontemporal store each:
+ * out[4 h + c], c = a0..a3).  No link or counter of ctx changes. */
 int su2_test_stream_pass(su2_ctx *ctx, int mu, int parity, void *out_dev);
 /* Host-side evaluation (no GPU needed) of the pass kernel's index map for
  * extents dims and traversal tile tile_z x tile_t (0 = default): for each of

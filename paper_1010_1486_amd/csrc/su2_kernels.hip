@@ -251,9 +251,9 @@ __global__ __launch_bounds__(256) void pass_kernel(const Rep *__restrict__ reps,
 // ------------------------------------------------------- streaming floor
 // The byte pattern of a (mu, parity) pass without its stencil: the seven
 // plane groups a pass reads (U_nu at both parities for nu != mu, U_mu at the
-// opposite parity), each at the thread's own half-site, and four planes
-// written to `out` (V/2 floats each).  Its duration is the bandwidth floor
-// of the pass's traffic; no link is touched.
+// opposite parity), each at the thread's own half-site, and one quaternion
+// per half-site written to `out` (V/2 float4).  Its duration is the
+// bandwidth floor of the pass's traffic; no link is touched.
 __global__ __launch_bounds__(256) void stream_kernel(const Rep *__restrict__ reps, int mu,
                                                      int par, float *__restrict__ out)
 {
@@ -268,12 +268,8 @@ __global__ __launch_bounds__(256) void stream_kernel(const Rep *__restrict__ rep
         a = qadd(a, ld(arr(R.links, vh, nu, par), h));
         a = qadd(a, ld(arr(R.links, vh, nu, opp), h));
     }
-    // nontemporal, as the pass stores its updated class
-    float *p = out + h;
-    __builtin_nontemporal_store(a.w, p);
-    __builtin_nontemporal_store(a.x, p + vh);
-    __builtin_nontemporal_store(a.y, p + 2 * (size_t)vh);
-    __builtin_nontemporal_store(a.z, p + 3 * (size_t)vh);
+    // one 16-byte nontemporal store, as the pass stores its updated link
+    st_nt(out, vh, 0, 0, h, a);
 }
 
 // -------------------------------------------------------------- plaquette

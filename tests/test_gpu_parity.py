@@ -183,7 +183,7 @@ def test_stream_floor_kernel_moves_the_pass_bytes(su2, orc):
         for mu, p in ((0, 0), (3, 1)):
             lat.test_stream_pass(mu, p, out)
             lat.synchronize()
-            got = out.cpu().numpy().reshape(4, V // 2).sum(axis=1)
+            got = out.cpu().numpy().reshape(V // 2, 4).sum(axis=0)
             want = before[:, [n for n in range(4) if n != mu]].sum(axis=(0, 1)) + \
                 before[par_of != p, mu].sum(axis=0)
             np.testing.assert_allclose(got, want, atol=1e-3)
@@ -191,5 +191,5 @@ def test_stream_floor_kernel_moves_the_pass_bytes(su2, orc):
     with su2.Lattice(dims, 2.0, 5, su2.SU2_COLD) as lat:
         lat.test_stream_pass(1, 0, out)
         lat.synchronize()
-        o = out.cpu().numpy().reshape(4, V // 2)
-        assert np.all(o[0] == 7.0) and np.all(o[1:] == 0.0)
+        o = out.cpu().numpy().reshape(V // 2, 4)
+        assert np.all(o[:, 0] == 7.0) and np.all(o[:, 1:] == 0.0)
