@@ -81,6 +81,46 @@ def test_fused_reunitarisation_sweep_matches_oracle(su2, orc, dims, n_or):
         assert abs(h[0, 0] - orc.plaquette(dims, U)) < 2e-6
 
 
+def test_fused_reunitarisation_learned_sweep_matches_oracle(su2, orc):
+    """The learned-proposal sweep (independence Metropolis with a random
+    network's table) on a reunitarisation sweep with the fused
+    reunitarisation, against the oracle's learned passes followed by its
+    reunitarisation: links unit to FP32 rounding, within 1e-5 of the oracle's
+    outside the cones of flagged Metropolis decisions."""
+    from tests.gpu_util import learned_flagged
+    announce("fused reunitarisation, learned proposal, vs oracle")
+    dims, beta, seed, sw = [4, 6, 2, 8], 2.2, 41, 4
+    params = (np.random.default_rng(16).standard_normal(orc.NN_NPARAM) * 0.2).astype(np.float32)
+    table = orc.nn_table(params)
+    links = inputs.random_links(dims, 151, spread=0.6)
+    with su2.NN(params=params) as net, su2.Lattice(dims, beta, seed) as lat:
+        net.build_table()
+        lat.set_proposal(net)
+        lat.set_reunit_fused(True)
+        lat.set_links(links)
+        lat.set_sweep(sw)
+        h = lat.sweep_measure(1, su2.SU2_LEARNED, reunit_every=5, meas=PLAQ).cpu().numpy()
+        got = lat.get_links()
+        proposed, accepted = lat.accept_stats()
+    U = links.astype(np.float64)
+    nflag = 0
+    for mu in range(4):
+        for p in range(2):
+            margin, _ = orc.learned_pass(dims, U, table, mu, p, sw, beta, seed)
+            nflag += int(learned_flagged(margin).sum())
+    orc.reunitarize(dims, U)
+    d = np.abs(got - U).max(axis=2)
+    bad = int((d > 1e-5).sum())
+    announce(f"  max |gpu - oracle| {d.max():.2e}; off by > 1e-5: {bad}; flagged {nflag}; "
+             f"accepted {int(np.sum(accepted))} of {int(np.sum(proposed))}; "
+             f"max ||U|^2 - 1| {norm_dev(got):.2e}")
+    assert int(np.sum(proposed)) > 0 and 0 < int(np.sum(accepted)) < int(np.sum(proposed))
+    assert norm_dev(got) < 3e-7
+    assert bad <= 500 * nflag, (bad, nflag)
+    if bad == 0:
+        assert abs(h[0, 0] - orc.plaquette(dims, U)) < 2e-6
+
+
 def test_fused_and_separate_reunitarisation_differ_by_rounding(su2, orc):
     """The same reunitarisation sweep both ways from the same links: links
     within 2e-6 when the oracle takes no decision of the sweep within the
