@@ -90,6 +90,24 @@ def test_su3_batch_sweep_matches_oracle_for_its_replica(su2, o3):
         assert abs(h[0, r] - ph[0]) < 2e-6
 
 
+def test_su3_batch_history_longer_than_one_chunk(su2):
+    """A history of 1100 sweeps crosses the device history chunk (1024 rows per
+    replica); the rows of every replica must still be those of its single
+    lattice, in order."""
+    dims, betas, seed = [4, 4, 4, 4], [5.8, 6.4], 23
+    announce("su3 batch history across the device chunk")
+    with su2.Batch3(dims, betas, seed, su2.SU2_HOT) as b:
+        inits = [b.get_links(r) for r in range(2)]
+        h = b.heatbath_sweep(1100, reunit_every=10, history=True)
+    assert h.shape == (1100, 2)
+    for r, beta in enumerate(betas):
+        with su2.Lattice3(dims, beta, seed) as lat:
+            lat.set_replica(r)
+            lat.set_links(inits[r])
+            np.testing.assert_array_equal(lat.heatbath_sweep(1100, reunit_every=10, history=True),
+                                          h[:, r])
+
+
 def test_su3_batch_arguments(su2):
     with su2.Batch3([4, 4, 4, 4], [5.7, 6.0], 1) as b:
         for r in (-1, 2):
