@@ -42,7 +42,7 @@ enum Acc3 { A3_PLAQ = 0, A3_POLY_RE = 1, A3_POLY_IM = 2, A3_POLY_ABS = 3 };
 enum Res3 { R3_PLAQ = 0, R3_POLY_RE = 1, R3_POLY_IM = 2, R3_POLY_ABS = 3, kRes3 = 8 };
 
 struct Launch3 {
-    int block = 256;
+    int block = 128;       // 128 beats 256 by 3-4 % with the grouped loads of the pass
     bool remap = true;     // XCD-aware workgroup -> tile mapping
     bool snake = true;     // odd-parity passes traverse backwards
 };
